@@ -1,0 +1,313 @@
+"""Seeded synthetic inputs for the local character-based solver.
+
+This module only *creates problems*: conductivity fields, the symmetric
+stencil coefficients of the implicit diffusion operator, heat sources and the
+right-hand side of each backward-Euler / Picard system.  It holds none of the
+method's arithmetic (no residuals, no marking, no Krylov iteration), so the
+HIP path and the CPU oracle can both consume its bytes without sharing code.
+
+Operators (cell-centred finite volumes, h = 1, zero-flux outer faces):
+
+* ``5pt`` (2-D) and ``7pt`` (3-D): A = I/dt + sum over faces f=(P,Q) of
+  T_f (e_P - e_Q)(e_P - e_Q)^T with the harmonic face value
+  T_f = 2 k_P k_Q / (k_P + k_Q), k = exp(log k).  This is the five-point
+  scheme of the paper's 2-D heat test (Section 3.1) with backward Euler in
+  time (its time-discrete equation), extended to 3-D.
+* ``9pt`` (2-D): A = I/dt + sum over interior cell corners c of
+  G_c^T K G_c, where G_c maps the four cells around the corner to a corner
+  gradient and K is a constant rotated anisotropic tensor.  The sum is SPD
+  but not an M-matrix (nine-point schemes are used for the paper's
+  deformed-mesh radiation systems, Section 3.3).
+
+Stencil storage is symmetric: ``coef[0]`` is the diagonal, the other rows hold
+the coupling to the "forward" neighbours only (the backward ones are read from
+the neighbour's entry).  Cell index i = x + nx*y (+ nx*ny*z).
+
+  5pt : C, E=(+1,0), N=(0,+1)
+  9pt : C, E=(+1,0), N=(0,+1), NE=(+1,+1), NW=(-1,+1)
+  7pt : C, E=(+1,0,0), N=(0,+1,0), U=(0,0,+1)
+
+Entries toward a neighbour outside the grid are 0 and are not part of the
+sparsity pattern.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Optional
+
+import numpy as np
+
+KIND_5PT = 0
+KIND_9PT = 1
+KIND_7PT = 2
+KIND_NAMES = {KIND_5PT: "5pt", KIND_9PT: "9pt", KIND_7PT: "7pt"}
+N_ARRAYS = {KIND_5PT: 3, KIND_9PT: 5, KIND_7PT: 4}
+
+BASE_SEED = 20010115
+
+
+# --------------------------------------------------------------------------
+# conductivity fields and operators
+# --------------------------------------------------------------------------
+def lognormal_logk(shape, sigma: float, seed: int) -> np.ndarray:
+    """Per-cell log-conductivity, i.i.d. N(0, sigma^2), from numpy's PCG64."""
+    rng = np.random.default_rng(seed)
+    return sigma * rng.standard_normal(size=shape)
+
+
+def _harmonic(kp: np.ndarray, kq: np.ndarray) -> np.ndarray:
+    return 2.0 * kp * kq / (kp + kq)
+
+
+def assemble_5pt(logk: np.ndarray, inv_dt: float) -> np.ndarray:
+    """Coefficients (3, N) of the 2-D five-point operator for logk[ny, nx]."""
+    ny, nx = logk.shape
+    k = np.exp(logk)
+    tx = _harmonic(k[:, :-1], k[:, 1:])          # face between (x, y) and (x+1, y)
+    ty = _harmonic(k[:-1, :], k[1:, :])          # face between (x, y) and (x, y+1)
+    c = np.full((ny, nx), inv_dt)
+    c[:, :-1] += tx
+    c[:, 1:] += tx
+    c[:-1, :] += ty
+    c[1:, :] += ty
+    e = np.zeros((ny, nx))
+    e[:, :-1] = -tx
+    n = np.zeros((ny, nx))
+    n[:-1, :] = -ty
+    return np.ascontiguousarray(np.stack([c, e, n]).reshape(3, nx * ny))
+
+
+def assemble_7pt(logk: np.ndarray, inv_dt: float) -> np.ndarray:
+    """Coefficients (4, N) of the 3-D seven-point operator for logk[nz, ny, nx]."""
+    nz, ny, nx = logk.shape
+    k = np.exp(logk)
+    tx = _harmonic(k[:, :, :-1], k[:, :, 1:])
+    ty = _harmonic(k[:, :-1, :], k[:, 1:, :])
+    tz = _harmonic(k[:-1, :, :], k[1:, :, :])
+    c = np.full((nz, ny, nx), inv_dt)
+    c[:, :, :-1] += tx
+    c[:, :, 1:] += tx
+    c[:, :-1, :] += ty
+    c[:, 1:, :] += ty
+    c[:-1, :, :] += tz
+    c[1:, :, :] += tz
+    e = np.zeros((nz, ny, nx))
+    e[:, :, :-1] = -tx
+    n = np.zeros((nz, ny, nx))
+    n[:, :-1, :] = -ty
+    u = np.zeros((nz, ny, nx))
+    u[:-1, :, :] = -tz
+    return np.ascontiguousarray(np.stack([c, e, n, u]).reshape(4, nx * ny * nz))
+
+
+def aniso_tensor(ratio: float, angle_deg: float):
+    """K = R(angle) diag(1, 1/ratio) R(angle)^T as (kxx, kxy, kyy)."""
+    t = math.radians(angle_deg)
+    c, s = math.cos(t), math.sin(t)
+    k1, k2 = 1.0, 1.0 / ratio
+    return (c * c * k1 + s * s * k2, c * s * (k1 - k2), s * s * k1 + c * c * k2)
+
+
+def assemble_9pt(nx: int, ny: int, inv_dt: float, ratio: float = 100.0,
+                 angle_deg: float = 30.0) -> np.ndarray:
+    """Coefficients (5, N) of the 2-D SPD nine-point anisotropic operator.
+
+    Each interior corner c, shared by cells a=(x,y), b=(x+1,y), c=(x,y+1),
+    d=(x+1,y+1), contributes G^T K G with the corner gradient
+    gx = ((x_b - x_a) + (x_d - x_c))/2, gy = ((x_c - x_a) + (x_d - x_b))/2.
+    """
+    kxx, kxy, kyy = aniso_tensor(ratio, angle_deg)
+    g = 0.5 * np.array([[-1.0, 1.0, -1.0, 1.0],
+                        [-1.0, -1.0, 1.0, 1.0]])
+    kt = np.array([[kxx, kxy], [kxy, kyy]])
+    m = g.T @ kt @ g                                  # 4x4 local matrix, rows a,b,c,d
+    off = [(0, 0), (1, 0), (0, 1), (1, 1)]            # cell offsets of a,b,c,d
+    c = np.full((ny, nx), inv_dt)
+    e = np.zeros((ny, nx))
+    n = np.zeros((ny, nx))
+    ne = np.zeros((ny, nx))
+    nw = np.zeros((ny, nx))
+    cy, cx = ny - 1, nx - 1                           # interior corners
+    for p in range(4):
+        px, py = off[p]
+        c[py:py + cy, px:px + cx] += m[p, p]
+        for q in range(4):
+            if q == p:
+                continue
+            dx, dy = off[q][0] - px, off[q][1] - py
+            # keep only forward couplings; the others are their transposes
+            if (dx, dy) == (1, 0):
+                e[py:py + cy, px:px + cx] += m[p, q]
+            elif (dx, dy) == (0, 1):
+                n[py:py + cy, px:px + cx] += m[p, q]
+            elif (dx, dy) == (1, 1):
+                ne[py:py + cy, px:px + cx] += m[p, q]
+            elif (dx, dy) == (-1, 1):
+                nw[py:py + cy, px:px + cx] += m[p, q]
+    return np.ascontiguousarray(np.stack([c, e, n, ne, nw]).reshape(5, nx * ny))
+
+
+# --------------------------------------------------------------------------
+# sources
+# --------------------------------------------------------------------------
+def disk_source(nx: int, ny: int, cx: float, cy: float, radius: float, q: float) -> np.ndarray:
+    y, x = np.mgrid[0:ny, 0:nx]
+    return np.where((x - cx) ** 2 + (y - cy) ** 2 <= radius * radius, q, 0.0).reshape(-1)
+
+
+def ball_source(nx: int, ny: int, nz: int, cx: float, cy: float, cz: float,
+                radius: float, q: float) -> np.ndarray:
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx]
+    r2 = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2
+    return np.where(r2 <= radius * radius, q, 0.0).reshape(-1)
+
+
+def patch_mask(nx: int, ny: int, x0: int, y0: int, w: int) -> np.ndarray:
+    m = np.zeros((ny, nx))
+    m[y0:y0 + w, x0:x0 + w] = 1.0
+    return m.reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# system sequences
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Workload:
+    """A sequence of SPD systems A x_k = b_k sharing one operator A.
+
+    ``rhs(k, x_prev)`` gives b_k from the previous solution (backward Euler:
+    b_k = x_prev/dt + q_k; Picard: b_s = x_n/dt + q(x_s)).  ``x_start`` is
+    the initial state x_{-1}.  Threshold and solver settings are part of the
+    workload because the configurations name them.
+    """
+    name: str
+    kind: int
+    nx: int
+    ny: int
+    nz: int
+    dt: float
+    coef: np.ndarray            # (n_arrays, N) float64
+    n_systems: int
+    rhs: Callable[[int, np.ndarray], np.ndarray]
+    x_start: np.ndarray
+    logk: Optional[np.ndarray] = None
+    eps: float = 1e-10
+    theta_res: float = 1e-3
+    alpha_grad: float = 1e-4
+    e_max: int = 1
+    precision: str = "fp64"     # or "mixed"
+    precond: str = "jacobi"     # or "rbsgs"
+    notes: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def dims(self):
+        return (self.nx, self.ny, self.nz)
+
+
+def c1_picard(nx: int = 64, ny: int = 64, sigma: float = 0.5, dt: float = 4.0,
+              patch: int = 8, q0: float = 1.0, n_systems: int = 10,
+              seed: int = BASE_SEED + 0) -> Workload:
+    """2-D nonlinear heat step: Picard iterates of A T_{s+1} = T_n/dt + q(T_s),
+    q(T) = q0 * 1_patch / (1 + T) on a patch x patch hot spot at the centre.
+    Only the patch entries of b change between systems."""
+    logk = lognormal_logk((ny, nx), sigma, seed)
+    inv_dt = 1.0 / dt
+    coef = assemble_5pt(logk, inv_dt)
+    pm = patch_mask(nx, ny, (nx - patch) // 2, (ny - patch) // 2, patch)
+    t_n = np.zeros(nx * ny)
+
+    def rhs(k: int, x_prev: np.ndarray) -> np.ndarray:
+        return t_n * inv_dt + q0 * pm / (1.0 + x_prev)
+
+    return Workload("c1_picard_64x64_5pt", KIND_5PT, nx, ny, 1, dt, coef, n_systems,
+                    rhs, t_n.copy(), logk, theta_res=1e-3, e_max=1,
+                    notes="Picard sequence, 8x8 nonlinear source patch")
+
+
+def c2_moving_disk(nx: int = 1024, ny: int = 1024, sigma: float = 1.0, dt: float = 4.0,
+                   radius: float = 40.0, speed: float = 4.0, q0: float = 1.0,
+                   n_systems: int = 20, seed: int = BASE_SEED + 1,
+                   x_offset: Optional[float] = None) -> Workload:
+    """2-D backward-Euler sequence with a disk heat source moving in +x."""
+    logk = lognormal_logk((ny, nx), sigma, seed)
+    inv_dt = 1.0 / dt
+    coef = assemble_5pt(logk, inv_dt)
+    x0c = nx / 4.0 if x_offset is None else x_offset
+
+    def rhs(k: int, x_prev: np.ndarray) -> np.ndarray:
+        q = disk_source(nx, ny, x0c + speed * k, ny / 2.0, radius, q0)
+        return x_prev * inv_dt + q
+
+    return Workload(f"c2_moving_disk_{nx}x{ny}_5pt", KIND_5PT, nx, ny, 1, dt, coef, n_systems,
+                    rhs, np.zeros(nx * ny), logk, theta_res=1e-3, alpha_grad=1e-4, e_max=1)
+
+
+def c3_aniso_front(nx: int = 4096, ny: int = 4096, dt: float = 4.0, ratio: float = 100.0,
+                   angle: float = 30.0, radius: float = 150.0, speed: float = 8.0,
+                   q0: float = 1.0, n_systems: int = 20) -> Workload:
+    """2-D nine-point rotated anisotropic operator, moving disk front."""
+    inv_dt = 1.0 / dt
+    coef = assemble_9pt(nx, ny, inv_dt, ratio, angle)
+    x0c = nx / 4.0
+
+    def rhs(k: int, x_prev: np.ndarray) -> np.ndarray:
+        q = disk_source(nx, ny, x0c + speed * k, ny / 2.0, radius, q0)
+        return x_prev * inv_dt + q
+
+    return Workload(f"c3_aniso9_{nx}x{ny}", KIND_9PT, nx, ny, 1, dt, coef, n_systems,
+                    rhs, np.zeros(nx * ny), None, theta_res=1e-3, e_max=1,
+                    precision="mixed", precond="jacobi")
+
+
+def c4_adjoint(nx: int = 2048, ny: int = 2048, sigma: float = 1.0, dt: float = 4.0,
+               radius: float = 40.0, speed: float = 4.0, window: int = 256,
+               k_sys: int = 10, seed: int = BASE_SEED + 3) -> Workload:
+    """2-D five-point FP64 system used for the adjoint (loss over a window)."""
+    w = c2_moving_disk(nx, ny, sigma, dt, radius, speed, 1.0, k_sys + 1, seed,
+                       x_offset=nx / 2.0 - speed * k_sys)
+    w.name = f"c4_adjoint_{nx}x{ny}_5pt"
+    w.notes = f"loss window {window}x{window} centred on the front at system {k_sys}"
+    return w
+
+
+def c5_sphere3d(n: int = 256, sigma: float = 1.5, dt: float = 4.0, radius: float = 20.0,
+                speed: float = 2.0, q0: float = 1.0, n_systems: int = 50,
+                seed: int = BASE_SEED + 4) -> Workload:
+    """3-D seven-point sequence with a spherical source moving in +x."""
+    logk = lognormal_logk((n, n, n), sigma, seed)
+    inv_dt = 1.0 / dt
+    coef = assemble_7pt(logk, inv_dt)
+    x0c = n / 4.0
+
+    def rhs(k: int, x_prev: np.ndarray) -> np.ndarray:
+        q = ball_source(n, n, n, x0c + speed * k, n / 2.0, n / 2.0, radius, q0)
+        return x_prev * inv_dt + q
+
+    return Workload(f"c5_sphere_{n}^3_7pt", KIND_7PT, n, n, n, dt, coef, n_systems,
+                    rhs, np.zeros(n ** 3), logk, theta_res=1e-3, e_max=1,
+                    precision="mixed", precond="rbsgs")
+
+
+# --------------------------------------------------------------------------
+# worked example of the paper (Example 1, Section 2.3)
+# --------------------------------------------------------------------------
+def example1():
+    """The 9x9 tridiagonal system of the paper's Example 1 as dense arrays.
+
+    a_ii = 1, a_{i,i+1} = a_{i+1,i} = -1/(i+2) for 0-based i; the exact
+    solution is x_i = 10^-(i+1); the initial iterate is 1, 0.1, then
+    1.001 * 10^-(i+1).  b = A x.  Returns (A, x, x0, b).
+    """
+    nn = 9
+    a = np.eye(nn)
+    for i in range(nn - 1):
+        a[i, i + 1] = a[i + 1, i] = -1.0 / (i + 2)
+    x = np.array([10.0 ** -(i + 1) for i in range(nn)])
+    x0 = np.array([1.0, 1e-1] + [1.001 * 10.0 ** -(i + 1) for i in range(2, nn)])
+    b = a @ x
+    return a, x, x0, b

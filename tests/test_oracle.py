@@ -1,0 +1,415 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the
+paper's worked example, closed forms, dense direct solves, exact-arithmetic
+properties of CG, brute-force set definitions and derivative checks.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_01158_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_5pt(nx=12, ny=10, sigma=0.7, dt=4.0, seed=3):
+    logk = W.lognormal_logk((ny, nx), sigma, seed)
+    return W.assemble_5pt(logk, 1.0 / dt), logk
+
+
+def small_9pt(nx=11, ny=9, dt=4.0):
+    return W.assemble_9pt(nx, ny, 1.0 / dt, 100.0, 30.0)
+
+
+def small_7pt(n=6, sigma=1.0, dt=4.0, seed=5):
+    logk = W.lognormal_logk((n, n, n), sigma, seed)
+    return W.assemble_7pt(logk, 1.0 / dt), logk
+
+
+# ----------------------------------------------------------------------------
+# Example 1 (Section 2.3): residual, threshold, expansion rounds
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def ex1():
+    a, x, x0, b = W.example1()
+    g = json.load(open(os.path.join(GOLDEN, "example1.json")))
+    return oracle.csr_from_dense(a), x, x0, b, g
+
+
+def test_example1_residual_matches_printed(ex1):
+    A, x, x0, b, g = ex1
+    r = oracle.residual(A, b, x0)
+    printed = np.array(g["r0_printed"])
+    printed[1] = g["r0_corrected_entry_1"]       # typo in the paper, see fixture note
+    # printed to three significant digits
+    np.testing.assert_allclose(r, printed, rtol=6e-3)
+    assert abs(r[1] - 3.66e-1) > 1e-3            # the typo really is a typo
+
+
+def test_example1_threshold_and_domain(ex1):
+    A, x, x0, b, g = ex1
+    d = oracle.build_local_domain(A, b, x0, oracle.MODE_RESIDUAL, g["eps"], oracle.TH_PAPER, g["e_max"])
+    assert d.tau == pytest.approx(g["tau_printed"], rel=2e-3)
+    assert (d.idx + 1).tolist() == g["rounds"][-1]["omega"]
+    assert d.K == g["K_final"]
+    assert d.rounds == 3            # rounds 1..3 add a point, round 4 adds none
+    # round stamps: initial {1,2,3}, then 4, 5, 6 in rounds 1, 2, 3
+    assert d.mask.tolist() == [1, 1, 1, 2, 3, 4, 0, 0, 0]
+
+
+@pytest.mark.parametrize("e_max", range(0, 7))
+def test_example1_rounds_table(ex1, e_max):
+    A, x, x0, b, g = ex1
+    d = oracle.build_local_domain(A, b, x0, oracle.MODE_RESIDUAL, g["eps"], oracle.TH_PAPER, e_max)
+    if e_max == 0:
+        assert (d.idx + 1).tolist() == g["omega_initial_1based"]
+    else:
+        row = g["rounds"][min(e_max, 4) - 1]
+        assert (d.idx + 1).tolist() == row["omega"]
+        assert d.K == row["K"]
+
+
+@pytest.mark.parametrize("row", range(4))
+def test_example1_expansion_bounds_bracketed(ex1, row):
+    """The printed bound |r_j| + sum |a_jl x_l| of each round is pinned by
+    placing an absolute threshold just below / above it."""
+    A, x, x0, b, g = ex1
+    info = g["rounds"][row]
+    v = info["bound"]
+    j = info["candidates"][0] - 1
+    lo = oracle.build_local_domain(A, b, x0, oracle.MODE_RESIDUAL, v * 0.999, oracle.TH_ABS, 6)
+    hi = oracle.build_local_domain(A, b, x0, oracle.MODE_RESIDUAL, v * 1.001, oracle.TH_ABS, 6)
+    assert lo.mask[j] != 0          # bound > tau: j joins
+    assert hi.mask[j] == 0          # bound < tau: j stays out
+
+
+# ----------------------------------------------------------------------------
+# operators
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [W.KIND_5PT, W.KIND_9PT, W.KIND_7PT])
+def test_csr_symmetric_spd(kind):
+    if kind == W.KIND_5PT:
+        coef, _ = small_5pt(); dims = (12, 10, 1)
+    elif kind == W.KIND_9PT:
+        coef = small_9pt(); dims = (11, 9, 1)
+    else:
+        coef, _ = small_7pt(); dims = (6, 6, 6)
+    A = oracle.csr_from_stencil(kind, *dims, coef)
+    a = A.dense()
+    assert np.array_equal(a, a.T)                  # bitwise symmetric
+    np.linalg.cholesky(a)                          # SPD
+    nnb = {W.KIND_5PT: 5, W.KIND_9PT: 9, W.KIND_7PT: 7}[kind]
+    assert np.diff(A.rp).max() == nnb
+    for i in range(A.n):                           # ascending columns
+        assert np.all(np.diff(A.col[A.rp[i]:A.rp[i + 1]]) > 0)
+    if kind != W.KIND_9PT:
+        off = a - np.diag(np.diag(a))
+        assert np.all(off <= 0) and np.all(np.diag(a) > 0)          # M-matrix signs
+        np.testing.assert_allclose(a.sum(axis=1), 0.25, rtol=0, atol=1e-12)   # Neumann: row sum 1/dt
+    else:
+        assert np.any(a - np.diag(np.diag(a)) > 0)   # the rotated nine-point operator is not an M-matrix
+
+
+def test_nine_point_checkerboard_mode():
+    """The corner-gradient operator's diffusion part annihilates the
+    checkerboard, so that mode is damped only by the mass term 1/dt."""
+    nx, ny = 9, 7
+    A = oracle.csr_from_stencil(W.KIND_9PT, nx, ny, 1, small_9pt(nx, ny))
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    v = ((-1.0) ** (xx + yy)).reshape(-1)
+    np.testing.assert_allclose(oracle.spmv(A, v), 0.25 * v, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# gradient mimic: five-point closed form (Section 2.2)
+# ----------------------------------------------------------------------------
+def test_gradient_five_point_closed_form():
+    nx, ny = 13, 9
+    coef, _ = small_5pt(nx, ny)
+    A = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, coef)
+    x = np.random.default_rng(1).standard_normal(nx * ny)
+    g = oracle.gradient(A, x)
+    X = x.reshape(ny, nx)
+    G = np.zeros_like(X)
+    G[:, 1:] += np.abs(X[:, :-1] - X[:, 1:])      # |x_{p-1,q} - x_{p,q}|
+    G[:, :-1] += np.abs(X[:, 1:] - X[:, :-1])     # |x_{p+1,q} - x_{p,q}|
+    G[1:, :] += np.abs(X[:-1, :] - X[1:, :])      # |x_{p,q-1} - x_{p,q}|
+    G[:-1, :] += np.abs(X[1:, :] - X[:-1, :])     # |x_{p,q+1} - x_{p,q}|
+    np.testing.assert_allclose(g, G.reshape(-1), rtol=1e-15, atol=0)
+
+
+def test_gradient_mode_limits_and_nesting():
+    nx, ny = 16, 16
+    coef, _ = small_5pt(nx, ny)
+    A = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, coef)
+    x0 = np.random.default_rng(2).random(A.n)
+    b = np.zeros(A.n)
+    full = oracle.build_local_domain(A, b, x0, oracle.MODE_GRADIENT, 0.0, oracle.TH_RELMAX, 0)
+    assert full.K == int(np.count_nonzero(full.score > 0))       # alpha = 0: {g_i > 0}
+    one = oracle.build_local_domain(A, b, x0, oracle.MODE_GRADIENT, 1.0, oracle.TH_RELMAX, 0)
+    assert one.K == 0                                             # alpha = 1: empty (strict >)
+    prev = None
+    for alpha in [1e-1, 1e-2, 1e-3, 1e-4]:                       # eta(alpha) monotone
+        d = oracle.build_local_domain(A, b, x0, oracle.MODE_GRADIENT, alpha, oracle.TH_RELMAX, 3)
+        assert d.rounds == 0                                      # no expansion in Algorithm 2
+        g = oracle.gradient(A, x0)
+        assert set(d.idx.tolist()) == set(np.nonzero(g > alpha * g.max())[0].tolist())
+        if prev is not None:
+            assert set(prev.idx.tolist()) <= set(d.idx.tolist())
+        prev = d
+
+
+# ----------------------------------------------------------------------------
+# residual mode: threshold sets vs a dense residual, expansion invariants
+# ----------------------------------------------------------------------------
+def _residual_problem(nx=20, ny=18, seed=4):
+    coef, _ = small_5pt(nx, ny)
+    A = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, coef)
+    rng = np.random.default_rng(seed)
+    x_true = np.zeros(A.n)
+    x_true.reshape(ny, nx)[6:10, 5:9] = 1.0 + rng.random((4, 4))
+    b = A.dense() @ x_true
+    x0 = x_true + 1e-4 * rng.standard_normal(A.n) * (np.abs(x_true) > 0)
+    return A, b, x0
+
+
+@pytest.mark.parametrize("theta", [1e-1, 1e-2, 1e-3])
+def test_residual_threshold_set_brute_force(theta):
+    A, b, x0 = _residual_problem()
+    r = b - A.dense() @ x0                           # dense residual, other summation order
+    tau = theta * np.abs(r).max()
+    assert np.min(np.abs(np.abs(r) - tau)) > 1e-9 * tau    # no near-ties in this case
+    d = oracle.build_local_domain(A, b, x0, oracle.MODE_RESIDUAL, theta, oracle.TH_RELMAX, 0)
+    assert d.idx.tolist() == np.nonzero(np.abs(r) > tau)[0].tolist()
+    np.testing.assert_allclose(d.score, r, rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+def test_expansion_invariants():
+    A, b, x0 = _residual_problem()
+    a = A.dense()
+    prev = None
+    for e_max in range(0, 6):
+        d = oracle.build_local_domain(A, b, x0, oracle.MODE_RESIDUAL, 1e-2, oracle.TH_RELMAX, e_max)
+        s = set(d.idx.tolist())
+        if prev is not None:
+            ps = set(prev.idx.tolist())
+            assert ps <= s                                   # nested in E_max
+            added = s - ps
+            # every added point is a structural neighbour of the previous set
+            for j in added:
+                assert any(a[j, l] != 0 for l in ps)
+            if not added:                                    # growth stopped: stays stopped
+                assert d.rounds == prev.rounds
+        assert d.rounds <= e_max
+        prev = d
+
+
+def test_relmax_zero_residual_gives_empty_domain():
+    coef, _ = small_5pt(8, 8)
+    A = oracle.csr_from_stencil(W.KIND_5PT, 8, 8, 1, coef)
+    x = np.random.default_rng(0).random(A.n)
+    b = oracle.spmv(A, x)
+    d = oracle.build_local_domain(A, b, x, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 2)
+    r = oracle.residual(A, b, x)
+    assert d.K == int(np.count_nonzero(np.abs(r) > 1e-3 * np.abs(r).max()))
+    d2 = oracle.build_local_domain(A, np.zeros(A.n), np.zeros(A.n), oracle.MODE_RESIDUAL, 1e-3,
+                                   oracle.TH_RELMAX, 2)
+    assert d2.K == 0                                         # max |r| = 0: empty
+
+
+# ----------------------------------------------------------------------------
+# restricted subsystem (eq. BEFC / loc-equ)
+# ----------------------------------------------------------------------------
+def test_restricted_is_principal_submatrix_and_rhs_identity():
+    A, b, x0 = _residual_problem()
+    d = oracle.build_local_domain(A, b, x0, oracle.MODE_RESIDUAL, 1e-2, oracle.TH_RELMAX, 1)
+    B = oracle.restricted(A, d.idx)
+    a = A.dense()
+    np.testing.assert_array_equal(B.dense(), a[np.ix_(d.idx, d.idx)])
+    np.linalg.cholesky(B.dense())
+    out = np.setdiff1d(np.arange(A.n), d.idx)
+    E = a[np.ix_(d.idx, out)]
+    lhs = b[d.idx] - E @ x0[out]                              # b_B - E x_C^(0)
+    r = oracle.residual(A, b, x0)
+    rhs = r[d.idx] + B.dense() @ x0[d.idx]                    # r^(0)_B + B x_B^(0)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+# ----------------------------------------------------------------------------
+# PCG and Algorithm 1
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,pc", [(W.KIND_5PT, oracle.PC_JACOBI), (W.KIND_5PT, oracle.PC_SGS),
+                                     (W.KIND_9PT, oracle.PC_JACOBI), (W.KIND_9PT, oracle.PC_SGS),
+                                     (W.KIND_7PT, oracle.PC_JACOBI), (W.KIND_7PT, oracle.PC_SGS)])
+def test_pcg_matches_dense_solve(kind, pc):
+    if kind == W.KIND_5PT:
+        coef, _ = small_5pt(16, 16); dims = (16, 16, 1)
+    elif kind == W.KIND_9PT:
+        coef = small_9pt(16, 15); dims = (16, 15, 1)
+    else:
+        coef, _ = small_7pt(6); dims = (6, 6, 6)
+    A = oracle.csr_from_stencil(kind, *dims, coef)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal(A.n)
+    x, st, it, res = oracle.pcg(A, b, np.zeros(A.n), pc, 1e-13 * np.linalg.norm(b), 5000)
+    assert st == oracle.OK and res <= 1e-13 * np.linalg.norm(b)
+    xd = np.linalg.solve(A.dense(), b)
+    cond = np.linalg.cond(A.dense())
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= max(10 * cond * 1e-13, 1e-12)
+
+
+def test_pcg_manufactured_solution():
+    coef, _ = small_5pt(24, 20)
+    A = oracle.csr_from_stencil(W.KIND_5PT, 24, 20, 1, coef)
+    xs = np.sin(np.arange(A.n) * 0.37)
+    b = A.dense() @ xs
+    x, st, it, _ = oracle.pcg(A, b, np.zeros(A.n), oracle.PC_JACOBI, 1e-14 * np.linalg.norm(b), 5000)
+    assert st == oracle.OK
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-11
+
+
+def test_cg_finite_termination():
+    """Unpreconditioned CG on an n x n SPD system reaches the solution in at
+    most n steps in exact arithmetic; with distinct eigenvalue count m < n,
+    in at most m steps."""
+    a = np.diag([1.0, 2.0, 3.0, 1.0, 2.0, 3.0, 2.0])      # 3 distinct eigenvalues
+    A = oracle.csr_from_dense(a)
+    b = np.arange(1.0, 8.0)
+    x, st, it, res = oracle.pcg(A, b, np.zeros(7), oracle.PC_NONE, 1e-12, 100)
+    assert st == oracle.OK and it <= 3
+    np.testing.assert_allclose(x, b / np.diag(a), rtol=1e-13)
+
+
+def test_pcg_breakdown_on_indefinite():
+    a = np.diag([1.0, -2.0, 3.0])
+    x, st, it, res = oracle.pcg(oracle.csr_from_dense(a), np.ones(3), np.zeros(3), oracle.PC_NONE,
+                                1e-12, 50)
+    assert st == oracle.EBREAKDOWN
+
+
+def test_gs_sweep_is_red_black_gauss_seidel():
+    """One red-black sweep = exact solve of each colour's rows given the others."""
+    coef, _ = small_5pt(9, 7)
+    A = oracle.csr_from_stencil(W.KIND_5PT, 9, 7, 1, coef)
+    a = A.dense()
+    rng = np.random.default_rng(9)
+    b, x = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    y = oracle.gs_sweeps(A, b, x, 1)
+    z = x.copy()
+    for c in range(2):
+        rows = np.nonzero(A.colour == c)[0]
+        # rows of one colour do not couple; solve them from the current others
+        for i in rows:
+            s = b[i] - a[i] @ z + a[i, i] * z[i]
+            z[i] = s / a[i, i]
+    np.testing.assert_allclose(y, z, rtol=1e-14, atol=1e-14)
+    # smoothing reduces the A-norm of the error
+    xs = np.linalg.solve(a, b)
+    en = lambda v: (v - xs) @ a @ (v - xs)
+    assert en(y) < en(x)
+
+
+def _sequence_problem(nx=48, dt=4.0):
+    w = W.c2_moving_disk(nx=nx, ny=nx, dt=dt, radius=6.0, speed=2.0, n_systems=3)
+    A = oracle.csr_from_stencil(w.kind, w.nx, w.ny, w.nz, w.coef)
+    x = w.x_start
+    for k in range(2):
+        b = w.rhs(k, x)
+        x = np.linalg.solve(A.dense(), b)
+    return w, A, w.rhs(2, x), x
+
+
+def test_local_then_global_meets_criterion():
+    w, A, b, x0 = _sequence_problem()
+    opts = oracle.Options(eps=1e-10)
+    a = A.dense()
+    xd = np.linalg.solve(a, b)
+    for mode, theta, th in [(oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX),
+                            (oracle.MODE_RESIDUAL, 1e-10, oracle.TH_PAPER),
+                            (oracle.MODE_GRADIENT, 1e-4, oracle.TH_RELMAX)]:
+        x, st, dom = oracle.local_then_global(A, b, x0, mode, theta, th, 1, opts)
+        assert st.status == oracle.OK
+        assert np.linalg.norm(b - a @ x) <= 1.01e-10 * np.linalg.norm(b)
+        assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-8
+        assert 0 < dom.K <= A.n
+
+
+def test_paper_threshold_usually_needs_no_global_solve():
+    """With the paper's threshold the assembled x~ already meets the
+    criterion in the common case (Section 3, discussion of Algorithm 1)."""
+    w, A, b, x0 = _sequence_problem()
+    x, st, dom = oracle.local_then_global(A, b, x0, oracle.MODE_RESIDUAL, 1e-10, oracle.TH_PAPER, 1,
+                                          oracle.Options(eps=1e-10))
+    assert st.its_global == 0 and st.relres_final <= 1e-10
+
+
+def test_empty_domain_equals_global_solve_bitwise():
+    w, A, b, x0 = _sequence_problem()
+    opts = oracle.Options(eps=1e-10, n_smooth=0)
+    xg, sg = oracle.solve_global(A, b, x0, opts)
+    xl, sl = oracle.solve_local(A, b, x0, np.zeros(0, np.int32), opts)
+    assert np.array_equal(xl, x0)                              # K = 0: x~ = x^(0)
+    xl, sl2 = oracle.solve_global(A, b, xl, opts)
+    assert np.array_equal(xl, xg) and sl2.its_global == sg.its_global
+
+
+def test_full_domain_local_solve_equals_global_pcg():
+    w, A, b, x0 = _sequence_problem()
+    opts = oracle.Options(eps=1e-10, n_smooth=0)
+    xl, sl = oracle.solve_local(A, b, x0, np.arange(A.n, dtype=np.int32), opts)
+    # K = N: B = A, correction form d = x - x0
+    r = oracle.residual(A, b, x0)
+    d, st, it, _ = oracle.pcg(A, r, np.zeros(A.n), oracle.PC_JACOBI, 1e-10 * np.linalg.norm(b), 20000)
+    assert sl.its_local == it
+    np.testing.assert_array_equal(xl, x0 + d)
+
+
+# ----------------------------------------------------------------------------
+# adjoint pieces
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [W.KIND_5PT, W.KIND_7PT])
+def test_assemble_logk_matches_generator(kind):
+    if kind == W.KIND_5PT:
+        logk = W.lognormal_logk((7, 9), 1.0, 11); dims = (9, 7, 1)
+        gen = W.assemble_5pt(logk, 0.25)
+    else:
+        logk = W.lognormal_logk((4, 5, 6), 1.0, 11); dims = (6, 5, 4)
+        gen = W.assemble_7pt(logk, 0.25)
+    c = oracle.assemble_logk(kind, *dims, 0.25, logk)
+    np.testing.assert_allclose(c, gen, rtol=1e-14, atol=1e-15)
+
+
+def test_adjoint_gradient_vs_dense_finite_differences():
+    """dL/dlogk and dL/db from one adjoint solve vs central differences of
+    the dense forward map L(l, b) = 0.5 ||W (A(l)^-1 b - x_obs)||^2."""
+    nx, ny, dt = 7, 6, 4.0
+    logk = W.lognormal_logk((ny, nx), 0.8, 21)
+    rng = np.random.default_rng(22)
+    b = rng.random(nx * ny)
+    x_obs = rng.random(nx * ny)
+    win = np.zeros(nx * ny); win.reshape(ny, nx)[1:4, 2:6] = 1.0
+
+    def loss(lk, bb):
+        a = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, W.assemble_5pt(lk, 1 / dt)).dense()
+        x = np.linalg.solve(a, bb)
+        return 0.5 * np.sum(win * (x - x_obs) ** 2)
+
+    A = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, oracle.assemble_logk(0, nx, ny, 1, 1 / dt, logk))
+    x, st, _, _ = oracle.pcg(A, b, np.zeros(A.n), oracle.PC_JACOBI, 1e-15, 5000)
+    gx = win * (x - x_obs)
+    lam, st, _, _ = oracle.pcg(A, gx, np.zeros(A.n), oracle.PC_JACOBI, 1e-15, 5000)
+    g_l = oracle.grad_logk(0, nx, ny, 1, logk, x, lam)
+    h = 1e-5
+    for p in range(0, nx * ny, 5):
+        e = np.zeros(nx * ny); e[p] = h
+        fd_l = (loss((logk.reshape(-1) + e).reshape(ny, nx), b)
+                - loss((logk.reshape(-1) - e).reshape(ny, nx), b)) / (2 * h)
+        assert abs(g_l[p] - fd_l) <= 1e-7 * max(1.0, abs(fd_l)), (p, g_l[p], fd_l)
+    for p in range(0, nx * ny, 7):
+        e = np.zeros(nx * ny); e[p] = h
+        fd = (loss(logk.reshape(ny, nx), b + e) - loss(logk.reshape(ny, nx), b - e)) / (2 * h)
+        assert abs(lam[p] - fd) <= 1e-7 * max(1.0, abs(fd))
