@@ -1,0 +1,182 @@
+/*
+ * lcs.h -- C ABI of the MI355X (gfx950) local character-based solver.
+ *
+ * Method: Ye, An, Xu, "A local character based method for solving linear
+ * systems of radiation diffusion problems" (arXiv 2001.01158).  For a system
+ * A x = b whose initial iterate x^(0) is the previous time step or nonlinear
+ * iterate (Section 2.1), the library
+ *   1. marks a local domain Omega by residual (Section 2.3, Algorithm 3) or by
+ *      the gradient mimic (Section 2.2, eq. grad, Algorithm 2),
+ *   2. compacts Omega into the restricted CSR system B = A[Omega, Omega]
+ *      (eq. BEFC) and solves B x_B = b_B - E x_C^(0) (eq. loc-equ) with PCG,
+ *   3. assembles x~ (eq. sol-assemble), applies Gauss-Seidel smoothing, and
+ *      finishes with a warm-started global PCG when x~ misses the criterion
+ *      ||b - A x|| <= eps ||b|| (eq. rel-res-conv-criteria; Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are symmetric stencils on a structured grid, row index
+ *     i = x + nx*y (+ nx*ny*z).  coef is a device array of n_arrays x N
+ *     doubles: row 0 the diagonal, then the couplings to forward neighbours
+ *       5-point 2-D : C, E(+1,0), N(0,+1)                        (3 arrays)
+ *       9-point 2-D : C, E(+1,0), N(0,+1), NE(+1,+1), NW(-1,+1)   (5 arrays)
+ *       7-point 3-D : C, E(+1,0,0), N(0,+1,0), U(0,0,+1)          (4 arrays)
+ *     a backward coupling is the forward coupling stored at the neighbour.
+ *     The sparsity pattern is every in-grid stencil neighbour.
+ *   - Vector arguments are device pointers of length N = nx*ny*nz (FP64)
+ *     owned by the caller; the library never frees them.  Index arrays are
+ *     int32 (N < 2^31).
+ *   - stream is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *     it; calls that need a host decision (K, convergence) synchronise it
+ *     before returning.
+ *   - Every call returns an lcs_status; on error lcs_last_error() gives a
+ *     message (thread-local).  No exception crosses the ABI.  On
+ *     LCS_ENOCONV / LCS_EBREAKDOWN, x holds the last iterate and stats are
+ *     filled.
+ *   - A context owns its device workspace (hipMalloc'd, grown on demand,
+ *     released by lcs_destroy).  A context is used by one host thread at a
+ *     time; calls on one context serialise on its workspace.
+ */
+#ifndef LCS_H
+#define LCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lcs_status {
+    LCS_OK = 0,
+    LCS_EINVAL = 1,       /* bad argument (sizes, kinds, NULL pointers)          */
+    LCS_EHIP = 2,         /* a HIP runtime call failed                            */
+    LCS_ENOMEM = 3,       /* device workspace allocation failed                   */
+    LCS_ENOCONV = 4,      /* max_iter / max_outer reached before the criterion    */
+    LCS_EBREAKDOWN = 5,   /* p^T A p <= 0 in CG: the operator is not SPD          */
+    LCS_ENONFINITE = 6    /* NaN / Inf in the input or the iteration              */
+} lcs_status;
+
+enum { LCS_STENCIL5_2D = 0, LCS_STENCIL9_2D = 1, LCS_STENCIL7_3D = 2 };
+enum { LCS_MODE_RESIDUAL = 0, LCS_MODE_GRADIENT = 1 };
+enum {
+    LCS_THRESH_REL_MAX = 0,  /* tau = theta * max_i |s_i|  (s = r^(0) or g)       */
+    LCS_THRESH_ABS = 1,      /* tau = theta                                        */
+    LCS_THRESH_PAPER = 2     /* tau = theta * ||b||_2 / sqrt(N), theta = epsilon,
+                                eq. (resi-local-domain-0); residual mode only      */
+};
+enum { LCS_PC_NONE = 0, LCS_PC_JACOBI = 1, LCS_PC_RBSGS = 2 };
+enum { LCS_PREC_FP64 = 0, LCS_PREC_MIXED = 1 };
+
+typedef struct lcs_matrix {
+    int32_t kind;          /* LCS_STENCIL*                                         */
+    int32_t nx, ny, nz;    /* grid; nz = 1 in 2-D                                  */
+    const double *coef;    /* device, n_arrays x N, FP64                           */
+    const float *coef32;   /* device, n_arrays x N, FP32 copy for LCS_PREC_MIXED;
+                              NULL: the library casts coef into its workspace      */
+} lcs_matrix;
+
+typedef struct lcs_options {
+    double eps;            /* global criterion ||b - A x||_2 <= eps ||b||_2 (1e-10) */
+    double tol_local;      /* local criterion ||r_B||_2 <= tol_local ||b||_2;
+                              <= 0 means eps                                        */
+    double inner_tol;      /* mixed precision: inner FP32 PCG stops at
+                              ||r32|| <= inner_tol ||r32_0|| (default 1e-5)         */
+    int32_t max_iter;      /* PCG iteration cap per solve (all outer steps)         */
+    int32_t precond;       /* LCS_PC_*; RBSGS needs a 2-colourable stencil
+                              (5- or 7-point)                                       */
+    int32_t precision;     /* LCS_PREC_FP64 or LCS_PREC_MIXED                       */
+    int32_t n_smooth;      /* Gauss-Seidel sweeps on x~ (Algorithm 1 step 7)        */
+    int32_t check_every;   /* PCG iterations between host convergence checks       */
+    int32_t max_outer;     /* mixed: refinement steps; FP64: restarts after a
+                              failed true-residual check                            */
+} lcs_options;
+
+typedef struct lcs_stats {
+    int64_t K;             /* |Omega|                                               */
+    int32_t e_rounds;      /* expansion rounds that added points                   */
+    int32_t its_local;     /* PCG iterations on B (all refinement steps)            */
+    int32_t its_global;    /* PCG iterations on A                                   */
+    int32_t n_outer;       /* refinement steps (mixed) or PCG restarts (FP64)       */
+    double tau;            /* threshold used for Omega                              */
+    double relres_after_local;  /* ||b - A x~|| / ||b|| after smoothing             */
+    double relres_final;   /* ||b - A x|| / ||b|| of the returned x (FP64)         */
+    double ms_construct, ms_local, ms_smooth, ms_global;  /* per-phase GPU time    */
+} lcs_stats;
+
+typedef struct lcs_ctx lcs_ctx;
+
+/* Fill o with the defaults named above (eps 1e-10, Jacobi, FP64, 1 sweep). */
+void lcs_default_options(lcs_options *o);
+
+/* Create a context on the current HIP device.  Returns LCS_EHIP if no device. */
+lcs_status lcs_create(lcs_ctx **ctx);
+void lcs_destroy(lcs_ctx *ctx);
+const char *lcs_last_error(void);
+
+/* Global PCG from x (in: x^(0), out: solution) to eq. (rel-res-conv-criteria):
+ * the baseline that Algorithm 1 is compared against (METHOD0's role). */
+lcs_status lcs_solve_global(lcs_ctx *ctx, const lcs_matrix *A, const double *b, double *x,
+                            const lcs_options *o, lcs_stats *st, void *stream);
+
+/* Local domain (Algorithm 2 / Algorithm 3).  Writes idx[0..K) (device, capacity
+ * N, ascending), *K (host) and, if mask != NULL, mask[N] (device uint8: 0 =
+ * outside, 1 = marked by the threshold, m+1 = added by expansion round m).
+ * e_max (0..250) is ignored in gradient mode.  st may be NULL. */
+lcs_status lcs_build_local_domain(lcs_ctx *ctx, const lcs_matrix *A, const double *b,
+                                  const double *x0, int32_t mode, int32_t thresh_kind,
+                                  double theta, int32_t e_max, int32_t *idx, uint8_t *mask,
+                                  int64_t *K, lcs_stats *st, void *stream);
+
+/* Steps 3-7 of Algorithm 1 for a given Omega = idx[0..K) (device, ascending,
+ * distinct): solve B d = r^(0)_Omega from d = 0 (the correction form of
+ * eq. loc-equ), x <- x + d on Omega (eq. sol-assemble), then n_smooth
+ * red-black Gauss-Seidel sweeps on A x = b.  x: in x^(0), out x~. */
+lcs_status lcs_solve_local(lcs_ctx *ctx, const lcs_matrix *A, const double *b, double *x,
+                           const int32_t *idx, int64_t K, const lcs_options *o,
+                           lcs_stats *st, void *stream);
+
+/* Algorithm 1: build Omega, solve locally, smooth, check, and finish with the
+ * global PCG from x~ when needed.  x: in x^(0), out solution. */
+lcs_status lcs_solve_local_then_global(lcs_ctx *ctx, const lcs_matrix *A, const double *b,
+                                       double *x, int32_t mode, int32_t thresh_kind,
+                                       double theta, int32_t e_max, const lcs_options *o,
+                                       lcs_stats *st, void *stream);
+
+/* ---- pieces of the path, exported for parity tests and measurement ---- */
+
+/* r = b - A x with the ascending-column FMA chain (score of Algorithm 3). */
+lcs_status lcs_residual(lcs_ctx *ctx, const lcs_matrix *A, const double *b, const double *x,
+                        double *r, void *stream);
+/* g_i = sum_{j stored, j != i} |x_i - x_j| (eq. grad). */
+lcs_status lcs_gradient(lcs_ctx *ctx, const lcs_matrix *A, const double *x, double *g,
+                        void *stream);
+/* y = A x; precision LCS_PREC_FP64 (x, y double) or LCS_PREC_MIXED (x, y float,
+ * coefficients from A->coef32 or a cast).  reps launches back to back. */
+lcs_status lcs_spmv(lcs_ctx *ctx, const lcs_matrix *A, const void *x, void *y,
+                    int32_t precision, int32_t reps, void *stream);
+/* Restricted B = A[idx, idx] in CSR (eq. BEFC): row_ptr int32[K+1],
+ * col int32[nnz], val double[nnz] (device, capacity 9K).  *nnz (host). */
+lcs_status lcs_gather_restricted(lcs_ctx *ctx, const lcs_matrix *A, const int32_t *idx,
+                                 int64_t K, int32_t *row_ptr, int32_t *col, double *val,
+                                 int64_t *nnz, void *stream);
+/* n_sweeps red-black (9-point: four-colour) Gauss-Seidel sweeps on A x = b. */
+lcs_status lcs_gs_sweeps(lcs_ctx *ctx, const lcs_matrix *A, const double *b, double *x,
+                         int32_t n_sweeps, void *stream);
+/* coef32 = (float) coef, n_arrays x N (device). */
+lcs_status lcs_cast_coef(lcs_ctx *ctx, const lcs_matrix *A, float *coef32, void *stream);
+
+/* ---- adjoint helpers (5- and 7-point log-conductivity operators) ---- */
+/* coef = stencil of A = I*inv_dt + sum_f T_f (e_P-e_Q)(e_P-e_Q)^T with
+ * T_f = 2 k_P k_Q / (k_P + k_Q), k = exp(logk); zero-flux outer faces. */
+lcs_status lcs_assemble_logk(lcs_ctx *ctx, int32_t kind, int32_t nx, int32_t ny, int32_t nz,
+                             double inv_dt, const double *logk, double *coef, void *stream);
+/* grad_P = -sum_{faces (P,Q)} (dT_f/dlogk_P) (x_P - x_Q)(lambda_P - lambda_Q),
+ * the derivative of lambda^T (b - A(logk) x) with respect to logk. */
+lcs_status lcs_grad_logk(lcs_ctx *ctx, int32_t kind, int32_t nx, int32_t ny, int32_t nz,
+                         const double *logk, const double *x, const double *lam,
+                         double *grad, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LCS_H */

@@ -1,0 +1,1028 @@
+// Host runtime and C ABI of the local character-based solver (see lcs.h).
+//
+// Every step of the method runs in the kernels of lcs_kernels.h; the host
+// only sizes launches, orders them on the caller's stream and reads a few
+// scalars (K, convergence flags) back through pinned memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "lcs.h"
+#include "lcs_kernels.h"
+
+using namespace lcs;
+
+namespace {
+
+thread_local std::string g_err;
+
+lcs_status fail(lcs_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(LCS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LCS_TRY(expr)                \
+    do {                             \
+        lcs_status s_ = (expr);      \
+        if (s_ != LCS_OK) return s_; \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                            \
+    do {                                                                          \
+        hipError_t e_ = hipGetLastError();                                        \
+        if (e_ != hipSuccess)                                                     \
+            return fail(LCS_EHIP, std::string("launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+int n_arrays(int kind) { return kind == LCS_STENCIL5_2D ? 3 : kind == LCS_STENCIL9_2D ? 5 : 4; }
+int n_colours(int kind) { return kind == LCS_STENCIL9_2D ? 4 : 2; }
+
+struct Launch {
+    int grid;
+    int64_t chunk;
+};
+
+// Chunked grid: at most kMaxGrid blocks (a multiple of 8 once large enough,
+// for the XCD remap), each owning `chunk` consecutive rows.
+Launch dims_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g >= 64) g = (g + kXcds - 1) / kXcds * kXcds;
+    int64_t chunk = (n + g - 1) / g;
+    if (chunk < 1) chunk = 1;
+    return {(int)g, chunk};
+}
+
+int flat_grid(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 8 * kMaxGrid) g = 8 * kMaxGrid;
+    return (int)g;
+}
+
+// Compaction tiling: tiles of kTile stamps, at most kMaxGrid blocks.
+struct Tiling {
+    int grid;
+    int64_t ntiles, tiles_per_block, npad;
+};
+Tiling tiling_for(int64_t n) {
+    Tiling t;
+    t.ntiles = (n + kTile - 1) / kTile;
+    if (t.ntiles < 1) t.ntiles = 1;
+    int64_t g = std::min<int64_t>(t.ntiles, kMaxGrid);
+    t.tiles_per_block = (t.ntiles + g - 1) / g;
+    t.grid = (int)((t.ntiles + t.tiles_per_block - 1) / t.tiles_per_block);
+    t.npad = t.ntiles * kTile;
+    return t;
+}
+
+enum BufId {
+    B_SCORE, B_R, B_Z, B_P0, B_P1, B_Q, B_RHSL, B_DL, B_RES, B_STAMP, B_INV, B_IDX, B_BLOCKOFF,
+    B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
+    B_P32A, B_P32B, B_Q32, B_COEF32, B_NUM
+};
+
+}  // namespace
+
+struct lcs_ctx {
+    int device = 0;
+    Scalars *dsc = nullptr;    // device state
+    Scalars *hsc = nullptr;    // pinned host copy
+    int32_t *hdone = nullptr;  // pinned: two slots for asynchronous convergence checks
+    double *partials = nullptr;
+    void *buf[B_NUM] = {};
+    size_t cap[B_NUM] = {};
+    hipEvent_t ev[5] = {};
+    hipEvent_t chk[2] = {};
+};
+
+namespace {
+
+template <typename T>
+lcs_status get_buf(lcs_ctx *c, BufId id, size_t count, T **out) {
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (c->cap[id] < bytes) {
+        if (c->buf[id]) {
+            HIP_TRY(hipDeviceSynchronize());  // the old buffer may still be in use
+            HIP_TRY(hipFree(c->buf[id]));
+        }
+        c->buf[id] = nullptr;
+        c->cap[id] = 0;
+        const size_t want = bytes + bytes / 8;  // slack for sequences of growing K
+        if (hipMalloc(&c->buf[id], want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LCS_ENOMEM, "device workspace allocation of " + std::to_string(want) +
+                                        " bytes failed");
+        }
+        c->cap[id] = want;
+    }
+    *out = static_cast<T *>(c->buf[id]);
+    return LCS_OK;
+}
+
+lcs_status read_scalars(lcs_ctx *c, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(c->hsc, c->dsc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return LCS_OK;
+}
+
+lcs_status check_matrix(const lcs_matrix *A) {
+    if (!A) return fail(LCS_EINVAL, "matrix is NULL");
+    if (A->kind < 0 || A->kind > 2) return fail(LCS_EINVAL, "unknown matrix kind");
+    if (A->nx < 1 || A->ny < 1 || A->nz < 1) return fail(LCS_EINVAL, "grid sizes must be >= 1");
+    if (A->kind != LCS_STENCIL7_3D && A->nz != 1) return fail(LCS_EINVAL, "2-D stencil needs nz = 1");
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    if (n >= ((int64_t)1 << 31) / 16) return fail(LCS_EINVAL, "N must be < 2^27");
+    if (!A->coef) return fail(LCS_EINVAL, "coef is NULL");
+    return LCS_OK;
+}
+
+lcs_status check_options(const lcs_options *o, int kind) {
+    if (!o) return fail(LCS_EINVAL, "options are NULL");
+    if (!(o->eps > 0.0)) return fail(LCS_EINVAL, "eps must be > 0");
+    if (o->max_iter < 0 || o->n_smooth < 0 || o->max_outer < 0)
+        return fail(LCS_EINVAL, "negative iteration counts");
+    if (o->precond < 0 || o->precond > 2) return fail(LCS_EINVAL, "unknown preconditioner");
+    if (o->precision < 0 || o->precision > 1) return fail(LCS_EINVAL, "unknown precision");
+    if (o->precond == LCS_PC_RBSGS && kind == LCS_STENCIL9_2D)
+        return fail(LCS_EINVAL, "red-black SGS needs a 2-colourable stencil (5- or 7-point)");
+    return LCS_OK;
+}
+
+lcs_status check_ptr(const void *p, const char *what) {
+    if (!p) return fail(LCS_EINVAL, std::string(what) + " is NULL");
+    return LCS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operators from the C description
+// ---------------------------------------------------------------------------
+template <typename real>
+Stencil5<real> op5(const lcs_matrix *A, const real *c) {
+    const int64_t n = (int64_t)A->nx * A->ny;
+    return {c, c + n, c + 2 * n, A->nx, A->ny, n};
+}
+template <typename real>
+Stencil9<real> op9(const lcs_matrix *A, const real *c) {
+    const int64_t n = (int64_t)A->nx * A->ny;
+    return {c, c + n, c + 2 * n, c + 3 * n, c + 4 * n, A->nx, A->ny, n};
+}
+template <typename real>
+Stencil7<real> op7(const lcs_matrix *A, const real *c) {
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    return {c, c + n, c + 2 * n, c + 3 * n, A->nx, A->ny, A->nz, n};
+}
+
+// Calls f(op64, op32) with the operator types of A's kind.
+template <class F>
+lcs_status with_ops(const lcs_matrix *A, const float *coef32, F &&f) {
+    switch (A->kind) {
+    case LCS_STENCIL5_2D: return f(op5<double>(A, A->coef), op5<float>(A, coef32));
+    case LCS_STENCIL9_2D: return f(op9<double>(A, A->coef), op9<float>(A, coef32));
+    default: return f(op7<double>(A, A->coef), op7<float>(A, coef32));
+    }
+}
+
+lcs_status ensure_coef32(lcs_ctx *c, const lcs_matrix *A, bool need, const float **out,
+                         hipStream_t s) {
+    *out = nullptr;
+    if (!need) return LCS_OK;
+    if (A->coef32) {
+        *out = A->coef32;
+        return LCS_OK;
+    }
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz * n_arrays(A->kind);
+    float *p;
+    LCS_TRY(get_buf(c, B_COEF32, (size_t)n, &p));
+    hipLaunchKernelGGL(k_cast, dim3(flat_grid(n)), dim3(kBlock), 0, s, A->coef, p, n);
+    LAUNCH_CHECK();
+    *out = p;
+    return LCS_OK;
+}
+
+lcs_status launch_norm(lcs_ctx *c, const double *v, int64_t n, double *out, hipStream_t s) {
+    const Launch L = dims_for(n);
+    hipLaunchKernelGGL(k_norm2, dim3(L.grid), dim3(kBlock), 0, s, v, n, L.chunk, out, c->dsc,
+                       c->partials);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PCG driver
+// ---------------------------------------------------------------------------
+template <typename real>
+struct PcgBufs {
+    real *r, *z, *p0, *p1, *q;
+};
+
+struct PcgResult {
+    int its = 0;
+    int status = kStOk;
+};
+
+// z = M^-1 r for the symmetric red-black (or four-colour) Gauss-Seidel
+// preconditioner from z = 0: colours 0..nc-1, then nc-2..0 (the backward
+// pass's first colour would repeat the forward pass's last one exactly).
+template <class Op, typename real, int kPc>
+lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<real> &B, const Launch &L,
+                          int ncol, hipStream_t s) {
+    if (kPc != LCS_PC_RBSGS) return LCS_OK;
+    real *part = reinterpret_cast<real *>(c->partials);
+    for (int col = 0; col < ncol; ++col)
+        hipLaunchKernelGGL((k_gs_half<Op, real, false>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                           (const real *)B.r, B.z, col, L.chunk, c->dsc, part);
+    for (int col = ncol - 2; col >= 0; --col) {
+        if (col == 0)
+            hipLaunchKernelGGL((k_gs_half<Op, real, true>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                               (const real *)B.r, B.z, col, L.chunk, c->dsc, part);
+        else
+            hipLaunchKernelGGL((k_gs_half<Op, real, false>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                               (const real *)B.r, B.z, col, L.chunk, c->dsc, part);
+    }
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+// PCG on op x = rhs.  Convergence lives on the device; the host enqueues
+// check_every iterations at a time and polls the flag of the previous chunk
+// while the next one runs, so the GPU never waits for the host.  Launches
+// after convergence exit at their first instruction.
+template <class Op, typename real, int kPc>
+lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const real *rhs, real *x, bool x_zero,
+                     const double *tol_base, double tol_factor, int max_iter, int check_every,
+                     const PcgBufs<real> &B, hipStream_t s, PcgResult *res) {
+    const Launch L = dims_for(A.n);
+    real *part = reinterpret_cast<real *>(c->partials);
+    if (x_zero) {
+        hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(A.n)), dim3(kBlock), 0, s, x, real(0), A.n);
+        LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL((k_pcg_init<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A, rhs,
+                       (const real *)x, B.r, B.z, L.chunk, x_zero ? 1 : 0, tol_base, tol_factor,
+                       max_iter, c->dsc, part);
+    LAUNCH_CHECK();
+    LCS_TRY((launch_precond<Op, real, kPc>(c, A, B, L, ncol, s)));
+    if (check_every < 1) check_every = 1;
+    int flip = 0, enqueued = 0;
+    auto enqueue_chunk = [&](int slot) -> lcs_status {
+        for (int k = 0; k < check_every; ++k) {
+            real *pold = flip ? B.p1 : B.p0;
+            real *pnew = flip ? B.p0 : B.p1;
+            hipLaunchKernelGGL((k_pcg_ap<Op, real>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                               (const real *)B.z, (const real *)pold, pnew, B.q, L.chunk, c->dsc,
+                               part);
+            hipLaunchKernelGGL((k_pcg_update<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                               x, (const real *)pnew, (const real *)B.q, B.r, B.z, L.chunk, c->dsc,
+                               part);
+            LAUNCH_CHECK();
+            LCS_TRY((launch_precond<Op, real, kPc>(c, A, B, L, ncol, s)));
+            flip ^= 1;
+        }
+        enqueued += check_every;
+        HIP_TRY(hipMemcpyAsync(&c->hdone[slot], &c->dsc->pcg.done, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(c->chk[slot], s));
+        return LCS_OK;
+    };
+    // the initial iterate may already satisfy the criterion
+    HIP_TRY(hipMemcpyAsync(&c->hdone[0], &c->dsc->pcg.done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(c->chk[0], s));
+    HIP_TRY(hipEventSynchronize(c->chk[0]));
+    if (!c->hdone[0]) {
+        LCS_TRY(enqueue_chunk(0));
+        int slot = 0;
+        for (;;) {
+            const bool more = enqueued < max_iter;
+            if (more) LCS_TRY(enqueue_chunk(slot ^ 1));
+            HIP_TRY(hipEventSynchronize(c->chk[slot]));
+            if (c->hdone[slot] || !more) break;
+            slot ^= 1;
+        }
+    }
+    LCS_TRY(read_scalars(c, s));
+    res->its = c->hsc->pcg.it;
+    res->status = c->hsc->pcg.status;
+    if (!c->hsc->pcg.done && res->status == kStOk) res->status = kStNoConv;
+    return LCS_OK;
+}
+
+template <class Op, typename real>
+lcs_status run_pcg(lcs_ctx *c, const Op &A, int ncol, int pc, const real *rhs, real *x,
+                   bool x_zero, const double *tol_base, double tol_factor, int max_iter,
+                   int check_every, const PcgBufs<real> &B, hipStream_t s, PcgResult *res) {
+    switch (pc) {
+    case LCS_PC_NONE:
+        return run_pcg_t<Op, real, 0>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
+                                      check_every, B, s, res);
+    case LCS_PC_JACOBI:
+        return run_pcg_t<Op, real, 1>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
+                                      check_every, B, s, res);
+    default:
+        return run_pcg_t<Op, real, 2>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
+                                      check_every, B, s, res);
+    }
+}
+
+lcs_status status_of(int st) {
+    switch (st) {
+    case kStOk: return LCS_OK;
+    case kStNoConv: return fail(LCS_ENOCONV, "iteration limit reached before the criterion");
+    case kStBreakdown: return fail(LCS_EBREAKDOWN, "p^T A p <= 0: operator not SPD");
+    default: return fail(LCS_ENONFINITE, "non-finite value in the iteration");
+    }
+}
+
+template <class Op>
+lcs_status launch_resnorm(lcs_ctx *c, const Op &A, const double *rhs, const double *x, double *r,
+                          const double *tol_base, double tol_factor, hipStream_t s) {
+    const Launch L = dims_for(A.n);
+    hipLaunchKernelGGL((k_resnorm<Op>), dim3(L.grid), dim3(kBlock), 0, s, A, rhs, x, r, L.chunk,
+                       tol_base, tol_factor, c->dsc, c->partials);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+struct SolveOut {
+    int its = 0;
+    int n_outer = 0;
+    double rr = 0.0;   // ||rhs - op x||^2 at exit (FP64)
+};
+
+// Solve op x = rhs to ||rhs - op x|| <= tol_factor * *tol_base.
+// FP64: PCG, then a true-residual check with up to max_outer restarts.
+// Mixed: FP64 residual -> scaled FP32 PCG correction to inner_tol -> FP64
+// update, repeated until the FP64 criterion holds.
+template <class Op64, class Op32>
+lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, const double *rhs,
+                        double *x, bool x_zero, const double *tol_base, double tol_factor,
+                        const lcs_options *o, hipStream_t s, SolveOut *out) {
+    const int64_t n = A.n;
+    *out = SolveOut();
+    if (n == 0) return LCS_OK;
+    const int check = o->check_every > 0 ? o->check_every : 8;
+    if (o->precision == LCS_PREC_FP64) {
+        PcgBufs<double> B;
+        LCS_TRY(get_buf(c, B_R, n, &B.r));
+        LCS_TRY(get_buf(c, B_Z, n, &B.z));
+        LCS_TRY(get_buf(c, B_P0, n, &B.p0));
+        LCS_TRY(get_buf(c, B_P1, n, &B.p1));
+        LCS_TRY(get_buf(c, B_Q, n, &B.q));
+        bool zero = x_zero;
+        for (int attempt = 0;; ++attempt) {
+            PcgResult pr;
+            LCS_TRY(run_pcg(c, A, ncol, o->precond, rhs, x, zero, tol_base, tol_factor,
+                            o->max_iter - out->its, check, B, s, &pr));
+            zero = false;
+            out->its += pr.its;
+            LCS_TRY(launch_resnorm(c, A, rhs, x, (double *)nullptr, tol_base, tol_factor, s));
+            LCS_TRY(read_scalars(c, s));
+            out->rr = c->hsc->pcg.rr;
+            if (pr.status != kStOk) return status_of(pr.status);
+            if (c->hsc->pcg.status != kStOk) return status_of(c->hsc->pcg.status);
+            if (c->hsc->pcg.done) return LCS_OK;
+            if (attempt >= o->max_outer || out->its >= o->max_iter) return status_of(kStNoConv);
+            out->n_outer += 1;
+        }
+    }
+    double *r64;
+    float *r32, *d32;
+    PcgBufs<float> B;
+    LCS_TRY(get_buf(c, B_RES, n, &r64));
+    LCS_TRY(get_buf(c, B_R32, n, &r32));
+    LCS_TRY(get_buf(c, B_D32, n, &d32));
+    LCS_TRY(get_buf(c, B_RI32, n, &B.r));
+    LCS_TRY(get_buf(c, B_Z32, n, &B.z));
+    LCS_TRY(get_buf(c, B_P32A, n, &B.p0));
+    LCS_TRY(get_buf(c, B_P32B, n, &B.p1));
+    LCS_TRY(get_buf(c, B_Q32, n, &B.q));
+    const double inner = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+    const int outer_cap = o->max_outer > 0 ? o->max_outer : 10;
+    if (x_zero) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, 0.0, n);
+        LAUNCH_CHECK();
+    }
+    for (int outer = 0;; ++outer) {
+        LCS_TRY(launch_resnorm(c, A, rhs, x, r64, tol_base, tol_factor, s));
+        LCS_TRY(read_scalars(c, s));
+        out->rr = c->hsc->pcg.rr;
+        if (c->hsc->pcg.status != kStOk) return status_of(c->hsc->pcg.status);
+        if (c->hsc->pcg.done) return LCS_OK;
+        if (outer >= outer_cap || out->its >= o->max_iter) return status_of(kStNoConv);
+        hipLaunchKernelGGL(k_cast_scale, dim3(flat_grid(n)), dim3(kBlock), 0, s,
+                           (const double *)r64, r32, n, c->dsc);
+        LAUNCH_CHECK();
+        PcgResult pr;
+        LCS_TRY(run_pcg(c, A32, ncol, o->precond, (const float *)r32, d32, true,
+                        (const double *)nullptr, inner, o->max_iter - out->its, check, B, s, &pr));
+        out->its += pr.its;
+        if (pr.status == kStBreakdown || pr.status == kStNonFinite) return status_of(pr.status);
+        hipLaunchKernelGGL(k_axpy_scaled, dim3(flat_grid(n)), dim3(kBlock), 0, s, x,
+                           (const float *)d32, n, (const Scalars *)c->dsc);
+        LAUNCH_CHECK();
+        out->n_outer += 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 / Algorithm 3: scores, threshold, expansion, compaction
+// ---------------------------------------------------------------------------
+// Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
+// ascending domain in idx; returns K (host).
+template <class Op>
+lcs_status build_domain(lcs_ctx *c, const Op &A, const double *b, const double *x0, int mode,
+                        int thresh, double theta, int e_max, int32_t *idx, int64_t *K,
+                        hipStream_t s) {
+    const int64_t n = A.n;
+    const Launch L = dims_for(n);
+    const Tiling T = tiling_for(n);
+    double *score;
+    uint8_t *stamp;
+    int32_t *inv, *blockoff;
+    LCS_TRY(get_buf(c, B_SCORE, n, &score));
+    LCS_TRY(get_buf(c, B_STAMP, T.npad, &stamp));
+    LCS_TRY(get_buf(c, B_INV, n, &inv));
+    LCS_TRY(get_buf(c, B_BLOCKOFF, kMaxGrid, &blockoff));
+    if (mode == LCS_MODE_RESIDUAL)
+        hipLaunchKernelGGL((k_score<Op, 0>), dim3(L.grid), dim3(kBlock), 0, s, A, b, x0, score,
+                           L.chunk, thresh, theta, c->dsc, c->partials);
+    else
+        hipLaunchKernelGGL((k_score<Op, 1>), dim3(L.grid), dim3(kBlock), 0, s, A, b, x0, score,
+                           L.chunk, thresh, theta, c->dsc, c->partials);
+    hipLaunchKernelGGL(k_mark, dim3(flat_grid(T.npad)), dim3(kBlock), 0, s, (const double *)score,
+                       stamp, n, T.npad, (const Scalars *)c->dsc);
+    LAUNCH_CHECK();
+    if (mode == LCS_MODE_RESIDUAL) {
+        for (int m = 1; m <= e_max; ++m)
+            hipLaunchKernelGGL((k_expand<Op>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                               (const double *)score, x0, stamp, m, L.chunk, c->dsc, c->partials);
+        LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_count, dim3(T.grid), dim3(kBlock), 0, s, (const uint8_t *)stamp, T.ntiles,
+                       T.tiles_per_block, blockoff, c->dsc);
+    hipLaunchKernelGGL(k_scatter, dim3(T.grid), dim3(kBlock), 0, s, (const uint8_t *)stamp, n,
+                       T.ntiles, T.tiles_per_block, (const int32_t *)blockoff, idx, inv);
+    LAUNCH_CHECK();
+    LCS_TRY(read_scalars(c, s));
+    *K = c->hsc->ms.K;
+    return LCS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// restricted system and local solve (steps 3-7 of Algorithm 1)
+// ---------------------------------------------------------------------------
+struct Restricted {
+    Csr<double> B64;
+    Csr<float> B32;
+    double *rhs;
+    int64_t nnz;
+};
+
+// B = A[idx, idx] in CSR (row lengths -> scan -> fill); rhs = r[idx].
+template <class Op>
+lcs_status gather(lcs_ctx *c, const Op &A, const int32_t *idx, int64_t K, const int32_t *inv,
+                  const double *r, bool with32, Restricted *R, hipStream_t s) {
+    int32_t *rowlen, *rp, *col, *blockoff;
+    double *val, *dg, *rhs;
+    float *val32 = nullptr, *dg32 = nullptr;
+    uint8_t *clr;
+    const int64_t cap = K * 9;
+    LCS_TRY(get_buf(c, B_ROWLEN, K, &rowlen));
+    LCS_TRY(get_buf(c, B_RP, K + 1, &rp));
+    LCS_TRY(get_buf(c, B_COL, cap, &col));
+    LCS_TRY(get_buf(c, B_VAL, cap, &val));
+    LCS_TRY(get_buf(c, B_DG, K, &dg));
+    LCS_TRY(get_buf(c, B_CLR, K, &clr));
+    LCS_TRY(get_buf(c, B_RHSL, K, &rhs));
+    LCS_TRY(get_buf(c, B_BLOCKOFF, kMaxGrid, &blockoff));
+    if (with32) {
+        LCS_TRY(get_buf(c, B_VAL32, cap, &val32));
+        LCS_TRY(get_buf(c, B_DG32, K, &dg32));
+    }
+    const Tiling T = tiling_for(K);
+    hipLaunchKernelGGL((k_gather_count<Op>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K,
+                       inv, rowlen);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)rowlen, K,
+                       T.tiles_per_block, blockoff, c->dsc);
+    hipLaunchKernelGGL(k_scan_apply, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)rowlen, K,
+                       T.tiles_per_block, (const int32_t *)blockoff, rp, (const Scalars *)c->dsc);
+    hipLaunchKernelGGL((k_gather_fill<Op>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K, inv,
+                       (const int32_t *)rp, col, val, val32, dg, dg32, clr, r, r ? rhs : nullptr);
+    LAUNCH_CHECK();
+    R->B64 = {rp, col, val, dg, clr, K};
+    R->B32 = {rp, col, val32, dg32, clr, K};
+    R->rhs = rhs;
+    R->nnz = -1;
+    return LCS_OK;
+}
+
+struct Timers {
+    lcs_ctx *c;
+    hipStream_t s;
+    bool on;
+    lcs_status mark(int k) {
+        if (on) HIP_TRY(hipEventRecord(c->ev[k], s));
+        return LCS_OK;
+    }
+    double ms(int a, int b) {
+        if (!on) return 0.0;
+        float v = 0.f;
+        if (hipEventElapsedTime(&v, c->ev[a], c->ev[b]) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0.0;
+        }
+        return v;
+    }
+};
+
+// x <- x + d on Omega after solving B d = r^(0)_Omega, then smoothing.
+// r0: r^(0) over the whole grid when the caller already has it, else null.
+template <class Op64, class Op32>
+lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const Op64 &A, const Op32 &A32,
+                       const double *b, double *x, const int32_t *idx, int64_t K,
+                       const int32_t *inv, const double *r0, const lcs_options *o,
+                       lcs_stats *st, Timers &tm, hipStream_t s) {
+    const int ncol = n_colours(M->kind);
+    if (K > 0) {
+        if (!r0) {
+            double *r;
+            LCS_TRY(get_buf(c, B_SCORE, A.n, &r));
+            LCS_TRY(launch_resnorm(c, A, b, (const double *)x, r, &c->dsc->bnorm, o->eps, s));
+            r0 = r;
+        }
+        Restricted R;
+        LCS_TRY(gather(c, A, idx, K, inv, r0, o->precision == LCS_PREC_MIXED, &R, s));
+        double *d;
+        LCS_TRY(get_buf(c, B_DL, K, &d));
+        const double tl = o->tol_local > 0 ? o->tol_local : o->eps;
+        SolveOut so;
+        const lcs_status ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
+                                           &c->dsc->bnorm, tl, o, s, &so);
+        // a local solve that stops at its iteration cap still improves x;
+        // the global finish takes over from there
+        if (ls != LCS_OK && ls != LCS_ENOCONV) return ls;
+        st->its_local = so.its;
+        st->n_outer += so.n_outer;
+        hipLaunchKernelGGL(k_scatter_add, dim3(flat_grid(K)), dim3(kBlock), 0, s, idx,
+                           (const double *)d, K, x);
+        LAUNCH_CHECK();
+    }
+    LCS_TRY(tm.mark(2));
+    if (o->n_smooth > 0) {
+        const Launch L = dims_for(A.n);
+        for (int sw = 0; sw < o->n_smooth; ++sw)
+            for (int col = 0; col < ncol; ++col)
+                hipLaunchKernelGGL((k_gs_half<Op64, double, false>), dim3(L.grid), dim3(kBlock), 0,
+                                   s, A, b, x, col, L.chunk, (Scalars *)nullptr, c->partials);
+        LAUNCH_CHECK();
+    }
+    LCS_TRY(tm.mark(3));
+    return LCS_OK;
+}
+
+// inv for a caller-supplied domain; rejects indices out of range or not
+// strictly ascending before anything reads through them.
+lcs_status set_inv(lcs_ctx *c, const int32_t *idx, int64_t K, int64_t n, int32_t *inv,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(1), 0, s, &c->dsc->bad_idx, 0, (int64_t)1);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(flat_grid(n)), dim3(kBlock), 0, s, inv, -1, n);
+    if (K > 0)
+        hipLaunchKernelGGL(k_set_inv, dim3(flat_grid(K)), dim3(kBlock), 0, s, idx, K, n, inv, c->dsc);
+    LAUNCH_CHECK();
+    LCS_TRY(read_scalars(c, s));
+    if (c->hsc->bad_idx) return fail(LCS_EINVAL, "idx must be strictly ascending indices in [0, N)");
+    return LCS_OK;
+}
+
+void init_stats(lcs_stats *st) {
+    std::memset(st, 0, sizeof(*st));
+    st->relres_after_local = NAN;
+    st->relres_final = NAN;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void lcs_default_options(lcs_options *o) {
+    if (!o) return;
+    o->eps = 1e-10;
+    o->tol_local = 0.0;
+    o->inner_tol = 1e-5;
+    o->max_iter = 20000;
+    o->precond = LCS_PC_JACOBI;
+    o->precision = LCS_PREC_FP64;
+    o->n_smooth = 1;
+    o->check_every = 8;
+    o->max_outer = 10;
+}
+
+const char *lcs_last_error(void) { return g_err.c_str(); }
+
+lcs_status lcs_create(lcs_ctx **out) {
+    if (!out) return fail(LCS_EINVAL, "ctx is NULL");
+    *out = nullptr;
+    lcs_ctx *c = new lcs_ctx();
+    auto cleanup = [&](lcs_status st) {
+        lcs_destroy(c);
+        return st;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return cleanup(fail(LCS_EHIP, "no HIP device"));
+    if (hipMalloc(&c->dsc, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_ENOMEM, "state"));
+    if (hipMemset(c->dsc, 0, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_EHIP, "memset"));
+    if (hipMalloc(&c->partials, sizeof(double) * kMaxGrid * 4) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "partials"));
+    if (hipHostMalloc(&c->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "pinned state"));
+    if (hipHostMalloc(&c->hdone, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "pinned flags"));
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(LCS_EHIP, "event"));
+    for (auto &e : c->chk)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(LCS_EHIP, "event"));
+    if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LCS_EHIP, "sync"));
+    *out = c;
+    return LCS_OK;
+}
+
+void lcs_destroy(lcs_ctx *c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < B_NUM; ++i)
+        if (c->buf[i]) (void)hipFree(c->buf[i]);
+    if (c->dsc) (void)hipFree(c->dsc);
+    if (c->partials) (void)hipFree(c->partials);
+    if (c->hsc) (void)hipHostFree(c->hsc);
+    if (c->hdone) (void)hipHostFree(c->hdone);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->chk)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const double *x,
+                        double *r, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x, "x"));
+    LCS_TRY(check_ptr(r, "r"));
+    hipStream_t s = (hipStream_t)stream;
+    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
+        LCS_TRY(launch_norm(c, b, op.n, &c->dsc->bnorm, s));
+        LCS_TRY(launch_resnorm(c, op, b, x, r, &c->dsc->bnorm, 1.0, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return LCS_OK;
+    });
+}
+
+lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double *g, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_ptr(x, "x"));
+    LCS_TRY(check_ptr(g, "g"));
+    hipStream_t s = (hipStream_t)stream;
+    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
+        const Launch L = dims_for(op.n);
+        hipLaunchKernelGGL((k_score<decltype(op), 1>), dim3(L.grid), dim3(kBlock), 0, s, op, x, x,
+                           g, L.chunk, 1, 0.0, c->dsc, c->partials);
+        LAUNCH_CHECK();
+        HIP_TRY(hipStreamSynchronize(s));
+        return LCS_OK;
+    });
+}
+
+lcs_status lcs_spmv(lcs_ctx *c, const lcs_matrix *A, const void *x, void *y, int32_t precision,
+                    int32_t reps, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_ptr(x, "x"));
+    LCS_TRY(check_ptr(y, "y"));
+    if (precision != LCS_PREC_FP64 && precision != LCS_PREC_MIXED)
+        return fail(LCS_EINVAL, "unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    const float *c32 = nullptr;
+    LCS_TRY(ensure_coef32(c, A, precision == LCS_PREC_MIXED, &c32, s));
+    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
+        const Launch L = dims_for(op.n);
+        for (int k = 0; k < std::max(reps, 1); ++k) {
+            if (precision == LCS_PREC_FP64)
+                hipLaunchKernelGGL((k_spmv<decltype(op), double>), dim3(L.grid), dim3(kBlock), 0, s,
+                                   op, (const double *)x, (double *)y, L.chunk);
+            else
+                hipLaunchKernelGGL((k_spmv<decltype(op32), float>), dim3(L.grid), dim3(kBlock), 0,
+                                   s, op32, (const float *)x, (float *)y, L.chunk);
+        }
+        LAUNCH_CHECK();
+        return LCS_OK;
+    });
+}
+
+lcs_status lcs_cast_coef(lcs_ctx *c, const lcs_matrix *A, float *coef32, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_ptr(coef32, "coef32"));
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz * n_arrays(A->kind);
+    hipLaunchKernelGGL(k_cast, dim3(flat_grid(n)), dim3(kBlock), 0, (hipStream_t)stream, A->coef,
+                       coef32, n);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+lcs_status lcs_build_local_domain(lcs_ctx *c, const lcs_matrix *A, const double *b,
+                                  const double *x0, int32_t mode, int32_t thresh_kind,
+                                  double theta, int32_t e_max, int32_t *idx, uint8_t *mask,
+                                  int64_t *K, lcs_stats *st, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x0, "x0"));
+    LCS_TRY(check_ptr(idx, "idx"));
+    LCS_TRY(check_ptr(K, "K"));
+    if (mode != LCS_MODE_RESIDUAL && mode != LCS_MODE_GRADIENT) return fail(LCS_EINVAL, "mode");
+    if (thresh_kind < 0 || thresh_kind > 2) return fail(LCS_EINVAL, "threshold kind");
+    if (thresh_kind == LCS_THRESH_PAPER && mode != LCS_MODE_RESIDUAL)
+        return fail(LCS_EINVAL, "the paper threshold belongs to the residual mode");
+    if (e_max < 0 || e_max > 250) return fail(LCS_EINVAL, "e_max must be in 0..250");
+    if (!(theta >= 0.0)) return fail(LCS_EINVAL, "theta must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
+        LCS_TRY(build_domain(c, op, b, x0, mode, thresh_kind, theta, e_max, idx, K, s));
+        if (mask) {
+            uint8_t *stamp;
+            LCS_TRY(get_buf(c, B_STAMP, tiling_for(op.n).npad, &stamp));
+            HIP_TRY(hipMemcpyAsync(mask, stamp, (size_t)op.n, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        if (st) {
+            init_stats(st);
+            st->K = *K;
+            st->e_rounds = c->hsc->ms.grown;
+            st->tau = c->hsc->ms.tau;
+        }
+        return LCS_OK;
+    });
+}
+
+lcs_status lcs_gather_restricted(lcs_ctx *c, const lcs_matrix *A, const int32_t *idx, int64_t K,
+                                 int32_t *row_ptr, int32_t *col, double *val, int64_t *nnz,
+                                 void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    if (K < 0 || K > n) return fail(LCS_EINVAL, "K out of range");
+    if (K > 0) {
+        LCS_TRY(check_ptr(idx, "idx"));
+        LCS_TRY(check_ptr(row_ptr, "row_ptr"));
+        LCS_TRY(check_ptr(col, "col"));
+        LCS_TRY(check_ptr(val, "val"));
+    }
+    LCS_TRY(check_ptr(nnz, "nnz"));
+    hipStream_t s = (hipStream_t)stream;
+    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
+        int32_t *inv;
+        LCS_TRY(get_buf(c, B_INV, n, &inv));
+        LCS_TRY(set_inv(c, idx, K, n, inv, s));
+        if (K == 0) {
+            *nnz = 0;
+            if (row_ptr) HIP_TRY(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s));
+            HIP_TRY(hipStreamSynchronize(s));
+            return LCS_OK;
+        }
+        Restricted R;
+        LCS_TRY(gather(c, op, idx, K, inv, nullptr, false, &R, s));
+        LCS_TRY(read_scalars(c, s));
+        *nnz = c->hsc->gather_nnz;
+        HIP_TRY(hipMemcpyAsync(row_ptr, R.B64.rp, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(col, R.B64.col, sizeof(int32_t) * *nnz, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(val, R.B64.val, sizeof(double) * *nnz, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return LCS_OK;
+    });
+}
+
+lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, double *x,
+                         int32_t n_sweeps, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x, "x"));
+    if (n_sweeps < 0) return fail(LCS_EINVAL, "n_sweeps < 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int ncol = n_colours(A->kind);
+    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
+        const Launch L = dims_for(op.n);
+        for (int sw = 0; sw < n_sweeps; ++sw)
+            for (int col = 0; col < ncol; ++col)
+                hipLaunchKernelGGL((k_gs_half<decltype(op), double, false>), dim3(L.grid),
+                                   dim3(kBlock), 0, s, op, b, x, col, L.chunk, (Scalars *)nullptr,
+                                   c->partials);
+        LAUNCH_CHECK();
+        HIP_TRY(hipStreamSynchronize(s));
+        return LCS_OK;
+    });
+}
+
+lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, double *x,
+                            const lcs_options *o, lcs_stats *st, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_options(o, A->kind));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x, "x"));
+    lcs_stats local;
+    if (!st) st = &local;
+    init_stats(st);
+    hipStream_t s = (hipStream_t)stream;
+    Timers tm{c, s, true};
+    const float *c32 = nullptr;
+    LCS_TRY(tm.mark(0));
+    LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
+    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
+        LCS_TRY(launch_norm(c, b, op.n, &c->dsc->bnorm, s));
+        LCS_TRY(tm.mark(3));
+        SolveOut so;
+        const lcs_status rs = solve_system(c, op, op32, n_colours(A->kind), b, x, false,
+                                           &c->dsc->bnorm, o->eps, o, s, &so);
+        LCS_TRY(tm.mark(4));
+        HIP_TRY(hipStreamSynchronize(s));
+        const double bn = c->hsc->bnorm;
+        st->its_global = so.its;
+        st->n_outer = so.n_outer;
+        st->relres_final = bn > 0 ? std::sqrt(so.rr) / bn : std::sqrt(so.rr);
+        st->ms_global = tm.ms(0, 4);
+        return rs;
+    });
+}
+
+lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, double *x,
+                           const int32_t *idx, int64_t K, const lcs_options *o, lcs_stats *st,
+                           void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_options(o, A->kind));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x, "x"));
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    if (K < 0 || K > n) return fail(LCS_EINVAL, "K out of range");
+    if (K > 0) LCS_TRY(check_ptr(idx, "idx"));
+    lcs_stats local;
+    if (!st) st = &local;
+    init_stats(st);
+    st->K = K;
+    hipStream_t s = (hipStream_t)stream;
+    Timers tm{c, s, true};
+    LCS_TRY(tm.mark(0));
+    const float *c32 = nullptr;
+    LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
+    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
+        LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
+        int32_t *inv;
+        LCS_TRY(get_buf(c, B_INV, n, &inv));
+        LCS_TRY(set_inv(c, idx, K, n, inv, s));
+        LCS_TRY(tm.mark(1));
+        LCS_TRY(local_phase(c, A, op, op32, b, x, idx, K, inv, nullptr, o, st, tm, s));
+        LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
+                               o->eps, s));
+        LCS_TRY(read_scalars(c, s));
+        const double bn = c->hsc->bnorm;
+        st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->pcg.rr) / bn : std::sqrt(c->hsc->pcg.rr);
+        st->relres_final = st->relres_after_local;
+        st->ms_construct = tm.ms(0, 1);
+        st->ms_local = tm.ms(1, 2);
+        st->ms_smooth = tm.ms(2, 3);
+        return LCS_OK;
+    });
+}
+
+lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const double *b,
+                                       double *x, int32_t mode, int32_t thresh_kind,
+                                       double theta, int32_t e_max, const lcs_options *o,
+                                       lcs_stats *st, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_options(o, A->kind));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x, "x"));
+    if (mode != LCS_MODE_RESIDUAL && mode != LCS_MODE_GRADIENT) return fail(LCS_EINVAL, "mode");
+    if (thresh_kind < 0 || thresh_kind > 2) return fail(LCS_EINVAL, "threshold kind");
+    if (thresh_kind == LCS_THRESH_PAPER && mode != LCS_MODE_RESIDUAL)
+        return fail(LCS_EINVAL, "the paper threshold belongs to the residual mode");
+    if (e_max < 0 || e_max > 250) return fail(LCS_EINVAL, "e_max must be in 0..250");
+    if (!(theta >= 0.0)) return fail(LCS_EINVAL, "theta must be >= 0");
+    lcs_stats local;
+    if (!st) st = &local;
+    init_stats(st);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    Timers tm{c, s, true};
+    LCS_TRY(tm.mark(0));
+    const float *c32 = nullptr;
+    LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
+    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
+        LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
+        int32_t *idx;
+        LCS_TRY(get_buf(c, B_IDX, n, &idx));
+        int64_t K = 0;
+        LCS_TRY(build_domain(c, op, b, (const double *)x, mode, thresh_kind, theta, e_max, idx, &K, s));
+        st->K = K;
+        st->e_rounds = c->hsc->ms.grown;
+        st->tau = c->hsc->ms.tau;
+        const double bn = c->hsc->bnorm;
+        LCS_TRY(tm.mark(1));
+        double *score, *r0 = nullptr;
+        int32_t *inv;
+        LCS_TRY(get_buf(c, B_SCORE, n, &score));
+        LCS_TRY(get_buf(c, B_INV, n, &inv));
+        if (mode == LCS_MODE_RESIDUAL) r0 = score;
+        LCS_TRY(local_phase(c, A, op, op32, b, x, idx, K, inv, r0, o, st, tm, s));
+        // criterion after the local solve and smoothing (Algorithm 1 step 8)
+        LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
+                               o->eps, s));
+        LCS_TRY(read_scalars(c, s));
+        st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->pcg.rr) / bn : std::sqrt(c->hsc->pcg.rr);
+        lcs_status rs = LCS_OK;
+        if (c->hsc->pcg.done) {
+            st->relres_final = st->relres_after_local;
+            LCS_TRY(tm.mark(4));
+        } else {
+            SolveOut so;
+            rs = solve_system(c, op, op32, n_colours(A->kind), b, x, false, &c->dsc->bnorm, o->eps,
+                              o, s, &so);
+            st->its_global = so.its;
+            st->n_outer += so.n_outer;
+            st->relres_final = bn > 0 ? std::sqrt(so.rr) / bn : std::sqrt(so.rr);
+            LCS_TRY(tm.mark(4));
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        st->ms_construct = tm.ms(0, 1);
+        st->ms_local = tm.ms(1, 2);
+        st->ms_smooth = tm.ms(2, 3);
+        st->ms_global = tm.ms(3, 4);
+        return rs;
+    });
+}
+
+lcs_status lcs_assemble_logk(lcs_ctx *c, int32_t kind, int32_t nx, int32_t ny, int32_t nz,
+                             double inv_dt, const double *logk, double *coef, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    if (kind != LCS_STENCIL5_2D && kind != LCS_STENCIL7_3D)
+        return fail(LCS_EINVAL, "log-conductivity assembly exists for the 5- and 7-point operators");
+    if (nx < 1 || ny < 1 || nz < 1 || (kind == LCS_STENCIL5_2D && nz != 1))
+        return fail(LCS_EINVAL, "grid sizes");
+    LCS_TRY(check_ptr(logk, "logk"));
+    LCS_TRY(check_ptr(coef, "coef"));
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipStream_t s = (hipStream_t)stream;
+    if (kind == LCS_STENCIL5_2D)
+        hipLaunchKernelGGL(k_assemble_logk<2>, dim3(flat_grid(n)), dim3(kBlock), 0, s, nx, ny, nz,
+                           inv_dt, logk, coef);
+    else
+        hipLaunchKernelGGL(k_assemble_logk<3>, dim3(flat_grid(n)), dim3(kBlock), 0, s, nx, ny, nz,
+                           inv_dt, logk, coef);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+lcs_status lcs_grad_logk(lcs_ctx *c, int32_t kind, int32_t nx, int32_t ny, int32_t nz,
+                         const double *logk, const double *x, const double *lam, double *grad,
+                         void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    if (kind != LCS_STENCIL5_2D && kind != LCS_STENCIL7_3D)
+        return fail(LCS_EINVAL, "log-conductivity gradient exists for the 5- and 7-point operators");
+    if (nx < 1 || ny < 1 || nz < 1 || (kind == LCS_STENCIL5_2D && nz != 1))
+        return fail(LCS_EINVAL, "grid sizes");
+    LCS_TRY(check_ptr(logk, "logk"));
+    LCS_TRY(check_ptr(x, "x"));
+    LCS_TRY(check_ptr(lam, "lam"));
+    LCS_TRY(check_ptr(grad, "grad"));
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipStream_t s = (hipStream_t)stream;
+    if (kind == LCS_STENCIL5_2D)
+        hipLaunchKernelGGL(k_grad_logk<2>, dim3(flat_grid(n)), dim3(kBlock), 0, s, nx, ny, nz, logk,
+                           x, lam, grad);
+    else
+        hipLaunchKernelGGL(k_grad_logk<3>, dim3(flat_grid(n)), dim3(kBlock), 0, s, nx, ny, nz, logk,
+                           x, lam, grad);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+}  // extern "C"

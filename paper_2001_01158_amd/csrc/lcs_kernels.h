@@ -1,0 +1,790 @@
+// HIP kernels of the local character-based solver (gfx950, wave64).
+//
+// Per-row kernels use a chunked grid: block b (after the XCD remap) owns rows
+// [b*chunk, (b+1)*chunk) and walks them 256 at a time, so loads are
+// coalesced and stencil neighbours stay in the owning XCD's L2.  Kernels
+// that reduce finish in the last block to arrive (deterministic order) and
+// leave their result in device state read by the next kernel, so a solve is
+// a stream of launches with no host round trip per iteration.
+#pragma once
+
+#include "lcs_device.h"
+
+namespace lcs {
+
+// ---------------------------------------------------------------------------
+// device state
+// ---------------------------------------------------------------------------
+struct MarkState {
+    double tau;       // threshold in use
+    double smax;      // max |s_i|
+    double bb;        // ||b||^2 (fixed-order block tree)
+    int64_t K;        // |Omega| after compaction
+    int32_t stop;     // an expansion round added nothing: later rounds are no-ops
+    int32_t grown;    // rounds that added points
+};
+
+struct PcgState {
+    double rz, alpha, beta, rr, tol, rr0, pq, rmax;
+    int32_t it, max_iter, done, status, first, pad;
+};
+
+enum : int32_t { kStOk = 0, kStNoConv = 4, kStBreakdown = 5, kStNonFinite = 6 };
+
+struct Scalars {
+    MarkState ms;
+    PcgState pcg;
+    double bnorm;        // ||b||_2
+    double scale;        // refinement step scale max|r| (mixed precision)
+    int64_t gather_nnz;  // nnz of the restricted matrix
+    int32_t bad_idx;     // a caller-supplied domain was out of range or not ascending
+    int32_t pad;
+    unsigned counters[16];
+};
+
+enum CounterSlot { kCntScore = 0, kCntExpand, kCntCount, kCntScan, kCntInit, kCntAp, kCntUpd,
+                   kCntSgs, kCntRes, kCntNorm };
+
+// ---------------------------------------------------------------------------
+// scores of Algorithms 2 and 3
+// ---------------------------------------------------------------------------
+// Residual mode: s = r^(0) = b - A x0 (FMA chain, ascending columns).
+// Gradient mode: s = g, g_i = sum_{j != i} |x_i - x_j| (eq. grad).
+// The last block sets tau: REL_MAX theta*max|s|, ABS theta,
+// PAPER theta*||b||_2/sqrt(N).
+template <class Op, int kMode>
+__global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict__ b,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ s, int64_t chunk,
+                                                  int thresh, double theta, Scalars *sc,
+                                                  double *partials) {
+    const Chunk c = my_chunk(A.n, chunk);
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        double acc;
+        if (kMode == 0) {
+            acc = b[i];
+            A.for_each(i, [&](int64_t j, double a) { acc = fma(-a, x[j], acc); });
+            const double bi = b[i];
+            v[1] += bi * bi;
+        } else {
+            const double xi = x[i];
+            acc = 0.0;
+            A.for_each(i, [&](int64_t j, double) {
+                if (j != i) acc += fabs(xi - x[j]);
+            });
+        }
+        s[i] = acc;
+        const double m = fabs(acc);
+        v[0] = m > v[0] ? m : v[0];
+    }
+    double tot[2];
+    if (last_block_reduce<double, 2>(v, Ops<1u>(), partials, &sc->counters[kCntScore], tot)) {
+        if (threadIdx.x == 0) {
+            double tau;
+            if (thresh == 0) tau = theta * tot[0];
+            else if (thresh == 1) tau = theta;
+            else tau = theta * sqrt(tot[1]) / sqrt((double)A.n);
+            sc->ms.tau = tau;
+            sc->ms.smax = tot[0];
+            sc->ms.bb = tot[1];
+            sc->ms.stop = 0;
+            sc->ms.grown = 0;
+        }
+    }
+}
+
+// stamp_i = 1 if |s_i| > tau (strict), else 0; zero on the padding [n, npad).
+__global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
+                                                 uint8_t *__restrict__ stamp, int64_t n,
+                                                 int64_t npad, const Scalars *sc) {
+    const double tau = sc->ms.tau;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < npad;
+         i += (int64_t)gridDim.x * kBlock)
+        stamp[i] = (i < n && fabs(s[i]) > tau) ? 1 : 0;
+}
+
+// One synchronous expansion round m (Algorithm 3, eq. extend-local-condition):
+// j outside Omega with a stored neighbour l in Omega (stamp 1..m) joins if
+// |r_j| + sum_{l in Omega, ascending} |a_jl x_l| > tau.  New members get
+// stamp m+1, which this round's readers treat as "outside".
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_expand(Op A, const double *__restrict__ r,
+                                                   const double *__restrict__ x,
+                                                   uint8_t *stamp, int m, int64_t chunk,
+                                                   Scalars *sc, double *partials) {
+    if (sc->ms.stop) return;
+    const Chunk c = my_chunk(A.n, chunk);
+    const double tau = sc->ms.tau;
+    double v[1] = {0.0};
+    for (int64_t j = c.begin + threadIdx.x; j < c.end; j += kBlock) {
+        if (stamp[j] != 0) continue;
+        bool nb = false;
+        double acc = fabs(r[j]);
+        A.for_each(j, [&](int64_t l, double a) {
+            const int sl = stamp[l];
+            if (l != j && sl != 0 && sl <= m) {
+                nb = true;
+                acc += fabs(a * x[l]);
+            }
+        });
+        if (nb && acc > tau) {
+            stamp[j] = (uint8_t)(m + 1);
+            v[0] += 1.0;
+        }
+    }
+    double tot[1];
+    if (last_block_reduce<double, 1>(v, Ops<0u>(), partials, &sc->counters[kCntExpand], tot)) {
+        if (threadIdx.x == 0) {
+            if (tot[0] == 0.0) sc->ms.stop = 1;
+            else sc->ms.grown += 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stream compaction: stamps -> idx (ascending), inv, K
+// ---------------------------------------------------------------------------
+// Tiles of 2048 stamps; thread t of a tile owns bytes [8t, 8t+8) read as one
+// 64-bit word.
+constexpr int kTile = kBlock * 8;
+
+__device__ __forceinline__ int nonzero_bytes(uint64_t w) {
+    uint64_t t = w | (w >> 4);
+    t |= t >> 2;
+    t |= t >> 1;
+    t &= 0x0101010101010101ull;
+    return __popcll(t);
+}
+
+// exclusive block scan of one int per thread; returns the prefix and the total
+__device__ __forceinline__ int block_exclusive_scan(int v, int &total) {
+    __shared__ int wsum[kWaves];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        if (q < w) base += wsum[q];
+        tot += wsum[q];
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+// Per-block count of members; the last block turns the counts into block
+// offsets (exclusive scan in block order) and K.
+__global__ __launch_bounds__(kBlock) void k_count(const uint8_t *__restrict__ stamp,
+                                                  int64_t ntiles, int64_t tiles_per_block,
+                                                  int32_t *blockoff, Scalars *sc) {
+    const int64_t lb = blockIdx.x;
+    const int64_t t0 = lb * tiles_per_block;
+    int64_t t1 = t0 + tiles_per_block;
+    if (t1 > ntiles) t1 = ntiles;
+    int cnt = 0;
+    const uint64_t *w = reinterpret_cast<const uint64_t *>(stamp);
+    for (int64_t t = t0; t < t1; ++t) cnt += nonzero_bytes(w[t * kBlock + threadIdx.x]);
+    __shared__ int red[kWaves];
+    int c = cnt;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
+    __syncthreads();
+    __shared__ bool is_last;
+    const unsigned g = gridDim.x;
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int q = 0; q < kWaves; ++q) s += red[q];
+        blockoff[blockIdx.x] = s;
+        __threadfence();
+        is_last = atomicAdd(&sc->counters[kCntCount], 1u) == g - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    // exclusive scan of g <= 8*kBlock counts, 8 consecutive per thread
+    int loc[8];
+    int mine = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const unsigned b = threadIdx.x * 8 + k;
+        loc[k] = b < g ? blockoff[b] : 0;
+        mine += loc[k];
+    }
+    int total;
+    int base = block_exclusive_scan(mine, total);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const unsigned b = threadIdx.x * 8 + k;
+        if (b < g) blockoff[b] = base;
+        base += loc[k];
+    }
+    if (threadIdx.x == 0) {
+        sc->ms.K = total;
+        sc->counters[kCntCount] = 0u;
+    }
+}
+
+// idx[pos] = i for members in ascending i; inv[i] = pos or -1.
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint8_t *__restrict__ stamp, int64_t n,
+                                                    int64_t ntiles, int64_t tiles_per_block,
+                                                    const int32_t *__restrict__ blockoff,
+                                                    int32_t *__restrict__ idx,
+                                                    int32_t *__restrict__ inv) {
+    const int64_t lb = blockIdx.x;
+    const int64_t t0 = lb * tiles_per_block;
+    int64_t t1 = t0 + tiles_per_block;
+    if (t1 > ntiles) t1 = ntiles;
+    int off = blockoff[blockIdx.x];
+    const uint64_t *w = reinterpret_cast<const uint64_t *>(stamp);
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint64_t word = w[t * kBlock + threadIdx.x];
+        const int c = nonzero_bytes(word);
+        int total;
+        int pos = off + block_exclusive_scan(c, total);
+        const int64_t row0 = t * kTile + (int64_t)threadIdx.x * 8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = row0 + k;
+            if (i >= n) break;
+            if ((word >> (8 * k)) & 0xffull) {
+                idx[pos] = (int32_t)i;
+                inv[i] = pos;
+                ++pos;
+            } else {
+                inv[i] = -1;
+            }
+        }
+        off += total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// generic exclusive scan of int32 (row lengths -> CSR row pointers)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ in, int64_t n,
+                                                        int64_t tiles_per_block,
+                                                        int32_t *blocksum, Scalars *sc) {
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+    int s = 0;
+    for (int64_t t = t0; t < t0 + tiles_per_block; ++t) {
+        const int64_t base = t * kTile + (int64_t)threadIdx.x * 8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (base + k < n) s += in[base + k];
+    }
+    __shared__ int red[kWaves];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    __shared__ bool is_last;
+    const unsigned g = gridDim.x;
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int q = 0; q < kWaves; ++q) a += red[q];
+        blocksum[blockIdx.x] = a;
+        __threadfence();
+        is_last = atomicAdd(&sc->counters[kCntScan], 1u) == g - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    int loc[8];
+    int mine = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const unsigned b = threadIdx.x * 8 + k;
+        loc[k] = b < g ? blocksum[b] : 0;
+        mine += loc[k];
+    }
+    int total;
+    int base = block_exclusive_scan(mine, total);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const unsigned b = threadIdx.x * 8 + k;
+        if (b < g) blocksum[b] = base;
+        base += loc[k];
+    }
+    if (threadIdx.x == 0) {
+        sc->gather_nnz = total;
+        sc->counters[kCntScan] = 0u;
+    }
+}
+
+// out[i] = sum_{k<i} in[k]; out[n] = total.
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict__ in, int64_t n,
+                                                       int64_t tiles_per_block,
+                                                       const int32_t *__restrict__ blockoff,
+                                                       int32_t *__restrict__ out,
+                                                       const Scalars *sc) {
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+    int off = blockoff[blockIdx.x];
+    for (int64_t t = t0; t < t0 + tiles_per_block; ++t) {
+        const int64_t base = t * kTile + (int64_t)threadIdx.x * 8;
+        int loc[8];
+        int mine = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            loc[k] = base + k < n ? in[base + k] : 0;
+            mine += loc[k];
+        }
+        int total;
+        int p = off + block_exclusive_scan(mine, total);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (base + k < n) out[base + k] = p;
+            p += loc[k];
+        }
+        off += total;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int32_t)sc->gather_nnz;
+}
+
+// ---------------------------------------------------------------------------
+// restricted system B = A[Omega, Omega] (eq. BEFC)
+// ---------------------------------------------------------------------------
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_gather_count(Op A, const int32_t *__restrict__ idx,
+                                                         int64_t K,
+                                                         const int32_t *__restrict__ inv,
+                                                         int32_t *__restrict__ rowlen) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock) {
+        int c = 0;
+        A.for_each(idx[k], [&](int64_t j, double) { c += inv[j] >= 0; });
+        rowlen[k] = c;
+    }
+}
+
+// Fills CSR columns (renumbered through inv, order kept), FP64 and FP32
+// values, the diagonal, the colour of each row and rhs_B = r^(0)_Omega
+// (right-hand side of the correction form of eq. loc-equ).
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_gather_fill(
+    Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv,
+    const int32_t *__restrict__ rp, int32_t *__restrict__ col, double *__restrict__ val,
+    float *__restrict__ val32, double *__restrict__ dg, float *__restrict__ dg32,
+    uint8_t *__restrict__ clr, const double *__restrict__ r, double *__restrict__ rhs) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = idx[k];
+        int32_t t = rp[k];
+        A.for_each(i, [&](int64_t j, double a) {
+            const int32_t cj = inv[j];
+            if (cj >= 0) {
+                col[t] = cj;
+                val[t] = a;
+                if (val32) val32[t] = (float)a;
+                ++t;
+            }
+        });
+        const double d = A.diag(i);
+        dg[k] = d;
+        if (dg32) dg32[k] = (float)d;
+        clr[k] = (uint8_t)A.colour(i);
+        if (rhs) rhs[k] = r[i];
+    }
+}
+
+// inv[idx[k]] = k for a caller-supplied domain (inv pre-filled with -1).
+// Entries out of [0, n) or not strictly ascending are skipped and flagged.
+__global__ __launch_bounds__(kBlock) void k_set_inv(const int32_t *__restrict__ idx, int64_t K,
+                                                    int64_t n, int32_t *__restrict__ inv,
+                                                    Scalars *sc) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock) {
+        const int32_t i = idx[k];
+        const bool ok = i >= 0 && i < n && (k == 0 || idx[k - 1] < i);
+        if (ok) inv[i] = (int32_t)k;
+        else atomicOr(&sc->bad_idx, 1);
+    }
+}
+
+// x[idx[k]] += d[k]  (eq. sol-assemble in correction form)
+__global__ __launch_bounds__(kBlock) void k_scatter_add(const int32_t *__restrict__ idx,
+                                                        const double *__restrict__ d, int64_t K,
+                                                        double *__restrict__ x) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock)
+        x[idx[k]] += d[k];
+}
+
+// ---------------------------------------------------------------------------
+// preconditioned CG (templated on operator and working precision)
+// ---------------------------------------------------------------------------
+// init: r = rhs - A x (or r = rhs when x = 0), rr; Jacobi: z = r / a_ii, rz;
+// RB-SGS: z = 0 (filled by the half sweeps).  The last block sets the
+// absolute tolerance (tol_factor * *tol_base, or tol_factor * ||r_0|| when
+// tol_base is null) and flags convergence of the initial iterate.
+template <class Op, typename real, int kPc>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const real *__restrict__ rhs,
+                                                     const real *__restrict__ x,
+                                                     real *__restrict__ r, real *__restrict__ z,
+                                                     int64_t chunk, int x_zero,
+                                                     const double *tol_base, double tol_factor,
+                                                     int max_iter, Scalars *sc, real *partials) {
+    const Chunk c = my_chunk(A.n, chunk);
+    real v[2] = {real(0), real(0)};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        real acc = rhs[i];
+        if (!x_zero) A.for_each(i, [&](int64_t j, real a) { acc = fma(-a, x[j], acc); });
+        r[i] = acc;
+        v[0] += acc * acc;
+        if (kPc == 1) {
+            const real zi = acc / A.diag(i);
+            z[i] = zi;
+            v[1] += acc * zi;
+        } else if (kPc == 2) {
+            z[i] = real(0);
+        } else {
+            z[i] = acc;
+            v[1] += acc * acc;
+        }
+    }
+    real tot[2];
+    if (last_block_reduce<real, 2>(v, Ops<0u>(), partials, &sc->counters[kCntInit], tot)) {
+        if (threadIdx.x == 0) {
+            PcgState &p = sc->pcg;
+            const double rr = (double)tot[0];
+            p.rr = rr;
+            p.rr0 = rr;
+            p.it = 0;
+            p.max_iter = max_iter;
+            p.first = 1;
+            p.rz = (double)tot[1];
+            p.tol = tol_base ? tol_factor * *tol_base : tol_factor * sqrt(rr);
+            p.status = kStOk;
+            p.done = 0;
+            if (!(rr == rr) || rr > 1.7e308) {
+                p.status = kStNonFinite;
+                p.done = 1;
+            } else if (sqrt(rr) <= p.tol) {
+                p.done = 1;
+            } else if (max_iter <= 0) {
+                p.status = kStNoConv;
+                p.done = 1;
+            }
+        }
+    }
+}
+
+// q = A p with p = z (first) or p = z + beta p_old, recomputed for each
+// neighbour so that p can be updated in the same pass (p_new written for
+// the own row only).  p.q -> alpha = rz / p.q.
+template <class Op, typename real>
+__global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const real *__restrict__ z,
+                                                   const real *__restrict__ pold,
+                                                   real *__restrict__ pnew, real *__restrict__ q,
+                                                   int64_t chunk, Scalars *sc, real *partials) {
+    if (sc->pcg.done) return;
+    const int first = sc->pcg.first;
+    const real beta = (real)sc->pcg.beta;
+    const Chunk c = my_chunk(A.n, chunk);
+    real v[1] = {real(0)};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        real acc = real(0);
+        if (first) {
+            A.for_each(i, [&](int64_t j, real a) { acc = fma(a, z[j], acc); });
+            const real pi = z[i];
+            pnew[i] = pi;
+            q[i] = acc;
+            v[0] += pi * acc;
+        } else {
+            A.for_each(i, [&](int64_t j, real a) { acc = fma(a, fma(beta, pold[j], z[j]), acc); });
+            const real pi = fma(beta, pold[i], z[i]);
+            pnew[i] = pi;
+            q[i] = acc;
+            v[0] += pi * acc;
+        }
+    }
+    real tot[1];
+    if (last_block_reduce<real, 1>(v, Ops<0u>(), partials, &sc->counters[kCntAp], tot)) {
+        if (threadIdx.x == 0) {
+            PcgState &p = sc->pcg;
+            p.first = 0;
+            const double pq = (double)tot[0];
+            p.pq = pq;
+            if (!(pq > 0.0)) {
+                p.status = (pq == pq) ? kStBreakdown : kStNonFinite;
+                p.done = 1;
+            } else {
+                p.alpha = (double)((real)p.rz / (real)pq);
+            }
+        }
+    }
+}
+
+// x += alpha p; r -= alpha q; Jacobi: z = r / a_ii; partials r.r (and r.z).
+// The last block counts the iteration, tests ||r|| <= tol and max_iter, and
+// (Jacobi) forms beta = r.z_new / r.z.
+template <class Op, typename real, int kPc>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, real *__restrict__ x,
+                                                       const real *__restrict__ p,
+                                                       const real *__restrict__ q,
+                                                       real *__restrict__ r, real *__restrict__ z,
+                                                       int64_t chunk, Scalars *sc, real *partials) {
+    if (sc->pcg.done) return;
+    const real alpha = (real)sc->pcg.alpha;
+    const Chunk c = my_chunk(A.n, chunk);
+    real v[2] = {real(0), real(0)};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const real ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        v[0] += ri * ri;
+        if (kPc == 1) {
+            const real zi = ri / A.diag(i);
+            z[i] = zi;
+            v[1] += ri * zi;
+        } else if (kPc == 2) {
+            z[i] = real(0);
+        } else {
+            z[i] = ri;
+            v[1] += ri * ri;
+        }
+    }
+    real tot[2];
+    if (last_block_reduce<real, 2>(v, Ops<0u>(), partials, &sc->counters[kCntUpd], tot)) {
+        if (threadIdx.x == 0) {
+            PcgState &s = sc->pcg;
+            const double rr = (double)tot[0];
+            s.rr = rr;
+            s.it += 1;
+            if (!(rr == rr)) {
+                s.status = kStNonFinite;
+                s.done = 1;
+            } else if (sqrt(rr) <= s.tol) {
+                s.status = kStOk;
+                s.done = 1;
+            } else if (s.it >= s.max_iter) {
+                s.status = kStNoConv;
+                s.done = 1;
+            } else if (kPc != 2) {
+                const real rzn = tot[1];
+                s.beta = (double)(rzn / (real)s.rz);
+                s.rz = (double)rzn;
+            }
+        }
+    }
+}
+
+// One Gauss-Seidel half sweep over colour c: for rows of that colour,
+// z_i = (r_i - sum_{j != i, ascending} a_ij z_j) / a_ii.  Rows of one colour
+// never couple, so the update is order-free.  With kRz the last block forms
+// r.z (all rows) and beta (or the initial r.z).  With a null state this is
+// the smoother of Algorithm 1 (r = b, z = x).
+template <class Op, typename real, bool kRz>
+__global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const real *__restrict__ r,
+                                                    real *z, int colour, int64_t chunk,
+                                                    Scalars *sc, real *partials) {
+    if (sc && sc->pcg.done) return;
+    const Chunk c = my_chunk(A.n, chunk);
+    real v[1] = {real(0)};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        const real ri = r[i];
+        real zi;
+        if (A.colour(i) == colour) {
+            real acc = ri, d = real(1);
+            A.for_each(i, [&](int64_t j, real a) {
+                if (j == i) d = a;
+                else acc = fma(-a, z[j], acc);
+            });
+            zi = acc / d;
+            z[i] = zi;
+        } else {
+            zi = z[i];
+        }
+        if (kRz) v[0] += ri * zi;
+    }
+    if (!kRz) return;
+    real tot[1];
+    if (last_block_reduce<real, 1>(v, Ops<0u>(), partials, &sc->counters[kCntSgs], tot)) {
+        if (threadIdx.x == 0) {
+            PcgState &s = sc->pcg;
+            const real rzn = tot[0];
+            if (!s.first) s.beta = (double)(rzn / (real)s.rz);
+            s.rz = (double)rzn;
+        }
+    }
+}
+
+// r = rhs - A x in FP64 with ||r||^2 and max|r|; the last block stores them
+// and flags done when ||r|| <= tol_factor * *tol_base.
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_resnorm(Op A, const double *__restrict__ rhs,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ r, int64_t chunk,
+                                                    const double *tol_base, double tol_factor,
+                                                    Scalars *sc, double *partials) {
+    const Chunk c = my_chunk(A.n, chunk);
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        double acc = rhs[i];
+        A.for_each(i, [&](int64_t j, double a) { acc = fma(-a, x[j], acc); });
+        if (r) r[i] = acc;
+        v[0] += acc * acc;
+        const double m = fabs(acc);
+        v[1] = m > v[1] ? m : v[1];
+    }
+    double tot[2];
+    if (last_block_reduce<double, 2>(v, Ops<2u>(), partials, &sc->counters[kCntRes], tot)) {
+        if (threadIdx.x == 0) {
+            PcgState &s = sc->pcg;
+            s.rr = tot[0];
+            s.rmax = tot[1];
+            s.tol = tol_factor * *tol_base;
+            s.done = sqrt(tot[0]) <= s.tol ? 1 : 0;
+            s.status = (tot[0] == tot[0]) ? kStOk : kStNonFinite;
+            if (s.status != kStOk) s.done = 1;
+        }
+    }
+}
+
+// ||v||_2 -> *out (fixed-order tree)
+__global__ __launch_bounds__(kBlock) void k_norm2(const double *__restrict__ v, int64_t n,
+                                                  int64_t chunk, double *out, Scalars *sc,
+                                                  double *partials) {
+    const Chunk c = my_chunk(n, chunk);
+    double a[1] = {0.0};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) a[0] += v[i] * v[i];
+    double tot[1];
+    if (last_block_reduce<double, 1>(a, Ops<0u>(), partials, &sc->counters[kCntNorm], tot))
+        if (threadIdx.x == 0) *out = sqrt(tot[0]);
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision refinement helpers
+// ---------------------------------------------------------------------------
+// r32 = (float)(r / s) with s = max|r| (keeps the FP32 residual near 1 and
+// clear of denormals); block 0 records s for the update.
+__global__ __launch_bounds__(kBlock) void k_cast_scale(const double *__restrict__ r,
+                                                       float *__restrict__ r32, int64_t n,
+                                                       Scalars *sc) {
+    const double s = sc->pcg.rmax > 0.0 ? sc->pcg.rmax : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->scale = s;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        r32[i] = (float)(r[i] / s);
+}
+
+// x += s * d32 in FP64 with the scale of the current refinement step
+__global__ __launch_bounds__(kBlock) void k_axpy_scaled(double *__restrict__ x,
+                                                        const float *__restrict__ d32,
+                                                        int64_t n, const Scalars *sc) {
+    const double s = sc->scale;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        x[i] = fma(s, (double)d32[i], x[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast(const double *__restrict__ a,
+                                                 float *__restrict__ b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        b[i] = (float)a[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ a, T v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        a[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(T *__restrict__ dst, const T *__restrict__ src,
+                                                 int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+// y = A x (measurement of the stencil SpMV on its own)
+template <class Op, typename real>
+__global__ __launch_bounds__(kBlock) void k_spmv(Op A, const real *__restrict__ x,
+                                                 real *__restrict__ y, int64_t chunk) {
+    const Chunk c = my_chunk(A.n, chunk);
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        real acc = real(0);
+        A.for_each(i, [&](int64_t j, real a) { acc = fma(a, x[j], acc); });
+        y[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint helpers: operator from log-conductivity and its derivative
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double harmonic(double kp, double kq) { return 2.0 * kp * kq / (kp + kq); }
+
+// one thread per cell: the cell's own forward faces plus the diagonal sum of
+// all its faces (each face value recomputed by both cells: no atomics)
+template <int kDim>
+__global__ __launch_bounds__(kBlock) void k_assemble_logk(int nx, int ny, int nz, double inv_dt,
+                                                          const double *__restrict__ logk,
+                                                          double *__restrict__ coef) {
+    const int64_t n = (int64_t)nx * ny * nz, pl = (int64_t)nx * ny;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int z = (int)(i / pl);
+        const int rr = (int)(i - (int64_t)z * pl);
+        const int y = rr / nx, x = rr - y * nx;
+        const double kp = exp(logk[i]);
+        double tw = 0, te = 0, ts = 0, tn = 0, td = 0, tu = 0;
+        if (x > 0) tw = harmonic(exp(logk[i - 1]), kp);
+        if (x < nx - 1) te = harmonic(kp, exp(logk[i + 1]));
+        if (y > 0) ts = harmonic(exp(logk[i - nx]), kp);
+        if (y < ny - 1) tn = harmonic(kp, exp(logk[i + nx]));
+        if (kDim == 3) {
+            if (z > 0) td = harmonic(exp(logk[i - pl]), kp);
+            if (z < nz - 1) tu = harmonic(kp, exp(logk[i + pl]));
+        }
+        double d = inv_dt;
+        d += tw; d += te; d += ts; d += tn;
+        if (kDim == 3) { d += td; d += tu; }
+        coef[i] = d;
+        coef[n + i] = -te;
+        coef[2 * n + i] = -tn;
+        if (kDim == 3) coef[3 * n + i] = -tu;
+    }
+}
+
+template <int kDim>
+__global__ __launch_bounds__(kBlock) void k_grad_logk(int nx, int ny, int nz,
+                                                      const double *__restrict__ logk,
+                                                      const double *__restrict__ xv,
+                                                      const double *__restrict__ lam,
+                                                      double *__restrict__ grad) {
+    const int64_t n = (int64_t)nx * ny * nz, pl = (int64_t)nx * ny;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int z = (int)(i / pl);
+        const int rr = (int)(i - (int64_t)z * pl);
+        const int y = rr / nx, x = rr - y * nx;
+        const double kp = exp(logk[i]), xp = xv[i], lp = lam[i];
+        double s = 0.0;
+        auto face = [&](int64_t j) {
+            const double kq = exp(logk[j]);
+            const double t = harmonic(kp, kq);
+            const double dtdl = t * kq / (kp + kq);
+            s += dtdl * (xp - xv[j]) * (lp - lam[j]);
+        };
+        if (kDim == 3 && z > 0) face(i - pl);
+        if (y > 0) face(i - nx);
+        if (x > 0) face(i - 1);
+        if (x < nx - 1) face(i + 1);
+        if (y < ny - 1) face(i + nx);
+        if (kDim == 3 && z < nz - 1) face(i + pl);
+        grad[i] = -s;
+    }
+}
+
+}  // namespace lcs

@@ -1,0 +1,367 @@
+"""Python binding of the C ABI in include/lcs.h (argument marshalling only).
+
+Tensors are torch device tensors (FP64 vectors of length N, int32 index
+arrays); the binding passes their data pointers and the current HIP stream to
+liblcs.so.  Every step of the method runs in the library's kernels.  There is
+no fallback: if the library is missing or fails to load, the import raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblcs.so")
+
+OK, EINVAL, EHIP, ENOMEM, ENOCONV, EBREAKDOWN, ENONFINITE = range(7)
+STENCIL5_2D, STENCIL9_2D, STENCIL7_3D = 0, 1, 2
+MODE_RESIDUAL, MODE_GRADIENT = 0, 1
+THRESH_REL_MAX, THRESH_ABS, THRESH_PAPER = 0, 1, 2
+PC_NONE, PC_JACOBI, PC_RBSGS = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+N_ARRAYS = {STENCIL5_2D: 3, STENCIL9_2D: 5, STENCIL7_3D: 4}
+
+_MODES = {"residual": MODE_RESIDUAL, "gradient": MODE_GRADIENT}
+_THRESH = {"relmax": THRESH_REL_MAX, "abs": THRESH_ABS, "paper": THRESH_PAPER}
+_PC = {"none": PC_NONE, "jacobi": PC_JACOBI, "rbsgs": PC_RBSGS}
+_PREC = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
+
+EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error",
+            "lcs_solve_global", "lcs_build_local_domain", "lcs_solve_local",
+            "lcs_solve_local_then_global", "lcs_residual", "lcs_gradient", "lcs_spmv",
+            "lcs_gather_restricted", "lcs_gs_sweeps", "lcs_cast_coef", "lcs_assemble_logk",
+            "lcs_grad_logk"]
+
+
+class LcsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lcs status {status}: {msg}")
+        self.status = status
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("coef", ctypes.c_void_p), ("coef32", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("tol_local", ctypes.c_double),
+                ("inner_tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_smooth", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int64), ("e_rounds", ctypes.c_int32), ("its_local", ctypes.c_int32),
+                ("its_global", ctypes.c_int32), ("n_outer", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("relres_after_local", ctypes.c_double), ("relres_final", ctypes.c_double),
+                ("ms_construct", ctypes.c_double), ("ms_local", ctypes.c_double),
+                ("ms_smooth", ctypes.c_double), ("ms_global", ctypes.c_double)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblcs.so and declare the ABI.  Raises if it is missing."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2001_01158_amd.build`")
+    L = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    PM, PO, PS = ctypes.POINTER(_Matrix), ctypes.POINTER(_Options), ctypes.POINTER(_Stats)
+    sig = {
+        "lcs_default_options": (None, [PO]),
+        "lcs_create": (I32, [ctypes.POINTER(P)]),
+        "lcs_destroy": (None, [P]),
+        "lcs_last_error": (ctypes.c_char_p, []),
+        "lcs_solve_global": (I32, [P, PM, P, P, PO, PS, P]),
+        "lcs_build_local_domain": (I32, [P, PM, P, P, I32, I32, D, I32, P, P,
+                                         ctypes.POINTER(I64), PS, P]),
+        "lcs_solve_local": (I32, [P, PM, P, P, P, I64, PO, PS, P]),
+        "lcs_solve_local_then_global": (I32, [P, PM, P, P, I32, I32, D, I32, PO, PS, P]),
+        "lcs_residual": (I32, [P, PM, P, P, P, P]),
+        "lcs_gradient": (I32, [P, PM, P, P, P]),
+        "lcs_spmv": (I32, [P, PM, P, P, I32, I32, P]),
+        "lcs_gather_restricted": (I32, [P, PM, P, I64, P, P, P, ctypes.POINTER(I64), P]),
+        "lcs_gs_sweeps": (I32, [P, PM, P, P, I32, P]),
+        "lcs_cast_coef": (I32, [P, PM, P, P]),
+        "lcs_assemble_logk": (I32, [P, I32, I32, I32, I32, D, P, P, P]),
+        "lcs_grad_logk": (I32, [P, I32, I32, I32, I32, P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise LcsError(status, lib().lcs_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _vec(t: torch.Tensor, n: int, dtype=torch.float64, name: str = "vector"):
+    if t.dtype != dtype or t.numel() != n:
+        raise ValueError(f"{name}: expected {dtype} with {n} elements, got {t.dtype} {t.numel()}")
+    return _ptr(t)
+
+
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Matrix:
+    """Symmetric structured-grid stencil (see include/lcs.h for the layout)."""
+    kind: int
+    nx: int
+    ny: int
+    nz: int
+    coef: torch.Tensor                    # (n_arrays, N) float64, device
+    coef32: Optional[torch.Tensor] = None  # (n_arrays, N) float32, device
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def c(self) -> _Matrix:
+        if self.coef.dtype != torch.float64 or self.coef.numel() != N_ARRAYS[self.kind] * self.n:
+            raise ValueError("coef must be float64 of shape (n_arrays, N)")
+        if self.coef32 is not None and (self.coef32.dtype != torch.float32
+                                        or self.coef32.numel() != self.coef.numel()):
+            raise ValueError("coef32 must be float32 of the same shape as coef")
+        return _Matrix(self.kind, self.nx, self.ny, self.nz, _ptr(self.coef), _ptr(self.coef32))
+
+
+@dataclasses.dataclass
+class Options:
+    eps: float = 1e-10
+    tol_local: float = 0.0
+    inner_tol: float = 1e-5
+    max_iter: int = 20000
+    precond: str = "jacobi"
+    precision: str = "fp64"
+    n_smooth: int = 1
+    check_every: int = 8
+    max_outer: int = 10
+
+    def c(self) -> _Options:
+        return _Options(self.eps, self.tol_local, self.inner_tol, self.max_iter, _PC[self.precond],
+                        _PREC[self.precision], self.n_smooth, self.check_every, self.max_outer)
+
+
+@dataclasses.dataclass
+class Stats:
+    K: int = 0
+    e_rounds: int = 0
+    its_local: int = 0
+    its_global: int = 0
+    n_outer: int = 0
+    tau: float = 0.0
+    relres_after_local: float = float("nan")
+    relres_final: float = float("nan")
+    ms_construct: float = 0.0
+    ms_local: float = 0.0
+    ms_smooth: float = 0.0
+    ms_global: float = 0.0
+
+    @staticmethod
+    def of(s: _Stats) -> "Stats":
+        return Stats(**{f: getattr(s, f) for f, _ in _Stats._fields_})
+
+
+class Context:
+    """Owns a device workspace (lcs_create / lcs_destroy)."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+        _check(lib().lcs_create(ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().lcs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Optional[Context] = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def _ctx(ctx):
+    return (ctx or default_context()).handle
+
+
+# ---------------------------------------------------------------------------
+# the four calls of the method
+# ---------------------------------------------------------------------------
+def solve_global(A: Matrix, b: torch.Tensor, x: torch.Tensor, opts: Options = None,
+                 ctx: Context = None) -> Stats:
+    """Global PCG from x (in place) to ||b - A x|| <= eps ||b||."""
+    opts = opts or Options()
+    st = _Stats()
+    o = opts.c()
+    _check(lib().lcs_solve_global(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+                                  _vec(x, A.n, name="x"), ctypes.byref(o), ctypes.byref(st), _stream()))
+    return Stats.of(st)
+
+
+def build_local_domain(A: Matrix, b: torch.Tensor, x0: torch.Tensor, mode: str = "residual",
+                       thresh: str = "relmax", theta: float = 1e-3, e_max: int = 1,
+                       want_mask: bool = False, ctx: Context = None):
+    """Algorithm 2 / 3.  Returns (idx[K] int32 device tensor, mask or None, Stats)."""
+    idx = torch.empty(max(A.n, 1), dtype=torch.int32, device=b.device)
+    mask = torch.empty(A.n, dtype=torch.uint8, device=b.device) if want_mask else None
+    K = ctypes.c_int64(0)
+    st = _Stats()
+    _check(lib().lcs_build_local_domain(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+                                        _vec(x0, A.n, name="x0"), _MODES[mode], _THRESH[thresh],
+                                        float(theta), int(e_max), _ptr(idx), _ptr(mask),
+                                        ctypes.byref(K), ctypes.byref(st), _stream()))
+    return idx[:K.value], mask, Stats.of(st)
+
+
+def solve_local(A: Matrix, b: torch.Tensor, x: torch.Tensor, idx: torch.Tensor,
+                opts: Options = None, ctx: Context = None) -> Stats:
+    """Steps 3-7 of Algorithm 1 on the given domain; x: in x^(0), out x~."""
+    opts = opts or Options()
+    if idx.dtype != torch.int32:
+        raise ValueError("idx must be int32")
+    idx = idx.contiguous()
+    st = _Stats()
+    o = opts.c()
+    _check(lib().lcs_solve_local(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+                                 _vec(x, A.n, name="x"), _ptr(idx) if idx.numel() else None,
+                                 idx.numel(), ctypes.byref(o), ctypes.byref(st), _stream()))
+    return Stats.of(st)
+
+
+def solve_local_then_global(A: Matrix, b: torch.Tensor, x: torch.Tensor, mode: str = "residual",
+                            thresh: str = "relmax", theta: float = 1e-3, e_max: int = 1,
+                            opts: Options = None, ctx: Context = None) -> Stats:
+    """Algorithm 1; x: in x^(0), out the solution."""
+    opts = opts or Options()
+    st = _Stats()
+    o = opts.c()
+    _check(lib().lcs_solve_local_then_global(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+                                             _vec(x, A.n, name="x"), _MODES[mode], _THRESH[thresh],
+                                             float(theta), int(e_max), ctypes.byref(o),
+                                             ctypes.byref(st), _stream()))
+    return Stats.of(st)
+
+
+# ---------------------------------------------------------------------------
+# pieces of the path
+# ---------------------------------------------------------------------------
+def residual(A: Matrix, b: torch.Tensor, x: torch.Tensor, ctx: Context = None) -> torch.Tensor:
+    r = torch.empty_like(b)
+    _check(lib().lcs_residual(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+                              _vec(x, A.n, name="x"), _ptr(r), _stream()))
+    return r
+
+
+def gradient(A: Matrix, x: torch.Tensor, ctx: Context = None) -> torch.Tensor:
+    g = torch.empty_like(x)
+    _check(lib().lcs_gradient(_ctx(ctx), ctypes.byref(A.c()), _vec(x, A.n, name="x"), _ptr(g),
+                              _stream()))
+    return g
+
+
+def spmv(A: Matrix, x: torch.Tensor, y: torch.Tensor, reps: int = 1, ctx: Context = None):
+    prec = PREC_FP64 if x.dtype == torch.float64 else PREC_MIXED
+    dt = torch.float64 if prec == PREC_FP64 else torch.float32
+    _check(lib().lcs_spmv(_ctx(ctx), ctypes.byref(A.c()), _vec(x, A.n, dt, "x"), _vec(y, A.n, dt, "y"),
+                          prec, int(reps), _stream()))
+    return y
+
+
+def gather_restricted(A: Matrix, idx: torch.Tensor, ctx: Context = None):
+    """B = A[idx, idx] as (row_ptr int32[K+1], col int32[nnz], val float64[nnz])."""
+    K = idx.numel()
+    dev = A.coef.device
+    rp = torch.zeros(K + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(max(9 * K, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(9 * K, 1), dtype=torch.float64, device=dev)
+    nnz = ctypes.c_int64(0)
+    _check(lib().lcs_gather_restricted(_ctx(ctx), ctypes.byref(A.c()),
+                                       _ptr(idx.contiguous()) if K else None, K, _ptr(rp), _ptr(col),
+                                       _ptr(val), ctypes.byref(nnz), _stream()))
+    return rp, col[:nnz.value], val[:nnz.value]
+
+
+def gs_sweeps(A: Matrix, b: torch.Tensor, x: torch.Tensor, n_sweeps: int = 1, ctx: Context = None):
+    _check(lib().lcs_gs_sweeps(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+                               _vec(x, A.n, name="x"), int(n_sweeps), _stream()))
+    return x
+
+
+def cast_coef(A: Matrix, ctx: Context = None) -> torch.Tensor:
+    c32 = torch.empty(A.coef.shape, dtype=torch.float32, device=A.coef.device)
+    _check(lib().lcs_cast_coef(_ctx(ctx), ctypes.byref(A.c()), _ptr(c32), _stream()))
+    return c32
+
+
+def assemble_logk(kind: int, nx: int, ny: int, nz: int, inv_dt: float, logk: torch.Tensor,
+                  ctx: Context = None) -> torch.Tensor:
+    n = nx * ny * nz
+    coef = torch.empty((N_ARRAYS[kind], n), dtype=torch.float64, device=logk.device)
+    _check(lib().lcs_assemble_logk(_ctx(ctx), kind, nx, ny, nz, float(inv_dt),
+                                   _vec(logk.contiguous(), n, name="logk"), _ptr(coef), _stream()))
+    return coef
+
+
+def grad_logk(kind: int, nx: int, ny: int, nz: int, logk: torch.Tensor, x: torch.Tensor,
+              lam: torch.Tensor, ctx: Context = None) -> torch.Tensor:
+    n = nx * ny * nz
+    g = torch.empty(n, dtype=torch.float64, device=x.device)
+    _check(lib().lcs_grad_logk(_ctx(ctx), kind, nx, ny, nz, _vec(logk.contiguous(), n, name="logk"),
+                               _vec(x, n, name="x"), _vec(lam, n, name="lam"), _ptr(g), _stream()))
+    return g
+
+
+def matrix_from_numpy(kind: int, nx: int, ny: int, nz: int, coef, device="cuda",
+                      with32: bool = False) -> Matrix:
+    c = torch.as_tensor(coef, dtype=torch.float64).reshape(N_ARRAYS[kind], nx * ny * nz)
+    c = c.to(device).contiguous()
+    M = Matrix(kind, nx, ny, nz, c)
+    if with32:
+        M.coef32 = cast_coef(M)
+    return M

@@ -1,0 +1,343 @@
+"""GPU parity: the HIP path through the C ABI vs the CPU oracle.
+
+Both sides read the same input bytes (seeded generators).  Integer and set
+results (local domain, stamps, restricted CSR) and every per-row FMA-chain
+result (residual, gradient, Gauss-Seidel sweeps) must match bit for bit.
+Iterative results are compared (a) at equal iteration counts (trajectory
+parity: only the dot-product summation order differs) and (b) after
+convergence, against the criterion recomputed by the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_01158_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2001_01158_amd import lcs  # noqa: E402
+
+DEV = "cuda:0"
+PC = {"jacobi": oracle.PC_JACOBI, "rbsgs": oracle.PC_SGS, "none": oracle.PC_NONE}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+# ragged grids: sizes that are not multiples of the 256-row blocks or the
+# 2048-stamp compaction tiles, spanning several of each
+CASES = {
+    "5pt": (W.KIND_5PT, (93, 71, 1)),
+    "9pt": (W.KIND_9PT, (83, 67, 1)),
+    "7pt": (W.KIND_7PT, (23, 19, 17)),
+}
+
+
+def make_case(name, seed=0, dt=4.0):
+    kind, (nx, ny, nz) = CASES[name]
+    if kind == W.KIND_5PT:
+        logk = W.lognormal_logk((ny, nx), 1.0, 100 + seed)
+        coef = W.assemble_5pt(logk, 1.0 / dt)
+    elif kind == W.KIND_9PT:
+        coef = W.assemble_9pt(nx, ny, 1.0 / dt, 100.0, 30.0)
+    else:
+        logk = W.lognormal_logk((nz, ny, nx), 1.0, 100 + seed)
+        coef = W.assemble_7pt(logk, 1.0 / dt)
+    n = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    # previous state x_true (background + hot box); x0 differs from it only on
+    # a central box, so r^(0) = A (x_true - x0) is localized
+    x_true = np.full(n, 0.1)
+    g = x_true.reshape(nz, ny, nx)
+    g[nz // 3: nz // 3 + max(1, nz // 3), ny // 3: ny // 3 + 9, nx // 4: nx // 4 + 11] = 1.0
+    f = 0.62 if nz == 1 else 0.72
+    sl = tuple(slice(int(m * (1 - f) / 2), int(m * (1 - f) / 2) + max(1, int(m * f)))
+               for m in (nz, ny, nx))
+    Ah = oracle.csr_from_stencil(kind, nx, ny, nz, coef)
+    b = oracle.spmv(Ah, x_true)
+    x0 = x_true.copy()
+    box = x0.reshape(nz, ny, nx)[sl]
+    x0.reshape(nz, ny, nx)[sl] = box * (1.0 + 0.3 * rng.random(box.shape))
+    A = lcs.matrix_from_numpy(kind, nx, ny, nz, coef, DEV)
+    return kind, (nx, ny, nz), coef, Ah, A, b, x0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return lcs.Context()
+
+
+# ----------------------------------------------------------------------------
+# per-row kernels: bit-exact
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_and_gradient_bitexact(name, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("residual/gradient", name, dims)
+    r = host(lcs.residual(A, dev(b), dev(x0), ctx=ctx))
+    assert np.array_equal(r, oracle.residual(Ah, b, x0))
+    g = host(lcs.gradient(A, dev(x0), ctx=ctx))
+    assert np.array_equal(g, oracle.gradient(Ah, x0))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gs_sweeps_bitexact(name, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("gs sweeps", name, dims)
+    x = dev(x0)
+    lcs.gs_sweeps(A, dev(b), x, 2, ctx=ctx)
+    assert np.array_equal(host(x), oracle.gs_sweeps(Ah, b, x0, 2))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_fp64(name, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("spmv", name, dims)
+    y = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    lcs.spmv(A, dev(x0), y, ctx=ctx)
+    assert np.array_equal(host(y), oracle.spmv(Ah, x0))
+
+
+# ----------------------------------------------------------------------------
+# local domain (Algorithms 2 and 3): bit-exact sets and stamps
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("mode,thresh,theta,e_max", [
+    ("residual", "relmax", 1e-3, 0), ("residual", "relmax", 1e-3, 1),
+    ("residual", "relmax", 1e-5, 3), ("residual", "abs", 1e-7, 2),
+    ("gradient", "relmax", 1e-2, 0), ("gradient", "relmax", 1e-4, 2),
+    ("residual", "relmax", 1.0, 1), ("gradient", "relmax", 0.0, 0),
+])
+def test_local_domain_bitexact(name, mode, thresh, theta, e_max, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("domain", name, dims, mode, thresh, theta, e_max)
+    idx, mask, st = lcs.build_local_domain(A, dev(b), dev(x0), mode, thresh, theta, e_max,
+                                           want_mask=True, ctx=ctx)
+    om = {"residual": oracle.MODE_RESIDUAL, "gradient": oracle.MODE_GRADIENT}[mode]
+    ot = {"relmax": oracle.TH_RELMAX, "abs": oracle.TH_ABS}[thresh]
+    d = oracle.build_local_domain(Ah, b, x0, om, theta, ot, e_max)
+    assert st.K == d.K
+    assert st.tau == d.tau
+    assert st.e_rounds == d.rounds
+    assert np.array_equal(host(idx), d.idx)
+    assert np.array_equal(host(mask), d.mask)
+
+
+@pytest.mark.parametrize("name", ["5pt", "7pt"])
+def test_local_domain_paper_threshold(name, ctx):
+    """tau = eps ||b|| / sqrt(N): ||b|| is summed in a different order on the
+    two sides, so points within a few ulps of tau may differ; none else."""
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("domain paper threshold", name, dims)
+    idx, mask, st = lcs.build_local_domain(A, dev(b), dev(x0), "residual", "paper", 1e-8, 1,
+                                           want_mask=True, ctx=ctx)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-8, oracle.TH_PAPER, 1)
+    assert abs(st.tau - d.tau) <= 4 * np.spacing(d.tau)
+    diff = np.nonzero(host(mask) != d.mask)[0]
+    r = d.score
+    for i in diff:   # only near-ties of the threshold may differ
+        assert abs(abs(r[i]) - d.tau) <= 8 * np.spacing(d.tau)
+    assert len(diff) == 0 or len(diff) < 3
+
+
+def test_empty_and_full_domains(ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case("5pt")
+    say("empty/full domains")
+    xs = oracle.spmv(Ah, x0)   # b = A x0 exactly: r = 0 up to rounding
+    idx, _, st = lcs.build_local_domain(A, dev(np.zeros(A.n)), dev(np.zeros(A.n)), "residual",
+                                        "relmax", 1e-3, 2, ctx=ctx)
+    assert st.K == 0 and idx.numel() == 0
+    idx, _, st = lcs.build_local_domain(A, dev(b), dev(x0), "residual", "abs", 0.0, 0, ctx=ctx)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 0.0, oracle.TH_ABS, 0)
+    assert st.K == d.K and np.array_equal(host(idx), d.idx)
+    del xs
+
+
+# ----------------------------------------------------------------------------
+# restricted system (eq. BEFC): bit-exact CSR
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CASES))
+def test_gather_restricted_bitexact(name, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("gather", name, dims)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-4, oracle.TH_RELMAX, 1)
+    assert d.K > 2048   # spans several compaction tiles
+    rp, col, val = lcs.gather_restricted(A, dev(d.idx, torch.int32), ctx=ctx)
+    B = oracle.restricted(Ah, d.idx)
+    assert np.array_equal(host(rp).astype(np.int64), B.rp)
+    assert np.array_equal(host(col), B.col)
+    assert np.array_equal(host(val), B.val)
+
+
+def test_gather_rejects_bad_domain(ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case("5pt")
+    say("gather rejects bad idx")
+    bad = dev(np.array([3, 2, 7], np.int32), torch.int32)          # not ascending
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.gather_restricted(A, bad, ctx=ctx)
+    assert e.value.status == lcs.EINVAL
+    bad = dev(np.array([1, A.n + 5], np.int32), torch.int32)       # out of range
+    with pytest.raises(lcs.LcsError):
+        lcs.gather_restricted(A, bad, ctx=ctx)
+
+
+# ----------------------------------------------------------------------------
+# PCG: trajectory parity at equal iteration counts, converged parity
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name,pc", [("5pt", "jacobi"), ("9pt", "jacobi"), ("7pt", "jacobi"),
+                                     ("5pt", "rbsgs"), ("7pt", "rbsgs"), ("5pt", "none")])
+def test_global_pcg_parity(name, pc, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("global pcg", name, dims, pc)
+    oo = oracle.Options(eps=1e-10, pc=PC[pc])
+    xo, so = oracle.solve_global(Ah, b, x0, oo)
+    assert so.status == oracle.OK
+    x = dev(x0)
+    st = lcs.solve_global(A, dev(b), x, lcs.Options(eps=1e-10, precond=pc), ctx=ctx)
+    xg = host(x)
+    nb = np.linalg.norm(b)
+    assert np.linalg.norm(oracle.residual(Ah, b, xg)) <= 1.0001e-10 * nb
+    assert abs(st.its_global - so.its_global) <= 1
+    # trajectory parity: stop both at the same iteration count
+    m = max(so.its_global // 2, 1)
+    xo_m, sto, it_o, _ = oracle.pcg(Ah, b, x0, PC[pc], 0.0, m)
+    xm = dev(x0)
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.solve_global(A, dev(b), xm, lcs.Options(eps=1e-30, precond=pc, max_iter=m,
+                                                    max_outer=0), ctx=ctx)
+    assert e.value.status == lcs.ENOCONV
+    rel = np.linalg.norm(host(xm) - xo_m) / np.linalg.norm(xo_m)
+    assert rel <= 1e-10, rel
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("mode,thresh,theta", [("residual", "relmax", 1e-3),
+                                               ("residual", "relmax", 0.3),
+                                               ("residual", "paper", 1e-10),
+                                               ("gradient", "relmax", 1e-4)])
+def test_local_then_global_parity(name, mode, thresh, theta, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("local_then_global", name, dims, mode, thresh, theta)
+    om = {"residual": oracle.MODE_RESIDUAL, "gradient": oracle.MODE_GRADIENT}[mode]
+    ot = {"relmax": oracle.TH_RELMAX, "paper": oracle.TH_PAPER}[thresh]
+    xo, so, dom = oracle.local_then_global(Ah, b, x0, om, theta, ot, 1, oracle.Options(eps=1e-10))
+    x = dev(x0)
+    st = lcs.solve_local_then_global(A, dev(b), x, mode, thresh, theta, 1, lcs.Options(eps=1e-10),
+                                     ctx=ctx)
+    xg = host(x)
+    nb = np.linalg.norm(b)
+    if thresh != "paper":
+        assert st.K == so.K
+    else:
+        assert abs(st.K - so.K) <= 2
+    assert abs(st.its_local - so.its_local) <= 1
+    assert np.linalg.norm(oracle.residual(Ah, b, xg)) <= 1.0001e-10 * nb
+    xd = oracle.pcg(Ah, b, xo, oracle.PC_JACOBI, 1e-14 * nb, 5000)[0]   # tight reference
+    err_g = np.linalg.norm(xg - xd) / np.linalg.norm(xd)
+    err_o = np.linalg.norm(xo - xd) / np.linalg.norm(xd)
+    say(f"  K={st.K} its_local={st.its_local} its_global={st.its_global} err_gpu={err_g:.2e} "
+        f"err_oracle={err_o:.2e}")
+    assert err_g <= max(10 * err_o, 1e-10)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_local_trajectory_parity(name, ctx):
+    """Local PCG on B stopped at equal iteration counts, then assembly and one
+    GS sweep: rounding-level agreement with the oracle."""
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("solve_local trajectory", name, dims)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-4, oracle.TH_RELMAX, 1)
+    oo = oracle.Options(eps=1e-10, max_iter=7, n_smooth=1)
+    xo, so = oracle.solve_local(Ah, b, x0, d.idx, oo)
+    x = dev(x0)
+    st = lcs.solve_local(A, dev(b), x, dev(d.idx, torch.int32),
+                         lcs.Options(eps=1e-10, max_iter=7, n_smooth=1), ctx=ctx)
+    assert st.its_local == so.its_local == 7
+    rel = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    assert rel <= 1e-12, rel
+
+
+# ----------------------------------------------------------------------------
+# mixed precision: FP32 inner sweeps + FP64 refinement
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("name,pc", [("5pt", "jacobi"), ("9pt", "jacobi"), ("7pt", "rbsgs")])
+def test_mixed_precision_refinement(name, pc, ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("mixed", name, dims, pc)
+    nb = np.linalg.norm(b)
+    xd = oracle.pcg(Ah, b, x0, oracle.PC_JACOBI, 1e-14 * nb, 5000)[0]
+    xo, so = oracle.solve_global(Ah, b, x0, oracle.Options(eps=1e-10, pc=PC[pc]))
+    err_o = np.linalg.norm(xo - xd) / np.linalg.norm(xd)
+    for call in ("global", "local"):
+        x = dev(x0)
+        o = lcs.Options(eps=1e-10, precond=pc, precision="mixed")
+        if call == "global":
+            st = lcs.solve_global(A, dev(b), x, o, ctx=ctx)
+        else:
+            st = lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1, o, ctx=ctx)
+        xg = host(x)
+        assert np.linalg.norm(oracle.residual(Ah, b, xg)) <= 1.0001e-10 * nb
+        err = np.linalg.norm(xg - xd) / np.linalg.norm(xd)
+        say(f"  {call}: outer={st.n_outer} its={st.its_local}+{st.its_global} err={err:.2e} "
+            f"fp64 oracle err={err_o:.2e}")
+        assert err <= max(10 * err_o, 1e-9)
+
+
+# ----------------------------------------------------------------------------
+# determinism and error paths
+# ----------------------------------------------------------------------------
+def test_run_twice_bitwise(ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case("5pt")
+    say("run twice")
+    out = []
+    for _ in range(2):
+        x = dev(x0)
+        lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1, ctx=ctx)
+        out.append(host(x))
+    assert np.array_equal(out[0], out[1])
+
+
+def test_argument_errors(ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case("9pt")
+    say("argument errors")
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.solve_global(A, dev(b), dev(x0), lcs.Options(precond="rbsgs"), ctx=ctx)
+    assert e.value.status == lcs.EINVAL
+    with pytest.raises(lcs.LcsError):
+        lcs.build_local_domain(A, dev(b), dev(x0), "gradient", "paper", 1e-3, 0, ctx=ctx)
+    with pytest.raises(lcs.LcsError):
+        lcs.build_local_domain(A, dev(b), dev(x0), "residual", "relmax", 1e-3, 300, ctx=ctx)
+
+
+def test_nonfinite_input_reported(ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case("5pt")
+    say("nonfinite")
+    bb = b.copy()
+    bb[17] = np.nan
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.solve_global(A, dev(bb), dev(x0), ctx=ctx)
+    assert e.value.status == lcs.ENONFINITE
+
+
+def test_breakdown_on_indefinite_operator(ctx):
+    kind, dims, coef, Ah, A, b, x0 = make_case("5pt")
+    say("breakdown")
+    c = coef.copy()
+    c[0] *= -1.0    # negative diagonal: not SPD
+    An = lcs.matrix_from_numpy(kind, *dims, c, DEV)
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.solve_global(An, dev(b), dev(x0), lcs.Options(precond="none"), ctx=ctx)
+    assert e.value.status in (lcs.EBREAKDOWN, lcs.ENOCONV)
