@@ -132,6 +132,10 @@ lcs_status get_buf(lcs_ctx *c, BufId id, size_t count, T **out) {
     return LCS_OK;
 }
 
+double *slot(lcs_ctx *c, int k) { return c->partials + (size_t)k * kSlotElems; }
+template <typename real>
+real *slot_as(lcs_ctx *c, int k) { return reinterpret_cast<real *>(slot(c, k)); }
+
 lcs_status read_scalars(lcs_ctx *c, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(c->hsc, c->dsc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -214,8 +218,9 @@ lcs_status ensure_coef32(lcs_ctx *c, const lcs_matrix *A, bool need, const float
 
 lcs_status launch_norm(lcs_ctx *c, const double *v, int64_t n, double *out, hipStream_t s) {
     const Launch L = dims_for(n);
-    hipLaunchKernelGGL(k_norm2, dim3(L.grid), dim3(kBlock), 0, s, v, n, L.chunk, out, c->dsc,
-                       c->partials);
+    hipLaunchKernelGGL(k_norm2, dim3(L.grid), dim3(kBlock), 0, s, v, n, L.chunk, slot(c, kPtNorm));
+    hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(kBlock), 0, s, (const double *)slot(c, kPtNorm),
+                       L.grid, out);
     LAUNCH_CHECK();
     return LCS_OK;
 }
@@ -240,17 +245,18 @@ template <class Op, typename real, int kPc>
 lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<real> &B, const Launch &L,
                           int ncol, hipStream_t s) {
     if (kPc != LCS_PC_RBSGS) return LCS_OK;
-    real *part = reinterpret_cast<real *>(c->partials);
+    real *part = slot_as<real>(c, kPtSgs);
+    const Scalars *sc = c->dsc;
     for (int col = 0; col < ncol; ++col)
         hipLaunchKernelGGL((k_gs_half<Op, real, false>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                           (const real *)B.r, B.z, col, L.chunk, c->dsc, part);
+                           (const real *)B.r, B.z, col, L.chunk, sc, part);
     for (int col = ncol - 2; col >= 0; --col) {
         if (col == 0)
             hipLaunchKernelGGL((k_gs_half<Op, real, true>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               (const real *)B.r, B.z, col, L.chunk, c->dsc, part);
+                               (const real *)B.r, B.z, col, L.chunk, sc, part);
         else
             hipLaunchKernelGGL((k_gs_half<Op, real, false>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               (const real *)B.r, B.z, col, L.chunk, c->dsc, part);
+                               (const real *)B.r, B.z, col, L.chunk, sc, part);
     }
     LAUNCH_CHECK();
     return LCS_OK;
@@ -265,57 +271,64 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const real *rhs, real *x
                      const double *tol_base, double tol_factor, int max_iter, int check_every,
                      const PcgBufs<real> &B, hipStream_t s, PcgResult *res) {
     const Launch L = dims_for(A.n);
-    real *part = reinterpret_cast<real *>(c->partials);
+    real *pupd = slot_as<real>(c, kPtUpd), *pap = slot_as<real>(c, kPtAp);
+    real *psgs = slot_as<real>(c, kPtSgs);
+    if (max_iter < 0) max_iter = 0;
     if (x_zero) {
         hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(A.n)), dim3(kBlock), 0, s, x, real(0), A.n);
         LAUNCH_CHECK();
     }
     hipLaunchKernelGGL((k_pcg_init<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A, rhs,
-                       (const real *)x, B.r, B.z, L.chunk, x_zero ? 1 : 0, tol_base, tol_factor,
-                       max_iter, c->dsc, part);
+                       (const real *)x, B.r, B.z, L.chunk, x_zero ? 1 : 0, c->dsc, pupd);
     LAUNCH_CHECK();
     LCS_TRY((launch_precond<Op, real, kPc>(c, A, B, L, ncol, s)));
     if (check_every < 1) check_every = 1;
-    int flip = 0, enqueued = 0;
-    auto enqueue_chunk = [&](int slot) -> lcs_status {
-        for (int k = 0; k < check_every; ++k) {
-            real *pold = flip ? B.p1 : B.p0;
+    int flip = 0, next_j = 0;
+    auto launch_ap = [&](int j) -> lcs_status {
+        real *pold = flip ? B.p1 : B.p0;
+        real *pnew = flip ? B.p0 : B.p1;
+        hipLaunchKernelGGL((k_pcg_ap<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                           (const real *)B.z, (const real *)pold, pnew, B.q, L.chunk, j, max_iter,
+                           tol_base, tol_factor, c->dsc, (const real *)pupd, (const real *)psgs, pap);
+        LAUNCH_CHECK();
+        return LCS_OK;
+    };
+    // iteration j = k_pcg_ap(j) + k_pcg_update(j) [+ RB-SGS half sweeps]; the
+    // stopping test of the iterate after update(j-1) runs at the start of ap(j)
+    auto enqueue_chunk = [&](int slot_id) -> lcs_status {
+        for (int k = 0; k < check_every && next_j < max_iter; ++k) {
+            const int j = next_j++;
+            LCS_TRY(launch_ap(j));
             real *pnew = flip ? B.p0 : B.p1;
-            hipLaunchKernelGGL((k_pcg_ap<Op, real>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               (const real *)B.z, (const real *)pold, pnew, B.q, L.chunk, c->dsc,
-                               part);
             hipLaunchKernelGGL((k_pcg_update<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               x, (const real *)pnew, (const real *)B.q, B.r, B.z, L.chunk, c->dsc,
-                               part);
+                               x, (const real *)pnew, (const real *)B.q, B.r, B.z, L.chunk, j,
+                               c->dsc, (const real *)pap, pupd);
             LAUNCH_CHECK();
             LCS_TRY((launch_precond<Op, real, kPc>(c, A, B, L, ncol, s)));
             flip ^= 1;
         }
-        enqueued += check_every;
-        HIP_TRY(hipMemcpyAsync(&c->hdone[slot], &c->dsc->pcg.done, sizeof(int32_t),
+        if (next_j >= max_iter) LCS_TRY(launch_ap(next_j));   // final stopping test
+        HIP_TRY(hipMemcpyAsync(&c->hdone[slot_id], &c->dsc->pcg.done, sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(c->chk[slot], s));
+        HIP_TRY(hipEventRecord(c->chk[slot_id], s));
         return LCS_OK;
     };
-    // the initial iterate may already satisfy the criterion
-    HIP_TRY(hipMemcpyAsync(&c->hdone[0], &c->dsc->pcg.done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(c->chk[0], s));
-    HIP_TRY(hipEventSynchronize(c->chk[0]));
-    if (!c->hdone[0]) {
-        LCS_TRY(enqueue_chunk(0));
-        int slot = 0;
-        for (;;) {
-            const bool more = enqueued < max_iter;
-            if (more) LCS_TRY(enqueue_chunk(slot ^ 1));
-            HIP_TRY(hipEventSynchronize(c->chk[slot]));
-            if (c->hdone[slot] || !more) break;
-            slot ^= 1;
-        }
+    LCS_TRY(enqueue_chunk(0));
+    int sl = 0;
+    for (;;) {
+        const bool more = next_j < max_iter;
+        if (more) LCS_TRY(enqueue_chunk(sl ^ 1));
+        HIP_TRY(hipEventSynchronize(c->chk[sl]));
+        if (c->hdone[sl] || !more) break;
+        sl ^= 1;
     }
     LCS_TRY(read_scalars(c, s));
     res->its = c->hsc->pcg.it;
     res->status = c->hsc->pcg.status;
-    if (!c->hsc->pcg.done && res->status == kStOk) res->status = kStNoConv;
+    if (!c->hsc->pcg.done) {   // cannot happen: the final test always runs
+        res->its = max_iter;
+        res->status = kStNoConv;
+    }
     return LCS_OK;
 }
 
@@ -350,7 +363,9 @@ lcs_status launch_resnorm(lcs_ctx *c, const Op &A, const double *rhs, const doub
                           const double *tol_base, double tol_factor, hipStream_t s) {
     const Launch L = dims_for(A.n);
     hipLaunchKernelGGL((k_resnorm<Op>), dim3(L.grid), dim3(kBlock), 0, s, A, rhs, x, r, L.chunk,
-                       tol_base, tol_factor, c->dsc, c->partials);
+                       slot(c, kPtRes));
+    hipLaunchKernelGGL(k_fin_res, dim3(1), dim3(kBlock), 0, s, (const double *)slot(c, kPtRes),
+                       L.grid, tol_base, tol_factor, c->dsc);
     LAUNCH_CHECK();
     return LCS_OK;
 }
@@ -389,10 +404,10 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
             out->its += pr.its;
             LCS_TRY(launch_resnorm(c, A, rhs, x, (double *)nullptr, tol_base, tol_factor, s));
             LCS_TRY(read_scalars(c, s));
-            out->rr = c->hsc->pcg.rr;
+            out->rr = c->hsc->res.rr;
             if (pr.status != kStOk) return status_of(pr.status);
-            if (c->hsc->pcg.status != kStOk) return status_of(c->hsc->pcg.status);
-            if (c->hsc->pcg.done) return LCS_OK;
+            if (c->hsc->res.status != kStOk) return status_of(c->hsc->res.status);
+            if (c->hsc->res.done) return LCS_OK;
             if (attempt >= o->max_outer || out->its >= o->max_iter) return status_of(kStNoConv);
             out->n_outer += 1;
         }
@@ -417,9 +432,9 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
     for (int outer = 0;; ++outer) {
         LCS_TRY(launch_resnorm(c, A, rhs, x, r64, tol_base, tol_factor, s));
         LCS_TRY(read_scalars(c, s));
-        out->rr = c->hsc->pcg.rr;
-        if (c->hsc->pcg.status != kStOk) return status_of(c->hsc->pcg.status);
-        if (c->hsc->pcg.done) return LCS_OK;
+        out->rr = c->hsc->res.rr;
+        if (c->hsc->res.status != kStOk) return status_of(c->hsc->res.status);
+        if (c->hsc->res.done) return LCS_OK;
         if (outer >= outer_cap || out->its >= o->max_iter) return status_of(kStNoConv);
         hipLaunchKernelGGL(k_cast_scale, dim3(flat_grid(n)), dim3(kBlock), 0, s,
                            (const double *)r64, r32, n, c->dsc);
@@ -457,23 +472,26 @@ lcs_status build_domain(lcs_ctx *c, const Op &A, const double *b, const double *
     LCS_TRY(get_buf(c, B_BLOCKOFF, kMaxGrid, &blockoff));
     if (mode == LCS_MODE_RESIDUAL)
         hipLaunchKernelGGL((k_score<Op, 0>), dim3(L.grid), dim3(kBlock), 0, s, A, b, x0, score,
-                           L.chunk, thresh, theta, c->dsc, c->partials);
+                           L.chunk, slot(c, kPtScore));
     else
         hipLaunchKernelGGL((k_score<Op, 1>), dim3(L.grid), dim3(kBlock), 0, s, A, b, x0, score,
-                           L.chunk, thresh, theta, c->dsc, c->partials);
-    hipLaunchKernelGGL(k_mark, dim3(flat_grid(T.npad)), dim3(kBlock), 0, s, (const double *)score,
-                       stamp, n, T.npad, (const Scalars *)c->dsc);
+                           L.chunk, slot(c, kPtScore));
+    const int gmark = std::min(flat_grid(T.npad), 512);
+    hipLaunchKernelGGL(k_mark, dim3(gmark), dim3(kBlock), 0, s, (const double *)score, stamp, n,
+                       T.npad, thresh, theta, (const double *)slot(c, kPtScore), L.grid, c->dsc);
     LAUNCH_CHECK();
-    if (mode == LCS_MODE_RESIDUAL) {
-        for (int m = 1; m <= e_max; ++m)
-            hipLaunchKernelGGL((k_expand<Op>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               (const double *)score, x0, stamp, m, L.chunk, c->dsc, c->partials);
-        LAUNCH_CHECK();
-    }
+    const int ex = mode == LCS_MODE_RESIDUAL ? e_max : 0;
+    for (int m = 1; m <= ex; ++m)
+        hipLaunchKernelGGL((k_expand<Op>), dim3(L.grid), dim3(kBlock), 0, s, A,
+                           (const double *)score, x0, stamp, m, L.chunk,
+                           (const double *)slot(c, kPtExp0 + ((m - 1) & 1)),
+                           slot(c, kPtExp0 + (m & 1)), c->dsc);
+    LAUNCH_CHECK();
     hipLaunchKernelGGL(k_count, dim3(T.grid), dim3(kBlock), 0, s, (const uint8_t *)stamp, T.ntiles,
-                       T.tiles_per_block, blockoff, c->dsc);
+                       T.tiles_per_block, blockoff, ex, (const double *)slot(c, kPtExp0 + (ex & 1)),
+                       L.grid, c->dsc);
     hipLaunchKernelGGL(k_scatter, dim3(T.grid), dim3(kBlock), 0, s, (const uint8_t *)stamp, n,
-                       T.ntiles, T.tiles_per_block, (const int32_t *)blockoff, idx, inv);
+                       T.ntiles, T.tiles_per_block, (const int32_t *)blockoff, idx, inv, c->dsc);
     LAUNCH_CHECK();
     LCS_TRY(read_scalars(c, s));
     *K = c->hsc->ms.K;
@@ -515,9 +533,9 @@ lcs_status gather(lcs_ctx *c, const Op &A, const int32_t *idx, int64_t K, const 
     hipLaunchKernelGGL((k_gather_count<Op>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K,
                        inv, rowlen);
     hipLaunchKernelGGL(k_scan_reduce, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)rowlen, K,
-                       T.tiles_per_block, blockoff, c->dsc);
+                       T.tiles_per_block, blockoff);
     hipLaunchKernelGGL(k_scan_apply, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)rowlen, K,
-                       T.tiles_per_block, (const int32_t *)blockoff, rp, (const Scalars *)c->dsc);
+                       T.tiles_per_block, (const int32_t *)blockoff, rp, c->dsc);
     hipLaunchKernelGGL((k_gather_fill<Op>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K, inv,
                        (const int32_t *)rp, col, val, val32, dg, dg32, clr, r, r ? rhs : nullptr);
     LAUNCH_CHECK();
@@ -585,7 +603,8 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const Op64 &A, const Op3
         for (int sw = 0; sw < o->n_smooth; ++sw)
             for (int col = 0; col < ncol; ++col)
                 hipLaunchKernelGGL((k_gs_half<Op64, double, false>), dim3(L.grid), dim3(kBlock), 0,
-                                   s, A, b, x, col, L.chunk, (Scalars *)nullptr, c->partials);
+                                   s, A, b, x, col, L.chunk, (const Scalars *)nullptr,
+                                   (double *)nullptr);
         LAUNCH_CHECK();
     }
     LCS_TRY(tm.mark(3));
@@ -645,7 +664,7 @@ lcs_status lcs_create(lcs_ctx **out) {
     if (hipGetDevice(&c->device) != hipSuccess) return cleanup(fail(LCS_EHIP, "no HIP device"));
     if (hipMalloc(&c->dsc, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_ENOMEM, "state"));
     if (hipMemset(c->dsc, 0, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_EHIP, "memset"));
-    if (hipMalloc(&c->partials, sizeof(double) * kMaxGrid * 4) != hipSuccess)
+    if (hipMalloc(&c->partials, sizeof(double) * kSlotElems * kPtSlots) != hipSuccess)
         return cleanup(fail(LCS_ENOMEM, "partials"));
     if (hipHostMalloc(&c->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(LCS_ENOMEM, "pinned state"));
@@ -702,7 +721,7 @@ lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double
     return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
         const Launch L = dims_for(op.n);
         hipLaunchKernelGGL((k_score<decltype(op), 1>), dim3(L.grid), dim3(kBlock), 0, s, op, x, x,
-                           g, L.chunk, 1, 0.0, c->dsc, c->partials);
+                           g, L.chunk, slot(c, kPtScore));
         LAUNCH_CHECK();
         HIP_TRY(hipStreamSynchronize(s));
         return LCS_OK;
@@ -832,8 +851,8 @@ lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, doubl
         for (int sw = 0; sw < n_sweeps; ++sw)
             for (int col = 0; col < ncol; ++col)
                 hipLaunchKernelGGL((k_gs_half<decltype(op), double, false>), dim3(L.grid),
-                                   dim3(kBlock), 0, s, op, b, x, col, L.chunk, (Scalars *)nullptr,
-                                   c->partials);
+                                   dim3(kBlock), 0, s, op, b, x, col, L.chunk,
+                                   (const Scalars *)nullptr, (double *)nullptr);
         LAUNCH_CHECK();
         HIP_TRY(hipStreamSynchronize(s));
         return LCS_OK;
@@ -903,7 +922,7 @@ lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, dou
                                o->eps, s));
         LCS_TRY(read_scalars(c, s));
         const double bn = c->hsc->bnorm;
-        st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->pcg.rr) / bn : std::sqrt(c->hsc->pcg.rr);
+        st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->res.rr) / bn : std::sqrt(c->hsc->res.rr);
         st->relres_final = st->relres_after_local;
         st->ms_construct = tm.ms(0, 1);
         st->ms_local = tm.ms(1, 2);
@@ -957,9 +976,9 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
                                o->eps, s));
         LCS_TRY(read_scalars(c, s));
-        st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->pcg.rr) / bn : std::sqrt(c->hsc->pcg.rr);
+        st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->res.rr) / bn : std::sqrt(c->hsc->res.rr);
         lcs_status rs = LCS_OK;
-        if (c->hsc->pcg.done) {
+        if (c->hsc->res.done) {
             st->relres_final = st->relres_after_local;
             LCS_TRY(tm.mark(4));
         } else {

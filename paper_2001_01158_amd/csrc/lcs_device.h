@@ -15,7 +15,7 @@ namespace lcs {
 constexpr int kBlock = 256;          // 4 wavefronts of 64
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kMaxGrid = 2048;       // 8 blocks per CU on 256 CUs
+constexpr int kMaxGrid = 1024;       // 4 blocks (16 waves) per CU on 256 CUs
 constexpr int kXcds = 8;
 
 // ---------------------------------------------------------------------------
@@ -206,45 +206,78 @@ struct Ops {
     }
 };
 
-// Writes this block's partials; the last block to arrive folds all partials
-// in block order (fixed tree) and returns true with the totals in `tot`
-// (valid in every thread of that block).  The counter is reset for reuse.
+// Producer side: this block's reduced values go to part[k * gridDim.x + b]
+// with plain stores.  There is no cross-block handshake inside a kernel: the
+// consumer is the next kernel on the stream, and the kernel boundary makes the
+// partials visible (on a multi-XCD part an in-kernel agent-scope fence per
+// block would write back and invalidate the XCD's L2 every time).
 template <typename T, int NV, class O>
-__device__ __forceinline__ bool last_block_reduce(T (&v)[NV], O ops, T *partials,
-                                                  unsigned *counter, T (&tot)[NV]) {
-    __shared__ bool is_last;
-    __shared__ T res[NV];
+__device__ __forceinline__ void write_partials(T (&v)[NV], O ops, T *part) {
     block_reduce<T, NV>(v, ops);
-    const unsigned g = gridDim.x;
     if (threadIdx.x == 0) {
+        const unsigned g = gridDim.x;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) partials[(size_t)k * g + blockIdx.x] = v[k];
-        __threadfence();
-        const unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == g - 1);
+        for (int k = 0; k < NV; ++k) part[(size_t)k * g + blockIdx.x] = v[k];
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
+}
+
+// Consumer side: fold the g partials of the producing kernel in a fixed order
+// (strided per thread, then the block tree).  Every block that calls this
+// gets bit-identical totals, valid in all of its threads.
+template <typename T, int NV, class O>
+__device__ __forceinline__ void read_partials(const T *part, int g, O ops, T (&tot)[NV]) {
+    __shared__ T res[NV];
     T a[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         a[k] = T(0);
-        for (unsigned b = threadIdx.x; b < g; b += kBlock) {
-            const T p = partials[(size_t)k * g + b];
-            a[k] = (b == threadIdx.x) ? p : ops.template apply<T>(k, a[k], p);
+        for (int b = threadIdx.x; b < g; b += kBlock) {
+            const T p = part[(size_t)k * g + b];
+            a[k] = (b == (int)threadIdx.x) ? p : ops.template apply<T>(k, a[k], p);
         }
     }
     block_reduce<T, NV>(a, ops);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) res[k] = a[k];
-        *counter = 0u;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NV; ++k) tot[k] = res[k];
-    return true;
+    __syncthreads();
+}
+
+// exclusive prefix of integer block counts: sum of cnt[0..upto) in every
+// thread, plus the grand total of cnt[0..g)
+__device__ __forceinline__ void block_prefix_of_counts(const int32_t *cnt, int g, int upto,
+                                                       int &before, int &total) {
+    __shared__ int red[2][kWaves];
+    int a = 0, t = 0;
+    for (int b = threadIdx.x; b < g; b += kBlock) {
+        const int c = cnt[b];
+        t += c;
+        if (b < upto) a += c;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, kWave);
+        t += __shfl_xor(t, o, kWave);
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[0][w] = a;
+        red[1][w] = t;
+    }
+    __syncthreads();
+    int sa = 0, st = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        sa += red[0][q];
+        st += red[1][q];
+    }
+    __syncthreads();
+    before = sa;
+    total = st;
 }
 
 }  // namespace lcs

@@ -3,9 +3,9 @@
 // Per-row kernels use a chunked grid: block b (after the XCD remap) owns rows
 // [b*chunk, (b+1)*chunk) and walks them 256 at a time, so loads are
 // coalesced and stencil neighbours stay in the owning XCD's L2.  Kernels
-// that reduce finish in the last block to arrive (deterministic order) and
-// leave their result in device state read by the next kernel, so a solve is
-// a stream of launches with no host round trip per iteration.
+// that reduce write per-block partials; the next kernel on the stream folds
+// them in a fixed order at its start, so a solve is a stream of launches
+// with no host round trip per iteration and no in-kernel cross-block fence.
 #pragma once
 
 #include "lcs_device.h"
@@ -15,6 +15,9 @@ namespace lcs {
 // ---------------------------------------------------------------------------
 // device state
 // ---------------------------------------------------------------------------
+// Every field is written by block 0 of one kernel and read only by later
+// kernels on the stream (or by the host), never by other blocks of the kernel
+// that writes it.
 struct MarkState {
     double tau;       // threshold in use
     double smax;      // max |s_i|
@@ -25,8 +28,17 @@ struct MarkState {
 };
 
 struct PcgState {
-    double rz, alpha, beta, rr, tol, rr0, pq, rmax;
-    int32_t it, max_iter, done, status, first, pad;
+    double tol;       // absolute tolerance on the recursive ||r||
+    double rz_next;   // r_j.z_j, formed by the A p kernel of iteration j
+    double rz_cur;    // the r.z that the update of the previous iteration used
+    double rr;        // ||r||^2 at exit
+    double rr0;       // ||r_0||^2
+    int32_t done, status, it, pad;
+};
+
+struct ResState {
+    double rr, rmax, tol;
+    int32_t done, status;
 };
 
 enum : int32_t { kStOk = 0, kStNoConv = 4, kStBreakdown = 5, kStNonFinite = 6 };
@@ -34,30 +46,29 @@ enum : int32_t { kStOk = 0, kStNoConv = 4, kStBreakdown = 5, kStNonFinite = 6 };
 struct Scalars {
     MarkState ms;
     PcgState pcg;
+    ResState res;
     double bnorm;        // ||b||_2
     double scale;        // refinement step scale max|r| (mixed precision)
     int64_t gather_nnz;  // nnz of the restricted matrix
     int32_t bad_idx;     // a caller-supplied domain was out of range or not ascending
     int32_t pad;
-    unsigned counters[16];
 };
 
-enum CounterSlot { kCntScore = 0, kCntExpand, kCntCount, kCntScan, kCntInit, kCntAp, kCntUpd,
-                   kCntSgs, kCntRes, kCntNorm };
+// partial-sum slots (each kMaxGrid x 4 doubles)
+enum PartSlot { kPtScore = 0, kPtExp0, kPtExp1, kPtNorm, kPtRes, kPtAp, kPtUpd, kPtSgs, kPtSlots };
+constexpr size_t kSlotElems = (size_t)kMaxGrid * 4;
 
 // ---------------------------------------------------------------------------
 // scores of Algorithms 2 and 3
 // ---------------------------------------------------------------------------
 // Residual mode: s = r^(0) = b - A x0 (FMA chain, ascending columns).
 // Gradient mode: s = g, g_i = sum_{j != i} |x_i - x_j| (eq. grad).
-// The last block sets tau: REL_MAX theta*max|s|, ABS theta,
-// PAPER theta*||b||_2/sqrt(N).
+// Partials: max |s_i| and ||b||^2.
 template <class Op, int kMode>
 __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict__ b,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ s, int64_t chunk,
-                                                  int thresh, double theta, Scalars *sc,
-                                                  double *partials) {
+                                                  double *part) {
     const Chunk c = my_chunk(A.n, chunk);
     double v[2] = {0.0, 0.0};
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
@@ -78,27 +89,29 @@ __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict
         const double m = fabs(acc);
         v[0] = m > v[0] ? m : v[0];
     }
-    double tot[2];
-    if (last_block_reduce<double, 2>(v, Ops<1u>(), partials, &sc->counters[kCntScore], tot)) {
-        if (threadIdx.x == 0) {
-            double tau;
-            if (thresh == 0) tau = theta * tot[0];
-            else if (thresh == 1) tau = theta;
-            else tau = theta * sqrt(tot[1]) / sqrt((double)A.n);
-            sc->ms.tau = tau;
-            sc->ms.smax = tot[0];
-            sc->ms.bb = tot[1];
-            sc->ms.stop = 0;
-            sc->ms.grown = 0;
-        }
-    }
+    write_partials<double, 2>(v, Ops<1u>(), part);
 }
 
-// stamp_i = 1 if |s_i| > tau (strict), else 0; zero on the padding [n, npad).
+// tau from the score partials: REL_MAX theta*max|s|, ABS theta,
+// PAPER theta*||b||_2/sqrt(N); then stamp_i = (|s_i| > tau) (strict), zero on
+// the padding [n, npad).
 __global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
                                                  uint8_t *__restrict__ stamp, int64_t n,
-                                                 int64_t npad, const Scalars *sc) {
-    const double tau = sc->ms.tau;
+                                                 int64_t npad, int thresh, double theta,
+                                                 const double *part, int gprod, Scalars *sc) {
+    double tot[2];
+    read_partials<double, 2>(part, gprod, Ops<1u>(), tot);
+    double tau;
+    if (thresh == 0) tau = theta * tot[0];
+    else if (thresh == 1) tau = theta;
+    else tau = theta * sqrt(tot[1]) / sqrt((double)n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->ms.tau = tau;
+        sc->ms.smax = tot[0];
+        sc->ms.bb = tot[1];
+        sc->ms.stop = 0;
+        sc->ms.grown = 0;
+    }
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < npad;
          i += (int64_t)gridDim.x * kBlock)
         stamp[i] = (i < n && fabs(s[i]) > tau) ? 1 : 0;
@@ -107,13 +120,25 @@ __global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
 // One synchronous expansion round m (Algorithm 3, eq. extend-local-condition):
 // j outside Omega with a stored neighbour l in Omega (stamp 1..m) joins if
 // |r_j| + sum_{l in Omega, ascending} |a_jl x_l| > tau.  New members get
-// stamp m+1, which this round's readers treat as "outside".
+// stamp m+1, which this round's readers treat as "outside".  Round m first
+// reads round m-1's count: if it added nothing, this and later rounds are
+// no-ops (Omega unchanged).
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_expand(Op A, const double *__restrict__ r,
                                                    const double *__restrict__ x,
                                                    uint8_t *stamp, int m, int64_t chunk,
-                                                   Scalars *sc, double *partials) {
+                                                   const double *part_prev, double *part,
+                                                   Scalars *sc) {
     if (sc->ms.stop) return;
+    if (m >= 2) {
+        double added[1];
+        read_partials<double, 1>(part_prev, gridDim.x, Ops<0u>(), added);
+        if (added[0] == 0.0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) sc->ms.stop = 1;
+            return;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->ms.grown = m - 1;
+    }
     const Chunk c = my_chunk(A.n, chunk);
     const double tau = sc->ms.tau;
     double v[1] = {0.0};
@@ -133,13 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Op A, const double *__restric
             v[0] += 1.0;
         }
     }
-    double tot[1];
-    if (last_block_reduce<double, 1>(v, Ops<0u>(), partials, &sc->counters[kCntExpand], tot)) {
-        if (threadIdx.x == 0) {
-            if (tot[0] == 0.0) sc->ms.stop = 1;
-            else sc->ms.grown += 1;
-        }
-    }
+    write_partials<double, 1>(v, Ops<0u>(), part);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,76 +199,54 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int &total) {
     return base + inc - v;
 }
 
-// Per-block count of members; the last block turns the counts into block
-// offsets (exclusive scan in block order) and K.
+// Per-block member count (plain store).  With expansion, first folds the
+// last round's additions into the round count.
 __global__ __launch_bounds__(kBlock) void k_count(const uint8_t *__restrict__ stamp,
                                                   int64_t ntiles, int64_t tiles_per_block,
-                                                  int32_t *blockoff, Scalars *sc) {
-    const int64_t lb = blockIdx.x;
-    const int64_t t0 = lb * tiles_per_block;
+                                                  int32_t *cnt, int e_max, const double *part_exp,
+                                                  int gexp, Scalars *sc) {
+    if (e_max >= 1 && !sc->ms.stop) {
+        double added[1];
+        read_partials<double, 1>(part_exp, gexp, Ops<0u>(), added);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && added[0] > 0.0) sc->ms.grown = e_max;
+    }
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
     int64_t t1 = t0 + tiles_per_block;
     if (t1 > ntiles) t1 = ntiles;
-    int cnt = 0;
+    int c = 0;
     const uint64_t *w = reinterpret_cast<const uint64_t *>(stamp);
-    for (int64_t t = t0; t < t1; ++t) cnt += nonzero_bytes(w[t * kBlock + threadIdx.x]);
+    for (int64_t t = t0; t < t1; ++t) c += nonzero_bytes(w[t * kBlock + threadIdx.x]);
     __shared__ int red[kWaves];
-    int c = cnt;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
     __syncthreads();
-    __shared__ bool is_last;
-    const unsigned g = gridDim.x;
     if (threadIdx.x == 0) {
-        int s = 0;
-        for (int q = 0; q < kWaves; ++q) s += red[q];
-        blockoff[blockIdx.x] = s;
-        __threadfence();
-        is_last = atomicAdd(&sc->counters[kCntCount], 1u) == g - 1;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    // exclusive scan of g <= 8*kBlock counts, 8 consecutive per thread
-    int loc[8];
-    int mine = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const unsigned b = threadIdx.x * 8 + k;
-        loc[k] = b < g ? blockoff[b] : 0;
-        mine += loc[k];
-    }
-    int total;
-    int base = block_exclusive_scan(mine, total);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const unsigned b = threadIdx.x * 8 + k;
-        if (b < g) blockoff[b] = base;
-        base += loc[k];
-    }
-    if (threadIdx.x == 0) {
-        sc->ms.K = total;
-        sc->counters[kCntCount] = 0u;
+        int a = 0;
+        for (int q = 0; q < kWaves; ++q) a += red[q];
+        cnt[blockIdx.x] = a;
     }
 }
 
-// idx[pos] = i for members in ascending i; inv[i] = pos or -1.
+// idx[pos] = i for members in ascending i; inv[i] = pos or -1.  Each block
+// starts at the sum of the counts of the blocks before it; block 0 records K.
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint8_t *__restrict__ stamp, int64_t n,
                                                     int64_t ntiles, int64_t tiles_per_block,
-                                                    const int32_t *__restrict__ blockoff,
+                                                    const int32_t *__restrict__ cnt,
                                                     int32_t *__restrict__ idx,
-                                                    int32_t *__restrict__ inv) {
-    const int64_t lb = blockIdx.x;
-    const int64_t t0 = lb * tiles_per_block;
+                                                    int32_t *__restrict__ inv, Scalars *sc) {
+    int off, total;
+    block_prefix_of_counts(cnt, gridDim.x, blockIdx.x, off, total);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->ms.K = total;
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
     int64_t t1 = t0 + tiles_per_block;
     if (t1 > ntiles) t1 = ntiles;
-    int off = blockoff[blockIdx.x];
     const uint64_t *w = reinterpret_cast<const uint64_t *>(stamp);
     for (int64_t t = t0; t < t1; ++t) {
         const uint64_t word = w[t * kBlock + threadIdx.x];
         const int c = nonzero_bytes(word);
-        int total;
-        int pos = off + block_exclusive_scan(c, total);
+        int tt;
+        int pos = off + block_exclusive_scan(c, tt);
         const int64_t row0 = t * kTile + (int64_t)threadIdx.x * 8;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -263,16 +260,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint8_t *__restrict__ 
                 inv[i] = -1;
             }
         }
-        off += total;
+        off += tt;
     }
 }
 
 // ---------------------------------------------------------------------------
-// generic exclusive scan of int32 (row lengths -> CSR row pointers)
+// exclusive scan of int32 (row lengths -> CSR row pointers)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ in, int64_t n,
-                                                        int64_t tiles_per_block,
-                                                        int32_t *blocksum, Scalars *sc) {
+                                                        int64_t tiles_per_block, int32_t *blocksum) {
     const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
     int s = 0;
     for (int64_t t = t0; t < t0 + tiles_per_block; ++t) {
@@ -286,48 +282,25 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restric
     for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
     __syncthreads();
-    __shared__ bool is_last;
-    const unsigned g = gridDim.x;
     if (threadIdx.x == 0) {
         int a = 0;
         for (int q = 0; q < kWaves; ++q) a += red[q];
         blocksum[blockIdx.x] = a;
-        __threadfence();
-        is_last = atomicAdd(&sc->counters[kCntScan], 1u) == g - 1;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    int loc[8];
-    int mine = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const unsigned b = threadIdx.x * 8 + k;
-        loc[k] = b < g ? blocksum[b] : 0;
-        mine += loc[k];
-    }
-    int total;
-    int base = block_exclusive_scan(mine, total);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const unsigned b = threadIdx.x * 8 + k;
-        if (b < g) blocksum[b] = base;
-        base += loc[k];
-    }
-    if (threadIdx.x == 0) {
-        sc->gather_nnz = total;
-        sc->counters[kCntScan] = 0u;
     }
 }
 
-// out[i] = sum_{k<i} in[k]; out[n] = total.
+// out[i] = sum_{k<i} in[k]; out[n] = total (also recorded as the nnz).
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict__ in, int64_t n,
                                                        int64_t tiles_per_block,
-                                                       const int32_t *__restrict__ blockoff,
-                                                       int32_t *__restrict__ out,
-                                                       const Scalars *sc) {
+                                                       const int32_t *__restrict__ blocksum,
+                                                       int32_t *__restrict__ out, Scalars *sc) {
+    int off, total;
+    block_prefix_of_counts(blocksum, gridDim.x, blockIdx.x, off, total);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->gather_nnz = total;
+        out[n] = total;
+    }
     const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
-    int off = blockoff[blockIdx.x];
     for (int64_t t = t0; t < t0 + tiles_per_block; ++t) {
         const int64_t base = t * kTile + (int64_t)threadIdx.x * 8;
         int loc[8];
@@ -337,16 +310,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict
             loc[k] = base + k < n ? in[base + k] : 0;
             mine += loc[k];
         }
-        int total;
-        int p = off + block_exclusive_scan(mine, total);
+        int tt;
+        int p = off + block_exclusive_scan(mine, tt);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             if (base + k < n) out[base + k] = p;
             p += loc[k];
         }
-        off += total;
+        off += tt;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int32_t)sc->gather_nnz;
 }
 
 // ---------------------------------------------------------------------------
@@ -421,17 +393,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter_add(const int32_t *__restric
 // ---------------------------------------------------------------------------
 // preconditioned CG (templated on operator and working precision)
 // ---------------------------------------------------------------------------
-// init: r = rhs - A x (or r = rhs when x = 0), rr; Jacobi: z = r / a_ii, rz;
-// RB-SGS: z = 0 (filled by the half sweeps).  The last block sets the
-// absolute tolerance (tol_factor * *tol_base, or tol_factor * ||r_0|| when
-// tol_base is null) and flags convergence of the initial iterate.
+// Iteration j is the pair k_pcg_ap(j), k_pcg_update(j) (plus the three
+// Gauss-Seidel half sweeps for RB-SGS).  Each kernel starts by folding the
+// partials of the kernel before it, so every block holds the same scalars;
+// block 0 records them for later kernels and the host.
+//
+// init: r = rhs - A x (or r = rhs when x = 0); Jacobi: z = r / a_ii; none:
+// z = r; RB-SGS: z = 0 (filled by the half sweeps).  Partials r.r, r.z.
 template <class Op, typename real, int kPc>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const real *__restrict__ rhs,
                                                      const real *__restrict__ x,
                                                      real *__restrict__ r, real *__restrict__ z,
-                                                     int64_t chunk, int x_zero,
-                                                     const double *tol_base, double tol_factor,
-                                                     int max_iter, Scalars *sc, real *partials) {
+                                                     int64_t chunk, int x_zero, Scalars *sc,
+                                                     real *part_upd) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pcg.done = 0;
+        sc->pcg.status = kStOk;
+        sc->pcg.it = 0;
+    }
     const Chunk c = my_chunk(A.n, chunk);
     real v[2] = {real(0), real(0)};
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
@@ -450,90 +429,104 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const real *__restric
             v[1] += acc * acc;
         }
     }
-    real tot[2];
-    if (last_block_reduce<real, 2>(v, Ops<0u>(), partials, &sc->counters[kCntInit], tot)) {
-        if (threadIdx.x == 0) {
-            PcgState &p = sc->pcg;
-            const double rr = (double)tot[0];
-            p.rr = rr;
-            p.rr0 = rr;
-            p.it = 0;
-            p.max_iter = max_iter;
-            p.first = 1;
-            p.rz = (double)tot[1];
-            p.tol = tol_base ? tol_factor * *tol_base : tol_factor * sqrt(rr);
-            p.status = kStOk;
-            p.done = 0;
-            if (!(rr == rr) || rr > 1.7e308) {
-                p.status = kStNonFinite;
-                p.done = 1;
-            } else if (sqrt(rr) <= p.tol) {
-                p.done = 1;
-            } else if (max_iter <= 0) {
-                p.status = kStNoConv;
-                p.done = 1;
-            }
-        }
-    }
+    write_partials<real, 2>(v, Ops<0u>(), part_upd);
 }
 
-// q = A p with p = z (first) or p = z + beta p_old, recomputed for each
-// neighbour so that p can be updated in the same pass (p_new written for
-// the own row only).  p.q -> alpha = rz / p.q.
-template <class Op, typename real>
+// Iteration j, first kernel.  Prologue: r_j.r_j and r_j.z_j from the
+// previous kernel's partials -> stop (criterion, max_iter, non-finite), else
+// beta_j = r_j.z_j / r_{j-1}.z_{j-1}.  Body: q = A p with p = z (j = 0) or
+// p = z + beta p_old, recomputed for each neighbour so that p is updated in
+// the same pass (p_new written for the own row only).  Partials p.q.
+template <class Op, typename real, int kPc>
 __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const real *__restrict__ z,
                                                    const real *__restrict__ pold,
                                                    real *__restrict__ pnew, real *__restrict__ q,
-                                                   int64_t chunk, Scalars *sc, real *partials) {
+                                                   int64_t chunk, int j, int max_iter,
+                                                   const double *tol_base, double tol_factor,
+                                                   Scalars *sc, const real *part_upd,
+                                                   const real *part_sgs, real *part_ap) {
     if (sc->pcg.done) return;
-    const int first = sc->pcg.first;
-    const real beta = (real)sc->pcg.beta;
+    real t[2];
+    read_partials<real, 2>(part_upd, gridDim.x, Ops<0u>(), t);
+    real rz = t[1];
+    if (kPc == 2) {
+        real u[1];
+        read_partials<real, 1>(part_sgs, gridDim.x, Ops<0u>(), u);
+        rz = u[0];
+    }
+    const double rr = (double)t[0];
+    double tol;
+    if (j == 0) tol = tol_base ? tol_factor * *tol_base : tol_factor * sqrt(rr);
+    else tol = sc->pcg.tol;
+    int stop = 0, status = kStOk;
+    if (!(rr == rr) || rr > 1.7e308) { stop = 1; status = kStNonFinite; }
+    else if (sqrt(rr) <= tol) stop = 1;
+    else if (j >= max_iter) { stop = 1; status = kStNoConv; }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (j == 0) {
+            sc->pcg.tol = tol;
+            sc->pcg.rr0 = rr;
+        }
+        sc->pcg.rr = rr;
+        sc->pcg.rz_next = (double)rz;
+        if (stop) {
+            sc->pcg.done = 1;
+            sc->pcg.status = status;
+            sc->pcg.it = j;
+        }
+    }
+    if (stop) return;
     const Chunk c = my_chunk(A.n, chunk);
     real v[1] = {real(0)};
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        real acc = real(0);
-        if (first) {
-            A.for_each(i, [&](int64_t j, real a) { acc = fma(a, z[j], acc); });
+    if (j == 0) {
+        for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+            real acc = real(0);
+            A.for_each(i, [&](int64_t jj, real a) { acc = fma(a, z[jj], acc); });
             const real pi = z[i];
             pnew[i] = pi;
             q[i] = acc;
             v[0] += pi * acc;
-        } else {
-            A.for_each(i, [&](int64_t j, real a) { acc = fma(a, fma(beta, pold[j], z[j]), acc); });
+        }
+    } else {
+        const real beta = rz / (real)sc->pcg.rz_cur;
+        for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+            real acc = real(0);
+            A.for_each(i, [&](int64_t jj, real a) { acc = fma(a, fma(beta, pold[jj], z[jj]), acc); });
             const real pi = fma(beta, pold[i], z[i]);
             pnew[i] = pi;
             q[i] = acc;
             v[0] += pi * acc;
         }
     }
-    real tot[1];
-    if (last_block_reduce<real, 1>(v, Ops<0u>(), partials, &sc->counters[kCntAp], tot)) {
-        if (threadIdx.x == 0) {
-            PcgState &p = sc->pcg;
-            p.first = 0;
-            const double pq = (double)tot[0];
-            p.pq = pq;
-            if (!(pq > 0.0)) {
-                p.status = (pq == pq) ? kStBreakdown : kStNonFinite;
-                p.done = 1;
-            } else {
-                p.alpha = (double)((real)p.rz / (real)pq);
-            }
-        }
-    }
+    write_partials<real, 1>(v, Ops<0u>(), part_ap);
 }
 
-// x += alpha p; r -= alpha q; Jacobi: z = r / a_ii; partials r.r (and r.z).
-// The last block counts the iteration, tests ||r|| <= tol and max_iter, and
-// (Jacobi) forms beta = r.z_new / r.z.
+// Iteration j, second kernel.  Prologue: p.q from the partials ->
+// breakdown if p.q <= 0, else alpha = r.z / p.q.  Body: x += alpha p;
+// r -= alpha q; Jacobi z = r / a_ii (none: z = r; RB-SGS: z = 0 for the
+// half sweeps).  Partials r.r, r.z.
 template <class Op, typename real, int kPc>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, real *__restrict__ x,
                                                        const real *__restrict__ p,
                                                        const real *__restrict__ q,
                                                        real *__restrict__ r, real *__restrict__ z,
-                                                       int64_t chunk, Scalars *sc, real *partials) {
+                                                       int64_t chunk, int j, Scalars *sc,
+                                                       const real *part_ap, real *part_upd) {
     if (sc->pcg.done) return;
-    const real alpha = (real)sc->pcg.alpha;
+    real t[1];
+    read_partials<real, 1>(part_ap, gridDim.x, Ops<0u>(), t);
+    const double pq = (double)t[0];
+    const double rzd = sc->pcg.rz_next;
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pcg.done = 1;
+            sc->pcg.status = (pq == pq) ? kStBreakdown : kStNonFinite;
+            sc->pcg.it = j;
+        }
+        return;
+    }
+    const real alpha = (real)rzd / t[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pcg.rz_cur = rzd;
     const Chunk c = my_chunk(A.n, chunk);
     real v[2] = {real(0), real(0)};
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
@@ -552,40 +545,18 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, real *__restrict__ 
             v[1] += ri * ri;
         }
     }
-    real tot[2];
-    if (last_block_reduce<real, 2>(v, Ops<0u>(), partials, &sc->counters[kCntUpd], tot)) {
-        if (threadIdx.x == 0) {
-            PcgState &s = sc->pcg;
-            const double rr = (double)tot[0];
-            s.rr = rr;
-            s.it += 1;
-            if (!(rr == rr)) {
-                s.status = kStNonFinite;
-                s.done = 1;
-            } else if (sqrt(rr) <= s.tol) {
-                s.status = kStOk;
-                s.done = 1;
-            } else if (s.it >= s.max_iter) {
-                s.status = kStNoConv;
-                s.done = 1;
-            } else if (kPc != 2) {
-                const real rzn = tot[1];
-                s.beta = (double)(rzn / (real)s.rz);
-                s.rz = (double)rzn;
-            }
-        }
-    }
+    write_partials<real, 2>(v, Ops<0u>(), part_upd);
 }
 
 // One Gauss-Seidel half sweep over colour c: for rows of that colour,
 // z_i = (r_i - sum_{j != i, ascending} a_ij z_j) / a_ii.  Rows of one colour
-// never couple, so the update is order-free.  With kRz the last block forms
-// r.z (all rows) and beta (or the initial r.z).  With a null state this is
-// the smoother of Algorithm 1 (r = b, z = x).
+// never couple, so the update is order-free.  With kRz the kernel also
+// writes partials of r.z (all rows).  With a null state this is the smoother
+// of Algorithm 1 (r = b, z = x).
 template <class Op, typename real, bool kRz>
 __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const real *__restrict__ r,
                                                     real *z, int colour, int64_t chunk,
-                                                    Scalars *sc, real *partials) {
+                                                    const Scalars *sc, real *part_sgs) {
     if (sc && sc->pcg.done) return;
     const Chunk c = my_chunk(A.n, chunk);
     real v[1] = {real(0)};
@@ -594,9 +565,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const real *__restrict
         real zi;
         if (A.colour(i) == colour) {
             real acc = ri, d = real(1);
-            A.for_each(i, [&](int64_t j, real a) {
-                if (j == i) d = a;
-                else acc = fma(-a, z[j], acc);
+            A.for_each(i, [&](int64_t jj, real a) {
+                if (jj == i) d = a;
+                else acc = fma(-a, z[jj], acc);
             });
             zi = acc / d;
             z[i] = zi;
@@ -605,26 +576,15 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const real *__restrict
         }
         if (kRz) v[0] += ri * zi;
     }
-    if (!kRz) return;
-    real tot[1];
-    if (last_block_reduce<real, 1>(v, Ops<0u>(), partials, &sc->counters[kCntSgs], tot)) {
-        if (threadIdx.x == 0) {
-            PcgState &s = sc->pcg;
-            const real rzn = tot[0];
-            if (!s.first) s.beta = (double)(rzn / (real)s.rz);
-            s.rz = (double)rzn;
-        }
-    }
+    if (kRz) write_partials<real, 1>(v, Ops<0u>(), part_sgs);
 }
 
-// r = rhs - A x in FP64 with ||r||^2 and max|r|; the last block stores them
-// and flags done when ||r|| <= tol_factor * *tol_base.
+// r = rhs - A x in FP64 (stored if r != null); partials ||r||^2, max|r|.
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_resnorm(Op A, const double *__restrict__ rhs,
                                                     const double *__restrict__ x,
                                                     double *__restrict__ r, int64_t chunk,
-                                                    const double *tol_base, double tol_factor,
-                                                    Scalars *sc, double *partials) {
+                                                    double *part) {
     const Chunk c = my_chunk(A.n, chunk);
     double v[2] = {0.0, 0.0};
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
@@ -635,30 +595,38 @@ __global__ __launch_bounds__(kBlock) void k_resnorm(Op A, const double *__restri
         const double m = fabs(acc);
         v[1] = m > v[1] ? m : v[1];
     }
+    write_partials<double, 2>(v, Ops<2u>(), part);
+}
+
+// one block: fold the residual partials; done when ||r|| <= tol_factor * *tol_base
+__global__ __launch_bounds__(kBlock) void k_fin_res(const double *part, int gprod,
+                                                    const double *tol_base, double tol_factor,
+                                                    Scalars *sc) {
     double tot[2];
-    if (last_block_reduce<double, 2>(v, Ops<2u>(), partials, &sc->counters[kCntRes], tot)) {
-        if (threadIdx.x == 0) {
-            PcgState &s = sc->pcg;
-            s.rr = tot[0];
-            s.rmax = tot[1];
-            s.tol = tol_factor * *tol_base;
-            s.done = sqrt(tot[0]) <= s.tol ? 1 : 0;
-            s.status = (tot[0] == tot[0]) ? kStOk : kStNonFinite;
-            if (s.status != kStOk) s.done = 1;
-        }
+    read_partials<double, 2>(part, gprod, Ops<2u>(), tot);
+    if (threadIdx.x == 0) {
+        ResState &s = sc->res;
+        s.rr = tot[0];
+        s.rmax = tot[1];
+        s.tol = tol_factor * *tol_base;
+        s.status = (tot[0] == tot[0]) ? kStOk : kStNonFinite;
+        s.done = (s.status != kStOk || sqrt(tot[0]) <= s.tol) ? 1 : 0;
     }
 }
 
-// ||v||_2 -> *out (fixed-order tree)
+// ||v||^2 partials, then one block folds them into *out = ||v||_2
 __global__ __launch_bounds__(kBlock) void k_norm2(const double *__restrict__ v, int64_t n,
-                                                  int64_t chunk, double *out, Scalars *sc,
-                                                  double *partials) {
+                                                  int64_t chunk, double *part) {
     const Chunk c = my_chunk(n, chunk);
     double a[1] = {0.0};
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) a[0] += v[i] * v[i];
+    write_partials<double, 1>(a, Ops<0u>(), part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_norm(const double *part, int gprod, double *out) {
     double tot[1];
-    if (last_block_reduce<double, 1>(a, Ops<0u>(), partials, &sc->counters[kCntNorm], tot))
-        if (threadIdx.x == 0) *out = sqrt(tot[0]);
+    read_partials<double, 1>(part, gprod, Ops<0u>(), tot);
+    if (threadIdx.x == 0) *out = sqrt(tot[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -669,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_norm2(const double *__restrict__ v, 
 __global__ __launch_bounds__(kBlock) void k_cast_scale(const double *__restrict__ r,
                                                        float *__restrict__ r32, int64_t n,
                                                        Scalars *sc) {
-    const double s = sc->pcg.rmax > 0.0 ? sc->pcg.rmax : 1.0;
+    const double s = sc->res.rmax > 0.0 ? sc->res.rmax : 1.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->scale = s;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)
@@ -698,14 +666,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ a, T v, int64_t
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)
         a[i] = v;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_copy(T *__restrict__ dst, const T *__restrict__ src,
-                                                 int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        dst[i] = src[i];
 }
 
 // y = A x (measurement of the stencil SpMV on its own)

@@ -1,0 +1,164 @@
+"""Adjoint of the local character-based solve vs the oracle's full-domain
+FP64 adjoint and central finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_01158_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2001_01158_amd import lcs  # noqa: E402
+from paper_2001_01158_amd.autograd import LocalSolve, SolveConfig  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def problem(kind, dims, seed, dt=4.0, window=None):
+    nx, ny, nz = dims
+    shape = (ny, nx) if kind == W.KIND_5PT else (nz, ny, nx)
+    logk = W.lognormal_logk(shape, 1.0, seed)
+    n = nx * ny * nz
+    rng = np.random.default_rng(seed + 1)
+    coef = (W.assemble_5pt if kind == W.KIND_5PT else W.assemble_7pt)(logk, 1.0 / dt)
+    Ah = oracle.csr_from_stencil(kind, nx, ny, nz, coef)
+    # previous state and a localized source: b = x_prev/dt + q
+    x_prev = 0.1 + 0.01 * rng.random(n)
+    q = np.zeros(n)
+    q.reshape(nz, ny, nx)[nz // 3: nz // 3 + max(1, nz // 3), ny // 3: ny // 2, nx // 3: nx // 2] = 1.0
+    b = x_prev / dt + q
+    x_obs = oracle.pcg(Ah, b, x_prev, oracle.PC_JACOBI, 1e-13 * np.linalg.norm(b), 20000)[0] * 0.9
+    win = np.zeros(n)
+    if window is None:
+        win.reshape(nz, ny, nx)[:, ny // 4: 3 * ny // 4, nx // 4: 3 * nx // 4] = 1.0
+    else:
+        win.reshape(nz, ny, nx)[window] = 1.0
+    return logk, b, x_prev, x_obs, win, Ah
+
+
+def oracle_adjoint(kind, dims, logk, b, x_prev, x_obs, win):
+    """Full-domain FP64 adjoint: tight global solves for x and lambda."""
+    nx, ny, nz = dims
+    coef = oracle.assemble_logk(kind, nx, ny, nz, 0.25, logk)
+    Ah = oracle.csr_from_stencil(kind, nx, ny, nz, coef)
+    nb = np.linalg.norm(b)
+    x = oracle.pcg(Ah, b, x_prev, oracle.PC_JACOBI, 1e-14 * nb, 50000)[0]
+    g = win * (x - x_obs)
+    lam = oracle.pcg(Ah, g, np.zeros_like(g), oracle.PC_JACOBI, 1e-14 * np.linalg.norm(g), 50000)[0]
+    return x, lam, oracle.grad_logk(kind, nx, ny, nz, logk, x, lam)
+
+
+def run_gpu(kind, dims, logk, b, x_prev, x_obs, win, eps, thresh="paper", theta=None):
+    nx, ny, nz = dims
+    cfg = SolveConfig(kind=kind, nx=nx, ny=ny, nz=nz, inv_dt=0.25, mode="residual", thresh=thresh,
+                      theta=eps if theta is None else theta, e_max=1, opts=lcs.Options(eps=eps))
+    lk = torch.tensor(logk, dtype=torch.float64, device=DEV, requires_grad=True)
+    bb = torch.tensor(b, dtype=torch.float64, device=DEV, requires_grad=True)
+    x = LocalSolve.apply(lk, bb, torch.tensor(x_prev, device=DEV), cfg, None)
+    wv = torch.tensor(win, device=DEV)
+    loss = 0.5 * torch.sum(wv * (x - torch.tensor(x_obs, device=DEV)) ** 2)
+    loss.backward()
+    return x.detach().cpu().numpy(), lk.grad.detach().cpu().numpy().reshape(-1), \
+        bb.grad.detach().cpu().numpy(), cfg
+
+
+@pytest.mark.parametrize("kind,dims", [(W.KIND_5PT, (64, 48, 1)), (W.KIND_7PT, (14, 12, 10))])
+def test_adjoint_matches_full_domain_oracle(kind, dims):
+    say("adjoint vs oracle", kind, dims)
+    logk, b, x_prev, x_obs, win, Ah = problem(kind, dims, 31)
+    xo, lamo, go = oracle_adjoint(kind, dims, logk, b, x_prev, x_obs, win)
+    xg, gl, gb, _ = run_gpu(kind, dims, logk, b, x_prev, x_obs, win, eps=1e-13)
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-10
+    assert np.linalg.norm(gb - lamo) / np.linalg.norm(lamo) < 1e-9
+    assert np.linalg.norm(gl - go) / np.linalg.norm(go) < 1e-9
+
+
+def test_adjoint_central_differences_small():
+    kind, dims = W.KIND_5PT, (40, 32, 1)
+    say("adjoint FD small")
+    logk, b, x_prev, x_obs, win, Ah = problem(kind, dims, 41)
+    xg, gl, gb, cfg = run_gpu(kind, dims, logk, b, x_prev, x_obs, win, eps=1e-14)
+
+    def L(lk, bv):
+        x = LocalSolve.apply(torch.tensor(lk, device=DEV), torch.tensor(bv, device=DEV),
+                             torch.tensor(x_prev, device=DEV), cfg, None)
+        return 0.5 * float(torch.sum(torch.tensor(win, device=DEV) *
+                                     (x - torch.tensor(x_obs, device=DEV)) ** 2))
+
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    for _ in range(4):
+        d = rng.choice([-1.0, 1.0], size=logk.shape)
+        fd = (L(logk + h * d, b) - L(logk - h * d, b)) / (2 * h)
+        ad = float(np.sum(gl * d.reshape(-1)))
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-12) + 1e-9, (fd, ad)
+        e = rng.choice([-1.0, 1.0], size=b.shape)
+        fd = (L(logk, b + h * e) - L(logk, b - h * e)) / (2 * h)
+        ad = float(np.sum(gb * e))
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-12) + 1e-9, (fd, ad)
+
+
+def test_adjoint_c4_scale():
+    """2048x2048 five-point FP64, loss over a 256x256 window: gradient of 4.2M
+    log-conductivities and b, against the oracle's full-domain adjoint and
+    central differences along 16 Rademacher directions."""
+    nx = ny = 2048
+    say("adjoint 2048^2")
+    w = W.c4_adjoint()
+    logk = w.logk
+    dims = (nx, ny, 1)
+    # state at system 10 of the sequence, evolved by the GPU
+    A = lcs.matrix_from_numpy(w.kind, nx, ny, 1, w.coef, DEV)
+    xp = torch.zeros(nx * ny, dtype=torch.float64, device=DEV)
+    for k in range(10):
+        q = torch.tensor(W.disk_source(nx, ny, nx / 2.0 - 4.0 * 10 + 4.0 * k, ny / 2.0, 40.0, 1.0),
+                         device=DEV)
+        b = xp * 0.25 + q
+        lcs.solve_global(A, b, xp, lcs.Options(eps=1e-12))
+    x_prev = xp.cpu().numpy()
+    q = W.disk_source(nx, ny, nx / 2.0, ny / 2.0, 40.0, 1.0)
+    b = x_prev * 0.25 + q
+    win = np.zeros(nx * ny)
+    c0 = nx // 2 - 128
+    win.reshape(ny, nx)[c0:c0 + 256, c0:c0 + 256] = 1.0
+    logk2 = W.lognormal_logk((ny, nx), 1.0, W.BASE_SEED + 4)
+    coef2 = W.assemble_5pt(logk2, 0.25)
+    A2 = lcs.matrix_from_numpy(w.kind, nx, ny, 1, coef2, DEV)
+    xo2 = torch.tensor(x_prev, device=DEV)
+    lcs.solve_global(A2, torch.tensor(b, device=DEV), xo2, lcs.Options(eps=1e-13))
+    x_obs = xo2.cpu().numpy()
+    say("  gpu forward/backward")
+    xg, gl, gb, cfg = run_gpu(W.KIND_5PT, dims, logk, b, x_prev, x_obs, win, eps=1e-13)
+    say("  oracle full-domain adjoint")
+    xo, lamo, go = oracle_adjoint(W.KIND_5PT, dims, logk, b, x_prev, x_obs, win)
+    ex = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    eb = np.linalg.norm(gb - lamo) / np.linalg.norm(lamo)
+    el = np.linalg.norm(gl - go) / np.linalg.norm(go)
+    say(f"  rel err x {ex:.2e}  dL/db {eb:.2e}  dL/dlogk {el:.2e}")
+    assert ex < 1e-9 and eb < 1e-8 and el < 1e-8
+    say("  central differences")
+
+    def L(lk, bv):
+        x = LocalSolve.apply(torch.tensor(lk, device=DEV), torch.tensor(bv, device=DEV),
+                             torch.tensor(x_prev, device=DEV), cfg, None)
+        return 0.5 * float(torch.sum(torch.tensor(win, device=DEV) *
+                                     (x - torch.tensor(x_obs, device=DEV)) ** 2))
+
+    rng = np.random.default_rng(16)
+    h = 1e-6
+    worst = 0.0
+    for _ in range(16):
+        d = rng.choice([-1.0, 1.0], size=logk.shape)
+        fd = (L(logk + h * d, b) - L(logk - h * d, b)) / (2 * h)
+        ad = float(np.sum(gl * d.reshape(-1)))
+        worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-30))
+    say(f"  worst FD relative gap over 16 directions: {worst:.2e}")
+    assert worst < 1e-4

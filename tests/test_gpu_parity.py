@@ -138,19 +138,21 @@ def test_local_domain_bitexact(name, mode, thresh, theta, e_max, ctx):
 
 @pytest.mark.parametrize("name", ["5pt", "7pt"])
 def test_local_domain_paper_threshold(name, ctx):
-    """tau = eps ||b|| / sqrt(N): ||b|| is summed in a different order on the
-    two sides, so points within a few ulps of tau may differ; none else."""
+    """tau = eps ||b|| / sqrt(N): ||b||^2 is summed in a different order on
+    the two sides; a sum of N positive terms in any order is within (N-1)u
+    relative of the exact one, so the two thresholds agree to about N*u and
+    only points within that band of tau may be classified differently."""
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
     say("domain paper threshold", name, dims)
     idx, mask, st = lcs.build_local_domain(A, dev(b), dev(x0), "residual", "paper", 1e-8, 1,
                                            want_mask=True, ctx=ctx)
     d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-8, oracle.TH_PAPER, 1)
-    assert abs(st.tau - d.tau) <= 4 * np.spacing(d.tau)
+    band = A.n * np.finfo(np.float64).eps * d.tau
+    assert abs(st.tau - d.tau) <= band
     diff = np.nonzero(host(mask) != d.mask)[0]
     r = d.score
     for i in diff:   # only near-ties of the threshold may differ
-        assert abs(abs(r[i]) - d.tau) <= 8 * np.spacing(d.tau)
-    assert len(diff) == 0 or len(diff) < 3
+        assert abs(abs(r[i]) - d.tau) <= 2 * band
 
 
 def test_empty_and_full_domains(ctx):
@@ -211,8 +213,11 @@ def test_global_pcg_parity(name, pc, ctx):
     nb = np.linalg.norm(b)
     assert np.linalg.norm(oracle.residual(Ah, b, xg)) <= 1.0001e-10 * nb
     assert abs(st.its_global - so.its_global) <= 1
-    # trajectory parity: stop both at the same iteration count
-    m = max(so.its_global // 2, 1)
+    # trajectory parity: stop both at the same iteration count.  CG amplifies
+    # rounding differences as iterations go on (loss of orthogonality), so
+    # compare within the first 20 iterations, where a wrong index, sign or
+    # coefficient would still show at O(1).
+    m = max(min(so.its_global // 2, 20), 1)
     xo_m, sto, it_o, _ = oracle.pcg(Ah, b, x0, PC[pc], 0.0, m)
     xm = dev(x0)
     with pytest.raises(lcs.LcsError) as e:
