@@ -72,6 +72,19 @@ int flat_grid(int64_t n) {
     return (int)g;
 }
 
+// Grid of the band kernels: a multiple of 8 (one band per XCD).  Kernels
+// whose partials the next kernel folds keep at most kMaxGrid blocks (each
+// consumer block reads them all); the others may use more.
+int band_grid(int64_t units, int cap) {
+    int64_t g = (units + kBlock - 1) / kBlock;
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    if (g < kXcds) g = kXcds;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+constexpr int kRedGrid = 512;     // reducing band kernels
+constexpr int kStreamGrid = 4096; // non-reducing band kernels
+
 // Compaction tiling: tiles of kTile stamps, at most kMaxGrid blocks.
 struct Tiling {
     int grid;
@@ -91,7 +104,7 @@ Tiling tiling_for(int64_t n) {
 enum BufId {
     B_SCORE, B_R, B_Z, B_P0, B_P1, B_Q, B_RHSL, B_DL, B_RES, B_STAMP, B_INV, B_IDX, B_BLOCKOFF,
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
-    B_P32A, B_P32B, B_Q32, B_COEF32, B_NUM
+    B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_NUM
 };
 
 }  // namespace
@@ -173,29 +186,61 @@ lcs_status check_ptr(const void *p, const char *what) {
 // ---------------------------------------------------------------------------
 // operators from the C description
 // ---------------------------------------------------------------------------
+// Scalar row operators (marking rounds, gather) and unit operators for the
+// grid-sized kernels.  Vector width: FP64 strips of 2, FP32 strips of 4 when
+// nx is a multiple of 4 and every pointer is 16-byte aligned, else 1.
 template <typename real>
-Stencil5<real> op5(const lcs_matrix *A, const real *c) {
+Stencil5<real> sop5(const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny;
     return {c, c + n, c + 2 * n, A->nx, A->ny, n};
 }
 template <typename real>
-Stencil9<real> op9(const lcs_matrix *A, const real *c) {
+Stencil9<real> sop9(const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny;
     return {c, c + n, c + 2 * n, c + 3 * n, c + 4 * n, A->nx, A->ny, n};
 }
 template <typename real>
-Stencil7<real> op7(const lcs_matrix *A, const real *c) {
+Stencil7<real> sop7(const lcs_matrix *A, const real *c) {
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    return {c, c + n, c + 2 * n, c + 3 * n, A->nx, A->ny, A->nz, n};
+}
+template <typename real, int V>
+U5<real, V> uop5(const lcs_matrix *A, const real *c) {
+    const int64_t n = (int64_t)A->nx * A->ny;
+    return {c, c + n, c + 2 * n, A->nx, A->ny, n};
+}
+template <typename real, int V>
+U9<real, V> uop9(const lcs_matrix *A, const real *c) {
+    const int64_t n = (int64_t)A->nx * A->ny;
+    return {c, c + n, c + 2 * n, c + 3 * n, c + 4 * n, A->nx, A->ny, n};
+}
+template <typename real, int V>
+U7<real, V> uop7(const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
     return {c, c + n, c + 2 * n, c + 3 * n, A->nx, A->ny, A->nz, n};
 }
 
-// Calls f(op64, op32) with the operator types of A's kind.
+template <int W>
+struct Width {
+    static constexpr int value = W;
+};
+
+bool aligned16(const void *p) { return p == nullptr || ((uintptr_t)p & 15u) == 0; }
+
+// Calls f(scalar_op64, unit_op64, unit_op32, Width<W>) for A's kind.
 template <class F>
-lcs_status with_ops(const lcs_matrix *A, const float *coef32, F &&f) {
+lcs_status with_ops(const lcs_matrix *A, const float *coef32, bool vec_ok, F &&f) {
+    const bool v = vec_ok && A->nx % 4 == 0 && aligned16(A->coef) && aligned16(coef32);
     switch (A->kind) {
-    case LCS_STENCIL5_2D: return f(op5<double>(A, A->coef), op5<float>(A, coef32));
-    case LCS_STENCIL9_2D: return f(op9<double>(A, A->coef), op9<float>(A, coef32));
-    default: return f(op7<double>(A, A->coef), op7<float>(A, coef32));
+    case LCS_STENCIL5_2D:
+        if (v) return f(sop5<double>(A, A->coef), uop5<double, 2>(A, A->coef), uop5<float, 4>(A, coef32), Width<5>());
+        return f(sop5<double>(A, A->coef), uop5<double, 1>(A, A->coef), uop5<float, 1>(A, coef32), Width<5>());
+    case LCS_STENCIL9_2D:
+        if (v) return f(sop9<double>(A, A->coef), uop9<double, 2>(A, A->coef), uop9<float, 4>(A, coef32), Width<9>());
+        return f(sop9<double>(A, A->coef), uop9<double, 1>(A, A->coef), uop9<float, 1>(A, coef32), Width<9>());
+    default:
+        if (v) return f(sop7<double>(A, A->coef), uop7<double, 2>(A, A->coef), uop7<float, 4>(A, coef32), Width<7>());
+        return f(sop7<double>(A, A->coef), uop7<double, 1>(A, A->coef), uop7<float, 1>(A, coef32), Width<7>());
     }
 }
 
@@ -241,73 +286,77 @@ struct PcgResult {
 // z = M^-1 r for the symmetric red-black (or four-colour) Gauss-Seidel
 // preconditioner from z = 0: colours 0..nc-1, then nc-2..0 (the backward
 // pass's first colour would repeat the forward pass's last one exactly).
-template <class Op, typename real, int kPc>
-lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<real> &B, const Launch &L,
+template <class Op, int kPc>
+lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<typename Op::real> &B, int grid,
                           int ncol, hipStream_t s) {
+    using real = typename Op::real;
     if (kPc != LCS_PC_RBSGS) return LCS_OK;
     real *part = slot_as<real>(c, kPtSgs);
     const Scalars *sc = c->dsc;
     for (int col = 0; col < ncol; ++col)
-        hipLaunchKernelGGL((k_gs_half<Op, real, false>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                           (const real *)B.r, B.z, col, L.chunk, sc, part);
+        hipLaunchKernelGGL((k_gs_half<Op, false>), dim3(grid), dim3(kBlock), 0, s, A,
+                           (const real *)B.r, B.z, col, sc, part);
     for (int col = ncol - 2; col >= 0; --col) {
         if (col == 0)
-            hipLaunchKernelGGL((k_gs_half<Op, real, true>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               (const real *)B.r, B.z, col, L.chunk, sc, part);
+            hipLaunchKernelGGL((k_gs_half<Op, true>), dim3(grid), dim3(kBlock), 0, s, A,
+                               (const real *)B.r, B.z, col, sc, part);
         else
-            hipLaunchKernelGGL((k_gs_half<Op, real, false>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               (const real *)B.r, B.z, col, L.chunk, sc, part);
+            hipLaunchKernelGGL((k_gs_half<Op, false>), dim3(grid), dim3(kBlock), 0, s, A,
+                               (const real *)B.r, B.z, col, sc, part);
     }
     LAUNCH_CHECK();
     return LCS_OK;
 }
 
-// PCG on op x = rhs.  Convergence lives on the device; the host enqueues
-// check_every iterations at a time and polls the flag of the previous chunk
-// while the next one runs, so the GPU never waits for the host.  Launches
-// after convergence exit at their first instruction.
-template <class Op, typename real, int kPc>
-lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const real *rhs, real *x, bool x_zero,
-                     const double *tol_base, double tol_factor, int max_iter, int check_every,
-                     const PcgBufs<real> &B, hipStream_t s, PcgResult *res) {
-    const Launch L = dims_for(A.n);
+// PCG on op x = rhs.  Convergence lives on the device: iteration j is
+// k_pcg_ap(j) + k_pcg_update(j), and the stopping test of the iterate after
+// update(j-1) runs at the start of ap(j).  The host enqueues check_every
+// iterations at a time and polls the flag of the previous chunk while the
+// next one runs, so the GPU never waits for the host; launches after
+// convergence exit at their first instruction.
+template <class Op, int kPc>
+lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real *rhs,
+                     typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
+                     int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
+                     hipStream_t s, PcgResult *res) {
+    using real = typename Op::real;
+    const int64_t n = A.units() * Op::V;
+    const int grid = band_grid(A.units(), kRedGrid);
     real *pupd = slot_as<real>(c, kPtUpd), *pap = slot_as<real>(c, kPtAp);
     real *psgs = slot_as<real>(c, kPtSgs);
     if (max_iter < 0) max_iter = 0;
     if (x_zero) {
-        hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(A.n)), dim3(kBlock), 0, s, x, real(0), A.n);
+        hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, real(0), n);
         LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL((k_pcg_init<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A, rhs,
-                       (const real *)x, B.r, B.z, L.chunk, x_zero ? 1 : 0, c->dsc, pupd);
+    hipLaunchKernelGGL((k_pcg_init<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A, rhs,
+                       (const real *)x, B.r, B.z, x_zero ? 1 : 0, c->dsc, pupd);
     LAUNCH_CHECK();
-    LCS_TRY((launch_precond<Op, real, kPc>(c, A, B, L, ncol, s)));
+    LCS_TRY((launch_precond<Op, kPc>(c, A, B, grid, ncol, s)));
     if (check_every < 1) check_every = 1;
     int flip = 0, next_j = 0;
     auto launch_ap = [&](int j) -> lcs_status {
         real *pold = flip ? B.p1 : B.p0;
         real *pnew = flip ? B.p0 : B.p1;
-        hipLaunchKernelGGL((k_pcg_ap<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                           (const real *)B.z, (const real *)pold, pnew, B.q, L.chunk, j, max_iter,
-                           tol_base, tol_factor, c->dsc, (const real *)pupd, (const real *)psgs, pap);
+        hipLaunchKernelGGL((k_pcg_ap<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A,
+                           (const real *)B.z, (const real *)pold, pnew, B.q, j, max_iter, tol_base,
+                           tol_factor, c->dsc, (const real *)pupd, (const real *)psgs, pap);
         LAUNCH_CHECK();
         return LCS_OK;
     };
-    // iteration j = k_pcg_ap(j) + k_pcg_update(j) [+ RB-SGS half sweeps]; the
-    // stopping test of the iterate after update(j-1) runs at the start of ap(j)
     auto enqueue_chunk = [&](int slot_id) -> lcs_status {
         for (int k = 0; k < check_every && next_j < max_iter; ++k) {
             const int j = next_j++;
             LCS_TRY(launch_ap(j));
             real *pnew = flip ? B.p0 : B.p1;
-            hipLaunchKernelGGL((k_pcg_update<Op, real, kPc>), dim3(L.grid), dim3(kBlock), 0, s, A,
-                               x, (const real *)pnew, (const real *)B.q, B.r, B.z, L.chunk, j,
-                               c->dsc, (const real *)pap, pupd);
+            hipLaunchKernelGGL((k_pcg_update<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A, x,
+                               (const real *)pnew, (const real *)B.q, B.r, B.z, j, c->dsc,
+                               (const real *)pap, pupd);
             LAUNCH_CHECK();
-            LCS_TRY((launch_precond<Op, real, kPc>(c, A, B, L, ncol, s)));
+            LCS_TRY((launch_precond<Op, kPc>(c, A, B, grid, ncol, s)));
             flip ^= 1;
         }
-        if (next_j >= max_iter) LCS_TRY(launch_ap(next_j));   // final stopping test
+        if (next_j >= max_iter) LCS_TRY(launch_ap(next_j));  // final stopping test
         HIP_TRY(hipMemcpyAsync(&c->hdone[slot_id], &c->dsc->pcg.done, sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(c->chk[slot_id], s));
@@ -325,27 +374,28 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const real *rhs, real *x
     LCS_TRY(read_scalars(c, s));
     res->its = c->hsc->pcg.it;
     res->status = c->hsc->pcg.status;
-    if (!c->hsc->pcg.done) {   // cannot happen: the final test always runs
+    if (!c->hsc->pcg.done) {  // cannot happen: the final test always runs
         res->its = max_iter;
         res->status = kStNoConv;
     }
     return LCS_OK;
 }
 
-template <class Op, typename real>
-lcs_status run_pcg(lcs_ctx *c, const Op &A, int ncol, int pc, const real *rhs, real *x,
-                   bool x_zero, const double *tol_base, double tol_factor, int max_iter,
-                   int check_every, const PcgBufs<real> &B, hipStream_t s, PcgResult *res) {
+template <class Op>
+lcs_status run_pcg(lcs_ctx *c, const Op &A, int ncol, int pc, const typename Op::real *rhs,
+                   typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
+                   int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
+                   hipStream_t s, PcgResult *res) {
     switch (pc) {
     case LCS_PC_NONE:
-        return run_pcg_t<Op, real, 0>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                      check_every, B, s, res);
+        return run_pcg_t<Op, 0>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
+                                check_every, B, s, res);
     case LCS_PC_JACOBI:
-        return run_pcg_t<Op, real, 1>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                      check_every, B, s, res);
+        return run_pcg_t<Op, 1>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
+                                check_every, B, s, res);
     default:
-        return run_pcg_t<Op, real, 2>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                      check_every, B, s, res);
+        return run_pcg_t<Op, 2>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
+                                check_every, B, s, res);
     }
 }
 
@@ -361,11 +411,11 @@ lcs_status status_of(int st) {
 template <class Op>
 lcs_status launch_resnorm(lcs_ctx *c, const Op &A, const double *rhs, const double *x, double *r,
                           const double *tol_base, double tol_factor, hipStream_t s) {
-    const Launch L = dims_for(A.n);
-    hipLaunchKernelGGL((k_resnorm<Op>), dim3(L.grid), dim3(kBlock), 0, s, A, rhs, x, r, L.chunk,
+    const int grid = band_grid(A.units(), kRedGrid);
+    hipLaunchKernelGGL((k_resnorm<Op>), dim3(grid), dim3(kBlock), 0, s, A, rhs, x, r,
                        slot(c, kPtRes));
     hipLaunchKernelGGL(k_fin_res, dim3(1), dim3(kBlock), 0, s, (const double *)slot(c, kPtRes),
-                       L.grid, tol_base, tol_factor, c->dsc);
+                       grid, tol_base, tol_factor, c->dsc);
     LAUNCH_CHECK();
     return LCS_OK;
 }
@@ -373,7 +423,7 @@ lcs_status launch_resnorm(lcs_ctx *c, const Op &A, const double *rhs, const doub
 struct SolveOut {
     int its = 0;
     int n_outer = 0;
-    double rr = 0.0;   // ||rhs - op x||^2 at exit (FP64)
+    double rr = 0.0;  // ||rhs - op x||^2 at exit (FP64)
 };
 
 // Solve op x = rhs to ||rhs - op x|| <= tol_factor * *tol_base.
@@ -384,7 +434,7 @@ template <class Op64, class Op32>
 lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, const double *rhs,
                         double *x, bool x_zero, const double *tol_base, double tol_factor,
                         const lcs_options *o, hipStream_t s, SolveOut *out) {
-    const int64_t n = A.n;
+    const int64_t n = A.units() * Op64::V;
     *out = SolveOut();
     if (n == 0) return LCS_OK;
     const int check = o->check_every > 0 ? o->check_every : 8;
@@ -456,33 +506,34 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
 // ---------------------------------------------------------------------------
 // Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
 // ascending domain in idx; returns K (host).
-template <class Op>
-lcs_status build_domain(lcs_ctx *c, const Op &A, const double *b, const double *x0, int mode,
-                        int thresh, double theta, int e_max, int32_t *idx, int64_t *K,
-                        hipStream_t s) {
-    const int64_t n = A.n;
+template <class SOp, class UOp>
+lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *b,
+                        const double *x0, int mode, int thresh, double theta, int e_max,
+                        int32_t *idx, int64_t *K, hipStream_t s) {
+    const int64_t n = As.n;
     const Launch L = dims_for(n);
     const Tiling T = tiling_for(n);
+    const int gs = band_grid(Au.units(), kRedGrid);
     double *score;
     uint8_t *stamp;
     int32_t *inv, *blockoff;
     LCS_TRY(get_buf(c, B_SCORE, n, &score));
     LCS_TRY(get_buf(c, B_STAMP, T.npad, &stamp));
     LCS_TRY(get_buf(c, B_INV, n, &inv));
-    LCS_TRY(get_buf(c, B_BLOCKOFF, kMaxGrid, &blockoff));
+    LCS_TRY(get_buf(c, B_BLOCKOFF, 2 * kMaxGrid, &blockoff));
     if (mode == LCS_MODE_RESIDUAL)
-        hipLaunchKernelGGL((k_score<Op, 0>), dim3(L.grid), dim3(kBlock), 0, s, A, b, x0, score,
-                           L.chunk, slot(c, kPtScore));
+        hipLaunchKernelGGL((k_score<UOp, 0>), dim3(gs), dim3(kBlock), 0, s, Au, b, x0, score,
+                           slot(c, kPtScore));
     else
-        hipLaunchKernelGGL((k_score<Op, 1>), dim3(L.grid), dim3(kBlock), 0, s, A, b, x0, score,
-                           L.chunk, slot(c, kPtScore));
+        hipLaunchKernelGGL((k_score<UOp, 1>), dim3(gs), dim3(kBlock), 0, s, Au, b, x0, score,
+                           slot(c, kPtScore));
     const int gmark = std::min(flat_grid(T.npad), 512);
     hipLaunchKernelGGL(k_mark, dim3(gmark), dim3(kBlock), 0, s, (const double *)score, stamp, n,
-                       T.npad, thresh, theta, (const double *)slot(c, kPtScore), L.grid, c->dsc);
+                       T.npad, thresh, theta, (const double *)slot(c, kPtScore), gs, c->dsc);
     LAUNCH_CHECK();
     const int ex = mode == LCS_MODE_RESIDUAL ? e_max : 0;
     for (int m = 1; m <= ex; ++m)
-        hipLaunchKernelGGL((k_expand<Op>), dim3(L.grid), dim3(kBlock), 0, s, A,
+        hipLaunchKernelGGL((k_expand<SOp>), dim3(L.grid), dim3(kBlock), 0, s, As,
                            (const double *)score, x0, stamp, m, L.chunk,
                            (const double *)slot(c, kPtExp0 + ((m - 1) & 1)),
                            slot(c, kPtExp0 + (m & 1)), c->dsc);
@@ -501,48 +552,36 @@ lcs_status build_domain(lcs_ctx *c, const Op &A, const double *b, const double *
 // ---------------------------------------------------------------------------
 // restricted system and local solve (steps 3-7 of Algorithm 1)
 // ---------------------------------------------------------------------------
+template <int W>
 struct Restricted {
-    Csr<double> B64;
-    Csr<float> B32;
+    UEll<double, W> B64;
+    UEll<float, W> B32;
     double *rhs;
-    int64_t nnz;
 };
 
-// B = A[idx, idx] in CSR (row lengths -> scan -> fill); rhs = r[idx].
-template <class Op>
-lcs_status gather(lcs_ctx *c, const Op &A, const int32_t *idx, int64_t K, const int32_t *inv,
-                  const double *r, bool with32, Restricted *R, hipStream_t s) {
-    int32_t *rowlen, *rp, *col, *blockoff;
+// B = A[idx, idx] in ELL (one pass, no scan); rhs = r[idx] when r is given.
+template <int W, class SOp>
+lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const int32_t *inv,
+                  const double *r, bool with32, Restricted<W> *R, hipStream_t s) {
+    int32_t *col;
     double *val, *dg, *rhs;
     float *val32 = nullptr, *dg32 = nullptr;
     uint8_t *clr;
-    const int64_t cap = K * 9;
-    LCS_TRY(get_buf(c, B_ROWLEN, K, &rowlen));
-    LCS_TRY(get_buf(c, B_RP, K + 1, &rp));
-    LCS_TRY(get_buf(c, B_COL, cap, &col));
-    LCS_TRY(get_buf(c, B_VAL, cap, &val));
+    LCS_TRY(get_buf(c, B_COL, (size_t)K * W, &col));
+    LCS_TRY(get_buf(c, B_VAL, (size_t)K * W, &val));
     LCS_TRY(get_buf(c, B_DG, K, &dg));
     LCS_TRY(get_buf(c, B_CLR, K, &clr));
     LCS_TRY(get_buf(c, B_RHSL, K, &rhs));
-    LCS_TRY(get_buf(c, B_BLOCKOFF, kMaxGrid, &blockoff));
     if (with32) {
-        LCS_TRY(get_buf(c, B_VAL32, cap, &val32));
+        LCS_TRY(get_buf(c, B_VAL32, (size_t)K * W, &val32));
         LCS_TRY(get_buf(c, B_DG32, K, &dg32));
     }
-    const Tiling T = tiling_for(K);
-    hipLaunchKernelGGL((k_gather_count<Op>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K,
-                       inv, rowlen);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)rowlen, K,
-                       T.tiles_per_block, blockoff);
-    hipLaunchKernelGGL(k_scan_apply, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)rowlen, K,
-                       T.tiles_per_block, (const int32_t *)blockoff, rp, c->dsc);
-    hipLaunchKernelGGL((k_gather_fill<Op>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K, inv,
-                       (const int32_t *)rp, col, val, val32, dg, dg32, clr, r, r ? rhs : nullptr);
+    hipLaunchKernelGGL((k_gather_ell<SOp>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K, inv,
+                       W, col, val, val32, dg, dg32, clr, r, r ? rhs : nullptr);
     LAUNCH_CHECK();
-    R->B64 = {rp, col, val, dg, clr, K};
-    R->B32 = {rp, col, val32, dg32, clr, K};
+    R->B64 = {col, val, dg, clr, K};
+    R->B32 = {col, val32, dg32, clr, K};
     R->rhs = rhs;
-    R->nnz = -1;
     return LCS_OK;
 }
 
@@ -567,8 +606,8 @@ struct Timers {
 
 // x <- x + d on Omega after solving B d = r^(0)_Omega, then smoothing.
 // r0: r^(0) over the whole grid when the caller already has it, else null.
-template <class Op64, class Op32>
-lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const Op64 &A, const Op32 &A32,
+template <int W, class SOp, class UOp>
+lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp &Au,
                        const double *b, double *x, const int32_t *idx, int64_t K,
                        const int32_t *inv, const double *r0, const lcs_options *o,
                        lcs_stats *st, Timers &tm, hipStream_t s) {
@@ -576,12 +615,12 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const Op64 &A, const Op3
     if (K > 0) {
         if (!r0) {
             double *r;
-            LCS_TRY(get_buf(c, B_SCORE, A.n, &r));
-            LCS_TRY(launch_resnorm(c, A, b, (const double *)x, r, &c->dsc->bnorm, o->eps, s));
+            LCS_TRY(get_buf(c, B_SCORE, As.n, &r));
+            LCS_TRY(launch_resnorm(c, Au, b, (const double *)x, r, &c->dsc->bnorm, o->eps, s));
             r0 = r;
         }
-        Restricted R;
-        LCS_TRY(gather(c, A, idx, K, inv, r0, o->precision == LCS_PREC_MIXED, &R, s));
+        Restricted<W> R;
+        LCS_TRY(gather<W>(c, As, idx, K, inv, r0, o->precision == LCS_PREC_MIXED, &R, s));
         double *d;
         LCS_TRY(get_buf(c, B_DL, K, &d));
         const double tl = o->tol_local > 0 ? o->tol_local : o->eps;
@@ -599,12 +638,11 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const Op64 &A, const Op3
     }
     LCS_TRY(tm.mark(2));
     if (o->n_smooth > 0) {
-        const Launch L = dims_for(A.n);
+        const int grid = band_grid(Au.units(), kStreamGrid);
         for (int sw = 0; sw < o->n_smooth; ++sw)
             for (int col = 0; col < ncol; ++col)
-                hipLaunchKernelGGL((k_gs_half<Op64, double, false>), dim3(L.grid), dim3(kBlock), 0,
-                                   s, A, b, x, col, L.chunk, (const Scalars *)nullptr,
-                                   (double *)nullptr);
+                hipLaunchKernelGGL((k_gs_half<UOp, false>), dim3(grid), dim3(kBlock), 0, s, Au, b, x,
+                                   col, (const Scalars *)nullptr, (double *)nullptr);
         LAUNCH_CHECK();
     }
     LCS_TRY(tm.mark(3));
@@ -629,6 +667,22 @@ void init_stats(lcs_stats *st) {
     std::memset(st, 0, sizeof(*st));
     st->relres_after_local = NAN;
     st->relres_final = NAN;
+}
+
+bool vec_ok(std::initializer_list<const void *> ps) {
+    for (const void *p : ps)
+        if (!aligned16(p)) return false;
+    return true;
+}
+
+lcs_status check_mode(int32_t mode, int32_t thresh_kind, double theta, int32_t e_max) {
+    if (mode != LCS_MODE_RESIDUAL && mode != LCS_MODE_GRADIENT) return fail(LCS_EINVAL, "mode");
+    if (thresh_kind < 0 || thresh_kind > 2) return fail(LCS_EINVAL, "threshold kind");
+    if (thresh_kind == LCS_THRESH_PAPER && mode != LCS_MODE_RESIDUAL)
+        return fail(LCS_EINVAL, "the paper threshold belongs to the residual mode");
+    if (e_max < 0 || e_max > 250) return fail(LCS_EINVAL, "e_max must be in 0..250");
+    if (!(theta >= 0.0)) return fail(LCS_EINVAL, "theta must be >= 0");
+    return LCS_OK;
 }
 
 }  // namespace
@@ -704,8 +758,9 @@ lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const 
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(r, "r"));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
-        LCS_TRY(launch_norm(c, b, op.n, &c->dsc->bnorm, s));
+    return with_ops(A, nullptr, vec_ok({b, x, r}), [&](auto, auto op, auto, auto) -> lcs_status {
+        const int64_t n = op.units() * decltype(op)::V;
+        LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         LCS_TRY(launch_resnorm(c, op, b, x, r, &c->dsc->bnorm, 1.0, s));
         HIP_TRY(hipStreamSynchronize(s));
         return LCS_OK;
@@ -718,10 +773,10 @@ lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(g, "g"));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
-        const Launch L = dims_for(op.n);
-        hipLaunchKernelGGL((k_score<decltype(op), 1>), dim3(L.grid), dim3(kBlock), 0, s, op, x, x,
-                           g, L.chunk, slot(c, kPtScore));
+    return with_ops(A, nullptr, vec_ok({x, g}), [&](auto, auto op, auto, auto) -> lcs_status {
+        const int grid = band_grid(op.units(), kRedGrid);
+        hipLaunchKernelGGL((k_score<decltype(op), 1>), dim3(grid), dim3(kBlock), 0, s, op, x, x, g,
+                           slot(c, kPtScore));
         LAUNCH_CHECK();
         HIP_TRY(hipStreamSynchronize(s));
         return LCS_OK;
@@ -739,15 +794,15 @@ lcs_status lcs_spmv(lcs_ctx *c, const lcs_matrix *A, const void *x, void *y, int
     hipStream_t s = (hipStream_t)stream;
     const float *c32 = nullptr;
     LCS_TRY(ensure_coef32(c, A, precision == LCS_PREC_MIXED, &c32, s));
-    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
-        const Launch L = dims_for(op.n);
+    return with_ops(A, c32, vec_ok({x, y}), [&](auto, auto op, auto op32, auto) -> lcs_status {
         for (int k = 0; k < std::max(reps, 1); ++k) {
             if (precision == LCS_PREC_FP64)
-                hipLaunchKernelGGL((k_spmv<decltype(op), double>), dim3(L.grid), dim3(kBlock), 0, s,
-                                   op, (const double *)x, (double *)y, L.chunk);
+                hipLaunchKernelGGL((k_spmv<decltype(op)>), dim3(band_grid(op.units(), kStreamGrid)),
+                                   dim3(kBlock), 0, s, op, (const double *)x, (double *)y);
             else
-                hipLaunchKernelGGL((k_spmv<decltype(op32), float>), dim3(L.grid), dim3(kBlock), 0,
-                                   s, op32, (const float *)x, (float *)y, L.chunk);
+                hipLaunchKernelGGL((k_spmv<decltype(op32)>),
+                                   dim3(band_grid(op32.units(), kStreamGrid)), dim3(kBlock), 0, s,
+                                   op32, (const float *)x, (float *)y);
         }
         LAUNCH_CHECK();
         return LCS_OK;
@@ -775,19 +830,14 @@ lcs_status lcs_build_local_domain(lcs_ctx *c, const lcs_matrix *A, const double 
     LCS_TRY(check_ptr(x0, "x0"));
     LCS_TRY(check_ptr(idx, "idx"));
     LCS_TRY(check_ptr(K, "K"));
-    if (mode != LCS_MODE_RESIDUAL && mode != LCS_MODE_GRADIENT) return fail(LCS_EINVAL, "mode");
-    if (thresh_kind < 0 || thresh_kind > 2) return fail(LCS_EINVAL, "threshold kind");
-    if (thresh_kind == LCS_THRESH_PAPER && mode != LCS_MODE_RESIDUAL)
-        return fail(LCS_EINVAL, "the paper threshold belongs to the residual mode");
-    if (e_max < 0 || e_max > 250) return fail(LCS_EINVAL, "e_max must be in 0..250");
-    if (!(theta >= 0.0)) return fail(LCS_EINVAL, "theta must be >= 0");
+    LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
-        LCS_TRY(build_domain(c, op, b, x0, mode, thresh_kind, theta, e_max, idx, K, s));
+    return with_ops(A, nullptr, vec_ok({b, x0}), [&](auto sop, auto op, auto, auto) -> lcs_status {
+        LCS_TRY(build_domain(c, sop, op, b, x0, mode, thresh_kind, theta, e_max, idx, K, s));
         if (mask) {
             uint8_t *stamp;
-            LCS_TRY(get_buf(c, B_STAMP, tiling_for(op.n).npad, &stamp));
-            HIP_TRY(hipMemcpyAsync(mask, stamp, (size_t)op.n, hipMemcpyDeviceToDevice, s));
+            LCS_TRY(get_buf(c, B_STAMP, tiling_for(sop.n).npad, &stamp));
+            HIP_TRY(hipMemcpyAsync(mask, stamp, (size_t)sop.n, hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipStreamSynchronize(s));
         }
         if (st) {
@@ -815,24 +865,33 @@ lcs_status lcs_gather_restricted(lcs_ctx *c, const lcs_matrix *A, const int32_t 
     }
     LCS_TRY(check_ptr(nnz, "nnz"));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
-        int32_t *inv;
+    return with_ops(A, nullptr, false, [&](auto sop, auto, auto, auto wtag) -> lcs_status {
+        constexpr int W = decltype(wtag)::value;
+        int32_t *inv, *len, *blocksum;
         LCS_TRY(get_buf(c, B_INV, n, &inv));
         LCS_TRY(set_inv(c, idx, K, n, inv, s));
         if (K == 0) {
             *nnz = 0;
-            if (row_ptr) HIP_TRY(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s));
+            HIP_TRY(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s));
             HIP_TRY(hipStreamSynchronize(s));
             return LCS_OK;
         }
-        Restricted R;
-        LCS_TRY(gather(c, op, idx, K, inv, nullptr, false, &R, s));
+        Restricted<W> R;
+        LCS_TRY(gather<W>(c, sop, idx, K, inv, nullptr, false, &R, s));
+        // ELL -> CSR: row lengths, exclusive scan, fill
+        LCS_TRY(get_buf(c, B_ROWLEN, K, &len));
+        LCS_TRY(get_buf(c, B_BLOCKOFF, 2 * kMaxGrid, &blocksum));
+        const Tiling T = tiling_for(K);
+        hipLaunchKernelGGL(k_ell_rowlen, dim3(flat_grid(K)), dim3(kBlock), 0, s, R.B64.col, K, W, len);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)len, K,
+                           T.tiles_per_block, blocksum);
+        hipLaunchKernelGGL(k_scan_apply, dim3(T.grid), dim3(kBlock), 0, s, (const int32_t *)len, K,
+                           T.tiles_per_block, (const int32_t *)blocksum, row_ptr, c->dsc);
+        hipLaunchKernelGGL(k_ell_to_csr, dim3(flat_grid(K)), dim3(kBlock), 0, s, R.B64.col, R.B64.val,
+                           K, W, (const int32_t *)row_ptr, col, val);
+        LAUNCH_CHECK();
         LCS_TRY(read_scalars(c, s));
         *nnz = c->hsc->gather_nnz;
-        HIP_TRY(hipMemcpyAsync(row_ptr, R.B64.rp, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(col, R.B64.col, sizeof(int32_t) * *nnz, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(val, R.B64.val, sizeof(double) * *nnz, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
         return LCS_OK;
     });
 }
@@ -846,13 +905,12 @@ lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, doubl
     if (n_sweeps < 0) return fail(LCS_EINVAL, "n_sweeps < 0");
     hipStream_t s = (hipStream_t)stream;
     const int ncol = n_colours(A->kind);
-    return with_ops(A, nullptr, [&](auto op, auto) -> lcs_status {
-        const Launch L = dims_for(op.n);
+    return with_ops(A, nullptr, vec_ok({b, x}), [&](auto, auto op, auto, auto) -> lcs_status {
+        const int grid = band_grid(op.units(), kStreamGrid);
         for (int sw = 0; sw < n_sweeps; ++sw)
             for (int col = 0; col < ncol; ++col)
-                hipLaunchKernelGGL((k_gs_half<decltype(op), double, false>), dim3(L.grid),
-                                   dim3(kBlock), 0, s, op, b, x, col, L.chunk,
-                                   (const Scalars *)nullptr, (double *)nullptr);
+                hipLaunchKernelGGL((k_gs_half<decltype(op), false>), dim3(grid), dim3(kBlock), 0, s,
+                                   op, b, x, col, (const Scalars *)nullptr, (double *)nullptr);
         LAUNCH_CHECK();
         HIP_TRY(hipStreamSynchronize(s));
         return LCS_OK;
@@ -874,8 +932,9 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
     const float *c32 = nullptr;
     LCS_TRY(tm.mark(0));
     LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
-    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
-        LCS_TRY(launch_norm(c, b, op.n, &c->dsc->bnorm, s));
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    return with_ops(A, c32, vec_ok({b, x}), [&](auto, auto op, auto op32, auto) -> lcs_status {
+        LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         LCS_TRY(tm.mark(3));
         SolveOut so;
         const lcs_status rs = solve_system(c, op, op32, n_colours(A->kind), b, x, false,
@@ -911,13 +970,14 @@ lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, dou
     LCS_TRY(tm.mark(0));
     const float *c32 = nullptr;
     LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
-    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
+    return with_ops(A, c32, vec_ok({b, x}), [&](auto sop, auto op, auto, auto wtag) -> lcs_status {
+        constexpr int W = decltype(wtag)::value;
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         int32_t *inv;
         LCS_TRY(get_buf(c, B_INV, n, &inv));
         LCS_TRY(set_inv(c, idx, K, n, inv, s));
         LCS_TRY(tm.mark(1));
-        LCS_TRY(local_phase(c, A, op, op32, b, x, idx, K, inv, nullptr, o, st, tm, s));
+        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, nullptr, o, st, tm, s));
         LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
                                o->eps, s));
         LCS_TRY(read_scalars(c, s));
@@ -940,12 +1000,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
     LCS_TRY(check_options(o, A->kind));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
-    if (mode != LCS_MODE_RESIDUAL && mode != LCS_MODE_GRADIENT) return fail(LCS_EINVAL, "mode");
-    if (thresh_kind < 0 || thresh_kind > 2) return fail(LCS_EINVAL, "threshold kind");
-    if (thresh_kind == LCS_THRESH_PAPER && mode != LCS_MODE_RESIDUAL)
-        return fail(LCS_EINVAL, "the paper threshold belongs to the residual mode");
-    if (e_max < 0 || e_max > 250) return fail(LCS_EINVAL, "e_max must be in 0..250");
-    if (!(theta >= 0.0)) return fail(LCS_EINVAL, "theta must be >= 0");
+    LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
     lcs_stats local;
     if (!st) st = &local;
     init_stats(st);
@@ -955,12 +1010,14 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
     LCS_TRY(tm.mark(0));
     const float *c32 = nullptr;
     LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
-    return with_ops(A, c32, [&](auto op, auto op32) -> lcs_status {
+    return with_ops(A, c32, vec_ok({b, x}), [&](auto sop, auto op, auto op32, auto wtag) -> lcs_status {
+        constexpr int W = decltype(wtag)::value;
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         int32_t *idx;
         LCS_TRY(get_buf(c, B_IDX, n, &idx));
         int64_t K = 0;
-        LCS_TRY(build_domain(c, op, b, (const double *)x, mode, thresh_kind, theta, e_max, idx, &K, s));
+        LCS_TRY(build_domain(c, sop, op, b, (const double *)x, mode, thresh_kind, theta, e_max, idx,
+                             &K, s));
         st->K = K;
         st->e_rounds = c->hsc->ms.grown;
         st->tau = c->hsc->ms.tau;
@@ -971,7 +1028,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         LCS_TRY(get_buf(c, B_SCORE, n, &score));
         LCS_TRY(get_buf(c, B_INV, n, &inv));
         if (mode == LCS_MODE_RESIDUAL) r0 = score;
-        LCS_TRY(local_phase(c, A, op, op32, b, x, idx, K, inv, r0, o, st, tm, s));
+        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, r0, o, st, tm, s));
         // criterion after the local solve and smoothing (Algorithm 1 step 8)
         LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
                                o->eps, s));

@@ -147,6 +147,407 @@ struct Csr {
 };
 
 // ---------------------------------------------------------------------------
+// unit operators: the grid-sized kernels walk "units" — a strip of V
+// consecutive cells of one grid row for the stencils (vector loads of every
+// coefficient array, halo cells by scalar loads), or one row of the
+// restricted matrix in column-major ELL form.  For each cell k of a unit,
+// slots s = 0..NB-1 enumerate the stored entries in ascending column order
+// (a[s][k] the coefficient, gather() the neighbour values), so every per-cell
+// sum has the same rounding sequence as the scalar for_each above.
+// ---------------------------------------------------------------------------
+template <typename T, int V>
+__device__ __forceinline__ void vld(const T *__restrict__ p, T (&o)[V]) {
+    if constexpr (V == 1) {
+        o[0] = p[0];
+    } else {
+        typedef T vt __attribute__((ext_vector_type(V)));
+        const vt t = *reinterpret_cast<const vt *>(p);
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = t[k];
+    }
+}
+template <typename T, int V>
+__device__ __forceinline__ void vst(T *__restrict__ p, const T (&o)[V]) {
+    if constexpr (V == 1) {
+        p[0] = o[0];
+    } else {
+        typedef T vt __attribute__((ext_vector_type(V)));
+        vt t;
+#pragma unroll
+        for (int k = 0; k < V; ++k) t[k] = o[k];
+        *reinterpret_cast<vt *>(p) = t;
+    }
+}
+
+// XCD bands: units [0, nu) are cut into 8 contiguous bands, band b%8 served
+// by the blocks b%8 == const (the hardware places block b on XCD b mod 8);
+// inside a band the blocks stride together, so rows y-1, y, y+1 are read by
+// one XCD close in time and stay in its L2.  gridDim.x is a multiple of 8.
+struct Band {
+    int64_t u, end, step;
+};
+__device__ __forceinline__ Band my_band(int64_t nu) {
+    const int64_t per = gridDim.x / kXcds;
+    const int64_t xcd = blockIdx.x % kXcds, pos = blockIdx.x / kXcds;
+    const int64_t band = (nu + kXcds - 1) / kXcds;
+    int64_t b0 = xcd * band, b1 = b0 + band;
+    if (b1 > nu) b1 = nu;
+    return {b0 + pos * kBlock + threadIdx.x, b1, per * kBlock};
+}
+
+template <typename real_, int V_>
+struct U5 {
+    using real = real_;
+    static constexpr int V = V_, NB = 5, kC = 2;
+    const real *C, *E, *N;
+    int nx, ny;
+    int64_t n;
+    struct Unit {
+        int64_t i0;
+        int x0, y;
+        real a[NB][V];
+    };
+    __host__ __device__ int64_t units() const { return n / V; }
+    __device__ __forceinline__ void geom(Unit &U, int64_t u) const {
+        U.i0 = u * V;
+        U.y = (int)((uint64_t)U.i0 / (uint64_t)nx);
+        U.x0 = (int)(U.i0 - (int64_t)U.y * nx);
+    }
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        geom(U, u);
+        const int64_t i0 = U.i0;
+        real c[V], e[V], nn[V], ns[V];
+        vld<real, V>(C + i0, c);
+        vld<real, V>(E + i0, e);
+        vld<real, V>(N + i0, nn);
+        if (U.y > 0) vld<real, V>(N + i0 - nx, ns);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) ns[k] = real(0);
+        const real ew = U.x0 > 0 ? E[i0 - 1] : real(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            U.a[0][k] = ns[k];
+            U.a[1][k] = k == 0 ? ew : e[k > 0 ? k - 1 : 0];
+            U.a[2][k] = c[k];
+            U.a[3][k] = e[k];
+            U.a[4][k] = nn[k];
+        }
+    }
+    __device__ __forceinline__ bool valid(const Unit &U, int s, int k) const {
+        switch (s) {
+        case 0: return U.y > 0;
+        case 1: return U.x0 + k > 0;
+        case 2: return true;
+        case 3: return U.x0 + k < nx - 1;
+        default: return U.y < ny - 1;
+        }
+    }
+    __device__ __forceinline__ bool is_diag(const Unit &, int s, int) const { return s == kC; }
+    template <typename T>
+    __device__ __forceinline__ void gather(const Unit &U, const T *__restrict__ v, T (&o)[NB][V]) const {
+        const int64_t i0 = U.i0;
+        T c[V], sv[V], nv[V];
+        vld<T, V>(v + i0, c);
+        if (U.y > 0) vld<T, V>(v + i0 - nx, sv);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) sv[k] = T(0);
+        if (U.y < ny - 1) vld<T, V>(v + i0 + nx, nv);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) nv[k] = T(0);
+        const T w = U.x0 > 0 ? v[i0 - 1] : T(0);
+        const T e = U.x0 + V < nx ? v[i0 + V] : T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o[0][k] = sv[k];
+            o[1][k] = k == 0 ? w : c[k > 0 ? k - 1 : 0];
+            o[2][k] = c[k];
+            o[3][k] = k == V - 1 ? e : c[k < V - 1 ? k + 1 : 0];
+            o[4][k] = nv[k];
+        }
+    }
+    __device__ __forceinline__ int colour(const Unit &U, int k) const { return (U.x0 + k + U.y) & 1; }
+    __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
+    template <typename T>
+    __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
+        vld<T, V>(p + U.i0, o);
+    }
+    template <typename T>
+    __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
+        vst<T, V>(p + U.i0, o);
+    }
+};
+
+template <typename real_, int V_>
+struct U9 {
+    using real = real_;
+    static constexpr int V = V_, NB = 9, kC = 4;
+    const real *C, *E, *N, *NE, *NW;
+    int nx, ny;
+    int64_t n;
+    struct Unit {
+        int64_t i0;
+        int x0, y;
+        real a[NB][V];
+    };
+    __host__ __device__ int64_t units() const { return n / V; }
+    __device__ __forceinline__ void geom(Unit &U, int64_t u) const {
+        U.i0 = u * V;
+        U.y = (int)((uint64_t)U.i0 / (uint64_t)nx);
+        U.x0 = (int)(U.i0 - (int64_t)U.y * nx);
+    }
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        geom(U, u);
+        const int64_t i0 = U.i0;
+        const bool s = U.y > 0, w = U.x0 > 0, e = U.x0 + V < nx;
+        real c[V], ee[V], nn[V], ne[V], nw[V], ns[V], nes[V], nws[V];
+        vld<real, V>(C + i0, c);
+        vld<real, V>(E + i0, ee);
+        vld<real, V>(N + i0, nn);
+        vld<real, V>(NE + i0, ne);
+        vld<real, V>(NW + i0, nw);
+        if (s) {
+            vld<real, V>(N + i0 - nx, ns);
+            vld<real, V>(NE + i0 - nx, nes);
+            vld<real, V>(NW + i0 - nx, nws);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; ++k) ns[k] = nes[k] = nws[k] = real(0);
+        }
+        const real ew = w ? E[i0 - 1] : real(0);
+        const real nesw = (s && w) ? NE[i0 - nx - 1] : real(0);
+        const real nwse = (s && e) ? NW[i0 - nx + V] : real(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            U.a[0][k] = k == 0 ? nesw : nes[k > 0 ? k - 1 : 0];
+            U.a[1][k] = ns[k];
+            U.a[2][k] = k == V - 1 ? nwse : nws[k < V - 1 ? k + 1 : 0];
+            U.a[3][k] = k == 0 ? ew : ee[k > 0 ? k - 1 : 0];
+            U.a[4][k] = c[k];
+            U.a[5][k] = ee[k];
+            U.a[6][k] = nw[k];
+            U.a[7][k] = nn[k];
+            U.a[8][k] = ne[k];
+        }
+    }
+    __device__ __forceinline__ bool valid(const Unit &U, int s, int k) const {
+        const bool w = U.x0 + k > 0, e = U.x0 + k < nx - 1, so = U.y > 0, no = U.y < ny - 1;
+        switch (s) {
+        case 0: return so && w;
+        case 1: return so;
+        case 2: return so && e;
+        case 3: return w;
+        case 4: return true;
+        case 5: return e;
+        case 6: return no && w;
+        case 7: return no;
+        default: return no && e;
+        }
+    }
+    __device__ __forceinline__ bool is_diag(const Unit &, int s, int) const { return s == kC; }
+    template <typename T>
+    __device__ __forceinline__ void row3(const Unit &U, const T *__restrict__ v, int64_t base, bool on,
+                                         T (&r)[V + 2]) const {
+        if (on) {
+            T m[V];
+            vld<T, V>(v + base, m);
+#pragma unroll
+            for (int k = 0; k < V; ++k) r[k + 1] = m[k];
+            r[0] = U.x0 > 0 ? v[base - 1] : T(0);
+            r[V + 1] = U.x0 + V < nx ? v[base + V] : T(0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V + 2; ++k) r[k] = T(0);
+        }
+    }
+    template <typename T>
+    __device__ __forceinline__ void gather(const Unit &U, const T *__restrict__ v, T (&o)[NB][V]) const {
+        T rs[V + 2], rc[V + 2], rn[V + 2];
+        row3(U, v, U.i0 - nx, U.y > 0, rs);
+        row3(U, v, U.i0, true, rc);
+        row3(U, v, U.i0 + nx, U.y < ny - 1, rn);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o[0][k] = rs[k];
+            o[1][k] = rs[k + 1];
+            o[2][k] = rs[k + 2];
+            o[3][k] = rc[k];
+            o[4][k] = rc[k + 1];
+            o[5][k] = rc[k + 2];
+            o[6][k] = rn[k];
+            o[7][k] = rn[k + 1];
+            o[8][k] = rn[k + 2];
+        }
+    }
+    __device__ __forceinline__ int colour(const Unit &U, int k) const {
+        return ((U.x0 + k) & 1) + 2 * (U.y & 1);
+    }
+    __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
+    template <typename T>
+    __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
+        vld<T, V>(p + U.i0, o);
+    }
+    template <typename T>
+    __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
+        vst<T, V>(p + U.i0, o);
+    }
+};
+
+template <typename real_, int V_>
+struct U7 {
+    using real = real_;
+    static constexpr int V = V_, NB = 7, kC = 3;
+    const real *C, *E, *N, *Up;
+    int nx, ny, nz;
+    int64_t n;
+    struct Unit {
+        int64_t i0;
+        int x0, y, z;
+        real a[NB][V];
+    };
+    __host__ __device__ int64_t units() const { return n / V; }
+    __device__ __forceinline__ void geom(Unit &U, int64_t u) const {
+        U.i0 = u * V;
+        const int64_t pl = (int64_t)nx * ny;
+        U.z = (int)((uint64_t)U.i0 / (uint64_t)pl);
+        const int64_t r = U.i0 - (int64_t)U.z * pl;
+        U.y = (int)((uint64_t)r / (uint64_t)nx);
+        U.x0 = (int)(r - (int64_t)U.y * nx);
+    }
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        geom(U, u);
+        const int64_t i0 = U.i0, pl = (int64_t)nx * ny;
+        real c[V], e[V], nn[V], uu[V], ns[V], ud[V];
+        vld<real, V>(C + i0, c);
+        vld<real, V>(E + i0, e);
+        vld<real, V>(N + i0, nn);
+        vld<real, V>(Up + i0, uu);
+        if (U.y > 0) vld<real, V>(N + i0 - nx, ns);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) ns[k] = real(0);
+        if (U.z > 0) vld<real, V>(Up + i0 - pl, ud);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) ud[k] = real(0);
+        const real ew = U.x0 > 0 ? E[i0 - 1] : real(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            U.a[0][k] = ud[k];
+            U.a[1][k] = ns[k];
+            U.a[2][k] = k == 0 ? ew : e[k > 0 ? k - 1 : 0];
+            U.a[3][k] = c[k];
+            U.a[4][k] = e[k];
+            U.a[5][k] = nn[k];
+            U.a[6][k] = uu[k];
+        }
+    }
+    __device__ __forceinline__ bool valid(const Unit &U, int s, int k) const {
+        switch (s) {
+        case 0: return U.z > 0;
+        case 1: return U.y > 0;
+        case 2: return U.x0 + k > 0;
+        case 3: return true;
+        case 4: return U.x0 + k < nx - 1;
+        case 5: return U.y < ny - 1;
+        default: return U.z < nz - 1;
+        }
+    }
+    __device__ __forceinline__ bool is_diag(const Unit &, int s, int) const { return s == kC; }
+    template <typename T>
+    __device__ __forceinline__ void gather(const Unit &U, const T *__restrict__ v, T (&o)[NB][V]) const {
+        const int64_t i0 = U.i0, pl = (int64_t)nx * ny;
+        T c[V], d[V], sv[V], nv[V], uv[V];
+        vld<T, V>(v + i0, c);
+        if (U.z > 0) vld<T, V>(v + i0 - pl, d);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) d[k] = T(0);
+        if (U.y > 0) vld<T, V>(v + i0 - nx, sv);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) sv[k] = T(0);
+        if (U.y < ny - 1) vld<T, V>(v + i0 + nx, nv);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) nv[k] = T(0);
+        if (U.z < nz - 1) vld<T, V>(v + i0 + pl, uv);
+        else
+#pragma unroll
+            for (int k = 0; k < V; ++k) uv[k] = T(0);
+        const T w = U.x0 > 0 ? v[i0 - 1] : T(0);
+        const T e = U.x0 + V < nx ? v[i0 + V] : T(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o[0][k] = d[k];
+            o[1][k] = sv[k];
+            o[2][k] = k == 0 ? w : c[k > 0 ? k - 1 : 0];
+            o[3][k] = c[k];
+            o[4][k] = k == V - 1 ? e : c[k < V - 1 ? k + 1 : 0];
+            o[5][k] = nv[k];
+            o[6][k] = uv[k];
+        }
+    }
+    __device__ __forceinline__ int colour(const Unit &U, int k) const { return (U.x0 + k + U.y + U.z) & 1; }
+    __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
+    template <typename T>
+    __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
+        vld<T, V>(p + U.i0, o);
+    }
+    template <typename T>
+    __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
+        vst<T, V>(p + U.i0, o);
+    }
+};
+
+// Restricted matrix B (K rows) in column-major ELL: slot s of row k at
+// [s*K + k]; members in ascending column order, then col = -1 padding.
+template <typename real_, int NB_>
+struct UEll {
+    using real = real_;
+    static constexpr int V = 1, NB = NB_;
+    const int32_t *col;
+    const real *val;
+    const real *dg;       // diagonal of B
+    const uint8_t *clr;   // colour of each row (from the grid)
+    int64_t n;            // K
+    struct Unit {
+        int64_t i0;
+        int32_t c[NB];
+        real a[NB][1];
+    };
+    __host__ __device__ int64_t units() const { return n; }
+    __device__ __forceinline__ void geom(Unit &U, int64_t u) const { U.i0 = u; }
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        U.i0 = u;
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+            U.c[s] = col[s * n + u];
+            U.a[s][0] = val[s * n + u];
+        }
+    }
+    __device__ __forceinline__ bool valid(const Unit &U, int s, int) const { return U.c[s] >= 0; }
+    __device__ __forceinline__ bool is_diag(const Unit &U, int s, int) const { return U.c[s] == U.i0; }
+    template <typename T>
+    __device__ __forceinline__ void gather(const Unit &U, const T *__restrict__ v, T (&o)[NB][1]) const {
+#pragma unroll
+        for (int s = 0; s < NB; ++s) o[s][0] = U.c[s] >= 0 ? v[U.c[s]] : T(0);
+    }
+    __device__ __forceinline__ int colour(const Unit &U, int) const { return clr[U.i0]; }
+    __device__ __forceinline__ void diag(const Unit &U, real (&d)[1]) const { d[0] = dg[U.i0]; }
+    template <typename T>
+    __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[1]) const {
+        o[0] = p[U.i0];
+    }
+    template <typename T>
+    __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[1]) const {
+        p[U.i0] = o[0];
+    }
+};
+
+// ---------------------------------------------------------------------------
 // deterministic reductions
 // ---------------------------------------------------------------------------
 struct OpSum {

@@ -67,27 +67,44 @@ constexpr size_t kSlotElems = (size_t)kMaxGrid * 4;
 template <class Op, int kMode>
 __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict__ b,
                                                   const double *__restrict__ x,
-                                                  double *__restrict__ s, int64_t chunk,
-                                                  double *part) {
-    const Chunk c = my_chunk(A.n, chunk);
+                                                  double *__restrict__ s, double *part) {
+    constexpr int V = Op::V, NB = Op::NB;
     double v[2] = {0.0, 0.0};
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        double acc;
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        A.load(U, B.u);
+        double xv[NB][V], out[V];
+        A.gather(U, x, xv);
         if (kMode == 0) {
-            acc = b[i];
-            A.for_each(i, [&](int64_t j, double a) { acc = fma(-a, x[j], acc); });
-            const double bi = b[i];
-            v[1] += bi * bi;
+            double bb[V];
+            A.own(U, b, bb);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                double acc = bb[k];
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (A.valid(U, q, k)) acc = fma(-U.a[q][k], xv[q][k], acc);
+                out[k] = acc;
+                v[1] += bb[k] * bb[k];
+            }
         } else {
-            const double xi = x[i];
-            acc = 0.0;
-            A.for_each(i, [&](int64_t j, double) {
-                if (j != i) acc += fabs(xi - x[j]);
-            });
+            double xo[V];
+            A.own(U, x, xo);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (A.valid(U, q, k) && !A.is_diag(U, q, k)) acc += fabs(xo[k] - xv[q][k]);
+                out[k] = acc;
+            }
         }
-        s[i] = acc;
-        const double m = fabs(acc);
-        v[0] = m > v[0] ? m : v[0];
+        A.put(U, s, out);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const double m = fabs(out[k]);
+            v[0] = m > v[0] ? m : v[0];
+        }
     }
     write_partials<double, 2>(v, Ops<1u>(), part);
 }
@@ -324,46 +341,69 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict
 // ---------------------------------------------------------------------------
 // restricted system B = A[Omega, Omega] (eq. BEFC)
 // ---------------------------------------------------------------------------
+// Row k of B (global row idx[k]) in column-major ELL of width W: members in
+// ascending column order (columns renumbered through inv, which keeps the
+// order), then col = -1.  Also the diagonal, the colour of the row and
+// rhs_B = r^(0)_Omega (right-hand side of the correction form of eq. loc-equ).
 template <class Op>
-__global__ __launch_bounds__(kBlock) void k_gather_count(Op A, const int32_t *__restrict__ idx,
-                                                         int64_t K,
-                                                         const int32_t *__restrict__ inv,
-                                                         int32_t *__restrict__ rowlen) {
-    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
-         k += (int64_t)gridDim.x * kBlock) {
-        int c = 0;
-        A.for_each(idx[k], [&](int64_t j, double) { c += inv[j] >= 0; });
-        rowlen[k] = c;
-    }
-}
-
-// Fills CSR columns (renumbered through inv, order kept), FP64 and FP32
-// values, the diagonal, the colour of each row and rhs_B = r^(0)_Omega
-// (right-hand side of the correction form of eq. loc-equ).
-template <class Op>
-__global__ __launch_bounds__(kBlock) void k_gather_fill(
-    Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv,
-    const int32_t *__restrict__ rp, int32_t *__restrict__ col, double *__restrict__ val,
-    float *__restrict__ val32, double *__restrict__ dg, float *__restrict__ dg32,
-    uint8_t *__restrict__ clr, const double *__restrict__ r, double *__restrict__ rhs) {
+__global__ __launch_bounds__(kBlock) void k_gather_ell(
+    Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv, int W,
+    int32_t *__restrict__ col, double *__restrict__ val, float *__restrict__ val32,
+    double *__restrict__ dg, float *__restrict__ dg32, uint8_t *__restrict__ clr,
+    const double *__restrict__ r, double *__restrict__ rhs) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
          k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = idx[k];
-        int32_t t = rp[k];
+        int t = 0;
         A.for_each(i, [&](int64_t j, double a) {
             const int32_t cj = inv[j];
             if (cj >= 0) {
-                col[t] = cj;
-                val[t] = a;
-                if (val32) val32[t] = (float)a;
+                col[t * K + k] = cj;
+                val[t * K + k] = a;
+                if (val32) val32[t * K + k] = (float)a;
                 ++t;
             }
         });
+        for (; t < W; ++t) {
+            col[t * K + k] = -1;
+            val[t * K + k] = 0.0;
+            if (val32) val32[t * K + k] = 0.0f;
+        }
         const double d = A.diag(i);
         dg[k] = d;
         if (dg32) dg32[k] = (float)d;
         clr[k] = (uint8_t)A.colour(i);
         if (rhs) rhs[k] = r[i];
+    }
+}
+
+// row lengths of the ELL form (members = col >= 0)
+__global__ __launch_bounds__(kBlock) void k_ell_rowlen(const int32_t *__restrict__ col, int64_t K,
+                                                       int W, int32_t *__restrict__ len) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock) {
+        int c = 0;
+        for (int t = 0; t < W; ++t) c += col[t * K + k] >= 0;
+        len[k] = c;
+    }
+}
+
+// ELL -> CSR (row pointers from the scan)
+__global__ __launch_bounds__(kBlock) void k_ell_to_csr(const int32_t *__restrict__ ecol,
+                                                       const double *__restrict__ eval, int64_t K,
+                                                       int W, const int32_t *__restrict__ rp,
+                                                       int32_t *__restrict__ col,
+                                                       double *__restrict__ val) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock) {
+        int32_t o = rp[k];
+        for (int t = 0; t < W; ++t) {
+            const int32_t c = ecol[t * K + k];
+            if (c < 0) break;
+            col[o] = c;
+            val[o] = eval[t * K + k];
+            ++o;
+        }
     }
 }
 
@@ -400,33 +440,55 @@ __global__ __launch_bounds__(kBlock) void k_scatter_add(const int32_t *__restric
 //
 // init: r = rhs - A x (or r = rhs when x = 0); Jacobi: z = r / a_ii; none:
 // z = r; RB-SGS: z = 0 (filled by the half sweeps).  Partials r.r, r.z.
-template <class Op, typename real, int kPc>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const real *__restrict__ rhs,
-                                                     const real *__restrict__ x,
-                                                     real *__restrict__ r, real *__restrict__ z,
-                                                     int64_t chunk, int x_zero, Scalars *sc,
-                                                     real *part_upd) {
+template <class Op, int kPc>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const typename Op::real *__restrict__ rhs,
+                                                     const typename Op::real *__restrict__ x,
+                                                     typename Op::real *__restrict__ r,
+                                                     typename Op::real *__restrict__ z, int x_zero,
+                                                     Scalars *sc, typename Op::real *part_upd) {
+    using real = typename Op::real;
+    constexpr int V = Op::V, NB = Op::NB;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->pcg.done = 0;
         sc->pcg.status = kStOk;
         sc->pcg.it = 0;
     }
-    const Chunk c = my_chunk(A.n, chunk);
     real v[2] = {real(0), real(0)};
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        real acc = rhs[i];
-        if (!x_zero) A.for_each(i, [&](int64_t j, real a) { acc = fma(-a, x[j], acc); });
-        r[i] = acc;
-        v[0] += acc * acc;
-        if (kPc == 1) {
-            const real zi = acc / A.diag(i);
-            z[i] = zi;
-            v[1] += acc * zi;
-        } else if (kPc == 2) {
-            z[i] = real(0);
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        real rr[V], zz[V];
+        if (x_zero) {
+            A.geom(U, B.u);
+            A.own(U, rhs, rr);
         } else {
-            z[i] = acc;
-            v[1] += acc * acc;
+            A.load(U, B.u);
+            real xv[NB][V], bb[V];
+            A.gather(U, x, xv);
+            A.own(U, rhs, bb);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                real acc = bb[k];
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (A.valid(U, q, k)) acc = fma(-U.a[q][k], xv[q][k], acc);
+                rr[k] = acc;
+            }
+        }
+        if (kPc == 1) {
+            real d[V];
+            A.diag(U, d);
+#pragma unroll
+            for (int k = 0; k < V; ++k) zz[k] = rr[k] / d[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; ++k) zz[k] = kPc == 2 ? real(0) : rr[k];
+        }
+        A.put(U, r, rr);
+        A.put(U, z, zz);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            v[0] += rr[k] * rr[k];
+            v[1] += rr[k] * zz[k];
         }
     }
     write_partials<real, 2>(v, Ops<0u>(), part_upd);
@@ -436,15 +498,19 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const real *__restric
 // previous kernel's partials -> stop (criterion, max_iter, non-finite), else
 // beta_j = r_j.z_j / r_{j-1}.z_{j-1}.  Body: q = A p with p = z (j = 0) or
 // p = z + beta p_old, recomputed for each neighbour so that p is updated in
-// the same pass (p_new written for the own row only).  Partials p.q.
-template <class Op, typename real, int kPc>
-__global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const real *__restrict__ z,
-                                                   const real *__restrict__ pold,
-                                                   real *__restrict__ pnew, real *__restrict__ q,
-                                                   int64_t chunk, int j, int max_iter,
-                                                   const double *tol_base, double tol_factor,
-                                                   Scalars *sc, const real *part_upd,
-                                                   const real *part_sgs, real *part_ap) {
+// the same pass (p_new written for the own cells only).  Partials p.q.
+template <class Op, int kPc>
+__global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real *__restrict__ z,
+                                                   const typename Op::real *__restrict__ pold,
+                                                   typename Op::real *__restrict__ pnew,
+                                                   typename Op::real *__restrict__ q, int j,
+                                                   int max_iter, const double *tol_base,
+                                                   double tol_factor, Scalars *sc,
+                                                   const typename Op::real *part_upd,
+                                                   const typename Op::real *part_sgs,
+                                                   typename Op::real *part_ap) {
+    using real = typename Op::real;
+    constexpr int V = Op::V, NB = Op::NB;
     if (sc->pcg.done) return;
     real t[2];
     read_partials<real, 2>(part_upd, gridDim.x, Ops<0u>(), t);
@@ -459,9 +525,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const real *__restrict_
     if (j == 0) tol = tol_base ? tol_factor * *tol_base : tol_factor * sqrt(rr);
     else tol = sc->pcg.tol;
     int stop = 0, status = kStOk;
-    if (!(rr == rr) || rr > 1.7e308) { stop = 1; status = kStNonFinite; }
-    else if (sqrt(rr) <= tol) stop = 1;
-    else if (j >= max_iter) { stop = 1; status = kStNoConv; }
+    if (!(rr == rr) || rr > 1.7e308) {
+        stop = 1;
+        status = kStNonFinite;
+    } else if (sqrt(rr) <= tol) {
+        stop = 1;
+    } else if (j >= max_iter) {
+        stop = 1;
+        status = kStNoConv;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (j == 0) {
             sc->pcg.tol = tol;
@@ -476,27 +548,40 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const real *__restrict_
         }
     }
     if (stop) return;
-    const Chunk c = my_chunk(A.n, chunk);
+    const real beta = j == 0 ? real(0) : rz / (real)sc->pcg.rz_cur;
     real v[1] = {real(0)};
-    if (j == 0) {
-        for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-            real acc = real(0);
-            A.for_each(i, [&](int64_t jj, real a) { acc = fma(a, z[jj], acc); });
-            const real pi = z[i];
-            pnew[i] = pi;
-            q[i] = acc;
-            v[0] += pi * acc;
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        A.load(U, B.u);
+        real pv[NB][V], po[V], zo[V];
+        A.gather(U, z, pv);
+        A.own(U, z, zo);
+        if (j == 0) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) po[k] = zo[k];
+        } else {
+            real ov[NB][V], oo[V];
+            A.gather(U, pold, ov);
+            A.own(U, pold, oo);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int k = 0; k < V; ++k) pv[q][k] = fma(beta, ov[q][k], pv[q][k]);
+#pragma unroll
+            for (int k = 0; k < V; ++k) po[k] = fma(beta, oo[k], zo[k]);
         }
-    } else {
-        const real beta = rz / (real)sc->pcg.rz_cur;
-        for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        real qq[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
             real acc = real(0);
-            A.for_each(i, [&](int64_t jj, real a) { acc = fma(a, fma(beta, pold[jj], z[jj]), acc); });
-            const real pi = fma(beta, pold[i], z[i]);
-            pnew[i] = pi;
-            q[i] = acc;
-            v[0] += pi * acc;
+#pragma unroll
+            for (int s2 = 0; s2 < NB; ++s2)
+                if (A.valid(U, s2, k)) acc = fma(U.a[s2][k], pv[s2][k], acc);
+            qq[k] = acc;
+            v[0] += po[k] * acc;
         }
+        A.put(U, pnew, po);
+        A.put(U, q, qq);
     }
     write_partials<real, 1>(v, Ops<0u>(), part_ap);
 }
@@ -505,13 +590,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const real *__restrict_
 // breakdown if p.q <= 0, else alpha = r.z / p.q.  Body: x += alpha p;
 // r -= alpha q; Jacobi z = r / a_ii (none: z = r; RB-SGS: z = 0 for the
 // half sweeps).  Partials r.r, r.z.
-template <class Op, typename real, int kPc>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, real *__restrict__ x,
-                                                       const real *__restrict__ p,
-                                                       const real *__restrict__ q,
-                                                       real *__restrict__ r, real *__restrict__ z,
-                                                       int64_t chunk, int j, Scalars *sc,
-                                                       const real *part_ap, real *part_upd) {
+template <class Op, int kPc>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *__restrict__ x,
+                                                       const typename Op::real *__restrict__ p,
+                                                       const typename Op::real *__restrict__ q,
+                                                       typename Op::real *__restrict__ r,
+                                                       typename Op::real *__restrict__ z, int j,
+                                                       Scalars *sc, const typename Op::real *part_ap,
+                                                       typename Op::real *part_upd) {
+    using real = typename Op::real;
+    constexpr int V = Op::V;
     if (sc->pcg.done) return;
     real t[1];
     read_partials<real, 1>(part_ap, gridDim.x, Ops<0u>(), t);
@@ -527,54 +615,69 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, real *__restrict__ 
     }
     const real alpha = (real)rzd / t[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->pcg.rz_cur = rzd;
-    const Chunk c = my_chunk(A.n, chunk);
     real v[2] = {real(0), real(0)};
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        x[i] = fma(alpha, p[i], x[i]);
-        const real ri = fma(-alpha, q[i], r[i]);
-        r[i] = ri;
-        v[0] += ri * ri;
-        if (kPc == 1) {
-            const real zi = ri / A.diag(i);
-            z[i] = zi;
-            v[1] += ri * zi;
-        } else if (kPc == 2) {
-            z[i] = real(0);
-        } else {
-            z[i] = ri;
-            v[1] += ri * ri;
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        A.geom(U, B.u);
+        real xx[V], pp[V], qq[V], rr[V], zz[V];
+        A.own(U, x, xx);
+        A.own(U, p, pp);
+        A.own(U, q, qq);
+        A.own(U, r, rr);
+        real d[V];
+        if (kPc == 1) A.diag(U, d);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            xx[k] = fma(alpha, pp[k], xx[k]);
+            rr[k] = fma(-alpha, qq[k], rr[k]);
+            zz[k] = kPc == 1 ? rr[k] / d[k] : (kPc == 2 ? real(0) : rr[k]);
+            v[0] += rr[k] * rr[k];
+            v[1] += rr[k] * zz[k];
         }
+        A.put(U, x, xx);
+        A.put(U, r, rr);
+        A.put(U, z, zz);
     }
     write_partials<real, 2>(v, Ops<0u>(), part_upd);
 }
 
-// One Gauss-Seidel half sweep over colour c: for rows of that colour,
-// z_i = (r_i - sum_{j != i, ascending} a_ij z_j) / a_ii.  Rows of one colour
-// never couple, so the update is order-free.  With kRz the kernel also
-// writes partials of r.z (all rows).  With a null state this is the smoother
-// of Algorithm 1 (r = b, z = x).
-template <class Op, typename real, bool kRz>
-__global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const real *__restrict__ r,
-                                                    real *z, int colour, int64_t chunk,
-                                                    const Scalars *sc, real *part_sgs) {
+// One Gauss-Seidel half sweep over colour c: for cells of that colour,
+// z_i = (r_i - sum_{j != i, ascending} a_ij z_j) / a_ii.  Cells of one
+// colour never couple, so the update is order-free.  With kRz the kernel
+// also writes partials of r.z (all cells).  With a null state this is the
+// smoother of Algorithm 1 (r = b, z = x).
+template <class Op, bool kRz>
+__global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const typename Op::real *__restrict__ r,
+                                                    typename Op::real *z, int colour,
+                                                    const Scalars *sc, typename Op::real *part_sgs) {
+    using real = typename Op::real;
+    constexpr int V = Op::V, NB = Op::NB;
     if (sc && sc->pcg.done) return;
-    const Chunk c = my_chunk(A.n, chunk);
     real v[1] = {real(0)};
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        const real ri = r[i];
-        real zi;
-        if (A.colour(i) == colour) {
-            real acc = ri, d = real(1);
-            A.for_each(i, [&](int64_t jj, real a) {
-                if (jj == i) d = a;
-                else acc = fma(-a, z[jj], acc);
-            });
-            zi = acc / d;
-            z[i] = zi;
-        } else {
-            zi = z[i];
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        A.load(U, B.u);
+        real zv[NB][V], ro[V], zo[V];
+        A.gather(U, (const real *)z, zv);
+        A.own(U, r, ro);
+        A.own(U, (const real *)z, zo);
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (A.colour(U, k) == colour) {
+                real acc = ro[k], d = real(1);
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    if (!A.valid(U, q, k)) continue;
+                    if (A.is_diag(U, q, k)) d = U.a[q][k];
+                    else acc = fma(-U.a[q][k], zv[q][k], acc);
+                }
+                zo[k] = acc / d;
+                any = true;
+            }
+            if (kRz) v[0] += ro[k] * zo[k];
         }
-        if (kRz) v[0] += ri * zi;
+        if (any) A.put(U, z, zo);
     }
     if (kRz) write_partials<real, 1>(v, Ops<0u>(), part_sgs);
 }
@@ -583,17 +686,27 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const real *__restrict
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_resnorm(Op A, const double *__restrict__ rhs,
                                                     const double *__restrict__ x,
-                                                    double *__restrict__ r, int64_t chunk,
-                                                    double *part) {
-    const Chunk c = my_chunk(A.n, chunk);
+                                                    double *__restrict__ r, double *part) {
+    constexpr int V = Op::V, NB = Op::NB;
     double v[2] = {0.0, 0.0};
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        double acc = rhs[i];
-        A.for_each(i, [&](int64_t j, double a) { acc = fma(-a, x[j], acc); });
-        if (r) r[i] = acc;
-        v[0] += acc * acc;
-        const double m = fabs(acc);
-        v[1] = m > v[1] ? m : v[1];
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        A.load(U, B.u);
+        double xv[NB][V], bb[V], out[V];
+        A.gather(U, x, xv);
+        A.own(U, rhs, bb);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            double acc = bb[k];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (A.valid(U, q, k)) acc = fma(-U.a[q][k], xv[q][k], acc);
+            out[k] = acc;
+            v[0] += acc * acc;
+            const double m = fabs(acc);
+            v[1] = m > v[1] ? m : v[1];
+        }
+        if (r) A.put(U, r, out);
     }
     write_partials<double, 2>(v, Ops<2u>(), part);
 }
@@ -669,14 +782,25 @@ __global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ a, T v, int64_t
 }
 
 // y = A x (measurement of the stencil SpMV on its own)
-template <class Op, typename real>
-__global__ __launch_bounds__(kBlock) void k_spmv(Op A, const real *__restrict__ x,
-                                                 real *__restrict__ y, int64_t chunk) {
-    const Chunk c = my_chunk(A.n, chunk);
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        real acc = real(0);
-        A.for_each(i, [&](int64_t j, real a) { acc = fma(a, x[j], acc); });
-        y[i] = acc;
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_spmv(Op A, const typename Op::real *__restrict__ x,
+                                                 typename Op::real *__restrict__ y) {
+    using real = typename Op::real;
+    constexpr int V = Op::V, NB = Op::NB;
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        A.load(U, B.u);
+        real xv[NB][V], out[V];
+        A.gather(U, x, xv);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            real acc = real(0);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (A.valid(U, q, k)) acc = fma(U.a[q][k], xv[q][k], acc);
+            out[k] = acc;
+        }
+        A.put(U, y, out);
     }
 }
 

@@ -38,11 +38,16 @@ def host(t):
 
 
 # ragged grids: sizes that are not multiples of the 256-row blocks or the
-# 2048-stamp compaction tiles, spanning several of each
+# 2048-stamp compaction tiles, spanning several of each.  nx odd runs the
+# scalar (one cell per thread) kernels; nx a multiple of 4 runs the vector
+# strips (2 FP64 / 4 FP32 cells per thread) with ragged ny, nz.
 CASES = {
     "5pt": (W.KIND_5PT, (93, 71, 1)),
     "9pt": (W.KIND_9PT, (83, 67, 1)),
     "7pt": (W.KIND_7PT, (23, 19, 17)),
+    "5pt_v": (W.KIND_5PT, (96, 71, 1)),
+    "9pt_v": (W.KIND_9PT, (84, 67, 1)),
+    "7pt_v": (W.KIND_7PT, (24, 19, 17)),
 }
 
 
@@ -111,6 +116,27 @@ def test_spmv_fp64(name, ctx):
     assert np.array_equal(host(y), oracle.spmv(Ah, x0))
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_fp32(name, ctx):
+    """FP32 SpMV (the inner operator of the mixed path): within the FP32
+    rounding bound of a 9-term fused sum, nb * u32 * sum_j |a_ij x_j|, of the
+    FP64 product of the same FP32-rounded inputs."""
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("spmv fp32", name, dims)
+    A.coef32 = lcs.cast_coef(A, ctx=ctx)
+    x32 = dev(x0, torch.float32)
+    y = torch.empty(A.n, dtype=torch.float32, device=DEV)
+    lcs.spmv(A, x32, y, ctx=ctx)
+    c32 = host(A.coef32).astype(np.float64)
+    np.testing.assert_array_equal(c32, coef.astype(np.float32).astype(np.float64))
+    A32h = oracle.csr_from_stencil(kind, *dims, c32)
+    xr = host(x32).astype(np.float64)
+    ref = oracle.spmv(A32h, xr)
+    absA = oracle.CSR(A32h.n, A32h.rp, A32h.col, np.abs(A32h.val))
+    bound = 9 * 2.0 ** -24 * oracle.spmv(absA, np.abs(xr)) + 1e-30
+    assert np.all(np.abs(host(y).astype(np.float64) - ref) <= bound)
+
+
 # ----------------------------------------------------------------------------
 # local domain (Algorithms 2 and 3): bit-exact sets and stamps
 # ----------------------------------------------------------------------------
@@ -136,7 +162,7 @@ def test_local_domain_bitexact(name, mode, thresh, theta, e_max, ctx):
     assert np.array_equal(host(mask), d.mask)
 
 
-@pytest.mark.parametrize("name", ["5pt", "7pt"])
+@pytest.mark.parametrize("name", ["5pt", "7pt", "5pt_v"])
 def test_local_domain_paper_threshold(name, ctx):
     """tau = eps ||b|| / sqrt(N): ||b||^2 is summed in a different order on
     the two sides; a sum of N positive terms in any order is within (N-1)u
@@ -200,7 +226,8 @@ def test_gather_rejects_bad_domain(ctx):
 # PCG: trajectory parity at equal iteration counts, converged parity
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("name,pc", [("5pt", "jacobi"), ("9pt", "jacobi"), ("7pt", "jacobi"),
-                                     ("5pt", "rbsgs"), ("7pt", "rbsgs"), ("5pt", "none")])
+                                     ("5pt", "rbsgs"), ("7pt", "rbsgs"), ("5pt", "none"),
+                                     ("5pt_v", "jacobi"), ("9pt_v", "jacobi"), ("7pt_v", "rbsgs")])
 def test_global_pcg_parity(name, pc, ctx):
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
     say("global pcg", name, dims, pc)
@@ -278,7 +305,8 @@ def test_solve_local_trajectory_parity(name, ctx):
 # ----------------------------------------------------------------------------
 # mixed precision: FP32 inner sweeps + FP64 refinement
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("name,pc", [("5pt", "jacobi"), ("9pt", "jacobi"), ("7pt", "rbsgs")])
+@pytest.mark.parametrize("name,pc", [("5pt", "jacobi"), ("9pt", "jacobi"), ("7pt", "rbsgs"),
+                                     ("5pt_v", "jacobi"), ("9pt_v", "jacobi"), ("7pt_v", "rbsgs")])
 def test_mixed_precision_refinement(name, pc, ctx):
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
     say("mixed", name, dims, pc)
