@@ -1,14 +1,18 @@
 """Benchmark: ms per linear system to relative residual 1e-10, local vs global PCG,
 plus SpMV HBM GB/s, on one MI355X.
 
-Workload (default): the 2-D 1024x1024 five-point FP64 sequence of 20 backward-
-Euler systems with log-normal conductivity (sigma = 1) and a radius-40 disk
-source moving 4 cells per system.  Setup (untimed) evolves the sequence on the
-GPU, so every system's x^(0) = x_{k-1} and b_k are resident in HBM before the
-timed region.  One step = one system solved by Algorithm 1 (local domain by
-residual, Algorithm 3, E_max = 1), cycling through the 20 systems.  The global
-Jacobi-PCG from the same x^(0) is timed the same way as the baseline, and the
-gradient-based local domain (Algorithm 2) as a second variant.
+Default workload (c2): the 2-D 1024x1024 five-point FP64 sequence of 20
+backward-Euler systems with log-normal conductivity (sigma = 1) and a
+radius-40 disk source moving 4 cells per system.  Setup (untimed) evolves the
+sequence on the GPU, so every system's x^(0) = x_{k-1} and b_k are resident
+in HBM before the timed region.  One step = one system solved by Algorithm 1
+(local domain by residual, Algorithm 3, paper threshold eps ||b|| / sqrt(N),
+E_max = 1), cycling through the systems.  The global Jacobi-PCG from the same
+x^(0) is timed the same way as the baseline, the gradient-based domain
+(Algorithm 2) and the max-norm-relative residual threshold as variants.
+
+--workload c3 / c5 run the 4096^2 nine-point (FP32 inner + FP64 refinement)
+and 256^3 seven-point (mixed, red-black SGS) sequences the same way.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
 """
@@ -32,11 +36,13 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=40)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--workload", choices=["c2", "c3", "c5"], default="c2")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
-    p.add_argument("--nx", type=int, default=1024)
     p.add_argument("--skip-spmv-hbm", action="store_true")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="also run a plain 512 MiB device copy (traffic-counter calibration)")
     return p.parse_args()
 
 
@@ -44,33 +50,59 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def make_workload(name):
+    from paper_2001_01158_amd import workloads as W
+    if name == "c2":
+        w = W.c2_moving_disk()
+        opts = dict(precond="jacobi", precision="fp64")
+        desc = ("2D 1024x1024 5-point FP64, 20-system backward-Euler sequence, sigma=1 log-normal "
+                "conductivity, disk radius 40 moving 4 cells/system; Algorithm 1, residual local "
+                "domain (paper threshold eps||b||/sqrt(N), E_max=1), Jacobi-PCG, eps=1e-10")
+        src = lambda k: W.disk_source(w.nx, w.ny, w.nx / 4.0 + 4.0 * k, w.ny / 2.0, 40.0, 1.0)
+    elif name == "c3":
+        w = W.c3_aniso_front(n_systems=12)
+        opts = dict(precond="jacobi", precision="mixed")
+        desc = ("2D 4096x4096 9-point anisotropic (ratio 100, 30 deg), moving disk radius 350, "
+                "FP32 inner Jacobi-PCG + FP64 refinement to 1e-10; Algorithm 1, paper threshold")
+        src = lambda k: W.disk_source(w.nx, w.ny, w.nx / 4.0 + 8.0 * k, w.ny / 2.0, 350.0, 1.0)
+    else:
+        w = W.c5_sphere3d(n_systems=12)
+        opts = dict(precond="rbsgs", precision="mixed")
+        desc = ("3D 256^3 7-point, sigma=1.5 log-normal conductivity, ball radius 20 moving 2 "
+                "cells/system, FP32 inner RB-SGS PCG + FP64 refinement to 1e-10; Algorithm 1, "
+                "paper threshold")
+        src = lambda k: W.ball_source(w.nx, w.ny, w.nz, w.nx / 4.0 + 2.0 * k, w.ny / 2.0,
+                                      w.nz / 2.0, 20.0, 1.0)
+    return w, opts, desc, src
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
-                                   "description only (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU; sharding across GPUs is a design "
+                                   "description only (DESIGN.md section 9)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2001_01158_amd import lcs, workloads as W
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    nx = args.nx
-    w = W.c2_moving_disk(nx=nx, ny=nx)
+    w, okw, desc, src = make_workload(args.workload)
     n = w.n
     log(f"workload {w.name} N={n} systems={w.n_systems}")
-    A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev)
+    A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
+                              with32=okw["precision"] == "mixed")
     ctx = lcs.Context()
     stream = torch.cuda.current_stream()
     inv_dt = 1.0 / w.dt
     eps = 1e-10
-    opts = lcs.Options(eps=eps, precond="jacobi", n_smooth=1, check_every=8)
+    opts = lcs.Options(eps=eps, n_smooth=1, check_every=8, **okw)
 
     # ---- setup: evolve the sequence (untimed) ----
     X = [torch.zeros(n, dtype=torch.float64, device=dev)]          # X[k] = x_{k-1}
     Bs = []
     for k in range(w.n_systems):
-        q = torch.as_tensor(W.disk_source(nx, nx, nx / 4.0 + 4.0 * k, nx / 2.0, 40.0, 1.0)).to(dev)
+        q = torch.as_tensor(src(k)).to(dev)
         b = X[-1] * inv_dt + q
         x = X[-1].clone()
         lcs.solve_global(A, b, x, opts, ctx=ctx)
@@ -79,23 +111,6 @@ def main():
     torch.cuda.synchronize()
     log("sequence ready")
     x = torch.empty(n, dtype=torch.float64, device=dev)
-
-    def run_leg(kind: str, steps: int, warm: int, collect: bool):
-        stats = []
-        for s in range(warm):
-            k = s % w.n_systems
-            x.copy_(X[k])
-            one(kind, k)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(steps):
-            k = s % w.n_systems
-            x.copy_(X[k])
-            st = one(kind, k)
-            if collect:
-                stats.append(st)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / steps, stats
 
     def one(kind, k):
         b = Bs[k]
@@ -107,14 +122,29 @@ def main():
             return lcs.solve_local_then_global(A, b, x, "residual", "relmax", 1e-3, 1, opts, ctx=ctx)
         return lcs.solve_local_then_global(A, b, x, "gradient", "relmax", 1e-4, 1, opts, ctx=ctx)
 
+    def run_leg(kind: str, steps: int, warm: int):
+        stats = []
+        for s in range(warm):
+            k = s % w.n_systems
+            x.copy_(X[k])
+            one(kind, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            k = s % w.n_systems
+            x.copy_(X[k])
+            stats.append(one(kind, k))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, stats
+
     # ---- timed legs ----
-    ms_local, st_local = run_leg("residual", args.steps, args.warmup, True)
+    ms_local, st_local = run_leg("residual", args.steps, args.warmup)
     log(f"local (residual, paper threshold): {ms_local:.3f} ms/system")
-    ms_global, st_global = run_leg("global", args.steps, max(2, args.warmup // 2), True)
+    ms_global, st_global = run_leg("global", args.steps, max(2, args.warmup // 2))
     log(f"global PCG: {ms_global:.3f} ms/system")
-    ms_grad, st_grad = run_leg("gradient", args.steps, max(2, args.warmup // 2), True)
+    ms_grad, st_grad = run_leg("gradient", args.steps, max(2, args.warmup // 2))
     log(f"local (gradient): {ms_grad:.3f} ms/system")
-    ms_relmax, st_relmax = run_leg("residual_relmax", args.steps, max(2, args.warmup // 2), True)
+    ms_relmax, st_relmax = run_leg("residual_relmax", args.steps, max(2, args.warmup // 2))
     log(f"local (residual, relmax 1e-3): {ms_relmax:.3f} ms/system")
 
     def summary(sts):
@@ -123,7 +153,35 @@ def main():
                 "its_local_mean": float(np.mean([s.its_local for s in sts])),
                 "its_global_mean": float(np.mean([s.its_global for s in sts])),
                 "relres_final_max": float(np.max([s.relres_final for s in sts])),
-                "global_finish_fraction": float(np.mean([s.its_global > 0 for s in sts]))}
+                "global_finish_fraction": float(np.mean([s.its_global > 0 for s in sts])),
+                "ms_construct_mean": float(np.mean([s.ms_construct for s in sts])),
+                "ms_local_mean": float(np.mean([s.ms_local for s in sts])),
+                "ms_smooth_mean": float(np.mean([s.ms_smooth for s in sts])),
+                "ms_global_mean": float(np.mean([s.ms_global for s in sts]))}
+
+    # ---- dominant kernel of the timed step, timed with HIP events ----
+    # The headline step is dominated by the local PCG; its A p kernel on the
+    # restricted ELL matrix is the larger of its two kernels.  Re-run the same
+    # timed steps with that kernel bracketed by events on the solve's stream.
+    W_ell = {W.KIND_5PT: 5, W.KIND_9PT: 9, W.KIND_7PT: 7}[w.kind]
+    real_b = 8 if okw["precision"] == "fp64" else 4
+    bytes_per_row = W_ell * (4 + real_b) + 4 * real_b    # ELL col+val, z and p_old in, p and q out
+    lcs.set_kernel_timing(lcs.TIME_LOCAL_AP, ctx=ctx)
+    _, st_t = run_leg("residual", args.steps, 0)
+    k_ms, k_launches = lcs.get_kernel_timing(ctx=ctx)
+    lcs.set_kernel_timing(lcs.TIME_NONE, ctx=ctx)
+    work_rows = float(sum(s.K * s.its_local for s in st_t))     # rows processed by working launches
+    avg_us = k_ms * 1e3 / max(k_launches, 1)
+    achieved = work_rows * bytes_per_row / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "kernel": f"k_pcg_ap<UEll<{'double' if real_b == 8 else 'float'},{W_ell}>,"
+                      f"{1 if okw['precond'] == 'jacobi' else 2}> (local PCG q = B p)",
+            "avg_launch_us": avg_us, "launches": k_launches,
+            "bytes_per_launch": work_rows * bytes_per_row / max(k_launches, 1),
+            "bytes_per_local_row": bytes_per_row,
+            "note": "latency-bound: K ~ 1e4-1e5 rows per launch; see DESIGN.md section 6"}
+    log(f"dominant kernel: {k_launches} launches, avg {avg_us:.2f} us, {achieved or 0:.0f} GB/s")
 
     # ---- SpMV GB/s ----
     def time_spmv(M, xx, yy, reps=50):
@@ -138,9 +196,9 @@ def main():
     xs = torch.rand(n, dtype=torch.float64, device=dev)
     ys = torch.empty_like(xs)
     spmv_ms = time_spmv(A, xs, ys)
-    spmv_bytes = n * (3 * 8 + 8 + 8)      # C, E, N + x + y
-    spmv = {"c2_5pt_fp64": {"n": n, "ms": spmv_ms, "GBs": spmv_bytes / spmv_ms / 1e6,
-                            "bytes_per_row": 40, "note": "working set 40 MB: Infinity-Cache resident"}}
+    nb_row = {W.KIND_5PT: 40, W.KIND_9PT: 56, W.KIND_7PT: 48}[w.kind]
+    spmv = {f"{args.workload}_fp64": {"n": n, "us": spmv_ms * 1e3, "GBs": n * nb_row / spmv_ms / 1e6,
+                                      "bytes_per_row": nb_row}}
     hbm = None
     if not args.skip_spmv_hbm:
         n3 = 4096
@@ -151,19 +209,24 @@ def main():
         y9 = torch.empty_like(x9)
         ms9 = time_spmv(A9, x9, y9)
         b9 = n3 * n3 * (5 * 4 + 4 + 4)
-        hbm = {"n": n3 * n3, "ms": ms9, "GBs": b9 / ms9 / 1e6, "bytes_per_row": 28,
-               "frac_of_8TBs": b9 / ms9 / 1e6 / HBM_PEAK_GBS}
-        spmv["c3_9pt_fp32_4096x4096"] = hbm
+        hbm = {"n": n3 * n3, "us": ms9 * 1e3, "GBs": b9 / ms9 / 1e6, "bytes_per_row": 28,
+               "frac_of_8TBs": b9 / ms9 / 1e6 / HBM_PEAK_GBS,
+               "kernel": "k_spmv<U9<float,4>>"}
+        spmv["c3_9pt_fp32_4096x4096_hbm"] = hbm
         log(f"SpMV 9pt FP32 4096^2: {ms9 * 1e3:.1f} us, {hbm['GBs']:.0f} GB/s")
         del A9, x9, y9
 
-    roof = {"bound": "hbm", "kernel": "k_spmv<Stencil9<float>> (9-point FP32 SpMV, 4096x4096)",
-            "achieved": hbm["GBs"] if hbm else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (hbm["GBs"] / HBM_PEAK_GBS) if hbm else None, "traffic": None}
+    if args.calib_copy:
+        src_t = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev)   # 512 MiB
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
 
     # ---- CPU baseline: the oracle on the same systems ----
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "c2":
         import oracle
         Ah = oracle.csr_from_stencil(w.kind, w.nx, w.ny, w.nz, w.coef)
         t_used, done, t_glob, n_glob = 0.0, 0, 0.0, 0
@@ -202,13 +265,9 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded log-normal conductivity, moving disk source)",
-        "config": {"workload": f"2D {nx}x{nx} 5-point FP64, 20-system backward-Euler sequence, "
-                               "sigma=1 log-normal conductivity, disk radius 40 moving 4 cells/system; "
-                               "Algorithm 1, residual local domain (paper threshold eps||b||/sqrt(N), "
-                               "E_max=1), Jacobi-PCG, eps=1e-10", "N": n, "systems": w.n_systems,
-                   "dt": w.dt},
+        "dtype": "f64" if okw["precision"] == "fp64" else "f32 inner / f64 refinement",
+        "data": "synthetic (seeded log-normal conductivity, moving source)",
+        "config": {"workload": desc, "N": n, "systems": w.n_systems, "dt": w.dt},
         "global_pcg_ms_per_system": ms_global,
         "speedup_vs_global": ms_global / ms_local,
         "local_gradient_ms_per_system": ms_grad,

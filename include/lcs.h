@@ -165,6 +165,23 @@ lcs_status lcs_gs_sweeps(lcs_ctx *ctx, const lcs_matrix *A, const double *b, dou
 /* coef32 = (float) coef, n_arrays x N (device). */
 lcs_status lcs_cast_coef(lcs_ctx *ctx, const lcs_matrix *A, float *coef32, void *stream);
 
+/* ---- kernel timing for measurement ---- */
+/* When on, every launch of the chosen kernel class goes through
+ * hipExtLaunchKernelGGL with a start / stop event pair recorded by the
+ * dispatch itself on the call's stream, so each interval is the kernel's
+ * execution; the elapsed times are folded after each solve's final
+ * synchronisation.  Setting a class (or LCS_TIME_NONE) resets the totals. */
+enum {
+    LCS_TIME_NONE = 0,
+    LCS_TIME_LOCAL_AP = 1,        /* q = B p kernel of the local PCG            */
+    LCS_TIME_LOCAL_UPDATE = 2,    /* x, r, z update kernel of the local PCG     */
+    LCS_TIME_GLOBAL_AP = 3,       /* q = A p kernel of the global PCG           */
+    LCS_TIME_GLOBAL_UPDATE = 4    /* x, r, z update kernel of the global PCG    */
+};
+lcs_status lcs_set_kernel_timing(lcs_ctx *ctx, int32_t what);
+/* total milliseconds and number of timed launches since the last set */
+lcs_status lcs_get_kernel_timing(lcs_ctx *ctx, double *ms_total, int64_t *launches);
+
 /* ---- adjoint helpers (5- and 7-point log-conductivity operators) ---- */
 /* coef = stencil of A = I*inv_dt + sum_f T_f (e_P-e_Q)(e_P-e_Q)^T with
  * T_f = 2 k_P k_Q / (k_P + k_Q), k = exp(logk); zero-flux outer faces. */

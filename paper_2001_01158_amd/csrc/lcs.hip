@@ -3,6 +3,7 @@
 // Every step of the method runs in the kernels of lcs_kernels.h; the host
 // only sizes launches, orders them on the caller's stream and reads a few
 // scalars (K, convergence flags) back through pinned memory.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "lcs.h"
 #include "lcs_kernels.h"
@@ -119,6 +121,13 @@ struct lcs_ctx {
     size_t cap[B_NUM] = {};
     hipEvent_t ev[5] = {};
     hipEvent_t chk[2] = {};
+    int last_its[2] = {0, 0};       // iterations of the previous global / local PCG
+    // optional kernel timing (HIP events around one kernel class)
+    int prof_what = 0;              // LCS_TIME_* or 0
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
 };
 
 namespace {
@@ -314,11 +323,47 @@ lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<typename Op::re
 // iterations at a time and polls the flag of the previous chunk while the
 // next one runs, so the GPU never waits for the host; launches after
 // convergence exit at their first instruction.
+// Launch one kernel; when kernel timing is on for its class, through
+// hipExtLaunchKernelGGL with a start / stop event pair that the dispatch
+// itself records (so the interval is the kernel's execution, not the host's
+// launch latency).
+template <class K, class... Args>
+lcs_status launch_maybe_timed(lcs_ctx *c, bool timed, K kernel, int grid, hipStream_t s,
+                              Args... args) {
+    if (!timed) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, args...);
+        LAUNCH_CHECK();
+        return LCS_OK;
+    }
+    while (c->prof_ev.size() < c->prof_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        c->prof_ev.push_back(e);
+    }
+    hipEvent_t e0 = c->prof_ev[c->prof_used++];
+    hipEvent_t e1 = c->prof_ev[c->prof_used++];
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, args...);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+// After the stream is idle: fold the recorded event pairs into the totals.
+lcs_status flush_prof(lcs_ctx *c) {
+    for (size_t k = 0; k + 1 < c->prof_used; k += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->prof_ev[k], c->prof_ev[k + 1]));
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+    }
+    c->prof_used = 0;
+    return LCS_OK;
+}
+
 template <class Op, int kPc>
 lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real *rhs,
                      typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
                      int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
-                     hipStream_t s, PcgResult *res) {
+                     hipStream_t s, PcgResult *res, int scope, bool sync_end) {
     using real = typename Op::real;
     const int64_t n = A.units() * Op::V;
     const int grid = band_grid(A.units(), kRedGrid);
@@ -335,24 +380,27 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
     LCS_TRY((launch_precond<Op, kPc>(c, A, B, grid, ncol, s)));
     if (check_every < 1) check_every = 1;
     int flip = 0, next_j = 0;
+    const bool time_ap = c->prof_what == (scope == 1 ? LCS_TIME_LOCAL_AP : LCS_TIME_GLOBAL_AP);
+    const bool time_up = c->prof_what == (scope == 1 ? LCS_TIME_LOCAL_UPDATE : LCS_TIME_GLOBAL_UPDATE);
     auto launch_ap = [&](int j) -> lcs_status {
         real *pold = flip ? B.p1 : B.p0;
         real *pnew = flip ? B.p0 : B.p1;
-        hipLaunchKernelGGL((k_pcg_ap<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A,
-                           (const real *)B.z, (const real *)pold, pnew, B.q, j, max_iter, tol_base,
-                           tol_factor, c->dsc, (const real *)pupd, (const real *)psgs, pap);
-        LAUNCH_CHECK();
-        return LCS_OK;
+        return launch_maybe_timed(c, time_ap, k_pcg_ap<Op, kPc>, grid, s, A, (const real *)B.z,
+                                  (const real *)pold, pnew, B.q, j, max_iter, tol_base, tol_factor,
+                                  c->dsc, (const real *)pupd, (const real *)psgs, pap);
     };
+    // the first chunk is sized from the previous solve of this kind (a
+    // sequence of systems converges in similar iteration counts)
+    int first_chunk = std::max(check_every, c->last_its[scope] - check_every / 2);
     auto enqueue_chunk = [&](int slot_id) -> lcs_status {
-        for (int k = 0; k < check_every && next_j < max_iter; ++k) {
+        const int len = next_j == 0 ? first_chunk : check_every;
+        for (int k = 0; k < len && next_j < max_iter; ++k) {
             const int j = next_j++;
             LCS_TRY(launch_ap(j));
             real *pnew = flip ? B.p0 : B.p1;
-            hipLaunchKernelGGL((k_pcg_update<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A, x,
-                               (const real *)pnew, (const real *)B.q, B.r, B.z, j, c->dsc,
-                               (const real *)pap, pupd);
-            LAUNCH_CHECK();
+            LCS_TRY(launch_maybe_timed(c, time_up, k_pcg_update<Op, kPc>, grid, s, A, x,
+                                       (const real *)pnew, (const real *)B.q, B.r, B.z, j, c->dsc,
+                                       (const real *)pap, pupd));
             LCS_TRY((launch_precond<Op, kPc>(c, A, B, grid, ncol, s)));
             flip ^= 1;
         }
@@ -371,13 +419,17 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
         if (c->hdone[sl] || !more) break;
         sl ^= 1;
     }
-    LCS_TRY(read_scalars(c, s));
-    res->its = c->hsc->pcg.it;
-    res->status = c->hsc->pcg.status;
-    if (!c->hsc->pcg.done) {  // cannot happen: the final test always runs
-        res->its = max_iter;
-        res->status = kStNoConv;
+    hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
+    LAUNCH_CHECK();
+    if (!sync_end) {   // the caller reads saved_it / saved_status later
+        res->its = -1;
+        res->status = kStOk;
+        return LCS_OK;
     }
+    LCS_TRY(read_scalars(c, s));
+    res->its = c->hsc->saved_it[scope];
+    res->status = c->hsc->saved_status[scope];
+    c->last_its[scope] = res->its;
     return LCS_OK;
 }
 
@@ -385,17 +437,17 @@ template <class Op>
 lcs_status run_pcg(lcs_ctx *c, const Op &A, int ncol, int pc, const typename Op::real *rhs,
                    typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
                    int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
-                   hipStream_t s, PcgResult *res) {
+                   hipStream_t s, PcgResult *res, int scope, bool sync_end) {
     switch (pc) {
     case LCS_PC_NONE:
         return run_pcg_t<Op, 0>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                check_every, B, s, res);
+                                check_every, B, s, res, scope, sync_end);
     case LCS_PC_JACOBI:
         return run_pcg_t<Op, 1>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                check_every, B, s, res);
+                                check_every, B, s, res, scope, sync_end);
     default:
         return run_pcg_t<Op, 2>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                check_every, B, s, res);
+                                check_every, B, s, res, scope, sync_end);
     }
 }
 
@@ -430,10 +482,14 @@ struct SolveOut {
 // FP64: PCG, then a true-residual check with up to max_outer restarts.
 // Mixed: FP64 residual -> scaled FP32 PCG correction to inner_tol -> FP64
 // update, repeated until the FP64 criterion holds.
+// scope 0 (global): after PCG the true residual is checked, with restarts.
+// scope 1 (local, FP64): one PCG run with no host round trip; its outcome is
+// left in saved_it[1] / saved_status[1] for the caller's next read (the
+// criterion that matters is the global one checked right after).
 template <class Op64, class Op32>
 lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, const double *rhs,
                         double *x, bool x_zero, const double *tol_base, double tol_factor,
-                        const lcs_options *o, hipStream_t s, SolveOut *out) {
+                        const lcs_options *o, hipStream_t s, SolveOut *out, int scope) {
     const int64_t n = A.units() * Op64::V;
     *out = SolveOut();
     if (n == 0) return LCS_OK;
@@ -445,11 +501,18 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
         LCS_TRY(get_buf(c, B_P0, n, &B.p0));
         LCS_TRY(get_buf(c, B_P1, n, &B.p1));
         LCS_TRY(get_buf(c, B_Q, n, &B.q));
+        if (scope == 1) {
+            PcgResult pr;
+            LCS_TRY(run_pcg(c, A, ncol, o->precond, rhs, x, x_zero, tol_base, tol_factor,
+                            o->max_iter, check, B, s, &pr, scope, false));
+            out->its = -1;
+            return LCS_OK;
+        }
         bool zero = x_zero;
         for (int attempt = 0;; ++attempt) {
             PcgResult pr;
             LCS_TRY(run_pcg(c, A, ncol, o->precond, rhs, x, zero, tol_base, tol_factor,
-                            o->max_iter - out->its, check, B, s, &pr));
+                            o->max_iter - out->its, check, B, s, &pr, scope, true));
             zero = false;
             out->its += pr.its;
             LCS_TRY(launch_resnorm(c, A, rhs, x, (double *)nullptr, tol_base, tol_factor, s));
@@ -491,7 +554,8 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
         LAUNCH_CHECK();
         PcgResult pr;
         LCS_TRY(run_pcg(c, A32, ncol, o->precond, (const float *)r32, d32, true,
-                        (const double *)nullptr, inner, o->max_iter - out->its, check, B, s, &pr));
+                        (const double *)nullptr, inner, o->max_iter - out->its, check, B, s, &pr,
+                        scope, true));
         out->its += pr.its;
         if (pr.status == kStBreakdown || pr.status == kStNonFinite) return status_of(pr.status);
         hipLaunchKernelGGL(k_axpy_scaled, dim3(flat_grid(n)), dim3(kBlock), 0, s, x,
@@ -626,11 +690,11 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         const double tl = o->tol_local > 0 ? o->tol_local : o->eps;
         SolveOut so;
         const lcs_status ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
-                                           &c->dsc->bnorm, tl, o, s, &so);
+                                           &c->dsc->bnorm, tl, o, s, &so, 1);
         // a local solve that stops at its iteration cap still improves x;
         // the global finish takes over from there
         if (ls != LCS_OK && ls != LCS_ENOCONV) return ls;
-        st->its_local = so.its;
+        st->its_local = so.its;   // -1: read from the device state after the next sync
         st->n_outer += so.n_outer;
         hipLaunchKernelGGL(k_scatter_add, dim3(flat_grid(K)), dim3(kBlock), 0, s, idx,
                            (const double *)d, K, x);
@@ -660,6 +724,16 @@ lcs_status set_inv(lcs_ctx *c, const int32_t *idx, int64_t K, int64_t n, int32_t
     LAUNCH_CHECK();
     LCS_TRY(read_scalars(c, s));
     if (c->hsc->bad_idx) return fail(LCS_EINVAL, "idx must be strictly ascending indices in [0, N)");
+    return LCS_OK;
+}
+
+// After a sync: the local PCG outcome left on the device (FP64 path).
+lcs_status finish_local(lcs_ctx *c, lcs_stats *st) {
+    if (st->its_local >= 0) return LCS_OK;
+    st->its_local = c->hsc->saved_it[1];
+    c->last_its[1] = st->its_local;
+    const int ls = c->hsc->saved_status[1];
+    if (ls == kStBreakdown || ls == kStNonFinite) return status_of(ls);
     return LCS_OK;
 }
 
@@ -747,6 +821,7 @@ void lcs_destroy(lcs_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chk)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->prof_ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -938,9 +1013,10 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
         LCS_TRY(tm.mark(3));
         SolveOut so;
         const lcs_status rs = solve_system(c, op, op32, n_colours(A->kind), b, x, false,
-                                           &c->dsc->bnorm, o->eps, o, s, &so);
+                                           &c->dsc->bnorm, o->eps, o, s, &so, 0);
         LCS_TRY(tm.mark(4));
         HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(flush_prof(c));
         const double bn = c->hsc->bnorm;
         st->its_global = so.its;
         st->n_outer = so.n_outer;
@@ -981,6 +1057,8 @@ lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, dou
         LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
                                o->eps, s));
         LCS_TRY(read_scalars(c, s));
+        LCS_TRY(flush_prof(c));
+        LCS_TRY(finish_local(c, st));
         const double bn = c->hsc->bnorm;
         st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->res.rr) / bn : std::sqrt(c->hsc->res.rr);
         st->relres_final = st->relres_after_local;
@@ -1033,6 +1111,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
                                o->eps, s));
         LCS_TRY(read_scalars(c, s));
+        LCS_TRY(finish_local(c, st));
         st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->res.rr) / bn : std::sqrt(c->hsc->res.rr);
         lcs_status rs = LCS_OK;
         if (c->hsc->res.done) {
@@ -1041,19 +1120,37 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         } else {
             SolveOut so;
             rs = solve_system(c, op, op32, n_colours(A->kind), b, x, false, &c->dsc->bnorm, o->eps,
-                              o, s, &so);
+                              o, s, &so, 0);
             st->its_global = so.its;
             st->n_outer += so.n_outer;
             st->relres_final = bn > 0 ? std::sqrt(so.rr) / bn : std::sqrt(so.rr);
             LCS_TRY(tm.mark(4));
         }
         HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(flush_prof(c));
         st->ms_construct = tm.ms(0, 1);
         st->ms_local = tm.ms(1, 2);
         st->ms_smooth = tm.ms(2, 3);
         st->ms_global = tm.ms(3, 4);
         return rs;
     });
+}
+
+lcs_status lcs_set_kernel_timing(lcs_ctx *c, int32_t what) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    if (what < LCS_TIME_NONE || what > LCS_TIME_GLOBAL_UPDATE) return fail(LCS_EINVAL, "timing class");
+    c->prof_what = what;
+    c->prof_used = 0;
+    c->prof_ms = 0.0;
+    c->prof_launches = 0;
+    return LCS_OK;
+}
+
+lcs_status lcs_get_kernel_timing(lcs_ctx *c, double *ms_total, int64_t *launches) {
+    if (!c || !ms_total || !launches) return fail(LCS_EINVAL, "NULL argument");
+    *ms_total = c->prof_ms;
+    *launches = c->prof_launches;
+    return LCS_OK;
 }
 
 lcs_status lcs_assemble_logk(lcs_ctx *c, int32_t kind, int32_t nx, int32_t ny, int32_t nz,

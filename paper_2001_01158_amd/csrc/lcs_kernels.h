@@ -52,6 +52,8 @@ struct Scalars {
     int64_t gather_nnz;  // nnz of the restricted matrix
     int32_t bad_idx;     // a caller-supplied domain was out of range or not ascending
     int32_t pad;
+    int32_t saved_it[2];      // PCG iterations of the last global (0) / local (1) solve
+    int32_t saved_status[2];
 };
 
 // partial-sum slots (each kMaxGrid x 4 doubles)
@@ -512,6 +514,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
     using real = typename Op::real;
     constexpr int V = Op::V, NB = Op::NB;
     if (sc->pcg.done) return;
+    // the first unit's coefficients are loaded before the partial fold so
+    // the two memory latencies overlap
+    Band B = my_band(A.units());
+    typename Op::Unit U;
+    if (B.u < B.end) A.load(U, B.u);
     real t[2];
     read_partials<real, 2>(part_upd, gridDim.x, Ops<0u>(), t);
     real rz = t[1];
@@ -550,9 +557,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
     if (stop) return;
     const real beta = j == 0 ? real(0) : rz / (real)sc->pcg.rz_cur;
     real v[1] = {real(0)};
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
-        typename Op::Unit U;
-        A.load(U, B.u);
+    for (bool first = true; B.u < B.end; B.u += B.step, first = false) {
+        if (!first) A.load(U, B.u);
         real pv[NB][V], po[V], zo[V];
         A.gather(U, z, pv);
         A.own(U, z, zo);
@@ -601,6 +607,20 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *
     using real = typename Op::real;
     constexpr int V = Op::V;
     if (sc->pcg.done) return;
+    // the first unit's vectors are loaded before the partial fold so the two
+    // memory latencies overlap
+    Band B = my_band(A.units());
+    typename Op::Unit U;
+    real xx[V], pp[V], qq[V], rr[V], zz[V], d[V];
+    auto load_unit = [&](int64_t u) {
+        A.geom(U, u);
+        A.own(U, x, xx);
+        A.own(U, p, pp);
+        A.own(U, q, qq);
+        A.own(U, r, rr);
+        if (kPc == 1) A.diag(U, d);
+    };
+    if (B.u < B.end) load_unit(B.u);
     real t[1];
     read_partials<real, 1>(part_ap, gridDim.x, Ops<0u>(), t);
     const double pq = (double)t[0];
@@ -616,16 +636,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *
     const real alpha = (real)rzd / t[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->pcg.rz_cur = rzd;
     real v[2] = {real(0), real(0)};
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
-        typename Op::Unit U;
-        A.geom(U, B.u);
-        real xx[V], pp[V], qq[V], rr[V], zz[V];
-        A.own(U, x, xx);
-        A.own(U, p, pp);
-        A.own(U, q, qq);
-        A.own(U, r, rr);
-        real d[V];
-        if (kPc == 1) A.diag(U, d);
+    for (bool first = true; B.u < B.end; B.u += B.step, first = false) {
+        if (!first) load_unit(B.u);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             xx[k] = fma(alpha, pp[k], xx[k]);
@@ -709,6 +721,14 @@ __global__ __launch_bounds__(kBlock) void k_resnorm(Op A, const double *__restri
         if (r) A.put(U, r, out);
     }
     write_partials<double, 2>(v, Ops<2u>(), part);
+}
+
+// keep the outcome of a PCG run whose result the host reads later
+__global__ void k_save_pcg(Scalars *sc, int scope) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->saved_it[scope] = sc->pcg.it;
+        sc->saved_status[scope] = sc->pcg.done ? sc->pcg.status : kStNoConv;
+    }
 }
 
 // one block: fold the residual partials; done when ||r|| <= tol_factor * *tol_base

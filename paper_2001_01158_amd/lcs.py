@@ -34,7 +34,8 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_solve_global", "lcs_build_local_domain", "lcs_solve_local",
             "lcs_solve_local_then_global", "lcs_residual", "lcs_gradient", "lcs_spmv",
             "lcs_gather_restricted", "lcs_gs_sweeps", "lcs_cast_coef", "lcs_assemble_logk",
-            "lcs_grad_logk"]
+            "lcs_grad_logk", "lcs_set_kernel_timing", "lcs_get_kernel_timing"]
+TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE = range(5)
 
 
 class LcsError(RuntimeError):
@@ -89,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lcs_cast_coef": (I32, [P, PM, P, P]),
         "lcs_assemble_logk": (I32, [P, I32, I32, I32, I32, D, P, P, P]),
         "lcs_grad_logk": (I32, [P, I32, I32, I32, I32, P, P, P, P, P]),
+        "lcs_set_kernel_timing": (I32, [P, I32]),
+        "lcs_get_kernel_timing": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(I64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -355,6 +358,19 @@ def grad_logk(kind: int, nx: int, ny: int, nz: int, logk: torch.Tensor, x: torch
     _check(lib().lcs_grad_logk(_ctx(ctx), kind, nx, ny, nz, _vec(logk.contiguous(), n, name="logk"),
                                _vec(x, n, name="x"), _vec(lam, n, name="lam"), _ptr(g), _stream()))
     return g
+
+
+def set_kernel_timing(what: int, ctx: Context = None):
+    """Time one kernel class with HIP events (TIME_* constants); resets totals."""
+    _check(lib().lcs_set_kernel_timing(_ctx(ctx), int(what)))
+
+
+def get_kernel_timing(ctx: Context = None):
+    """(total ms, number of timed launches) since the last set_kernel_timing."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().lcs_get_kernel_timing(_ctx(ctx), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def matrix_from_numpy(kind: int, nx: int, ny: int, nz: int, coef, device="cuda",

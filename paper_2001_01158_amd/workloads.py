@@ -248,9 +248,11 @@ def c2_moving_disk(nx: int = 1024, ny: int = 1024, sigma: float = 1.0, dt: float
 
 
 def c3_aniso_front(nx: int = 4096, ny: int = 4096, dt: float = 4.0, ratio: float = 100.0,
-                   angle: float = 30.0, radius: float = 150.0, speed: float = 8.0,
+                   angle: float = 30.0, radius: float = 350.0, speed: float = 8.0,
                    q0: float = 1.0, n_systems: int = 20) -> Workload:
-    """2-D nine-point rotated anisotropic operator, moving disk front."""
+    """2-D nine-point rotated anisotropic operator, moving disk front.  With
+    radius 350 the changing region (disk plus a ~40-cell tail) covers about
+    3 % of a 4096^2 grid under the paper's residual threshold."""
     inv_dt = 1.0 / dt
     coef = assemble_9pt(nx, ny, inv_dt, ratio, angle)
     x0c = nx / 4.0
