@@ -165,7 +165,16 @@ def main():
     # timed steps with that kernel bracketed by events on the solve's stream.
     W_ell = {W.KIND_5PT: 5, W.KIND_9PT: 9, W.KIND_7PT: 7}[w.kind]
     real_b = 8 if okw["precision"] == "fp64" else 4
-    bytes_per_row = W_ell * (4 + real_b) + 4 * real_b    # ELL col+val, z and p_old in, p and q out
+    if okw["precond"] == "rbsgs":
+        # two-kernel PCG, q = B p kernel: ELL col+val, z and p_old in, p and q out
+        bytes_per_row = W_ell * (4 + real_b) + 4 * real_b
+        kname = f"k_pcg_ap<UEll<{'double' if real_b == 8 else 'float'},{W_ell}>,2> (local PCG q = B p)"
+    else:
+        # single-synchronisation PCG iteration: ELL col+val; x, p, s, r, w, diag in;
+        # x, p, s, r, w out
+        bytes_per_row = W_ell * (4 + real_b) + 11 * real_b
+        kname = (f"k_cg_iter<UEll<{'double' if real_b == 8 else 'float'},{W_ell}>,1> "
+                 "(local PCG iteration, one launch per iteration)")
     lcs.set_kernel_timing(lcs.TIME_LOCAL_AP, ctx=ctx)
     _, st_t = run_leg("residual", args.steps, 0)
     k_ms, k_launches = lcs.get_kernel_timing(ctx=ctx)
@@ -175,8 +184,7 @@ def main():
     achieved = work_rows * bytes_per_row / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-            "kernel": f"k_pcg_ap<UEll<{'double' if real_b == 8 else 'float'},{W_ell}>,"
-                      f"{1 if okw['precond'] == 'jacobi' else 2}> (local PCG q = B p)",
+            "kernel": kname,
             "avg_launch_us": avg_us, "launches": k_launches,
             "bytes_per_launch": work_rows * bytes_per_row / max(k_launches, 1),
             "bytes_per_local_row": bytes_per_row,

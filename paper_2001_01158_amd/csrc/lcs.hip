@@ -106,7 +106,8 @@ Tiling tiling_for(int64_t n) {
 enum BufId {
     B_SCORE, B_R, B_Z, B_P0, B_P1, B_Q, B_RHSL, B_DL, B_RES, B_STAMP, B_INV, B_IDX, B_BLOCKOFF,
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
-    B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_NUM
+    B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_W0, B_W1, B_S0, B_S1, B_W32A, B_W32B,
+    B_S32A, B_S32B, B_NUM
 };
 
 }  // namespace
@@ -285,6 +286,7 @@ lcs_status launch_norm(lcs_ctx *c, const double *v, int64_t n, double *out, hipS
 template <typename real>
 struct PcgBufs {
     real *r, *z, *p0, *p1, *q;
+    real *w0, *w1, *s0, *s1;   // single-synchronisation PCG
 };
 
 struct PcgResult {
@@ -356,6 +358,72 @@ lcs_status flush_prof(lcs_ctx *c) {
         c->prof_launches += 1;
     }
     c->prof_used = 0;
+    return LCS_OK;
+}
+
+// Single-synchronisation PCG (Jacobi / none): k_cg_init1, k_cg_init2, then
+// one k_cg_iter per iteration; the stopping test of x_j runs at the start of
+// iteration j.  Buffers: r, w, s double-buffered by iteration parity.
+template <class Op, int kPc>
+lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typename Op::real *x,
+                   bool x_zero, const double *tol_base, double tol_factor, int max_iter,
+                   int check_every, const PcgBufs<typename Op::real> &B, hipStream_t s,
+                   PcgResult *res, int scope, bool sync_end) {
+    using real = typename Op::real;
+    const int64_t n = A.units() * Op::V;
+    const int grid = band_grid(A.units(), kRedGrid);
+    real *part[2] = {slot_as<real>(c, kPtAp), slot_as<real>(c, kPtUpd)};
+    real *r[2] = {B.r, B.z}, *w[2] = {B.w0, B.w1}, *sv[2] = {B.s0, B.s1};
+    if (max_iter < 0) max_iter = 0;
+    if (x_zero) {
+        hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, real(0), n);
+        LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL((k_cg_init1<Op>), dim3(grid), dim3(kBlock), 0, s, A, rhs, (const real *)x,
+                       r[0], x_zero ? 1 : 0, c->dsc);
+    hipLaunchKernelGGL((k_cg_init2<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A,
+                       (const real *)r[0], w[0], part[0]);
+    LAUNCH_CHECK();
+    if (check_every < 1) check_every = 1;
+    const bool timed = c->prof_what == (scope == 1 ? LCS_TIME_LOCAL_AP : LCS_TIME_GLOBAL_AP);
+    int next_j = 0;
+    auto launch_iter = [&](int j) -> lcs_status {
+        const int a = j & 1, b = a ^ 1;
+        return launch_maybe_timed(c, timed, k_cg_iter<Op, kPc>, grid, s, A, x, B.p0,
+                                  (const real *)sv[b], sv[a], (const real *)r[a], r[b],
+                                  (const real *)w[a], w[b], j, max_iter, tol_base, tol_factor,
+                                  c->dsc, (const real *)part[a], part[b]);
+    };
+    int first_chunk = std::max(check_every, c->last_its[scope] - check_every / 2);
+    auto enqueue_chunk = [&](int slot_id) -> lcs_status {
+        const int len = next_j == 0 ? first_chunk : check_every;
+        for (int k = 0; k < len && next_j < max_iter; ++k) LCS_TRY(launch_iter(next_j++));
+        if (next_j >= max_iter) LCS_TRY(launch_iter(next_j));  // final stopping test
+        HIP_TRY(hipMemcpyAsync(&c->hdone[slot_id], &c->dsc->pcg.done, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(c->chk[slot_id], s));
+        return LCS_OK;
+    };
+    LCS_TRY(enqueue_chunk(0));
+    int sl = 0;
+    for (;;) {
+        const bool more = next_j < max_iter;
+        if (more) LCS_TRY(enqueue_chunk(sl ^ 1));
+        HIP_TRY(hipEventSynchronize(c->chk[sl]));
+        if (c->hdone[sl] || !more) break;
+        sl ^= 1;
+    }
+    hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
+    LAUNCH_CHECK();
+    if (!sync_end) {
+        res->its = -1;
+        res->status = kStOk;
+        return LCS_OK;
+    }
+    LCS_TRY(read_scalars(c, s));
+    res->its = c->hsc->saved_it[scope];
+    res->status = c->hsc->saved_status[scope];
+    c->last_its[scope] = res->its;
     return LCS_OK;
 }
 
@@ -440,11 +508,11 @@ lcs_status run_pcg(lcs_ctx *c, const Op &A, int ncol, int pc, const typename Op:
                    hipStream_t s, PcgResult *res, int scope, bool sync_end) {
     switch (pc) {
     case LCS_PC_NONE:
-        return run_pcg_t<Op, 0>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                check_every, B, s, res, scope, sync_end);
+        return run_cg1<Op, 0>(c, A, rhs, x, x_zero, tol_base, tol_factor, max_iter, check_every, B,
+                              s, res, scope, sync_end);
     case LCS_PC_JACOBI:
-        return run_pcg_t<Op, 1>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                check_every, B, s, res, scope, sync_end);
+        return run_cg1<Op, 1>(c, A, rhs, x, x_zero, tol_base, tol_factor, max_iter, check_every, B,
+                              s, res, scope, sync_end);
     default:
         return run_pcg_t<Op, 2>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
                                 check_every, B, s, res, scope, sync_end);
@@ -501,6 +569,10 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
         LCS_TRY(get_buf(c, B_P0, n, &B.p0));
         LCS_TRY(get_buf(c, B_P1, n, &B.p1));
         LCS_TRY(get_buf(c, B_Q, n, &B.q));
+        LCS_TRY(get_buf(c, B_W0, n, &B.w0));
+        LCS_TRY(get_buf(c, B_W1, n, &B.w1));
+        LCS_TRY(get_buf(c, B_S0, n, &B.s0));
+        LCS_TRY(get_buf(c, B_S1, n, &B.s1));
         if (scope == 1) {
             PcgResult pr;
             LCS_TRY(run_pcg(c, A, ncol, o->precond, rhs, x, x_zero, tol_base, tol_factor,
@@ -536,6 +608,10 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
     LCS_TRY(get_buf(c, B_P32A, n, &B.p0));
     LCS_TRY(get_buf(c, B_P32B, n, &B.p1));
     LCS_TRY(get_buf(c, B_Q32, n, &B.q));
+    LCS_TRY(get_buf(c, B_W32A, n, &B.w0));
+    LCS_TRY(get_buf(c, B_W32B, n, &B.w1));
+    LCS_TRY(get_buf(c, B_S32A, n, &B.s0));
+    LCS_TRY(get_buf(c, B_S32B, n, &B.s1));
     const double inner = o->inner_tol > 0 ? o->inner_tol : 1e-5;
     const int outer_cap = o->max_outer > 0 ? o->max_outer : 10;
     if (x_zero) {

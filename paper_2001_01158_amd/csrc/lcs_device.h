@@ -166,20 +166,6 @@ __device__ __forceinline__ void vld(const T *__restrict__ p, T (&o)[V]) {
         for (int k = 0; k < V; ++k) o[k] = t[k];
     }
 }
-// streaming load for data read once per kernel (the own-row coefficients):
-// the non-temporal hint keeps it from displacing the x rows that neighbouring
-// strips re-read from L2
-template <typename T, int V>
-__device__ __forceinline__ void vld_nt(const T *__restrict__ p, T (&o)[V]) {
-    if constexpr (V == 1) {
-        o[0] = __builtin_nontemporal_load(p);
-    } else {
-        typedef T vt __attribute__((ext_vector_type(V)));
-        const vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(p));
-#pragma unroll
-        for (int k = 0; k < V; ++k) o[k] = t[k];
-    }
-}
 template <typename T, int V>
 __device__ __forceinline__ void vst(T *__restrict__ p, const T (&o)[V]) {
     if constexpr (V == 1) {
@@ -231,9 +217,9 @@ struct U5 {
         geom(U, u);
         const int64_t i0 = U.i0;
         real c[V], e[V], nn[V], ns[V];
-        vld_nt<real, V>(C + i0, c);
-        vld_nt<real, V>(E + i0, e);
-        vld_nt<real, V>(N + i0, nn);
+        vld<real, V>(C + i0, c);
+        vld<real, V>(E + i0, e);
+        vld<real, V>(N + i0, nn);
         if (U.y > 0) vld<real, V>(N + i0 - nx, ns);
         else
 #pragma unroll
@@ -284,6 +270,7 @@ struct U5 {
     }
     __device__ __forceinline__ int colour(const Unit &U, int k) const { return (U.x0 + k + U.y) & 1; }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
+    __device__ __forceinline__ const real *diag_ptr() const { return C; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
         vld<T, V>(p + U.i0, o);
@@ -317,11 +304,11 @@ struct U9 {
         const int64_t i0 = U.i0;
         const bool s = U.y > 0, w = U.x0 > 0, e = U.x0 + V < nx;
         real c[V], ee[V], nn[V], ne[V], nw[V], ns[V], nes[V], nws[V];
-        vld_nt<real, V>(C + i0, c);
-        vld_nt<real, V>(E + i0, ee);
-        vld_nt<real, V>(N + i0, nn);
-        vld_nt<real, V>(NE + i0, ne);
-        vld_nt<real, V>(NW + i0, nw);
+        vld<real, V>(C + i0, c);
+        vld<real, V>(E + i0, ee);
+        vld<real, V>(N + i0, nn);
+        vld<real, V>(NE + i0, ne);
+        vld<real, V>(NW + i0, nw);
         if (s) {
             vld<real, V>(N + i0 - nx, ns);
             vld<real, V>(NE + i0 - nx, nes);
@@ -399,6 +386,7 @@ struct U9 {
         return ((U.x0 + k) & 1) + 2 * (U.y & 1);
     }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
+    __device__ __forceinline__ const real *diag_ptr() const { return C; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
         vld<T, V>(p + U.i0, o);
@@ -434,10 +422,10 @@ struct U7 {
         geom(U, u);
         const int64_t i0 = U.i0, pl = (int64_t)nx * ny;
         real c[V], e[V], nn[V], uu[V], ns[V], ud[V];
-        vld_nt<real, V>(C + i0, c);
-        vld_nt<real, V>(E + i0, e);
-        vld_nt<real, V>(N + i0, nn);
-        vld_nt<real, V>(Up + i0, uu);
+        vld<real, V>(C + i0, c);
+        vld<real, V>(E + i0, e);
+        vld<real, V>(N + i0, nn);
+        vld<real, V>(Up + i0, uu);
         if (U.y > 0) vld<real, V>(N + i0 - nx, ns);
         else
 #pragma unroll
@@ -506,6 +494,7 @@ struct U7 {
     }
     __device__ __forceinline__ int colour(const Unit &U, int k) const { return (U.x0 + k + U.y + U.z) & 1; }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
+    __device__ __forceinline__ const real *diag_ptr() const { return C; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
         vld<T, V>(p + U.i0, o);
@@ -551,6 +540,7 @@ struct UEll {
     }
     __device__ __forceinline__ int colour(const Unit &U, int) const { return clr[U.i0]; }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[1]) const { d[0] = dg[U.i0]; }
+    __device__ __forceinline__ const real *diag_ptr() const { return dg; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[1]) const {
         o[0] = p[U.i0];

@@ -54,6 +54,8 @@ struct Scalars {
     int32_t pad;
     int32_t saved_it[2];      // PCG iterations of the last global (0) / local (1) solve
     int32_t saved_status[2];
+    double cg_gamma[2];       // single-synchronisation PCG: r_j.z_j by iteration parity
+    double cg_alpha[2];       //                             alpha_j by iteration parity
 };
 
 // partial-sum slots (each kMaxGrid x 4 doubles)
@@ -692,6 +694,234 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const typename Op::rea
         if (any) A.put(U, z, zo);
     }
     if (kRz) write_partials<real, 1>(v, Ops<0u>(), part_sgs);
+}
+
+// ---------------------------------------------------------------------------
+// single-synchronisation PCG (Jacobi or none): one kernel per iteration
+// ---------------------------------------------------------------------------
+// The recurrences of Chronopoulos and Gear: w_j = A z_j, and one combined
+// reduction gamma_j = r_j.z_j, delta_j = w_j.z_j (plus rho_j = r_j.r_j for
+// the stopping test) per iteration; beta_j = gamma_j / gamma_{j-1},
+// alpha_j = gamma_j / (delta_j - beta_j gamma_j / alpha_{j-1}),
+// p_j = z_j + beta_j p_{j-1}, s_j = w_j + beta_j s_{j-1} (= A p_j),
+// x += alpha_j p_j, r_{j+1} = r_j - alpha_j s_j.  In exact arithmetic these
+// are the iterates of the standard PCG.  With a pointwise preconditioner the
+// next z is known at every neighbour from the stored r_j, w_j, s_{j-1} and
+// the diagonal, so w_{j+1} = A z_{j+1} is formed in the same pass: one launch
+// and one reduction per iteration.  r, w and s are double-buffered by
+// iteration parity (neighbours read the old values); p and x are own-only.
+
+// r_0 = rhs - A x (or rhs when x = 0)
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_cg_init1(Op A, const typename Op::real *__restrict__ rhs,
+                                                     const typename Op::real *__restrict__ x,
+                                                     typename Op::real *__restrict__ r, int x_zero,
+                                                     Scalars *sc) {
+    using real = typename Op::real;
+    constexpr int V = Op::V, NB = Op::NB;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pcg.done = 0;
+        sc->pcg.status = kStOk;
+        sc->pcg.it = 0;
+    }
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        real rr[V];
+        if (x_zero) {
+            A.geom(U, B.u);
+            A.own(U, rhs, rr);
+        } else {
+            A.load(U, B.u);
+            real xv[NB][V], bb[V];
+            A.gather(U, x, xv);
+            A.own(U, rhs, bb);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                real acc = bb[k];
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (A.valid(U, q, k)) acc = fma(-U.a[q][k], xv[q][k], acc);
+                rr[k] = acc;
+            }
+        }
+        A.put(U, r, rr);
+    }
+}
+
+// w_0 = A z_0 with z_0 = M^-1 r_0 (formed at each neighbour); partials
+// gamma_0, delta_0, rho_0
+template <class Op, int kPc>
+__global__ __launch_bounds__(kBlock) void k_cg_init2(Op A, const typename Op::real *__restrict__ r,
+                                                     typename Op::real *__restrict__ w,
+                                                     typename Op::real *part) {
+    using real = typename Op::real;
+    constexpr int V = Op::V, NB = Op::NB;
+    real v[3] = {real(0), real(0), real(0)};
+    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+        typename Op::Unit U;
+        A.load(U, B.u);
+        real rv[NB][V], ro[V], zo[V], wo[V];
+        A.gather(U, r, rv);
+        A.own(U, r, ro);
+        if (kPc == 1) {
+            real dv[NB][V], dd[V];
+            A.gather(U, A.diag_ptr(), dv);
+            A.diag(U, dd);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int k = 0; k < V; ++k) rv[q][k] = A.valid(U, q, k) ? rv[q][k] / dv[q][k] : real(0);
+#pragma unroll
+            for (int k = 0; k < V; ++k) zo[k] = ro[k] / dd[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; ++k) zo[k] = ro[k];
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            real acc = real(0);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (A.valid(U, q, k)) acc = fma(U.a[q][k], rv[q][k], acc);
+            wo[k] = acc;
+            v[0] += ro[k] * zo[k];
+            v[1] += acc * zo[k];
+            v[2] += ro[k] * ro[k];
+        }
+        A.put(U, w, wo);
+    }
+    write_partials<real, 3>(v, Ops<0u>(), part);
+}
+
+// Iteration j.  Prologue: gamma_j, delta_j, rho_j from the partials -> stop
+// (criterion on rho_j, max_iter, non-finite) or alpha_j, beta_j (breakdown
+// when the denominator is not positive).  Body: p_j, s_j, x_{j+1}, r_{j+1}
+// for the own cells, z_{j+1} at every neighbour, w_{j+1} = A z_{j+1}, and
+// the partials gamma_{j+1}, delta_{j+1}, rho_{j+1}.
+template <class Op, int kPc>
+__global__ __launch_bounds__(kBlock) void k_cg_iter(
+    Op A, typename Op::real *__restrict__ x, typename Op::real *__restrict__ p,
+    const typename Op::real *__restrict__ s_old, typename Op::real *__restrict__ s_new,
+    const typename Op::real *__restrict__ r_cur, typename Op::real *__restrict__ r_next,
+    const typename Op::real *__restrict__ w_cur, typename Op::real *__restrict__ w_next, int j,
+    int max_iter, const double *tol_base, double tol_factor, Scalars *sc,
+    const typename Op::real *part_in, typename Op::real *part_out) {
+    using real = typename Op::real;
+    constexpr int V = Op::V, NB = Op::NB;
+    if (sc->pcg.done) return;
+    // the first unit's coefficients are loaded before the partial fold so the
+    // two memory latencies overlap
+    Band B = my_band(A.units());
+    typename Op::Unit U;
+    if (B.u < B.end) A.load(U, B.u);
+    real t[3];
+    read_partials<real, 3>(part_in, gridDim.x, Ops<0u>(), t);
+    const double rho = (double)t[2];
+    double tol;
+    if (j == 0) tol = tol_base ? tol_factor * *tol_base : tol_factor * sqrt(rho);
+    else tol = sc->pcg.tol;
+    int stop = 0, status = kStOk;
+    real alpha = real(0), beta = real(0);
+    if (!(rho == rho) || rho > 1.7e308) {
+        stop = 1;
+        status = kStNonFinite;
+    } else if (sqrt(rho) <= tol) {
+        stop = 1;
+    } else if (j >= max_iter) {
+        stop = 1;
+        status = kStNoConv;
+    } else {
+        const real gamma = t[0], delta = t[1];
+        real den = delta;
+        if (j > 0) {
+            beta = gamma / (real)sc->cg_gamma[(j - 1) & 1];
+            den = delta - beta * gamma / (real)sc->cg_alpha[(j - 1) & 1];
+        }
+        if (!(den > real(0))) {
+            stop = 1;
+            status = (den == den) ? kStBreakdown : kStNonFinite;
+        } else {
+            alpha = gamma / den;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (j == 0) {
+            sc->pcg.tol = tol;
+            sc->pcg.rr0 = rho;
+        }
+        sc->pcg.rr = rho;
+        sc->cg_gamma[j & 1] = (double)t[0];
+        sc->cg_alpha[j & 1] = (double)alpha;
+        if (stop) {
+            sc->pcg.done = 1;
+            sc->pcg.status = status;
+            sc->pcg.it = j;
+        }
+    }
+    if (stop) return;
+    real v[3] = {real(0), real(0), real(0)};
+    for (bool first = true; B.u < B.end; B.u += B.step, first = false) {
+        if (!first) A.load(U, B.u);
+        real rv[NB][V], wv[NB][V], ro[V], wo[V], xo[V], po[V], so[V], dd[V];
+        A.gather(U, r_cur, rv);
+        A.gather(U, w_cur, wv);
+        A.own(U, r_cur, ro);
+        A.own(U, w_cur, wo);
+        A.own(U, (const real *)x, xo);
+        if (kPc == 1) A.diag(U, dd);
+        if (j > 0) {
+            real sv[NB][V];
+            A.gather(U, s_old, sv);
+            A.own(U, s_old, so);
+            A.own(U, (const real *)p, po);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int k = 0; k < V; ++k) wv[q][k] = fma(beta, sv[q][k], wv[q][k]);
+        }
+        // neighbours: s = w + beta s_old (in wv), r' = r - alpha s, z' = M^-1 r'
+        if (kPc == 1) {
+            real dv[NB][V];
+            A.gather(U, A.diag_ptr(), dv);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int k = 0; k < V; ++k)
+                    rv[q][k] = A.valid(U, q, k) ? fma(-alpha, wv[q][k], rv[q][k]) / dv[q][k] : real(0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int k = 0; k < V; ++k)
+                    rv[q][k] = A.valid(U, q, k) ? fma(-alpha, wv[q][k], rv[q][k]) : real(0);
+        }
+        real sn[V], rn[V], wn[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const real zk = kPc == 1 ? ro[k] / dd[k] : ro[k];
+            const real pk = j > 0 ? fma(beta, po[k], zk) : zk;
+            const real sk = j > 0 ? fma(beta, so[k], wo[k]) : wo[k];
+            po[k] = pk;
+            sn[k] = sk;
+            xo[k] = fma(alpha, pk, xo[k]);
+            rn[k] = fma(-alpha, sk, ro[k]);
+            const real zn = kPc == 1 ? rn[k] / dd[k] : rn[k];
+            real acc = real(0);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (A.valid(U, q, k)) acc = fma(U.a[q][k], rv[q][k], acc);
+            wn[k] = acc;
+            v[0] += rn[k] * zn;
+            v[1] += acc * zn;
+            v[2] += rn[k] * rn[k];
+        }
+        A.put(U, x, xo);
+        A.put(U, p, po);
+        A.put(U, s_new, sn);
+        A.put(U, r_next, rn);
+        A.put(U, w_next, wn);
+    }
+    write_partials<real, 3>(v, Ops<0u>(), part_out);
 }
 
 // r = rhs - A x in FP64 (stored if r != null); partials ||r||^2, max|r|.
