@@ -173,14 +173,31 @@ lcs_status lcs_cast_coef(lcs_ctx *ctx, const lcs_matrix *A, float *coef32, void 
  * synchronisation.  Setting a class (or LCS_TIME_NONE) resets the totals. */
 enum {
     LCS_TIME_NONE = 0,
-    LCS_TIME_LOCAL_AP = 1,        /* q = B p kernel of the local PCG            */
-    LCS_TIME_LOCAL_UPDATE = 2,    /* x, r, z update kernel of the local PCG     */
-    LCS_TIME_GLOBAL_AP = 3,       /* q = A p kernel of the global PCG           */
-    LCS_TIME_GLOBAL_UPDATE = 4    /* x, r, z update kernel of the global PCG    */
+    LCS_TIME_LOCAL_AP = 1,        /* local PCG kernel that applies B: the whole
+                                     iteration for Jacobi / none, q = B p for
+                                     RB-SGS                                     */
+    LCS_TIME_LOCAL_UPDATE = 2,    /* x, r, z update kernel of the local RB-SGS PCG */
+    LCS_TIME_GLOBAL_AP = 3,       /* the same two classes for the global PCG    */
+    LCS_TIME_GLOBAL_UPDATE = 4
 };
 lcs_status lcs_set_kernel_timing(lcs_ctx *ctx, int32_t what);
 /* total milliseconds and number of timed launches since the last set */
 lcs_status lcs_get_kernel_timing(lcs_ctx *ctx, double *ms_total, int64_t *launches);
+
+/* ---- tiling of the 2-D stencil kernels ---- */
+/* The grid-sized 2-D stencil kernels (nx a multiple of 4) walk the grid in one
+ * of two ways: a flat walk (each thread takes strips in turn; rows y-1 and y+1
+ * are re-read from cache), or row-marching tiles, where a wavefront owns 64
+ * consecutive strips of one grid row and walks up march_rows rows, keeping the
+ * row below in registers, with non-temporal loads of the own-cell coefficient
+ * arrays and non-temporal stores.  march_rows < 0 forces the flat walk,
+ * 0 restores the automatic choice (marching once an FP64 pass streams more
+ * than the 256 MB last-level cache, about 2048 tiles of at most 32 rows),
+ * > 0 forces marching with that many rows; nontemporal 0 turns the
+ * non-temporal hints of marching off, 1 or < 0 leaves them on.  Per-cell
+ * results (residual, SpMV, scores, Gauss-Seidel) do not depend on these
+ * settings; reductions may round differently. */
+lcs_status lcs_set_tiling(lcs_ctx *ctx, int32_t march_rows, int32_t nontemporal);
 
 /* ---- adjoint helpers (5- and 7-point log-conductivity operators) ---- */
 /* coef = stencil of A = I*inv_dt + sum_f T_f (e_P-e_Q)(e_P-e_Q)^T with

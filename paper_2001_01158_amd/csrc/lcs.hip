@@ -87,6 +87,20 @@ int band_grid(int64_t units, int cap) {
 constexpr int kRedGrid = 512;     // reducing band kernels
 constexpr int kStreamGrid = 4096; // non-reducing band kernels
 
+// Grid of a unit-operator kernel: one wave per row-marching tile for the 2-D
+// stencils (waves loop over tiles beyond the cap), else the band grid.
+template <class Op>
+int grid_for(const Op &A, int cap) {
+    if constexpr (Op::kMarch) {
+        int64_t g = (A.tiles() + kWaves - 1) / kWaves;
+        g = (g + kXcds - 1) / kXcds * kXcds;
+        g = std::max<int64_t>(kXcds, std::min<int64_t>(g, cap));
+        return (int)g;
+    } else {
+        return band_grid(A.units(), cap);
+    }
+}
+
 // Compaction tiling: tiles of kTile stamps, at most kMaxGrid blocks.
 struct Tiling {
     int grid;
@@ -129,6 +143,9 @@ struct lcs_ctx {
     size_t prof_used = 0;
     double prof_ms = 0.0;
     int64_t prof_launches = 0;
+    // row-marching tiling of the 2-D stencil kernels (0 / -1: automatic)
+    int march_rows = 0;
+    int nontemporal = -1;
 };
 
 namespace {
@@ -214,15 +231,41 @@ Stencil7<real> sop7(const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
     return {c, c + n, c + 2 * n, c + 3 * n, A->nx, A->ny, A->nz, n};
 }
-template <typename real, int V>
-U5<real, V> uop5(const lcs_matrix *A, const real *c) {
-    const int64_t n = (int64_t)A->nx * A->ny;
-    return {c, c + n, c + 2 * n, A->nx, A->ny, n};
+// Row-marching tiles of the 2-D unit operators: about 2048 tiles (8 waves
+// per CU) of at most 32 rows.  The own-cell coefficient arrays are read with
+// non-temporal loads once a pass streams more than the 256 MB last-level
+// cache can hold (coefficients plus about six vectors).
+// lcs_set_tiling overrides each choice.
+struct Tuning {
+    int march_rows, nontemporal;
+};
+MarchGeom march_geom(const Tuning &t, int64_t upr, int ny) {
+    int64_t h = march_strips(upr) * (int64_t)ny / 2048;
+    h = std::max<int64_t>(1, std::min<int64_t>(32, h));
+    if (t.march_rows > 0) h = t.march_rows;
+    return {(int)h};
 }
-template <typename real, int V>
-U9<real, V> uop9(const lcs_matrix *A, const real *c) {
+// Walk mode of the 2-D operators (see MarchGeom): row marching with
+// non-temporal streams once the FP64 pass (coefficients plus about six
+// vectors) exceeds the 256 MB last-level cache, else the flat walk, whose
+// repeated row reads are cache hits there.
+int walk_mode(const Tuning &t, const lcs_matrix *A, int n_arr) {
+    const double bytes = (double)A->nx * A->ny * (double)(n_arr + 6) * 8.0;
+    int m = bytes > 256.0 * 1024 * 1024 ? 2 : 0;
+    if (t.march_rows < 0) m = 0;
+    else if (t.march_rows > 0) m = 2;
+    if (m > 0 && t.nontemporal == 0) m = 1;
+    return m;
+}
+template <typename real, int V, int W>
+U5<real, V, W> uop5(const Tuning &t, const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny;
-    return {c, c + n, c + 2 * n, c + 3 * n, c + 4 * n, A->nx, A->ny, n};
+    return {c, c + n, c + 2 * n, A->nx, A->ny, n, march_geom(t, A->nx / V, A->ny)};
+}
+template <typename real, int V, int W>
+U9<real, V, W> uop9(const Tuning &t, const lcs_matrix *A, const real *c) {
+    const int64_t n = (int64_t)A->nx * A->ny;
+    return {c, c + n, c + 2 * n, c + 3 * n, c + 4 * n, A->nx, A->ny, n, march_geom(t, A->nx / V, A->ny)};
 }
 template <typename real, int V>
 U7<real, V> uop7(const lcs_matrix *A, const real *c) {
@@ -239,15 +282,28 @@ bool aligned16(const void *p) { return p == nullptr || ((uintptr_t)p & 15u) == 0
 
 // Calls f(scalar_op64, unit_op64, unit_op32, Width<W>) for A's kind.
 template <class F>
-lcs_status with_ops(const lcs_matrix *A, const float *coef32, bool vec_ok, F &&f) {
+lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, bool vec_ok, F &&f) {
     const bool v = vec_ok && A->nx % 4 == 0 && aligned16(A->coef) && aligned16(coef32);
+    const Tuning t{c->march_rows, c->nontemporal};
     switch (A->kind) {
-    case LCS_STENCIL5_2D:
-        if (v) return f(sop5<double>(A, A->coef), uop5<double, 2>(A, A->coef), uop5<float, 4>(A, coef32), Width<5>());
-        return f(sop5<double>(A, A->coef), uop5<double, 1>(A, A->coef), uop5<float, 1>(A, coef32), Width<5>());
-    case LCS_STENCIL9_2D:
-        if (v) return f(sop9<double>(A, A->coef), uop9<double, 2>(A, A->coef), uop9<float, 4>(A, coef32), Width<9>());
-        return f(sop9<double>(A, A->coef), uop9<double, 1>(A, A->coef), uop9<float, 1>(A, coef32), Width<9>());
+    case LCS_STENCIL5_2D: {
+        const auto s5 = sop5<double>(A, A->coef);
+        if (!v) return f(s5, uop5<double, 1, 0>(t, A, A->coef), uop5<float, 1, 0>(t, A, coef32), Width<5>());
+        switch (walk_mode(t, A, 3)) {
+        case 0: return f(s5, uop5<double, 2, 0>(t, A, A->coef), uop5<float, 4, 0>(t, A, coef32), Width<5>());
+        case 1: return f(s5, uop5<double, 2, 1>(t, A, A->coef), uop5<float, 4, 1>(t, A, coef32), Width<5>());
+        default: return f(s5, uop5<double, 2, 2>(t, A, A->coef), uop5<float, 4, 2>(t, A, coef32), Width<5>());
+        }
+    }
+    case LCS_STENCIL9_2D: {
+        const auto s9 = sop9<double>(A, A->coef);
+        if (!v) return f(s9, uop9<double, 1, 0>(t, A, A->coef), uop9<float, 1, 0>(t, A, coef32), Width<9>());
+        switch (walk_mode(t, A, 5)) {
+        case 0: return f(s9, uop9<double, 2, 0>(t, A, A->coef), uop9<float, 4, 0>(t, A, coef32), Width<9>());
+        case 1: return f(s9, uop9<double, 2, 1>(t, A, A->coef), uop9<float, 4, 1>(t, A, coef32), Width<9>());
+        default: return f(s9, uop9<double, 2, 2>(t, A, A->coef), uop9<float, 4, 2>(t, A, coef32), Width<9>());
+        }
+    }
     default:
         if (v) return f(sop7<double>(A, A->coef), uop7<double, 2>(A, A->coef), uop7<float, 4>(A, coef32), Width<7>());
         return f(sop7<double>(A, A->coef), uop7<double, 1>(A, A->coef), uop7<float, 1>(A, coef32), Width<7>());
@@ -371,7 +427,7 @@ lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typena
                    PcgResult *res, int scope, bool sync_end) {
     using real = typename Op::real;
     const int64_t n = A.units() * Op::V;
-    const int grid = band_grid(A.units(), kRedGrid);
+    const int grid = grid_for(A, kRedGrid);
     real *part[2] = {slot_as<real>(c, kPtAp), slot_as<real>(c, kPtUpd)};
     real *r[2] = {B.r, B.z}, *w[2] = {B.w0, B.w1}, *sv[2] = {B.s0, B.s1};
     if (max_iter < 0) max_iter = 0;
@@ -434,7 +490,7 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
                      hipStream_t s, PcgResult *res, int scope, bool sync_end) {
     using real = typename Op::real;
     const int64_t n = A.units() * Op::V;
-    const int grid = band_grid(A.units(), kRedGrid);
+    const int grid = grid_for(A, kRedGrid);
     real *pupd = slot_as<real>(c, kPtUpd), *pap = slot_as<real>(c, kPtAp);
     real *psgs = slot_as<real>(c, kPtSgs);
     if (max_iter < 0) max_iter = 0;
@@ -531,7 +587,7 @@ lcs_status status_of(int st) {
 template <class Op>
 lcs_status launch_resnorm(lcs_ctx *c, const Op &A, const double *rhs, const double *x, double *r,
                           const double *tol_base, double tol_factor, hipStream_t s) {
-    const int grid = band_grid(A.units(), kRedGrid);
+    const int grid = grid_for(A, kRedGrid);
     hipLaunchKernelGGL((k_resnorm<Op>), dim3(grid), dim3(kBlock), 0, s, A, rhs, x, r,
                        slot(c, kPtRes));
     hipLaunchKernelGGL(k_fin_res, dim3(1), dim3(kBlock), 0, s, (const double *)slot(c, kPtRes),
@@ -653,7 +709,7 @@ lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *
     const int64_t n = As.n;
     const Launch L = dims_for(n);
     const Tiling T = tiling_for(n);
-    const int gs = band_grid(Au.units(), kRedGrid);
+    const int gs = grid_for(Au, kRedGrid);
     double *score;
     uint8_t *stamp;
     int32_t *inv, *blockoff;
@@ -778,7 +834,7 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
     }
     LCS_TRY(tm.mark(2));
     if (o->n_smooth > 0) {
-        const int grid = band_grid(Au.units(), kStreamGrid);
+        const int grid = grid_for(Au, kStreamGrid);
         for (int sw = 0; sw < o->n_smooth; ++sw)
             for (int col = 0; col < ncol; ++col)
                 hipLaunchKernelGGL((k_gs_half<UOp, false>), dim3(grid), dim3(kBlock), 0, s, Au, b, x,
@@ -909,7 +965,7 @@ lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const 
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(r, "r"));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, vec_ok({b, x, r}), [&](auto, auto op, auto, auto) -> lcs_status {
+    return with_ops(c, A, nullptr, vec_ok({b, x, r}), [&](auto, auto op, auto, auto) -> lcs_status {
         const int64_t n = op.units() * decltype(op)::V;
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         LCS_TRY(launch_resnorm(c, op, b, x, r, &c->dsc->bnorm, 1.0, s));
@@ -924,8 +980,8 @@ lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(g, "g"));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, vec_ok({x, g}), [&](auto, auto op, auto, auto) -> lcs_status {
-        const int grid = band_grid(op.units(), kRedGrid);
+    return with_ops(c, A, nullptr, vec_ok({x, g}), [&](auto, auto op, auto, auto) -> lcs_status {
+        const int grid = grid_for(op, kRedGrid);
         hipLaunchKernelGGL((k_score<decltype(op), 1>), dim3(grid), dim3(kBlock), 0, s, op, x, x, g,
                            slot(c, kPtScore));
         LAUNCH_CHECK();
@@ -945,14 +1001,14 @@ lcs_status lcs_spmv(lcs_ctx *c, const lcs_matrix *A, const void *x, void *y, int
     hipStream_t s = (hipStream_t)stream;
     const float *c32 = nullptr;
     LCS_TRY(ensure_coef32(c, A, precision == LCS_PREC_MIXED, &c32, s));
-    return with_ops(A, c32, vec_ok({x, y}), [&](auto, auto op, auto op32, auto) -> lcs_status {
+    return with_ops(c, A, c32, vec_ok({x, y}), [&](auto, auto op, auto op32, auto) -> lcs_status {
         for (int k = 0; k < std::max(reps, 1); ++k) {
             if (precision == LCS_PREC_FP64)
-                hipLaunchKernelGGL((k_spmv<decltype(op)>), dim3(band_grid(op.units(), kStreamGrid)),
+                hipLaunchKernelGGL((k_spmv<decltype(op)>), dim3(grid_for(op, kStreamGrid)),
                                    dim3(kBlock), 0, s, op, (const double *)x, (double *)y);
             else
                 hipLaunchKernelGGL((k_spmv<decltype(op32)>),
-                                   dim3(band_grid(op32.units(), kStreamGrid)), dim3(kBlock), 0, s,
+                                   dim3(grid_for(op32, kStreamGrid)), dim3(kBlock), 0, s,
                                    op32, (const float *)x, (float *)y);
         }
         LAUNCH_CHECK();
@@ -983,7 +1039,7 @@ lcs_status lcs_build_local_domain(lcs_ctx *c, const lcs_matrix *A, const double 
     LCS_TRY(check_ptr(K, "K"));
     LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, vec_ok({b, x0}), [&](auto sop, auto op, auto, auto) -> lcs_status {
+    return with_ops(c, A, nullptr, vec_ok({b, x0}), [&](auto sop, auto op, auto, auto) -> lcs_status {
         LCS_TRY(build_domain(c, sop, op, b, x0, mode, thresh_kind, theta, e_max, idx, K, s));
         if (mask) {
             uint8_t *stamp;
@@ -1016,7 +1072,7 @@ lcs_status lcs_gather_restricted(lcs_ctx *c, const lcs_matrix *A, const int32_t 
     }
     LCS_TRY(check_ptr(nnz, "nnz"));
     hipStream_t s = (hipStream_t)stream;
-    return with_ops(A, nullptr, false, [&](auto sop, auto, auto, auto wtag) -> lcs_status {
+    return with_ops(c, A, nullptr, false, [&](auto sop, auto, auto, auto wtag) -> lcs_status {
         constexpr int W = decltype(wtag)::value;
         int32_t *inv, *len, *blocksum;
         LCS_TRY(get_buf(c, B_INV, n, &inv));
@@ -1056,8 +1112,8 @@ lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, doubl
     if (n_sweeps < 0) return fail(LCS_EINVAL, "n_sweeps < 0");
     hipStream_t s = (hipStream_t)stream;
     const int ncol = n_colours(A->kind);
-    return with_ops(A, nullptr, vec_ok({b, x}), [&](auto, auto op, auto, auto) -> lcs_status {
-        const int grid = band_grid(op.units(), kStreamGrid);
+    return with_ops(c, A, nullptr, vec_ok({b, x}), [&](auto, auto op, auto, auto) -> lcs_status {
+        const int grid = grid_for(op, kStreamGrid);
         for (int sw = 0; sw < n_sweeps; ++sw)
             for (int col = 0; col < ncol; ++col)
                 hipLaunchKernelGGL((k_gs_half<decltype(op), false>), dim3(grid), dim3(kBlock), 0, s,
@@ -1084,7 +1140,7 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
     LCS_TRY(tm.mark(0));
     LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
-    return with_ops(A, c32, vec_ok({b, x}), [&](auto, auto op, auto op32, auto) -> lcs_status {
+    return with_ops(c, A, c32, vec_ok({b, x}), [&](auto, auto op, auto op32, auto) -> lcs_status {
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         LCS_TRY(tm.mark(3));
         SolveOut so;
@@ -1122,7 +1178,7 @@ lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, dou
     LCS_TRY(tm.mark(0));
     const float *c32 = nullptr;
     LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
-    return with_ops(A, c32, vec_ok({b, x}), [&](auto sop, auto op, auto, auto wtag) -> lcs_status {
+    return with_ops(c, A, c32, vec_ok({b, x}), [&](auto sop, auto op, auto, auto wtag) -> lcs_status {
         constexpr int W = decltype(wtag)::value;
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         int32_t *inv;
@@ -1164,7 +1220,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
     LCS_TRY(tm.mark(0));
     const float *c32 = nullptr;
     LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
-    return with_ops(A, c32, vec_ok({b, x}), [&](auto sop, auto op, auto op32, auto wtag) -> lcs_status {
+    return with_ops(c, A, c32, vec_ok({b, x}), [&](auto sop, auto op, auto op32, auto wtag) -> lcs_status {
         constexpr int W = decltype(wtag)::value;
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         int32_t *idx;
@@ -1219,6 +1275,14 @@ lcs_status lcs_set_kernel_timing(lcs_ctx *c, int32_t what) {
     c->prof_used = 0;
     c->prof_ms = 0.0;
     c->prof_launches = 0;
+    return LCS_OK;
+}
+
+lcs_status lcs_set_tiling(lcs_ctx *c, int32_t march_rows, int32_t nontemporal) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    if (nontemporal > 1) return fail(LCS_EINVAL, "nontemporal must be -1, 0 or 1");
+    c->march_rows = march_rows < 0 ? -1 : march_rows;
+    c->nontemporal = nontemporal < 0 ? -1 : nontemporal;
     return LCS_OK;
 }
 

@@ -3,8 +3,8 @@
 // Operators visit the stored entries of a row in ascending column order, so
 // every per-row sum (residual, SpMV, gradient mimic, expansion bound,
 // Gauss-Seidel update) has one fixed rounding sequence.  Reductions are
-// deterministic: a fixed wave-shuffle / LDS tree per block, then the last
-// block to finish folds the per-block partials in block order.
+// deterministic: a fixed wave-shuffle / LDS tree per block writes one partial
+// per block, and every block of the next kernel folds them in block order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -179,6 +179,65 @@ __device__ __forceinline__ void vst(T *__restrict__ p, const T (&o)[V]) {
     }
 }
 
+// Non-temporal vector load: for arrays that a pass reads exactly once (the
+// own-cell coefficients), so they do not displace the vectors that
+// neighbouring strips read again.
+template <typename T, int V>
+__device__ __forceinline__ void vld_nt(const T *__restrict__ p, T (&o)[V]) {
+    if constexpr (V == 1) {
+        o[0] = __builtin_nontemporal_load(p);
+    } else {
+        typedef T vt __attribute__((ext_vector_type(V)));
+        const vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(p));
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = t[k];
+    }
+}
+// The choice is a template parameter: a run-time flag lets the compiler merge
+// the two loads and drop the hint.
+template <bool kNT, typename T, int V>
+__device__ __forceinline__ void vld_sel(const T *__restrict__ p, T (&o)[V]) {
+    if constexpr (kNT) vld_nt<T, V>(p, o);
+    else vld<T, V>(p, o);
+}
+template <bool kNT, typename T, int V>
+__device__ __forceinline__ void vst_sel(T *__restrict__ p, const T (&o)[V]) {
+    if constexpr (!kNT) {
+        vst<T, V>(p, o);
+    } else if constexpr (V == 1) {
+        __builtin_nontemporal_store(o[0], p);
+    } else {
+        typedef T vt __attribute__((ext_vector_type(V)));
+        vt t;
+#pragma unroll
+        for (int k = 0; k < V; ++k) t[k] = o[k];
+        __builtin_nontemporal_store(t, reinterpret_cast<vt *>(p));
+    }
+}
+
+// Three consecutive grid rows of one vector around a strip of V cells, with
+// one halo cell on each side: r[0] = column x0-1, r[1..V] = x0..x0+V-1,
+// r[V+1] = x0+V (zero outside the grid or when not asked for).
+template <typename T, int V>
+struct Rows {
+    T s[V + 2], c[V + 2], n[V + 2];
+};
+template <typename T, int V>
+__device__ __forceinline__ void row_load(const T *__restrict__ v, int64_t base, int64_t safe, int x0,
+                                         int nx, bool on, bool halo, T (&r)[V + 2]) {
+    // straight-line: the strip is loaded from base when the row exists, else
+    // from the in-range row safe, and selected to zero
+    const int64_t b = on ? base : safe;
+    T m[V];
+    vld<T, V>(v + b, m);
+    const T w = (on && halo && x0 > 0) ? v[b - 1] : T(0);
+    const T e = (on && halo && x0 + V < nx) ? v[b + V] : T(0);
+    r[0] = w;
+#pragma unroll
+    for (int k = 0; k < V; ++k) r[k + 1] = on ? m[k] : T(0);
+    r[V + 1] = e;
+}
+
 // XCD bands: units [0, nu) are cut into 8 contiguous bands, band b%8 served
 // by the blocks b%8 == const (the hardware places block b on XCD b mod 8);
 // inside a band the blocks stride together, so rows y-1, y, y+1 are read by
@@ -195,19 +254,91 @@ __device__ __forceinline__ Band my_band(int64_t nu) {
     return {b0 + pos * kBlock + threadIdx.x, b1, per * kBlock};
 }
 
-template <typename real_, int V_>
+// Row marching (2-D stencils).  A wave owns a tile: a strip of 64 units of
+// one grid row (lane l -> unit l of the strip) over mh consecutive rows, and
+// walks up the rows.  The coefficients of the row below (south faces) and the
+// rows y-1, y of every gathered vector stay in registers from the previous
+// step, so each row is fetched once per pass instead of three times.  The
+// per-cell sums are the same FMA chains as in the flat walk.
+// Walk mode W of a 2-D operator: 0 the flat band walk, 1 row marching, 2 row
+// marching with non-temporal loads of the own-cell coefficient arrays and
+// non-temporal stores (for passes that stream more than the last-level cache).
+struct MarchGeom {
+    int mh;    // rows per tile
+};
+__host__ __device__ inline int64_t march_strips(int64_t upr) { return (upr + kWave - 1) / kWave; }
+
+template <typename real_, int V_, int W_>
 struct U5 {
     using real = real_;
     static constexpr int V = V_, NB = 5, kC = 2;
+    static constexpr bool kMarch = W_ > 0, kNT = W_ == 2;
     const real *C, *E, *N;
     int nx, ny;
     int64_t n;
+    MarchGeom mg;
     struct Unit {
         int64_t i0;
         int x0, y;
         real a[NB][V];
     };
     __host__ __device__ int64_t units() const { return n / V; }
+    __host__ __device__ int64_t upr() const { return nx / V; }
+    __host__ __device__ int rows() const { return ny; }
+    __host__ __device__ int64_t tiles() const {
+        return march_strips(upr()) * (int64_t)((ny + mg.mh - 1) / mg.mh);
+    }
+    // south faces of row y: N of row y-1
+    struct South {
+        real ns[V];
+    };
+    __device__ __forceinline__ void south_init(South &S, const Unit &U) const {
+        const bool s = U.y > 0;
+        real t[V];
+        vld<real, V>(N + (s ? U.i0 - nx : U.i0), t);
+#pragma unroll
+        for (int k = 0; k < V; ++k) S.ns[k] = s ? t[k] : real(0);
+    }
+    __device__ __forceinline__ void load_row(Unit &U, South &S) const {
+        const int64_t i0 = U.i0;
+        real c[V], e[V], nn[V];
+        vld_sel<kNT, real, V>(C + i0, c);
+        vld_sel<kNT, real, V>(E + i0, e);
+        vld<real, V>(N + i0, nn);
+        real ex[V + 1];   // E at columns x0-1 .. x0+V-1
+        ex[0] = U.x0 > 0 ? E[i0 - 1] : real(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) ex[k + 1] = e[k];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            U.a[0][k] = S.ns[k];
+            U.a[1][k] = ex[k];
+            U.a[2][k] = c[k];
+            U.a[3][k] = e[k];
+            U.a[4][k] = nn[k];
+            S.ns[k] = nn[k];
+        }
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_init(Rows<T, V> &R, const T *__restrict__ v, const Unit &U) const {
+        row_load<T, V>(v, U.i0 - nx, U.i0, U.x0, nx, U.y > 0, false, R.s);
+        row_load<T, V>(v, U.i0, U.i0, U.x0, nx, true, true, R.c);
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_next(Rows<T, V> &R, const T *__restrict__ v, const Unit &U) const {
+        row_load<T, V>(v, U.i0 + nx, U.i0, U.x0, nx, U.y < ny - 1, true, R.n);
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_slots(const Rows<T, V> &R, T (&o)[NB][V]) const {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o[0][k] = R.s[k + 1];
+            o[1][k] = R.c[k];
+            o[2][k] = R.c[k + 1];
+            o[3][k] = R.c[k + 2];
+            o[4][k] = R.n[k + 1];
+        }
+    }
     __device__ __forceinline__ void geom(Unit &U, int64_t u) const {
         U.i0 = u * V;
         U.y = (int)((uint64_t)U.i0 / (uint64_t)nx);
@@ -277,23 +408,122 @@ struct U5 {
     }
     template <typename T>
     __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
-        vst<T, V>(p + U.i0, o);
+        vst_sel<kNT, T, V>(p + U.i0, o);
+    }
+    // geometry of unit u at column x0, row y, known to the row walk
+    __device__ __forceinline__ void geom_xy(Unit &U, int64_t u, int x0, int y) const {
+        U.i0 = u * V;
+        U.x0 = x0;
+        U.y = y;
     }
 };
 
-template <typename real_, int V_>
+template <typename real_, int V_, int W_>
 struct U9 {
     using real = real_;
     static constexpr int V = V_, NB = 9, kC = 4;
+    static constexpr bool kMarch = W_ > 0, kNT = W_ == 2;
     const real *C, *E, *N, *NE, *NW;
     int nx, ny;
     int64_t n;
+    MarchGeom mg;
     struct Unit {
         int64_t i0;
         int x0, y;
         real a[NB][V];
     };
     __host__ __device__ int64_t units() const { return n / V; }
+    __host__ __device__ int64_t upr() const { return nx / V; }
+    __host__ __device__ int rows() const { return ny; }
+    __host__ __device__ int64_t tiles() const {
+        return march_strips(upr()) * (int64_t)((ny + mg.mh - 1) / mg.mh);
+    }
+    // south faces of row y, all from row y-1: ne[k] = NE at column x0+k-1,
+    // n[k] = N at x0+k, nw[k] = NW at x0+k (k = 0..V)
+    struct South {
+        real ne[V + 1], n[V], nw[V + 1];
+    };
+    // straight-line on purpose (loads from row y when there is no row y-1,
+    // then selected away): branch-wise stores would be merged through a
+    // pointer phi that keeps the carried state out of registers
+    __device__ __forceinline__ void south_init(South &S, const Unit &U) const {
+        const bool s = U.y > 0;
+        const int64_t bs = s ? U.i0 - nx : U.i0;
+        real tn[V], tne[V], tnw[V];
+        vld<real, V>(N + bs, tn);
+        vld<real, V>(NE + bs, tne);
+        vld<real, V>(NW + bs, tnw);
+        const real ne_w = (s && U.x0 > 0) ? NE[bs - 1] : real(0);
+        const real nw_e = (s && U.x0 + V < nx) ? NW[bs + V] : real(0);
+        S.ne[0] = ne_w;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            S.n[k] = s ? tn[k] : real(0);
+            S.ne[k + 1] = s ? tne[k] : real(0);
+            S.nw[k] = s ? tnw[k] : real(0);
+        }
+        S.nw[V] = nw_e;
+    }
+    __device__ __forceinline__ void load_row(Unit &U, South &S) const {
+        const int64_t i0 = U.i0;
+        const bool w = U.x0 > 0, e = U.x0 + V < nx;
+        real c[V], ee[V], nn[V], ne[V], nw[V];
+        vld_sel<kNT, real, V>(C + i0, c);
+        vld_sel<kNT, real, V>(E + i0, ee);
+        vld<real, V>(N + i0, nn);
+        vld<real, V>(NE + i0, ne);
+        vld<real, V>(NW + i0, nw);
+        real ex[V + 1];   // E at columns x0-1 .. x0+V-1
+        ex[0] = w ? E[i0 - 1] : real(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) ex[k + 1] = ee[k];
+        const real ne_w = w ? NE[i0 - 1] : real(0);   // NE at x0-1 of this row
+        const real nw_e = e ? NW[i0 + V] : real(0);   // NW at x0+V of this row
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            U.a[0][k] = S.ne[k];
+            U.a[1][k] = S.n[k];
+            U.a[2][k] = S.nw[k + 1];
+            U.a[3][k] = ex[k];
+            U.a[4][k] = c[k];
+            U.a[5][k] = ee[k];
+            U.a[6][k] = nw[k];
+            U.a[7][k] = nn[k];
+            U.a[8][k] = ne[k];
+        }
+        S.ne[0] = ne_w;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            S.ne[k + 1] = ne[k];
+            S.n[k] = nn[k];
+            S.nw[k] = nw[k];
+        }
+        S.nw[V] = nw_e;
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_init(Rows<T, V> &R, const T *__restrict__ v, const Unit &U) const {
+        row_load<T, V>(v, U.i0 - nx, U.i0, U.x0, nx, U.y > 0, true, R.s);
+        row_load<T, V>(v, U.i0, U.i0, U.x0, nx, true, true, R.c);
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_next(Rows<T, V> &R, const T *__restrict__ v, const Unit &U) const {
+        row_load<T, V>(v, U.i0 + nx, U.i0, U.x0, nx, U.y < ny - 1, true, R.n);
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_slots(const Rows<T, V> &R, T (&o)[NB][V]) const {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o[0][k] = R.s[k];
+            o[1][k] = R.s[k + 1];
+            o[2][k] = R.s[k + 2];
+            o[3][k] = R.c[k];
+            o[4][k] = R.c[k + 1];
+            o[5][k] = R.c[k + 2];
+            o[6][k] = R.n[k];
+            o[7][k] = R.n[k + 1];
+            o[8][k] = R.n[k + 2];
+        }
+    }
     __device__ __forceinline__ void geom(Unit &U, int64_t u) const {
         U.i0 = u * V;
         U.y = (int)((uint64_t)U.i0 / (uint64_t)nx);
@@ -393,7 +623,13 @@ struct U9 {
     }
     template <typename T>
     __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
-        vst<T, V>(p + U.i0, o);
+        vst_sel<kNT, T, V>(p + U.i0, o);
+    }
+    // geometry of unit u at column x0, row y, known to the row walk
+    __device__ __forceinline__ void geom_xy(Unit &U, int64_t u, int x0, int y) const {
+        U.i0 = u * V;
+        U.x0 = x0;
+        U.y = y;
     }
 };
 
@@ -401,6 +637,7 @@ template <typename real_, int V_>
 struct U7 {
     using real = real_;
     static constexpr int V = V_, NB = 7, kC = 3;
+    static constexpr bool kMarch = false;
     const real *C, *E, *N, *Up;
     int nx, ny, nz;
     int64_t n;
@@ -511,6 +748,7 @@ template <typename real_, int NB_>
 struct UEll {
     using real = real_;
     static constexpr int V = 1, NB = NB_;
+    static constexpr bool kMarch = false;
     const int32_t *col;
     const real *val;
     const real *dg;       // diagonal of B
@@ -550,6 +788,102 @@ struct UEll {
         p[U.i0] = o[0];
     }
 };
+
+
+// ---------------------------------------------------------------------------
+// walks: the order in which a grid-sized kernel visits its units
+// ---------------------------------------------------------------------------
+// Kernel loop:  for (auto W = walk<NG>(A); W.valid(); W.advance()) {
+//                   W.load(U);  W.template gather<j>(U, v_j, o);  ... }
+// NG is the number of gathered vectors; gather<j> must be called for the same
+// vector at every unit of a launch, and load() at every unit or at none.
+template <class Op, int NG>
+struct FlatWalk {
+    using Unit = typename Op::Unit;
+    Band B;
+    __device__ __forceinline__ explicit FlatWalk(const Op &a) : B(my_band(a.units())) {}
+    __device__ __forceinline__ bool valid() const { return B.u < B.end; }
+    __device__ __forceinline__ void geom(const Op &A, Unit &U) const { A.geom(U, B.u); }
+    __device__ __forceinline__ void load(const Op &A, Unit &U) { A.load(U, B.u); }
+    template <int j>
+    __device__ __forceinline__ void gather(const Op &A, const Unit &U, const typename Op::real *__restrict__ v,
+                                           typename Op::real (&o)[Op::NB][Op::V]) {
+        A.gather(U, v, o);
+    }
+    __device__ __forceinline__ void advance() { B.u += B.step; }
+};
+
+template <class Op, int NG>
+struct RowWalk {
+    using real = typename Op::real;
+    using Unit = typename Op::Unit;
+    static constexpr int V = Op::V;
+    int64_t u, upr, t, tiles, strips;
+    int left, mh, ny, y, x0;
+    int fresh;
+    typename Op::South S;
+    Rows<real, V> R[NG > 0 ? NG : 1];
+    __device__ __forceinline__ explicit RowWalk(const Op &a) {
+        upr = a.upr();
+        strips = march_strips(upr);
+        tiles = a.tiles();
+        mh = a.mg.mh;
+        ny = a.rows();
+        t = (int64_t)logical_block() * kWaves + threadIdx.x / kWave;
+        start();
+    }
+    __device__ __forceinline__ void start() {
+        const int lane = threadIdx.x % kWave;
+        left = 0;
+        for (; t < tiles; t += (int64_t)gridDim.x * kWaves) {
+            const int64_t strip = t % strips, seg = t / strips;
+            const int64_t xu = strip * kWave + lane;
+            if (xu >= upr) continue;
+            y = (int)seg * mh;
+            x0 = (int)xu * V;
+            left = min(mh, ny - y);
+            u = (int64_t)y * upr + xu;
+            fresh = 1;
+            return;
+        }
+    }
+    __device__ __forceinline__ bool valid() const { return left > 0; }
+    __device__ __forceinline__ void geom(const Op &A, Unit &U) const { A.geom_xy(U, u, x0, y); }
+    __device__ __forceinline__ void load(const Op &A, Unit &U) {
+        A.geom_xy(U, u, x0, y);
+        if (fresh) A.south_init(S, U);
+        A.load_row(U, S);
+    }
+    template <int j>
+    __device__ __forceinline__ void gather(const Op &A, const Unit &U, const real *__restrict__ v,
+                                           real (&o)[Op::NB][Op::V]) {
+        static_assert(j < NG, "gather stream index out of range");
+        Rows<real, V> &r = R[j];
+        if (fresh) A.rows_init(r, v, U);
+        A.rows_next(r, v, U);
+        A.rows_slots(r, o);
+#pragma unroll
+        for (int k = 0; k < V + 2; ++k) {
+            r.s[k] = r.c[k];
+            r.c[k] = r.n[k];
+        }
+    }
+    __device__ __forceinline__ void advance() {
+        fresh = 0;
+        u += upr;
+        ++y;
+        if (--left == 0) {
+            t += (int64_t)gridDim.x * kWaves;
+            start();
+        }
+    }
+};
+
+template <int NG, class Op>
+__device__ __forceinline__ auto walk(const Op &A) {
+    if constexpr (Op::kMarch) return RowWalk<Op, NG>(A);
+    else return FlatWalk<Op, NG>(A);
+}
 
 // ---------------------------------------------------------------------------
 // deterministic reductions

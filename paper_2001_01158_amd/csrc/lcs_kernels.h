@@ -74,11 +74,11 @@ __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict
                                                   double *__restrict__ s, double *part) {
     constexpr int V = Op::V, NB = Op::NB;
     double v[2] = {0.0, 0.0};
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+    for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
-        A.load(U, B.u);
+        W.load(A, U);
         double xv[NB][V], out[V];
-        A.gather(U, x, xv);
+        W.template gather<0>(A, U, x, xv);
         if (kMode == 0) {
             double bb[V];
             A.own(U, b, bb);
@@ -458,16 +458,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const typename Op::re
         sc->pcg.it = 0;
     }
     real v[2] = {real(0), real(0)};
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+    for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
         real rr[V], zz[V];
         if (x_zero) {
-            A.geom(U, B.u);
+            W.geom(A, U);
             A.own(U, rhs, rr);
         } else {
-            A.load(U, B.u);
+            W.load(A, U);
             real xv[NB][V], bb[V];
-            A.gather(U, x, xv);
+            W.template gather<0>(A, U, x, xv);
             A.own(U, rhs, bb);
 #pragma unroll
             for (int k = 0; k < V; ++k) {
@@ -518,9 +518,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
     if (sc->pcg.done) return;
     // the first unit's coefficients are loaded before the partial fold so
     // the two memory latencies overlap
-    Band B = my_band(A.units());
+    auto W = walk<2>(A);
     typename Op::Unit U;
-    if (B.u < B.end) A.load(U, B.u);
+    if (W.valid()) W.load(A, U);
     real t[2];
     read_partials<real, 2>(part_upd, gridDim.x, Ops<0u>(), t);
     real rz = t[1];
@@ -559,17 +559,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
     if (stop) return;
     const real beta = j == 0 ? real(0) : rz / (real)sc->pcg.rz_cur;
     real v[1] = {real(0)};
-    for (bool first = true; B.u < B.end; B.u += B.step, first = false) {
-        if (!first) A.load(U, B.u);
+    for (bool first = true; W.valid(); W.advance(), first = false) {
+        if (!first) W.load(A, U);
         real pv[NB][V], po[V], zo[V];
-        A.gather(U, z, pv);
+        W.template gather<0>(A, U, z, pv);
         A.own(U, z, zo);
         if (j == 0) {
 #pragma unroll
             for (int k = 0; k < V; ++k) po[k] = zo[k];
         } else {
             real ov[NB][V], oo[V];
-            A.gather(U, pold, ov);
+            W.template gather<1>(A, U, pold, ov);
             A.own(U, pold, oo);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
@@ -668,11 +668,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const typename Op::rea
     constexpr int V = Op::V, NB = Op::NB;
     if (sc && sc->pcg.done) return;
     real v[1] = {real(0)};
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+    for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
-        A.load(U, B.u);
+        W.load(A, U);
         real zv[NB][V], ro[V], zo[V];
-        A.gather(U, (const real *)z, zv);
+        W.template gather<0>(A, U, (const real *)z, zv);
         A.own(U, r, ro);
         A.own(U, (const real *)z, zo);
         bool any = false;
@@ -724,16 +724,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_init1(Op A, const typename Op::re
         sc->pcg.status = kStOk;
         sc->pcg.it = 0;
     }
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+    for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
         real rr[V];
         if (x_zero) {
-            A.geom(U, B.u);
+            W.geom(A, U);
             A.own(U, rhs, rr);
         } else {
-            A.load(U, B.u);
+            W.load(A, U);
             real xv[NB][V], bb[V];
-            A.gather(U, x, xv);
+            W.template gather<0>(A, U, x, xv);
             A.own(U, rhs, bb);
 #pragma unroll
             for (int k = 0; k < V; ++k) {
@@ -757,15 +757,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_init2(Op A, const typename Op::re
     using real = typename Op::real;
     constexpr int V = Op::V, NB = Op::NB;
     real v[3] = {real(0), real(0), real(0)};
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+    for (auto W = walk<2>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
-        A.load(U, B.u);
+        W.load(A, U);
         real rv[NB][V], ro[V], zo[V], wo[V];
-        A.gather(U, r, rv);
+        W.template gather<0>(A, U, r, rv);
         A.own(U, r, ro);
         if (kPc == 1) {
             real dv[NB][V], dd[V];
-            A.gather(U, A.diag_ptr(), dv);
+            W.template gather<1>(A, U, A.diag_ptr(), dv);
             A.diag(U, dd);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
@@ -811,9 +811,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
     if (sc->pcg.done) return;
     // the first unit's coefficients are loaded before the partial fold so the
     // two memory latencies overlap
-    Band B = my_band(A.units());
+    auto W = walk<4>(A);
     typename Op::Unit U;
-    if (B.u < B.end) A.load(U, B.u);
+    if (W.valid()) W.load(A, U);
     real t[3];
     read_partials<real, 3>(part_in, gridDim.x, Ops<0u>(), t);
     const double rho = (double)t[2];
@@ -860,18 +860,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
     }
     if (stop) return;
     real v[3] = {real(0), real(0), real(0)};
-    for (bool first = true; B.u < B.end; B.u += B.step, first = false) {
-        if (!first) A.load(U, B.u);
+    for (bool first = true; W.valid(); W.advance(), first = false) {
+        if (!first) W.load(A, U);
         real rv[NB][V], wv[NB][V], ro[V], wo[V], xo[V], po[V], so[V], dd[V];
-        A.gather(U, r_cur, rv);
-        A.gather(U, w_cur, wv);
+        W.template gather<0>(A, U, r_cur, rv);
+        W.template gather<1>(A, U, w_cur, wv);
         A.own(U, r_cur, ro);
         A.own(U, w_cur, wo);
         A.own(U, (const real *)x, xo);
         if (kPc == 1) A.diag(U, dd);
         if (j > 0) {
             real sv[NB][V];
-            A.gather(U, s_old, sv);
+            W.template gather<2>(A, U, s_old, sv);
             A.own(U, s_old, so);
             A.own(U, (const real *)p, po);
 #pragma unroll
@@ -882,7 +882,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
         // neighbours: s = w + beta s_old (in wv), r' = r - alpha s, z' = M^-1 r'
         if (kPc == 1) {
             real dv[NB][V];
-            A.gather(U, A.diag_ptr(), dv);
+            W.template gather<3>(A, U, A.diag_ptr(), dv);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -931,11 +931,11 @@ __global__ __launch_bounds__(kBlock) void k_resnorm(Op A, const double *__restri
                                                     double *__restrict__ r, double *part) {
     constexpr int V = Op::V, NB = Op::NB;
     double v[2] = {0.0, 0.0};
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+    for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
-        A.load(U, B.u);
+        W.load(A, U);
         double xv[NB][V], bb[V], out[V];
-        A.gather(U, x, xv);
+        W.template gather<0>(A, U, x, xv);
         A.own(U, rhs, bb);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -1037,11 +1037,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op A, const typename Op::real *
                                                  typename Op::real *__restrict__ y) {
     using real = typename Op::real;
     constexpr int V = Op::V, NB = Op::NB;
-    for (Band B = my_band(A.units()); B.u < B.end; B.u += B.step) {
+    for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
-        A.load(U, B.u);
+        W.load(A, U);
         real xv[NB][V], out[V];
-        A.gather(U, x, xv);
+        W.template gather<0>(A, U, x, xv);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             real acc = real(0);

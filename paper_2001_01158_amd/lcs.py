@@ -34,7 +34,8 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_solve_global", "lcs_build_local_domain", "lcs_solve_local",
             "lcs_solve_local_then_global", "lcs_residual", "lcs_gradient", "lcs_spmv",
             "lcs_gather_restricted", "lcs_gs_sweeps", "lcs_cast_coef", "lcs_assemble_logk",
-            "lcs_grad_logk", "lcs_set_kernel_timing", "lcs_get_kernel_timing"]
+            "lcs_grad_logk", "lcs_set_kernel_timing", "lcs_get_kernel_timing",
+            "lcs_set_tiling"]
 TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE = range(5)
 
 
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lcs_grad_logk": (I32, [P, I32, I32, I32, I32, P, P, P, P, P]),
         "lcs_set_kernel_timing": (I32, [P, I32]),
         "lcs_get_kernel_timing": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(I64)]),
+        "lcs_set_tiling": (I32, [P, I32, I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -371,6 +373,13 @@ def get_kernel_timing(ctx: Context = None):
     n = ctypes.c_int64(0)
     _check(lib().lcs_get_kernel_timing(_ctx(ctx), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def set_tiling(march_rows: int = 0, nontemporal: int = -1, ctx: Context = None):
+    """Walk of the 2-D stencil kernels: march_rows < 0 flat, 0 automatic, > 0
+    row-marching tiles of that many rows; nontemporal 0 turns the marching
+    kernels' non-temporal hints off."""
+    _check(lib().lcs_set_tiling(_ctx(ctx), int(march_rows), int(nontemporal)))
 
 
 def matrix_from_numpy(kind: int, nx: int, ny: int, nz: int, coef, device="cuda",

@@ -80,9 +80,17 @@ def make_case(name, seed=0, dt=4.0):
     return kind, (nx, ny, nz), coef, Ah, A, b, x0
 
 
-@pytest.fixture(scope="module")
-def ctx():
-    return lcs.Context()
+# Tilings of the 2-D stencil kernels: the automatic one (one-row tiles at
+# these sizes), and 5-row marching tiles (a partial last tile, rows carried in
+# registers) with non-temporal coefficient loads.
+TILINGS = {"auto": (0, -1), "rows5_nt": (5, 1)}
+
+
+@pytest.fixture(scope="module", params=list(TILINGS))
+def ctx(request):
+    c = lcs.Context()
+    lcs.set_tiling(*TILINGS[request.param], ctx=c)
+    return c
 
 
 # ----------------------------------------------------------------------------
