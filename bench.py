@@ -31,6 +31,28 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel measured by two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) of this script, each scaled by what the counter
+# reads for a plain 512 MiB device copy, divided by the kernel's algorithmic
+# bytes over the same dispatches (the --summarize output records the run).
+# Valid only while the kernel sources hash to src_sha256; otherwise the
+# roofline reports traffic null.
+MEASURED_TRAFFIC = {
+    "c2": {"ratio": 1.083, "kernel": "k_cg_iter<UEll<double,5>,1>",
+           "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
+           "src_sha256": "4131a8b3d93bbba99d3894f9f7e5b12a77c0d64086398a2d109f5a4267f772e0"},
+}
+KERNEL_SOURCES = ["paper_2001_01158_amd/csrc/lcs_device.h", "paper_2001_01158_amd/csrc/lcs_kernels.h"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -43,6 +65,11 @@ def parse():
     p.add_argument("--skip-spmv-hbm", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 512 MiB device copy (traffic-counter calibration)")
+    p.add_argument("--tiling-sweep", action="store_true",
+                   help="time the 4096^2 nine-point FP32 SpMV under each walk / tiling and exit")
+    p.add_argument("--summarize", metavar="DIR",
+                   help="print a summary of rocprofv3 output under DIR (trace/, fetch/, write/) "
+                        "and exit; no GPU needed")
     return p.parse_args()
 
 
@@ -76,8 +103,119 @@ def make_workload(name):
     return w, opts, desc, src
 
 
+def summarize(d: str, steps: int):
+    """Markdown summary of rocprofv3 output: kernel statistics of the traced
+    run, the dominant local-PCG kernel over the timed pass only (the last
+    `steps` residual-mode solves, each of which starts with one k_score<., 0>
+    dispatch), and its FETCH_SIZE / WRITE_SIZE traffic per dispatch scaled by
+    the 512 MiB copy calibration."""
+    import csv
+    import glob
+
+    def rows(pattern):
+        f = sorted(glob.glob(os.path.join(d, pattern)))
+        return list(csv.DictReader(open(f[0]))) if f else []
+
+    import re
+    dom = "void lcs::k_cg_iter<lcs::UEll<double, 5>, 1>"
+    start_mark = re.compile(r"void lcs::k_score<lcs::U5<double, 2(, \d)?>, 0>")
+    short = lambda name: name.split("(")[0].replace("void ", "", 1)
+    out = []
+    stats = rows("trace/*kernel_stats.csv")
+    if stats:
+        out.append("| kernel | calls | avg us | total ms | % |")
+        out.append("|---|---|---|---|---|")
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+            out.append(f"| `{short(r['Name'])}` | {r['Calls']} | "
+                       f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                       f"{float(r['Percentage']):.1f} |")
+
+    def window(recs, name_key, ts_key):
+        marks = [int(r[ts_key]) for r in recs if start_mark.match(r[name_key])]
+        if len(marks) < steps:
+            return []
+        t0 = sorted(marks)[-steps]
+        return [r for r in recs if r[name_key].startswith(dom) and int(r[ts_key]) >= t0]
+
+    trace = rows("trace/*kernel_trace.csv")
+    if trace:
+        allk = [r for r in trace if r["Kernel_Name"].startswith(dom)]
+        win = window(trace, "Kernel_Name", "Start_Timestamp")
+        dur = lambda rs: sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rs) / max(len(rs), 1) / 1e3
+        out.append("")
+        out.append(f"dominant kernel `{short(dom)}`: whole run {len(allk)} dispatches, avg {dur(allk):.2f} us; "
+                   f"timed pass (last {steps} residual-mode systems) {len(win)} dispatches, avg {dur(win):.2f} us")
+    fetch, write = rows("fetch/*counter_collection.csv"), rows("write/*counter_collection.csv")
+    if fetch and write:
+        copy = lambda rs: max(float(r["Counter_Value"]) for r in rs if "copyBuffer" in r["Kernel_Name"])
+        f_fetch = 512 * 1024 / copy(fetch)
+        f_write = 512 * 1024 / copy(write)
+        wf = window(fetch, "Kernel_Name", "Start_Timestamp")
+        ww = window(write, "Kernel_Name", "Start_Timestamp")
+        kib_f = sum(float(r["Counter_Value"]) for r in wf) / max(len(wf), 1)
+        kib_w = sum(float(r["Counter_Value"]) for r in ww) / max(len(ww), 1)
+        traffic = (kib_f * f_fetch + kib_w * f_write) * 1024
+        out.append("")
+        out.append(f"calibration (512 MiB copy): FETCH_SIZE x{f_fetch:.3f}, WRITE_SIZE x{f_write:.3f}")
+        out.append(f"dominant kernel over the timed pass: {len(wf)} / {len(ww)} dispatches, "
+                   f"FETCH {kib_f:.1f} KiB, WRITE {kib_w:.1f} KiB per dispatch -> "
+                   f"{traffic / 1e6:.3f} MB per dispatch (calibrated)")
+        spm = "void lcs::k_spmv<lcs::U9<float, 4, 2> >"
+        sf = [float(r["Counter_Value"]) for r in fetch if r["Kernel_Name"].startswith(spm)]
+        sw = [float(r["Counter_Value"]) for r in write if r["Kernel_Name"].startswith(spm)]
+        if sf and sw:
+            t = (sum(sf) / len(sf) * f_fetch + sum(sw) / len(sw) * f_write) * 1024
+            alg = 4096 * 4096 * 28
+            out.append(f"`{short(spm)}` (4096^2, FP32): {len(sf)} dispatches, {t / 1e6:.1f} MB per dispatch "
+                       f"(calibrated) vs {alg / 1e6:.1f} MB algorithmic -> ratio {t / alg:.3f}")
+        bj = os.path.join(d, "fetch_bench.json")
+        if os.path.exists(bj):
+            bpl = json.load(open(bj))["roofline"]["bytes_per_launch"]
+            out.append(f"algorithmic bytes per launch in that run: {bpl / 1e6:.3f} MB -> "
+                       f"traffic / algorithmic = {traffic / bpl:.3f}")
+    print("\n".join(out))
+
+
+def tiling_sweep():
+    """The 4096^2 nine-point FP32 SpMV under each walk of the 2-D kernels
+    (lcs_set_tiling): flat, and row marching with and without the
+    non-temporal hints, over several tile heights."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+    dev = "cuda:0"
+    ctx = lcs.Context()
+    stream = torch.cuda.current_stream()
+    n3 = 4096
+    c9 = W.assemble_9pt(n3, n3, 0.25, 100.0, 30.0)
+    A9 = lcs.matrix_from_numpy(W.KIND_9PT, n3, n3, 1, c9, dev, with32=True)
+    del c9
+    x = torch.rand(n3 * n3, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    print("| walk | rows per tile | non-temporal | us | GB/s |")
+    print("|---|---|---|---|---|")
+    for rows, nt in [(-1, 0), (0, -1), (4, 0), (16, 0), (32, 0), (4, 1), (8, 1), (16, 1), (32, 1)]:
+        lcs.set_tiling(rows, nt, ctx=ctx)
+        lcs.spmv(A9, x, y, reps=5, ctx=ctx)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lcs.spmv(A9, x, y, reps=50, ctx=ctx)
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) / 50 * 1e3
+        walk = "flat" if rows < 0 else ("marching (automatic)" if rows == 0 else "marching")
+        print(f"| {walk} | {'-' if rows < 0 else (32 if rows == 0 else rows)} | "
+              f"{'-' if rows < 0 else ('no' if nt == 0 else 'yes')} | {us:.1f} | "
+              f"{n3 * n3 * 28 / us / 1e3:.0f} |", flush=True)
+
+
 def main():
     args = parse()
+    if args.summarize:
+        summarize(args.summarize, args.steps)
+        return
+    if args.tiling_sweep:
+        tiling_sweep()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; sharding across GPUs is a design "
                                    "description only (DESIGN.md section 9)", "n_gpus": args.gpus}))
@@ -182,11 +320,17 @@ def main():
     work_rows = float(sum(s.K * s.its_local for s in st_t))     # rows processed by working launches
     avg_us = k_ms * 1e3 / max(k_launches, 1)
     achieved = work_rows * bytes_per_row / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
+    bytes_per_launch = work_rows * bytes_per_row / max(k_launches, 1)
+    mt = MEASURED_TRAFFIC.get(args.workload)
+    traffic = None
+    if mt and mt["src_sha256"] == kernel_sources_sha256():
+        traffic = mt["ratio"] * bytes_per_launch
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+            "traffic_unit": "bytes per launch", "traffic_ratio": mt["ratio"] if traffic else None,
             "kernel": kname,
             "avg_launch_us": avg_us, "launches": k_launches,
-            "bytes_per_launch": work_rows * bytes_per_row / max(k_launches, 1),
+            "bytes_per_launch": bytes_per_launch,
             "bytes_per_local_row": bytes_per_row,
             "note": "latency-bound: K ~ 1e4-1e5 rows per launch; see DESIGN.md section 6"}
     log(f"dominant kernel: {k_launches} launches, avg {avg_us:.2f} us, {achieved or 0:.0f} GB/s")
@@ -219,7 +363,7 @@ def main():
         b9 = n3 * n3 * (5 * 4 + 4 + 4)
         hbm = {"n": n3 * n3, "us": ms9 * 1e3, "GBs": b9 / ms9 / 1e6, "bytes_per_row": 28,
                "frac_of_8TBs": b9 / ms9 / 1e6 / HBM_PEAK_GBS,
-               "kernel": "k_spmv<U9<float,4>>"}
+               "kernel": "k_spmv<U9<float,4,2>> (row marching, non-temporal streams)"}
         spmv["c3_9pt_fp32_4096x4096_hbm"] = hbm
         log(f"SpMV 9pt FP32 4096^2: {ms9 * 1e3:.1f} us, {hbm['GBs']:.0f} GB/s")
         del A9, x9, y9
