@@ -965,7 +965,7 @@ __device__ __forceinline__ void write_partials(T (&v)[NV], O ops, T *part) {
 // gets bit-identical totals, valid in all of its threads.
 template <typename T, int NV, class O>
 __device__ __forceinline__ void read_partials(const T *part, int g, O ops, T (&tot)[NV]) {
-    __shared__ T res[NV];
+    __shared__ T lds[kWaves][NV];
     T a[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -974,16 +974,23 @@ __device__ __forceinline__ void read_partials(const T *part, int g, O ops, T (&t
             const T p = part[(size_t)k * g + b];
             a[k] = (b == (int)threadIdx.x) ? p : ops.template apply<T>(k, a[k], p);
         }
+        a[k] = ops.template reduce_wave<T>(k, a[k]);   // xor butterfly: the same in every lane
     }
-    block_reduce<T, NV>(a, ops);
-    if (threadIdx.x == 0) {
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) res[k] = a[k];
+        for (int k = 0; k < NV; ++k) lds[w][k] = a[k];
     }
     __syncthreads();
+    // every thread combines the wave sums in the same order
 #pragma unroll
-    for (int k = 0; k < NV; ++k) tot[k] = res[k];
-    __syncthreads();
+    for (int k = 0; k < NV; ++k) {
+        T s = lds[0][k];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) s = ops.template apply<T>(k, s, lds[q][k]);
+        tot[k] = s;
+    }
+    __syncthreads();   // lds may be reused by the next fold
 }
 
 // exclusive prefix of integer block counts: sum of cnt[0..upto) in every

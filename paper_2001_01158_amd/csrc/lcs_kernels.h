@@ -515,9 +515,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
                                                    typename Op::real *part_ap) {
     using real = typename Op::real;
     constexpr int V = Op::V, NB = Op::NB;
-    if (sc->pcg.done) return;
-    // the first unit's coefficients are loaded before the partial fold so
-    // the two memory latencies overlap
+    // scalars, stop flag and the first unit's coefficients before the fold
+    // (their latencies overlap; see k_cg_iter)
+    const int done = sc->pcg.done;
+    const double tol_prev = sc->pcg.tol, rz_prev = sc->pcg.rz_cur;
+    const double tol_in = (j == 0 && tol_base) ? *tol_base : 0.0;
     auto W = walk<2>(A);
     typename Op::Unit U;
     if (W.valid()) W.load(A, U);
@@ -529,10 +531,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
         read_partials<real, 1>(part_sgs, gridDim.x, Ops<0u>(), u);
         rz = u[0];
     }
+    if (done) return;
     const double rr = (double)t[0];
     double tol;
-    if (j == 0) tol = tol_base ? tol_factor * *tol_base : tol_factor * sqrt(rr);
-    else tol = sc->pcg.tol;
+    if (j == 0) tol = tol_base ? tol_factor * tol_in : tol_factor * sqrt(rr);
+    else tol = tol_prev;
     int stop = 0, status = kStOk;
     if (!(rr == rr) || rr > 1.7e308) {
         stop = 1;
@@ -557,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
         }
     }
     if (stop) return;
-    const real beta = j == 0 ? real(0) : rz / (real)sc->pcg.rz_cur;
+    const real beta = j == 0 ? real(0) : rz / (real)rz_prev;
     real v[1] = {real(0)};
     for (bool first = true; W.valid(); W.advance(), first = false) {
         if (!first) W.load(A, U);
@@ -608,9 +611,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *
                                                        typename Op::real *part_upd) {
     using real = typename Op::real;
     constexpr int V = Op::V;
-    if (sc->pcg.done) return;
-    // the first unit's vectors are loaded before the partial fold so the two
-    // memory latencies overlap
+    // stop flag, r.z and the first unit's vectors before the partial fold
+    // (their latencies overlap; see k_cg_iter)
+    const int done = sc->pcg.done;
+    const double rzd = sc->pcg.rz_next;
     Band B = my_band(A.units());
     typename Op::Unit U;
     real xx[V], pp[V], qq[V], rr[V], zz[V], d[V];
@@ -625,8 +629,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *
     if (B.u < B.end) load_unit(B.u);
     real t[1];
     read_partials<real, 1>(part_ap, gridDim.x, Ops<0u>(), t);
+    if (done) return;
     const double pq = (double)t[0];
-    const double rzd = sc->pcg.rz_next;
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->pcg.done = 1;
@@ -808,18 +812,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
     const typename Op::real *part_in, typename Op::real *part_out) {
     using real = typename Op::real;
     constexpr int V = Op::V, NB = Op::NB;
-    if (sc->pcg.done) return;
-    // the first unit's coefficients are loaded before the partial fold so the
-    // two memory latencies overlap
+    // The scalars of the previous iterations, the stop flag and the first
+    // unit's coefficients are loaded before the partial fold so that their
+    // latencies overlap (block 0 of this launch writes other parities and
+    // fields only; a block that sees the flag set by this launch would stop
+    // anyway).
+    const int done = sc->pcg.done;
+    const double tol_prev = sc->pcg.tol;
+    const double gamma_prev = sc->cg_gamma[(j - 1) & 1], alpha_prev = sc->cg_alpha[(j - 1) & 1];
+    const double tol_in = (j == 0 && tol_base) ? *tol_base : 0.0;
     auto W = walk<4>(A);
     typename Op::Unit U;
     if (W.valid()) W.load(A, U);
     real t[3];
     read_partials<real, 3>(part_in, gridDim.x, Ops<0u>(), t);
+    if (done) return;
     const double rho = (double)t[2];
     double tol;
-    if (j == 0) tol = tol_base ? tol_factor * *tol_base : tol_factor * sqrt(rho);
-    else tol = sc->pcg.tol;
+    if (j == 0) tol = tol_base ? tol_factor * tol_in : tol_factor * sqrt(rho);
+    else tol = tol_prev;
     int stop = 0, status = kStOk;
     real alpha = real(0), beta = real(0);
     if (!(rho == rho) || rho > 1.7e308) {
@@ -834,8 +845,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
         const real gamma = t[0], delta = t[1];
         real den = delta;
         if (j > 0) {
-            beta = gamma / (real)sc->cg_gamma[(j - 1) & 1];
-            den = delta - beta * gamma / (real)sc->cg_alpha[(j - 1) & 1];
+            beta = gamma / (real)gamma_prev;
+            den = delta - beta * gamma / (real)alpha_prev;
         }
         if (!(den > real(0))) {
             stop = 1;
