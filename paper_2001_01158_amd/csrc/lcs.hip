@@ -360,7 +360,8 @@ lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<typename Op::re
     if (kPc != LCS_PC_RBSGS) return LCS_OK;
     real *part = slot_as<real>(c, kPtSgs);
     const Scalars *sc = c->dsc;
-    for (int col = 0; col < ncol; ++col)
+    // colour 0 of the forward sweep is done by the kernel that formed r
+    for (int col = 1; col < ncol; ++col)
         hipLaunchKernelGGL((k_gs_half<Op, false>), dim3(grid), dim3(kBlock), 0, s, A,
                            (const real *)B.r, B.z, col, sc, part);
     for (int col = ncol - 2; col >= 0; --col) {

@@ -437,13 +437,19 @@ __global__ __launch_bounds__(kBlock) void k_scatter_add(const int32_t *__restric
 // ---------------------------------------------------------------------------
 // preconditioned CG (templated on operator and working precision)
 // ---------------------------------------------------------------------------
-// Iteration j is the pair k_pcg_ap(j), k_pcg_update(j) (plus the three
+// Iteration j is the pair k_pcg_ap(j), k_pcg_update(j) (plus the
 // Gauss-Seidel half sweeps for RB-SGS).  Each kernel starts by folding the
 // partials of the kernel before it, so every block holds the same scalars;
 // block 0 records them for later kernels and the host.
 //
+// RB-SGS applies the symmetric colour-ordered sweeps 0, 1, .., c-1, .., 1, 0
+// to M z = r from z = 0.  The first sweep, over colour 0 with every
+// neighbour still zero, is z_i = r_i / a_ii exactly (each fma(-a, 0, acc)
+// leaves acc unchanged), so the kernels that form r also do it; the host
+// launches the remaining sweeps from colour 1.
+//
 // init: r = rhs - A x (or r = rhs when x = 0); Jacobi: z = r / a_ii; none:
-// z = r; RB-SGS: z = 0 (filled by the half sweeps).  Partials r.r, r.z.
+// z = r; RB-SGS: z = r / a_ii on colour 0, else 0.  Partials r.r, r.z.
 template <class Op, int kPc>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const typename Op::real *__restrict__ rhs,
                                                      const typename Op::real *__restrict__ x,
@@ -478,14 +484,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Op A, const typename Op::re
                 rr[k] = acc;
             }
         }
-        if (kPc == 1) {
+        if (kPc >= 1) {
             real d[V];
             A.diag(U, d);
 #pragma unroll
-            for (int k = 0; k < V; ++k) zz[k] = rr[k] / d[k];
+            for (int k = 0; k < V; ++k)
+                zz[k] = (kPc == 1 || A.colour(U, k) == 0) ? rr[k] / d[k] : real(0);
         } else {
 #pragma unroll
-            for (int k = 0; k < V; ++k) zz[k] = kPc == 2 ? real(0) : rr[k];
+            for (int k = 0; k < V; ++k) zz[k] = rr[k];
         }
         A.put(U, r, rr);
         A.put(U, z, zz);
@@ -599,8 +606,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
 
 // Iteration j, second kernel.  Prologue: p.q from the partials ->
 // breakdown if p.q <= 0, else alpha = r.z / p.q.  Body: x += alpha p;
-// r -= alpha q; Jacobi z = r / a_ii (none: z = r; RB-SGS: z = 0 for the
-// half sweeps).  Partials r.r, r.z.
+// r -= alpha q; Jacobi z = r / a_ii (none: z = r; RB-SGS: the colour-0 sweep
+// from z = 0, as in init).  Partials r.r, r.z.
 template <class Op, int kPc>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *__restrict__ x,
                                                        const typename Op::real *__restrict__ p,
@@ -624,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *
         A.own(U, p, pp);
         A.own(U, q, qq);
         A.own(U, r, rr);
-        if (kPc == 1) A.diag(U, d);
+        if (kPc >= 1) A.diag(U, d);
     };
     if (B.u < B.end) load_unit(B.u);
     real t[1];
@@ -648,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op A, typename Op::real *
         for (int k = 0; k < V; ++k) {
             xx[k] = fma(alpha, pp[k], xx[k]);
             rr[k] = fma(-alpha, qq[k], rr[k]);
-            zz[k] = kPc == 1 ? rr[k] / d[k] : (kPc == 2 ? real(0) : rr[k]);
+            zz[k] = kPc == 0 ? rr[k] : (kPc == 1 || A.colour(U, k) == 0) ? rr[k] / d[k] : real(0);
             v[0] += rr[k] * rr[k];
             v[1] += rr[k] * zz[k];
         }

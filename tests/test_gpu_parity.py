@@ -361,6 +361,29 @@ def test_argument_errors(ctx):
         lcs.build_local_domain(A, dev(b), dev(x0), "gradient", "paper", 1e-3, 0, ctx=ctx)
     with pytest.raises(lcs.LcsError):
         lcs.build_local_domain(A, dev(b), dev(x0), "residual", "relmax", 1e-3, 300, ctx=ctx)
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.set_tiling(4, 2, ctx=lcs.Context())
+    assert e.value.status == lcs.EINVAL
+
+
+@pytest.mark.parametrize("name", ["5pt_v", "9pt_v"])
+@pytest.mark.parametrize("rows,nt", [(-1, -1), (3, 0), (7, 1), (200, 1)])
+def test_walks_agree_bitwise(name, rows, nt):
+    """Every walk of the 2-D kernels (flat; marching with and without the
+    non-temporal hints; tiles taller than the grid) gives the oracle's per-row
+    results bit for bit, and Algorithm 1 meets the criterion."""
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    say("walk", name, rows, nt)
+    c = lcs.Context()
+    lcs.set_tiling(rows, nt, ctx=c)
+    r = host(lcs.residual(A, dev(b), dev(x0), ctx=c))
+    assert np.array_equal(r, oracle.residual(Ah, b, x0))
+    x = dev(x0)
+    lcs.gs_sweeps(A, dev(b), x, 1, ctx=c)
+    assert np.array_equal(host(x), oracle.gs_sweeps(Ah, b, x0, 1))
+    x = dev(x0)
+    lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1, ctx=c)
+    assert np.linalg.norm(oracle.residual(Ah, b, host(x))) <= 1.0001e-10 * np.linalg.norm(b)
 
 
 def test_nonfinite_input_reported(ctx):
