@@ -273,6 +273,7 @@ struct U5 {
     using real = real_;
     static constexpr int V = V_, NB = 5, kC = 2;
     static constexpr bool kMarch = W_ > 0, kNT = W_ == 2;
+    static constexpr bool kCenter = true;   // slot kC of a gather is the own cell
     const real *C, *E, *N;
     int nx, ny;
     int64_t n;
@@ -423,6 +424,7 @@ struct U9 {
     using real = real_;
     static constexpr int V = V_, NB = 9, kC = 4;
     static constexpr bool kMarch = W_ > 0, kNT = W_ == 2;
+    static constexpr bool kCenter = true;
     const real *C, *E, *N, *NE, *NW;
     int nx, ny;
     int64_t n;
@@ -637,7 +639,7 @@ template <typename real_, int V_>
 struct U7 {
     using real = real_;
     static constexpr int V = V_, NB = 7, kC = 3;
-    static constexpr bool kMarch = false;
+    static constexpr bool kMarch = false, kCenter = true;
     const real *C, *E, *N, *Up;
     int nx, ny, nz;
     int64_t n;
@@ -749,6 +751,7 @@ struct UEll {
     using real = real_;
     static constexpr int V = 1, NB = NB_;
     static constexpr bool kMarch = false;
+    static constexpr bool kCenter = false;   // the diagonal slot varies by row
     const int32_t *col;
     const real *val;
     const real *dg;       // diagonal of B

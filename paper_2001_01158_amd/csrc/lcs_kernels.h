@@ -58,6 +58,31 @@ struct Scalars {
     double cg_alpha[2];       //                             alpha_j by iteration parity
 };
 
+// Own value of a gathered vector and the diagonal: for the stencils the
+// gather's centre slot and the loaded C coefficients already hold them; the
+// restricted matrix loads them.
+template <class Op, typename T>
+__device__ __forceinline__ void own_of(const Op &A, const typename Op::Unit &U,
+                                       const T (&g)[Op::NB][Op::V], const T *__restrict__ v,
+                                       T (&o)[Op::V]) {
+    if constexpr (Op::kCenter) {
+#pragma unroll
+        for (int k = 0; k < Op::V; ++k) o[k] = g[Op::kC][k];
+    } else {
+        A.own(U, v, o);
+    }
+}
+template <class Op>
+__device__ __forceinline__ void diag_of(const Op &A, const typename Op::Unit &U,
+                                        typename Op::real (&d)[Op::V]) {
+    if constexpr (Op::kCenter) {
+#pragma unroll
+        for (int k = 0; k < Op::V; ++k) d[k] = U.a[Op::kC][k];
+    } else {
+        A.diag(U, d);
+    }
+}
+
 // partial-sum slots (each kMaxGrid x 4 doubles)
 enum PartSlot { kPtScore = 0, kPtExp0, kPtExp1, kPtNorm, kPtRes, kPtAp, kPtUpd, kPtSgs, kPtSlots };
 constexpr size_t kSlotElems = (size_t)kMaxGrid * 4;
@@ -93,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict
             }
         } else {
             double xo[V];
-            A.own(U, x, xo);
+            own_of(A, U, xv, x, xo);
 #pragma unroll
             for (int k = 0; k < V; ++k) {
                 double acc = 0.0;
@@ -573,14 +598,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
         if (!first) W.load(A, U);
         real pv[NB][V], po[V], zo[V];
         W.template gather<0>(A, U, z, pv);
-        A.own(U, z, zo);
+        own_of(A, U, pv, z, zo);
         if (j == 0) {
 #pragma unroll
             for (int k = 0; k < V; ++k) po[k] = zo[k];
         } else {
             real ov[NB][V], oo[V];
             W.template gather<1>(A, U, pold, ov);
-            A.own(U, pold, oo);
+            own_of(A, U, ov, pold, oo);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -685,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const typename Op::rea
         real zv[NB][V], ro[V], zo[V];
         W.template gather<0>(A, U, (const real *)z, zv);
         A.own(U, r, ro);
-        A.own(U, (const real *)z, zo);
+        own_of(A, U, zv, (const real *)z, zo);
         bool any = false;
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -773,11 +798,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_init2(Op A, const typename Op::re
         W.load(A, U);
         real rv[NB][V], ro[V], zo[V], wo[V];
         W.template gather<0>(A, U, r, rv);
-        A.own(U, r, ro);
+        own_of(A, U, rv, r, ro);
         if (kPc == 1) {
             real dv[NB][V], dd[V];
             W.template gather<1>(A, U, A.diag_ptr(), dv);
-            A.diag(U, dd);
+            diag_of(A, U, dd);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -883,14 +908,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
         real rv[NB][V], wv[NB][V], ro[V], wo[V], xo[V], po[V], so[V], dd[V];
         W.template gather<0>(A, U, r_cur, rv);
         W.template gather<1>(A, U, w_cur, wv);
-        A.own(U, r_cur, ro);
-        A.own(U, w_cur, wo);
+        own_of(A, U, rv, r_cur, ro);
+        own_of(A, U, wv, w_cur, wo);
         A.own(U, (const real *)x, xo);
-        if (kPc == 1) A.diag(U, dd);
+        if (kPc == 1) diag_of(A, U, dd);
         if (j > 0) {
             real sv[NB][V];
             W.template gather<2>(A, U, s_old, sv);
-            A.own(U, s_old, so);
+            own_of(A, U, sv, s_old, so);
             A.own(U, (const real *)p, po);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
