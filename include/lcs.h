@@ -184,13 +184,14 @@ lcs_status lcs_set_kernel_timing(lcs_ctx *ctx, int32_t what);
 /* total milliseconds and number of timed launches since the last set */
 lcs_status lcs_get_kernel_timing(lcs_ctx *ctx, double *ms_total, int64_t *launches);
 
-/* ---- tiling of the 2-D stencil kernels ---- */
-/* The grid-sized 2-D stencil kernels (nx a multiple of 4) walk the grid in one
- * of two ways: a flat walk (each thread takes strips in turn; rows y-1 and y+1
- * are re-read from cache), or row-marching tiles, where a wavefront owns 64
- * consecutive strips of one grid row and walks up march_rows rows, keeping the
- * row below in registers, with non-temporal loads of the own-cell coefficient
- * arrays and non-temporal stores.  march_rows < 0 forces the flat walk,
+/* ---- tiling of the stencil kernels ---- */
+/* The grid-sized stencil kernels (nx a multiple of 4) walk the grid in one of
+ * two ways: a flat walk (each thread takes strips in turn; neighbour rows are
+ * re-read from cache), or row-marching tiles, where a wavefront owns 64
+ * consecutive strips of one grid row (3-D: of one plane) and walks up
+ * march_rows rows (3-D: planes), keeping the row (plane row) below in
+ * registers, with non-temporal loads of the own-cell coefficient arrays and
+ * non-temporal stores.  march_rows < 0 forces the flat walk,
  * 0 restores the automatic choice (marching once an FP64 pass streams more
  * than the 256 MB last-level cache, about 2048 tiles of at most 32 rows),
  * > 0 forces marching with that many rows; nontemporal 0 turns the

@@ -239,18 +239,18 @@ Stencil7<real> sop7(const lcs_matrix *A, const real *c) {
 struct Tuning {
     int march_rows, nontemporal;
 };
-MarchGeom march_geom(const Tuning &t, int64_t upr, int ny) {
-    int64_t h = march_strips(upr) * (int64_t)ny / 2048;
+MarchGeom march_geom(const Tuning &t, int64_t upr, int rows) {
+    int64_t h = march_strips(upr) * (int64_t)rows / 2048;
     h = std::max<int64_t>(1, std::min<int64_t>(32, h));
     if (t.march_rows > 0) h = t.march_rows;
     return {(int)h};
 }
-// Walk mode of the 2-D operators (see MarchGeom): row marching with
+// Walk mode of the stencil operators (see MarchGeom): row marching with
 // non-temporal streams once the FP64 pass (coefficients plus about six
 // vectors) exceeds the 256 MB last-level cache, else the flat walk, whose
 // repeated row reads are cache hits there.
 int walk_mode(const Tuning &t, const lcs_matrix *A, int n_arr) {
-    const double bytes = (double)A->nx * A->ny * (double)(n_arr + 6) * 8.0;
+    const double bytes = (double)A->nx * A->ny * A->nz * (double)(n_arr + 6) * 8.0;
     int m = bytes > 256.0 * 1024 * 1024 ? 2 : 0;
     if (t.march_rows < 0) m = 0;
     else if (t.march_rows > 0) m = 2;
@@ -267,10 +267,11 @@ U9<real, V, W> uop9(const Tuning &t, const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny;
     return {c, c + n, c + 2 * n, c + 3 * n, c + 4 * n, A->nx, A->ny, n, march_geom(t, A->nx / V, A->ny)};
 }
-template <typename real, int V>
-U7<real, V> uop7(const lcs_matrix *A, const real *c) {
+template <typename real, int V, int W>
+U7<real, V, W> uop7(const Tuning &t, const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
-    return {c, c + n, c + 2 * n, c + 3 * n, A->nx, A->ny, A->nz, n};
+    return {c, c + n, c + 2 * n, c + 3 * n, A->nx, A->ny, A->nz, n,
+            march_geom(t, (int64_t)A->nx * A->ny / V, A->nz)};
 }
 
 template <int W>
@@ -304,9 +305,15 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
         default: return f(s9, uop9<double, 2, 2>(t, A, A->coef), uop9<float, 4, 2>(t, A, coef32), Width<9>());
         }
     }
-    default:
-        if (v) return f(sop7<double>(A, A->coef), uop7<double, 2>(A, A->coef), uop7<float, 4>(A, coef32), Width<7>());
-        return f(sop7<double>(A, A->coef), uop7<double, 1>(A, A->coef), uop7<float, 1>(A, coef32), Width<7>());
+    default: {
+        const auto s7 = sop7<double>(A, A->coef);
+        if (!v) return f(s7, uop7<double, 1, 0>(t, A, A->coef), uop7<float, 1, 0>(t, A, coef32), Width<7>());
+        switch (walk_mode(t, A, 4)) {
+        case 0: return f(s7, uop7<double, 2, 0>(t, A, A->coef), uop7<float, 4, 0>(t, A, coef32), Width<7>());
+        case 1: return f(s7, uop7<double, 2, 1>(t, A, A->coef), uop7<float, 4, 1>(t, A, coef32), Width<7>());
+        default: return f(s7, uop7<double, 2, 2>(t, A, A->coef), uop7<float, 4, 2>(t, A, coef32), Width<7>());
+        }
+    }
     }
 }
 

@@ -254,9 +254,9 @@ __device__ __forceinline__ Band my_band(int64_t nu) {
     return {b0 + pos * kBlock + threadIdx.x, b1, per * kBlock};
 }
 
-// Row marching (2-D stencils).  A wave owns a tile: a strip of 64 units of
-// one grid row (lane l -> unit l of the strip) over mh consecutive rows, and
-// walks up the rows.  The coefficients of the row below (south faces) and the
+// Row marching.  A wave owns a tile: a strip of 64 units of one grid row
+// (lane l -> unit l of the strip; 3-D: of one plane) over mh consecutive rows
+// (3-D: planes), and walks up.  The coefficients of the row below (south faces) and the
 // rows y-1, y of every gathered vector stay in registers from the previous
 // step, so each row is fetched once per pass instead of three times.  The
 // per-cell sums are the same FMA chains as in the flat walk.
@@ -411,11 +411,22 @@ struct U5 {
     __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
         vst_sel<kNT, T, V>(p + U.i0, o);
     }
-    // geometry of unit u at column x0, row y, known to the row walk
-    __device__ __forceinline__ void geom_xy(Unit &U, int64_t u, int x0, int y) const {
+    // geometry of unit u, unit xu of grid row `row`, known to the row walk
+    __device__ __forceinline__ void geom_walk(Unit &U, int64_t u, int xu, int row) const {
         U.i0 = u * V;
-        U.x0 = x0;
-        U.y = y;
+        U.x0 = xu * V;
+        U.y = row;
+    }
+    // carried rows of a gathered vector and their shift to the next row
+    template <typename T>
+    using Carry = Rows<T, V>;
+    template <typename T>
+    __device__ __forceinline__ void rows_shift(Rows<T, V> &R) const {
+#pragma unroll
+        for (int k = 0; k < V + 2; ++k) {
+            R.s[k] = R.c[k];
+            R.c[k] = R.n[k];
+        }
     }
 };
 
@@ -627,28 +638,139 @@ struct U9 {
     __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
         vst_sel<kNT, T, V>(p + U.i0, o);
     }
-    // geometry of unit u at column x0, row y, known to the row walk
-    __device__ __forceinline__ void geom_xy(Unit &U, int64_t u, int x0, int y) const {
+    // geometry of unit u, unit xu of grid row `row`, known to the row walk
+    __device__ __forceinline__ void geom_walk(Unit &U, int64_t u, int xu, int row) const {
         U.i0 = u * V;
-        U.x0 = x0;
-        U.y = y;
+        U.x0 = xu * V;
+        U.y = row;
+    }
+    // carried rows of a gathered vector and their shift to the next row
+    template <typename T>
+    using Carry = Rows<T, V>;
+    template <typename T>
+    __device__ __forceinline__ void rows_shift(Rows<T, V> &R) const {
+#pragma unroll
+        for (int k = 0; k < V + 2; ++k) {
+            R.s[k] = R.c[k];
+            R.c[k] = R.n[k];
+        }
     }
 };
 
-template <typename real_, int V_>
+template <typename real_, int V_, int W_>
 struct U7 {
     using real = real_;
     static constexpr int V = V_, NB = 7, kC = 3;
-    static constexpr bool kMarch = false, kCenter = true;
+    static constexpr bool kMarch = W_ > 0, kNT = W_ == 2, kCenter = true;
     const real *C, *E, *N, *Up;
     int nx, ny, nz;
     int64_t n;
+    MarchGeom mg;
     struct Unit {
         int64_t i0;
         int x0, y, z;
         real a[NB][V];
     };
     __host__ __device__ int64_t units() const { return n / V; }
+    // Marching goes up the planes: a tile is 64 strips of one plane (lanes
+    // cover grid rows y of the plane) over mh planes.  Carried: the rows of
+    // planes z-1, z at this (y) and the Up coefficients of plane z-1; the
+    // in-plane neighbour rows y-1, y+1 are loaded at every step (they are the
+    // own rows of the neighbouring lanes / wavefronts at the same step).
+    __host__ __device__ int64_t upr() const { return (int64_t)nx * ny / V; }
+    __host__ __device__ int rows() const { return nz; }
+    __host__ __device__ int64_t tiles() const {
+        return march_strips(upr()) * (int64_t)((nz + mg.mh - 1) / mg.mh);
+    }
+    __device__ __forceinline__ void geom_walk(Unit &U, int64_t u, int xu, int row) const {
+        const int upx = nx / V;
+        U.i0 = u * V;
+        U.y = xu / upx;
+        U.x0 = (xu - U.y * upx) * V;
+        U.z = row;
+    }
+    struct South {
+        real ud[V];   // Up of plane z-1 (the face below)
+    };
+    __device__ __forceinline__ void south_init(South &S, const Unit &U) const {
+        const int64_t pl = (int64_t)nx * ny;
+        const bool d = U.z > 0;
+        real t[V];
+        vld<real, V>(Up + (d ? U.i0 - pl : U.i0), t);
+#pragma unroll
+        for (int k = 0; k < V; ++k) S.ud[k] = d ? t[k] : real(0);
+    }
+    __device__ __forceinline__ void load_row(Unit &U, South &S) const {
+        const int64_t i0 = U.i0;
+        const bool s = U.y > 0;
+        real c[V], e[V], nn[V], uu[V], ts[V];
+        vld_sel<kNT, real, V>(C + i0, c);
+        vld_sel<kNT, real, V>(E + i0, e);
+        vld<real, V>(N + i0, nn);
+        vld_sel<kNT, real, V>(Up + i0, uu);
+        vld<real, V>(N + (s ? i0 - nx : i0), ts);
+        real ex[V + 1];   // E at columns x0-1 .. x0+V-1
+        ex[0] = U.x0 > 0 ? E[i0 - 1] : real(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) ex[k + 1] = e[k];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            U.a[0][k] = S.ud[k];
+            U.a[1][k] = s ? ts[k] : real(0);
+            U.a[2][k] = ex[k];
+            U.a[3][k] = c[k];
+            U.a[4][k] = e[k];
+            U.a[5][k] = nn[k];
+            U.a[6][k] = uu[k];
+            S.ud[k] = uu[k];
+        }
+    }
+    template <typename T>
+    struct Carry {
+        T s[V + 2], c[V + 2], n[V + 2];   // planes z-1, z, z+1 at this (y)
+        T ys[V], yn[V];                   // rows y-1, y+1 of plane z
+    };
+    template <typename T>
+    __device__ __forceinline__ void rows_init(Carry<T> &R, const T *__restrict__ v, const Unit &U) const {
+        const int64_t pl = (int64_t)nx * ny;
+        row_load<T, V>(v, U.i0 - pl, U.i0, U.x0, nx, U.z > 0, false, R.s);
+        row_load<T, V>(v, U.i0, U.i0, U.x0, nx, true, true, R.c);
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_next(Carry<T> &R, const T *__restrict__ v, const Unit &U) const {
+        const int64_t pl = (int64_t)nx * ny;
+        row_load<T, V>(v, U.i0 + pl, U.i0, U.x0, nx, U.z < nz - 1, true, R.n);
+        const bool s = U.y > 0, no = U.y < ny - 1;
+        T a[V], b[V];
+        vld<T, V>(v + (s ? U.i0 - nx : U.i0), a);
+        vld<T, V>(v + (no ? U.i0 + nx : U.i0), b);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            R.ys[k] = s ? a[k] : T(0);
+            R.yn[k] = no ? b[k] : T(0);
+        }
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_slots(const Carry<T> &R, T (&o)[NB][V]) const {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o[0][k] = R.s[k + 1];
+            o[1][k] = R.ys[k];
+            o[2][k] = R.c[k];
+            o[3][k] = R.c[k + 1];
+            o[4][k] = R.c[k + 2];
+            o[5][k] = R.yn[k];
+            o[6][k] = R.n[k + 1];
+        }
+    }
+    template <typename T>
+    __device__ __forceinline__ void rows_shift(Carry<T> &R) const {
+#pragma unroll
+        for (int k = 0; k < V + 2; ++k) {
+            R.s[k] = R.c[k];
+            R.c[k] = R.n[k];
+        }
+    }
     __device__ __forceinline__ void geom(Unit &U, int64_t u) const {
         U.i0 = u * V;
         const int64_t pl = (int64_t)nx * ny;
@@ -740,7 +862,7 @@ struct U7 {
     }
     template <typename T>
     __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
-        vst<T, V>(p + U.i0, o);
+        vst_sel<kNT, T, V>(p + U.i0, o);
     }
 };
 
@@ -822,16 +944,16 @@ struct RowWalk {
     using Unit = typename Op::Unit;
     static constexpr int V = Op::V;
     int64_t u, upr, t, tiles, strips;
-    int left, mh, ny, y, x0;
+    int left, mh, nrows, row, xu;
     int fresh;
     typename Op::South S;
-    Rows<real, V> R[NG > 0 ? NG : 1];
+    typename Op::template Carry<real> R[NG > 0 ? NG : 1];
     __device__ __forceinline__ explicit RowWalk(const Op &a) {
         upr = a.upr();
         strips = march_strips(upr);
         tiles = a.tiles();
         mh = a.mg.mh;
-        ny = a.rows();
+        nrows = a.rows();
         t = (int64_t)logical_block() * kWaves + threadIdx.x / kWave;
         start();
     }
@@ -840,20 +962,20 @@ struct RowWalk {
         left = 0;
         for (; t < tiles; t += (int64_t)gridDim.x * kWaves) {
             const int64_t strip = t % strips, seg = t / strips;
-            const int64_t xu = strip * kWave + lane;
-            if (xu >= upr) continue;
-            y = (int)seg * mh;
-            x0 = (int)xu * V;
-            left = min(mh, ny - y);
-            u = (int64_t)y * upr + xu;
+            const int64_t x = strip * kWave + lane;
+            if (x >= upr) continue;
+            row = (int)seg * mh;
+            xu = (int)x;
+            left = min(mh, nrows - row);
+            u = (int64_t)row * upr + x;
             fresh = 1;
             return;
         }
     }
     __device__ __forceinline__ bool valid() const { return left > 0; }
-    __device__ __forceinline__ void geom(const Op &A, Unit &U) const { A.geom_xy(U, u, x0, y); }
+    __device__ __forceinline__ void geom(const Op &A, Unit &U) const { A.geom_walk(U, u, xu, row); }
     __device__ __forceinline__ void load(const Op &A, Unit &U) {
-        A.geom_xy(U, u, x0, y);
+        A.geom_walk(U, u, xu, row);
         if (fresh) A.south_init(S, U);
         A.load_row(U, S);
     }
@@ -861,20 +983,16 @@ struct RowWalk {
     __device__ __forceinline__ void gather(const Op &A, const Unit &U, const real *__restrict__ v,
                                            real (&o)[Op::NB][Op::V]) {
         static_assert(j < NG, "gather stream index out of range");
-        Rows<real, V> &r = R[j];
+        auto &r = R[j];
         if (fresh) A.rows_init(r, v, U);
         A.rows_next(r, v, U);
         A.rows_slots(r, o);
-#pragma unroll
-        for (int k = 0; k < V + 2; ++k) {
-            r.s[k] = r.c[k];
-            r.c[k] = r.n[k];
-        }
+        A.rows_shift(r);
     }
     __device__ __forceinline__ void advance() {
         fresh = 0;
         u += upr;
-        ++y;
+        ++row;
         if (--left == 0) {
             t += (int64_t)gridDim.x * kWaves;
             start();

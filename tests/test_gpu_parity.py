@@ -80,9 +80,9 @@ def make_case(name, seed=0, dt=4.0):
     return kind, (nx, ny, nz), coef, Ah, A, b, x0
 
 
-# Tilings of the 2-D stencil kernels: the automatic one (one-row tiles at
-# these sizes), and 5-row marching tiles (a partial last tile, rows carried in
-# registers) with non-temporal coefficient loads.
+# Tilings of the stencil kernels: the automatic one (the flat walk at these
+# sizes), and 5-row (3-D: 5-plane) marching tiles (a partial last tile, rows
+# carried in registers) with non-temporal coefficient loads.
 TILINGS = {"auto": (0, -1), "rows5_nt": (5, 1)}
 
 
@@ -366,12 +366,13 @@ def test_argument_errors(ctx):
     assert e.value.status == lcs.EINVAL
 
 
-@pytest.mark.parametrize("name", ["5pt_v", "9pt_v"])
+@pytest.mark.parametrize("name", ["5pt_v", "9pt_v", "7pt_v"])
 @pytest.mark.parametrize("rows,nt", [(-1, -1), (3, 0), (7, 1), (200, 1)])
 def test_walks_agree_bitwise(name, rows, nt):
-    """Every walk of the 2-D kernels (flat; marching with and without the
-    non-temporal hints; tiles taller than the grid) gives the oracle's per-row
-    results bit for bit, and Algorithm 1 meets the criterion."""
+    """Every walk of the stencil kernels (flat; marching up rows or planes
+    with and without the non-temporal hints; tiles taller than the grid) gives
+    the oracle's per-row results bit for bit, and Algorithm 1 meets the
+    criterion."""
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
     say("walk", name, rows, nt)
     c = lcs.Context()
