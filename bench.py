@@ -65,6 +65,9 @@ def parse():
     p.add_argument("--skip-spmv-hbm", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 512 MiB device copy (traffic-counter calibration)")
+    p.add_argument("--param-sweep", action="store_true",
+                   help="sweep the gradient threshold alpha (1 .. 1e-11) and E_max (0 .. 6) on the "
+                        "workload's sequence and exit")
     p.add_argument("--tiling-sweep", action="store_true",
                    help="time the 4096^2 nine-point FP32 SpMV under each walk / tiling and exit")
     p.add_argument("--summarize", metavar="DIR",
@@ -176,6 +179,85 @@ def summarize(d: str, steps: int):
     print("\n".join(out))
 
 
+def setup_sequence(workload: str):
+    """Operator, context, options and the evolved sequence (untimed): X[k] is
+    x_(k-1) and Bs[k] is b_k of system k, resident on the GPU."""
+    import torch
+    from paper_2001_01158_amd import lcs
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    w, okw, desc, src = make_workload(workload)
+    log(f"workload {w.name} N={w.n} systems={w.n_systems}")
+    A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
+                              with32=okw["precision"] == "mixed")
+    ctx = lcs.Context()
+    opts = lcs.Options(eps=1e-10, n_smooth=1, check_every=8, **okw)
+    X = [torch.zeros(w.n, dtype=torch.float64, device=dev)]
+    Bs = []
+    for k in range(w.n_systems):
+        q = torch.as_tensor(src(k)).to(dev)
+        b = X[-1] * (1.0 / w.dt) + q
+        x = X[-1].clone()
+        lcs.solve_global(A, b, x, opts, ctx=ctx)
+        Bs.append(b)
+        X.append(x)
+    torch.cuda.synchronize()
+    log("sequence ready")
+    return w, okw, desc, A, ctx, opts, X, Bs
+
+
+def param_sweep(workload: str, steps: int):
+    """The paper's parameter studies on this sequence: the gradient threshold
+    alpha of Algorithm 2 from 1 to 1e-11 (Section 3.5.1) and the expansion
+    limit E_max of Algorithm 3 from 0 to 6 (Section 3.5.2), each against the
+    global PCG from the same x^(0).  Reports ms per system, eta = K/N, and in
+    how many systems x~ met the criterion without a global finish."""
+    import torch
+    from paper_2001_01158_amd import lcs
+    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(workload)
+    x = torch.empty(w.n, dtype=torch.float64, device="cuda:0")
+
+    def leg(call):
+        sts = []
+        for s in range(2):
+            x.copy_(X[s % w.n_systems])
+            call(s % w.n_systems)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            k = s % w.n_systems
+            x.copy_(X[k])
+            sts.append(call(k))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, sts
+
+    ms_g, _ = leg(lambda k: lcs.solve_global(A, Bs[k], x, opts, ctx=ctx))
+    print(f"{desc}; {steps} systems per setting; global PCG {ms_g:.3f} ms per system\n")
+
+    def table(title, rows):
+        print(f"| {title} | ms per system | speedup | eta | local + global its | x~ met the criterion |")
+        print("|---|---|---|---|---|---|")
+        for label, (ms, sts) in rows:
+            eta = np.mean([s.K for s in sts]) / w.n
+            met = sum(s.its_global == 0 for s in sts)
+            its = f"{np.mean([s.its_local for s in sts]):.1f} + {np.mean([s.its_global for s in sts]):.1f}"
+            print(f"| {label} | {ms:.3f} | {ms_g / ms:.2f} | {100 * eta:.2f} % | {its} | {met} / {len(sts)} |",
+                  flush=True)
+        print()
+
+    rows = []
+    for e in range(0, 12):
+        alpha = 10.0 ** (-e)
+        rows.append((f"{alpha:.0e}", leg(lambda k: lcs.solve_local_then_global(
+            A, Bs[k], x, "gradient", "relmax", alpha, 0, opts, ctx=ctx))))
+    table("gradient, alpha", rows)
+    rows = []
+    for e_max in range(0, 7):
+        rows.append((str(e_max), leg(lambda k: lcs.solve_local_then_global(
+            A, Bs[k], x, "residual", "paper", opts.eps, e_max, opts, ctx=ctx))))
+    table("residual (paper threshold), E_max", rows)
+
+
 def tiling_sweep():
     """The 4096^2 nine-point FP32 SpMV under each walk of the 2-D kernels
     (lcs_set_tiling): flat, and row marching with and without the
@@ -216,6 +298,9 @@ def main():
     if args.tiling_sweep:
         tiling_sweep()
         return
+    if args.param_sweep:
+        param_sweep(args.workload, args.steps)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; sharding across GPUs is a design "
                                    "description only (DESIGN.md section 9)", "n_gpus": args.gpus}))
@@ -224,30 +309,10 @@ def main():
     from paper_2001_01158_amd import lcs, workloads as W
 
     dev = "cuda:0"
-    torch.cuda.set_device(0)
-    w, okw, desc, src = make_workload(args.workload)
+    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload)
     n = w.n
-    log(f"workload {w.name} N={n} systems={w.n_systems}")
-    A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
-                              with32=okw["precision"] == "mixed")
-    ctx = lcs.Context()
     stream = torch.cuda.current_stream()
-    inv_dt = 1.0 / w.dt
-    eps = 1e-10
-    opts = lcs.Options(eps=eps, n_smooth=1, check_every=8, **okw)
-
-    # ---- setup: evolve the sequence (untimed) ----
-    X = [torch.zeros(n, dtype=torch.float64, device=dev)]          # X[k] = x_{k-1}
-    Bs = []
-    for k in range(w.n_systems):
-        q = torch.as_tensor(src(k)).to(dev)
-        b = X[-1] * inv_dt + q
-        x = X[-1].clone()
-        lcs.solve_global(A, b, x, opts, ctx=ctx)
-        Bs.append(b)
-        X.append(x)
-    torch.cuda.synchronize()
-    log("sequence ready")
+    eps = opts.eps
     x = torch.empty(n, dtype=torch.float64, device=dev)
 
     def one(kind, k):

@@ -92,6 +92,7 @@ def lib():
         L.orc_solve_local.argtypes = [I64, P, P, P, P, P, P, I64, P, I32, P, P]
         L.orc_assemble_logk.argtypes = [I32, I32, I32, I32, D, P, P]
         L.orc_grad_logk.argtypes = [I32, I32, I32, I32, P, P, P, P]
+        L.orc_heat_assemble.argtypes = [I32, I32, D, D, D, D, P, P, P, P]
         _lib = L
     return _lib
 
@@ -325,3 +326,15 @@ def grad_logk(kind: int, nx: int, ny: int, nz: int, logk, x, lam) -> np.ndarray:
     if st != OK:
         raise ValueError(f"orc_grad_logk status {st}")
     return g
+
+
+def heat_assemble(nx: int, ny: int, inv_dt: float, power: float, tl: float, tr: float, tlin, told):
+    """Picard system of the 2-D heat-conduction test (Section 3.1):
+    (coef [3, N] of A with k = T_lin^power, b from T_old)."""
+    tlin, told = _f64(tlin).reshape(-1), _f64(told).reshape(-1)
+    n = nx * ny
+    coef, b = np.empty(3 * n), np.empty(n)
+    st = lib().orc_heat_assemble(nx, ny, inv_dt, power, tl, tr, _p(tlin), _p(told), _p(coef), _p(b))
+    if st != OK:
+        raise ValueError(f"orc_heat_assemble status {st}")
+    return coef.reshape(3, n), b

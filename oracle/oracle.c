@@ -22,8 +22,10 @@
  * Parity pins (see the CPU tests): the worked Example 1 (Section 2.3,
  * Table "extension process"), the five-point closed form of the gradient
  * (Section 2.2), dense direct solves, manufactured solutions, CG's finite
- * termination, brute-force set definitions and the adjoint's dense
- * derivative.  No function here is "parity unpinned".
+ * termination, brute-force set definitions, the adjoint's dense
+ * derivative, and for the heat-conduction assembly the exactness of the
+ * finite-volume scheme on linear profiles and its constant-coefficient limit.
+ * No function here is "parity unpinned".
  */
 #include <math.h>
 #include <stdint.h>
@@ -562,5 +564,52 @@ int orc_grad_logk(int kind, int nx, int ny, int nz, const double *logk, const do
                 }
                 grad[p] = -s;
             }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* 2-D nonlinear heat conduction test problem (Section 3.1)            */
+/* ------------------------------------------------------------------ */
+/* Picard system of dT/dt = div(k(T) grad T) on the unit square, k = T^power,
+ * T = tl at x = 0 and T = tr at x = 1, zero flux at y = 0 and y = 1, backward
+ * Euler (eq. picard-equs).  Reading (the paper says only "five-point finite
+ * difference"): cell-centred finite volumes, nx x ny cells of width
+ * h = 1/nx, the equation multiplied by h^2, so
+ *   A = I h^2/dt + sum_faces t_f (e_P - e_Q)(e_P - e_Q)^T + Dirichlet faces,
+ *   t_f = 2 k_P k_Q / (k_P + k_Q) (lower index first) for interior faces,
+ *   t_b = 2 * (2 k_b k_P / (k_b + k_P)) on an x boundary face (half a cell to
+ *         the boundary value), k_b = k(tl) or k(tr), with b gaining t_b T_b;
+ *   b = T_old h^2/dt + boundary terms.
+ * k(T) = exp(power * log(T)).  Diagonal sums in the order inv_dt, west,
+ * east, south, north.  coef = [C, E, N] (symmetric storage). */
+static double orc_kpow(double t, double power) { return exp(power * log(t)); }
+static double orc_harm(double a, double b) { return 2.0 * a * b / (a + b); }
+
+int orc_heat_assemble(int nx, int ny, double inv_dt, double power, double tl, double tr,
+                      const double *tlin, const double *told, double *coef, double *b) {
+    if (nx < 1 || ny < 1) return ORC_EINVAL;
+    int64_t n = (int64_t)nx * ny;
+    double kl = orc_kpow(tl, power), kr = orc_kpow(tr, power);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            int64_t p = x + (int64_t)nx * y;
+            double kp = orc_kpow(tlin[p], power);
+            double tw = x > 0 ? orc_harm(orc_kpow(tlin[p - 1], power), kp) : 2.0 * orc_harm(kl, kp);
+            double te = x < nx - 1 ? orc_harm(kp, orc_kpow(tlin[p + 1], power)) : 2.0 * orc_harm(kp, kr);
+            double ts = y > 0 ? orc_harm(orc_kpow(tlin[p - nx], power), kp) : 0.0;
+            double tn = y < ny - 1 ? orc_harm(kp, orc_kpow(tlin[p + nx], power)) : 0.0;
+            double d = inv_dt;
+            d += tw;
+            d += te;
+            d += ts;
+            d += tn;
+            coef[p] = d;
+            coef[n + p] = x < nx - 1 ? -te : 0.0;
+            coef[2 * n + p] = y < ny - 1 ? -tn : 0.0;
+            double r = told[p] * inv_dt;
+            if (x == 0) r += tw * tl;
+            if (x == nx - 1) r += te * tr;
+            b[p] = r;
+        }
     return ORC_OK;
 }

@@ -413,3 +413,70 @@ def test_adjoint_gradient_vs_dense_finite_differences():
         e = np.zeros(nx * ny); e[p] = h
         fd = (loss(logk.reshape(ny, nx), b + e) - loss(logk.reshape(ny, nx), b - e)) / (2 * h)
         assert abs(lam[p] - fd) <= 1e-7 * max(1.0, abs(fd))
+
+
+# ----------------------------------------------------------------------------
+# 2-D nonlinear heat-conduction test problem (Section 3.1): Picard assembly
+# ----------------------------------------------------------------------------
+def _heat_case(nx=11, ny=7, seed=3):
+    rng = np.random.default_rng(seed)
+    t = 1e-4 + rng.random(nx * ny)            # positive temperatures
+    told = 1e-4 + rng.random(nx * ny)
+    return t, told
+
+
+def test_heat_assembly_constant_conductivity_limit():
+    """power = 0 (k = 1): the interior operator is the generic five-point
+    assembly with unit conductivity, and each x boundary face adds the
+    half-cell transmissibility 2 to the diagonal and 2 T_b to the rhs."""
+    nx, ny, inv_dt, tl, tr = 11, 7, 0.37, 1.0, 0.25
+    t, told = _heat_case(nx, ny)
+    coef, b = oracle.heat_assemble(nx, ny, inv_dt, 0.0, tl, tr, t, told)
+    ref = W.assemble_5pt(np.zeros((ny, nx)), inv_dt).reshape(3, ny, nx).copy()
+    ref[0][:, 0] += 2.0
+    ref[0][:, -1] += 2.0
+    np.testing.assert_array_equal(coef, ref.reshape(3, -1))
+    rb = (told * inv_dt).reshape(ny, nx).copy()
+    rb[:, 0] += 2.0 * tl
+    rb[:, -1] += 2.0 * tr
+    np.testing.assert_allclose(b, rb.reshape(-1), rtol=1e-15, atol=0)
+
+
+def test_heat_assembly_exact_on_linear_steady_profile():
+    """The finite-volume scheme with Dirichlet faces half a cell away is exact
+    for the linear profile between T_l and T_r: (A - I/dt) T = boundary rhs."""
+    nx, ny, inv_dt, tl, tr = 13, 5, 0.2, 1.0, 1e-4
+    x = (np.arange(nx) + 0.5) / nx
+    prof = np.tile(tl + (tr - tl) * x, ny)
+    coef, b = oracle.heat_assemble(nx, ny, inv_dt, 0.0, tl, tr, prof, np.zeros(nx * ny))
+    A = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, coef)
+    lhs = oracle.spmv(A, prof) - inv_dt * prof
+    np.testing.assert_allclose(lhs, b, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("power", [3.5, 1.0])
+def test_heat_assembly_symmetric_m_matrix_and_row_sums(power):
+    """k = T^power: A is symmetric with non-positive off-diagonals and strictly
+    dominant diagonal; A 1 = 1/dt + (Dirichlet transmissibility), and the
+    boundary rhs term is that transmissibility times T_b."""
+    # moderate temperatures: with T_r = 1e-4 the right boundary term (k ~ 1e-14)
+    # would vanish under the rounding of the row sum
+    nx, ny, inv_dt, tl, tr = 9, 8, 0.05, 1.0, 0.5
+    t, told = _heat_case(nx, ny, seed=5)
+    t = 0.5 + t
+    coef, b = oracle.heat_assemble(nx, ny, inv_dt, power, tl, tr, t, told)
+    A = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, coef).dense()
+    assert np.array_equal(A, A.T)
+    off = A - np.diag(np.diag(A))
+    assert (off <= 0).all()
+    assert (np.diag(A) - np.abs(off).sum(1) >= inv_dt * (1 - 1e-12)).all()
+    extra = (A.sum(1) - inv_dt).reshape(ny, nx)
+    src = (b - told * inv_dt).reshape(ny, nx)
+    np.testing.assert_allclose(extra[:, 1:-1], 0.0, atol=1e-12)
+    np.testing.assert_allclose(src[:, 1:-1], 0.0, atol=0)
+    np.testing.assert_allclose(src[:, 0], extra[:, 0] * tl, rtol=1e-12)
+    np.testing.assert_allclose(src[:, -1], extra[:, -1] * tr, rtol=1e-12)
+    # the interior face between cells p, q is the harmonic mean of T_p^power, T_q^power
+    k = t ** power
+    p = 3 + nx * 2
+    np.testing.assert_allclose(-A[p, p + 1], 2 * k[p] * k[p + 1] / (k[p] + k[p + 1]), rtol=1e-13)
