@@ -70,6 +70,10 @@ def parse():
                         "workload's sequence and exit")
     p.add_argument("--tiling-sweep", action="store_true",
                    help="time the 4096^2 nine-point FP32 SpMV under each walk / tiling and exit")
+    p.add_argument("--heat", type=int, metavar="N",
+                   help="run the 2-D nonlinear heat-conduction test (Section 3.1) on N x N cells with "
+                        "the three methods and exit")
+    p.add_argument("--heat-steps", type=int, default=100, help="time steps of --heat (paper: 100)")
     p.add_argument("--summarize", metavar="DIR",
                    help="print a summary of rocprofv3 output under DIR (trace/, fetch/, write/) "
                         "and exit; no GPU needed")
@@ -290,8 +294,78 @@ def tiling_sweep():
               f"{n3 * n3 * 28 / us / 1e3:.0f} |", flush=True)
 
 
+def heat_run(n: int, steps: int):
+    """The 2-D nonlinear heat-conduction test of Section 3.1 on n x n cells:
+    the global PCG (M0), the gradient-domain method (M1, alpha = 1e-4) and the
+    residual-domain method (M2, E_max = 1) each advance their own simulation
+    by backward Euler and Picard iteration, in lockstep so that the solutions
+    can be compared at every time step (e_1^0, e_2^0 of the paper).  Times are
+    those of the linear solves only (as the paper's CPU_total), each solve
+    synchronised.  Prints a markdown report."""
+    import torch
+    from paper_2001_01158_amd import lcs
+    from paper_2001_01158_amd.heat2d import Heat2D, METHODS
+    torch.cuda.set_device(0)
+    N = n * n
+    # warm-up: one time step of each method on a throwaway simulation
+    for m in METHODS:
+        Heat2D(n, m).step()
+    torch.cuda.synchronize()
+    sims = {m: Heat2D(n, m, ctx=lcs.Context()) for m in METHODS}
+    recs = {m: [] for m in METHODS}
+    e = {"gradient": [], "residual": []}
+    zero = torch.zeros(N, dtype=torch.float64, device="cuda:0")
+    t_start = time.perf_counter()
+    for k in range(steps):
+        for m in METHODS:
+            recs[m].append(sims[m].step())
+        t0 = sims["global"].T
+        nt0 = lcs.norm2_diff(t0, zero)
+        for m in e:
+            e[m].append(lcs.norm2_diff(sims[m].T, t0) / nt0)
+        if k % 5 == 4 or k == steps - 1:
+            last = {m: recs[m][-1] for m in METHODS}
+            log(f"heat {n}^2 step {k + 1}/{steps}: picard " +
+                " ".join(f"{m}={len(last[m])}" for m in METHODS) +
+                f"; eta M1={np.mean([r.K for r in last['gradient']]) / N:.3f} "
+                f"M2={np.mean([r.K for r in last['residual']]) / N:.3f}; "
+                f"e1={e['gradient'][-1]:.1e} e2={e['residual'][-1]:.1e}; "
+                f"{time.perf_counter() - t_start:.0f} s")
+    flat = {m: [r for step in recs[m] for r in step] for m in METHODS}
+    tot = {m: sum(r.ms for r in flat[m]) for m in METHODS}
+    avg = {m: tot[m] / len(flat[m]) for m in METHODS}
+    label = {"global": "M0 (global PCG)", "gradient": "M1 (gradient, alpha 1e-4)",
+             "residual": "M2 (residual, E_max 1)"}
+    print(f"### 2-D nonlinear heat conduction, {n} x {n} cells, {steps} time steps, dt = 1e-2\n")
+    print("| method | systems (N_eq) | total solve s | ms per system | S (per system) | "
+          "mean eta | local its per system | global its per system |")
+    print("|---|---|---|---|---|---|---|---|")
+    for m in METHODS:
+        f = flat[m]
+        eta = "-" if m == "global" else f"{100 * np.mean([r.K for r in f]) / N:.2f} %"
+        sp = "-" if m == "global" else f"{avg['global'] / avg[m]:.2f}"
+        print(f"| {label[m]} | {len(f)} | {tot[m] / 1e3:.3f} | {avg[m]:.3f} | {sp} | {eta} | "
+              f"{np.mean([r.its_local for r in f]):.1f} | {np.mean([r.its_global for r in f]):.1f} |")
+    print(f"\nmax over the steps: e1 = {max(e['gradient']):.2e}, e2 = {max(e['residual']):.2e} "
+          "(||T_Mi - T_M0||_2 / ||T_M0||_2)\n")
+    marks = sorted({min(steps, s) for s in (1, steps // 4, steps // 2, 3 * steps // 4, steps) if s > 0})
+    print("| time step | Picard M0 / M1 / M2 | eta M1 | eta M2 | S M1 | S M2 |")
+    print("|---|---|---|---|---|---|")
+    for s in marks:
+        st = {m: recs[m][s - 1] for m in METHODS}
+        a = {m: np.mean([r.ms for r in st[m]]) for m in METHODS}
+        print(f"| {s} | {len(st['global'])} / {len(st['gradient'])} / {len(st['residual'])} | "
+              f"{100 * np.mean([r.K for r in st['gradient']]) / N:.2f} % | "
+              f"{100 * np.mean([r.K for r in st['residual']]) / N:.2f} % | "
+              f"{a['global'] / a['gradient']:.2f} | {a['global'] / a['residual']:.2f} |", flush=True)
+    print()
+
+
 def main():
     args = parse()
+    if args.heat:
+        heat_run(args.heat, args.heat_steps)
+        return
     if args.summarize:
         summarize(args.summarize, args.steps)
         return

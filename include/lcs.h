@@ -136,7 +136,11 @@ lcs_status lcs_solve_local(lcs_ctx *ctx, const lcs_matrix *A, const double *b, d
                            lcs_stats *st, void *stream);
 
 /* Algorithm 1: build Omega, solve locally, smooth, check, and finish with the
- * global PCG from x~ when needed.  x: in x^(0), out solution. */
+ * global PCG from x~ when needed.  x: in x^(0), out solution.  An x^(0) that
+ * already meets the criterion ||b - A x^(0)||_2 <= eps ||b||_2 (eq.
+ * rel-res-conv-criteria) is the solution and is returned unchanged: no local
+ * solve, no smoothing, K = its_local = its_global = 0 (the global PCG does the
+ * same with such an x^(0)). */
 lcs_status lcs_solve_local_then_global(lcs_ctx *ctx, const lcs_matrix *A, const double *b,
                                        double *x, int32_t mode, int32_t thresh_kind,
                                        double theta, int32_t e_max, const lcs_options *o,
@@ -210,6 +214,23 @@ lcs_status lcs_assemble_logk(lcs_ctx *ctx, int32_t kind, int32_t nx, int32_t ny,
 lcs_status lcs_grad_logk(lcs_ctx *ctx, int32_t kind, int32_t nx, int32_t ny, int32_t nz,
                          const double *logk, const double *x, const double *lam,
                          double *grad, void *stream);
+
+/* ---- the 2-D heat-conduction test problem (Section 3.1) ---- */
+/* Picard system (eq. picard-equs) of dT/dt = div(k(T) grad T) with
+ * k = T^power, T = t_left at x = 0, T = t_right at x = 1, zero flux at the
+ * y faces: cell-centred finite volumes on nx x ny square cells of side
+ * h = 1/nx (the unit square when ny = nx), scaled by h^2 (inv_dt = h^2/dt).  coef [3 x N] (C, E, N, the
+ * 5-point layout of lcs_matrix) from k(t_lin); b [N] = t_old inv_dt plus the
+ * Dirichlet terms.  Interior faces (k_P + k_Q) / 2; Dirichlet faces half a
+ * cell away: 2 * (k_b + k_P) / 2, b += that * T_b.
+ * Temperatures must be > 0 (k = exp(power log T)).  All arrays device. */
+lcs_status lcs_assemble_heat(lcs_ctx *ctx, int32_t nx, int32_t ny, double inv_dt, double power,
+                             double t_left, double t_right, const double *t_lin,
+                             const double *t_old, double *coef, double *b, void *stream);
+/* *out (host) = ||a - b||_2 over n entries (device arrays); synchronises the
+ * stream.  The nonlinear (Picard) stopping test of the same section. */
+lcs_status lcs_norm2_diff(lcs_ctx *ctx, const double *a, const double *b, int64_t n, double *out,
+                          void *stream);
 
 #ifdef __cplusplus
 }

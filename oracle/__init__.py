@@ -295,7 +295,21 @@ def solve_local(A: CSR, b, x0, idx, opts: Options = Options()):
 def local_then_global(A: CSR, b, x0, mode: int = MODE_RESIDUAL, theta: float = 1e-3,
                       thresh: int = TH_RELMAX, e_max: int = 1, opts: Options = Options()):
     """Algorithm 1: construct Omega, solve the local system, assemble, smooth,
-    check eq. (rel-res-conv-criteria), else finish with the global solve."""
+    check eq. (rel-res-conv-criteria), else finish with the global solve.
+
+    An x0 that already meets eq. (rel-res-conv-criteria) is the solution and
+    comes back unchanged with K = 0 and an empty domain: the paper's
+    algorithm presumes an x0 that is not yet converged, and the global solve
+    (Krylov methods generally) stops at once on such an x0."""
+    b = _f64(b)
+    x0 = _f64(x0)
+    r0n = float(np.linalg.norm(residual(A, b, x0)))
+    bn = float(np.linalg.norm(b))
+    if r0n <= opts.eps * bn:
+        rel = r0n / bn if bn > 0 else r0n
+        st = Stats(status=OK, relres_after_local=rel, relres_final=rel)
+        dom = Domain(np.zeros(0, np.int32), np.zeros(A.n, np.uint8), 0, 0, 0.0, np.zeros(A.n))
+        return x0.copy(), st, dom
     dom = build_local_domain(A, b, x0, mode, theta, thresh, e_max)
     x, sl = solve_local(A, b, x0, dom.idx, opts)
     if sl.relres_after_local <= opts.eps:

@@ -576,14 +576,17 @@ int orc_grad_logk(int kind, int nx, int ny, int nz, const double *logk, const do
  * difference"): cell-centred finite volumes, nx x ny cells of width
  * h = 1/nx, the equation multiplied by h^2, so
  *   A = I h^2/dt + sum_faces t_f (e_P - e_Q)(e_P - e_Q)^T + Dirichlet faces,
- *   t_f = 2 k_P k_Q / (k_P + k_Q) (lower index first) for interior faces,
- *   t_b = 2 * (2 k_b k_P / (k_b + k_P)) on an x boundary face (half a cell to
- *         the boundary value), k_b = k(tl) or k(tr), with b gaining t_b T_b;
+ *   t_f = (k_P + k_Q) / 2, the arithmetic mean of the two cells' k, on
+ *         interior faces (the harmonic mean would shut the face between a
+ *         hot cell and a cold one, k(1e-4) = 1e-14, and freeze the front
+ *         that the paper's local domains follow across the time steps);
+ *   t_b = 2 * (k_b + k_P) / 2 on an x boundary face (half a cell to the
+ *         boundary value), k_b = k(tl) or k(tr), with b gaining t_b T_b;
  *   b = T_old h^2/dt + boundary terms.
  * k(T) = exp(power * log(T)).  Diagonal sums in the order inv_dt, west,
  * east, south, north.  coef = [C, E, N] (symmetric storage). */
 static double orc_kpow(double t, double power) { return exp(power * log(t)); }
-static double orc_harm(double a, double b) { return 2.0 * a * b / (a + b); }
+static double orc_mean(double a, double b) { return 0.5 * (a + b); }
 
 int orc_heat_assemble(int nx, int ny, double inv_dt, double power, double tl, double tr,
                       const double *tlin, const double *told, double *coef, double *b) {
@@ -594,10 +597,10 @@ int orc_heat_assemble(int nx, int ny, double inv_dt, double power, double tl, do
         for (int x = 0; x < nx; ++x) {
             int64_t p = x + (int64_t)nx * y;
             double kp = orc_kpow(tlin[p], power);
-            double tw = x > 0 ? orc_harm(orc_kpow(tlin[p - 1], power), kp) : 2.0 * orc_harm(kl, kp);
-            double te = x < nx - 1 ? orc_harm(kp, orc_kpow(tlin[p + 1], power)) : 2.0 * orc_harm(kp, kr);
-            double ts = y > 0 ? orc_harm(orc_kpow(tlin[p - nx], power), kp) : 0.0;
-            double tn = y < ny - 1 ? orc_harm(kp, orc_kpow(tlin[p + nx], power)) : 0.0;
+            double tw = x > 0 ? orc_mean(orc_kpow(tlin[p - 1], power), kp) : 2.0 * orc_mean(kl, kp);
+            double te = x < nx - 1 ? orc_mean(kp, orc_kpow(tlin[p + 1], power)) : 2.0 * orc_mean(kp, kr);
+            double ts = y > 0 ? orc_mean(orc_kpow(tlin[p - nx], power), kp) : 0.0;
+            double tn = y < ny - 1 ? orc_mean(kp, orc_kpow(tlin[p + nx], power)) : 0.0;
             double d = inv_dt;
             d += tw;
             d += te;

@@ -709,11 +709,13 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
 // Algorithm 2 / Algorithm 3: scores, threshold, expansion, compaction
 // ---------------------------------------------------------------------------
 // Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
-// ascending domain in idx; returns K (host).
+// ascending domain in idx; returns K (host).  eps0 >= 0: an x0 with
+// ||b - A x0|| <= eps0 ||b|| (||b|| already in dsc->bnorm) gives the empty
+// domain and hsc->ms.conv0 = 1.
 template <class SOp, class UOp>
 lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *b,
                         const double *x0, int mode, int thresh, double theta, int e_max,
-                        int32_t *idx, int64_t *K, hipStream_t s) {
+                        double eps0, int32_t *idx, int64_t *K, hipStream_t s) {
     const int64_t n = As.n;
     const Launch L = dims_for(n);
     const Tiling T = tiling_for(n);
@@ -733,7 +735,7 @@ lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *
                            slot(c, kPtScore));
     const int gmark = std::min(flat_grid(T.npad), 512);
     hipLaunchKernelGGL(k_mark, dim3(gmark), dim3(kBlock), 0, s, (const double *)score, stamp, n,
-                       T.npad, thresh, theta, (const double *)slot(c, kPtScore), gs, c->dsc);
+                       T.npad, thresh, theta, eps0, (const double *)slot(c, kPtScore), gs, c->dsc);
     LAUNCH_CHECK();
     const int ex = mode == LCS_MODE_RESIDUAL ? e_max : 0;
     for (int m = 1; m <= ex; ++m)
@@ -1048,7 +1050,7 @@ lcs_status lcs_build_local_domain(lcs_ctx *c, const lcs_matrix *A, const double 
     LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
     hipStream_t s = (hipStream_t)stream;
     return with_ops(c, A, nullptr, vec_ok({b, x0}), [&](auto sop, auto op, auto, auto) -> lcs_status {
-        LCS_TRY(build_domain(c, sop, op, b, x0, mode, thresh_kind, theta, e_max, idx, K, s));
+        LCS_TRY(build_domain(c, sop, op, b, x0, mode, thresh_kind, theta, e_max, -1.0, idx, K, s));
         if (mask) {
             uint8_t *stamp;
             LCS_TRY(get_buf(c, B_STAMP, tiling_for(sop.n).npad, &stamp));
@@ -1234,12 +1236,24 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         int32_t *idx;
         LCS_TRY(get_buf(c, B_IDX, n, &idx));
         int64_t K = 0;
-        LCS_TRY(build_domain(c, sop, op, b, (const double *)x, mode, thresh_kind, theta, e_max, idx,
-                             &K, s));
+        LCS_TRY(build_domain(c, sop, op, b, (const double *)x, mode, thresh_kind, theta, e_max,
+                             o->eps, idx, &K, s));
         st->K = K;
         st->e_rounds = c->hsc->ms.grown;
         st->tau = c->hsc->ms.tau;
         const double bn = c->hsc->bnorm;
+        if (c->hsc->ms.conv0) {
+            // x^(0) already meets the criterion: it is the solution, returned
+            // as it is (no local solve, no smoothing), as the global PCG
+            // returns an initial iterate that passes its first test
+            const double rr0 = std::sqrt(c->hsc->ms.rr0);
+            st->relres_after_local = st->relres_final = bn > 0 ? rr0 / bn : rr0;
+            LCS_TRY(tm.mark(1));
+            HIP_TRY(hipStreamSynchronize(s));
+            LCS_TRY(flush_prof(c));
+            st->ms_construct = tm.ms(0, 1);
+            return LCS_OK;
+        }
         LCS_TRY(tm.mark(1));
         double *score, *r0 = nullptr;
         int32_t *inv;
@@ -1298,6 +1312,46 @@ lcs_status lcs_get_kernel_timing(lcs_ctx *c, double *ms_total, int64_t *launches
     if (!c || !ms_total || !launches) return fail(LCS_EINVAL, "NULL argument");
     *ms_total = c->prof_ms;
     *launches = c->prof_launches;
+    return LCS_OK;
+}
+
+lcs_status lcs_assemble_heat(lcs_ctx *c, int32_t nx, int32_t ny, double inv_dt, double power,
+                             double t_left, double t_right, const double *t_lin,
+                             const double *t_old, double *coef, double *b, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    if (nx < 1 || ny < 1) return fail(LCS_EINVAL, "grid sizes");
+    if (!(t_left > 0.0) || !(t_right > 0.0)) return fail(LCS_EINVAL, "boundary temperatures must be > 0");
+    LCS_TRY(check_ptr(t_lin, "t_lin"));
+    LCS_TRY(check_ptr(t_old, "t_old"));
+    LCS_TRY(check_ptr(coef, "coef"));
+    LCS_TRY(check_ptr(b, "b"));
+    const int64_t n = (int64_t)nx * ny;
+    hipLaunchKernelGGL(k_assemble_heat, dim3(flat_grid(n)), dim3(kBlock), 0, (hipStream_t)stream,
+                       nx, ny, inv_dt, power, t_left, t_right, t_lin, t_old, coef, b);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+lcs_status lcs_norm2_diff(lcs_ctx *c, const double *a, const double *b, int64_t n, double *out,
+                          void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(LCS_EINVAL, "n < 0");
+    LCS_TRY(check_ptr(out, "out"));
+    if (n == 0) {
+        *out = 0.0;
+        return LCS_OK;
+    }
+    LCS_TRY(check_ptr(a, "a"));
+    LCS_TRY(check_ptr(b, "b"));
+    hipStream_t s = (hipStream_t)stream;
+    const Launch L = dims_for(n);
+    hipLaunchKernelGGL(k_norm2_diff, dim3(L.grid), dim3(kBlock), 0, s, a, b, n, L.chunk,
+                       slot(c, kPtNorm));
+    hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(kBlock), 0, s, (const double *)slot(c, kPtNorm),
+                       L.grid, &c->dsc->scratch_norm);
+    LAUNCH_CHECK();
+    LCS_TRY(read_scalars(c, s));
+    *out = c->hsc->scratch_norm;
     return LCS_OK;
 }
 

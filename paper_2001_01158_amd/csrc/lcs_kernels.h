@@ -25,6 +25,9 @@ struct MarkState {
     int64_t K;        // |Omega| after compaction
     int32_t stop;     // an expansion round added nothing: later rounds are no-ops
     int32_t grown;    // rounds that added points
+    double rr0;       // ||b - A x0||^2
+    int32_t conv0;    // x0 already met the criterion: nothing was marked
+    int32_t pad;
 };
 
 struct PcgState {
@@ -56,6 +59,7 @@ struct Scalars {
     int32_t saved_status[2];
     double cg_gamma[2];       // single-synchronisation PCG: r_j.z_j by iteration parity
     double cg_alpha[2];       //                             alpha_j by iteration parity
+    double scratch_norm;      // result of lcs_norm2_diff
 };
 
 // Own value of a gathered vector and the diagonal: for the stencils the
@@ -92,30 +96,33 @@ constexpr size_t kSlotElems = (size_t)kMaxGrid * 4;
 // ---------------------------------------------------------------------------
 // Residual mode: s = r^(0) = b - A x0 (FMA chain, ascending columns).
 // Gradient mode: s = g, g_i = sum_{j != i} |x_i - x_j| (eq. grad).
-// Partials: max |s_i| and ||b||^2.
+// Partials: max |s_i|, ||b||^2 and ||r^(0)||^2 (the gradient mode forms r^(0)
+// in registers for the last one).
 template <class Op, int kMode>
 __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict__ b,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ s, double *part) {
     constexpr int V = Op::V, NB = Op::NB;
-    double v[2] = {0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0};
     for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
         W.load(A, U);
-        double xv[NB][V], out[V];
+        double xv[NB][V], out[V], res[V], bb[V];
         W.template gather<0>(A, U, x, xv);
+        A.own(U, b, bb);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            double acc = bb[k];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (A.valid(U, q, k)) acc = fma(-U.a[q][k], xv[q][k], acc);
+            res[k] = acc;
+            v[1] += bb[k] * bb[k];
+            v[2] += acc * acc;
+        }
         if (kMode == 0) {
-            double bb[V];
-            A.own(U, b, bb);
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                double acc = bb[k];
-#pragma unroll
-                for (int q = 0; q < NB; ++q)
-                    if (A.valid(U, q, k)) acc = fma(-U.a[q][k], xv[q][k], acc);
-                out[k] = acc;
-                v[1] += bb[k] * bb[k];
-            }
+            for (int k = 0; k < V; ++k) out[k] = res[k];
         } else {
             double xo[V];
             own_of(A, U, xv, x, xo);
@@ -135,32 +142,38 @@ __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict
             v[0] = m > v[0] ? m : v[0];
         }
     }
-    write_partials<double, 2>(v, Ops<1u>(), part);
+    write_partials<double, 3>(v, Ops<1u>(), part);
 }
 
 // tau from the score partials: REL_MAX theta*max|s|, ABS theta,
 // PAPER theta*||b||_2/sqrt(N); then stamp_i = (|s_i| > tau) (strict), zero on
-// the padding [n, npad).
+// the padding [n, npad).  With eps0 >= 0, an x0 that already meets the
+// criterion ||r^(0)|| <= eps0 ||b|| (||b|| from sc->bnorm) marks nothing and
+// sets conv0.
 __global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
                                                  uint8_t *__restrict__ stamp, int64_t n,
                                                  int64_t npad, int thresh, double theta,
-                                                 const double *part, int gprod, Scalars *sc) {
-    double tot[2];
-    read_partials<double, 2>(part, gprod, Ops<1u>(), tot);
+                                                 double eps0, const double *part, int gprod,
+                                                 Scalars *sc) {
+    double tot[3];
+    read_partials<double, 3>(part, gprod, Ops<1u>(), tot);
     double tau;
     if (thresh == 0) tau = theta * tot[0];
     else if (thresh == 1) tau = theta;
     else tau = theta * sqrt(tot[1]) / sqrt((double)n);
+    const bool conv0 = eps0 >= 0.0 && sqrt(tot[2]) <= eps0 * sc->bnorm;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->ms.tau = tau;
         sc->ms.smax = tot[0];
         sc->ms.bb = tot[1];
+        sc->ms.rr0 = tot[2];
+        sc->ms.conv0 = conv0 ? 1 : 0;
         sc->ms.stop = 0;
         sc->ms.grown = 0;
     }
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < npad;
          i += (int64_t)gridDim.x * kBlock)
-        stamp[i] = (i < n && fabs(s[i]) > tau) ? 1 : 0;
+        stamp[i] = (!conv0 && i < n && fabs(s[i]) > tau) ? 1 : 0;
 }
 
 // One synchronous expansion round m (Algorithm 3, eq. extend-local-condition):
@@ -1029,6 +1042,18 @@ __global__ __launch_bounds__(kBlock) void k_norm2(const double *__restrict__ v, 
     write_partials<double, 1>(a, Ops<0u>(), part);
 }
 
+// ||a - b||^2 partials (chunked, like k_norm2)
+__global__ __launch_bounds__(kBlock) void k_norm2_diff(const double *__restrict__ a,
+                                                       const double *__restrict__ b, int64_t n,
+                                                       int64_t chunk, double *part) {
+    const Chunk c = my_chunk(n, chunk);
+    double s[1] = {0.0};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        const double d = a[i] - b[i];
+        s[0] += d * d;
+    }
+    write_partials<double, 1>(s, Ops<0u>(), part);
+}
 __global__ __launch_bounds__(kBlock) void k_fin_norm(const double *part, int gprod, double *out) {
     double tot[1];
     read_partials<double, 1>(part, gprod, Ops<0u>(), tot);
@@ -1131,6 +1156,47 @@ __global__ __launch_bounds__(kBlock) void k_assemble_logk(int nx, int ny, int nz
         coef[n + i] = -te;
         coef[2 * n + i] = -tn;
         if (kDim == 3) coef[3 * n + i] = -tu;
+    }
+}
+
+// Picard system of the 2-D heat-conduction test (Section 3.1, eq.
+// picard-equs): cell-centred finite volumes scaled by h^2, k = T_lin^power,
+// interior faces take the arithmetic mean (k_P + k_Q) / 2 (the harmonic mean
+// would close the faces into the cold region, k(1e-4) = 1e-14, and the front
+// could not advance), Dirichlet faces at x = 0 / x = 1 half a cell away
+// (transmissibility 2 * mean(k_b, k_P), rhs gains it times T_b), zero flux
+// in y.  One thread per cell; diagonal sums in the order 1/dt, west, east,
+// south, north.
+__device__ __forceinline__ double kpow(double t, double power) { return exp(power * log(t)); }
+__device__ __forceinline__ double face_mean(double kp, double kq) { return 0.5 * (kp + kq); }
+__global__ __launch_bounds__(kBlock) void k_assemble_heat(int nx, int ny, double inv_dt, double power,
+                                                          double tl, double tr,
+                                                          const double *__restrict__ tlin,
+                                                          const double *__restrict__ told,
+                                                          double *__restrict__ coef,
+                                                          double *__restrict__ b) {
+    const int64_t n = (int64_t)nx * ny;
+    const double kl = kpow(tl, power), kr = kpow(tr, power);
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int y = (int)(i / nx), x = (int)(i - (int64_t)y * nx);
+        const double kp = kpow(tlin[i], power);
+        const double tw = x > 0 ? face_mean(kpow(tlin[i - 1], power), kp) : 2.0 * face_mean(kl, kp);
+        const double te = x < nx - 1 ? face_mean(kp, kpow(tlin[i + 1], power)) : 2.0 * face_mean(kp, kr);
+        const double ts = y > 0 ? face_mean(kpow(tlin[i - nx], power), kp) : 0.0;
+        const double tn = y < ny - 1 ? face_mean(kp, kpow(tlin[i + nx], power)) : 0.0;
+        double d = inv_dt;
+        d += tw;
+        d += te;
+        d += ts;
+        d += tn;
+        coef[i] = d;
+        coef[n + i] = x < nx - 1 ? -te : 0.0;
+        coef[2 * n + i] = y < ny - 1 ? -tn : 0.0;
+        double r = told[i] * inv_dt;
+        if (x == 0) r += tw * tl;
+        if (x == nx - 1) r += te * tr;
+        b[i] = r;
     }
 }
 

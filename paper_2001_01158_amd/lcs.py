@@ -35,7 +35,7 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_solve_local_then_global", "lcs_residual", "lcs_gradient", "lcs_spmv",
             "lcs_gather_restricted", "lcs_gs_sweeps", "lcs_cast_coef", "lcs_assemble_logk",
             "lcs_grad_logk", "lcs_set_kernel_timing", "lcs_get_kernel_timing",
-            "lcs_set_tiling"]
+            "lcs_set_tiling", "lcs_assemble_heat", "lcs_norm2_diff"]
 TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE = range(5)
 
 
@@ -94,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lcs_set_kernel_timing": (I32, [P, I32]),
         "lcs_get_kernel_timing": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "lcs_set_tiling": (I32, [P, I32, I32]),
+        "lcs_assemble_heat": (I32, [P, I32, I32, D, D, D, D, P, P, P, P, P]),
+        "lcs_norm2_diff": (I32, [P, P, P, I64, ctypes.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -373,6 +375,31 @@ def get_kernel_timing(ctx: Context = None):
     n = ctypes.c_int64(0)
     _check(lib().lcs_get_kernel_timing(_ctx(ctx), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def assemble_heat(nx: int, ny: int, inv_dt: float, power: float, t_left: float, t_right: float,
+                  t_lin: torch.Tensor, t_old: torch.Tensor, coef: torch.Tensor = None,
+                  b: torch.Tensor = None, ctx: Context = None):
+    """Picard system of the 2-D heat-conduction test: (coef [3, N], b [N])."""
+    n = nx * ny
+    if coef is None:
+        coef = torch.empty((3, n), dtype=torch.float64, device=t_lin.device)
+    if b is None:
+        b = torch.empty(n, dtype=torch.float64, device=t_lin.device)
+    _check(lib().lcs_assemble_heat(_ctx(ctx), nx, ny, float(inv_dt), float(power), float(t_left),
+                                   float(t_right), _vec(t_lin, n, name="t_lin"),
+                                   _vec(t_old, n, name="t_old"), _vec(coef.view(-1), 3 * n, name="coef"),
+                                   _vec(b, n, name="b"), _stream()))
+    return coef, b
+
+
+def norm2_diff(a: torch.Tensor, b: torch.Tensor, ctx: Context = None) -> float:
+    """||a - b||_2 (FP64 device vectors of the same length)."""
+    n = a.numel()
+    out = ctypes.c_double(0.0)
+    _check(lib().lcs_norm2_diff(_ctx(ctx), _vec(a, n, name="a"), _vec(b, n, name="b"), n,
+                                ctypes.byref(out), _stream()))
+    return out.value
 
 
 def set_tiling(march_rows: int = 0, nontemporal: int = -1, ctx: Context = None):

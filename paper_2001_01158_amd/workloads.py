@@ -313,3 +313,23 @@ def example1():
     x0 = np.array([1.0, 1e-1] + [1.001 * 10.0 ** -(i + 1) for i in range(2, nn)])
     b = a @ x
     return a, x, x0, b
+
+
+# ---------------------------------------------------------------------------
+# 2-D nonlinear heat-conduction test problem (Section 3.1)
+# ---------------------------------------------------------------------------
+HEAT_T_LEFT = 1.0          # T at x = 0
+HEAT_T_RIGHT = 1e-4        # T at x = 1
+HEAT_POWER = 3.5           # k(T) = T^3.5
+HEAT_DT = 1e-2             # time step
+HEAT_STEPS = 100           # physical time 0 .. 1
+HEAT_PICARD_TOL = 1e-8     # ||T^(n+1,s+1) - T^(n+1,s)||_2
+HEAT_ALPHA = 1e-4          # gradient threshold of the gradient-based method
+HEAT_E_MAX = 1             # expansion rounds of the residual-based method
+
+
+def heat2d_initial(nx: int, ny: int) -> np.ndarray:
+    """T_0(x, y) = exp(-100 x) T_l + T_r at the centres of nx x ny cells of the
+    unit square, row-major (y slowest)."""
+    x = (np.arange(nx) + 0.5) / nx
+    return np.ascontiguousarray(np.tile(np.exp(-100.0 * x) * HEAT_T_LEFT + HEAT_T_RIGHT, ny))

@@ -202,6 +202,26 @@ def test_empty_and_full_domains(ctx):
     del xs
 
 
+@pytest.mark.parametrize("mode,thresh,theta", [("residual", "paper", 1e-10),
+                                               ("gradient", "relmax", 1e-4)])
+def test_converged_x0_returned_unchanged(mode, thresh, theta, ctx):
+    """x0 meeting the criterion: the solution is x0 itself, bit for bit, with
+    no local or global iteration (as the oracle and the global PCG)."""
+    kind, dims, coef, Ah, A, b, x0 = make_case("5pt")
+    say("converged x0", mode)
+    nb = np.linalg.norm(b)
+    xs = oracle.pcg(Ah, b, x0, oracle.PC_JACOBI, 1e-13 * nb, 5000)[0]
+    xo, so, dom = oracle.local_then_global(Ah, b, xs, oracle.MODE_RESIDUAL, 1e-10,
+                                           oracle.TH_PAPER, 1, oracle.Options(eps=1e-10))
+    assert dom.K == 0 and np.array_equal(xo, xs)
+    x = dev(xs)
+    st = lcs.solve_local_then_global(A, dev(b), x, mode, thresh, theta, 1, lcs.Options(eps=1e-10),
+                                     ctx=ctx)
+    assert st.K == 0 and st.its_local == 0 and st.its_global == 0
+    assert np.array_equal(host(x), xs)
+    assert st.relres_final <= 1e-10
+
+
 # ----------------------------------------------------------------------------
 # restricted system (eq. BEFC): bit-exact CSR
 # ----------------------------------------------------------------------------

@@ -338,6 +338,34 @@ def test_local_then_global_meets_criterion():
         assert 0 < dom.K <= A.n
 
 
+def test_converged_x0_is_returned_unchanged():
+    """An x0 that already meets eq. (rel-res-conv-criteria) is a solution in
+    the paper's sense: Algorithm 1 returns it as it is, as the global PCG
+    does (zero iterations).  An x0 just outside the criterion goes through
+    the local solve."""
+    w, A, b, _ = _sequence_problem()
+    a = A.dense()
+    xs = np.linalg.solve(a, b)
+    nb = np.linalg.norm(b)
+    assert np.linalg.norm(b - a @ xs) <= 1e-13 * nb
+    opts = oracle.Options(eps=1e-10)
+    xg, sg = oracle.solve_global(A, b, xs, opts)
+    assert sg.its_global == 0 and np.array_equal(xg, xs)
+    for mode, theta, th in [(oracle.MODE_RESIDUAL, 1e-10, oracle.TH_PAPER),
+                            (oracle.MODE_GRADIENT, 1e-4, oracle.TH_RELMAX)]:
+        x, st, dom = oracle.local_then_global(A, b, xs, mode, theta, th, 1, opts)
+        assert np.array_equal(x, xs)
+        assert dom.K == 0 and st.its_local == 0 and st.its_global == 0
+        assert st.relres_final <= 1e-13
+    # perturb one cell so that ||r|| is 10 eps ||b||: the method runs
+    xp = xs.copy()
+    i = A.n // 2
+    xp[i] += 10 * 1e-10 * nb / np.linalg.norm(a[:, i])
+    x, st, dom = oracle.local_then_global(A, b, xp, oracle.MODE_RESIDUAL, 1e-10, oracle.TH_PAPER, 1,
+                                          opts)
+    assert dom.K > 0 and st.relres_final <= 1e-10
+
+
 def test_paper_threshold_usually_needs_no_global_solve():
     """With the paper's threshold the assembled x~ already meets the
     criterion in the common case (Section 3, discussion of Algorithm 1)."""
@@ -476,7 +504,36 @@ def test_heat_assembly_symmetric_m_matrix_and_row_sums(power):
     np.testing.assert_allclose(src[:, 1:-1], 0.0, atol=0)
     np.testing.assert_allclose(src[:, 0], extra[:, 0] * tl, rtol=1e-12)
     np.testing.assert_allclose(src[:, -1], extra[:, -1] * tr, rtol=1e-12)
-    # the interior face between cells p, q is the harmonic mean of T_p^power, T_q^power
+    # interior faces: the arithmetic mean of T_p^power, T_q^power (x and y);
+    # Dirichlet faces: twice the mean of k(T_b) and k(T_p)
     k = t ** power
     p = 3 + nx * 2
-    np.testing.assert_allclose(-A[p, p + 1], 2 * k[p] * k[p + 1] / (k[p] + k[p + 1]), rtol=1e-13)
+    np.testing.assert_allclose(-A[p, p + 1], 0.5 * (k[p] + k[p + 1]), rtol=1e-13)
+    np.testing.assert_allclose(-A[p, p + nx], 0.5 * (k[p] + k[p + nx]), rtol=1e-13)
+    kk = k.reshape(ny, nx)
+    np.testing.assert_allclose(extra[:, 0], tl ** power + kk[:, 0], rtol=1e-12)
+    np.testing.assert_allclose(extra[:, -1], tr ** power + kk[:, -1], rtol=1e-12)
+
+
+def test_heat_assembly_conducts_into_cold_cells():
+    """A hot column next to cold cells at the test's temperatures (T = 1 and
+    1e-4, k = 1 and 1e-14): the face between them carries about half the hot
+    conductivity, so one backward-Euler step from a step profile moves heat
+    into the first cold column by the amount that the 1-D three-cell balance
+    gives exactly."""
+    nx, ny, inv_dt = 6, 3, 0.5
+    tl, tr = 1.0, 1e-4
+    t = np.tile(np.array([1.0, 1.0, 1e-4, 1e-4, 1e-4, 1e-4]), ny)
+    coef, b = oracle.heat_assemble(nx, ny, inv_dt, 3.5, tl, tr, t, t)
+    A = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, coef).dense()
+    # face (1, 2): (1 + 1e-14) / 2; the harmonic mean would give 2e-14
+    assert -A[1, 2] == pytest.approx(0.5, rel=1e-13)
+    # no flow in y (identical rows): the solution is the 1-D one of each row
+    x = np.linalg.solve(A, b).reshape(ny, nx)
+    np.testing.assert_allclose(x, np.tile(x[0], (ny, 1)), rtol=1e-12)
+    # heat entered column 2 (from 1e-4 to well above it) and the row's total
+    # heat changed by what the two Dirichlet faces delivered
+    assert x[0, 2] > 0.05
+    fl = (tl ** 3.5 + 1.0) * (tl - x[0, 0])          # inflow at x = 0
+    fr = (tr ** 3.5 + 1e-14) * (x[0, -1] - tr)       # outflow at x = 1
+    np.testing.assert_allclose(inv_dt * (x[0].sum() - t[:nx].sum()), fl - fr, rtol=1e-10)
