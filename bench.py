@@ -74,6 +74,9 @@ def parse():
                    help="run the 2-D nonlinear heat-conduction test (Section 3.1) on N x N cells with "
                         "the three methods and exit")
     p.add_argument("--heat-steps", type=int, default=100, help="time steps of --heat (paper: 100)")
+    p.add_argument("--mg", action="store_true",
+                   help="time the 64 group systems of a multi-group source iteration (Section 3.3): "
+                        "batched (one launch) and per system, and exit")
     p.add_argument("--summarize", metavar="DIR",
                    help="print a summary of rocprofv3 output under DIR (trace/, fetch/, write/) "
                         "and exit; no GPU needed")
@@ -304,6 +307,7 @@ def heat_run(n: int, steps: int):
     synchronised.  Prints a markdown report."""
     import torch
     from paper_2001_01158_amd import lcs
+    from paper_2001_01158_amd import workloads as W
     from paper_2001_01158_amd.heat2d import Heat2D, METHODS
     torch.cuda.set_device(0)
     N = n * n
@@ -315,8 +319,30 @@ def heat_run(n: int, steps: int):
     recs = {m: [] for m in METHODS}
     e = {"gradient": [], "residual": []}
     zero = torch.zeros(N, dtype=torch.float64, device="cuda:0")
+    marks = sorted({min(steps, s) for s in (1, steps // 4, steps // 2, 3 * steps // 4, steps) if s > 0})
+    # the two local domains of the first Picard system of the marked steps
+    # (the paper compares them at time steps 25, 50, 75 and 100)
+    omega = {}
+    dctx = lcs.Context()
+    coef_d = torch.empty((3, N), dtype=torch.float64, device="cuda:0")
+    b_d = torch.empty(N, dtype=torch.float64, device="cuda:0")
+    A_d = lcs.Matrix(lcs.STENCIL5_2D, n, n, 1, coef_d)
     t_start = time.perf_counter()
     for k in range(steps):
+        if k + 1 in marks:
+            T = sims["global"].T
+            lcs.assemble_heat(n, n, sims["global"].inv_dt, W.HEAT_POWER, W.HEAT_T_LEFT, W.HEAT_T_RIGHT,
+                              T, T, coef_d, b_d, ctx=dctx)
+            i1, _, _ = lcs.build_local_domain(A_d, b_d, T, "gradient", "relmax", W.HEAT_ALPHA, 0,
+                                              ctx=dctx)
+            i2, _, _ = lcs.build_local_domain(A_d, b_d, T, "residual", "paper", 1e-10, W.HEAT_E_MAX,
+                                              ctx=dctx)
+            m1 = torch.zeros(N, dtype=torch.bool, device="cuda:0")
+            m2 = torch.zeros_like(m1)
+            m1[i1.long()] = True
+            m2[i2.long()] = True
+            inter, union = int((m1 & m2).sum()), int((m1 | m2).sum())
+            omega[k + 1] = (i1.numel(), i2.numel(), inter / union if union else 1.0)
         for m in METHODS:
             recs[m].append(sims[m].step())
         t0 = sims["global"].T
@@ -348,21 +374,126 @@ def heat_run(n: int, steps: int):
               f"{np.mean([r.its_local for r in f]):.1f} | {np.mean([r.its_global for r in f]):.1f} |")
     print(f"\nmax over the steps: e1 = {max(e['gradient']):.2e}, e2 = {max(e['residual']):.2e} "
           "(||T_Mi - T_M0||_2 / ||T_M0||_2)\n")
-    marks = sorted({min(steps, s) for s in (1, steps // 4, steps // 2, 3 * steps // 4, steps) if s > 0})
-    print("| time step | Picard M0 / M1 / M2 | eta M1 | eta M2 | S M1 | S M2 |")
-    print("|---|---|---|---|---|---|")
+    print("| time step | Picard M0 / M1 / M2 | eta M1 | eta M2 | S M1 | S M2 | "
+          "first system: K(Omega_1) / K(Omega_2), overlap |")
+    print("|---|---|---|---|---|---|---|")
     for s in marks:
         st = {m: recs[m][s - 1] for m in METHODS}
         a = {m: np.mean([r.ms for r in st[m]]) for m in METHODS}
+        k1, k2, jac = omega[s]
         print(f"| {s} | {len(st['global'])} / {len(st['gradient'])} / {len(st['residual'])} | "
               f"{100 * np.mean([r.K for r in st['gradient']]) / N:.2f} % | "
               f"{100 * np.mean([r.K for r in st['residual']]) / N:.2f} % | "
-              f"{a['global'] / a['gradient']:.2f} | {a['global'] / a['residual']:.2f} |", flush=True)
+              f"{a['global'] / a['gradient']:.2f} | {a['global'] / a['residual']:.2f} | "
+              f"{k1} / {k2}, {100 * jac:.1f} % |", flush=True)
+    print("\n(overlap = |Omega_1 & Omega_2| / |Omega_1 | Omega_2| on the system of the first Picard "
+          "iteration, from the global-PCG trajectory)\n")
+
+
+def mg_run(reps: int):
+    """The G = 64 group systems of one source iteration of the multi-group
+    test (Section 3.3; seeded stand-in, 88 x 80 = 7040 cells, nine-point):
+    M0 = global Jacobi PCG, M1 = gradient domain (alpha = 1e-10), M2 =
+    residual domain (paper threshold, E_max = 1), eps = 1e-8, one GS sweep.
+    (1) all 64 systems in one batched launch (one workgroup per system);
+    (2) single systems (the batched call with G = 1) for the groups of the
+    paper's Table speedup-MG; (3) the 64 systems one after another through
+    the grid-wide single-system path.  Wall time per call, inputs resident."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    w = W.mg_batch()
+    N = w.nx * w.ny
+    coef = torch.as_tensor(w.coef).to(dev)
+    b = torch.as_tensor(w.b).to(dev)
+    x0 = torch.as_tensor(w.x0).to(dev)
+    x = torch.empty_like(x0)
+    ctx = lcs.Context()
+    o = lcs.Options(eps=W.MG_EPS)
+    label = {"M0": "M0 (global PCG)", "M1": "M1 (gradient, alpha 1e-10)",
+             "M2": "M2 (residual, E_max 1)"}
+
+    def batched(A, bb, xx, m):
+        if m == "M0":
+            return lcs.solve_global_batched(A, bb, xx, o, ctx=ctx)
+        if m == "M1":
+            return lcs.solve_local_then_global_batched(A, bb, xx, "gradient", "relmax", W.MG_ALPHA,
+                                                       0, o, ctx=ctx)
+        return lcs.solve_local_then_global_batched(A, bb, xx, "residual", "paper", W.MG_EPS,
+                                                   W.MG_E_MAX, o, ctx=ctx)
+
+    def timed(call, xx, xs):
+        for _ in range(2):
+            xx.copy_(xs)
+            call()
+        ts, out = [], None
+        for _ in range(reps):
+            xx.copy_(xs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = call()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts)), out
+
+    A = lcs.BatchMatrix(W.KIND_9PT, w.nx, w.ny, 1, coef)
+    print(f"### Multi-group source iteration: {w.G} systems of {w.nx} x {w.ny} = {N} cells, "
+          f"nine-point, eps = {W.MG_EPS:g}\n")
+    print("| method | one batched launch, 64 systems (ms) | per system (ms) | mean eta | max its per "
+          "system (local + global) |")
+    print("|---|---|---|---|---|")
+    res = {}
+    for m in ("M0", "M1", "M2"):
+        ms, sts = timed(lambda: batched(A, b, x, m), x, x0)
+        res[m] = ms
+        eta = "-" if m == "M0" else f"{100 * np.mean([s.K for s in sts]) / N:.1f} %"
+        worst = max(sts, key=lambda s: s.its_local + s.its_global)
+        print(f"| {label[m]} | {ms:.3f} | {ms / w.G:.4f} | {eta} | "
+              f"{worst.its_local} + {worst.its_global} |", flush=True)
+    print()
+    print("| group | kappa_g | eta M1 | eta M2 | M0 ms | M1 ms | M2 ms | S M1 | S M2 | its M0 / M1 / M2 |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    for g in (1, 10, 41, 55, 63):
+        Ag = lcs.BatchMatrix(W.KIND_9PT, w.nx, w.ny, 1, coef[g:g + 1].contiguous())
+        bg, xs, xg = b[g:g + 1].contiguous(), x0[g:g + 1].contiguous(), torch.empty_like(x0[:1])
+        t, st = {}, {}
+        for m in ("M0", "M1", "M2"):
+            t[m], sts = timed(lambda: batched(Ag, bg, xg, m), xg, xs)
+            st[m] = sts[0]
+        its = " / ".join(f"{st[m].its_local}+{st[m].its_global}" for m in ("M0", "M1", "M2"))
+        print(f"| {g} | {w.kappa[g]:.3g} | {100 * st['M1'].K / N:.1f} % | {100 * st['M2'].K / N:.1f} % | "
+              f"{t['M0']:.3f} | {t['M1']:.3f} | {t['M2']:.3f} | {t['M0'] / t['M1']:.2f} | "
+              f"{t['M0'] / t['M2']:.2f} | {its} |", flush=True)
+    print()
+    # the same 64 systems through the grid-wide single-system path
+    mats = [lcs.Matrix(W.KIND_9PT, w.nx, w.ny, 1, coef[g].contiguous()) for g in range(w.G)]
+
+    def sequential(m):
+        for g in range(w.G):
+            xx = x[g]
+            if m == "M0":
+                lcs.solve_global(mats[g], b[g], xx, o, ctx=ctx)
+            elif m == "M1":
+                lcs.solve_local_then_global(mats[g], b[g], xx, "gradient", "relmax", W.MG_ALPHA, 0, o,
+                                            ctx=ctx)
+            else:
+                lcs.solve_local_then_global(mats[g], b[g], xx, "residual", "paper", W.MG_EPS,
+                                            W.MG_E_MAX, o, ctx=ctx)
+
+    print("| method | 64 systems one after another, grid-wide path (ms) | batched launch (ms) | "
+          "batched gain |")
+    print("|---|---|---|---|")
+    for m in ("M0", "M1", "M2"):
+        ms, _ = timed(lambda: sequential(m), x, x0)
+        print(f"| {label[m]} | {ms:.2f} | {res[m]:.3f} | {ms / res[m]:.1f}x |", flush=True)
     print()
 
 
 def main():
     args = parse()
+    if args.mg:
+        mg_run(max(args.steps // 4, 5))
+        return
     if args.heat:
         heat_run(args.heat, args.heat_steps)
         return

@@ -204,6 +204,33 @@ lcs_status lcs_get_kernel_timing(lcs_ctx *ctx, double *ms_total, int64_t *launch
  * settings; reductions may round differently. */
 lcs_status lcs_set_tiling(lcs_ctx *ctx, int32_t march_rows, int32_t nontemporal);
 
+/* ---- batched solves: the G decoupled group systems of a source iteration ---- */
+/* In each source iteration of the multi-group radiation diffusion equations
+ * (Section 3.3, Algorithm 7) the G group equations are decoupled: G systems
+ * A_g x_g = b_g on one grid and stencil kind.  These calls solve all G in one
+ * launch, one workgroup per system, with the same results per system as the
+ * single-system calls: lcs_solve_global_batched as lcs_solve_global, and
+ * lcs_solve_local_then_global_batched as lcs_solve_local_then_global
+ * (Algorithm 1, the same domain bit for bit, the same criterion).
+ *   A->coef: device, G coefficient sets one after another, [G][n_arrays][N]
+ *            (the layout of lcs_matrix per set); A->coef32 is ignored.
+ *   b, x:    device, [G][N]; x in x^(0), out the solutions.
+ *   st:      host array of G stats, or NULL; ms_* fields are 0 (one launch
+ *            serves all systems: time the call).
+ * FP64 only (precision must be LCS_PREC_FP64), Jacobi or no preconditioner,
+ * 1 <= G <= 65535, N <= 2^24 cells per system; otherwise LCS_EINVAL.  Every
+ * system runs to completion; the call then returns the error of the first
+ * system that failed (LCS_ENOCONV, LCS_EBREAKDOWN, LCS_ENONFINITE) with its
+ * index in lcs_last_error(), or LCS_OK.  Synchronises the stream.  Intended
+ * for small systems (about 10^3 - 10^5 cells each), where a solve through the
+ * grid-wide kernels is bound by launch latency. */
+lcs_status lcs_solve_global_batched(lcs_ctx *ctx, const lcs_matrix *A, int32_t G, const double *b,
+                                    double *x, const lcs_options *o, lcs_stats *st, void *stream);
+lcs_status lcs_solve_local_then_global_batched(lcs_ctx *ctx, const lcs_matrix *A, int32_t G,
+                                               const double *b, double *x, int32_t mode,
+                                               int32_t thresh_kind, double theta, int32_t e_max,
+                                               const lcs_options *o, lcs_stats *st, void *stream);
+
 /* ---- adjoint helpers (5- and 7-point log-conductivity operators) ---- */
 /* coef = stencil of A = I*inv_dt + sum_f T_f (e_P-e_Q)(e_P-e_Q)^T with
  * T_f = 2 k_P k_Q / (k_P + k_Q), k = exp(logk); zero-flux outer faces. */

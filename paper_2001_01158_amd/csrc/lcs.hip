@@ -15,6 +15,7 @@
 
 #include "lcs.h"
 #include "lcs_kernels.h"
+#include "lcs_batched.h"
 
 using namespace lcs;
 
@@ -121,7 +122,7 @@ enum BufId {
     B_SCORE, B_R, B_Z, B_P0, B_P1, B_Q, B_RHSL, B_DL, B_RES, B_STAMP, B_INV, B_IDX, B_BLOCKOFF,
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
     B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_W0, B_W1, B_S0, B_S1, B_W32A, B_W32B,
-    B_S32A, B_S32B, B_NUM
+    B_S32A, B_S32B, B_BWS, B_BSTAMP, B_BIDX, B_BOUT, B_NUM
 };
 
 }  // namespace
@@ -146,6 +147,9 @@ struct lcs_ctx {
     // row-marching tiling of the 2-D stencil kernels (0 / -1: automatic)
     int march_rows = 0;
     int nontemporal = -1;
+    // pinned host copy of the per-system results of a batched solve
+    BatchOut *hbout = nullptr;
+    int32_t hbout_cap = 0;
 };
 
 namespace {
@@ -906,6 +910,112 @@ lcs_status check_mode(int32_t mode, int32_t thresh_kind, double theta, int32_t e
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// batched solves (G systems on one grid, one workgroup each)
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class S>
+lcs_status launch_batch(lcs_ctx *c, const S &A, int pc, const BatchArgs &a, int32_t G,
+                        const double *b, double *x, double *ws, uint8_t *stamp, int32_t *idx,
+                        BatchOut *out, hipStream_t s) {
+    if (pc == LCS_PC_JACOBI)
+        hipLaunchKernelGGL((k_batch_solve<S, 1>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b, x, ws,
+                           stamp, idx, out);
+    else
+        hipLaunchKernelGGL((k_batch_solve<S, 0>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b, x, ws,
+                           stamp, idx, out);
+    LAUNCH_CHECK();
+    return LCS_OK;
+}
+
+lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const double *b, double *x,
+                         int local, int32_t mode, int32_t thresh_kind, double theta, int32_t e_max,
+                         const lcs_options *o, lcs_stats *st, void *stream) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    LCS_TRY(check_matrix(A));
+    LCS_TRY(check_options(o, A->kind));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x, "x"));
+    if (local) LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
+    if (G < 1 || G > kMaxBatch) return fail(LCS_EINVAL, "batch size G must be 1..65535");
+    if (o->precision != LCS_PREC_FP64) return fail(LCS_EINVAL, "batched solves run in FP64");
+    if (o->precond == LCS_PC_RBSGS)
+        return fail(LCS_EINVAL, "batched solves take the Jacobi preconditioner or none");
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    if (n > kMaxBatchN) return fail(LCS_EINVAL, "batched solves take at most 2^24 cells per system");
+    hipStream_t s = (hipStream_t)stream;
+    BatchArgs a{};
+    a.coef_stride = (int64_t)n_arrays(A->kind) * n;
+    a.local = local;
+    a.mode = mode;
+    a.thresh = thresh_kind;
+    a.theta = theta;
+    a.e_max = e_max;
+    a.eps = o->eps;
+    a.tol_local = o->tol_local > 0.0 ? o->tol_local : o->eps;
+    a.max_iter = o->max_iter;
+    a.max_outer = o->max_outer;
+    a.n_smooth = o->n_smooth;
+    double *ws;
+    uint8_t *stamp;
+    int32_t *idx;
+    BatchOut *dout;
+    LCS_TRY(get_buf(c, B_BWS, (size_t)4 * n * G, &ws));
+    LCS_TRY(get_buf(c, B_BSTAMP, (size_t)n * G, &stamp));
+    LCS_TRY(get_buf(c, B_BIDX, (size_t)n * G, &idx));
+    LCS_TRY(get_buf(c, B_BOUT, (size_t)G, &dout));
+    if (c->hbout_cap < G) {
+        if (c->hbout) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipHostFree(c->hbout));
+        }
+        c->hbout = nullptr;
+        c->hbout_cap = 0;
+        if (hipHostMalloc(&c->hbout, sizeof(BatchOut) * (size_t)G, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LCS_ENOMEM, "pinned batch results");
+        }
+        c->hbout_cap = G;
+    }
+    switch (A->kind) {
+    case LCS_STENCIL5_2D:
+        LCS_TRY(launch_batch(c, sop5<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));
+        break;
+    case LCS_STENCIL9_2D:
+        LCS_TRY(launch_batch(c, sop9<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));
+        break;
+    default:
+        LCS_TRY(launch_batch(c, sop7<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));
+        break;
+    }
+    HIP_TRY(hipMemcpyAsync(c->hbout, dout, sizeof(BatchOut) * (size_t)G, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int first_bad = -1;
+    for (int32_t g = 0; g < G; ++g) {
+        const BatchOut &r = c->hbout[g];
+        if (st) {
+            init_stats(&st[g]);
+            st[g].K = r.K;
+            st[g].e_rounds = r.e_rounds;
+            st[g].its_local = r.its_local;
+            st[g].its_global = r.its_global;
+            st[g].n_outer = r.n_outer;
+            st[g].tau = r.tau;
+            if (local) st[g].relres_after_local = r.relres_after_local;
+            st[g].relres_final = r.relres_final;
+        }
+        if (r.status != kStOk && first_bad < 0) first_bad = g;
+    }
+    if (first_bad >= 0) {
+        const lcs_status e = status_of(c->hbout[first_bad].status);
+        return fail(e, "system " + std::to_string(first_bad) + " of the batch: " + g_err);
+    }
+    return LCS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void lcs_default_options(lcs_options *o) {
@@ -959,6 +1069,7 @@ void lcs_destroy(lcs_ctx *c) {
     if (c->partials) (void)hipFree(c->partials);
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hdone) (void)hipHostFree(c->hdone);
+    if (c->hbout) (void)hipHostFree(c->hbout);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chk)
@@ -1288,6 +1399,18 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         st->ms_global = tm.ms(3, 4);
         return rs;
     });
+}
+
+lcs_status lcs_solve_global_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const double *b,
+                                    double *x, const lcs_options *o, lcs_stats *st, void *stream) {
+    return solve_batched(c, A, G, b, x, 0, 0, 0, 0.0, 0, o, st, stream);
+}
+
+lcs_status lcs_solve_local_then_global_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G,
+                                               const double *b, double *x, int32_t mode,
+                                               int32_t thresh_kind, double theta, int32_t e_max,
+                                               const lcs_options *o, lcs_stats *st, void *stream) {
+    return solve_batched(c, A, G, b, x, 1, mode, thresh_kind, theta, e_max, o, st, stream);
 }
 
 lcs_status lcs_set_kernel_timing(lcs_ctx *c, int32_t what) {

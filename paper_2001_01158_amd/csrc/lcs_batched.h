@@ -1,0 +1,405 @@
+// Batched solves: G independent systems on one grid, one workgroup each.
+//
+// In a source iteration of the multi-group radiation diffusion equations the
+// G group equations are decoupled (Algorithm 7): G systems A_g x_g = b_g of
+// the same grid and stencil, each small (thousands of cells).  A solve of one
+// such system through the grid-wide kernels is a chain of a few hundred
+// launches, each far too small to fill the chip, so its time is launch and
+// synchronisation latency.  Here one workgroup of 1024 threads runs the whole
+// of Algorithm 1 for one system (scores, threshold, expansion rounds,
+// compaction, local PCG on Omega, assembly, Gauss-Seidel sweeps, check,
+// global PCG finish): every reduction is a workgroup reduction, every
+// dependency a workgroup barrier, and one launch serves all G systems, which
+// run side by side on separate compute units.  A system's vectors (about
+// 37 B per cell) stay in the L2 of the XCD that runs it.
+//
+// The local system is applied as the stencil restricted to Omega: rows are
+// the compacted idx, and the search direction p is zero outside Omega, so
+// (B p)_i = sum_{j in Omega} a_ij p_j is the FMA chain of the stencil row in
+// ascending column order with zero terms for j outside Omega (bit-identical
+// to the gathered B up to the sign of a zero).  Every per-row quantity
+// (residual, gradient, expansion bound, Gauss-Seidel update) uses the same
+// for_each order as the grid-wide kernels and the oracle; only the dot
+// products are summed in another order (a fixed workgroup tree).
+#pragma once
+
+#include "lcs_kernels.h"
+
+namespace lcs {
+
+constexpr int kBatchBlock = 1024;
+constexpr int kBatchWaves = kBatchBlock / kWave;
+constexpr int32_t kMaxBatch = 65535;          // one workgroup per system on grid x
+constexpr int64_t kMaxBatchN = int64_t(1) << 24;   // cells per system (int32 idx, time)
+
+// per-system result, written by thread 0 of the system's workgroup
+struct BatchOut {
+    int64_t K;
+    int32_t e_rounds, its_local, its_global, n_outer;
+    int32_t status, status_local;
+    double tau, relres_after_local, relres_final;
+};
+
+template <typename real>
+__device__ __forceinline__ Stencil5<real> shifted(Stencil5<real> A, int64_t off) {
+    A.C += off;
+    A.E += off;
+    A.N += off;
+    return A;
+}
+template <typename real>
+__device__ __forceinline__ Stencil9<real> shifted(Stencil9<real> A, int64_t off) {
+    A.C += off;
+    A.E += off;
+    A.N += off;
+    A.NE += off;
+    A.NW += off;
+    return A;
+}
+template <typename real>
+__device__ __forceinline__ Stencil7<real> shifted(Stencil7<real> A, int64_t off) {
+    A.C += off;
+    A.E += off;
+    A.N += off;
+    A.U += off;
+    return A;
+}
+
+// Workgroup reduction of NV values (bit k of the Ops mask: value k is a max);
+// the result is in every thread, identical in all of them (every thread
+// combines the wave results in the same order).
+template <int NV, class O>
+__device__ __forceinline__ void wg_reduce(double (&v)[NV], O ops) {
+    __shared__ double lds[kBatchWaves][NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = ops.template reduce_wave<double>(k, v[k]);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[w][k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = lds[0][k];
+#pragma unroll
+        for (int q = 1; q < kBatchWaves; ++q) s = ops.template apply<double>(k, s, lds[q][k]);
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// exclusive workgroup scan of one count per thread; total in every thread
+__device__ __forceinline__ int64_t wg_exclusive_scan(int v, int64_t &total) {
+    __shared__ int64_t wsum[kBatchWaves];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int64_t base = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kBatchWaves; ++q) {
+        if (q < w) base += wsum[q];
+        tot += wsum[q];
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+// Row t of the active set: idx[t] for a local system, t itself for A.
+__device__ __forceinline__ int64_t row_of(const int32_t *idx, int64_t t) { return idx ? idx[t] : t; }
+
+// PCG (standard recurrences, as the oracle's) on the rows of the active set
+// (cnt rows: idx[0..cnt) or all of A), Jacobi (kPc 1) or none (kPc 0).
+// In: r = residual of the initial sol on the active rows, p zero outside
+// them.  sol (d for the local system, x for A) is updated in place; stops at
+// ||r|| <= tol or max_iter.  Returns kStOk, kStNoConv, kStBreakdown or
+// kStNonFinite; *its = iterations.
+template <class S, int kPc>
+__device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, double *r,
+                      double *sol, double *p, double *q, double tol, int max_iter, int *its) {
+    const int tid = threadIdx.x;
+    *its = 0;
+    double v[2] = {0.0, 0.0};
+    for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+        const int64_t i = row_of(idx, t);
+        const double ri = r[i];
+        const double z = kPc ? ri / A.diag(i) : ri;
+        p[i] = z;
+        v[0] += ri * ri;
+        v[1] += ri * z;
+    }
+    wg_reduce<2>(v, Ops<0u>());   // its barrier also publishes p
+    double rr = v[0], rz = v[1];
+    if (!(rr == rr)) return kStNonFinite;
+    if (sqrt(rr) <= tol) return kStOk;
+    int it = 0;
+    while (it < max_iter) {
+        double pq[1] = {0.0};
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            double acc = 0.0;
+            A.for_each(i, [&](int64_t l, double a) { acc = fma(a, p[l], acc); });
+            q[i] = acc;
+            pq[0] += p[i] * acc;
+        }
+        wg_reduce<1>(pq, Ops<0u>());
+        if (!(pq[0] > 0.0)) {
+            *its = it;
+            return pq[0] == pq[0] ? kStBreakdown : kStNonFinite;
+        }
+        const double alpha = rz / pq[0];
+        double w[2] = {0.0, 0.0};
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            sol[i] = fma(alpha, p[i], sol[i]);
+            const double ri = fma(-alpha, q[i], r[i]);
+            r[i] = ri;
+            w[0] += ri * ri;
+            w[1] += ri * (kPc ? ri / A.diag(i) : ri);
+        }
+        wg_reduce<2>(w, Ops<0u>());
+        ++it;
+        rr = w[0];
+        if (!(rr == rr)) {
+            *its = it;
+            return kStNonFinite;
+        }
+        if (sqrt(rr) <= tol) {
+            *its = it;
+            return kStOk;
+        }
+        const double beta = w[1] / rz;
+        rz = w[1];
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            const double z = kPc ? r[i] / A.diag(i) : r[i];
+            p[i] = fma(beta, p[i], z);
+        }
+        __syncthreads();
+    }
+    *its = it;
+    return kStNoConv;
+}
+
+// r = b - A x over all rows (FMA chain, ascending columns); returns ||r||^2
+// in every thread.
+template <class S>
+__device__ double wg_residual(const S &A, const double *__restrict__ b, const double *x, double *r) {
+    double v[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < A.n; i += kBatchBlock) {
+        double acc = b[i];
+        A.for_each(i, [&](int64_t l, double a) { acc = fma(-a, x[l], acc); });
+        r[i] = acc;
+        v[0] += acc * acc;
+    }
+    wg_reduce<1>(v, Ops<0u>());
+    return v[0];
+}
+
+// Global finish: PCG from x with a true-residual check, restarting from the
+// current x while the check fails (at most max_outer restarts, max_iter
+// iterations in all).  r must hold b - A x on entry.
+template <class S, int kPc>
+__device__ int wg_global(const S &A, const double *__restrict__ b, double *x, double *r, double *p,
+                         double *q, double tol, int max_iter, int max_outer, int *its_total,
+                         int *restarts, double *rr_true) {
+    int st = kStOk, total = 0;
+    *restarts = 0;
+    for (int attempt = 0;; ++attempt) {
+        int it = 0;
+        st = wg_pcg<S, kPc>(A, nullptr, A.n, r, x, p, q, tol, max_iter - total, &it);
+        total += it;
+        const double rr = wg_residual(A, b, x, r);
+        *rr_true = rr;
+        if (st != kStOk) break;
+        if (sqrt(rr) <= tol) break;
+        if (attempt >= max_outer || total >= max_iter) {
+            st = kStNoConv;
+            break;
+        }
+        *restarts += 1;
+    }
+    *its_total = total;
+    return st;
+}
+
+struct BatchArgs {
+    int64_t coef_stride;   // doubles between consecutive systems' coefficient sets
+    int local;             // 0: global PCG only (the baseline); 1: Algorithm 1
+    int mode, thresh;      // LCS_MODE_*, LCS_THRESH_* values
+    double theta;
+    int e_max;
+    double eps, tol_local;
+    int max_iter, max_outer, n_smooth;
+};
+
+// One workgroup per system g = blockIdx.x.  ws: 4 n doubles per system
+// (r, p, q, d); stamp: n bytes; idx: n ints.
+template <class S, int kPc>
+__global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
+                                                             const double *__restrict__ b_all,
+                                                             double *x_all, double *ws,
+                                                             uint8_t *stamp_all, int32_t *idx_all,
+                                                             BatchOut *out) {
+    const int g = blockIdx.x;
+    const S A = shifted(A0, (int64_t)g * a.coef_stride);
+    const int64_t n = A.n;
+    const int tid = threadIdx.x;
+    const double *b = b_all + (int64_t)g * n;
+    double *x = x_all + (int64_t)g * n;
+    double *r = ws + (int64_t)g * 4 * n, *p = r + n, *q = p + n, *d = q + n;
+    uint8_t *stamp = stamp_all + (int64_t)g * n;
+    int32_t *idx = idx_all + (int64_t)g * n;
+    BatchOut o{};
+    o.status = kStOk;
+
+    // ---- r0 = b - A x0; ||b||^2, ||r0||^2, max |score| (Algorithms 2, 3) ----
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = tid; i < n; i += kBatchBlock) {
+        const double bi = b[i];
+        double acc = bi;
+        A.for_each(i, [&](int64_t l, double c) { acc = fma(-c, x[l], acc); });
+        r[i] = acc;
+        v[1] += bi * bi;
+        v[2] += acc * acc;
+        double s = acc;
+        if (a.local && a.mode == LCS_MODE_GRADIENT) {
+            const double xi = x[i];
+            double gsum = 0.0;
+            A.for_each(i, [&](int64_t l, double) {
+                if (l != i) gsum += fabs(xi - x[l]);
+            });
+            s = gsum;
+            q[i] = gsum;   // q holds the gradient score until the local PCG
+        }
+        const double m = fabs(s);
+        v[0] = m > v[0] ? m : v[0];
+    }
+    wg_reduce<3>(v, Ops<1u>());
+    const double bn = sqrt(v[1]);
+    const double tol = a.eps * bn;
+    const double rr0 = v[2];
+    if (!(v[1] == v[1]) || !(rr0 == rr0) || !(v[0] == v[0])) {
+        o.status = kStNonFinite;
+        if (tid == 0) out[g] = o;
+        return;
+    }
+    double rr = rr0;
+    int st_global = kStOk;
+    bool need_global = true;
+
+    if (a.local) {
+        double tau;
+        if (a.thresh == LCS_THRESH_REL_MAX) tau = a.theta * v[0];
+        else if (a.thresh == LCS_THRESH_ABS) tau = a.theta;
+        else tau = a.theta * bn / sqrt((double)n);
+        o.tau = tau;
+        if (sqrt(rr0) <= tol) {
+            // x0 already meets the criterion: it is the solution
+            o.relres_after_local = o.relres_final = bn > 0 ? sqrt(rr0) / bn : sqrt(rr0);
+            if (tid == 0) out[g] = o;
+            return;
+        }
+        const bool res_mode = a.mode == LCS_MODE_RESIDUAL;
+        // ---- mark (strict >) ----
+        for (int64_t i = tid; i < n; i += kBatchBlock)
+            stamp[i] = fabs(res_mode ? r[i] : q[i]) > tau ? 1 : 0;
+        __syncthreads();
+        // ---- synchronous expansion rounds (Algorithm 3, eq. extend-local-condition) ----
+        const int ex = res_mode ? a.e_max : 0;
+        for (int m = 1; m <= ex; ++m) {
+            double added[1] = {0.0};
+            for (int64_t j = tid; j < n; j += kBatchBlock) {
+                if (stamp[j] != 0) continue;
+                bool nb = false;
+                double acc = fabs(r[j]);
+                A.for_each(j, [&](int64_t l, double c) {
+                    const int sl = stamp[l];
+                    if (l != j && sl != 0 && sl <= m) {
+                        nb = true;
+                        acc += fabs(c * x[l]);
+                    }
+                });
+                if (nb && acc > tau) {
+                    stamp[j] = (uint8_t)(m + 1);
+                    added[0] += 1.0;
+                }
+            }
+            wg_reduce<1>(added, Ops<0u>());
+            if (added[0] == 0.0) break;
+            o.e_rounds = m;
+        }
+        // ---- compaction: contiguous chunks per thread, ascending ----
+        const int64_t chunk = (n + kBatchBlock - 1) / kBatchBlock;
+        const int64_t cb = tid * chunk < n ? tid * chunk : n;
+        const int64_t ce = cb + chunk < n ? cb + chunk : n;
+        int cnt = 0;
+        for (int64_t i = cb; i < ce; ++i) cnt += stamp[i] != 0;
+        int64_t K = 0;
+        int64_t off = wg_exclusive_scan(cnt, K);
+        for (int64_t i = cb; i < ce; ++i)
+            if (stamp[i] != 0) idx[off++] = (int32_t)i;
+        o.K = K;
+        __syncthreads();   // idx is read below by threads that did not write it
+        // ---- local PCG on Omega from d = 0, rhs r0_Omega (correction form) ----
+        for (int64_t i = tid; i < n; i += kBatchBlock) p[i] = 0.0;
+        for (int64_t t = tid; t < K; t += kBatchBlock) d[idx[t]] = 0.0;
+        __syncthreads();
+        int its = 0;
+        o.status_local = wg_pcg<S, kPc>(A, idx, K, r, d, p, q, a.tol_local * bn, a.max_iter, &its);
+        o.its_local = its;
+        if (o.status_local == kStBreakdown || o.status_local == kStNonFinite) {
+            o.status = o.status_local;
+            if (tid == 0) out[g] = o;
+            return;
+        }
+        // ---- assemble x~ (eq. sol-assemble) and smooth ----
+        for (int64_t t = tid; t < K; t += kBatchBlock) {
+            const int64_t i = idx[t];
+            x[i] += d[i];
+        }
+        __syncthreads();
+        for (int sw = 0; sw < a.n_smooth; ++sw)
+            for (int c = 0; c < S::kColours; ++c) {
+                for (int64_t i = tid; i < n; i += kBatchBlock) {
+                    if (A.colour(i) != c) continue;
+                    double acc = b[i], dd = 1.0;
+                    A.for_each(i, [&](int64_t l, double cf) {
+                        if (l == i) dd = cf;
+                        else acc = fma(-cf, x[l], acc);
+                    });
+                    x[i] = acc / dd;
+                }
+                __syncthreads();
+            }
+        // ---- check (eq. rel-res-conv-criteria) ----
+        rr = wg_residual(A, b, x, r);
+        o.relres_after_local = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
+        need_global = !(sqrt(rr) <= tol);
+        if (!(rr == rr)) {
+            o.status = kStNonFinite;
+            if (tid == 0) out[g] = o;
+            return;
+        }
+    }
+    if (need_global) {
+        // r holds b - A x here (either r0 or the post-smoothing residual)
+        int its = 0, restarts = 0;
+        st_global = wg_global<S, kPc>(A, b, x, r, p, q, tol, a.max_iter, a.max_outer, &its,
+                                      &restarts, &rr);
+        o.its_global = its;
+        o.n_outer = restarts;
+    }
+    o.status = st_global;
+    o.relres_final = bn > 0 ? sqrt(rr) / bn : sqrt(rr);
+    if (tid == 0) out[g] = o;
+}
+
+}  // namespace lcs

@@ -35,7 +35,8 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_solve_local_then_global", "lcs_residual", "lcs_gradient", "lcs_spmv",
             "lcs_gather_restricted", "lcs_gs_sweeps", "lcs_cast_coef", "lcs_assemble_logk",
             "lcs_grad_logk", "lcs_set_kernel_timing", "lcs_get_kernel_timing",
-            "lcs_set_tiling", "lcs_assemble_heat", "lcs_norm2_diff"]
+            "lcs_set_tiling", "lcs_assemble_heat", "lcs_norm2_diff",
+            "lcs_solve_global_batched", "lcs_solve_local_then_global_batched"]
 TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE = range(5)
 
 
@@ -83,6 +84,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.POINTER(I64), PS, P]),
         "lcs_solve_local": (I32, [P, PM, P, P, P, I64, PO, PS, P]),
         "lcs_solve_local_then_global": (I32, [P, PM, P, P, I32, I32, D, I32, PO, PS, P]),
+        "lcs_solve_global_batched": (I32, [P, PM, I32, P, P, PO, P, P]),
+        "lcs_solve_local_then_global_batched": (I32, [P, PM, I32, P, P, I32, I32, D, I32, PO, P,
+                                                      P]),
         "lcs_residual": (I32, [P, PM, P, P, P, P]),
         "lcs_gradient": (I32, [P, PM, P, P, P]),
         "lcs_spmv": (I32, [P, PM, P, P, I32, I32, P]),
@@ -293,6 +297,69 @@ def solve_local_then_global(A: Matrix, b: torch.Tensor, x: torch.Tensor, mode: s
                                              float(theta), int(e_max), ctypes.byref(o),
                                              ctypes.byref(st), _stream()))
     return Stats.of(st)
+
+
+# ---------------------------------------------------------------------------
+# batched solves: G systems on one grid (one workgroup each)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class BatchMatrix:
+    """G stencil operators of one grid and kind: coef (G, n_arrays, N) float64."""
+    kind: int
+    nx: int
+    ny: int
+    nz: int
+    coef: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def G(self) -> int:
+        return self.coef.shape[0]
+
+    def c(self) -> _Matrix:
+        if (self.coef.dtype != torch.float64 or self.coef.dim() != 3
+                or tuple(self.coef.shape[1:]) != (N_ARRAYS[self.kind], self.n)):
+            raise ValueError("coef must be float64 of shape (G, n_arrays, N)")
+        return _Matrix(self.kind, self.nx, self.ny, self.nz, _ptr(self.coef), None)
+
+
+def _batch_stats(arr, G):
+    return [Stats.of(arr[g]) for g in range(G)]
+
+
+def solve_global_batched(A: BatchMatrix, b: torch.Tensor, x: torch.Tensor, opts: Options = None,
+                         ctx: Context = None):
+    """Global PCG of each of the G systems (b, x: (G, N)); x in place.
+    Returns G Stats."""
+    opts = opts or Options()
+    G = A.G
+    arr = (_Stats * G)()
+    o = opts.c()
+    _check(lib().lcs_solve_global_batched(_ctx(ctx), ctypes.byref(A.c()), G,
+                                          _vec(b, G * A.n, name="b"), _vec(x, G * A.n, name="x"),
+                                          ctypes.byref(o), arr, _stream()))
+    return _batch_stats(arr, G)
+
+
+def solve_local_then_global_batched(A: BatchMatrix, b: torch.Tensor, x: torch.Tensor,
+                                    mode: str = "residual", thresh: str = "relmax",
+                                    theta: float = 1e-3, e_max: int = 1, opts: Options = None,
+                                    ctx: Context = None):
+    """Algorithm 1 on each of the G systems (b, x: (G, N)); x in place.
+    Returns G Stats."""
+    opts = opts or Options()
+    G = A.G
+    arr = (_Stats * G)()
+    o = opts.c()
+    _check(lib().lcs_solve_local_then_global_batched(_ctx(ctx), ctypes.byref(A.c()), G,
+                                                     _vec(b, G * A.n, name="b"),
+                                                     _vec(x, G * A.n, name="x"), _MODES[mode],
+                                                     _THRESH[thresh], float(theta), int(e_max),
+                                                     ctypes.byref(o), arr, _stream()))
+    return _batch_stats(arr, G)
 
 
 # ---------------------------------------------------------------------------

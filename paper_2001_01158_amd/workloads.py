@@ -333,3 +333,86 @@ def heat2d_initial(nx: int, ny: int) -> np.ndarray:
     unit square, row-major (y slowest)."""
     x = (np.arange(nx) + 0.5) / nx
     return np.ascontiguousarray(np.tile(np.exp(-100.0 * x) * HEAT_T_LEFT + HEAT_T_RIGHT, ny))
+
+
+# ---------------------------------------------------------------------------
+# Multi-group batch (Section 3.3, Algorithm 7): G decoupled group systems
+# ---------------------------------------------------------------------------
+MG_EPS = 1e-8              # linear tolerance of the paper's multi-group test
+MG_ALPHA = 1e-10           # gradient threshold of the gradient-based method there
+MG_E_MAX = 1
+
+
+@dataclasses.dataclass
+class MGBatch:
+    name: str
+    nx: int
+    ny: int
+    G: int
+    coef: np.ndarray       # (G, 5, N) nine-point operators
+    b: np.ndarray          # (G, N)
+    x0: np.ndarray         # (G, N) previous state of each group
+    kappa: np.ndarray      # (G,) diffusion coefficient per group
+
+
+def _scipy_matrix(kind: int, nx: int, ny: int, nz: int, coef: np.ndarray):
+    """The full symmetric matrix of a stencil coefficient set (scipy CSR), to
+    generate previous states by a direct solve."""
+    import scipy.sparse as sp
+    n = nx * ny * nz
+    c = np.asarray(coef).reshape(N_ARRAYS[kind], n)
+    idx = np.arange(n).reshape(nz, ny, nx)
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [c[0]]
+
+    def couple(arr, src, dst):
+        rows.extend([src, dst])
+        cols.extend([dst, src])
+        vals.extend([arr[src], arr[src]])
+
+    couple(c[1], idx[:, :, :-1].ravel(), idx[:, :, 1:].ravel())            # E
+    couple(c[2], idx[:, :-1, :].ravel(), idx[:, 1:, :].ravel())            # N
+    if kind == KIND_9PT:
+        couple(c[3], idx[:, :-1, :-1].ravel(), idx[:, 1:, 1:].ravel())     # NE
+        couple(c[4], idx[:, :-1, 1:].ravel(), idx[:, 1:, :-1].ravel())     # NW
+    if kind == KIND_7PT:
+        couple(c[3], idx[:-1].ravel(), idx[1:].ravel())                    # U
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n))
+
+
+def mg_batch(nx: int = 88, ny: int = 80, G: int = 64, dt: float = 1.0, sigma: float = 1.0,
+             kappa_lo: float = 0.1, kappa_hi: float = 316.0, radius: float = 6.0,
+             shift: float = 3.0, seed: int = BASE_SEED + 6) -> MGBatch:
+    """The G group systems of one source iteration: nx x ny = 7040 cells (the
+    paper's cell count), nine-point operators (anisotropy 4 at 30 degrees,
+    standing in for a deforming mesh), A_g = (1/dt + sigma) I + kappa_g L with
+    kappa_g log-spaced from kappa_lo to kappa_hi (higher groups diffuse
+    further, so their local domains grow, as the paper reports).
+
+    x0_g is the steady state of a disk source of strength Q_g (log-normal per
+    group) at c0: (sigma I + kappa_g L) x0_g = q(c0).  The new system has the
+    disk moved by `shift` cells: b_g = x0_g / dt + q(c1), so
+    A_g (x_g - x0_g) = q(c1) - q(c0): the change is driven by the source's
+    move alone and spreads over sqrt(kappa_g / (1/dt + sigma)) cells."""
+    import scipy.sparse.linalg as spla
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    kappa = np.exp(np.linspace(np.log(kappa_lo), np.log(kappa_hi), G))
+    qg = np.exp(rng.normal(0.0, 0.5, G))
+    lap = assemble_9pt(nx, ny, 0.0, 4.0, 30.0)          # L alone (zero mass)
+    c0 = (nx / 2.0 - shift / 2.0, ny / 2.0)
+    c1 = (nx / 2.0 + shift / 2.0, ny / 2.0)
+    coef = np.empty((G, 5, n))
+    b = np.empty((G, n))
+    x0 = np.empty((G, n))
+    for g in range(G):
+        L = kappa[g] * lap
+        ss = L.copy()
+        ss[0] += sigma
+        q0 = disk_source(nx, ny, c0[0], c0[1], radius, qg[g])
+        q1 = disk_source(nx, ny, c1[0], c1[1], radius, qg[g])
+        x0[g] = spla.spsolve(_scipy_matrix(KIND_9PT, nx, ny, 1, ss).tocsc(), q0)
+        coef[g] = L
+        coef[g, 0] += 1.0 / dt + sigma
+        b[g] = x0[g] / dt + q1
+    return MGBatch(f"mg{G}_{nx}x{ny}_9pt", nx, ny, G, coef, b, x0, kappa)
