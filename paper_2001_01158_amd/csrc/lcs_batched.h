@@ -65,6 +65,126 @@ __device__ __forceinline__ Stencil7<real> shifted(Stencil7<real> A, int64_t off)
     return A;
 }
 
+// Branch-free neighbour table of one stencil row.  Slot k runs over the
+// row's entries in ascending column order (the order of for_each): column
+// j[k] (the row itself where the neighbour is missing), ok[k] whether it
+// exists, and coef() loads the coefficients at those clamped positions, so
+// every load of a row is unconditional and independent of the others (many
+// in flight at once), while the sums skip the missing slots exactly as
+// for_each does.
+template <class S>
+struct RowN;
+
+template <typename real>
+struct RowN<Stencil5<real>> {
+    static constexpr int NB = 5, kC = 2;
+    int32_t j[NB];   // fits: at most 2^24 cells per system
+    bool ok[NB];
+    __device__ __forceinline__ RowN(const Stencil5<real> &A, int64_t i) {
+        const int y = (int)((uint32_t)i / (uint32_t)A.nx), x = (int)i - y * A.nx;
+        ok[0] = y > 0;
+        ok[1] = x > 0;
+        ok[2] = true;
+        ok[3] = x < A.nx - 1;
+        ok[4] = y < A.ny - 1;
+        const int32_t ii = (int32_t)i, nx = A.nx;
+        const int32_t d[NB] = {-nx, -1, 0, 1, nx};
+#pragma unroll
+        for (int k = 0; k < NB; ++k) j[k] = ok[k] ? ii + d[k] : ii;
+    }
+    __device__ __forceinline__ void coef(const Stencil5<real> &A, int64_t i, double (&a)[NB]) const {
+        a[0] = A.N[j[0]];
+        a[1] = A.E[j[1]];
+        a[2] = A.C[i];
+        a[3] = A.E[i];
+        a[4] = A.N[i];
+    }
+};
+
+template <typename real>
+struct RowN<Stencil9<real>> {
+    static constexpr int NB = 9, kC = 4;
+    int32_t j[NB];   // fits: at most 2^24 cells per system
+    bool ok[NB];
+    __device__ __forceinline__ RowN(const Stencil9<real> &A, int64_t i) {
+        const int y = (int)((uint32_t)i / (uint32_t)A.nx), x = (int)i - y * A.nx;
+        const bool w = x > 0, e = x < A.nx - 1, s = y > 0, n = y < A.ny - 1;
+        ok[0] = s && w;
+        ok[1] = s;
+        ok[2] = s && e;
+        ok[3] = w;
+        ok[4] = true;
+        ok[5] = e;
+        ok[6] = n && w;
+        ok[7] = n;
+        ok[8] = n && e;
+        const int32_t ii = (int32_t)i, nx = A.nx;
+        const int32_t d[NB] = {-nx - 1, -nx, -nx + 1, -1, 0, 1, nx - 1, nx, nx + 1};
+#pragma unroll
+        for (int k = 0; k < NB; ++k) j[k] = ok[k] ? ii + d[k] : ii;
+    }
+    __device__ __forceinline__ void coef(const Stencil9<real> &A, int64_t i, double (&a)[NB]) const {
+        a[0] = A.NE[j[0]];
+        a[1] = A.N[j[1]];
+        a[2] = A.NW[j[2]];
+        a[3] = A.E[j[3]];
+        a[4] = A.C[i];
+        a[5] = A.E[i];
+        a[6] = A.NW[i];
+        a[7] = A.N[i];
+        a[8] = A.NE[i];
+    }
+};
+
+template <typename real>
+struct RowN<Stencil7<real>> {
+    static constexpr int NB = 7, kC = 3;
+    int32_t j[NB];   // fits: at most 2^24 cells per system
+    bool ok[NB];
+    __device__ __forceinline__ RowN(const Stencil7<real> &A, int64_t i) {
+        const int64_t pl = (int64_t)A.nx * A.ny;
+        const int z = (int)((uint64_t)i / (uint64_t)pl);
+        const int r = (int)(i - (int64_t)z * pl);
+        const int y = (int)((uint32_t)r / (uint32_t)A.nx), x = r - y * A.nx;
+        ok[0] = z > 0;
+        ok[1] = y > 0;
+        ok[2] = x > 0;
+        ok[3] = true;
+        ok[4] = x < A.nx - 1;
+        ok[5] = y < A.ny - 1;
+        ok[6] = z < A.nz - 1;
+        const int32_t ii = (int32_t)i, nx = A.nx, p32 = (int32_t)pl;
+        const int32_t d[NB] = {-p32, -nx, -1, 0, 1, nx, p32};
+#pragma unroll
+        for (int k = 0; k < NB; ++k) j[k] = ok[k] ? ii + d[k] : ii;
+    }
+    __device__ __forceinline__ void coef(const Stencil7<real> &A, int64_t i, double (&a)[NB]) const {
+        a[0] = A.U[j[0]];
+        a[1] = A.N[j[1]];
+        a[2] = A.E[j[2]];
+        a[3] = A.C[i];
+        a[4] = A.E[i];
+        a[5] = A.N[i];
+        a[6] = A.U[i];
+    }
+};
+
+// sum over the row's existing entries in ascending column order:
+// acc = fma(sign * a_k, v[j_k], acc)
+template <class S, int kSign>
+__device__ __forceinline__ double row_fma(const S &A, int64_t i, const double *v, double acc) {
+    const RowN<S> R(A, i);
+    constexpr int NB = RowN<S>::NB;
+    double a[NB], w[NB];
+    R.coef(A, i, a);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) w[k] = v[R.j[k]];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        if (R.ok[k]) acc = fma(kSign > 0 ? a[k] : -a[k], w[k], acc);
+    return acc;
+}
+
 // Workgroup reduction of NV values (bit k of the Ops mask: value k is a max);
 // the result is in every thread, identical in all of them (every thread
 // combines the wave results in the same order).
@@ -142,10 +262,10 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
     int it = 0;
     while (it < max_iter) {
         double pq[1] = {0.0};
+#pragma unroll 4
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
-            double acc = 0.0;
-            A.for_each(i, [&](int64_t l, double a) { acc = fma(a, p[l], acc); });
+            const double acc = row_fma<S, 1>(A, i, p, 0.0);
             q[i] = acc;
             pq[0] += p[i] * acc;
         }
@@ -156,6 +276,7 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
         }
         const double alpha = rz / pq[0];
         double w[2] = {0.0, 0.0};
+#pragma unroll 4
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
             sol[i] = fma(alpha, p[i], sol[i]);
@@ -177,6 +298,7 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
         }
         const double beta = w[1] / rz;
         rz = w[1];
+#pragma unroll 4
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
             const double z = kPc ? r[i] / A.diag(i) : r[i];
@@ -193,9 +315,9 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
 template <class S>
 __device__ double wg_residual(const S &A, const double *__restrict__ b, const double *x, double *r) {
     double v[1] = {0.0};
+#pragma unroll 4
     for (int64_t i = threadIdx.x; i < A.n; i += kBatchBlock) {
-        double acc = b[i];
-        A.for_each(i, [&](int64_t l, double a) { acc = fma(-a, x[l], acc); });
+        const double acc = row_fma<S, -1>(A, i, x, b[i]);
         r[i] = acc;
         v[0] += acc * acc;
     }
@@ -262,20 +384,28 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
 
     // ---- r0 = b - A x0; ||b||^2, ||r0||^2, max |score| (Algorithms 2, 3) ----
     double v[3] = {0.0, 0.0, 0.0};
+    using RN = RowN<S>;
     for (int64_t i = tid; i < n; i += kBatchBlock) {
         const double bi = b[i];
+        const RN R(A, i);
+        double cf[RN::NB], xv[RN::NB];
+        R.coef(A, i, cf);
+#pragma unroll
+        for (int k = 0; k < RN::NB; ++k) xv[k] = x[R.j[k]];
         double acc = bi;
-        A.for_each(i, [&](int64_t l, double c) { acc = fma(-c, x[l], acc); });
+#pragma unroll
+        for (int k = 0; k < RN::NB; ++k)
+            if (R.ok[k]) acc = fma(-cf[k], xv[k], acc);
         r[i] = acc;
         v[1] += bi * bi;
         v[2] += acc * acc;
         double s = acc;
         if (a.local && a.mode == LCS_MODE_GRADIENT) {
-            const double xi = x[i];
+            const double xi = xv[RN::kC];
             double gsum = 0.0;
-            A.for_each(i, [&](int64_t l, double) {
-                if (l != i) gsum += fabs(xi - x[l]);
-            });
+#pragma unroll
+            for (int k = 0; k < RN::NB; ++k)
+                if (R.ok[k] && k != RN::kC) gsum += fabs(xi - xv[k]);
             s = gsum;
             q[i] = gsum;   // q holds the gradient score until the local PCG
         }
@@ -318,15 +448,24 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
             double added[1] = {0.0};
             for (int64_t j = tid; j < n; j += kBatchBlock) {
                 if (stamp[j] != 0) continue;
+                const RN R(A, j);
+                double cf[RN::NB], xv[RN::NB];
+                int sl[RN::NB];
+                R.coef(A, j, cf);
+#pragma unroll
+                for (int k = 0; k < RN::NB; ++k) {
+                    xv[k] = x[R.j[k]];
+                    sl[k] = stamp[R.j[k]];
+                }
                 bool nb = false;
                 double acc = fabs(r[j]);
-                A.for_each(j, [&](int64_t l, double c) {
-                    const int sl = stamp[l];
-                    if (l != j && sl != 0 && sl <= m) {
+#pragma unroll
+                for (int k = 0; k < RN::NB; ++k) {
+                    if (R.ok[k] && k != RN::kC && sl[k] != 0 && sl[k] <= m) {
                         nb = true;
-                        acc += fabs(c * x[l]);
+                        acc += fabs(cf[k] * xv[k]);
                     }
-                });
+                }
                 if (nb && acc > tau) {
                     stamp[j] = (uint8_t)(m + 1);
                     added[0] += 1.0;
@@ -370,12 +509,16 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
             for (int c = 0; c < S::kColours; ++c) {
                 for (int64_t i = tid; i < n; i += kBatchBlock) {
                     if (A.colour(i) != c) continue;
-                    double acc = b[i], dd = 1.0;
-                    A.for_each(i, [&](int64_t l, double cf) {
-                        if (l == i) dd = cf;
-                        else acc = fma(-cf, x[l], acc);
-                    });
-                    x[i] = acc / dd;
+                    const RN R(A, i);
+                    double cf[RN::NB], xv[RN::NB];
+                    R.coef(A, i, cf);
+#pragma unroll
+                    for (int k = 0; k < RN::NB; ++k) xv[k] = x[R.j[k]];
+                    double acc = b[i];
+#pragma unroll
+                    for (int k = 0; k < RN::NB; ++k)
+                        if (R.ok[k] && k != RN::kC) acc = fma(-cf[k], xv[k], acc);
+                    x[i] = acc / cf[RN::kC];
                 }
                 __syncthreads();
             }
