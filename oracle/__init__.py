@@ -29,6 +29,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 MODE_RESIDUAL, MODE_GRADIENT = 0, 1
 TH_RELMAX, TH_ABS, TH_PAPER = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_SGS = 0, 1, 2
+KRYLOV_CG, KRYLOV_GMRES = 0, 1
 OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN = 0, 1, 3, 4, 5
 
 
@@ -52,7 +53,7 @@ D = ctypes.c_double
 
 class _Opts(ctypes.Structure):
     _fields_ = [("eps", D), ("tol_local", D), ("max_iter", I32), ("pc", I32),
-                ("n_smooth", I32), ("max_restart", I32)]
+                ("n_smooth", I32), ("max_restart", I32), ("krylov", I32), ("gmres_m", I32)]
 
 
 class _Stats(ctypes.Structure):
@@ -86,6 +87,7 @@ def lib():
         L.orc_restricted.argtypes = [P, P, P, P, I64, P, P, P, P]
         L.orc_restricted.restype = None
         L.orc_pcg.argtypes = [I64, P, P, P, P, P, I32, P, I32, D, I32, P, P]
+        L.orc_gmres.argtypes = [I64, P, P, P, P, P, I32, I32, D, I32, P, P]
         L.orc_gs_sweeps.argtypes = [I64, P, P, P, P, P, P, I32, I32]
         L.orc_gs_sweeps.restype = None
         L.orc_solve_global.argtypes = [I64, P, P, P, P, P, P, I32, P, P]
@@ -232,6 +234,19 @@ def pcg(A: CSR, b, x0, pc: int = PC_JACOBI, tol_abs: float = 1e-10, max_iter: in
     return x, st, it.value, res.value
 
 
+def gmres(A: CSR, b, x0, pc: int = PC_JACOBI, m: int = 40, tol_abs: float = 1e-10,
+          max_iter: int = 10000):
+    """Restarted GMRES(m), right-preconditioned.  Returns (x, status,
+    iterations, last residual estimate)."""
+    b = _f64(b)
+    x = _f64(x0).copy()
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    st = lib().orc_gmres(A.n, _p(A.rp), _p(A.col), _p(A.val), _p(b), _p(x), pc, m, tol_abs,
+                         max_iter, ctypes.byref(it), ctypes.byref(res))
+    return x, st, it.value, res.value
+
+
 def gs_sweeps(A: CSR, b, x, n_sweeps: int = 1) -> np.ndarray:
     b = _f64(b)
     x = _f64(x).copy()
@@ -248,10 +263,13 @@ class Options:
     pc: int = PC_JACOBI
     n_smooth: int = 1
     max_restart: int = 3
+    krylov: int = KRYLOV_CG       # KRYLOV_GMRES for a non-symmetric A
+    gmres_m: int = 40             # GMRES restart length
 
     def c(self) -> _Opts:
         return _Opts(self.eps, self.eps if self.tol_local is None else self.tol_local,
-                     self.max_iter, self.pc, self.n_smooth, self.max_restart)
+                     self.max_iter, self.pc, self.n_smooth, self.max_restart, self.krylov,
+                     self.gmres_m)
 
 
 @dataclasses.dataclass

@@ -42,6 +42,7 @@
 #define ORC_K5 0
 #define ORC_K9 1
 #define ORC_K7 2
+#define ORC_K9N 3 /* nine-point, full storage: array s = slot s of each row */
 
 /* local-domain construction */
 #define ORC_MODE_RESIDUAL 0 /* Section 2.3, Algorithm 3 */
@@ -69,6 +70,7 @@ static int stencil_offsets(int kind, const int (**off)[3]) {
     switch (kind) {
     case ORC_K5: *off = OFF5; return 5;
     case ORC_K9: *off = OFF9; return 9;
+    case ORC_K9N: *off = OFF9; return 9;
     case ORC_K7: *off = OFF7; return 7;
     default: return 0;
     }
@@ -80,6 +82,7 @@ static int stencil_offsets(int kind, const int (**off)[3]) {
 static double stencil_value(int kind, const double *coef, int64_t n, int64_t p,
                             int dx, int dy, int dz, int64_t sx, int64_t sy) {
     int64_t q = p + dx + dy * sx + dz * sy;
+    if (kind == ORC_K9N) return coef[(int64_t)((dy + 1) * 3 + (dx + 1)) * n + p];
     if (dx == 0 && dy == 0 && dz == 0) return coef[p];
     const double *E = coef + n, *N = coef + 2 * n;
     if (dz == 0 && dy == 0) return dx > 0 ? E[p] : E[q];
@@ -142,9 +145,10 @@ int orc_grid_colours(int kind, int nx, int ny, int nz, int8_t *colour) {
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 int64_t p = x + (int64_t)nx * y + (int64_t)nx * ny * z;
-                colour[p] = (int8_t)(kind == ORC_K9 ? (x & 1) + 2 * (y & 1) : (x + y + z) & 1);
+                colour[p] = (int8_t)(kind == ORC_K9 || kind == ORC_K9N ? (x & 1) + 2 * (y & 1)
+                                                                      : (x + y + z) & 1);
             }
-    return kind == ORC_K9 ? 4 : 2;
+    return kind == ORC_K9 || kind == ORC_K9N ? 4 : 2;
 }
 
 /* ------------------------------------------------------------------ */
@@ -418,6 +422,106 @@ void orc_gs_sweeps(int64_t n, const int64_t *rp, const int32_t *col, const doubl
         for (int c = 0; c < ncol; ++c) gs_colour(n, rp, col, val, b, x, colour, c);
 }
 
+/*
+ * Restarted GMRES(m) for a general (non-symmetric) A, the Krylov method of
+ * the paper's experiments (Section 3), right-preconditioned:
+ * A M^-1 u = r0, x = x0 + M^-1 u, with M = diag(A) (ORC_PC_JACOBI) or I.
+ * Each cycle: r = b - A x, beta = ||r||; stop if beta <= tol_abs;
+ * v_0 = r / beta, g = beta e_1; for j = 0..m-1: w = A M^-1 v_j; modified
+ * Gram-Schmidt h_ij = v_i . w, w -= h_ij v_i (i = 0..j); h_{j+1,j} = ||w||;
+ * the Givens rotations of columns 0..j-1 are applied to column j, a new one
+ * (c, s) = (h_jj, h_{j+1,j}) / sqrt(h_jj^2 + h_{j+1,j}^2) zeroes h_{j+1,j}
+ * and g_{j+1} = -s g_j, g_j = c g_j; |g_{j+1}| is ||b - A x_j||; stop the
+ * cycle when it is <= tol_abs, when h_{j+1,j} = 0, or after m steps;
+ * v_{j+1} = w / h_{j+1,j}.  Then H y = g by back substitution over the k
+ * columns, and x += M^-1 (sum_i y_i v_i).  Cycles repeat until the estimate
+ * meets tol_abs or max_iter steps were taken.
+ * Returns ORC_OK, ORC_ENOCONV or ORC_EBREAKDOWN (a zero column: singular
+ * A M^-1); *iters = Arnoldi steps, *res = the last residual estimate.
+ */
+int orc_gmres(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const double *b,
+              double *x, int pc, int m, double tol_abs, int max_iter, int *iters, double *res) {
+    *iters = 0;
+    *res = 0.0;
+    if (n == 0) return ORC_OK;
+    if (m < 1) m = 1;
+    double *V = malloc(sizeof(double) * (size_t)(m + 1) * n);
+    double *w = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
+    double *diag = malloc(sizeof(double) * n);
+    double *H = calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = malloc(sizeof(double) * m), *sn = malloc(sizeof(double) * m);
+    double *g = malloc(sizeof(double) * (m + 1)), *y = malloc(sizeof(double) * m);
+    if (!V || !w || !z || !diag || !H || !cs || !sn || !g || !y) {
+        free(V); free(w); free(z); free(diag); free(H); free(cs); free(sn); free(g); free(y);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) diag[i] = diag_of(rp, col, val, i);
+#define HH(i, j) H[(size_t)(j) * (m + 1) + (i)]
+    int status = ORC_ENOCONV, it = 0;
+    for (;;) {
+        orc_residual(n, rp, col, val, b, x, w);
+        double beta = orc_norm2(n, w);
+        *res = beta;
+        if (beta <= tol_abs) { status = ORC_OK; break; }
+        if (it >= max_iter) break;
+        for (int64_t i = 0; i < n; ++i) V[i] = w[i] / beta;
+        for (int q = 0; q <= m; ++q) g[q] = 0.0;
+        g[0] = beta;
+        int k = 0, stop = 0;
+        for (int j = 0; j < m && it < max_iter; ++j) {
+            const double *vj = V + (size_t)j * n;
+            for (int64_t i = 0; i < n; ++i) z[i] = pc == ORC_PC_JACOBI ? vj[i] / diag[i] : vj[i];
+            orc_spmv(n, rp, col, val, z, w);
+            for (int i = 0; i <= j; ++i) {
+                const double *vi = V + (size_t)i * n;
+                double h = orc_dot(n, vi, w);
+                HH(i, j) = h;
+                for (int64_t l = 0; l < n; ++l) w[l] = fma(-h, vi[l], w[l]);
+            }
+            double hn = orc_norm2(n, w);
+            HH(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                double t = cs[i] * HH(i, j) + sn[i] * HH(i + 1, j);
+                HH(i + 1, j) = -sn[i] * HH(i, j) + cs[i] * HH(i + 1, j);
+                HH(i, j) = t;
+            }
+            double a = HH(j, j), bb = HH(j + 1, j);
+            double den = sqrt(a * a + bb * bb);
+            ++it;
+            if (!(den > 0.0)) { status = ORC_EBREAKDOWN; stop = 2; k = j; break; }
+            cs[j] = a / den;
+            sn[j] = bb / den;
+            HH(j, j) = den;
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            *res = fabs(g[j + 1]);
+            k = j + 1;
+            if (*res <= tol_abs || hn == 0.0) { stop = 1; break; }
+            double *vn = V + (size_t)(j + 1) * n;
+            for (int64_t l = 0; l < n; ++l) vn[l] = w[l] / hn;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int l = i + 1; l < k; ++l) acc -= HH(i, l) * y[l];
+            y[i] = acc / HH(i, i);
+        }
+        for (int64_t l = 0; l < n; ++l) {
+            double u = 0.0;
+            for (int q = 0; q < k; ++q) u = fma(y[q], V[(size_t)q * n + l], u);
+            if (pc == ORC_PC_JACOBI) u = u / diag[l];
+            x[l] += u;
+        }
+        if (stop == 2) break;
+        if (stop == 1) { status = ORC_OK; break; }
+        if (it >= max_iter) break;
+    }
+#undef HH
+    *iters = it;
+    free(V); free(w); free(z); free(diag); free(H); free(cs); free(sn); free(g); free(y);
+    return status;
+}
+
 /* ------------------------------------------------------------------ */
 /* Algorithm 1                                                         */
 /* ------------------------------------------------------------------ */
@@ -427,8 +531,23 @@ typedef struct {
     int max_iter;
     int pc;           /* ORC_PC_* */
     int n_smooth;     /* GS sweeps applied to x~ */
-    int max_restart;  /* global PCG restarts after a failed true-residual check */
+    int max_restart;  /* global restarts after a failed true-residual check */
+    int krylov;       /* ORC_KRYLOV_CG (SPD A) or ORC_KRYLOV_GMRES (any A) */
+    int gmres_m;      /* GMRES restart length */
 } orc_opts;
+
+#define ORC_KRYLOV_CG 0
+#define ORC_KRYLOV_GMRES 1
+
+/* The Krylov solve of Algorithm 1's local and global steps: PCG for SPD A,
+ * GMRES(m) otherwise (same arguments). */
+static int orc_krylov(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+                      const double *b, double *x, const orc_opts *o, const int8_t *colour,
+                      int ncol, double tol_abs, int max_iter, int *iters, double *res) {
+    if (o->krylov == ORC_KRYLOV_GMRES)
+        return orc_gmres(n, rp, col, val, b, x, o->pc, o->gmres_m, tol_abs, max_iter, iters, res);
+    return orc_pcg(n, rp, col, val, b, x, o->pc, colour, ncol, tol_abs, max_iter, iters, res);
+}
 
 typedef struct {
     int64_t K;
@@ -448,7 +567,7 @@ int orc_solve_global(int64_t n, const int64_t *rp, const int32_t *col, const dou
     st->restarts = 0;
     for (int attempt = 0;; ++attempt) {
         int it; double res;
-        status = orc_pcg(n, rp, col, val, b, x, o->pc, colour, ncol, tol, o->max_iter - total, &it, &res);
+        status = orc_krylov(n, rp, col, val, b, x, o, colour, ncol, tol, o->max_iter - total, &it, &res);
         total += it;
         orc_residual(n, rp, col, val, b, x, r);
         double tr = orc_norm2(n, r);
@@ -492,8 +611,8 @@ int orc_solve_local(int64_t n, const int64_t *rp, const int32_t *col, const doub
             bcolour[k] = colour ? colour[idx[k]] : 0;
         }
         int it; double res;
-        st->status_local = orc_pcg(K, brp, bcol, bval, rhs, d, o->pc, bcolour, ncol,
-                                   o->tol_local * nb, o->max_iter, &it, &res);
+        st->status_local = orc_krylov(K, brp, bcol, bval, rhs, d, o, bcolour, ncol,
+                                      o->tol_local * nb, o->max_iter, &it, &res);
         st->its_local = it;
         for (int64_t k = 0; k < K; ++k) x[idx[k]] += d[k];
         free(inv); free(r); free(brp); free(bcol); free(bval); free(rhs); free(d); free(bcolour);

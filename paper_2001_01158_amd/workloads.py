@@ -41,8 +41,9 @@ import numpy as np
 KIND_5PT = 0
 KIND_9PT = 1
 KIND_7PT = 2
-KIND_NAMES = {KIND_5PT: "5pt", KIND_9PT: "9pt", KIND_7PT: "7pt"}
-N_ARRAYS = {KIND_5PT: 3, KIND_9PT: 5, KIND_7PT: 4}
+KIND_9N = 3       # nine-point, full storage (non-symmetric)
+KIND_NAMES = {KIND_5PT: "5pt", KIND_9PT: "9pt", KIND_7PT: "7pt", KIND_9N: "9n"}
+N_ARRAYS = {KIND_5PT: 3, KIND_9PT: 5, KIND_7PT: 4, KIND_9N: 9}
 
 BASE_SEED = 20010115
 
@@ -264,6 +265,74 @@ def c3_aniso_front(nx: int = 4096, ny: int = 4096, dt: float = 4.0, ratio: float
     return Workload(f"c3_aniso9_{nx}x{ny}", KIND_9PT, nx, ny, 1, dt, coef, n_systems,
                     rhs, np.zeros(nx * ny), None, theta_res=1e-3, e_max=1,
                     precision="mixed", precond="jacobi")
+
+
+def full_from_symmetric9(nx: int, ny: int, sym: np.ndarray) -> np.ndarray:
+    """Full storage (9, N) of a symmetric nine-point operator given in
+    symmetric storage (C, E, N, NE, NW): slot s of row i holds a(i, j_s) for
+    the neighbours SW, S, SE, W, C, E, NW, N, NE; zero outside the grid."""
+    c, e, nn, ne, nw = (np.asarray(a).reshape(ny, nx) for a in sym)
+    f = np.zeros((9, ny, nx))
+    f[0][1:, 1:] = ne[:-1, :-1]        # SW: the NE coupling of (x-1, y-1)
+    f[1][1:, :] = nn[:-1, :]           # S
+    f[2][1:, :-1] = nw[:-1, 1:]        # SE: the NW coupling of (x+1, y-1)
+    f[3][:, 1:] = e[:, :-1]            # W
+    f[4] = c
+    f[5][:, :-1] = e[:, :-1]           # E
+    f[6][:-1, 1:] = nw[:-1, 1:]        # NW
+    f[7][:-1, :] = nn[:-1, :]          # N
+    f[8][:-1, :-1] = ne[:-1, :-1]      # NE
+    return f.reshape(9, nx * ny)
+
+
+def assemble_9n(nx: int, ny: int, inv_dt: float, ratio: float = 4.0, angle_deg: float = 30.0,
+                speed: float = 2.0) -> np.ndarray:
+    """Full-storage coefficients (9, N) of a non-symmetric nine-point
+    operator: the symmetric corner-gradient diffusion of assemble_9pt plus
+    first-order upwind convection by the rotating, divergence-free velocity
+    u = speed * (-(y - cy), x - cx) / (n / 2) (cells of size 1), standing in
+    for the convection-bearing schemes on deforming meshes of the paper's
+    application.  Face velocities are sampled at face centres; each face
+    adds max(u_f, 0) to the upwind cell's diagonal and min(u_f, 0) to its
+    coupling to the downwind cell."""
+    f = full_from_symmetric9(nx, ny, assemble_9pt(nx, ny, inv_dt, ratio, angle_deg))
+    f = f.reshape(9, ny, nx)
+    scale = speed / (0.5 * max(nx, ny))
+    cx, cy = nx / 2.0, ny / 2.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    ue = -scale * ((y + 0.5) - cy)          # x-velocity at the east face of each cell
+    vn = scale * ((x + 0.5) - cx)           # y-velocity at the north face of each cell
+    # east faces between (x, y) and (x+1, y)
+    a = ue[:, :-1]
+    f[4][:, :-1] += np.maximum(a, 0.0)
+    f[5][:, :-1] += np.minimum(a, 0.0)
+    f[4][:, 1:] += np.maximum(-a, 0.0)
+    f[3][:, 1:] += np.minimum(-a, 0.0)
+    # north faces between (x, y) and (x, y+1)
+    v = vn[:-1, :]
+    f[4][:-1, :] += np.maximum(v, 0.0)
+    f[7][:-1, :] += np.minimum(v, 0.0)
+    f[4][1:, :] += np.maximum(-v, 0.0)
+    f[1][1:, :] += np.minimum(-v, 0.0)
+    return np.ascontiguousarray(f.reshape(9, nx * ny))
+
+
+def c6_nonsym9(nx: int = 1024, ny: int = 1024, dt: float = 4.0, radius: float = 40.0,
+               speed: float = 4.0, q0: float = 1.0, n_systems: int = 20) -> Workload:
+    """2-D non-symmetric nine-point sequence (diffusion with anisotropy 4 at
+    30 degrees plus upwind convection in a rotating flow), disk source moving
+    `speed` cells per system; solved by GMRES(40)."""
+    inv_dt = 1.0 / dt
+    coef = assemble_9n(nx, ny, inv_dt)
+    x0c = nx / 4.0
+
+    def rhs(k: int, x_prev: np.ndarray) -> np.ndarray:
+        q = disk_source(nx, ny, x0c + speed * k, ny / 2.0, radius, q0)
+        return x_prev * inv_dt + q
+
+    return Workload(f"c6_nonsym9_{nx}x{ny}", KIND_9N, nx, ny, 1, dt, coef, n_systems,
+                    rhs, np.zeros(nx * ny), None, theta_res=1e-3, e_max=1,
+                    precision="fp64", precond="jacobi")
 
 
 def c4_adjoint(nx: int = 2048, ny: int = 2048, sigma: float = 1.0, dt: float = 4.0,

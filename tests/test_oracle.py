@@ -537,3 +537,106 @@ def test_heat_assembly_conducts_into_cold_cells():
     fl = (tl ** 3.5 + 1.0) * (tl - x[0, 0])          # inflow at x = 0
     fr = (tr ** 3.5 + 1e-14) * (x[0, -1] - tr)       # outflow at x = 1
     np.testing.assert_allclose(inv_dt * (x[0].sum() - t[:nx].sum()), fl - fr, rtol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# GMRES(m) for the non-symmetric nine-point operator (the paper's Krylov
+# method); the full-storage kind
+# ---------------------------------------------------------------------------
+def _nonsym_case(nx=9, ny=7, seed=11):
+    coef = W.assemble_9n(nx, ny, 0.25, speed=3.0)
+    A = oracle.csr_from_stencil(W.KIND_9N, nx, ny, 1, coef)
+    rng = np.random.default_rng(seed)
+    return coef, A, rng.standard_normal(A.n), rng.standard_normal(A.n)
+
+
+def test_full_storage_reproduces_symmetric_storage():
+    """The full-storage layout (slot s = SW..NE of each row) of a symmetric
+    nine-point operator gives the same matrix as its symmetric storage."""
+    nx, ny = 8, 6
+    sym = W.assemble_9pt(nx, ny, 0.3, 4.0, 30.0)
+    full = W.full_from_symmetric9(nx, ny, sym)
+    A1 = oracle.csr_from_stencil(W.KIND_9PT, nx, ny, 1, sym)
+    A3 = oracle.csr_from_stencil(W.KIND_9N, nx, ny, 1, full)
+    assert np.array_equal(A1.rp, A3.rp) and np.array_equal(A1.col, A3.col)
+    assert np.array_equal(A1.val, A3.val)
+    assert A3.ncolours == 4 and np.array_equal(A1.colour, A3.colour)
+
+
+@pytest.mark.parametrize("pc", [oracle.PC_NONE, oracle.PC_JACOBI])
+def test_gmres_minimises_the_residual_over_the_krylov_space(pc):
+    """After k steps without restart, GMRES's x minimises ||b - A x|| over
+    x0 + M^-1 K_k(A M^-1, r0).  The minimum is computed independently: an
+    orthonormal basis of the Krylov space by QR of the explicit power basis,
+    then a dense least-squares solve."""
+    coef, A, b, x0 = _nonsym_case()
+    a = A.dense()
+    minv = np.diag(1.0 / np.diag(a)) if pc == oracle.PC_JACOBI else np.eye(A.n)
+    am = a @ minv
+    r0 = b - a @ x0
+    for k in range(1, 8):
+        x, st, it, res = oracle.gmres(A, b, x0, pc, m=40, tol_abs=0.0, max_iter=k)
+        assert it == k and st == oracle.ENOCONV
+        kry = np.stack([np.linalg.matrix_power(am, i) @ r0 for i in range(k)], axis=1)
+        q, _ = np.linalg.qr(kry)
+        c, *_ = np.linalg.lstsq(am @ q, r0, rcond=None)
+        best = np.linalg.norm(r0 - am @ q @ c)
+        got = np.linalg.norm(b - a @ x)
+        assert got == pytest.approx(best, rel=1e-9)
+        assert res == pytest.approx(got, rel=1e-8)   # the estimate is the true residual
+
+
+def test_gmres_terminates_within_n_steps():
+    """In exact arithmetic GMRES without restart terminates in at most n
+    steps; here n = 35 < m = 40, so it reaches 1e-12 relative within n steps
+    and matches the dense solve."""
+    coef, A, b, x0 = _nonsym_case(7, 5)
+    x, st, it, res = oracle.gmres(A, b, x0, oracle.PC_JACOBI, m=40,
+                                  tol_abs=1e-12 * np.linalg.norm(b), max_iter=100)
+    assert st == oracle.OK and it <= A.n
+    xd = np.linalg.solve(A.dense(), b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+
+
+def test_restarted_gmres_converges_and_residuals_do_not_grow():
+    """GMRES(5) with restarts on a 16 x 16 convection-diffusion system: the
+    residual estimate at the end of each cycle never grows, and the method
+    reaches the tolerance."""
+    coef, A, b, x0 = _nonsym_case(16, 16, seed=3)
+    a = A.dense()
+    tol = 1e-10 * np.linalg.norm(b)
+    last = np.inf
+    x = x0
+    for cycle in range(200):
+        x, st, it, res = oracle.gmres(A, b, x, oracle.PC_JACOBI, m=5, tol_abs=tol, max_iter=5)
+        true = np.linalg.norm(b - a @ x)
+        assert true <= last * (1 + 1e-12)
+        last = true
+        if st == oracle.OK:
+            break
+    assert st == oracle.OK and np.linalg.norm(b - a @ x) <= 1.0001 * tol
+
+
+def test_local_then_global_with_gmres():
+    """Algorithm 1 on a non-symmetric sequence system with GMRES for the
+    local and the global solves meets the criterion; with an empty domain
+    and no smoothing it is the global GMRES bit for bit."""
+    w = W.c6_nonsym9(nx=48, ny=40, radius=5.0, speed=2.0, n_systems=3)
+    A = oracle.csr_from_stencil(W.KIND_9N, w.nx, w.ny, 1, w.coef)
+    a = A.dense()
+    x = w.x_start
+    for k in range(2):
+        x = np.linalg.solve(a, w.rhs(k, x))
+    b = w.rhs(2, x)
+    opts = oracle.Options(eps=1e-10, krylov=oracle.KRYLOV_GMRES)
+    for mode, theta, th in [(oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX),
+                            (oracle.MODE_GRADIENT, 1e-4, oracle.TH_RELMAX)]:
+        xo, st, dom = oracle.local_then_global(A, b, x, mode, theta, th, 1, opts)
+        assert st.status == oracle.OK and 0 < dom.K < A.n
+        assert np.linalg.norm(b - a @ xo) <= 1.0001e-10 * np.linalg.norm(b)
+    o0 = oracle.Options(eps=1e-10, krylov=oracle.KRYLOV_GMRES, n_smooth=0)
+    xg, sg = oracle.solve_global(A, b, x, o0)
+    xl, sl = oracle.solve_local(A, b, x, np.zeros(0, np.int32), o0)
+    assert np.array_equal(xl, x)
+    xl, sl2 = oracle.solve_global(A, b, xl, o0)
+    assert np.array_equal(xl, xg) and sl2.its_global == sg.its_global
