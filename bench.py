@@ -59,7 +59,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=40)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", choices=["c2", "c3", "c5"], default="c2")
+    p.add_argument("--workload", choices=["c2", "c3", "c5", "c6"], default="c2")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--skip-spmv-hbm", action="store_true")
@@ -102,6 +102,13 @@ def make_workload(name):
         desc = ("2D 4096x4096 9-point anisotropic (ratio 100, 30 deg), moving disk radius 350, "
                 "FP32 inner Jacobi-PCG + FP64 refinement to 1e-10; Algorithm 1, paper threshold")
         src = lambda k: W.disk_source(w.nx, w.ny, w.nx / 4.0 + 8.0 * k, w.ny / 2.0, 350.0, 1.0)
+    elif name == "c6":
+        w = W.c6_nonsym9(n_systems=12)
+        opts = dict(precond="jacobi", precision="fp64")
+        desc = ("2D 1024x1024 non-symmetric 9-point (anisotropic diffusion + upwind convection in "
+                "a rotating flow), disk radius 40 moving 4 cells/system, GMRES(40) with Jacobi, "
+                "FP64; Algorithm 1, paper threshold")
+        src = lambda k: W.disk_source(w.nx, w.ny, w.nx / 4.0 + 4.0 * k, w.ny / 2.0, 40.0, 1.0)
     else:
         w = W.c5_sphere3d(n_systems=12)
         opts = dict(precond="rbsgs", precision="mixed")
@@ -571,7 +578,7 @@ def main():
     # The headline step is dominated by the local PCG; its A p kernel on the
     # restricted ELL matrix is the larger of its two kernels.  Re-run the same
     # timed steps with that kernel bracketed by events on the solve's stream.
-    W_ell = {W.KIND_5PT: 5, W.KIND_9PT: 9, W.KIND_7PT: 7}[w.kind]
+    W_ell = {W.KIND_5PT: 5, W.KIND_9PT: 9, W.KIND_7PT: 7, W.KIND_9N: 9}[w.kind]
     real_b = 8 if okw["precision"] == "fp64" else 4
     if okw["precond"] == "rbsgs":
         # two-kernel PCG, q = B p kernel: ELL col+val, z and p_old in, p and q out
@@ -595,6 +602,8 @@ def main():
     traffic = None
     if mt and mt["src_sha256"] == kernel_sources_sha256():
         traffic = mt["ratio"] * bytes_per_launch
+    if w.kind == W.KIND_9N:
+        kname = "GMRES kernels (not bracketed by events; see the rocprofv3 kernel trace)"
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
             "traffic_unit": "bytes per launch", "traffic_ratio": mt["ratio"] if traffic else None,
@@ -618,7 +627,7 @@ def main():
     xs = torch.rand(n, dtype=torch.float64, device=dev)
     ys = torch.empty_like(xs)
     spmv_ms = time_spmv(A, xs, ys)
-    nb_row = {W.KIND_5PT: 40, W.KIND_9PT: 56, W.KIND_7PT: 48}[w.kind]
+    nb_row = {W.KIND_5PT: 40, W.KIND_9PT: 56, W.KIND_7PT: 48, W.KIND_9N: 88}[w.kind]
     spmv = {f"{args.workload}_fp64": {"n": n, "us": spmv_ms * 1e3, "GBs": n * nb_row / spmv_ms / 1e6,
                                       "bytes_per_row": nb_row}}
     hbm = None

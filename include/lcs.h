@@ -22,6 +22,16 @@
  *       7-point 3-D : C, E(+1,0,0), N(0,+1,0), U(0,0,+1)          (4 arrays)
  *     a backward coupling is the forward coupling stored at the neighbour.
  *     The sparsity pattern is every in-grid stencil neighbour.
+ *   - LCS_STENCIL9N_2D is the non-symmetric nine-point operator (for example
+ *     a deforming-mesh scheme with convection, Section 3.3) in full storage:
+ *     9 arrays, array s holding each row's own coefficient at slot s, slots
+ *     in ascending column order SW(-1,-1), S(0,-1), SE(+1,-1), W(-1,0), C,
+ *     E(+1,0), NW(-1,+1), N(0,+1), NE(+1,+1); entries whose neighbour lies
+ *     outside the grid are ignored.  Its solves (global, local, and the
+ *     global finish) use restarted GMRES(m), the paper's Krylov method,
+ *     right-preconditioned by Jacobi or nothing, in FP64; the criterion and
+ *     Algorithm 1 are unchanged.  Batched solves and the adjoint take the
+ *     symmetric kinds only.
  *   - Vector arguments are device pointers of length N = nx*ny*nz (FP64)
  *     owned by the caller; the library never frees them.  Index arrays are
  *     int32 (N < 2^31).
@@ -56,7 +66,7 @@ typedef enum lcs_status {
     LCS_ENONFINITE = 6    /* NaN / Inf in the input or the iteration              */
 } lcs_status;
 
-enum { LCS_STENCIL5_2D = 0, LCS_STENCIL9_2D = 1, LCS_STENCIL7_3D = 2 };
+enum { LCS_STENCIL5_2D = 0, LCS_STENCIL9_2D = 1, LCS_STENCIL7_3D = 2, LCS_STENCIL9N_2D = 3 };
 enum { LCS_MODE_RESIDUAL = 0, LCS_MODE_GRADIENT = 1 };
 enum {
     LCS_THRESH_REL_MAX = 0,  /* tau = theta * max_i |s_i|  (s = r^(0) or g)       */
@@ -89,6 +99,8 @@ typedef struct lcs_options {
     int32_t check_every;   /* PCG iterations between host convergence checks       */
     int32_t max_outer;     /* mixed: refinement steps; FP64: restarts after a
                               failed true-residual check                            */
+    int32_t restart;       /* GMRES restart length m (LCS_STENCIL9N_2D), 1..64;
+                              default 40                                            */
 } lcs_options;
 
 typedef struct lcs_stats {

@@ -16,6 +16,7 @@
 #include "lcs.h"
 #include "lcs_kernels.h"
 #include "lcs_batched.h"
+#include "lcs_gmres.h"
 
 using namespace lcs;
 
@@ -48,8 +49,10 @@ lcs_status fail(lcs_status s, const std::string &msg) {
             return fail(LCS_EHIP, std::string("launch: ") + hipGetErrorString(e_)); \
     } while (0)
 
-int n_arrays(int kind) { return kind == LCS_STENCIL5_2D ? 3 : kind == LCS_STENCIL9_2D ? 5 : 4; }
-int n_colours(int kind) { return kind == LCS_STENCIL9_2D ? 4 : 2; }
+int n_arrays(int kind) {
+    return kind == LCS_STENCIL5_2D ? 3 : kind == LCS_STENCIL9_2D ? 5 : kind == LCS_STENCIL9N_2D ? 9 : 4;
+}
+int n_colours(int kind) { return kind == LCS_STENCIL9_2D || kind == LCS_STENCIL9N_2D ? 4 : 2; }
 
 struct Launch {
     int grid;
@@ -122,7 +125,8 @@ enum BufId {
     B_SCORE, B_R, B_Z, B_P0, B_P1, B_Q, B_RHSL, B_DL, B_RES, B_STAMP, B_INV, B_IDX, B_BLOCKOFF,
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
     B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_W0, B_W1, B_S0, B_S1, B_W32A, B_W32B,
-    B_S32A, B_S32B, B_BWS, B_BSTAMP, B_BIDX, B_BOUT, B_NUM
+    B_S32A, B_S32B, B_BWS, B_BSTAMP, B_BIDX, B_BOUT, B_GMV, B_GMW0, B_GMW1, B_GMP0,
+    B_GMPN, B_GMS, B_NUM
 };
 
 }  // namespace
@@ -150,6 +154,8 @@ struct lcs_ctx {
     // pinned host copy of the per-system results of a batched solve
     BatchOut *hbout = nullptr;
     int32_t hbout_cap = 0;
+    // pinned host copy of the GMRES cycle state
+    GmState *hgm = nullptr;
 };
 
 namespace {
@@ -188,7 +194,7 @@ lcs_status read_scalars(lcs_ctx *c, hipStream_t s) {
 
 lcs_status check_matrix(const lcs_matrix *A) {
     if (!A) return fail(LCS_EINVAL, "matrix is NULL");
-    if (A->kind < 0 || A->kind > 2) return fail(LCS_EINVAL, "unknown matrix kind");
+    if (A->kind < 0 || A->kind > 3) return fail(LCS_EINVAL, "unknown matrix kind");
     if (A->nx < 1 || A->ny < 1 || A->nz < 1) return fail(LCS_EINVAL, "grid sizes must be >= 1");
     if (A->kind != LCS_STENCIL7_3D && A->nz != 1) return fail(LCS_EINVAL, "2-D stencil needs nz = 1");
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
@@ -204,8 +210,14 @@ lcs_status check_options(const lcs_options *o, int kind) {
         return fail(LCS_EINVAL, "negative iteration counts");
     if (o->precond < 0 || o->precond > 2) return fail(LCS_EINVAL, "unknown preconditioner");
     if (o->precision < 0 || o->precision > 1) return fail(LCS_EINVAL, "unknown precision");
-    if (o->precond == LCS_PC_RBSGS && kind == LCS_STENCIL9_2D)
+    if (o->precond == LCS_PC_RBSGS && (kind == LCS_STENCIL9_2D || kind == LCS_STENCIL9N_2D))
         return fail(LCS_EINVAL, "red-black SGS needs a 2-colourable stencil (5- or 7-point)");
+    if (kind == LCS_STENCIL9N_2D) {
+        if (o->precision != LCS_PREC_FP64)
+            return fail(LCS_EINVAL, "the non-symmetric operator is solved by GMRES in FP64");
+        if (o->restart < 1 || o->restart > kMaxRestart)
+            return fail(LCS_EINVAL, "GMRES restart length must be 1..64");
+    }
     return LCS_OK;
 }
 
@@ -229,6 +241,14 @@ template <typename real>
 Stencil9<real> sop9(const lcs_matrix *A, const real *c) {
     const int64_t n = (int64_t)A->nx * A->ny;
     return {c, c + n, c + 2 * n, c + 3 * n, c + 4 * n, A->nx, A->ny, n};
+}
+template <typename real>
+Stencil9N<real> sop9n(const lcs_matrix *A, const real *c) {
+    return {c, A->nx, A->ny, (int64_t)A->nx * A->ny};
+}
+template <typename real>
+U9N<real, 1> uop9n(const lcs_matrix *A, const real *c) {
+    return {c, A->nx, A->ny, (int64_t)A->nx * A->ny};
 }
 template <typename real>
 Stencil7<real> sop7(const lcs_matrix *A, const real *c) {
@@ -309,6 +329,10 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
         default: return f(s9, uop9<double, 2, 2>(t, A, A->coef), uop9<float, 4, 2>(t, A, coef32), Width<9>());
         }
     }
+    case LCS_STENCIL9N_2D:
+        // full storage, flat walk, one row per unit (GMRES vectors)
+        return f(sop9n<double>(A, A->coef), uop9n<double>(A, A->coef), uop9n<float>(A, coef32),
+                 Width<9>());
     default: {
         const auto s7 = sop7<double>(A, A->coef);
         if (!v) return f(s7, uop7<double, 1, 0>(t, A, A->coef), uop7<float, 1, 0>(t, A, coef32), Width<7>());
@@ -623,7 +647,7 @@ struct SolveOut {
 // left in saved_it[1] / saved_status[1] for the caller's next read (the
 // criterion that matters is the global one checked right after).
 template <class Op64, class Op32>
-lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, const double *rhs,
+lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, const double *rhs,
                         double *x, bool x_zero, const double *tol_base, double tol_factor,
                         const lcs_options *o, hipStream_t s, SolveOut *out, int scope) {
     const int64_t n = A.units() * Op64::V;
@@ -709,6 +733,122 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
     }
 }
 
+
+// Restarted GMRES(m) on a non-symmetric operator (see lcs_gmres.h): cycles
+// of at most m Arnoldi steps, enqueued in chunks of check_every steps with a
+// read of the done flag in between; after the residual estimate meets the
+// tolerance the true residual is checked, and a failed check restarts (at
+// most max_outer times), as for PCG.
+template <class Op, int kPc>
+lcs_status run_gmres_t(lcs_ctx *c, const Op &A, const double *rhs, double *x, bool x_zero,
+                       const double *tol_base, double tol_factor, const lcs_options *o,
+                       hipStream_t s, SolveOut *out) {
+    const int64_t n = A.units();
+    const int m = std::max(1, std::min(o->restart > 0 ? o->restart : 40, kMaxRestart));
+    double *V, *W0, *W1, *ph0, *pn;
+    GmState *st;
+    LCS_TRY(get_buf(c, B_GMV, (size_t)(m + 1) * n, &V));
+    LCS_TRY(get_buf(c, B_GMW0, n, &W0));
+    LCS_TRY(get_buf(c, B_GMW1, n, &W1));
+    LCS_TRY(get_buf(c, B_GMP0, (size_t)kGmPartVals * kGmGrid, &ph0));
+    LCS_TRY(get_buf(c, B_GMPN, (size_t)kGmGrid, &pn));
+    LCS_TRY(get_buf(c, B_GMS, 1, &st));
+    if (!c->hgm && hipHostMalloc(&c->hgm, sizeof(GmState), hipHostMallocDefault) != hipSuccess) {
+        c->hgm = nullptr;
+        (void)hipGetLastError();
+        return fail(LCS_ENOMEM, "pinned GMRES state");
+    }
+    const int g = band_grid(n, kGmGrid);
+    const int check = o->check_every > 0 ? o->check_every : 8;
+    if (x_zero) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, 0.0, n);
+        LAUNCH_CHECK();
+    }
+    bool from_zero = x_zero;
+    int outer = 0;
+    for (;;) {
+        const int steps = (int)std::min<int64_t>(m, (int64_t)o->max_iter - out->its);
+        hipLaunchKernelGGL((k_gm_init<Op>), dim3(g), dim3(kBlock), 0, s, A, rhs,
+                           from_zero ? (const double *)nullptr : (const double *)x, W0, pn, st,
+                           tol_base, tol_factor);
+        hipLaunchKernelGGL(k_gm_fold_n, dim3(1), dim3(kBlock), 0, s, (const double *)pn, g, 0, st);
+        LAUNCH_CHECK();
+        from_zero = false;
+        int j = 0;
+        while (j < steps) {
+            double *Wc = (j & 1) ? W1 : W0, *Wn = (j & 1) ? W0 : W1;
+            hipLaunchKernelGGL((k_gm_arnoldi<Op, kPc>), dim3(g), dim3(kBlock), 0, s, A, V, n,
+                               (const double *)Wc, Wn, j, ph0, (const GmState *)st);
+            hipLaunchKernelGGL(k_gm_fold_h, dim3(j + 1), dim3(kBlock), 0, s, (const double *)ph0, g,
+                               j, st, 0);
+            hipLaunchKernelGGL((k_gm_cgs<Op>), dim3(g), dim3(kBlock), 0, s, A, (const double *)V, n,
+                               Wn, j, ph0, (const GmState *)st, 0);
+            hipLaunchKernelGGL(k_gm_fold_h, dim3(j + 1), dim3(kBlock), 0, s, (const double *)ph0, g,
+                               j, st, 1);
+            hipLaunchKernelGGL((k_gm_cgs<Op>), dim3(g), dim3(kBlock), 0, s, A, (const double *)V, n,
+                               Wn, j, pn, (const GmState *)st, 1);
+            hipLaunchKernelGGL(k_gm_fold_n, dim3(1), dim3(kBlock), 0, s, (const double *)pn, g,
+                               j + 1, st);
+            LAUNCH_CHECK();
+            ++j;
+            if (j % check == 0 && j < steps) {
+                HIP_TRY(hipMemcpyAsync(c->hdone, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (c->hdone[0]) break;
+            }
+        }
+        hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kBlock), 0, s, st);
+        hipLaunchKernelGGL((k_gm_update<Op, kPc>), dim3(g), dim3(kBlock), 0, s, A, (const double *)V,
+                           n, x, (const GmState *)st);
+        LAUNCH_CHECK();
+        HIP_TRY(hipMemcpyAsync(c->hgm, st, sizeof(GmState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const GmState &h = *c->hgm;
+        out->its += h.k;
+        if (h.status != kStOk) return status_of(h.status);
+        if (h.done || out->its >= o->max_iter) {
+            LCS_TRY(launch_resnorm(c, A, rhs, (const double *)x, (double *)nullptr, tol_base,
+                                   tol_factor, s));
+            LCS_TRY(read_scalars(c, s));
+            out->rr = c->hsc->res.rr;
+            if (c->hsc->res.status != kStOk) return status_of(c->hsc->res.status);
+            if (c->hsc->res.done) return LCS_OK;
+            if (out->its >= o->max_iter || outer >= o->max_outer) return status_of(kStNoConv);
+            ++outer;
+            out->n_outer += 1;
+        }
+    }
+}
+
+template <class Op>
+lcs_status run_gmres(lcs_ctx *c, const Op &A, const double *rhs, double *x, bool x_zero,
+                     const double *tol_base, double tol_factor, const lcs_options *o, hipStream_t s,
+                     SolveOut *out) {
+    *out = SolveOut();
+    if (A.units() == 0) return LCS_OK;
+    if (o->precond == LCS_PC_JACOBI)
+        return run_gmres_t<Op, 1>(c, A, rhs, x, x_zero, tol_base, tol_factor, o, s, out);
+    return run_gmres_t<Op, 0>(c, A, rhs, x, x_zero, tol_base, tol_factor, o, s, out);
+}
+
+// Solve op x = rhs: GMRES for a non-symmetric operator (the full-storage
+// stencil at compile time, the restricted system of one at run time), else
+// PCG as above.
+template <class Op64, class Op32>
+lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, const double *rhs,
+                        double *x, bool x_zero, const double *tol_base, double tol_factor,
+                        const lcs_options *o, hipStream_t s, SolveOut *out, int scope,
+                        bool gmres = false) {
+    if constexpr (is_nonsym<Op64>) {
+        return run_gmres(c, A, rhs, x, x_zero, tol_base, tol_factor, o, s, out);
+    } else {
+        if constexpr (is_ell<Op64>) {
+            if (gmres) return run_gmres(c, A, rhs, x, x_zero, tol_base, tol_factor, o, s, out);
+        }
+        return solve_system_sym(c, A, A32, ncol, rhs, x, x_zero, tol_base, tol_factor, o, s, out,
+                                scope);
+    }
+}
 // ---------------------------------------------------------------------------
 // Algorithm 2 / Algorithm 3: scores, threshold, expansion, compaction
 // ---------------------------------------------------------------------------
@@ -836,7 +976,8 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         const double tl = o->tol_local > 0 ? o->tol_local : o->eps;
         SolveOut so;
         const lcs_status ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
-                                           &c->dsc->bnorm, tl, o, s, &so, 1);
+                                           &c->dsc->bnorm, tl, o, s, &so, 1,
+                                           M->kind == LCS_STENCIL9N_2D);
         // a local solve that stops at its iteration cap still improves x;
         // the global finish takes over from there
         if (ls != LCS_OK && ls != LCS_ENOCONV) return ls;
@@ -938,6 +1079,8 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     if (local) LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
+    if (A->kind == LCS_STENCIL9N_2D)
+        return fail(LCS_EINVAL, "batched solves take the symmetric stencils (PCG)");
     if (G < 1 || G > kMaxBatch) return fail(LCS_EINVAL, "batch size G must be 1..65535");
     if (o->precision != LCS_PREC_FP64) return fail(LCS_EINVAL, "batched solves run in FP64");
     if (o->precond == LCS_PC_RBSGS)
@@ -1029,6 +1172,7 @@ void lcs_default_options(lcs_options *o) {
     o->n_smooth = 1;
     o->check_every = 8;
     o->max_outer = 10;
+    o->restart = 40;
 }
 
 const char *lcs_last_error(void) { return g_err.c_str(); }
@@ -1070,6 +1214,7 @@ void lcs_destroy(lcs_ctx *c) {
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hdone) (void)hipHostFree(c->hdone);
     if (c->hbout) (void)hipHostFree(c->hbout);
+    if (c->hgm) (void)hipHostFree(c->hgm);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chk)

@@ -129,6 +129,38 @@ struct Stencil7 {
     static constexpr int kColours = 2;
 };
 
+// Nine-point operator in full storage (non-symmetric, e.g. with convection):
+// a[s * n + i] is the coefficient of row i at slot s, slots in ascending
+// column order SW, S, SE, W, C, E, NW, N, NE; entries whose neighbour lies
+// outside the grid are ignored.
+template <typename real>
+struct Stencil9N {
+    const real *a;
+    int nx, ny;
+    int64_t n;
+    template <class F>
+    __device__ __forceinline__ void for_each(int64_t i, F &&f) const {
+        const int y = (int)((uint32_t)i / (uint32_t)nx);
+        const int x = (int)i - y * nx;
+        const bool w = x > 0, e = x < nx - 1, s = y > 0, nn = y < ny - 1;
+        if (s && w) f(i - nx - 1, a[i]);
+        if (s) f(i - nx, a[n + i]);
+        if (s && e) f(i - nx + 1, a[2 * n + i]);
+        if (w) f(i - 1, a[3 * n + i]);
+        f(i, a[4 * n + i]);
+        if (e) f(i + 1, a[5 * n + i]);
+        if (nn && w) f(i + nx - 1, a[6 * n + i]);
+        if (nn) f(i + nx, a[7 * n + i]);
+        if (nn && e) f(i + nx + 1, a[8 * n + i]);
+    }
+    __device__ __forceinline__ real diag(int64_t i) const { return a[4 * n + i]; }
+    __device__ __forceinline__ int colour(int64_t i) const {
+        const int y = (int)((uint32_t)i / (uint32_t)nx);
+        return (((int)i - y * nx) & 1) + 2 * (y & 1);
+    }
+    static constexpr int kColours = 4;
+};
+
 // Restricted system B in CSR (row_ptr int32, ascending columns).
 template <typename real>
 struct Csr {
@@ -656,6 +688,111 @@ struct U9 {
         }
     }
 };
+
+// Full-storage nine-point unit operator (Stencil9N's layout), flat walk only:
+// every coefficient is the own row's, so a unit loads nine contiguous strips.
+template <typename real_, int V_>
+struct U9N {
+    using real = real_;
+    static constexpr int V = V_, NB = 9, kC = 4;
+    static constexpr bool kMarch = false, kNT = false, kCenter = true;
+    const real *a;   // [9][n]
+    int nx, ny;
+    int64_t n;
+    struct Unit {
+        int64_t i0;
+        int x0, y;
+        real a[NB][V];
+    };
+    __host__ __device__ int64_t units() const { return n / V; }
+    __device__ __forceinline__ void geom(Unit &U, int64_t u) const {
+        U.i0 = u * V;
+        U.y = (int)((uint64_t)U.i0 / (uint64_t)nx);
+        U.x0 = (int)(U.i0 - (int64_t)U.y * nx);
+    }
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        geom(U, u);
+#pragma unroll
+        for (int s = 0; s < NB; ++s) vld<real, V>(a + s * n + U.i0, U.a[s]);
+    }
+    __device__ __forceinline__ bool valid(const Unit &U, int s, int k) const {
+        const bool w = U.x0 + k > 0, e = U.x0 + k < nx - 1, so = U.y > 0, no = U.y < ny - 1;
+        switch (s) {
+        case 0: return so && w;
+        case 1: return so;
+        case 2: return so && e;
+        case 3: return w;
+        case 4: return true;
+        case 5: return e;
+        case 6: return no && w;
+        case 7: return no;
+        default: return no && e;
+        }
+    }
+    __device__ __forceinline__ bool is_diag(const Unit &, int s, int) const { return s == kC; }
+    template <typename T>
+    __device__ __forceinline__ void row3(const Unit &U, const T *__restrict__ v, int64_t base, bool on,
+                                         T (&r)[V + 2]) const {
+        if (on) {
+            T m[V];
+            vld<T, V>(v + base, m);
+#pragma unroll
+            for (int k = 0; k < V; ++k) r[k + 1] = m[k];
+            r[0] = U.x0 > 0 ? v[base - 1] : T(0);
+            r[V + 1] = U.x0 + V < nx ? v[base + V] : T(0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V + 2; ++k) r[k] = T(0);
+        }
+    }
+    template <typename T>
+    __device__ __forceinline__ void gather(const Unit &U, const T *__restrict__ v, T (&o)[NB][V]) const {
+        T rs[V + 2], rc[V + 2], rn[V + 2];
+        row3(U, v, U.i0 - nx, U.y > 0, rs);
+        row3(U, v, U.i0, true, rc);
+        row3(U, v, U.i0 + nx, U.y < ny - 1, rn);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o[0][k] = rs[k];
+            o[1][k] = rs[k + 1];
+            o[2][k] = rs[k + 2];
+            o[3][k] = rc[k];
+            o[4][k] = rc[k + 1];
+            o[5][k] = rc[k + 2];
+            o[6][k] = rn[k];
+            o[7][k] = rn[k + 1];
+            o[8][k] = rn[k + 2];
+        }
+    }
+    __device__ __forceinline__ int colour(const Unit &U, int k) const {
+        return ((U.x0 + k) & 1) + 2 * (U.y & 1);
+    }
+    __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const {
+        vld<real, V>(a + 4 * n + U.i0, d);
+    }
+    __device__ __forceinline__ const real *diag_ptr() const { return a + 4 * n; }
+    template <typename T>
+    __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
+        vld<T, V>(p + U.i0, o);
+    }
+    template <typename T>
+    __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[V]) const {
+        vst<T, V>(p + U.i0, o);
+    }
+};
+
+// operators whose matrix need not be symmetric (solved by GMRES), and the
+// restricted ELL system (solved by GMRES when the full matrix is one of them)
+template <class Op>
+constexpr bool is_nonsym = false;
+template <typename real, int V>
+constexpr bool is_nonsym<U9N<real, V>> = true;
+template <typename real, int NB>
+struct UEll;
+template <class Op>
+constexpr bool is_ell = false;
+template <typename real, int NB>
+constexpr bool is_ell<UEll<real, NB>> = true;
 
 template <typename real_, int V_, int W_>
 struct U7 {

@@ -18,12 +18,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblcs.so")
 
 OK, EINVAL, EHIP, ENOMEM, ENOCONV, EBREAKDOWN, ENONFINITE = range(7)
-STENCIL5_2D, STENCIL9_2D, STENCIL7_3D = 0, 1, 2
+STENCIL5_2D, STENCIL9_2D, STENCIL7_3D, STENCIL9N_2D = 0, 1, 2, 3
 MODE_RESIDUAL, MODE_GRADIENT = 0, 1
 THRESH_REL_MAX, THRESH_ABS, THRESH_PAPER = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_RBSGS = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-N_ARRAYS = {STENCIL5_2D: 3, STENCIL9_2D: 5, STENCIL7_3D: 4}
+N_ARRAYS = {STENCIL5_2D: 3, STENCIL9_2D: 5, STENCIL7_3D: 4, STENCIL9N_2D: 9}
 
 _MODES = {"residual": MODE_RESIDUAL, "gradient": MODE_GRADIENT}
 _THRESH = {"relmax": THRESH_REL_MAX, "abs": THRESH_ABS, "paper": THRESH_PAPER}
@@ -56,7 +56,7 @@ class _Options(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("n_smooth", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -178,10 +178,12 @@ class Options:
     n_smooth: int = 1
     check_every: int = 8
     max_outer: int = 10
+    restart: int = 40        # GMRES(m) restart length (non-symmetric operator)
 
     def c(self) -> _Options:
         return _Options(self.eps, self.tol_local, self.inner_tol, self.max_iter, _PC[self.precond],
-                        _PREC[self.precision], self.n_smooth, self.check_every, self.max_outer)
+                        _PREC[self.precision], self.n_smooth, self.check_every, self.max_outer,
+                        self.restart)
 
 
 @dataclasses.dataclass
