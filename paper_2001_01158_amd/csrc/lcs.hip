@@ -1060,12 +1060,23 @@ template <class S>
 lcs_status launch_batch(lcs_ctx *c, const S &A, int pc, const BatchArgs &a, int32_t G,
                         const double *b, double *x, double *ws, uint8_t *stamp, int32_t *idx,
                         BatchOut *out, hipStream_t s) {
-    if (pc == LCS_PC_JACOBI)
-        hipLaunchKernelGGL((k_batch_solve<S, 1>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b, x, ws,
-                           stamp, idx, out);
-    else
-        hipLaunchKernelGGL((k_batch_solve<S, 0>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b, x, ws,
-                           stamp, idx, out);
+    // systems of at most kLdsRows cells keep the PCG vectors in registers and LDS
+    const bool lds = A.n <= kLdsRows;
+    if (pc == LCS_PC_JACOBI) {
+        if (lds)
+            hipLaunchKernelGGL((k_batch_solve<S, 1, true>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b,
+                               x, ws, stamp, idx, out);
+        else
+            hipLaunchKernelGGL((k_batch_solve<S, 1, false>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b,
+                               x, ws, stamp, idx, out);
+    } else {
+        if (lds)
+            hipLaunchKernelGGL((k_batch_solve<S, 0, true>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b,
+                               x, ws, stamp, idx, out);
+        else
+            hipLaunchKernelGGL((k_batch_solve<S, 0, false>), dim3(G), dim3(kBatchBlock), 0, s, A, a, b,
+                               x, ws, stamp, idx, out);
+    }
     LAUNCH_CHECK();
     return LCS_OK;
 }

@@ -30,6 +30,7 @@ namespace lcs {
 constexpr int kBatchBlock = 1024;
 constexpr int kBatchWaves = kBatchBlock / kWave;
 constexpr int32_t kMaxBatch = 65535;          // one workgroup per system on grid x
+constexpr int64_t kLdsRows = 7168;             // systems up to this size keep p in 56 KB of LDS
 constexpr int64_t kMaxBatchN = int64_t(1) << 24;   // cells per system (int32 idx, time)
 
 // per-system result, written by thread 0 of the system's workgroup
@@ -310,6 +311,89 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
     return kStNoConv;
 }
 
+// The same PCG for systems of at most kLdsRows cells with the search
+// direction p in LDS (p_lds, indexed by cell, zero outside the active rows):
+// the nine gathers of each SpMV row are LDS reads, and the global traffic per
+// iteration is the coefficients plus the own rows of r, sol and q.  Same
+// recurrences and FMA orders as wg_pcg.
+template <class S, int kPc>
+__device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t cnt, double *r,
+                          double *sol, double *q, double *p_lds, double tol, int max_iter,
+                          int *its) {
+    using RN = RowN<S>;
+    const int tid = threadIdx.x;
+    *its = 0;
+    for (int64_t i = tid; i < A.n; i += kBatchBlock) p_lds[i] = 0.0;
+    __syncthreads();
+    double v[2] = {0.0, 0.0};
+    for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+        const int64_t i = row_of(idx, t);
+        const double ri = r[i];
+        const double z = kPc ? ri / A.diag(i) : ri;
+        p_lds[i] = z;
+        v[0] += ri * ri;
+        v[1] += ri * z;
+    }
+    wg_reduce<2>(v, Ops<0u>());   // its barrier also publishes p_lds
+    double rr = v[0], rz = v[1];
+    if (!(rr == rr)) return kStNonFinite;
+    if (sqrt(rr) <= tol) return kStOk;
+    int it = 0;
+    while (it < max_iter) {
+        double pq[1] = {0.0};
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            const RN Rw(A, i);
+            double cf[RN::NB];
+            Rw.coef(A, i, cf);
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < RN::NB; ++s)
+                if (Rw.ok[s]) acc = fma(cf[s], p_lds[Rw.j[s]], acc);
+            q[i] = acc;
+            pq[0] += p_lds[i] * acc;
+        }
+        wg_reduce<1>(pq, Ops<0u>());
+        if (!(pq[0] > 0.0)) {
+            *its = it;
+            return pq[0] == pq[0] ? kStBreakdown : kStNonFinite;
+        }
+        const double alpha = rz / pq[0];
+        double w[2] = {0.0, 0.0};
+#pragma unroll 2
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            sol[i] = fma(alpha, p_lds[i], sol[i]);
+            const double ri = fma(-alpha, q[i], r[i]);
+            r[i] = ri;
+            w[0] += ri * ri;
+            w[1] += ri * (kPc ? ri / A.diag(i) : ri);
+        }
+        wg_reduce<2>(w, Ops<0u>());
+        ++it;
+        rr = w[0];
+        if (!(rr == rr)) {
+            *its = it;
+            return kStNonFinite;
+        }
+        if (sqrt(rr) <= tol) {
+            *its = it;
+            return kStOk;
+        }
+        const double beta = w[1] / rz;
+        rz = w[1];
+#pragma unroll 2
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            const double z = kPc ? r[i] / A.diag(i) : r[i];
+            p_lds[i] = fma(beta, p_lds[i], z);
+        }
+        __syncthreads();
+    }
+    *its = it;
+    return kStNoConv;
+}
+
 // r = b - A x over all rows (FMA chain, ascending columns); returns ||r||^2
 // in every thread.
 template <class S>
@@ -328,15 +412,18 @@ __device__ double wg_residual(const S &A, const double *__restrict__ b, const do
 // Global finish: PCG from x with a true-residual check, restarting from the
 // current x while the check fails (at most max_outer restarts, max_iter
 // iterations in all).  r must hold b - A x on entry.
-template <class S, int kPc>
+template <class S, int kPc, bool kLds>
 __device__ int wg_global(const S &A, const double *__restrict__ b, double *x, double *r, double *p,
-                         double *q, double tol, int max_iter, int max_outer, int *its_total,
-                         int *restarts, double *rr_true) {
+                         double *q, double *p_lds, double tol, int max_iter, int max_outer,
+                         int *its_total, int *restarts, double *rr_true) {
     int st = kStOk, total = 0;
     *restarts = 0;
     for (int attempt = 0;; ++attempt) {
         int it = 0;
-        st = wg_pcg<S, kPc>(A, nullptr, A.n, r, x, p, q, tol, max_iter - total, &it);
+        if constexpr (kLds)
+            st = wg_pcg_lds<S, kPc>(A, nullptr, A.n, r, x, q, p_lds, tol, max_iter - total, &it);
+        else
+            st = wg_pcg<S, kPc>(A, nullptr, A.n, r, x, p, q, tol, max_iter - total, &it);
         total += it;
         const double rr = wg_residual(A, b, x, r);
         *rr_true = rr;
@@ -364,7 +451,7 @@ struct BatchArgs {
 
 // One workgroup per system g = blockIdx.x.  ws: 4 n doubles per system
 // (r, p, q, d); stamp: n bytes; idx: n ints.
-template <class S, int kPc>
+template <class S, int kPc, bool kLds>
 __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
                                                              const double *__restrict__ b_all,
                                                              double *x_all, double *ws,
@@ -381,6 +468,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
     int32_t *idx = idx_all + (int64_t)g * n;
     BatchOut o{};
     o.status = kStOk;
+    __shared__ double p_lds_buf[kLds ? kLdsRows : 1];
+    double *p_lds = p_lds_buf;
 
     // ---- r0 = b - A x0; ||b||^2, ||r0||^2, max |score| (Algorithms 2, 3) ----
     double v[3] = {0.0, 0.0, 0.0};
@@ -492,7 +581,12 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
         for (int64_t t = tid; t < K; t += kBatchBlock) d[idx[t]] = 0.0;
         __syncthreads();
         int its = 0;
-        o.status_local = wg_pcg<S, kPc>(A, idx, K, r, d, p, q, a.tol_local * bn, a.max_iter, &its);
+        if constexpr (kLds)
+            o.status_local = wg_pcg_lds<S, kPc>(A, idx, K, r, d, q, p_lds, a.tol_local * bn,
+                                                a.max_iter, &its);
+        else
+            o.status_local = wg_pcg<S, kPc>(A, idx, K, r, d, p, q, a.tol_local * bn, a.max_iter,
+                                            &its);
         o.its_local = its;
         if (o.status_local == kStBreakdown || o.status_local == kStNonFinite) {
             o.status = o.status_local;
@@ -535,8 +629,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
     if (need_global) {
         // r holds b - A x here (either r0 or the post-smoothing residual)
         int its = 0, restarts = 0;
-        st_global = wg_global<S, kPc>(A, b, x, r, p, q, tol, a.max_iter, a.max_outer, &its,
-                                      &restarts, &rr);
+        st_global = wg_global<S, kPc, kLds>(A, b, x, r, p, q, p_lds, tol, a.max_iter,
+                                            a.max_outer, &its, &restarts, &rr);
         o.its_global = its;
         o.n_outer = restarts;
     }

@@ -263,3 +263,28 @@ def test_multigroup_batch_full_size():
             assert abs(sts[g].its_local - so.its_local) <= 1
             say(f"  g={g} K={sts[g].K} its={sts[g].its_local}+{sts[g].its_global} "
                 f"(oracle {so.K}, {so.its_local}+{so.its_global})")
+
+
+@pytest.mark.parametrize("name,dims", [("5pt", (97, 83, 1)), ("9pt", (91, 80, 1))])
+def test_batched_systems_above_the_lds_size(name, dims):
+    """Systems larger than the LDS-resident PCG takes (7168 cells) run the
+    global-memory PCG of the same kernel: same checks against the oracle."""
+    G = 2
+    say("batched large", name, dims)
+    A, Ahs, b, x0 = make_batch(name, G, dims)
+    assert A.n > 7168
+    x = dev(x0)
+    sts = lcs.solve_local_then_global_batched(A, dev(b), x, "residual", "relmax", 1e-3, 1,
+                                              lcs.Options(eps=1e-10))
+    xg = host(x)
+    for g in range(G):
+        xo, so, dom = oracle.local_then_global(Ahs[g], b[g], x0[g], oracle.MODE_RESIDUAL, 1e-3,
+                                               oracle.TH_RELMAX, 1, oracle.Options(eps=1e-10))
+        assert sts[g].K == so.K and abs(sts[g].its_local - so.its_local) <= 1
+        nb = np.linalg.norm(b[g])
+        assert np.linalg.norm(oracle.residual(Ahs[g], b[g], xg[g])) <= 1.0001e-10 * nb
+    xs = dev(x0)
+    stg = lcs.solve_global_batched(A, dev(b), xs, lcs.Options(eps=1e-10))
+    for g in range(G):
+        xo, so = oracle.solve_global(Ahs[g], b[g], x0[g], oracle.Options(eps=1e-10))
+        assert abs(stg[g].its_global - so.its_global) <= 1
