@@ -514,8 +514,8 @@ def main():
         param_sweep(args.workload, args.steps)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; sharding across GPUs is a design "
-                                   "description only (DESIGN.md section 9)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this implementation runs on one GPU; the row-slab sharding "
+                                   "across GPUs is described, not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2001_01158_amd import lcs, workloads as W
@@ -611,7 +611,7 @@ def main():
             "avg_launch_us": avg_us, "launches": k_launches,
             "bytes_per_launch": bytes_per_launch,
             "bytes_per_local_row": bytes_per_row,
-            "note": "latency-bound: K ~ 1e4-1e5 rows per launch; see DESIGN.md section 6"}
+            "note": "latency-bound: one launch per PCG iteration on K ~ 1e4-1e5 local rows"}
     log(f"dominant kernel: {k_launches} launches, avg {avg_us:.2f} us, {achieved or 0:.0f} GB/s")
 
     # ---- SpMV GB/s ----

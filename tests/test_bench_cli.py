@@ -1,5 +1,5 @@
 """bench.py's command-line contract that needs no GPU: more than one GPU is
-refused with a message (this build runs on one GPU), and the rocprofv3
+refused with a message (the implementation runs on one GPU), and the rocprofv3
 summarizer runs on the host."""
 import json
 import os
