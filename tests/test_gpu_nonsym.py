@@ -173,3 +173,43 @@ def test_nonsym_full_size_1024():
     nb = np.linalg.norm(b)
     assert np.linalg.norm(oracle.residual(Ah, b, host(x))) <= 1.0001e-10 * nb
     say(f"  K={st.K} its={st.its_local}+{st.its_global}")
+
+
+@pytest.mark.parametrize("grid", list(GRIDS))
+def test_nonsym_solve_local_trajectory_parity(grid):
+    """Steps 3-7 of Algorithm 1 on a caller-supplied domain: GMRES on B
+    stopped after the same number of steps on both sides (restart 4, so the
+    cap of 11 crosses two restarts), then assembly and one Gauss-Seidel
+    sweep: rounding-level agreement with the oracle."""
+    coef, Ah, A, b, x0 = make_case(grid)
+    say("nonsym solve_local", grid)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-4, oracle.TH_RELMAX, 1)
+    assert 0 < d.K < A.n
+    oo = gm_opts(eps=1e-10, max_iter=11, n_smooth=1, gmres_m=4)
+    xo, so = oracle.solve_local(Ah, b, x0, d.idx, oo)
+    x = dev(x0)
+    st = lcs.solve_local(A, dev(b), x, torch.as_tensor(d.idx, dtype=torch.int32).to(DEV),
+                         lcs.Options(eps=1e-10, max_iter=11, n_smooth=1, restart=4))
+    assert st.its_local == so.its_local == 11
+    rel = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    assert rel <= 1e-12, rel
+
+
+@pytest.mark.parametrize("grid", list(GRIDS))
+def test_nonsym_spmv_fp32(grid):
+    """FP32 SpMV of the full-storage operator: within the FP32 rounding bound
+    of a 9-term fused sum of the FP64 product of the same FP32-rounded
+    inputs."""
+    coef, Ah, A, b, x0 = make_case(grid)
+    A.coef32 = lcs.cast_coef(A)
+    c32 = host(A.coef32).astype(np.float64)
+    np.testing.assert_array_equal(c32, coef.astype(np.float32).astype(np.float64))
+    x32 = torch.as_tensor(x0, dtype=torch.float32).to(DEV)
+    y = torch.empty(A.n, dtype=torch.float32, device=DEV)
+    lcs.spmv(A, x32, y)
+    A32h = oracle.csr_from_stencil(W.KIND_9N, A.nx, A.ny, 1, c32)
+    xr = host(x32).astype(np.float64)
+    ref = oracle.spmv(A32h, xr)
+    absA = oracle.CSR(A32h.n, A32h.rp, A32h.col, np.abs(A32h.val))
+    bound = 9 * 2.0 ** -24 * oracle.spmv(absA, np.abs(xr)) + 1e-30
+    assert np.all(np.abs(host(y).astype(np.float64) - ref) <= bound)
