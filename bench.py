@@ -149,7 +149,7 @@ def summarize(d: str, steps: int):
 
     def window(recs, name_key, ts_key):
         marks = [int(r[ts_key]) for r in recs if start_mark.match(r[name_key])]
-        if len(marks) < steps:
+        if steps <= 0 or len(marks) < steps:
             return []
         t0 = sorted(marks)[-steps]
         return [r for r in recs if r[name_key].startswith(dom) and int(r[ts_key]) >= t0]
@@ -159,9 +159,25 @@ def summarize(d: str, steps: int):
         allk = [r for r in trace if r["Kernel_Name"].startswith(dom)]
         win = window(trace, "Kernel_Name", "Start_Timestamp")
         dur = lambda rs: sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rs) / max(len(rs), 1) / 1e3
-        out.append("")
-        out.append(f"dominant kernel `{short(dom)}`: whole run {len(allk)} dispatches, avg {dur(allk):.2f} us; "
-                   f"timed pass (last {steps} residual-mode systems) {len(win)} dispatches, avg {dur(win):.2f} us")
+        if allk:
+            out.append("")
+            out.append(f"dominant kernel `{short(dom)}`: whole run {len(allk)} dispatches, avg {dur(allk):.2f} us; "
+                       f"timed pass (last {steps} residual-mode systems) {len(win)} dispatches, avg "
+                       f"{dur(win):.2f} us")
+        # batched launches, split by the number of systems (one workgroup each)
+        by = {}
+        for r in trace:
+            if "k_batch_solve" in r["Kernel_Name"]:
+                g = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
+                by.setdefault((short(r["Kernel_Name"]), g), []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        if by:
+            out.append("")
+            out.append("| batched kernel | systems per launch | launches | median us | min us | max us |")
+            out.append("|---|---|---|---|---|---|")
+            for (name, g), ds in sorted(by.items(), key=lambda kv: (-kv[0][1], kv[0][0])):
+                out.append(f"| `{name}` | {g} | {len(ds)} | {np.median(ds):.1f} | {min(ds):.1f} | "
+                           f"{max(ds):.1f} |")
     fetch, write = rows("fetch/*counter_collection.csv"), rows("write/*counter_collection.csv")
     if fetch and write:
         copy = lambda rs: max(float(r["Counter_Value"]) for r in rs if "copyBuffer" in r["Kernel_Name"])

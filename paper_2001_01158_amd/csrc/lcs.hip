@@ -1060,7 +1060,7 @@ template <class S>
 lcs_status launch_batch(lcs_ctx *c, const S &A, int pc, const BatchArgs &a, int32_t G,
                         const double *b, double *x, double *ws, uint8_t *stamp, int32_t *idx,
                         BatchOut *out, hipStream_t s) {
-    // systems of at most kLdsRows cells keep the PCG vectors in registers and LDS
+    // systems of at most kLdsRows cells keep p and q of the PCG in LDS
     const bool lds = A.n <= kLdsRows;
     if (pc == LCS_PC_JACOBI) {
         if (lds)

@@ -30,7 +30,7 @@ namespace lcs {
 constexpr int kBatchBlock = 1024;
 constexpr int kBatchWaves = kBatchBlock / kWave;
 constexpr int32_t kMaxBatch = 65535;          // one workgroup per system on grid x
-constexpr int64_t kLdsRows = 7168;             // systems up to this size keep p in 56 KB of LDS
+constexpr int64_t kLdsRows = 7168;             // systems up to this size keep p and q in 112 KB of LDS
 constexpr int64_t kMaxBatchN = int64_t(1) << 24;   // cells per system (int32 idx, time)
 
 // per-system result, written by thread 0 of the system's workgroup
@@ -240,7 +240,9 @@ __device__ __forceinline__ int64_t row_of(const int32_t *idx, int64_t t) { retur
 // (cnt rows: idx[0..cnt) or all of A), Jacobi (kPc 1) or none (kPc 0).
 // In: r = residual of the initial sol on the active rows, p zero outside
 // them.  sol (d for the local system, x for A) is updated in place; stops at
-// ||r|| <= tol or max_iter.  Returns kStOk, kStNoConv, kStBreakdown or
+// ||r|| <= tol or max_iter.  Each row is handled by the same thread in every
+// loop, so once the r update has consumed q[i] the slot holds the row's
+// preconditioned residual z for the p update.  Returns kStOk, kStNoConv, kStBreakdown or
 // kStNonFinite; *its = iterations.
 template <class S, int kPc>
 __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, double *r,
@@ -283,8 +285,10 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
             sol[i] = fma(alpha, p[i], sol[i]);
             const double ri = fma(-alpha, q[i], r[i]);
             r[i] = ri;
+            const double z = kPc ? ri / A.diag(i) : ri;
+            q[i] = z;   // q is dead from here on; its slot carries z to the p update
             w[0] += ri * ri;
-            w[1] += ri * (kPc ? ri / A.diag(i) : ri);
+            w[1] += ri * z;
         }
         wg_reduce<2>(w, Ops<0u>());
         ++it;
@@ -302,8 +306,7 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
 #pragma unroll 4
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
-            const double z = kPc ? r[i] / A.diag(i) : r[i];
-            p[i] = fma(beta, p[i], z);
+            p[i] = fma(beta, p[i], q[i]);
         }
         __syncthreads();
     }
@@ -311,17 +314,22 @@ __device__ int wg_pcg(const S &A, const int32_t *__restrict__ idx, int64_t cnt, 
     return kStNoConv;
 }
 
-// The same PCG for systems of at most kLdsRows cells with the search
-// direction p in LDS (p_lds, indexed by cell, zero outside the active rows):
-// the nine gathers of each SpMV row are LDS reads, and the global traffic per
-// iteration is the coefficients plus the own rows of r, sol and q.  Same
-// recurrences and FMA orders as wg_pcg.
+// The same PCG for systems of at most kLdsRows cells, with the search
+// direction p and the product q = A p in LDS (lds[0, kLdsRows) and
+// lds[kLdsRows, 2 kLdsRows), indexed by cell; p is zero outside the active
+// rows).  The nine gathers of each SpMV row are LDS reads, and the global
+// traffic per iteration is the coefficients, the diagonal and the own rows of
+// r and sol.  Each row is handled by the same thread in every loop, so after
+// the r update the row's preconditioned residual z takes the place of its
+// (now dead) q entry and the p update reads only LDS.  Same recurrences and
+// FMA orders as wg_pcg.
 template <class S, int kPc>
 __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t cnt, double *r,
-                          double *sol, double *q, double *p_lds, double tol, int max_iter,
+                          double *sol, double *lds, double tol, int max_iter,
                           int *its) {
     using RN = RowN<S>;
     const int tid = threadIdx.x;
+    double *p_lds = lds, *q_lds = lds + kLdsRows;
     *its = 0;
     for (int64_t i = tid; i < A.n; i += kBatchBlock) p_lds[i] = 0.0;
     __syncthreads();
@@ -344,13 +352,20 @@ __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t c
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
             const RN Rw(A, i);
-            double cf[RN::NB];
+            double cf[RN::NB], pv[RN::NB];
             Rw.coef(A, i, cf);
+            // every gather first (clamped columns are valid), then the sum
+            // with missing slots skipped by a select: the LDS reads of a row
+            // issue together instead of one wait per neighbour
+#pragma unroll
+            for (int s = 0; s < RN::NB; ++s) pv[s] = p_lds[Rw.j[s]];
             double acc = 0.0;
 #pragma unroll
-            for (int s = 0; s < RN::NB; ++s)
-                if (Rw.ok[s]) acc = fma(cf[s], p_lds[Rw.j[s]], acc);
-            q[i] = acc;
+            for (int s = 0; s < RN::NB; ++s) {
+                const double t = fma(cf[s], pv[s], acc);
+                acc = Rw.ok[s] ? t : acc;
+            }
+            q_lds[i] = acc;   // read back below by this thread only
             pq[0] += p_lds[i] * acc;
         }
         wg_reduce<1>(pq, Ops<0u>());
@@ -364,10 +379,12 @@ __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t c
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
             sol[i] = fma(alpha, p_lds[i], sol[i]);
-            const double ri = fma(-alpha, q[i], r[i]);
+            const double ri = fma(-alpha, q_lds[i], r[i]);
             r[i] = ri;
+            const double z = kPc ? ri / A.diag(i) : ri;
+            q_lds[i] = z;   // q is dead from here on; its slot carries z to the p update
             w[0] += ri * ri;
-            w[1] += ri * (kPc ? ri / A.diag(i) : ri);
+            w[1] += ri * z;
         }
         wg_reduce<2>(w, Ops<0u>());
         ++it;
@@ -385,8 +402,7 @@ __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t c
 #pragma unroll 2
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
-            const double z = kPc ? r[i] / A.diag(i) : r[i];
-            p_lds[i] = fma(beta, p_lds[i], z);
+            p_lds[i] = fma(beta, p_lds[i], q_lds[i]);
         }
         __syncthreads();
     }
@@ -421,7 +437,7 @@ __device__ int wg_global(const S &A, const double *__restrict__ b, double *x, do
     for (int attempt = 0;; ++attempt) {
         int it = 0;
         if constexpr (kLds)
-            st = wg_pcg_lds<S, kPc>(A, nullptr, A.n, r, x, q, p_lds, tol, max_iter - total, &it);
+            st = wg_pcg_lds<S, kPc>(A, nullptr, A.n, r, x, p_lds, tol, max_iter - total, &it);
         else
             st = wg_pcg<S, kPc>(A, nullptr, A.n, r, x, p, q, tol, max_iter - total, &it);
         total += it;
@@ -468,8 +484,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
     int32_t *idx = idx_all + (int64_t)g * n;
     BatchOut o{};
     o.status = kStOk;
-    __shared__ double p_lds_buf[kLds ? kLdsRows : 1];
-    double *p_lds = p_lds_buf;
+    __shared__ double lds_buf[kLds ? 2 * kLdsRows : 1];   // p, then q, of the LDS PCG
+    double *p_lds = lds_buf;
 
     // ---- r0 = b - A x0; ||b||^2, ||r0||^2, max |score| (Algorithms 2, 3) ----
     double v[3] = {0.0, 0.0, 0.0};
@@ -582,7 +598,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
         __syncthreads();
         int its = 0;
         if constexpr (kLds)
-            o.status_local = wg_pcg_lds<S, kPc>(A, idx, K, r, d, q, p_lds, a.tol_local * bn,
+            o.status_local = wg_pcg_lds<S, kPc>(A, idx, K, r, d, p_lds, a.tol_local * bn,
                                                 a.max_iter, &its);
         else
             o.status_local = wg_pcg<S, kPc>(A, idx, K, r, d, p, q, a.tol_local * bn, a.max_iter,
