@@ -61,6 +61,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--workload", choices=["c2", "c3", "c5", "c6"], default="c2")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--precond", choices=["jacobi", "rbsgs", "none"],
+                   help="replace the workload's preconditioner (rbsgs: colour-ordered symmetric "
+                        "Gauss-Seidel, four colours on the nine-point stencil)")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--skip-spmv-hbm", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
@@ -209,15 +212,19 @@ def summarize(d: str, steps: int):
     print("\n".join(out))
 
 
-def setup_sequence(workload: str):
+def setup_sequence(workload: str, precond: str | None = None):
     """Operator, context, options and the evolved sequence (untimed): X[k] is
-    x_(k-1) and Bs[k] is b_k of system k, resident on the GPU."""
+    x_(k-1) and Bs[k] is b_k of system k, resident on the GPU.  precond
+    replaces the workload's preconditioner."""
     import torch
     from paper_2001_01158_amd import lcs
     dev = "cuda:0"
     torch.cuda.set_device(0)
     w, okw, desc, src = make_workload(workload)
-    log(f"workload {w.name} N={w.n} systems={w.n_systems}")
+    if precond is not None and precond != okw["precond"]:
+        okw = dict(okw, precond=precond)
+        desc = f"{desc}; preconditioner {precond}"
+    log(f"workload {w.name} N={w.n} systems={w.n_systems} precond={okw['precond']}")
     A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
                               with32=okw["precision"] == "mixed")
     ctx = lcs.Context()
@@ -537,7 +544,7 @@ def main():
     from paper_2001_01158_amd import lcs, workloads as W
 
     dev = "cuda:0"
-    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload)
+    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload, args.precond)
     n = w.n
     stream = torch.cuda.current_stream()
     eps = opts.eps

@@ -92,8 +92,12 @@ typedef struct lcs_options {
     double inner_tol;      /* mixed precision: inner FP32 PCG stops at
                               ||r32|| <= inner_tol ||r32_0|| (default 1e-5)         */
     int32_t max_iter;      /* PCG iteration cap per solve (all outer steps)         */
-    int32_t precond;       /* LCS_PC_*; RBSGS needs a 2-colourable stencil
-                              (5- or 7-point)                                       */
+    int32_t precond;       /* LCS_PC_*; RBSGS is the symmetric colour-ordered
+                              Gauss-Seidel preconditioner from z = 0 (colours
+                              0..c-1, then back to 0): red-black (c = 2) for the
+                              5- and 7-point stencils, four colours (x mod 2 +
+                              2 (y mod 2)) for the 9-point stencil; EINVAL for
+                              LCS_STENCIL9N_2D                                      */
     int32_t precision;     /* LCS_PREC_FP64 or LCS_PREC_MIXED                       */
     int32_t n_smooth;      /* Gauss-Seidel sweeps on x~ (Algorithm 1 step 7)        */
     int32_t check_every;   /* PCG iterations between host convergence checks       */

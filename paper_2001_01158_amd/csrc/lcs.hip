@@ -210,8 +210,8 @@ lcs_status check_options(const lcs_options *o, int kind) {
         return fail(LCS_EINVAL, "negative iteration counts");
     if (o->precond < 0 || o->precond > 2) return fail(LCS_EINVAL, "unknown preconditioner");
     if (o->precision < 0 || o->precision > 1) return fail(LCS_EINVAL, "unknown precision");
-    if (o->precond == LCS_PC_RBSGS && (kind == LCS_STENCIL9_2D || kind == LCS_STENCIL9N_2D))
-        return fail(LCS_EINVAL, "red-black SGS needs a 2-colourable stencil (5- or 7-point)");
+    if (o->precond == LCS_PC_RBSGS && kind == LCS_STENCIL9N_2D)
+        return fail(LCS_EINVAL, "symmetric Gauss-Seidel needs a symmetric operator");
     if (kind == LCS_STENCIL9N_2D) {
         if (o->precision != LCS_PREC_FP64)
             return fail(LCS_EINVAL, "the non-symmetric operator is solved by GMRES in FP64");

@@ -262,6 +262,49 @@ def test_pcg_matches_dense_solve(kind, pc):
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= max(10 * cond * 1e-13, 1e-12)
 
 
+@pytest.mark.parametrize("kind", [W.KIND_5PT, W.KIND_9PT, W.KIND_7PT])
+def test_sgs_colours_never_couple(kind):
+    """The Gauss-Seidel colouring: no stored off-diagonal entry joins two
+    cells of one colour (so a colour's rows update independently); two colours
+    for the five- and seven-point stencils, four for the nine-point one."""
+    if kind == W.KIND_5PT:
+        coef, _ = small_5pt(9, 8); dims = (9, 8, 1)
+    elif kind == W.KIND_9PT:
+        coef = small_9pt(9, 8); dims = (9, 8, 1)
+    else:
+        coef, _ = small_7pt(5); dims = (5, 5, 5)
+    A = oracle.csr_from_stencil(kind, *dims, coef)
+    assert A.ncolours == (4 if kind == W.KIND_9PT else 2)
+    rows = np.repeat(np.arange(A.n), np.diff(A.rp))
+    off = rows != A.col
+    assert np.all(A.colour[rows[off]] != A.colour[A.col[off]])
+    assert set(np.unique(A.colour)) == set(range(A.ncolours))
+
+
+@pytest.mark.parametrize("kind", [W.KIND_5PT, W.KIND_9PT])
+def test_sgs_pcg_first_step_is_dense_symmetric_gauss_seidel(kind):
+    """One SGS-PCG step from x = 0 against the dense formula: with the cells
+    ordered by colour, A = D + L + U and M = (D + L) D^-1 (D + U); z = M^-1 b,
+    x_1 = (b.z / z.A z) z."""
+    if kind == W.KIND_5PT:
+        coef, _ = small_5pt(7, 6); dims = (7, 6, 1)
+    else:
+        coef = small_9pt(7, 6); dims = (7, 6, 1)
+    A = oracle.csr_from_stencil(kind, *dims, coef)
+    a = A.dense()
+    order = np.argsort(A.colour, kind="stable")
+    ap = a[np.ix_(order, order)]
+    D = np.diag(np.diag(ap))
+    M = (D + np.tril(ap, -1)) @ np.linalg.inv(D) @ (D + np.triu(ap, 1))
+    b = np.random.default_rng(17).standard_normal(A.n)
+    z = np.empty(A.n)
+    z[order] = np.linalg.solve(M, b[order])
+    x1 = (b @ z) / (z @ a @ z) * z
+    x, st, it, res = oracle.pcg(A, b, np.zeros(A.n), oracle.PC_SGS, 0.0, 1)
+    assert it == 1
+    np.testing.assert_allclose(x, x1, rtol=1e-12, atol=1e-14 * np.abs(x1).max())
+
+
 def test_pcg_manufactured_solution():
     coef, _ = small_5pt(24, 20)
     A = oracle.csr_from_stencil(W.KIND_5PT, 24, 20, 1, coef)
