@@ -295,6 +295,31 @@ def param_sweep(workload: str, steps: int):
     table("residual (paper threshold), E_max", rows)
 
 
+def csr_from_nine_point(coef, nx: int, ny: int):
+    """CSR (int32 row pointers and columns, ascending columns per row) of the
+    symmetric nine-point stencil whose arrays are coef = [C, E, N, NE, NW]
+    (torch tensors on any device): row i couples to i +- 1 through E, to
+    i +- nx through N, to i +- (nx + 1) through NE and to i +- (nx - 1)
+    through NW, each coefficient stored once, at the lower-indexed cell."""
+    import torch
+    C, E, N, NE, NW = coef
+    n = nx * ny
+    dev = C.device
+    i = torch.arange(n, device=dev, dtype=torch.int64)
+    y, x = i // nx, i % nx
+    w, e, s_, nn = x > 0, x < nx - 1, y > 0, y < ny - 1
+    slots = [(s_ & w, -nx - 1, NE, True), (s_, -nx, N, True), (s_ & e, -nx + 1, NW, True),
+             (w, -1, E, True), (torch.ones_like(w), 0, C, False), (e, 1, E, False),
+             (nn & w, nx - 1, NW, False), (nn, nx, N, False), (nn & e, nx + 1, NE, False)]
+    ok = torch.stack([m for m, _, _, _ in slots], 1)
+    col = torch.stack([i + d for _, d, _, _ in slots], 1)
+    val = torch.stack([arr[torch.where(m, i + d, i)] if lower else arr
+                       for m, d, arr, lower in slots], 1)
+    crow = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    crow[1:] = torch.cumsum(ok.sum(1), 0)
+    return crow.to(torch.int32), col[ok].to(torch.int32), val[ok]
+
+
 def tiling_sweep():
     """The 4096^2 nine-point FP32 SpMV under each walk of the 2-D kernels
     (lcs_set_tiling): flat, and row marching with and without the
@@ -325,6 +350,38 @@ def tiling_sweep():
         print(f"| {walk} | {'-' if rows < 0 else (32 if rows == 0 else rows)} | "
               f"{'-' if rows < 0 else ('no' if nt == 0 else 'yes')} | {us:.1f} | "
               f"{n3 * n3 * 28 / us / 1e3:.0f} |", flush=True)
+    # external yardstick: the same FP32 matrix as CSR through torch's sparse
+    # matrix-vector products (the ROCm sparse library underneath)
+    crow, col, val = csr_from_nine_point(A9.coef32.reshape(5, -1), n3, n3)
+    Acsr = torch.sparse_csr_tensor(crow, col, val, size=(n3 * n3, n3 * n3))
+    del crow, col, val
+    csr_yardstick("torch.sparse.mm", lambda: torch.sparse.mm(Acsr, x.reshape(-1, 1)), A9, x, y,
+                  n3, Acsr.values().numel(), stream, ctx)
+
+
+def csr_yardstick(name, prod, A9, x, y, n3, nnz, stream, ctx):
+    """One row of the tiling-sweep table: a library CSR product of the same
+    matrix, its time, GB/s on the stencil's 28 B per row and on its own
+    bytes, and its largest difference from the stencil SpMV."""
+    import torch
+    from paper_2001_01158_amd import lcs
+    for _ in range(3):
+        yc = prod()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        yc = prod()
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) / 20 * 1e3
+    lcs.set_tiling(0, -1, ctx=ctx)
+    lcs.spmv(A9, x, y, ctx=ctx)
+    torch.cuda.synchronize()
+    rel = float((yc.reshape(-1) - y).abs().max() / y.abs().max())
+    csr_bytes = nnz * 8 + (n3 * n3 + 1) * 4 + 2 * n3 * n3 * 4
+    print(f"| CSR, {name} (library) | - | - | {us:.1f} | {n3 * n3 * 28 / us / 1e3:.0f} "
+          f"(its own {csr_bytes / n3 / n3:.0f} B per row: {csr_bytes / us / 1e3:.0f}; max rel. "
+          f"difference {rel:.1e}) |", flush=True)
 
 
 def heat_run(n: int, steps: int):
