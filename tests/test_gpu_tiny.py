@@ -1,7 +1,8 @@
 """GPU parity on degenerate grids: single cells, one-cell-wide strips, grids
 smaller than one marching tile or one vector unit, for every stencil kind.
 Per-row kernels and local domains bit for bit against the oracle; converged
-solves (global and Algorithm 1) against the oracle's criterion and a dense
+solves (global and Algorithm 1; FP64 and mixed, Jacobi and SGS; single and
+batched) against the oracle's criterion and a dense
 solve."""
 import numpy as np
 import pytest
@@ -41,14 +42,7 @@ def host(t):
 
 def make(kind, dims, seed=0):
     nx, ny, nz = dims
-    if kind == W.KIND_5PT:
-        coef = W.assemble_5pt(W.lognormal_logk((ny, nx), 1.0, 40 + seed), 0.25)
-    elif kind == W.KIND_9PT:
-        coef = W.assemble_9pt(nx, ny, 0.25, 100.0, 30.0)
-    elif kind == W.KIND_7PT:
-        coef = W.assemble_7pt(W.lognormal_logk((nz, ny, nx), 1.0, 40 + seed), 0.25)
-    else:
-        coef = W.assemble_9n(nx, ny, 0.25, speed=2.0)
+    coef = W.assemble_9n(nx, ny, 0.25, speed=2.0) if kind == W.KIND_9N else lcs_coef(kind, dims, seed)
     Ah = oracle.csr_from_stencil(kind, nx, ny, nz, coef)
     rng = np.random.default_rng(seed)
     x_true = rng.random(Ah.n) + 0.5
@@ -96,13 +90,52 @@ def test_tiny_solves_converge(kind, dims):
     nb = np.linalg.norm(b)
     xd = np.linalg.solve(Ah.dense(), b)
     cond = np.linalg.cond(Ah.dense())
-    for call in ("global", "residual", "gradient"):
-        x = dev(x0)
-        o = lcs.Options(eps=1e-10)
-        if call == "global":
-            lcs.solve_global(A, dev(b), x, o)
-        else:
-            lcs.solve_local_then_global(A, dev(b), x, call, "relmax", 0.3, 1, o)
-        xg = host(x)
-        assert np.linalg.norm(oracle.residual(Ah, b, xg)) <= 1.0001e-10 * nb, call
-        assert np.linalg.norm(xg - xd) / np.linalg.norm(xd) <= max(10 * cond * 1e-10, 1e-12), call
+    variants = [dict()]
+    if kind != W.KIND_9N:   # GMRES runs in FP64 with Jacobi or nothing
+        variants += [dict(precond="rbsgs"), dict(precision="mixed"),
+                     dict(precision="mixed", precond="rbsgs")]
+    for extra in variants:
+        o = lcs.Options(eps=1e-10, **extra)
+        if extra.get("precision") == "mixed":
+            A.coef32 = lcs.cast_coef(A)
+        for call in ("global", "residual", "gradient"):
+            x = dev(x0)
+            if call == "global":
+                lcs.solve_global(A, dev(b), x, o)
+            else:
+                lcs.solve_local_then_global(A, dev(b), x, call, "relmax", 0.3, 1, o)
+            xg = host(x)
+            what = (call, extra)
+            assert np.linalg.norm(oracle.residual(Ah, b, xg)) <= 1.0001e-10 * nb, what
+            assert np.linalg.norm(xg - xd) / np.linalg.norm(xd) <= max(10 * cond * 1e-10, 1e-12), what
+
+
+@pytest.mark.parametrize("kind,dims", [(k, s) for k, s in CASES if k != W.KIND_9N],
+                         ids=[name(k, s) for k, s in CASES if k != W.KIND_9N])
+def test_tiny_batched(kind, dims):
+    """Three systems of a degenerate grid in one batched launch: each meets
+    the criterion, with the oracle's domain size."""
+    nx, ny, nz = dims
+    say("tiny batched", name(kind, dims))
+    cases = [make(kind, dims, seed=g) for g in range(3)]
+    coef = np.stack([lcs_coef(kind, dims, g) for g in range(3)])
+    b = np.stack([c[2] for c in cases])
+    x0 = np.stack([c[3] for c in cases])
+    A = lcs.BatchMatrix(kind, nx, ny, nz, dev(coef))
+    x = dev(x0)
+    sts = lcs.solve_local_then_global_batched(A, dev(b), x, "residual", "relmax", 0.3, 1,
+                                              lcs.Options(eps=1e-10))
+    xg = host(x)
+    for g, (Ah, _, bg, x0g) in enumerate(cases):
+        d = oracle.build_local_domain(Ah, bg, x0g, oracle.MODE_RESIDUAL, 0.3, oracle.TH_RELMAX, 1)
+        assert sts[g].K == d.K
+        assert np.linalg.norm(oracle.residual(Ah, bg, xg[g])) <= 1.0001e-10 * np.linalg.norm(bg)
+
+
+def lcs_coef(kind, dims, seed):
+    nx, ny, nz = dims
+    if kind == W.KIND_5PT:
+        return W.assemble_5pt(W.lognormal_logk((ny, nx), 1.0, 40 + seed), 0.25)
+    if kind == W.KIND_9PT:
+        return W.assemble_9pt(nx, ny, 0.25, 100.0, 30.0)
+    return W.assemble_7pt(W.lognormal_logk((nz, ny, nx), 1.0, 40 + seed), 0.25)
