@@ -77,6 +77,9 @@ def parse():
                    help="run the 2-D nonlinear heat-conduction test (Section 3.1) on N x N cells with "
                         "the three methods and exit")
     p.add_argument("--heat-steps", type=int, default=100, help="time steps of --heat (paper: 100)")
+    p.add_argument("--adjoint", action="store_true",
+                   help="time the forward and backward passes of one step of the 2048^2 sequence "
+                        "(loss over a 256^2 window) against a full-domain adjoint, and exit")
     p.add_argument("--mg", action="store_true",
                    help="time the 64 group systems of a multi-group source iteration (Section 3.3): "
                         "batched (one launch) and per system, and exit")
@@ -164,9 +167,11 @@ def summarize(d: str, steps: int):
         dur = lambda rs: sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rs) / max(len(rs), 1) / 1e3
         if allk:
             out.append("")
-            out.append(f"dominant kernel `{short(dom)}`: whole run {len(allk)} dispatches, avg {dur(allk):.2f} us; "
-                       f"timed pass (last {steps} residual-mode systems) {len(win)} dispatches, avg "
-                       f"{dur(win):.2f} us")
+            line = f"`{short(dom)}`: whole run {len(allk)} dispatches, avg {dur(allk):.2f} us"
+            if steps > 0:
+                line = (f"dominant kernel {line}; timed pass (last {steps} residual-mode systems) "
+                        f"{len(win)} dispatches, avg {dur(win):.2f} us")
+            out.append(line)
         # batched launches, split by the number of systems (one workgroup each)
         by = {}
         for r in trace:
@@ -477,6 +482,95 @@ def heat_run(n: int, steps: int):
           "iteration, from the global-PCG trajectory)\n")
 
 
+def adjoint_run(reps: int):
+    """The adjoint of one step: system 10 of the 2048^2 five-point sequence
+    (sigma = 1, disk radius 40), loss 0.5 ||x - x_obs||^2 over a 256^2 window on the
+    front, gradients with respect to b and the 4.2M log-conductivities.
+    Forward = Algorithm 1 from x_(k-1) (assembly from log k, domain, local
+    solve, finish); backward = lambda on the forward's domain (local solve,
+    finish) plus the grad log k kernel.  Against: the global PCG forward and a
+    full-domain adjoint (global PCG for lambda from 0, same gradient kernel).
+    Median wall ms over reps, inputs resident."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+    from paper_2001_01158_amd.autograd import LocalSolve, SolveConfig
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    w = W.c4_adjoint()
+    nx, ny, n = w.nx, w.ny, w.nx * w.ny
+    inv_dt = 1.0 / w.dt
+    eps = 1e-10
+    ctx = lcs.Context()
+    logk = torch.as_tensor(w.logk.reshape(-1)).to(dev)
+    A = lcs.Matrix(W.KIND_5PT, nx, ny, 1, lcs.assemble_logk(W.KIND_5PT, nx, ny, 1, inv_dt, logk,
+                                                             ctx=ctx))
+    o = lcs.Options(eps=eps)
+    zero = np.zeros(n)
+    x_prev = torch.zeros(n, dtype=torch.float64, device=dev)
+    for k in range(w.n_systems - 1):   # the sequence up to x_(k-1) of the last system
+        b = x_prev * inv_dt + torch.as_tensor(w.rhs(k, zero)).to(dev)
+        lcs.solve_global(A, b, x_prev, o, ctx=ctx)
+    b = x_prev * inv_dt + torch.as_tensor(w.rhs(w.n_systems - 1, zero)).to(dev)
+    logk2 = torch.as_tensor(W.lognormal_logk((ny, nx), 1.0, W.BASE_SEED + 4).reshape(-1)).to(dev)
+    A2 = lcs.Matrix(W.KIND_5PT, nx, ny, 1, lcs.assemble_logk(W.KIND_5PT, nx, ny, 1, inv_dt, logk2,
+                                                              ctx=ctx))
+    x_obs = x_prev.clone()
+    lcs.solve_global(A2, b, x_obs, o, ctx=ctx)
+    win = torch.zeros(ny, nx, dtype=torch.float64, device=dev)
+    win[ny // 2 - 128: ny // 2 + 128, nx // 2 - 128: nx // 2 + 128] = 1.0
+    win = win.reshape(-1)
+    cfg = SolveConfig(kind=W.KIND_5PT, nx=nx, ny=ny, nz=1, inv_dt=inv_dt, mode="residual",
+                      thresh="paper", theta=eps, e_max=1, opts=o)
+
+    def med(ts):
+        return float(np.median(ts))
+
+    fwd, bwd, fwd_g, bwd_g = [], [], [], []
+    grads = None
+    for _ in range(reps + 1):
+        lk = logk.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = LocalSolve.apply(lk, b, x_prev, cfg, ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * torch.sum(win * (x - x_obs) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd.append((t1 - t0) * 1e3)
+        bwd.append((t2 - t1) * 1e3)
+        # full-domain reference: global PCG forward and adjoint
+        xg = x_prev.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lcs.solve_global(A, b, xg, o, ctx=ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = (win * (xg - x_obs)).contiguous()
+        lam = torch.zeros_like(g)
+        lcs.solve_global(A, g, lam, o, ctx=ctx)
+        gl = lcs.grad_logk(W.KIND_5PT, nx, ny, 1, logk, xg, lam, ctx=ctx)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd_g.append((t1 - t0) * 1e3)
+        bwd_g.append((t2 - t1) * 1e3)
+        grads = (lk.grad.detach(), gl)
+    fwd, bwd, fwd_g, bwd_g = fwd[1:], bwd[1:], fwd_g[1:], bwd_g[1:]
+    rel = float(torch.linalg.norm(grads[0] - grads[1]) / torch.linalg.norm(grads[1]))
+    print(f"### Adjoint of one step: {nx} x {ny} five-point FP64, loss over a 256 x 256 window, "
+          f"eps = {eps:g}\n")
+    print("| path | forward ms | backward ms | forward + backward ms |")
+    print("|---|---|---|---|")
+    print(f"| local (Algorithm 1 forward, adjoint on its domain) | {med(fwd):.3f} | {med(bwd):.3f} | "
+          f"{med(fwd) + med(bwd):.3f} |")
+    print(f"| full domain (global PCG forward and adjoint) | {med(fwd_g):.3f} | {med(bwd_g):.3f} | "
+          f"{med(fwd_g) + med(bwd_g):.3f} |")
+    print(f"\nspeedup {(med(fwd_g) + med(bwd_g)) / (med(fwd) + med(bwd)):.2f}; "
+          f"|grad log k (local) - grad log k (full domain)| / |full domain| = {rel:.2e}; "
+          f"median of {reps} repetitions", flush=True)
+
+
 def mg_run(reps: int):
     """The G = 64 group systems of one source iteration of the multi-group
     test (Section 3.3; seeded stand-in, 88 x 80 = 7040 cells, nine-point):
@@ -580,6 +674,9 @@ def main():
     args = parse()
     if args.mg:
         mg_run(max(args.steps // 4, 5))
+        return
+    if args.adjoint:
+        adjoint_run(max(args.steps // 8, 3))
         return
     if args.heat:
         heat_run(args.heat, args.heat_steps)
