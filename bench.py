@@ -80,6 +80,8 @@ def parse():
     p.add_argument("--adjoint", action="store_true",
                    help="time the forward and backward passes of one step of the 2048^2 sequence "
                         "(loss over a 256^2 window) against a full-domain adjoint, and exit")
+    p.add_argument("--mg-nonsym", action="store_true",
+                   help="--mg with non-symmetric group operators solved by GMRES(40)")
     p.add_argument("--mg", action="store_true",
                    help="time the 64 group systems of a multi-group source iteration (Section 3.3): "
                         "batched (one launch) and per system, and exit")
@@ -571,7 +573,7 @@ def adjoint_run(reps: int):
           f"median of {reps} repetitions", flush=True)
 
 
-def mg_run(reps: int):
+def mg_run(reps: int, nonsym: bool = False):
     """The G = 64 group systems of one source iteration of the multi-group
     test (Section 3.3; seeded stand-in, 88 x 80 = 7040 cells, nine-point):
     M0 = global Jacobi PCG, M1 = gradient domain (alpha = 1e-10), M2 =
@@ -579,12 +581,14 @@ def mg_run(reps: int):
     (1) all 64 systems in one batched launch (one workgroup per system);
     (2) single systems (the batched call with G = 1) for the groups of the
     paper's Table speedup-MG; (3) the 64 systems one after another through
-    the grid-wide single-system path.  Wall time per call, inputs resident."""
+    the grid-wide single-system path.  Wall time per call, inputs resident.
+    nonsym: the non-symmetric operators of mg_batch_nonsym (full storage),
+    solved by GMRES(40) in both the local and the global solves."""
     import torch
     from paper_2001_01158_amd import lcs, workloads as W
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    w = W.mg_batch()
+    w = W.mg_batch_nonsym() if nonsym else W.mg_batch()
     N = w.nx * w.ny
     coef = torch.as_tensor(w.coef).to(dev)
     b = torch.as_tensor(w.b).to(dev)
@@ -592,8 +596,8 @@ def mg_run(reps: int):
     x = torch.empty_like(x0)
     ctx = lcs.Context()
     o = lcs.Options(eps=W.MG_EPS)
-    label = {"M0": "M0 (global PCG)", "M1": "M1 (gradient, alpha 1e-10)",
-             "M2": "M2 (residual, E_max 1)"}
+    label = {"M0": "M0 (global GMRES)" if nonsym else "M0 (global PCG)",
+             "M1": "M1 (gradient, alpha 1e-10)", "M2": "M2 (residual, E_max 1)"}
 
     def batched(A, bb, xx, m):
         if m == "M0":
@@ -617,9 +621,10 @@ def mg_run(reps: int):
             ts.append((time.perf_counter() - t0) * 1e3)
         return float(np.median(ts)), out
 
-    A = lcs.BatchMatrix(W.KIND_9PT, w.nx, w.ny, 1, coef)
+    A = lcs.BatchMatrix(w.kind, w.nx, w.ny, 1, coef)
+    op = "non-symmetric nine-point, GMRES(40)" if nonsym else "nine-point, PCG"
     print(f"### Multi-group source iteration: {w.G} systems of {w.nx} x {w.ny} = {N} cells, "
-          f"nine-point, eps = {W.MG_EPS:g}\n")
+          f"{op}, eps = {W.MG_EPS:g}\n")
     print("| method | one batched launch, 64 systems (ms) | per system (ms) | mean eta | max its per "
           "system (local + global) |")
     print("|---|---|---|---|---|")
@@ -635,7 +640,7 @@ def mg_run(reps: int):
     print("| group | kappa_g | eta M1 | eta M2 | M0 ms | M1 ms | M2 ms | S M1 | S M2 | its M0 / M1 / M2 |")
     print("|---|---|---|---|---|---|---|---|---|---|")
     for g in (1, 10, 41, 55, 63):
-        Ag = lcs.BatchMatrix(W.KIND_9PT, w.nx, w.ny, 1, coef[g:g + 1].contiguous())
+        Ag = lcs.BatchMatrix(w.kind, w.nx, w.ny, 1, coef[g:g + 1].contiguous())
         bg, xs, xg = b[g:g + 1].contiguous(), x0[g:g + 1].contiguous(), torch.empty_like(x0[:1])
         t, st = {}, {}
         for m in ("M0", "M1", "M2"):
@@ -647,7 +652,7 @@ def mg_run(reps: int):
               f"{t['M0'] / t['M2']:.2f} | {its} |", flush=True)
     print()
     # the same 64 systems through the grid-wide single-system path
-    mats = [lcs.Matrix(W.KIND_9PT, w.nx, w.ny, 1, coef[g].contiguous()) for g in range(w.G)]
+    mats = [lcs.Matrix(w.kind, w.nx, w.ny, 1, coef[g].contiguous()) for g in range(w.G)]
 
     def sequential(m):
         for g in range(w.G):
@@ -672,8 +677,8 @@ def mg_run(reps: int):
 
 def main():
     args = parse()
-    if args.mg:
-        mg_run(max(args.steps // 4, 5))
+    if args.mg or args.mg_nonsym:
+        mg_run(max(args.steps // 4, 5), nonsym=args.mg_nonsym)
         return
     if args.adjoint:
         adjoint_run(max(args.steps // 8, 3))

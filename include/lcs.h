@@ -233,6 +233,9 @@ lcs_status lcs_set_tiling(lcs_ctx *ctx, int32_t march_rows, int32_t nontemporal)
  *   b, x:    device, [G][N]; x in x^(0), out the solutions.
  *   st:      host array of G stats, or NULL; ms_* fields are 0 (one launch
  *            serves all systems: time the call).
+ * The symmetric kinds run PCG; LCS_STENCIL9N_2D runs restarted GMRES(m)
+ * (o->restart) in the local and the global solve, as the single-system
+ * calls do, with a workspace of (m + 1) N doubles per system for the bases.
  * FP64 only (precision must be LCS_PREC_FP64), Jacobi or no preconditioner,
  * 1 <= G <= 65535, N <= 2^24 cells per system; otherwise LCS_EINVAL.  Every
  * system runs to completion; the call then returns the error of the first

@@ -126,7 +126,7 @@ enum BufId {
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
     B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_W0, B_W1, B_S0, B_S1, B_W32A, B_W32B,
     B_S32A, B_S32B, B_BWS, B_BSTAMP, B_BIDX, B_BOUT, B_GMV, B_GMW0, B_GMW1, B_GMP0,
-    B_GMPN, B_GMS, B_NUM
+    B_GMPN, B_GMS, B_BGMV, B_NUM
 };
 
 }  // namespace
@@ -1060,7 +1060,8 @@ template <class S>
 lcs_status launch_batch(lcs_ctx *c, const S &A, int pc, const BatchArgs &a, int32_t G,
                         const double *b, double *x, double *ws, uint8_t *stamp, int32_t *idx,
                         BatchOut *out, hipStream_t s) {
-    // systems of at most kLdsRows cells keep p and q of the PCG in LDS
+    // systems of at most kLdsRows cells keep PCG's p and q (GMRES: z and w)
+    // in LDS
     const bool lds = A.n <= kLdsRows;
     if (pc == LCS_PC_JACOBI) {
         if (lds)
@@ -1090,8 +1091,6 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     if (local) LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
-    if (A->kind == LCS_STENCIL9N_2D)
-        return fail(LCS_EINVAL, "batched solves take the symmetric stencils (PCG)");
     if (G < 1 || G > kMaxBatch) return fail(LCS_EINVAL, "batch size G must be 1..65535");
     if (o->precision != LCS_PREC_FP64) return fail(LCS_EINVAL, "batched solves run in FP64");
     if (o->precond == LCS_PC_RBSGS)
@@ -1111,6 +1110,12 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
     a.max_iter = o->max_iter;
     a.max_outer = o->max_outer;
     a.n_smooth = o->n_smooth;
+    a.restart = 0;
+    a.gm_V = nullptr;
+    if (A->kind == LCS_STENCIL9N_2D) {   // GMRES(m): one basis per system
+        a.restart = o->restart;
+        LCS_TRY(get_buf(c, B_BGMV, (size_t)(a.restart + 1) * n * G, &a.gm_V));
+    }
     double *ws;
     uint8_t *stamp;
     int32_t *idx;
@@ -1138,6 +1143,9 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
         break;
     case LCS_STENCIL9_2D:
         LCS_TRY(launch_batch(c, sop9<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));
+        break;
+    case LCS_STENCIL9N_2D:
+        LCS_TRY(launch_batch(c, sop9n<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));
         break;
     default:
         LCS_TRY(launch_batch(c, sop7<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));

@@ -21,8 +21,18 @@
 // (residual, gradient, expansion bound, Gauss-Seidel update) uses the same
 // for_each order as the grid-wide kernels and the oracle; only the dot
 // products are summed in another order (a fixed workgroup tree).
+//
+// The non-symmetric nine-point kind (full storage) is solved by restarted
+// GMRES(m) instead of PCG, in the local and the global solve, with the same
+// steps as the grid-wide GMRES: classical Gram-Schmidt applied twice, Givens
+// rotations on the Hessenberg matrix, right Jacobi preconditioning, a true
+// residual at the start of every cycle.  The basis lives in a per-system
+// workspace, the Hessenberg matrix and the rotations in LDS.
 #pragma once
 
+#include <type_traits>
+
+#include "lcs_gmres.h"
 #include "lcs_kernels.h"
 
 namespace lcs {
@@ -65,6 +75,17 @@ __device__ __forceinline__ Stencil7<real> shifted(Stencil7<real> A, int64_t off)
     A.U += off;
     return A;
 }
+
+template <typename real>
+__device__ __forceinline__ Stencil9N<real> shifted(Stencil9N<real> A, int64_t off) {
+    A.a += off;
+    return A;
+}
+
+template <class S>
+struct is_full9 : std::false_type {};
+template <typename real>
+struct is_full9<Stencil9N<real>> : std::true_type {};
 
 // Branch-free neighbour table of one stencil row.  Slot k runs over the
 // row's entries in ascending column order (the order of for_each): column
@@ -167,6 +188,35 @@ struct RowN<Stencil7<real>> {
         a[4] = A.E[i];
         a[5] = A.N[i];
         a[6] = A.U[i];
+    }
+};
+
+template <typename real>
+struct RowN<Stencil9N<real>> {
+    static constexpr int NB = 9, kC = 4;
+    int32_t j[NB];   // fits: at most 2^24 cells per system
+    bool ok[NB];
+    __device__ __forceinline__ RowN(const Stencil9N<real> &A, int64_t i) {
+        const int y = (int)((uint32_t)i / (uint32_t)A.nx), x = (int)i - y * A.nx;
+        const bool w = x > 0, e = x < A.nx - 1, s = y > 0, n = y < A.ny - 1;
+        ok[0] = s && w;
+        ok[1] = s;
+        ok[2] = s && e;
+        ok[3] = w;
+        ok[4] = true;
+        ok[5] = e;
+        ok[6] = n && w;
+        ok[7] = n;
+        ok[8] = n && e;
+        const int32_t ii = (int32_t)i, nx = A.nx;
+        const int32_t d[NB] = {-nx - 1, -nx, -nx + 1, -1, 0, 1, nx - 1, nx, nx + 1};
+#pragma unroll
+        for (int k = 0; k < NB; ++k) j[k] = ok[k] ? ii + d[k] : ii;
+    }
+    // full storage: all nine coefficients of row i sit in row i's slots
+    __device__ __forceinline__ void coef(const Stencil9N<real> &A, int64_t i, double (&a)[NB]) const {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) a[k] = A.a[(int64_t)k * A.n + i];
     }
 };
 
@@ -455,6 +505,173 @@ __device__ int wg_global(const S &A, const double *__restrict__ b, double *x, do
     return st;
 }
 
+// Restarted GMRES(m) of one workgroup on the active rows (cnt rows: idx[0..cnt)
+// or all of A), right-preconditioned by Jacobi (kPc 1) or by nothing:
+// A M^-1 u = rhs - A sol, sol += M^-1 u.  zb holds a vector supported on the
+// active rows (zero elsewhere) for the SpMV gathers, wb the current Arnoldi
+// vector (own rows only), V the (m + 1) x n basis.  Every cycle starts from
+// the true residual; a cycle ends after m steps, at the estimate meeting tol,
+// or at max_iter steps in all.  A cycle that ended on the estimate (or the
+// cap) is followed by a check of the true residual, and at most max_outer
+// such checks may fail before kStNoConv.  Returns kStOk, kStNoConv,
+// kStBreakdown or kStNonFinite; *its = Arnoldi steps, *rr_true = the last
+// true ||rhs - A sol||^2.
+constexpr int kGmChunk = 4;   // basis vectors per workgroup reduction of a Gram-Schmidt pass
+
+template <class S, int kPc>
+__device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt,
+                        const double *__restrict__ rhs, double *sol, double *zb, double *wb,
+                        double *V, int m, double tol, int max_iter, int max_outer, int *its,
+                        int *restarts, double *rr_true) {
+    using RN = RowN<S>;
+    __shared__ GmState L;   // Hessenberg matrix, rotations, g, y (one per workgroup)
+    const int tid = threadIdx.x;
+    const int64_t n = A.n;
+    int it = 0, outer = 0;
+    *its = 0;
+    *restarts = 0;
+    for (int64_t i = tid; i < n; i += kBatchBlock) zb[i] = 0.0;
+    __syncthreads();
+    // w = v - A zb over the active rows, v = rhs (residual) or 0 (product)
+    auto spmv_rows = [&](bool residual) {
+        double acc2 = 0.0;
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            const RN Rw(A, i);
+            double cf[RN::NB], zv[RN::NB];
+            Rw.coef(A, i, cf);
+#pragma unroll
+            for (int q = 0; q < RN::NB; ++q) zv[q] = zb[Rw.j[q]];
+            double acc = residual ? rhs[i] : 0.0;
+#pragma unroll
+            for (int q = 0; q < RN::NB; ++q) {
+                const double tt = residual ? fma(-cf[q], zv[q], acc) : fma(cf[q], zv[q], acc);
+                acc = Rw.ok[q] ? tt : acc;
+            }
+            wb[i] = acc;
+            acc2 += acc * acc;
+        }
+        return acc2;
+    };
+    bool check_pending = false;
+    for (;;) {
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            zb[i] = sol[i];
+        }
+        __syncthreads();
+        double v[1] = {spmv_rows(true)};
+        wg_reduce<1>(v, Ops<0u>());
+        const double beta = sqrt(v[0]);
+        *rr_true = v[0];
+        if (!(beta == beta)) {
+            *its = it;
+            return kStNonFinite;
+        }
+        if (beta <= tol) {
+            *its = it;
+            return kStOk;
+        }
+        if (check_pending) {   // the true residual missed tol after the estimate met it
+            if (it >= max_iter || outer >= max_outer) {
+                *its = it;
+                return kStNoConv;
+            }
+            ++outer;
+            *restarts = outer;
+        } else if (it >= max_iter) {
+            *its = it;
+            return kStNoConv;
+        }
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            V[i] = wb[i] / beta;
+        }
+        if (tid == 0) {
+            L.tol = tol;
+            L.done = 0;
+            L.status = kStOk;
+            gm_column(&L, 0, beta);
+        }
+        for (int j = 0; j < m && it < max_iter; ++j) {
+            const double *vj = V + (int64_t)j * n;
+            for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+                const int64_t i = row_of(idx, t);
+                zb[i] = kPc ? vj[i] / A.diag(i) : vj[i];
+            }
+            __syncthreads();
+            (void)spmv_rows(false);   // w = A M^-1 v_j
+            // classical Gram-Schmidt, twice: h = V^T w, w -= V h
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int c0 = 0; c0 <= j; c0 += kGmChunk) {
+                    double d[kGmChunk] = {0.0, 0.0, 0.0, 0.0};
+                    for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+                        const int64_t i = row_of(idx, t);
+                        const double wi = wb[i];
+#pragma unroll
+                        for (int q = 0; q < kGmChunk; ++q)
+                            if (c0 + q <= j) d[q] += V[(int64_t)(c0 + q) * n + i] * wi;
+                    }
+                    wg_reduce<kGmChunk>(d, Ops<0u>());
+                    if (tid == 0)
+                        for (int q = 0; q < kGmChunk && c0 + q <= j; ++q) L.hc[c0 + q] = d[q];
+                }
+                __syncthreads();   // hc of this pass visible
+                for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+                    const int64_t i = row_of(idx, t);
+                    double wi = wb[i];
+                    for (int q = 0; q <= j; ++q) wi = fma(-L.hc[q], V[(int64_t)q * n + i], wi);
+                    wb[i] = wi;
+                }
+                if (tid == 0) {
+                    double *h = L.H + j * kGmLd;
+                    for (int q = 0; q <= j; ++q) h[q] = pass == 0 ? L.hc[q] : h[q] + L.hc[q];
+                }
+                __syncthreads();   // hc read by all before the next pass rewrites it
+            }
+            double nv[1] = {0.0};
+            for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+                const int64_t i = row_of(idx, t);
+                nv[0] += wb[i] * wb[i];
+            }
+            wg_reduce<1>(nv, Ops<0u>());
+            const double nrm = sqrt(nv[0]);
+            ++it;
+            if (tid == 0) gm_column(&L, j + 1, nrm);   // rotations, residual estimate
+            __syncthreads();
+            if (L.done) break;
+            double *vn = V + (int64_t)(j + 1) * n;
+            for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+                const int64_t i = row_of(idx, t);
+                vn[i] = wb[i] / nrm;
+            }
+        }
+        if (L.status != kStOk) {
+            *its = it;
+            return L.status;
+        }
+        if (tid == 0) {   // back substitution, H y = g on the k completed columns
+            const int k = L.k;
+            for (int i = k - 1; i >= 0; --i) {
+                double acc = L.g[i];
+                for (int l = i + 1; l < k; ++l) acc -= L.H[l * kGmLd + i] * L.y[l];
+                L.y[i] = acc / L.H[i * kGmLd + i];
+            }
+        }
+        __syncthreads();
+        const int k = L.k;
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
+            const int64_t i = row_of(idx, t);
+            double u = 0.0;
+            for (int q = 0; q < k; ++q) u = fma(L.y[q], V[(int64_t)q * n + i], u);
+            if (kPc) u = u / A.diag(i);
+            sol[i] += u;
+        }
+        check_pending = L.done || it >= max_iter;
+        __syncthreads();   // L read by all before the next cycle rewrites it
+    }
+}
+
 struct BatchArgs {
     int64_t coef_stride;   // doubles between consecutive systems' coefficient sets
     int local;             // 0: global PCG only (the baseline); 1: Algorithm 1
@@ -463,6 +680,8 @@ struct BatchArgs {
     int e_max;
     double eps, tol_local;
     int max_iter, max_outer, n_smooth;
+    int restart;           // GMRES restart length (non-symmetric kind)
+    double *gm_V;          // GMRES bases: (restart + 1) x n doubles per system
 };
 
 // One workgroup per system g = blockIdx.x.  ws: 4 n doubles per system
@@ -480,6 +699,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
     const double *b = b_all + (int64_t)g * n;
     double *x = x_all + (int64_t)g * n;
     double *r = ws + (int64_t)g * 4 * n, *p = r + n, *q = p + n, *d = q + n;
+    double *gm_V = a.gm_V ? a.gm_V + (int64_t)g * (a.restart + 1) * n : nullptr;
     uint8_t *stamp = stamp_all + (int64_t)g * n;
     int32_t *idx = idx_all + (int64_t)g * n;
     BatchOut o{};
@@ -597,12 +817,21 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
         for (int64_t t = tid; t < K; t += kBatchBlock) d[idx[t]] = 0.0;
         __syncthreads();
         int its = 0;
-        if constexpr (kLds)
+        if constexpr (is_full9<S>::value) {
+            int rst = 0;
+            double rr_loc = 0.0;
+            double *zb = kLds ? p_lds : p, *wb = kLds ? p_lds + kLdsRows : q;
+            o.status_local = wg_gmres<S, kPc>(A, idx, K, r, d, zb, wb, gm_V, a.restart,
+                                              a.tol_local * bn, a.max_iter, a.max_outer, &its,
+                                              &rst, &rr_loc);
+            o.n_outer += rst;
+        } else if constexpr (kLds) {
             o.status_local = wg_pcg_lds<S, kPc>(A, idx, K, r, d, p_lds, a.tol_local * bn,
                                                 a.max_iter, &its);
-        else
+        } else {
             o.status_local = wg_pcg<S, kPc>(A, idx, K, r, d, p, q, a.tol_local * bn, a.max_iter,
                                             &its);
+        }
         o.its_local = its;
         if (o.status_local == kStBreakdown || o.status_local == kStNonFinite) {
             o.status = o.status_local;
@@ -645,10 +874,16 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(S A0, BatchArgs a,
     if (need_global) {
         // r holds b - A x here (either r0 or the post-smoothing residual)
         int its = 0, restarts = 0;
-        st_global = wg_global<S, kPc, kLds>(A, b, x, r, p, q, p_lds, tol, a.max_iter,
-                                            a.max_outer, &its, &restarts, &rr);
+        if constexpr (is_full9<S>::value) {
+            double *zb = kLds ? p_lds : p, *wb = kLds ? p_lds + kLdsRows : q;
+            st_global = wg_gmres<S, kPc>(A, nullptr, A.n, b, x, zb, wb, gm_V, a.restart, tol,
+                                         a.max_iter, a.max_outer, &its, &restarts, &rr);
+        } else {
+            st_global = wg_global<S, kPc, kLds>(A, b, x, r, p, q, p_lds, tol, a.max_iter,
+                                                a.max_outer, &its, &restarts, &rr);
+        }
         o.its_global = its;
-        o.n_outer = restarts;
+        o.n_outer += restarts;
     }
     o.status = st_global;
     o.relres_final = bn > 0 ? sqrt(rr) / bn : sqrt(rr);

@@ -422,6 +422,7 @@ class MGBatch:
     b: np.ndarray          # (G, N)
     x0: np.ndarray         # (G, N) previous state of each group
     kappa: np.ndarray      # (G,) diffusion coefficient per group
+    kind: int = KIND_9PT   # KIND_9PT (coef (G, 5, N)) or KIND_9N (coef (G, 9, N))
 
 
 def _scipy_matrix(kind: int, nx: int, ny: int, nz: int, coef: np.ndarray):
@@ -485,3 +486,60 @@ def mg_batch(nx: int = 88, ny: int = 80, G: int = 64, dt: float = 1.0, sigma: fl
         coef[g, 0] += 1.0 / dt + sigma
         b[g] = x0[g] / dt + q1
     return MGBatch(f"mg{G}_{nx}x{ny}_9pt", nx, ny, G, coef, b, x0, kappa)
+
+
+NINE_OFFSETS = [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 0), (0, 1), (1, -1), (1, 0), (1, 1)]
+
+
+def _scipy_matrix_9n(nx: int, ny: int, coef: np.ndarray):
+    """The matrix of full-storage nine-point coefficients (scipy CSR): slot k
+    of row (x, y) couples to (x + dx_k, y + dy_k), in the slot order of
+    assemble_9n, to generate previous states by a direct solve."""
+    import scipy.sparse as sp
+    c = np.asarray(coef).reshape(9, ny, nx)
+    y, x = np.mgrid[0:ny, 0:nx]
+    rows, cols, vals = [], [], []
+    for k, (dy, dx) in enumerate(NINE_OFFSETS):
+        m = (x + dx >= 0) & (x + dx < nx) & (y + dy >= 0) & (y + dy < ny)
+        rows.append((y * nx + x)[m])
+        cols.append(((y + dy) * nx + (x + dx))[m])
+        vals.append(c[k][m])
+    n = nx * ny
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n))
+
+
+def mg_batch_nonsym(nx: int = 88, ny: int = 80, G: int = 64, dt: float = 1.0, sigma: float = 1.0,
+                    kappa_lo: float = 0.1, kappa_hi: float = 316.0, radius: float = 6.0,
+                    shift: float = 3.0, speed: float = 2.0,
+                    seed: int = BASE_SEED + 7) -> MGBatch:
+    """The G group systems of mg_batch with non-symmetric operators, as the
+    paper's deforming-mesh systems are (solved by GMRES):
+    A_g = (1/dt + sigma) I + kappa_g D + C, with D the anisotropic nine-point
+    diffusion of assemble_9n and C its upwind convection in a rotating flow of
+    the given speed, the same for every group.  x0_g is the steady state of the
+    source at c0, (sigma I + kappa_g D + C) x0_g = q(c0), and b_g moves the
+    source to c1, as in mg_batch."""
+    import scipy.sparse.linalg as spla
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    kappa = np.exp(np.linspace(np.log(kappa_lo), np.log(kappa_hi), G))
+    qg = np.exp(rng.normal(0.0, 0.5, G))
+    dif = assemble_9n(nx, ny, 0.0, 4.0, 30.0, speed=0.0)
+    conv = assemble_9n(nx, ny, 0.0, 4.0, 30.0, speed=speed) - dif
+    c0 = (nx / 2.0 - shift / 2.0, ny / 2.0)
+    c1 = (nx / 2.0 + shift / 2.0, ny / 2.0)
+    coef = np.empty((G, 9, n))
+    b = np.empty((G, n))
+    x0 = np.empty((G, n))
+    for g in range(G):
+        L = kappa[g] * dif + conv
+        ss = L.copy()
+        ss[4] += sigma
+        q0 = disk_source(nx, ny, c0[0], c0[1], radius, qg[g])
+        q1 = disk_source(nx, ny, c1[0], c1[1], radius, qg[g])
+        x0[g] = spla.spsolve(_scipy_matrix_9n(nx, ny, ss).tocsc(), q0)
+        coef[g] = L
+        coef[g, 4] += 1.0 / dt + sigma
+        b[g] = x0[g] / dt + q1
+    return MGBatch(f"mg{G}_{nx}x{ny}_9n", nx, ny, G, coef, b, x0, kappa, kind=KIND_9N)
