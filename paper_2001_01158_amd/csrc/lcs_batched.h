@@ -516,8 +516,6 @@ __device__ int wg_global(const S &A, const double *__restrict__ b, double *x, do
 // such checks may fail before kStNoConv.  Returns kStOk, kStNoConv,
 // kStBreakdown or kStNonFinite; *its = Arnoldi steps, *rr_true = the last
 // true ||rhs - A sol||^2.
-constexpr int kGmChunk = 4;   // basis vectors per workgroup reduction of a Gram-Schmidt pass
-
 template <class S, int kPc>
 __device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt,
                         const double *__restrict__ rhs, double *sol, double *zb, double *wb,
@@ -548,7 +546,7 @@ __device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt
                 const double tt = residual ? fma(-cf[q], zv[q], acc) : fma(cf[q], zv[q], acc);
                 acc = Rw.ok[q] ? tt : acc;
             }
-            wb[i] = acc;
+            wb[t] = acc;
             acc2 += acc * acc;
         }
         return acc2;
@@ -583,10 +581,7 @@ __device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt
             *its = it;
             return kStNoConv;
         }
-        for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-            const int64_t i = row_of(idx, t);
-            V[i] = wb[i] / beta;
-        }
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) V[t] = wb[t] / beta;
         if (tid == 0) {
             L.tol = tol;
             L.done = 0;
@@ -597,31 +592,28 @@ __device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt
             const double *vj = V + (int64_t)j * n;
             for (int64_t t = tid; t < cnt; t += kBatchBlock) {
                 const int64_t i = row_of(idx, t);
-                zb[i] = kPc ? vj[i] / A.diag(i) : vj[i];
+                zb[i] = kPc ? vj[t] / A.diag(i) : vj[t];
             }
             __syncthreads();
             (void)spmv_rows(false);   // w = A M^-1 v_j
-            // classical Gram-Schmidt, twice: h = V^T w, w -= V h
+            // classical Gram-Schmidt, twice: h = V^T w, w -= V h.  Wave q
+            // forms the dot products of basis vectors q, q + 16, ... over all
+            // rows and reduces them within the wave: one barrier per pass.
             for (int pass = 0; pass < 2; ++pass) {
-                for (int c0 = 0; c0 <= j; c0 += kGmChunk) {
-                    double d[kGmChunk] = {0.0, 0.0, 0.0, 0.0};
-                    for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-                        const int64_t i = row_of(idx, t);
-                        const double wi = wb[i];
-#pragma unroll
-                        for (int q = 0; q < kGmChunk; ++q)
-                            if (c0 + q <= j) d[q] += V[(int64_t)(c0 + q) * n + i] * wi;
-                    }
-                    wg_reduce<kGmChunk>(d, Ops<0u>());
-                    if (tid == 0)
-                        for (int q = 0; q < kGmChunk && c0 + q <= j; ++q) L.hc[c0 + q] = d[q];
+                __syncthreads();   // w of the SpMV or of the last update visible
+                const int wave = tid / kWave, lane = tid & (kWave - 1);
+                for (int c = wave; c <= j; c += kBatchWaves) {
+                    const double *vc = V + (int64_t)c * n;
+                    double acc = 0.0;
+                    for (int64_t t = lane; t < cnt; t += kWave) acc += vc[t] * wb[t];
+                    acc = wave_reduce(acc, OpSum());
+                    if (lane == 0) L.hc[c] = acc;
                 }
                 __syncthreads();   // hc of this pass visible
                 for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-                    const int64_t i = row_of(idx, t);
-                    double wi = wb[i];
-                    for (int q = 0; q <= j; ++q) wi = fma(-L.hc[q], V[(int64_t)q * n + i], wi);
-                    wb[i] = wi;
+                    double wi = wb[t];
+                    for (int q = 0; q <= j; ++q) wi = fma(-L.hc[q], V[(int64_t)q * n + t], wi);
+                    wb[t] = wi;
                 }
                 if (tid == 0) {
                     double *h = L.H + j * kGmLd;
@@ -630,10 +622,7 @@ __device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt
                 __syncthreads();   // hc read by all before the next pass rewrites it
             }
             double nv[1] = {0.0};
-            for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-                const int64_t i = row_of(idx, t);
-                nv[0] += wb[i] * wb[i];
-            }
+            for (int64_t t = tid; t < cnt; t += kBatchBlock) nv[0] += wb[t] * wb[t];
             wg_reduce<1>(nv, Ops<0u>());
             const double nrm = sqrt(nv[0]);
             ++it;
@@ -641,10 +630,7 @@ __device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt
             __syncthreads();
             if (L.done) break;
             double *vn = V + (int64_t)(j + 1) * n;
-            for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-                const int64_t i = row_of(idx, t);
-                vn[i] = wb[i] / nrm;
-            }
+            for (int64_t t = tid; t < cnt; t += kBatchBlock) vn[t] = wb[t] / nrm;
         }
         if (L.status != kStOk) {
             *its = it;
@@ -663,7 +649,7 @@ __device__ int wg_gmres(const S &A, const int32_t *__restrict__ idx, int64_t cnt
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
             const int64_t i = row_of(idx, t);
             double u = 0.0;
-            for (int q = 0; q < k; ++q) u = fma(L.y[q], V[(int64_t)q * n + i], u);
+            for (int q = 0; q < k; ++q) u = fma(L.y[q], V[(int64_t)q * n + t], u);
             if (kPc) u = u / A.diag(i);
             sol[i] += u;
         }
