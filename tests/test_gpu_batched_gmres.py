@@ -213,3 +213,24 @@ def test_multigroup_nonsym_batch_full_size():
             assert rel <= 1.0001 * W.MG_EPS, (name, g, rel)
         say(f"  {name}: worst relres {worst:.2e}, its of group 63: "
             f"{sts[-1].its_local}+{sts[-1].its_global}")
+
+
+@pytest.mark.parametrize("call", ["global", "local_then_global"])
+def test_batched_gmres_nonfinite_system_reported_others_solved(call):
+    A, Ahs, b, x0 = make_batch(3, GRIDS["lds"])
+    b = b.copy()
+    b[1, 5] = np.nan
+    say("batched gmres nonfinite", call)
+    x = dev(x0)
+    with pytest.raises(lcs.LcsError) as e:
+        if call == "global":
+            lcs.solve_global_batched(A, dev(b), x, lcs.Options(eps=1e-10))
+        else:
+            lcs.solve_local_then_global_batched(A, dev(b), x, "residual", "relmax", 1e-3, 1,
+                                                lcs.Options(eps=1e-10))
+    assert e.value.status == lcs.ENONFINITE
+    assert "system 1" in str(e.value)
+    xg = host(x)
+    for g in (0, 2):
+        nb = np.linalg.norm(b[g])
+        assert np.linalg.norm(oracle.residual(Ahs[g], b[g], xg[g])) <= 1.0001e-10 * nb
