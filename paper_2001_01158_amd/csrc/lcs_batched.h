@@ -380,12 +380,18 @@ __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t c
     using RN = RowN<S>;
     const int tid = threadIdx.x;
     double *p_lds = lds, *q_lds = lds + kLdsRows;
+    // the active rows of a local system, copied once into LDS: every row
+    // loop below reads its cell index from there instead of global memory
+    __shared__ int32_t idx_lds[kLdsRows];
+    auto row = [&](int64_t t) -> int64_t { return idx ? (int64_t)idx_lds[t] : t; };
     *its = 0;
+    if (idx)
+        for (int64_t t = tid; t < cnt; t += kBatchBlock) idx_lds[t] = idx[t];
     for (int64_t i = tid; i < A.n; i += kBatchBlock) p_lds[i] = 0.0;
     __syncthreads();
     double v[2] = {0.0, 0.0};
     for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-        const int64_t i = row_of(idx, t);
+        const int64_t i = row(t);
         const double ri = r[i];
         const double z = kPc ? ri / A.diag(i) : ri;
         p_lds[i] = z;
@@ -400,7 +406,7 @@ __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t c
     while (it < max_iter) {
         double pq[1] = {0.0};
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-            const int64_t i = row_of(idx, t);
+            const int64_t i = row(t);
             const RN Rw(A, i);
             double cf[RN::NB], pv[RN::NB];
             Rw.coef(A, i, cf);
@@ -427,7 +433,7 @@ __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t c
         double w[2] = {0.0, 0.0};
 #pragma unroll 2
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-            const int64_t i = row_of(idx, t);
+            const int64_t i = row(t);
             sol[i] = fma(alpha, p_lds[i], sol[i]);
             const double ri = fma(-alpha, q_lds[i], r[i]);
             r[i] = ri;
@@ -451,7 +457,7 @@ __device__ int wg_pcg_lds(const S &A, const int32_t *__restrict__ idx, int64_t c
         rz = w[1];
 #pragma unroll 2
         for (int64_t t = tid; t < cnt; t += kBatchBlock) {
-            const int64_t i = row_of(idx, t);
+            const int64_t i = row(t);
             p_lds[i] = fma(beta, p_lds[i], q_lds[i]);
         }
         __syncthreads();
