@@ -32,6 +32,23 @@
  *     right-preconditioned by Jacobi or nothing, in FP64; the criterion and
  *     Algorithm 1 are unchanged.  Batched solves and the adjoint take the
  *     symmetric kinds only.
+ *   - LCS_CSR is a general symmetric sparse matrix (the paper's setting
+ *     before any grid is assumed, Section 2.1) in CSR: nx = N, ny = nz = 1,
+ *     row_ptr int32[N+1], col int32[nnz] strictly ascending within each row
+ *     with the diagonal stored, val double[nnz]; every row holds 1..16
+ *     entries.  Each call checks this structure before any kernel reads
+ *     through col (LCS_EINVAL naming what failed; symmetry is the caller's
+ *     to ensure, as for the stencils) and copies A into column-major ELL
+ *     of width 8 or 16 in the context's workspace, on which the whole path
+ *     runs.  Scores, thresholds, expansion, compaction and the gather of B
+ *     follow the stencil kinds' definitions over the stored entries.  The
+ *     Gauss-Seidel sweeps and the RB-SGS preconditioner need a colouring:
+ *     colour uint8[N] (device) with n_colours classes such that no stored
+ *     off-diagonal entry joins two rows of one colour (checked).  Without
+ *     one (colour = NULL) Algorithm 1 skips the smoothing step, RB-SGS and
+ *     lcs_gs_sweeps return LCS_EINVAL.  coef and coef32 are ignored; the
+ *     FP32 copy for LCS_PREC_MIXED is made inside each call.  Batched
+ *     solves, lcs_cast_coef and the adjoint helpers take stencils only.
  *   - Vector arguments are device pointers of length N = nx*ny*nz (FP64)
  *     owned by the caller; the library never frees them.  Index arrays are
  *     int32 (N < 2^31).
@@ -66,7 +83,8 @@ typedef enum lcs_status {
     LCS_ENONFINITE = 6    /* NaN / Inf in the input or the iteration              */
 } lcs_status;
 
-enum { LCS_STENCIL5_2D = 0, LCS_STENCIL9_2D = 1, LCS_STENCIL7_3D = 2, LCS_STENCIL9N_2D = 3 };
+enum { LCS_STENCIL5_2D = 0, LCS_STENCIL9_2D = 1, LCS_STENCIL7_3D = 2, LCS_STENCIL9N_2D = 3,
+       LCS_CSR = 4 };
 enum { LCS_MODE_RESIDUAL = 0, LCS_MODE_GRADIENT = 1 };
 enum {
     LCS_THRESH_REL_MAX = 0,  /* tau = theta * max_i |s_i|  (s = r^(0) or g)       */
@@ -78,11 +96,18 @@ enum { LCS_PC_NONE = 0, LCS_PC_JACOBI = 1, LCS_PC_RBSGS = 2 };
 enum { LCS_PREC_FP64 = 0, LCS_PREC_MIXED = 1 };
 
 typedef struct lcs_matrix {
-    int32_t kind;          /* LCS_STENCIL*                                         */
-    int32_t nx, ny, nz;    /* grid; nz = 1 in 2-D                                  */
+    int32_t kind;          /* LCS_STENCIL* or LCS_CSR                              */
+    int32_t nx, ny, nz;    /* grid; nz = 1 in 2-D; CSR: N, 1, 1                    */
     const double *coef;    /* device, n_arrays x N, FP64                           */
     const float *coef32;   /* device, n_arrays x N, FP32 copy for LCS_PREC_MIXED;
                               NULL: the library casts coef into its workspace      */
+    /* LCS_CSR only (zero / NULL for the stencil kinds) */
+    const int32_t *row_ptr;   /* device, N + 1                                     */
+    const int32_t *col;       /* device, nnz                                       */
+    const double *val;        /* device, nnz                                       */
+    int64_t nnz;
+    const uint8_t *colour;    /* device, N, or NULL                                */
+    int32_t n_colours;        /* 1..255 with a colouring                           */
 } lcs_matrix;
 
 typedef struct lcs_options {

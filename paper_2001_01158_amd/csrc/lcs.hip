@@ -17,6 +17,7 @@
 #include "lcs_kernels.h"
 #include "lcs_batched.h"
 #include "lcs_gmres.h"
+#include "lcs_csr.h"
 
 using namespace lcs;
 
@@ -53,6 +54,11 @@ int n_arrays(int kind) {
     return kind == LCS_STENCIL5_2D ? 3 : kind == LCS_STENCIL9_2D ? 5 : kind == LCS_STENCIL9N_2D ? 9 : 4;
 }
 int n_colours(int kind) { return kind == LCS_STENCIL9_2D || kind == LCS_STENCIL9N_2D ? 4 : 2; }
+// colours of the Gauss-Seidel sweeps; 0 for a general sparse matrix given
+// without a colouring (no sweeps)
+int colours_of(const lcs_matrix *A) {
+    return A->kind == LCS_CSR ? (A->colour ? A->n_colours : 0) : n_colours(A->kind);
+}
 
 struct Launch {
     int grid;
@@ -126,7 +132,7 @@ enum BufId {
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
     B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_W0, B_W1, B_S0, B_S1, B_W32A, B_W32B,
     B_S32A, B_S32B, B_BWS, B_BSTAMP, B_BIDX, B_BOUT, B_GMV, B_GMW0, B_GMW1, B_GMP0,
-    B_GMPN, B_GMS, B_BGMV, B_NUM
+    B_GMPN, B_GMS, B_BGMV, B_ACOL, B_AVAL, B_ACLR, B_AFLAGS, B_NUM
 };
 
 }  // namespace
@@ -156,6 +162,14 @@ struct lcs_ctx {
     int32_t hbout_cap = 0;
     // pinned host copy of the GMRES cycle state
     GmState *hgm = nullptr;
+    // ELL copy of the general sparse matrix of the current call
+    struct {
+        int width = 0;         // 8 or 16
+        int64_t n = 0;
+        int32_t *col = nullptr;
+        double *val = nullptr;   // width x n values, then the diagonal
+        uint8_t *clr = nullptr;
+    } ell;
 };
 
 namespace {
@@ -194,8 +208,18 @@ lcs_status read_scalars(lcs_ctx *c, hipStream_t s) {
 
 lcs_status check_matrix(const lcs_matrix *A) {
     if (!A) return fail(LCS_EINVAL, "matrix is NULL");
-    if (A->kind < 0 || A->kind > 3) return fail(LCS_EINVAL, "unknown matrix kind");
+    if (A->kind < 0 || A->kind > 4) return fail(LCS_EINVAL, "unknown matrix kind");
     if (A->nx < 1 || A->ny < 1 || A->nz < 1) return fail(LCS_EINVAL, "grid sizes must be >= 1");
+    if (A->kind == LCS_CSR) {
+        if (A->ny != 1 || A->nz != 1) return fail(LCS_EINVAL, "a CSR matrix has nx = N, ny = nz = 1");
+        if (A->nx >= (1 << 27)) return fail(LCS_EINVAL, "N must be < 2^27");
+        if (!A->row_ptr || !A->col || !A->val) return fail(LCS_EINVAL, "row_ptr, col or val is NULL");
+        if (A->nnz < 1 || A->nnz > (int64_t)kCsrMaxRow * A->nx)
+            return fail(LCS_EINVAL, "nnz must be in 1 .. 16 N");
+        if (A->colour && (A->n_colours < 1 || A->n_colours > 255))
+            return fail(LCS_EINVAL, "n_colours must be 1..255 with a colouring");
+        return LCS_OK;
+    }
     if (A->kind != LCS_STENCIL7_3D && A->nz != 1) return fail(LCS_EINVAL, "2-D stencil needs nz = 1");
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
     if (n >= ((int64_t)1 << 31) / 16) return fail(LCS_EINVAL, "N must be < 2^27");
@@ -218,6 +242,13 @@ lcs_status check_options(const lcs_options *o, int kind) {
         if (o->restart < 1 || o->restart > kMaxRestart)
             return fail(LCS_EINVAL, "GMRES restart length must be 1..64");
     }
+    return LCS_OK;
+}
+
+lcs_status check_options_for(const lcs_options *o, const lcs_matrix *A) {
+    LCS_TRY(check_options(o, A->kind));
+    if (A->kind == LCS_CSR && o->precond == LCS_PC_RBSGS && !A->colour)
+        return fail(LCS_EINVAL, "symmetric Gauss-Seidel on a CSR matrix needs its colouring");
     return LCS_OK;
 }
 
@@ -310,6 +341,17 @@ template <class F>
 lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, bool vec_ok, F &&f) {
     const bool v = vec_ok && A->nx % 4 == 0 && aligned16(A->coef) && aligned16(coef32);
     const Tuning t{c->march_rows, c->nontemporal};
+    if (A->kind == LCS_CSR) {   // the ELL copy made by prepare_matrix
+        const auto &E = c->ell;
+        const float *v32 = coef32, *d32 = coef32 ? coef32 + (int64_t)E.width * E.n : nullptr;
+        if (E.width == 8)
+            return f(EllRows<double, 8>{E.col, E.val, E.val + 8 * E.n, E.clr, E.n},
+                     UEll<double, 8>{E.col, E.val, E.val + 8 * E.n, E.clr, E.n},
+                     UEll<float, 8>{E.col, v32, d32, E.clr, E.n}, Width<8>());
+        return f(EllRows<double, 16>{E.col, E.val, E.val + 16 * E.n, E.clr, E.n},
+                 UEll<double, 16>{E.col, E.val, E.val + 16 * E.n, E.clr, E.n},
+                 UEll<float, 16>{E.col, v32, d32, E.clr, E.n}, Width<16>());
+    }
     switch (A->kind) {
     case LCS_STENCIL5_2D: {
         const auto s5 = sop5<double>(A, A->coef);
@@ -345,10 +387,63 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
     }
 }
 
+// General sparse input: check the structure (one synchronisation, before
+// any kernel reads through the column indices), then copy A into
+// column-major ELL of width 8 or 16 in the context.  Stencil kinds: nothing.
+lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
+    if (A->kind != LCS_CSR) return LCS_OK;
+    const int64_t n = A->nx;
+    int32_t *flags;
+    LCS_TRY(get_buf(c, B_AFLAGS, 2, &flags));
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, s, flags, 0, (int64_t)2);
+    hipLaunchKernelGGL(k_csr_check, dim3(std::min(flat_grid(n), kMaxGrid)), dim3(kBlock), 0, s,
+                       A->row_ptr, A->col, n, A->nnz, A->colour, A->n_colours, flags);
+    LAUNCH_CHECK();
+    int32_t h[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h[0]) {
+        std::string m = "CSR matrix:";
+        if (h[0] & kCsrBadPtr) m += " row_ptr not non-decreasing in [0, nnz];";
+        if (h[0] & kCsrEnds) m += " row_ptr[0] != 0 or row_ptr[N] != nnz;";
+        if (h[0] & kCsrEmpty) m += " empty row;";
+        if (h[0] & kCsrLong) m += " row longer than 16 entries;";
+        if (h[0] & kCsrCol) m += " column out of range;";
+        if (h[0] & kCsrOrder) m += " columns not strictly ascending;";
+        if (h[0] & kCsrNoDiag) m += " diagonal entry missing;";
+        if (h[0] & kCsrColour) m += " colouring invalid (colour >= n_colours or two coupled rows share one);";
+        return fail(LCS_EINVAL, m);
+    }
+    const int W = h[1] <= 8 ? 8 : 16;
+    LCS_TRY(get_buf(c, B_ACOL, (size_t)W * n, &c->ell.col));
+    LCS_TRY(get_buf(c, B_AVAL, (size_t)(W + 1) * n, &c->ell.val));
+    LCS_TRY(get_buf(c, B_ACLR, (size_t)n, &c->ell.clr));
+    if (W == 8)
+        hipLaunchKernelGGL(k_csr_to_ell<8>, dim3(flat_grid(n)), dim3(kBlock), 0, s, A->row_ptr,
+                           A->col, A->val, n, A->colour, c->ell.col, c->ell.val, c->ell.clr);
+    else
+        hipLaunchKernelGGL(k_csr_to_ell<16>, dim3(flat_grid(n)), dim3(kBlock), 0, s, A->row_ptr,
+                           A->col, A->val, n, A->colour, c->ell.col, c->ell.val, c->ell.clr);
+    LAUNCH_CHECK();
+    c->ell.width = W;
+    c->ell.n = n;
+    return LCS_OK;
+}
+
 lcs_status ensure_coef32(lcs_ctx *c, const lcs_matrix *A, bool need, const float **out,
                          hipStream_t s) {
     *out = nullptr;
     if (!need) return LCS_OK;
+    if (A->kind == LCS_CSR) {   // FP32 copy of the ELL values and the diagonal
+        const int64_t m = (int64_t)(c->ell.width + 1) * c->ell.n;
+        float *p;
+        LCS_TRY(get_buf(c, B_COEF32, (size_t)m, &p));
+        hipLaunchKernelGGL(k_cast, dim3(flat_grid(m)), dim3(kBlock), 0, s, (const double *)c->ell.val,
+                           p, m);
+        LAUNCH_CHECK();
+        *out = p;
+        return LCS_OK;
+    }
     if (A->coef32) {
         *out = A->coef32;
         return LCS_OK;
@@ -395,7 +490,16 @@ lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<typename Op::re
     if (kPc != LCS_PC_RBSGS) return LCS_OK;
     real *part = slot_as<real>(c, kPtSgs);
     const Scalars *sc = c->dsc;
-    // colour 0 of the forward sweep is done by the kernel that formed r
+    // colour 0 of the forward sweep is done by the kernel that formed r.
+    // One colour (a diagonal matrix with a one-class colouring): the backward
+    // pass is colour 0 again, which reproduces z bit for bit and writes the
+    // r.z partials.
+    if (ncol == 1) {
+        hipLaunchKernelGGL((k_gs_half<Op, true>), dim3(grid), dim3(kBlock), 0, s, A,
+                           (const real *)B.r, B.z, 0, sc, part);
+        LAUNCH_CHECK();
+        return LCS_OK;
+    }
     for (int col = 1; col < ncol; ++col)
         hipLaunchKernelGGL((k_gs_half<Op, false>), dim3(grid), dim3(kBlock), 0, s, A,
                            (const real *)B.r, B.z, col, sc, part);
@@ -961,7 +1065,7 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
                        const double *b, double *x, const int32_t *idx, int64_t K,
                        const int32_t *inv, const double *r0, const lcs_options *o,
                        lcs_stats *st, Timers &tm, hipStream_t s) {
-    const int ncol = n_colours(M->kind);
+    const int ncol = colours_of(M);
     if (K > 0) {
         if (!r0) {
             double *r;
@@ -1087,7 +1191,8 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
                          const lcs_options *o, lcs_stats *st, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
-    LCS_TRY(check_options(o, A->kind));
+    if (A->kind == LCS_CSR) return fail(LCS_EINVAL, "batched solves take the stencil kinds");
+    LCS_TRY(check_options_for(o, A));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     if (local) LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
@@ -1246,6 +1351,7 @@ lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const 
                         double *r, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(r, "r"));
@@ -1262,6 +1368,7 @@ lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const 
 lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double *g, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(g, "g"));
     hipStream_t s = (hipStream_t)stream;
@@ -1279,6 +1386,7 @@ lcs_status lcs_spmv(lcs_ctx *c, const lcs_matrix *A, const void *x, void *y, int
                     int32_t reps, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(y, "y"));
     if (precision != LCS_PREC_FP64 && precision != LCS_PREC_MIXED)
@@ -1304,6 +1412,8 @@ lcs_status lcs_spmv(lcs_ctx *c, const lcs_matrix *A, const void *x, void *y, int
 lcs_status lcs_cast_coef(lcs_ctx *c, const lcs_matrix *A, float *coef32, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    if (A->kind == LCS_CSR)
+        return fail(LCS_EINVAL, "the FP32 copy of a CSR matrix is made inside each call");
     LCS_TRY(check_ptr(coef32, "coef32"));
     const int64_t n = (int64_t)A->nx * A->ny * A->nz * n_arrays(A->kind);
     hipLaunchKernelGGL(k_cast, dim3(flat_grid(n)), dim3(kBlock), 0, (hipStream_t)stream, A->coef,
@@ -1318,6 +1428,7 @@ lcs_status lcs_build_local_domain(lcs_ctx *c, const lcs_matrix *A, const double 
                                   int64_t *K, lcs_stats *st, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x0, "x0"));
     LCS_TRY(check_ptr(idx, "idx"));
@@ -1347,6 +1458,7 @@ lcs_status lcs_gather_restricted(lcs_ctx *c, const lcs_matrix *A, const int32_t 
                                  void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
     if (K < 0 || K > n) return fail(LCS_EINVAL, "K out of range");
     if (K > 0) {
@@ -1392,11 +1504,13 @@ lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, doubl
                          int32_t n_sweeps, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     if (n_sweeps < 0) return fail(LCS_EINVAL, "n_sweeps < 0");
     hipStream_t s = (hipStream_t)stream;
-    const int ncol = n_colours(A->kind);
+    const int ncol = colours_of(A);
+    if (ncol == 0) return fail(LCS_EINVAL, "Gauss-Seidel sweeps on a CSR matrix need its colouring");
     return with_ops(c, A, nullptr, vec_ok({b, x}), [&](auto, auto op, auto, auto) -> lcs_status {
         const int grid = grid_for(op, kStreamGrid);
         for (int sw = 0; sw < n_sweeps; ++sw)
@@ -1413,7 +1527,8 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
                             const lcs_options *o, lcs_stats *st, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
-    LCS_TRY(check_options(o, A->kind));
+    LCS_TRY(check_options_for(o, A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     lcs_stats local;
@@ -1429,7 +1544,7 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         LCS_TRY(tm.mark(3));
         SolveOut so;
-        const lcs_status rs = solve_system(c, op, op32, n_colours(A->kind), b, x, false,
+        const lcs_status rs = solve_system(c, op, op32, colours_of(A), b, x, false,
                                            &c->dsc->bnorm, o->eps, o, s, &so, 0);
         LCS_TRY(tm.mark(4));
         HIP_TRY(hipStreamSynchronize(s));
@@ -1448,7 +1563,8 @@ lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, dou
                            void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
-    LCS_TRY(check_options(o, A->kind));
+    LCS_TRY(check_options_for(o, A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
@@ -1492,7 +1608,8 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
                                        lcs_stats *st, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
-    LCS_TRY(check_options(o, A->kind));
+    LCS_TRY(check_options_for(o, A));
+    LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
@@ -1548,7 +1665,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
             LCS_TRY(tm.mark(4));
         } else {
             SolveOut so;
-            rs = solve_system(c, op, op32, n_colours(A->kind), b, x, false, &c->dsc->bnorm, o->eps,
+            rs = solve_system(c, op, op32, colours_of(A), b, x, false, &c->dsc->bnorm, o->eps,
                               o, s, &so, 0);
             st->its_global = so.its;
             st->n_outer += so.n_outer;

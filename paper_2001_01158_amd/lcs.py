@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblcs.so")
 
 OK, EINVAL, EHIP, ENOMEM, ENOCONV, EBREAKDOWN, ENONFINITE = range(7)
-STENCIL5_2D, STENCIL9_2D, STENCIL7_3D, STENCIL9N_2D = 0, 1, 2, 3
+STENCIL5_2D, STENCIL9_2D, STENCIL7_3D, STENCIL9N_2D, CSR = 0, 1, 2, 3, 4
 MODE_RESIDUAL, MODE_GRADIENT = 0, 1
 THRESH_REL_MAX, THRESH_ABS, THRESH_PAPER = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_RBSGS = 0, 1, 2
@@ -48,7 +48,9 @@ class LcsError(RuntimeError):
 
 class _Matrix(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nz", ctypes.c_int32), ("coef", ctypes.c_void_p), ("coef32", ctypes.c_void_p)]
+                ("nz", ctypes.c_int32), ("coef", ctypes.c_void_p), ("coef32", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64), ("colour", ctypes.c_void_p), ("n_colours", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -154,9 +156,15 @@ class Matrix:
     coef: torch.Tensor                    # (n_arrays, N) float64, device
     coef32: Optional[torch.Tensor] = None  # (n_arrays, N) float32, device
 
+    max_row = 9   # entries per row, at most
+
     @property
     def n(self) -> int:
         return self.nx * self.ny * self.nz
+
+    @property
+    def device(self) -> torch.device:
+        return self.coef.device
 
     def c(self) -> _Matrix:
         if self.coef.dtype != torch.float64 or self.coef.numel() != N_ARRAYS[self.kind] * self.n:
@@ -165,6 +173,45 @@ class Matrix:
                                         or self.coef32.numel() != self.coef.numel()):
             raise ValueError("coef32 must be float32 of the same shape as coef")
         return _Matrix(self.kind, self.nx, self.ny, self.nz, _ptr(self.coef), _ptr(self.coef32))
+
+
+@dataclasses.dataclass
+class CsrMatrix:
+    """General symmetric sparse matrix in CSR (columns strictly ascending in
+    each row, diagonal stored, 1..16 entries per row), optionally with a
+    colouring for the Gauss-Seidel sweeps; see include/lcs.h."""
+    row_ptr: torch.Tensor                  # int32 [N + 1], device
+    col: torch.Tensor                      # int32 [nnz], device
+    val: torch.Tensor                      # float64 [nnz], device
+    colour: Optional[torch.Tensor] = None  # uint8 [N], device
+    n_colours: int = 0
+    kind = CSR
+    max_row = 16
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.numel() - 1
+
+    @property
+    def device(self) -> torch.device:
+        return self.val.device
+
+    def c(self) -> _Matrix:
+        if self.row_ptr.dtype != torch.int32 or self.col.dtype != torch.int32:
+            raise ValueError("row_ptr and col must be int32")
+        if self.val.dtype != torch.float64 or self.val.numel() != self.col.numel():
+            raise ValueError("val must be float64 with one value per column index")
+        if not (self.row_ptr.is_contiguous() and self.col.is_contiguous() and self.val.is_contiguous()):
+            raise ValueError("row_ptr, col and val must be contiguous")
+        if self.colour is not None and (self.colour.dtype != torch.uint8
+                                        or self.colour.numel() != self.n
+                                        or not self.colour.is_contiguous()):
+            raise ValueError("colour must be contiguous uint8 of length N")
+        m = _Matrix(CSR, self.n, 1, 1, None, None)
+        m.row_ptr, m.col, m.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
+        m.nnz = self.col.numel()
+        m.colour, m.n_colours = _ptr(self.colour), int(self.n_colours)
+        return m
 
 
 @dataclasses.dataclass
@@ -392,10 +439,10 @@ def spmv(A: Matrix, x: torch.Tensor, y: torch.Tensor, reps: int = 1, ctx: Contex
 def gather_restricted(A: Matrix, idx: torch.Tensor, ctx: Context = None):
     """B = A[idx, idx] as (row_ptr int32[K+1], col int32[nnz], val float64[nnz])."""
     K = idx.numel()
-    dev = A.coef.device
+    dev = A.device
     rp = torch.zeros(K + 1, dtype=torch.int32, device=dev)
-    col = torch.empty(max(9 * K, 1), dtype=torch.int32, device=dev)
-    val = torch.empty(max(9 * K, 1), dtype=torch.float64, device=dev)
+    col = torch.empty(max(A.max_row * K, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(A.max_row * K, 1), dtype=torch.float64, device=dev)
     nnz = ctypes.c_int64(0)
     _check(lib().lcs_gather_restricted(_ctx(ctx), ctypes.byref(A.c()),
                                        _ptr(idx.contiguous()) if K else None, K, _ptr(rp), _ptr(col),

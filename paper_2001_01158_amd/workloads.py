@@ -543,3 +543,66 @@ def mg_batch_nonsym(nx: int = 88, ny: int = 80, G: int = 64, dt: float = 1.0, si
         coef[g, 4] += 1.0 / dt + sigma
         b[g] = x0[g] / dt + q1
     return MGBatch(f"mg{G}_{nx}x{ny}_9n", nx, ny, G, coef, b, x0, kappa, kind=KIND_9N)
+
+
+# ---------------------------------------------------------------------------
+# General sparse input: an irregular graph over the cells of an nx x ny grid
+# ---------------------------------------------------------------------------
+def irregular_spd(nx: int, ny: int, seed: int, p_diag: float = 0.5, p_long: float = 0.1,
+                  sigma: float = 1.0, mass: float = 0.25):
+    """Symmetric, strictly diagonally dominant M-matrix on an irregular graph
+    (a stand-in for an unstructured mesh): every cell couples to its four
+    grid neighbours, to each diagonal neighbour with probability p_diag and
+    to the cell two steps east or north with probability p_long, with
+    log-normal weights; the diagonal is the sum of the weights plus mass.
+    At most 11 entries per row.  Returns CSR (rp int64, col int32 ascending,
+    val float64)."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    rows = [dict() for _ in range(n)]
+
+    def link(i, j):
+        w = math.exp(sigma * rng.standard_normal())
+        rows[i][j] = -w
+        rows[j][i] = -w
+
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            if x + 1 < nx:
+                link(i, i + 1)
+            if y + 1 < ny:
+                link(i, i + nx)
+            if x + 1 < nx and y + 1 < ny and rng.random() < p_diag:
+                link(i, i + nx + 1)
+            if x > 0 and y + 1 < ny and rng.random() < p_diag:
+                link(i, i + nx - 1)
+            if x + 2 < nx and rng.random() < p_long:
+                link(i, i + 2)
+            if y + 2 < ny and rng.random() < p_long:
+                link(i, i + 2 * nx)
+    rp = np.zeros(n + 1, np.int64)
+    cols, vals = [], []
+    for i in range(n):
+        r = rows[i]
+        r[i] = -sum(r.values()) + mass
+        for j in sorted(r):
+            cols.append(j)
+            vals.append(r[j])
+        rp[i + 1] = len(cols)
+    return rp, np.array(cols, np.int32), np.array(vals, np.float64)
+
+
+def greedy_colouring(rp: np.ndarray, col: np.ndarray):
+    """Colour rows in index order with the smallest colour unused by any
+    stored neighbour (no entry joins two rows of one colour).  Returns
+    (colour int8[n], number of colours)."""
+    n = rp.size - 1
+    colour = np.full(n, -1, np.int64)
+    for i in range(n):
+        used = {int(colour[j]) for j in col[rp[i]:rp[i + 1]] if j != i and colour[j] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        colour[i] = c
+    return colour.astype(np.int8), int(colour.max()) + 1 if n else 0

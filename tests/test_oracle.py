@@ -683,3 +683,50 @@ def test_local_then_global_with_gmres():
     assert np.array_equal(xl, x)
     xl, sl2 = oracle.solve_global(A, b, xl, o0)
     assert np.array_equal(xl, xg) and sl2.its_global == sg.its_global
+
+
+# ---- general sparse input (an irregular graph, no grid stencil) ----
+def _irregular(nx=13, ny=11, seed=3):
+    rp, col, val = W.irregular_spd(nx, ny, seed)
+    colour, nc = W.greedy_colouring(rp, col)
+    return oracle.CSR(nx * ny, rp, col, val, colour, nc)
+
+
+def test_irregular_input_is_a_symmetric_m_matrix_with_a_valid_colouring():
+    A = _irregular()
+    a = A.dense()
+    assert np.array_equal(a, a.T)
+    off = a - np.diag(np.diag(a))
+    assert (off <= 0).all()
+    assert (np.diag(a) > -off.sum(axis=1)).all()          # strict diagonal dominance
+    assert np.diff(A.rp).max() <= 16
+    for i in range(A.n):
+        cols = A.col[A.rp[i]:A.rp[i + 1]]
+        assert (np.diff(cols) > 0).all() and i in cols
+        assert all(A.colour[j] != A.colour[i] for j in cols if j != i)
+
+
+def test_irregular_gs_sweep_and_solves():
+    """On the irregular pattern: one colour-ordered sweep is the exact solve
+    of each colour's rows given the others; PCG (Jacobi, SGS) and Algorithm 1
+    reach the dense solution."""
+    A = _irregular()
+    a = A.dense()
+    rng = np.random.default_rng(4)
+    b, x = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    y = oracle.gs_sweeps(A, b, x, 1)
+    z = x.copy()
+    for c in range(A.ncolours):
+        for i in np.nonzero(A.colour == c)[0]:
+            z[i] = (b[i] - a[i] @ z + a[i, i] * z[i]) / a[i, i]
+    np.testing.assert_allclose(y, z, rtol=1e-14, atol=1e-14)
+    xs = np.linalg.solve(a, b)
+    for pc in (oracle.PC_JACOBI, oracle.PC_SGS):
+        xo, so = oracle.solve_global(A, b, np.zeros(A.n), oracle.Options(eps=1e-12, pc=pc))
+        assert np.linalg.norm(xo - xs) <= 1e-9 * np.linalg.norm(xs)
+    x0 = xs.copy()
+    x0[40:60] += 0.5
+    xo, so, _ = oracle.local_then_global(A, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1,
+                                         oracle.Options(eps=1e-12))
+    assert 0 < so.K < A.n
+    assert np.linalg.norm(xo - xs) <= 1e-9 * np.linalg.norm(xs)
