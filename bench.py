@@ -65,6 +65,9 @@ def parse():
                    help="replace the workload's preconditioner (rbsgs: colour-ordered symmetric "
                         "Gauss-Seidel, four colours on the nine-point stencil)")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
+    p.add_argument("--csr", action="store_true",
+                   help="hand the workload's matrix to the library in CSR (general sparse "
+                        "input) instead of as a stencil; symmetric workloads")
     p.add_argument("--skip-spmv-hbm", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 512 MiB device copy (traffic-counter calibration)")
@@ -219,10 +222,24 @@ def summarize(d: str, steps: int):
     print("\n".join(out))
 
 
-def setup_sequence(workload: str, precond: str | None = None):
+def csr_input(kind: int, nx: int, ny: int, nz: int, coef, dev):
+    """The stencil matrix as general sparse input: CSR with ascending columns
+    and the grid's colouring (red-black; four colours for nine points)."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+    S = W._scipy_matrix(kind, nx, ny, nz, coef).tocsr()
+    S.sort_indices()
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    colour = (x & 1) + 2 * (y & 1) if kind == W.KIND_9PT else (x + y + z) & 1
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).to(dev)
+    return lcs.CsrMatrix(t(S.indptr, torch.int32), t(S.indices, torch.int32), t(S.data, torch.float64),
+                         t(colour.ravel(), torch.uint8), 4 if kind == W.KIND_9PT else 2)
+
+
+def setup_sequence(workload: str, precond: str | None = None, csr: bool = False):
     """Operator, context, options and the evolved sequence (untimed): X[k] is
     x_(k-1) and Bs[k] is b_k of system k, resident on the GPU.  precond
-    replaces the workload's preconditioner."""
+    replaces the workload's preconditioner; csr hands the matrix over in CSR."""
     import torch
     from paper_2001_01158_amd import lcs
     dev = "cuda:0"
@@ -232,8 +249,15 @@ def setup_sequence(workload: str, precond: str | None = None):
         okw = dict(okw, precond=precond)
         desc = f"{desc}; preconditioner {precond}"
     log(f"workload {w.name} N={w.n} systems={w.n_systems} precond={okw['precond']}")
-    A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
-                              with32=okw["precision"] == "mixed")
+    if csr:
+        from paper_2001_01158_amd import workloads as W
+        if w.kind == W.KIND_9N:
+            raise SystemExit("--csr takes the symmetric workloads")
+        A = csr_input(w.kind, w.nx, w.ny, w.nz, w.coef, dev)
+        desc = f"{desc}; matrix handed over in CSR (general sparse input)"
+    else:
+        A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
+                                  with32=okw["precision"] == "mixed")
     ctx = lcs.Context()
     opts = lcs.Options(eps=1e-10, n_smooth=1, check_every=8, **okw)
     X = [torch.zeros(w.n, dtype=torch.float64, device=dev)]
@@ -703,7 +727,7 @@ def main():
     from paper_2001_01158_amd import lcs, workloads as W
 
     dev = "cuda:0"
-    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload, args.precond)
+    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload, args.precond, args.csr)
     n = w.n
     stream = torch.cuda.current_stream()
     eps = opts.eps
@@ -828,6 +852,25 @@ def main():
         spmv["c3_9pt_fp32_4096x4096_hbm"] = hbm
         log(f"SpMV 9pt FP32 4096^2: {ms9 * 1e3:.1f} us, {hbm['GBs']:.0f} GB/s")
         del A9, x9, y9
+    if args.csr and not args.skip_spmv_hbm:
+        # general sparse input: 4096^2 five-point FP64 in CSR, run on its ELL
+        # copy (width 5); CSR's own bytes per row: 5 x (4 + 8) + 4 (row
+        # pointer) + 8 (x) + 8 (y)
+        n3 = 4096
+        c5 = W.assemble_5pt(W.lognormal_logk((n3, n3), 1.0, 7), 0.25)
+        A5 = csr_input(W.KIND_5PT, n3, n3, 1, c5, dev)
+        del c5
+        x5 = torch.rand(n3 * n3, dtype=torch.float64, device=dev)
+        y5 = torch.empty_like(x5)
+        ms5 = time_spmv(A5, x5, y5)
+        b5 = n3 * n3 * 80
+        spmv["csr_5pt_fp64_4096x4096"] = {
+            "n": n3 * n3, "us": ms5 * 1e3, "GBs": b5 / ms5 / 1e6, "bytes_per_row": 80,
+            "frac_of_8TBs": b5 / ms5 / 1e6 / HBM_PEAK_GBS,
+            "kernel": "k_spmv<UEll<double,5>> (row per lane on the ELL copy)",
+            "note": "one call: includes the structure check, the ELL copy and one synchronisation"}
+        log(f"SpMV CSR 5pt FP64 4096^2: {ms5 * 1e3:.1f} us per product")
+        del A5, x5, y5
 
     if args.calib_copy:
         src_t = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev)   # 512 MiB

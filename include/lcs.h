@@ -39,7 +39,7 @@
  *     entries.  Each call checks this structure before any kernel reads
  *     through col (LCS_EINVAL naming what failed; symmetry is the caller's
  *     to ensure, as for the stencils) and copies A into column-major ELL
- *     of width 8 or 16 in the context's workspace, on which the whole path
+ *     of width 5, 7, 9 or 16 in the context's workspace, on which the whole path
  *     runs.  Scores, thresholds, expansion, compaction and the gather of B
  *     follow the stencil kinds' definitions over the stored entries.  The
  *     Gauss-Seidel sweeps and the RB-SGS preconditioner need a colouring:

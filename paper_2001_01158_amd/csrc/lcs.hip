@@ -343,14 +343,20 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
     const Tuning t{c->march_rows, c->nontemporal};
     if (A->kind == LCS_CSR) {   // the ELL copy made by prepare_matrix
         const auto &E = c->ell;
-        const float *v32 = coef32, *d32 = coef32 ? coef32 + (int64_t)E.width * E.n : nullptr;
-        if (E.width == 8)
-            return f(EllRows<double, 8>{E.col, E.val, E.val + 8 * E.n, E.clr, E.n},
-                     UEll<double, 8>{E.col, E.val, E.val + 8 * E.n, E.clr, E.n},
-                     UEll<float, 8>{E.col, v32, d32, E.clr, E.n}, Width<8>());
-        return f(EllRows<double, 16>{E.col, E.val, E.val + 16 * E.n, E.clr, E.n},
-                 UEll<double, 16>{E.col, E.val, E.val + 16 * E.n, E.clr, E.n},
-                 UEll<float, 16>{E.col, v32, d32, E.clr, E.n}, Width<16>());
+        const float *d32 = coef32 ? coef32 + (int64_t)E.width * E.n : nullptr;
+        auto go = [&](auto wtag) -> lcs_status {
+            constexpr int W = decltype(wtag)::value;
+            const double *dg = E.val + (int64_t)W * E.n;
+            return f(EllRows<double, W>{E.col, E.val, dg, E.clr, E.n},
+                     UEll<double, W>{E.col, E.val, dg, E.clr, E.n},
+                     UEll<float, W>{E.col, coef32, d32, E.clr, E.n}, wtag);
+        };
+        switch (E.width) {
+        case 5: return go(Width<5>());
+        case 7: return go(Width<7>());
+        case 9: return go(Width<9>());
+        default: return go(Width<16>());
+        }
     }
     switch (A->kind) {
     case LCS_STENCIL5_2D: {
@@ -414,16 +420,22 @@ lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
         if (h[0] & kCsrColour) m += " colouring invalid (colour >= n_colours or two coupled rows share one);";
         return fail(LCS_EINVAL, m);
     }
-    const int W = h[1] <= 8 ? 8 : 16;
+    // the widths of the stencil kinds, whose ELL operators the local
+    // systems already use, then 16
+    const int W = h[1] <= 5 ? 5 : h[1] <= 7 ? 7 : h[1] <= 9 ? 9 : 16;
     LCS_TRY(get_buf(c, B_ACOL, (size_t)W * n, &c->ell.col));
     LCS_TRY(get_buf(c, B_AVAL, (size_t)(W + 1) * n, &c->ell.val));
     LCS_TRY(get_buf(c, B_ACLR, (size_t)n, &c->ell.clr));
-    if (W == 8)
-        hipLaunchKernelGGL(k_csr_to_ell<8>, dim3(flat_grid(n)), dim3(kBlock), 0, s, A->row_ptr,
-                           A->col, A->val, n, A->colour, c->ell.col, c->ell.val, c->ell.clr);
-    else
-        hipLaunchKernelGGL(k_csr_to_ell<16>, dim3(flat_grid(n)), dim3(kBlock), 0, s, A->row_ptr,
-                           A->col, A->val, n, A->colour, c->ell.col, c->ell.val, c->ell.clr);
+    auto conv = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(flat_grid(n)), dim3(kBlock), 0, s, A->row_ptr, A->col,
+                           A->val, n, A->colour, c->ell.col, c->ell.val, c->ell.clr);
+    };
+    switch (W) {
+    case 5: conv(k_csr_to_ell<5>); break;
+    case 7: conv(k_csr_to_ell<7>); break;
+    case 9: conv(k_csr_to_ell<9>); break;
+    default: conv(k_csr_to_ell<16>); break;
+    }
     LAUNCH_CHECK();
     c->ell.width = W;
     c->ell.n = n;

@@ -1,7 +1,7 @@
 // General sparse input.  A matrix given in CSR (ascending columns within a
 // row, diagonal stored) is checked and copied, once per library call, into
 // the column-major ELL layout of the restricted systems, with the width
-// rounded up to 8 or 16.  Every step of the path (scores and marking of
+// rounded up to 5, 7, 9 or 16.  Every step of the path (scores and marking of
 // Algorithms 2 and 3, the gather of B = A[Omega, Omega] of eq. BEFC, PCG,
 // Gauss-Seidel sweeps) then runs on the same row-per-lane ELL operator as
 // the restricted systems: slot s of consecutive rows is contiguous, so the

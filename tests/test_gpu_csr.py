@@ -1,5 +1,5 @@
 """GPU parity on general sparse input (LCS_CSR): irregular graphs with rows
-of up to 11 entries (ELL width 16) and of 5 entries (width 8), a nine-point
+of up to 11 entries (ELL width 16) and of 5 entries (width 5), a nine-point
 stencil given as CSR, and degenerate sizes.  Per-row kernels, local domains
 and the restricted system bit for bit against the oracle; global PCG and
 Algorithm 1 converged and at equal iteration counts; malformed structures
@@ -52,6 +52,11 @@ def make_case(name):
         Ah, (nx, ny) = irregular(61, 47, 11)
     elif name == "irr8":
         Ah, (nx, ny) = irregular(53, 41, 12, p_diag=0.0, p_long=0.0)
+    elif name == "grid7":   # 3-D seven-point stencil (red-black), planes stacked in y
+        nx, ny, nz = 19, 17, 9
+        coef = W.assemble_7pt(W.lognormal_logk((nz, ny, nx), 1.0, 13), 0.25)
+        Ah = oracle.csr_from_stencil(W.KIND_7PT, nx, ny, nz, coef)
+        ny *= nz
     else:   # nine-point stencil as CSR, with its four-colour grid colouring
         nx, ny = 45, 37
         coef = W.assemble_9pt(nx, ny, 0.25, 100.0, 30.0)
@@ -65,7 +70,7 @@ def make_case(name):
     return Ah, gpu_matrix(Ah), b, x0
 
 
-CASES = ["irr16", "irr8", "grid9"]
+CASES = ["irr16", "irr8", "grid9", "grid7"]   # ELL widths 16, 5, 9, 7
 
 
 @pytest.fixture(scope="module")
@@ -124,7 +129,8 @@ def test_csr_local_domain_and_gather_bitexact(name, mode, theta, e_max, ctx):
 
 
 @pytest.mark.parametrize("name,pc", [("irr16", "jacobi"), ("irr16", "rbsgs"), ("irr16", "none"),
-                                     ("irr8", "jacobi"), ("irr8", "rbsgs"), ("grid9", "rbsgs")])
+                                     ("irr8", "jacobi"), ("irr8", "rbsgs"), ("grid9", "rbsgs"),
+                                     ("grid7", "jacobi"), ("grid7", "rbsgs")])
 def test_csr_global_pcg_parity(name, pc, ctx):
     Ah, A, b, x0 = make_case(name)
     say("csr global pcg", name, pc)
@@ -184,7 +190,7 @@ def test_csr_local_then_global_parity(name, coloured, mode, thresh, theta, ctx):
     assert err_g <= max(10 * err_o, 1e-10)
 
 
-@pytest.mark.parametrize("name,pc", [("irr16", "jacobi"), ("irr8", "rbsgs")])
+@pytest.mark.parametrize("name,pc", [("irr16", "jacobi"), ("irr8", "rbsgs"), ("grid7", "rbsgs")])
 def test_csr_solve_local_trajectory(name, pc, ctx):
     Ah, A, b, x0 = make_case(name)
     say("csr solve_local trajectory", name, pc)
@@ -198,7 +204,8 @@ def test_csr_solve_local_trajectory(name, pc, ctx):
     assert rel <= 1e-12, rel
 
 
-@pytest.mark.parametrize("name,pc", [("irr16", "jacobi"), ("irr8", "rbsgs"), ("grid9", "jacobi")])
+@pytest.mark.parametrize("name,pc", [("irr16", "jacobi"), ("irr8", "rbsgs"), ("grid9", "jacobi"),
+                                     ("grid7", "rbsgs")])
 def test_csr_mixed_precision(name, pc, ctx):
     Ah, A, b, x0 = make_case(name)
     say("csr mixed", name, pc)
