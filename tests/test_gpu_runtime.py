@@ -120,3 +120,43 @@ def test_batched_run_twice_bitwise():
                                             lcs.Options(eps=1e-10))
         out.append(host(x))
     assert np.array_equal(out[0], out[1])
+
+
+def test_context_reuse_with_csr_input():
+    """One context through CSR matrices of ELL widths 16 and 5 and a stencil
+    in between, then the first CSR matrix again: each result equals a fresh
+    context's bit for bit (the ELL copy is rebuilt for every call)."""
+    def csr_case(nx, ny, seed, **kw):
+        rp, col, val = W.irregular_spd(nx, ny, seed, **kw)
+        colour, nc = W.greedy_colouring(rp, col)
+        Ah = oracle.CSR(nx * ny, rp, col, val, colour, nc)
+        A = lcs.CsrMatrix(dev(rp).to(torch.int32), dev(col).to(torch.int32), dev(val),
+                          dev(colour).to(torch.uint8), nc)
+        rng = np.random.default_rng(seed)
+        x_true = np.full(Ah.n, 0.1)
+        x_true[: Ah.n // 5] = 1.0
+        b = oracle.spmv(Ah, x_true)
+        return Ah, A, b, x_true * (1.0 + 0.2 * rng.random(Ah.n))
+
+    def run(A, b, x0, ctx):
+        x = dev(x0)
+        st = lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1,
+                                         lcs.Options(eps=1e-10, precond="rbsgs"), ctx=ctx)
+        return host(x), (st.K, st.its_local, st.its_global)
+
+    first = csr_case(47, 39, 1)
+    seq = [first, csr_case(31, 23, 2, p_diag=0.0, p_long=0.0), "stencil", first]
+    shared = lcs.Context()
+    for k, item in enumerate(seq):
+        say("context reuse with csr", k)
+        if item == "stencil":
+            coef, Ah, b, x0 = case(W.KIND_5PT, (64, 40, 1), seed=k)
+            xs, _ = solve(W.KIND_5PT, (64, 40, 1), coef, b, x0, shared)
+            xf, _ = solve(W.KIND_5PT, (64, 40, 1), coef, b, x0, lcs.Context())
+            assert np.array_equal(xs, xf)
+            continue
+        Ah, A, b, x0 = item
+        xs, ss = run(A, b, x0, shared)
+        xf, sf = run(A, b, x0, lcs.Context())
+        assert np.array_equal(xs, xf) and ss == sf
+        assert np.linalg.norm(oracle.residual(Ah, b, xs)) <= 1.0001e-10 * np.linalg.norm(b)
