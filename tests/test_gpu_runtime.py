@@ -1,6 +1,7 @@
 """Runtime behaviour of the library on the GPU: work follows the caller's
-stream, one context serves systems of different kinds and sizes (its
-workspace grows and is reused) with results bit-identical to fresh contexts,
+stream, one context serves systems of different kinds and sizes, CSR input
+included (its workspace grows and is reused), with results bit-identical to
+fresh contexts,
 and repeated GMRES and batched solves are bitwise deterministic."""
 import numpy as np
 import pytest
