@@ -65,9 +65,11 @@ def parse():
                    help="replace the workload's preconditioner (rbsgs: colour-ordered symmetric "
                         "Gauss-Seidel, four colours on the nine-point stencil)")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
-    p.add_argument("--csr", action="store_true",
+    p.add_argument("--csr", nargs="?", const="copy", choices=["copy", "reuse"],
                    help="hand the workload's matrix to the library in CSR (general sparse "
-                        "input) instead of as a stencil; symmetric workloads")
+                        "input) instead of as a stencil; symmetric workloads.  copy: every "
+                        "call checks and copies it; reuse: the context keeps the copy of the "
+                        "(constant) matrix")
     p.add_argument("--skip-spmv-hbm", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a plain 512 MiB device copy (traffic-counter calibration)")
@@ -236,7 +238,7 @@ def csr_input(kind: int, nx: int, ny: int, nz: int, coef, dev):
                          t(colour.ravel(), torch.uint8), 4 if kind == W.KIND_9PT else 2)
 
 
-def setup_sequence(workload: str, precond: str | None = None, csr: bool = False):
+def setup_sequence(workload: str, precond: str | None = None, csr: str | None = None):
     """Operator, context, options and the evolved sequence (untimed): X[k] is
     x_(k-1) and Bs[k] is b_k of system k, resident on the GPU.  precond
     replaces the workload's preconditioner; csr hands the matrix over in CSR."""
@@ -255,6 +257,8 @@ def setup_sequence(workload: str, precond: str | None = None, csr: bool = False)
             raise SystemExit("--csr takes the symmetric workloads")
         A = csr_input(w.kind, w.nx, w.ny, w.nz, w.coef, dev)
         desc = f"{desc}; matrix handed over in CSR (general sparse input)"
+        if csr == "reuse":   # constant matrix: the context keeps its checked ELL copy
+            desc = f"{desc}, checked and copied once"
     else:
         A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
                                   with32=okw["precision"] == "mixed")
@@ -270,6 +274,8 @@ def setup_sequence(workload: str, precond: str | None = None, csr: bool = False)
         Bs.append(b)
         X.append(x)
     torch.cuda.synchronize()
+    if csr == "reuse":
+        A.reuse = True
     log("sequence ready")
     return w, okw, desc, A, ctx, opts, X, Bs
 

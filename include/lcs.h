@@ -108,6 +108,12 @@ typedef struct lcs_matrix {
     int64_t nnz;
     const uint8_t *colour;    /* device, N, or NULL                                */
     int32_t n_colours;        /* 1..255 with a colouring                           */
+    int32_t csr_reuse;        /* 1: the caller states that these arrays, at these
+                                 addresses, are unchanged since the previous call
+                                 on this context that checked and copied them;
+                                 the context then reuses its ELL copy (pointers,
+                                 N, nnz and n_colours must match, else the call
+                                 checks and copies as with 0)                    */
 } lcs_matrix;
 
 typedef struct lcs_options {

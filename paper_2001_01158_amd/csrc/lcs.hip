@@ -169,6 +169,11 @@ struct lcs_ctx {
         int32_t *col = nullptr;
         double *val = nullptr;   // width x n values, then the diagonal
         uint8_t *clr = nullptr;
+        // the matrix the copy was made from (valid after a successful check)
+        bool valid = false;
+        const void *rp = nullptr, *col_in = nullptr, *val_in = nullptr, *clr_in = nullptr;
+        int64_t nnz = 0;
+        int32_t ncol = 0;
     } ell;
 };
 
@@ -399,6 +404,11 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
 lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
     if (A->kind != LCS_CSR) return LCS_OK;
     const int64_t n = A->nx;
+    auto &E = c->ell;
+    if (A->csr_reuse && E.valid && E.n == n && E.rp == A->row_ptr && E.col_in == A->col &&
+        E.val_in == A->val && E.clr_in == A->colour && E.nnz == A->nnz && E.ncol == A->n_colours)
+        return LCS_OK;
+    E.valid = false;
     int32_t *flags;
     LCS_TRY(get_buf(c, B_AFLAGS, 2, &flags));
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, s, flags, 0, (int64_t)2);
@@ -437,8 +447,15 @@ lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
     default: conv(k_csr_to_ell<16>); break;
     }
     LAUNCH_CHECK();
-    c->ell.width = W;
-    c->ell.n = n;
+    E.width = W;
+    E.n = n;
+    E.rp = A->row_ptr;
+    E.col_in = A->col;
+    E.val_in = A->val;
+    E.clr_in = A->colour;
+    E.nnz = A->nnz;
+    E.ncol = A->n_colours;
+    E.valid = true;
     return LCS_OK;
 }
 

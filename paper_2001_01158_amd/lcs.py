@@ -50,7 +50,8 @@ class _Matrix(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("coef", ctypes.c_void_p), ("coef32", ctypes.c_void_p),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
-                ("nnz", ctypes.c_int64), ("colour", ctypes.c_void_p), ("n_colours", ctypes.c_int32)]
+                ("nnz", ctypes.c_int64), ("colour", ctypes.c_void_p), ("n_colours", ctypes.c_int32),
+                ("csr_reuse", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -185,6 +186,7 @@ class CsrMatrix:
     val: torch.Tensor                      # float64 [nnz], device
     colour: Optional[torch.Tensor] = None  # uint8 [N], device
     n_colours: int = 0
+    reuse: bool = False   # arrays unchanged since the context last copied them
     kind = CSR
     max_row = 16
 
@@ -211,6 +213,7 @@ class CsrMatrix:
         m.row_ptr, m.col, m.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
         m.nnz = self.col.numel()
         m.colour, m.n_colours = _ptr(self.colour), int(self.n_colours)
+        m.csr_reuse = 1 if self.reuse else 0
         return m
 
 

@@ -331,3 +331,35 @@ def test_csr_option_errors_and_context_reuse(ctx):
     lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1, lcs.Options(eps=1e-10),
                                 ctx=ctx)
     assert np.linalg.norm(oracle.residual(Ah, b, host(x))) <= 1.0001e-10 * np.linalg.norm(b)
+
+
+def test_csr_reuse_of_the_checked_copy(ctx):
+    """reuse = True on the matrix the context copied last gives the copying
+    call's result bit for bit; on another matrix (other addresses) the call
+    checks and copies it, so it is solved correctly; a malformed matrix is
+    still rejected."""
+    Ah, A, b, x0 = make_case("irr16")
+    Bh, B, bb, y0 = make_case("grid7")
+    say("csr reuse")
+
+    def run(M, rhs, z0):
+        x = dev(z0)
+        st = lcs.solve_local_then_global(M, dev(rhs), x, "residual", "relmax", 1e-3, 1,
+                                         lcs.Options(eps=1e-10, precond="rbsgs"), ctx=ctx)
+        return host(x), (st.K, st.its_local, st.its_global)
+
+    ref, sref = run(A, b, x0)
+    A.reuse = True
+    for _ in range(2):
+        got, sgot = run(A, b, x0)
+        assert np.array_equal(got, ref) and sgot == sref
+    B.reuse = True                      # not the context's copy: checked and copied
+    yb, _ = run(B, bb, y0)
+    assert np.linalg.norm(oracle.residual(Bh, bb, yb)) <= 1.0001e-10 * np.linalg.norm(bb)
+    got, sgot = run(A, b, x0)           # A again: B's copy replaced it, so A is copied again
+    assert np.array_equal(got, ref) and sgot == sref
+    bad = _bad("unsorted")
+    bad.reuse = True
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.solve_global(bad, dev(np.ones(bad.n)), dev(np.zeros(bad.n)), ctx=ctx)
+    assert e.value.status == lcs.EINVAL
