@@ -206,7 +206,8 @@ lcs_status lcs_gradient(lcs_ctx *ctx, const lcs_matrix *A, const double *x, doub
 lcs_status lcs_spmv(lcs_ctx *ctx, const lcs_matrix *A, const void *x, void *y,
                     int32_t precision, int32_t reps, void *stream);
 /* Restricted B = A[idx, idx] in CSR (eq. BEFC): row_ptr int32[K+1],
- * col int32[nnz], val double[nnz] (device, capacity 9K).  *nnz (host). */
+ * col int32[nnz], val double[nnz] (device, capacity 9K; 16K for LCS_CSR).
+ * *nnz (host). */
 lcs_status lcs_gather_restricted(lcs_ctx *ctx, const lcs_matrix *A, const int32_t *idx,
                                  int64_t K, int32_t *row_ptr, int32_t *col, double *val,
                                  int64_t *nnz, void *stream);
