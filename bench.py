@@ -216,6 +216,19 @@ def summarize(d: str, steps: int):
             alg = 4096 * 4096 * 28
             out.append(f"`{short(spm)}` (4096^2, FP32): {len(sf)} dispatches, {t / 1e6:.1f} MB per dispatch "
                        f"(calibrated) vs {alg / 1e6:.1f} MB algorithmic -> ratio {t / alg:.3f}")
+        # the 4096^2 five-point product of CSR input (bench.py --csr): the
+        # larger of the two sizes k_spmv<UEll<double, 5>> runs on
+        spe = "void lcs::k_spmv<lcs::UEll<double, 5> >"
+        ef = [float(r["Counter_Value"]) for r in fetch if r["Kernel_Name"].startswith(spe)]
+        ew = [float(r["Counter_Value"]) for r in write if r["Kernel_Name"].startswith(spe)]
+        if ef and ew:
+            big_f = [v for v in ef if v > max(ef) / 2]
+            big_w = [v for v in ew if v > max(ew) / 2]
+            t = (sum(big_f) / len(big_f) * f_fetch + sum(big_w) / len(big_w) * f_write) * 1024
+            alg = 4096 * 4096 * 76
+            out.append(f"`{short(spe)}` (4096^2 CSR input, FP64): {len(big_f)} / {len(big_w)} dispatches, "
+                       f"{t / 1e6:.1f} MB per dispatch (calibrated) vs {alg / 1e6:.1f} MB algorithmic "
+                       f"(76 B per row) -> ratio {t / alg:.3f}")
         bj = os.path.join(d, "fetch_bench.json")
         if os.path.exists(bj):
             bpl = json.load(open(bj))["roofline"]["bytes_per_launch"]
