@@ -217,8 +217,8 @@ def summarize(d: str, steps: int):
             out.append(f"`{short(spm)}` (4096^2, FP32): {len(sf)} dispatches, {t / 1e6:.1f} MB per dispatch "
                        f"(calibrated) vs {alg / 1e6:.1f} MB algorithmic -> ratio {t / alg:.3f}")
         # the 4096^2 five-point product of CSR input (bench.py --csr): the
-        # larger of the two sizes k_spmv<UEll<double, 5>> runs on
-        spe = "void lcs::k_spmv<lcs::UEll<double, 5> >"
+        # streaming ELL operator (the larger of the sizes the ELL SpMV runs on)
+        spe = "void lcs::k_spmv<lcs::UEllStream<double, 5> >"
         ef = [float(r["Counter_Value"]) for r in fetch if r["Kernel_Name"].startswith(spe)]
         ew = [float(r["Counter_Value"]) for r in write if r["Kernel_Name"].startswith(spe)]
         if ef and ew:

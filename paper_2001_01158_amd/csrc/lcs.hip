@@ -349,11 +349,17 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
     if (A->kind == LCS_CSR) {   // the ELL copy made by prepare_matrix
         const auto &E = c->ell;
         const float *d32 = coef32 ? coef32 + (int64_t)E.width * E.n : nullptr;
+        // stream the copy once an FP64 pass (indices, values and about six
+        // vectors) exceeds the 256 MB last-level cache
+        const bool stream = (double)E.n * (E.width * 12.0 + 48.0) > 256.0 * 1024 * 1024;
         auto go = [&](auto wtag) -> lcs_status {
             constexpr int W = decltype(wtag)::value;
             const double *dg = E.val + (int64_t)W * E.n;
-            return f(EllRows<double, W>{E.col, E.val, dg, E.clr, E.n},
-                     UEll<double, W>{E.col, E.val, dg, E.clr, E.n},
+            const EllRows<double, W> rows{E.col, E.val, dg, E.clr, E.n};
+            if (stream)
+                return f(rows, UEllStream<double, W>{{E.col, E.val, dg, E.clr, E.n}},
+                         UEllStream<float, W>{{E.col, coef32, d32, E.clr, E.n}}, wtag);
+            return f(rows, UEll<double, W>{E.col, E.val, dg, E.clr, E.n},
                      UEll<float, W>{E.col, coef32, d32, E.clr, E.n}, wtag);
         };
         switch (E.width) {

@@ -120,6 +120,28 @@ __global__ __launch_bounds__(kBlock) void k_csr_to_ell(const int32_t *__restrict
     }
 }
 
+// The ELL copy as a unit operator that streams: column indices and values
+// are read, and results written, with non-temporal loads and stores.  For
+// matrices whose pass exceeds the last-level cache, as the stencil kernels
+// do in that case; the gathers of x keep ordinary loads.
+template <typename real_, int NB_>
+struct UEllStream : UEll<real_, NB_> {
+    using Base = UEll<real_, NB_>;
+    using Unit = typename Base::Unit;
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        U.i0 = u;
+#pragma unroll
+        for (int s = 0; s < NB_; ++s) {
+            U.c[s] = __builtin_nontemporal_load(this->col + s * this->n + u);
+            U.a[s][0] = __builtin_nontemporal_load(this->val + s * this->n + u);
+        }
+    }
+    template <typename T>
+    __device__ __forceinline__ void put(const Unit &U, T *__restrict__ p, const T (&o)[1]) const {
+        __builtin_nontemporal_store(o[0], p + U.i0);
+    }
+};
+
 // Row operator over the ELL copy (the marking rounds and the gather of B):
 // the members of row i in ascending column order.
 template <typename real, int W>

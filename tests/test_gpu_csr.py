@@ -363,3 +363,30 @@ def test_csr_reuse_of_the_checked_copy(ctx):
     with pytest.raises(lcs.LcsError) as e:
         lcs.solve_global(bad, dev(np.ones(bad.n)), dev(np.zeros(bad.n)), ctx=ctx)
     assert e.value.status == lcs.EINVAL
+
+
+def test_csr_streaming_operator_large(ctx):
+    """A five-point matrix of 1600 x 1600 given in CSR: its FP64 pass exceeds
+    the last-level cache, so the ELL copy is read with non-temporal loads.
+    Per-row kernels bit-exact; Algorithm 1 meets the criterion."""
+    nx = ny = 1600
+    coef = W.assemble_5pt(W.lognormal_logk((ny, nx), 1.0, 21), 0.25)
+    Ah = oracle.csr_from_stencil(W.KIND_5PT, nx, ny, 1, coef)
+    A = gpu_matrix(Ah)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    x_true = (0.2 + 0.1 * np.sin(xx / 70.0) * np.cos(yy / 50.0)).ravel()
+    b = oracle.spmv(Ah, x_true)
+    x0 = x_true.copy()
+    x0[((xx - 500) ** 2 + (yy - 800) ** 2 < 40 ** 2).ravel()] += 0.5
+    say("csr streaming", A.n)
+    assert np.array_equal(host(lcs.residual(A, dev(b), dev(x0), ctx=ctx)), oracle.residual(Ah, b, x0))
+    assert np.array_equal(host(lcs.gradient(A, dev(x0), ctx=ctx)), oracle.gradient(Ah, x0))
+    y = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    lcs.spmv(A, dev(x0), y, ctx=ctx)
+    assert np.array_equal(host(y), oracle.spmv(Ah, x0))
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1)
+    x = dev(x0)
+    st = lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1,
+                                     lcs.Options(eps=1e-10), ctx=ctx)
+    assert st.K == d.K
+    assert np.linalg.norm(oracle.residual(Ah, b, host(x))) <= 1.0001e-10 * np.linalg.norm(b)
