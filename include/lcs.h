@@ -32,8 +32,9 @@
  *     right-preconditioned by Jacobi or nothing, in FP64; the criterion and
  *     Algorithm 1 are unchanged.  Batched solves and the adjoint take the
  *     symmetric kinds only.
- *   - LCS_CSR is a general symmetric sparse matrix (the paper's setting
- *     before any grid is assumed, Section 2.1) in CSR: nx = N, ny = nz = 1,
+ *   - LCS_CSR is a general sparse matrix (the paper's setting before any
+ *     grid is assumed, Section 2.1) in CSR, symmetric unless csr_nonsym is
+ *     set (then solved by GMRES(m) as LCS_STENCIL9N_2D is): nx = N, ny = nz = 1,
  *     row_ptr int32[N+1], col int32[nnz] strictly ascending within each row
  *     with the diagonal stored, val double[nnz]; every row holds 1..16
  *     entries.  Each call checks this structure before any kernel reads
@@ -114,6 +115,10 @@ typedef struct lcs_matrix {
                                  the context then reuses its ELL copy (pointers,
                                  N, nnz and n_colours must match, else the call
                                  checks and copies as with 0)                    */
+    int32_t csr_nonsym;       /* 1: A is not symmetric; every solve (global,
+                                 local, global finish) uses GMRES(m) in FP64
+                                 with Jacobi or no preconditioner, as for
+                                 LCS_STENCIL9N_2D                                */
 } lcs_matrix;
 
 typedef struct lcs_options {

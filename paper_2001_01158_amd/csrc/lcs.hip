@@ -54,6 +54,10 @@ int n_arrays(int kind) {
     return kind == LCS_STENCIL5_2D ? 3 : kind == LCS_STENCIL9_2D ? 5 : kind == LCS_STENCIL9N_2D ? 9 : 4;
 }
 int n_colours(int kind) { return kind == LCS_STENCIL9_2D || kind == LCS_STENCIL9N_2D ? 4 : 2; }
+// solves by GMRES(m): the non-symmetric stencil and non-symmetric CSR input
+bool uses_gmres(const lcs_matrix *A) {
+    return A->kind == LCS_STENCIL9N_2D || (A->kind == LCS_CSR && A->csr_nonsym);
+}
 // colours of the Gauss-Seidel sweeps; 0 for a general sparse matrix given
 // without a colouring (no sweeps)
 int colours_of(const lcs_matrix *A) {
@@ -251,7 +255,8 @@ lcs_status check_options(const lcs_options *o, int kind) {
 }
 
 lcs_status check_options_for(const lcs_options *o, const lcs_matrix *A) {
-    LCS_TRY(check_options(o, A->kind));
+    // non-symmetric CSR input follows the non-symmetric stencil's rules
+    LCS_TRY(check_options(o, uses_gmres(A) ? (int)LCS_STENCIL9N_2D : A->kind));
     if (A->kind == LCS_CSR && o->precond == LCS_PC_RBSGS && !A->colour)
         return fail(LCS_EINVAL, "symmetric Gauss-Seidel on a CSR matrix needs its colouring");
     return LCS_OK;
@@ -1116,7 +1121,7 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         SolveOut so;
         const lcs_status ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
                                            &c->dsc->bnorm, tl, o, s, &so, 1,
-                                           M->kind == LCS_STENCIL9N_2D);
+                                           uses_gmres(M));
         // a local solve that stops at its iteration cap still improves x;
         // the global finish takes over from there
         if (ls != LCS_OK && ls != LCS_ENOCONV) return ls;
@@ -1580,7 +1585,7 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
         LCS_TRY(tm.mark(3));
         SolveOut so;
         const lcs_status rs = solve_system(c, op, op32, colours_of(A), b, x, false,
-                                           &c->dsc->bnorm, o->eps, o, s, &so, 0);
+                                           &c->dsc->bnorm, o->eps, o, s, &so, 0, uses_gmres(A));
         LCS_TRY(tm.mark(4));
         HIP_TRY(hipStreamSynchronize(s));
         LCS_TRY(flush_prof(c));
@@ -1701,7 +1706,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         } else {
             SolveOut so;
             rs = solve_system(c, op, op32, colours_of(A), b, x, false, &c->dsc->bnorm, o->eps,
-                              o, s, &so, 0);
+                              o, s, &so, 0, uses_gmres(A));
             st->its_global = so.its;
             st->n_outer += so.n_outer;
             st->relres_final = bn > 0 ? std::sqrt(so.rr) / bn : std::sqrt(so.rr);

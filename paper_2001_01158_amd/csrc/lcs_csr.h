@@ -142,6 +142,9 @@ struct UEllStream : UEll<real_, NB_> {
     }
 };
 
+template <typename real, int NB>
+constexpr bool is_ell<UEllStream<real, NB>> = true;
+
 // Row operator over the ELL copy (the marking rounds and the gather of B):
 // the members of row i in ascending column order.
 template <typename real, int W>

@@ -51,7 +51,7 @@ class _Matrix(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("coef", ctypes.c_void_p), ("coef32", ctypes.c_void_p),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("nnz", ctypes.c_int64), ("colour", ctypes.c_void_p), ("n_colours", ctypes.c_int32),
-                ("csr_reuse", ctypes.c_int32)]
+                ("csr_reuse", ctypes.c_int32), ("csr_nonsym", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -187,6 +187,7 @@ class CsrMatrix:
     colour: Optional[torch.Tensor] = None  # uint8 [N], device
     n_colours: int = 0
     reuse: bool = False   # arrays unchanged since the context last copied them
+    nonsym: bool = False  # not symmetric: solves use GMRES(m)
     kind = CSR
     max_row = 16
 
@@ -214,6 +215,7 @@ class CsrMatrix:
         m.nnz = self.col.numel()
         m.colour, m.n_colours = _ptr(self.colour), int(self.n_colours)
         m.csr_reuse = 1 if self.reuse else 0
+        m.csr_nonsym = 1 if self.nonsym else 0
         return m
 
 

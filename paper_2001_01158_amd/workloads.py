@@ -606,3 +606,30 @@ def greedy_colouring(rp: np.ndarray, col: np.ndarray):
             c += 1
         colour[i] = c
     return colour.astype(np.int8), int(colour.max()) + 1 if n else 0
+
+
+def irregular_nonsym(nx: int, ny: int, seed: int, skew: float = 0.6, mass: float = 0.25, **kw):
+    """Non-symmetric variant of irregular_spd (a convection-like skew): each
+    coupling pair i < j gets a_ij = -w (1 + s), a_ji = -w (1 - s) with s
+    uniform in [-skew, skew]; the diagonal is the row's absolute off-diagonal
+    sum plus mass, so every row is strictly diagonally dominant.  Same
+    pattern as irregular_spd(nx, ny, seed, **kw)."""
+    rp, col, val = irregular_spd(nx, ny, seed, mass=mass, **kw)
+    rng = np.random.default_rng(seed + 1000)
+    n = rp.size - 1
+    pos = {}
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            pos[(i, int(col[k]))] = k
+    val = val.copy()
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            j = int(col[k])
+            if j > i:
+                s = rng.uniform(-skew, skew)
+                val[k] *= 1.0 + s
+                val[pos[(j, i)]] *= 1.0 - s
+    for i in range(n):
+        off = [k for k in range(rp[i], rp[i + 1]) if col[k] != i]
+        val[pos[(i, i)]] = sum(abs(val[k]) for k in off) + mass
+    return rp, col, val

@@ -390,3 +390,85 @@ def test_csr_streaming_operator_large(ctx):
                                      lcs.Options(eps=1e-10), ctx=ctx)
     assert st.K == d.K
     assert np.linalg.norm(oracle.residual(Ah, b, host(x))) <= 1.0001e-10 * np.linalg.norm(b)
+
+
+# ---- non-symmetric CSR input: GMRES(m) ----
+def nonsym_case(nx=57, ny=43, seed=31, coloured=True):
+    rp, col, val = W.irregular_nonsym(nx, ny, seed)
+    colour, nc = W.greedy_colouring(rp, col)
+    Ah = oracle.CSR(nx * ny, rp, col, val, colour if coloured else None, nc if coloured else 0)
+    A = gpu_matrix(Ah, coloured)
+    A.nonsym = True
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    x_true = (0.2 + 0.1 * np.sin(xx / 7.0) * np.cos(yy / 5.0)).ravel()
+    b = oracle.spmv(Ah, x_true)
+    x0 = x_true.copy()
+    x0[((xx - nx / 3) ** 2 + (yy - ny / 2) ** 2 < (min(nx, ny) / 6) ** 2).ravel()] += 0.5
+    return Ah, A, b, x0
+
+
+def gm(**kw):
+    return oracle.Options(krylov=oracle.KRYLOV_GMRES, **kw)
+
+
+@pytest.mark.parametrize("coloured", [True, False])
+@pytest.mark.parametrize("mode,thresh,theta", [("residual", "relmax", 1e-3),
+                                               ("residual", "paper", 1e-10),
+                                               ("gradient", "relmax", 1e-3)])
+def test_csr_nonsym_local_then_global_gmres(coloured, mode, thresh, theta, ctx):
+    Ah, A, b, x0 = nonsym_case(coloured=coloured)
+    say("csr nonsym local_then_global", coloured, mode, thresh)
+    om = {"residual": oracle.MODE_RESIDUAL, "gradient": oracle.MODE_GRADIENT}[mode]
+    ot = {"relmax": oracle.TH_RELMAX, "paper": oracle.TH_PAPER}[thresh]
+    xo, so, _ = oracle.local_then_global(Ah, b, x0, om, theta, ot, 1, gm(eps=1e-10))
+    x = dev(x0)
+    st = lcs.solve_local_then_global(A, dev(b), x, mode, thresh, theta, 1, lcs.Options(eps=1e-10),
+                                     ctx=ctx)
+    xg = host(x)
+    nb = np.linalg.norm(b)
+    assert abs(st.K - so.K) <= (2 if thresh == "paper" else 0)
+    assert abs(st.its_local - so.its_local) <= 2
+    assert np.linalg.norm(oracle.residual(Ah, b, xg)) <= 1.0001e-10 * nb
+    xd = np.linalg.solve(Ah.dense(), b)
+    err_g = np.linalg.norm(xg - xd) / np.linalg.norm(xd)
+    err_o = np.linalg.norm(xo - xd) / np.linalg.norm(xd)
+    say(f"  K={st.K} its {st.its_local}+{st.its_global} (oracle {so.its_local}+{so.its_global}) "
+        f"err {err_g:.1e} / {err_o:.1e}")
+    assert err_g <= max(10 * err_o, 1e-10)
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "none"])
+def test_csr_nonsym_gmres_trajectory(pc, ctx):
+    """GMRES(4) stopped after k steps (k = 11 crosses two restarts): global
+    solve against the oracle's GMRES; Algorithm 1 with k steps in the local
+    and the global solve against the oracle's Algorithm 1."""
+    Ah, A, b, x0 = nonsym_case()
+    opc = {"jacobi": oracle.PC_JACOBI, "none": oracle.PC_NONE}[pc]
+    for k in (3, 11):
+        say("csr nonsym trajectory", pc, k)
+        o = lcs.Options(eps=1e-30, precond=pc, max_iter=k, restart=4, max_outer=0)
+        x = dev(x0)
+        with pytest.raises(lcs.LcsError) as e:
+            lcs.solve_global(A, dev(b), x, o, ctx=ctx)
+        assert e.value.status == lcs.ENOCONV
+        xk, _, itk, _ = oracle.gmres(Ah, b, x0, opc, m=4, tol_abs=0.0, max_iter=k)
+        assert itk == k
+        assert np.linalg.norm(host(x) - xk) / np.linalg.norm(xk) <= 1e-10
+        x = dev(x0)
+        with pytest.raises(lcs.LcsError) as e:
+            lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1, o, ctx=ctx)
+        assert e.value.status == lcs.ENOCONV
+        xo, _, _ = oracle.local_then_global(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1,
+                                            gm(eps=1e-30, max_iter=k, gmres_m=4, pc=opc))
+        assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) <= 1e-10
+
+
+def test_csr_nonsym_option_errors(ctx):
+    Ah, A, b, x0 = nonsym_case()
+    say("csr nonsym option errors")
+    x = dev(x0)
+    for o in [lcs.Options(precision="mixed"), lcs.Options(precond="rbsgs"), lcs.Options(restart=0)]:
+        with pytest.raises(lcs.LcsError) as e:
+            lcs.solve_global(A, dev(b), x, o, ctx=ctx)
+        assert e.value.status == lcs.EINVAL
+    assert np.array_equal(host(x), x0)

@@ -730,3 +730,28 @@ def test_irregular_gs_sweep_and_solves():
                                          oracle.Options(eps=1e-12))
     assert 0 < so.K < A.n
     assert np.linalg.norm(xo - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_irregular_nonsym_input_and_gmres():
+    """The non-symmetric irregular generator keeps the pattern, is strictly
+    diagonally dominant and not symmetric; oracle GMRES and Algorithm 1 with
+    GMRES reach the dense solution."""
+    rp, col, val = W.irregular_nonsym(13, 11, 3)
+    rs, cs, _ = W.irregular_spd(13, 11, 3)
+    assert np.array_equal(rp, rs) and np.array_equal(col, cs)
+    A = oracle.CSR(13 * 11, rp, col, val, None, 0)
+    a = A.dense()
+    off = a - np.diag(np.diag(a))
+    assert np.abs(a - a.T).max() > 0.1
+    assert (np.diag(a) > np.abs(off).sum(axis=1)).all()
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(A.n)
+    xs = np.linalg.solve(a, b)
+    o = oracle.Options(eps=1e-12, krylov=oracle.KRYLOV_GMRES, gmres_m=20)
+    xo, so = oracle.solve_global(A, b, np.zeros(A.n), o)
+    assert np.linalg.norm(xo - xs) <= 1e-9 * np.linalg.norm(xs)
+    x0 = xs.copy()
+    x0[30:50] += 0.5
+    xo, so, _ = oracle.local_then_global(A, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1, o)
+    assert 0 < so.K < A.n
+    assert np.linalg.norm(xo - xs) <= 1e-9 * np.linalg.norm(xs)
