@@ -67,7 +67,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--csr", nargs="?", const="copy", choices=["copy", "reuse"],
                    help="hand the workload's matrix to the library in CSR (general sparse "
-                        "input) instead of as a stencil; symmetric workloads.  copy: every "
+                        "input) instead of as a stencil (c6: non-symmetric, GMRES).  copy: every "
                         "call checks and copies it; reuse: the context keeps the copy of the "
                         "(constant) matrix")
     p.add_argument("--skip-spmv-hbm", action="store_true")
@@ -242,13 +242,17 @@ def csr_input(kind: int, nx: int, ny: int, nz: int, coef, dev):
     and the grid's colouring (red-black; four colours for nine points)."""
     import torch
     from paper_2001_01158_amd import lcs, workloads as W
-    S = W._scipy_matrix(kind, nx, ny, nz, coef).tocsr()
+    if kind == W.KIND_9N:
+        S = W._scipy_matrix_9n(nx, ny, coef).tocsr()
+    else:
+        S = W._scipy_matrix(kind, nx, ny, nz, coef).tocsr()
     S.sort_indices()
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    colour = (x & 1) + 2 * (y & 1) if kind == W.KIND_9PT else (x + y + z) & 1
+    nine = kind in (W.KIND_9PT, W.KIND_9N)
+    colour = (x & 1) + 2 * (y & 1) if nine else (x + y + z) & 1
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).to(dev)
     return lcs.CsrMatrix(t(S.indptr, torch.int32), t(S.indices, torch.int32), t(S.data, torch.float64),
-                         t(colour.ravel(), torch.uint8), 4 if kind == W.KIND_9PT else 2)
+                         t(colour.ravel(), torch.uint8), 4 if nine else 2, nonsym=kind == W.KIND_9N)
 
 
 def setup_sequence(workload: str, precond: str | None = None, csr: str | None = None):
@@ -265,9 +269,6 @@ def setup_sequence(workload: str, precond: str | None = None, csr: str | None = 
         desc = f"{desc}; preconditioner {precond}"
     log(f"workload {w.name} N={w.n} systems={w.n_systems} precond={okw['precond']}")
     if csr:
-        from paper_2001_01158_amd import workloads as W
-        if w.kind == W.KIND_9N:
-            raise SystemExit("--csr takes the symmetric workloads")
         A = csr_input(w.kind, w.nx, w.ny, w.nz, w.coef, dev)
         desc = f"{desc}; matrix handed over in CSR (general sparse input)"
         if csr == "reuse":   # constant matrix: the context keeps its checked ELL copy
