@@ -237,11 +237,11 @@ def summarize(d: str, steps: int):
     print("\n".join(out))
 
 
-def csr_input(kind: int, nx: int, ny: int, nz: int, coef, dev):
-    """The stencil matrix as general sparse input: CSR with ascending columns
-    and the grid's colouring (red-black; four colours for nine points)."""
-    import torch
-    from paper_2001_01158_amd import lcs, workloads as W
+def csr_arrays(kind: int, nx: int, ny: int, nz: int, coef):
+    """The stencil matrix as general sparse input (host arrays): CSR with
+    ascending columns, and the grid's colouring (red-black; four colours for
+    nine points).  Returns (row_ptr, col, val, colour, n_colours)."""
+    from paper_2001_01158_amd import workloads as W
     if kind == W.KIND_9N:
         S = W._scipy_matrix_9n(nx, ny, coef).tocsr()
     else:
@@ -250,9 +250,18 @@ def csr_input(kind: int, nx: int, ny: int, nz: int, coef, dev):
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     nine = kind in (W.KIND_9PT, W.KIND_9N)
     colour = (x & 1) + 2 * (y & 1) if nine else (x + y + z) & 1
+    return S.indptr, S.indices, S.data, colour.ravel(), 4 if nine else 2
+
+
+def csr_input(kind: int, nx: int, ny: int, nz: int, coef, dev):
+    """csr_arrays on the device as an lcs.CsrMatrix (non-symmetric for the
+    full-storage nine-point kind)."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+    rp, col, val, colour, nc = csr_arrays(kind, nx, ny, nz, coef)
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).to(dev)
-    return lcs.CsrMatrix(t(S.indptr, torch.int32), t(S.indices, torch.int32), t(S.data, torch.float64),
-                         t(colour.ravel(), torch.uint8), 4 if nine else 2, nonsym=kind == W.KIND_9N)
+    return lcs.CsrMatrix(t(rp, torch.int32), t(col, torch.int32), t(val, torch.float64),
+                         t(colour, torch.uint8), nc, nonsym=kind == W.KIND_9N)
 
 
 def setup_sequence(workload: str, precond: str | None = None, csr: str | None = None):

@@ -1,11 +1,15 @@
 """bench.py's parts that need no GPU: more than one GPU is refused with a
 message (the implementation runs on one GPU), the rocprofv3 summarizer runs on
-the host, and the CSR built for the library SpMV yardstick is the oracle's CSR
-of the same nine-point stencil."""
+the host, the CSR built for the library SpMV yardstick is the oracle's CSR
+of the same nine-point stencil, and the CSR input of bench.py --csr is the
+oracle's CSR of each stencil kind."""
 import json
 import os
 import subprocess
 import sys
+
+import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -39,3 +43,27 @@ def test_csr_yardstick_matrix_is_the_oracles_csr():
         assert np.array_equal(crow.numpy(), A.rp)
         assert np.array_equal(col.numpy(), A.col)
         assert np.array_equal(val.numpy(), A.val)
+
+
+@pytest.mark.parametrize("kind,dims", [(0, (13, 9, 1)), (1, (11, 8, 1)), (2, (7, 6, 5)), (3, (10, 7, 1))])
+def test_bench_csr_input_is_the_oracles_csr(kind, dims):
+    """The CSR that bench.py --csr hands to the library equals the oracle's
+    CSR of the same stencil (pattern, order and values) and the oracle's
+    grid colouring."""
+    import bench
+    import oracle
+    from paper_2001_01158_amd import workloads as W
+    nx, ny, nz = dims
+    if kind == W.KIND_5PT:
+        coef = W.assemble_5pt(W.lognormal_logk((ny, nx), 1.0, 3), 0.25)
+    elif kind == W.KIND_9PT:
+        coef = W.assemble_9pt(nx, ny, 0.25, 100.0, 30.0)
+    elif kind == W.KIND_7PT:
+        coef = W.assemble_7pt(W.lognormal_logk((nz, ny, nx), 1.0, 3), 0.25)
+    else:
+        coef = W.assemble_9n(nx, ny, 0.25, speed=2.0)
+    rp, col, val, colour, nc = bench.csr_arrays(kind, nx, ny, nz, coef)
+    Ah = oracle.csr_from_stencil(kind, nx, ny, nz, coef)
+    assert np.array_equal(rp, Ah.rp) and np.array_equal(col, Ah.col)
+    assert np.array_equal(val, Ah.val)
+    assert np.array_equal(colour, Ah.colour) and nc == Ah.ncolours
