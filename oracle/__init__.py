@@ -25,6 +25,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+# ORACLE_SANITIZE=1: load a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer instead (host code; run under
+# LD_PRELOAD=libasan.so, as tests/test_oracle_sanitized.py does)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+if _SANITIZE:
+    _LIB = os.path.join(_HERE, "liboracle_san.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+              "-fno-omit-frame-pointer", "-g"]
 
 MODE_RESIDUAL, MODE_GRADIENT = 0, 1
 TH_RELMAX, TH_ABS, TH_PAPER = 0, 1, 2
@@ -33,17 +42,43 @@ KRYLOV_CG, KRYLOV_GMRES = 0, 1
 OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN = 0, 1, 3, 4, 5
 
 
+def _compile(out: str, extra: list):
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                           "-fPIC", "-shared"] + extra + ["-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, out)
+
+
+def _stale(lib_path: str) -> bool:
+    return not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(_SRC)
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c (no FP contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile oracle.c (no FP contraction, no fast-math): the serial checker
+    liboracle.so and the OpenMP build liboracle_omp.so of the same source
+    (row loops on all host cores, bit-identical results; timing only)."""
+    if force or _stale(_LIB):
+        _compile(_LIB, _SAN_FLAGS if _SANITIZE else [])
+    if force or _stale(_LIB_OMP):
+        _compile(_LIB_OMP, ["-fopenmp"])
     return _LIB
 
 
 _lib = None
+_lib_omp = None
+_parallel = False
+
+
+def set_parallel(on: bool) -> None:
+    """Route every oracle call to the OpenMP build (True) or the serial
+    build (False, the default and the checker the tests use)."""
+    global _parallel
+    _parallel = bool(on)
+
+
+def threads() -> int:
+    """Host threads of the build in use (1 for the serial one)."""
+    return int(lib().orc_threads())
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -62,41 +97,53 @@ class _Stats(ctypes.Structure):
 
 
 def lib():
-    global _lib
+    global _lib, _lib_omp
+    if _parallel:
+        if _lib_omp is None:
+            if _stale(_LIB_OMP):
+                build(force=True)
+            _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale(_LIB):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
-        L.orc_stencil_nnz.restype = I64
-        L.orc_stencil_nnz.argtypes = [I32, I32, I32, I32]
-        L.orc_csr_from_stencil.argtypes = [I32, I32, I32, I32, P, P, P, P]
-        L.orc_grid_colours.argtypes = [I32, I32, I32, I32, P]
-        L.orc_residual.argtypes = [I64, P, P, P, P, P, P]
-        L.orc_residual.restype = None
-        L.orc_spmv.argtypes = [I64, P, P, P, P, P]
-        L.orc_spmv.restype = None
-        L.orc_dot.argtypes = [I64, P, P]
-        L.orc_dot.restype = D
-        L.orc_norm2.argtypes = [I64, P]
-        L.orc_norm2.restype = D
-        L.orc_gradient.argtypes = [I64, P, P, P, P]
-        L.orc_gradient.restype = None
-        L.orc_build_local_domain.argtypes = [I64, P, P, P, P, P, I32, I32, D, I32, P, P, P, P, P, P]
-        L.orc_restricted_nnz.argtypes = [I64, P, P, P, I64, P]
-        L.orc_restricted_nnz.restype = I64
-        L.orc_restricted.argtypes = [P, P, P, P, I64, P, P, P, P]
-        L.orc_restricted.restype = None
-        L.orc_pcg.argtypes = [I64, P, P, P, P, P, I32, P, I32, D, I32, P, P]
-        L.orc_gmres.argtypes = [I64, P, P, P, P, P, I32, I32, D, I32, P, P]
-        L.orc_gs_sweeps.argtypes = [I64, P, P, P, P, P, P, I32, I32]
-        L.orc_gs_sweeps.restype = None
-        L.orc_solve_global.argtypes = [I64, P, P, P, P, P, P, I32, P, P]
-        L.orc_solve_local.argtypes = [I64, P, P, P, P, P, P, I64, P, I32, P, P]
-        L.orc_assemble_logk.argtypes = [I32, I32, I32, I32, D, P, P]
-        L.orc_grad_logk.argtypes = [I32, I32, I32, I32, P, P, P, P]
-        L.orc_heat_assemble.argtypes = [I32, I32, D, D, D, D, P, P, P, P]
-        _lib = L
+        _lib = _declare(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _declare(L):
+    """ctypes signatures of the oracle's exports."""
+    L.orc_stencil_nnz.restype = I64
+    L.orc_stencil_nnz.argtypes = [I32, I32, I32, I32]
+    L.orc_csr_from_stencil.argtypes = [I32, I32, I32, I32, P, P, P, P]
+    L.orc_grid_colours.argtypes = [I32, I32, I32, I32, P]
+    L.orc_residual.argtypes = [I64, P, P, P, P, P, P]
+    L.orc_residual.restype = None
+    L.orc_spmv.argtypes = [I64, P, P, P, P, P]
+    L.orc_spmv.restype = None
+    L.orc_dot.argtypes = [I64, P, P]
+    L.orc_dot.restype = D
+    L.orc_norm2.argtypes = [I64, P]
+    L.orc_norm2.restype = D
+    L.orc_gradient.argtypes = [I64, P, P, P, P]
+    L.orc_gradient.restype = None
+    L.orc_build_local_domain.argtypes = [I64, P, P, P, P, P, I32, I32, D, I32, P, P, P, P, P, P]
+    L.orc_restricted_nnz.argtypes = [I64, P, P, P, I64, P]
+    L.orc_restricted_nnz.restype = I64
+    L.orc_restricted.argtypes = [P, P, P, P, I64, P, P, P, P]
+    L.orc_restricted.restype = None
+    L.orc_pcg.argtypes = [I64, P, P, P, P, P, I32, P, I32, D, I32, P, P]
+    L.orc_gmres.argtypes = [I64, P, P, P, P, P, I32, I32, D, I32, P, P]
+    L.orc_gs_sweeps.argtypes = [I64, P, P, P, P, P, P, I32, I32]
+    L.orc_gs_sweeps.restype = None
+    L.orc_solve_global.argtypes = [I64, P, P, P, P, P, P, I32, P, P]
+    L.orc_solve_local.argtypes = [I64, P, P, P, P, P, P, I64, P, I32, P, P]
+    L.orc_assemble_logk.argtypes = [I32, I32, I32, I32, D, P, P]
+    L.orc_grad_logk.argtypes = [I32, I32, I32, I32, P, P, P, P]
+    L.orc_heat_assemble.argtypes = [I32, I32, D, D, D, D, P, P, P, P]
+    L.orc_threads.restype = I32
+    L.orc_threads.argtypes = []
+    return L
 
 
 def _p(a: Optional[np.ndarray]):

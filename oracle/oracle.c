@@ -11,6 +11,15 @@
  * contraction, so every product and sum below is rounded exactly as written;
  * fma() is used only where a fused step is stated).
  *
+ * The same source built with -fopenmp (liboracle_omp.so) runs the loops
+ * whose rows are independent on all host cores: residuals, products,
+ * gradients, marking, an expansion round, Jacobi, the PCG vector updates
+ * and one colour of a Gauss-Seidel sweep (rows of one colour never couple,
+ * which the grid colourings guarantee).  Dot products, norms and the
+ * compaction stay serial, so both builds return bit-identical results; the
+ * parallel build exists to time the oracle on many cores, and the tests
+ * check it against the serial one.
+ *
  * Conventions (the readings of the paper are listed with each function):
  *   - A is CSR with ascending column indices per row; "a_ij != 0" of the
  *     paper is read as "a_ij is stored" (the structural pattern).
@@ -31,6 +40,18 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Host threads the row loops use: 1 in the serial build. */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #define ORC_OK 0
 #define ORC_EINVAL 1
@@ -157,6 +178,7 @@ int orc_grid_colours(int kind, int nx, int ny, int nz, int8_t *colour) {
 /* r = b - A x.  Component form of the residual (Section 2.3.1). */
 void orc_residual(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
                   const double *b, const double *x, double *r) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double acc = b[i];
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc = fma(-val[k], x[col[k]], acc);
@@ -167,6 +189,7 @@ void orc_residual(int64_t n, const int64_t *rp, const int32_t *col, const double
 /* y = A x */
 void orc_spmv(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
               const double *x, double *y) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc = fma(val[k], x[col[k]], acc);
@@ -185,6 +208,7 @@ double orc_norm2(int64_t n, const double *a) { return sqrt(orc_dot(n, a, a)); }
 /* Gradient mimic g_i = sum over stored j of |x_i - x_j|, eq. (grad),
  * Section 2.2.  The j = i term is |0| and is left out (it adds +0). */
 void orc_gradient(int64_t n, const int64_t *rp, const int32_t *col, const double *x, double *g) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
@@ -233,6 +257,7 @@ int orc_build_local_domain(int64_t n, const int64_t *rp, const int32_t *col, con
     double tau;
     if (thresh_kind == ORC_TH_RELMAX) {
         double m = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : m)
         for (int64_t i = 0; i < n; ++i) {
             double s = fabs(score[i]);
             if (s > m) m = s;
@@ -247,6 +272,7 @@ int orc_build_local_domain(int64_t n, const int64_t *rp, const int32_t *col, con
     }
     *tau_out = tau;
 
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) mask[i] = fabs(score[i]) > tau ? 1 : 0;
 
     int grown = 0;
@@ -256,6 +282,7 @@ int orc_build_local_domain(int64_t n, const int64_t *rp, const int32_t *col, con
         for (int m = 1; m <= e_max; ++m) {
             for (int64_t i = 0; i < n; ++i) in_start[i] = mask[i] != 0;
             int64_t added = 0;
+#pragma omp parallel for schedule(static) reduction(+ : added)
             for (int64_t j = 0; j < n; ++j) {
                 if (in_start[j]) continue;
                 int neighbour = 0;
@@ -332,6 +359,7 @@ static double diag_of(const int64_t *rp, const int32_t *col, const double *val, 
  * x_i = (rhs_i - sum_{j != i, ascending} a_ij x_j) / a_ii. */
 static void gs_colour(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
                       const double *rhs, double *x, const int8_t *colour, int c) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         if (colour[i] != c) continue;
         double acc = rhs[i], d = 0.0;
@@ -348,6 +376,7 @@ static void apply_precond(int64_t n, const int64_t *rp, const int32_t *col, cons
                           int pc, const double *diag, const int8_t *colour, int ncol,
                           const double *r, double *z) {
     if (pc == ORC_PC_JACOBI) {
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) z[i] = r[i] / diag[i];
     } else if (pc == ORC_PC_SGS) {
         /* symmetric GS from z = 0: colours forward then backward */
@@ -379,6 +408,7 @@ int orc_pcg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
     double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
     double *diag = malloc(sizeof(double) * n);
     if (!r || !z || !p || !q || !diag) { free(r); free(z); free(p); free(q); free(diag); return ORC_ENOMEM; }
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) diag[i] = diag_of(rp, col, val, i);
     orc_residual(n, rp, col, val, b, x, r);
     double rr = orc_dot(n, r, r);
@@ -394,6 +424,7 @@ int orc_pcg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
             double pq = orc_dot(n, p, q);
             if (!(pq > 0.0)) { status = ORC_EBREAKDOWN; break; }
             double alpha = rz / pq;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) {
                 x[i] = fma(alpha, p[i], x[i]);
                 r[i] = fma(-alpha, q[i], r[i]);
@@ -405,6 +436,7 @@ int orc_pcg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
             double rz_new = orc_dot(n, r, z);
             double beta = rz_new / rz;
             rz = rz_new;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) p[i] = fma(beta, p[i], z[i]);
         }
     }

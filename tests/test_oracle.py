@@ -486,6 +486,67 @@ def test_adjoint_gradient_vs_dense_finite_differences():
         assert abs(lam[p] - fd) <= 1e-7 * max(1.0, abs(fd))
 
 
+def test_adjoint_gradient_seven_point_vs_dense_finite_differences():
+    """The seven-point branch of the adjoint pieces on a 4 x 4 x 3 grid:
+    dL/dlogk from one adjoint solve (orc_grad_logk on the oracle's assembly)
+    against central differences of the dense forward map, whose operator is
+    the generator's own seven-point assembly."""
+    nx, ny, nz, dt = 4, 4, 3, 4.0
+    n = nx * ny * nz
+    logk = W.lognormal_logk((nz, ny, nx), 0.8, 31)
+    rng = np.random.default_rng(32)
+    b = rng.random(n)
+    x_obs = rng.random(n)
+    win = np.zeros(n); win.reshape(nz, ny, nx)[1:, 1:3, :3] = 1.0
+
+    def loss(lk):
+        a = oracle.csr_from_stencil(W.KIND_7PT, nx, ny, nz, W.assemble_7pt(lk, 1 / dt)).dense()
+        x = np.linalg.solve(a, b)
+        return 0.5 * np.sum(win * (x - x_obs) ** 2)
+
+    A = oracle.csr_from_stencil(W.KIND_7PT, nx, ny, nz,
+                                oracle.assemble_logk(W.KIND_7PT, nx, ny, nz, 1 / dt, logk))
+    x, _, _, _ = oracle.pcg(A, b, np.zeros(n), oracle.PC_JACOBI, 1e-15, 5000)
+    lam, _, _, _ = oracle.pcg(A, win * (x - x_obs), np.zeros(n), oracle.PC_JACOBI, 1e-15, 5000)
+    g_l = oracle.grad_logk(W.KIND_7PT, nx, ny, nz, logk, x, lam)
+    h = 1e-5
+    for p in range(n):
+        e = np.zeros(n); e[p] = h
+        fd = (loss((logk.reshape(-1) + e).reshape(nz, ny, nx))
+              - loss((logk.reshape(-1) - e).reshape(nz, ny, nx))) / (2 * h)
+        assert abs(g_l[p] - fd) <= 1e-7 * max(1.0, abs(fd)), (p, g_l[p], fd)
+    assert np.abs(g_l).max() > 1e-4     # the check is not vacuous
+
+
+def test_assemble_logk_seven_point_properties():
+    """Mathematical properties of the seven-point log-conductivity operator
+    A = I/dt + sum_f T_f (e_P - e_Q)(e_P - e_Q)^T with zero-flux outer faces:
+    symmetric; every row sums to 1/dt (A 1 = 1/dt); with a constant
+    conductivity k each interior face carries exactly k (the harmonic mean
+    of equal values), so an interior row is 6k + 1/dt with -k off the
+    diagonal; a face between k_P and k_Q carries 2 k_P k_Q / (k_P + k_Q)."""
+    nx, ny, nz, inv_dt = 4, 4, 3, 0.25
+    n = nx * ny * nz
+    logk = W.lognormal_logk((nz, ny, nx), 1.0, 41)
+    a = oracle.csr_from_stencil(W.KIND_7PT, nx, ny, nz,
+                                oracle.assemble_logk(W.KIND_7PT, nx, ny, nz, inv_dt, logk)).dense()
+    np.testing.assert_array_equal(a, a.T)
+    np.testing.assert_allclose(a.sum(axis=1), inv_dt, rtol=0, atol=1e-13)
+    k = np.exp(logk.reshape(-1))
+    i, j = 5, 6                   # x-neighbours inside the first plane
+    assert abs(-a[i, j] - 2 * k[i] * k[j] / (k[i] + k[j])) <= 1e-15 * k.max()
+    i, j = 5, 5 + nx * ny         # z-neighbours
+    assert abs(-a[i, j] - 2 * k[i] * k[j] / (k[i] + k[j])) <= 1e-15 * k.max()
+    kc = 1.7
+    ac = oracle.csr_from_stencil(W.KIND_7PT, nx, ny, nz, oracle.assemble_logk(
+        W.KIND_7PT, nx, ny, nz, inv_dt, np.full((nz, ny, nx), np.log(kc)))).dense()
+    c = 1 + nx + nx * ny          # the interior cell (1, 1, 1)
+    assert abs(ac[c, c] - (6 * kc + inv_dt)) <= 1e-13
+    nbrs = [c - 1, c + 1, c - nx, c + nx, c - nx * ny, c + nx * ny]
+    np.testing.assert_allclose(ac[c, nbrs], -kc, rtol=1e-15)
+    assert np.count_nonzero(ac[c]) == 7
+
+
 # ----------------------------------------------------------------------------
 # 2-D nonlinear heat-conduction test problem (Section 3.1): Picard assembly
 # ----------------------------------------------------------------------------
@@ -755,3 +816,42 @@ def test_irregular_nonsym_input_and_gmres():
     xo, so, _ = oracle.local_then_global(A, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1, o)
     assert 0 < so.K < A.n
     assert np.linalg.norm(xo - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_openmp_build_is_bit_identical_to_the_serial_oracle():
+    """liboracle_omp.so (row loops on all host cores, used to time the oracle)
+    returns the serial oracle's results bit for bit: its parallel loops are
+    row-independent and every dot product stays serial.  Covers Algorithm 1
+    with both domain kinds, the global PCG with Jacobi and with the
+    colour-ordered SGS preconditioner (nine-point: four colours), and an
+    expansion round."""
+    import oracle
+    from paper_2001_01158_amd import workloads as W
+    cases = []
+    w = W.c2_moving_disk(nx=96, ny=80, radius=10.0, speed=2.0, n_systems=2)
+    cases.append((w.kind, (w.nx, w.ny, 1), w.coef, w.rhs(1, np.zeros(w.n)), 0.1 * np.ones(w.n)))
+    c9 = W.assemble_9pt(70, 50, 0.25, 100.0, 30.0)
+    src = W.disk_source(70, 50, 30.0, 25.0, 8.0, 1.0)
+    cases.append((W.KIND_9PT, (70, 50, 1), c9, src, np.zeros(3500)))
+    try:
+        for kind, (nx, ny, nz), coef, b, x0 in cases:
+            A = oracle.csr_from_stencil(kind, nx, ny, nz, coef)
+            outs = {}
+            for par in (False, True):
+                oracle.set_parallel(par)
+                if par:
+                    assert oracle.threads() >= 1
+                r = []
+                for mode, th, theta, e in [(oracle.MODE_RESIDUAL, oracle.TH_PAPER, 1e-10, 2),
+                                           (oracle.MODE_GRADIENT, oracle.TH_RELMAX, 1e-4, 0)]:
+                    x, st, d = oracle.local_then_global(A, b, x0, mode, theta, th, e,
+                                                        oracle.Options(eps=1e-10))
+                    r += [x, d.mask, np.array([st.its_local, st.its_global, d.K])]
+                for pc in (oracle.PC_JACOBI, oracle.PC_SGS):
+                    x, st = oracle.solve_global(A, b, x0, oracle.Options(eps=1e-10, pc=pc))
+                    r += [x, np.array([st.its_global])]
+                outs[par] = r
+            for a, c in zip(outs[False], outs[True]):
+                assert np.array_equal(a, c)
+    finally:
+        oracle.set_parallel(False)
