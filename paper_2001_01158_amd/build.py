@@ -15,8 +15,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lcs.hip")
-HEADERS = [os.path.join(HERE, "csrc", "lcs_device.h"), os.path.join(HERE, "csrc", "lcs_kernels.h"),
-           os.path.join(ROOT, "include", "lcs.h")]
 LIB = os.path.join(HERE, "liblcs.so")
 ARCH = os.environ.get("LCS_OFFLOAD_ARCH", "gfx950")
 
@@ -37,13 +35,6 @@ def build(verbose: bool = False) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
-
-
-def stale() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in [SRC] + HEADERS)
 
 
 if __name__ == "__main__":
