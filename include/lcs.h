@@ -60,9 +60,13 @@
  *     message (thread-local).  No exception crosses the ABI.  On
  *     LCS_ENOCONV / LCS_EBREAKDOWN, x holds the last iterate and stats are
  *     filled.
- *   - A context owns its device workspace (hipMalloc'd, grown on demand,
- *     released by lcs_destroy).  A context is used by one host thread at a
- *     time; calls on one context serialise on its workspace.
+ *   - A context made by lcs_create owns its device workspace (hipMalloc'd,
+ *     grown on demand, released by lcs_destroy; growing it synchronises the
+ *     device).  A context made by lcs_create_with_workspace takes every
+ *     device buffer from one caller-owned buffer and never allocates,
+ *     frees or synchronises the device in a call.  A context is used by one
+ *     host thread at a time; calls on one context serialise on its
+ *     workspace.
  */
 #ifndef LCS_H
 #define LCS_H
@@ -163,6 +167,30 @@ void lcs_default_options(lcs_options *o);
 /* Create a context on the current HIP device.  Returns LCS_EHIP if no device. */
 lcs_status lcs_create(lcs_ctx **ctx);
 void lcs_destroy(lcs_ctx *ctx);
+
+/* Bytes of a caller-owned device workspace (lcs_create_with_workspace) that
+ * serves every single-system call on A with options o (NULL: the defaults of
+ * lcs_default_options): a fixed head (device state, reduction partials) plus
+ * every buffer the path may use at its largest.  The local domain is counted
+ * at K = N, because Algorithms 2 and 3 may mark the whole grid, and general
+ * sparse input counts its ELL copy at width 16.  About 240 B per row for the
+ * nine-point stencil in mixed precision.  Host arithmetic only, no device
+ * call.  Returns 0 if A or o is invalid (lcs_last_error() says why). */
+size_t lcs_workspace_bytes(const lcs_matrix *A, const lcs_options *o);
+/* The same for the batched calls on G systems of A's grid (1 <= G <= 65535). */
+size_t lcs_workspace_bytes_batched(const lcs_matrix *A, int32_t G, const lcs_options *o);
+/* Create a context on the current HIP device whose device state and buffers
+ * all live in `workspace`: a caller-owned device buffer (for example a torch
+ * uint8 tensor) of `bytes` bytes, 256-byte aligned, at least the fixed head.
+ * Each call lays out the buffers it needs at its start and returns
+ * LCS_EINVAL, before any work, if `bytes` is smaller than
+ * lcs_workspace_bytes(A, o) of that call; it never allocates or frees device
+ * memory and never synchronises the device (only its stream, where the call
+ * needs a host decision).  The context's only allocations are made here:
+ * small pinned host copies of the device state, and events.  The caller keeps
+ * the buffer alive until lcs_destroy returns; the library never frees it.
+ * LCS_EINVAL for a NULL or misaligned workspace or one below the head. */
+lcs_status lcs_create_with_workspace(lcs_ctx **ctx, void *workspace, size_t bytes);
 const char *lcs_last_error(void);
 
 /* Global PCG from x (in: x^(0), out: solution) to eq. (rel-res-conv-criteria):

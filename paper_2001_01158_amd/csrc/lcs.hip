@@ -149,6 +149,13 @@ struct lcs_ctx {
     double *partials = nullptr;
     void *buf[B_NUM] = {};
     size_t cap[B_NUM] = {};
+    // caller-owned workspace (lcs_create_with_workspace): the state, the
+    // partials and every buffer are carved from it at offsets planned at the
+    // start of each call; null: the context owns grow-only buffers
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t ws_off[B_NUM] = {};
+    size_t ws_len[B_NUM] = {};
     hipEvent_t ev[5] = {};
     hipEvent_t chk[2] = {};
     int last_its[2] = {0, 0};       // iterations of the previous global / local PCG
@@ -161,14 +168,14 @@ struct lcs_ctx {
     // row-marching tiling of the 2-D stencil kernels (0 / -1: automatic)
     int march_rows = 0;
     int nontemporal = -1;
-    // pinned host copy of the per-system results of a batched solve
+    // pinned host copy of the per-system results of a batched solve, read
+    // back kBoutChunk systems at a time
     BatchOut *hbout = nullptr;
-    int32_t hbout_cap = 0;
     // pinned host copy of the GMRES cycle state
     GmState *hgm = nullptr;
     // ELL copy of the general sparse matrix of the current call
     struct {
-        int width = 0;         // 8 or 16
+        int width = 0;         // 5, 7, 9 or 16
         int64_t n = 0;
         int32_t *col = nullptr;
         double *val = nullptr;   // width x n values, then the diagonal
@@ -186,6 +193,14 @@ namespace {
 template <typename T>
 lcs_status get_buf(lcs_ctx *c, BufId id, size_t count, T **out) {
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (c->ws) {   // caller-owned workspace: the slot planned for this call
+        if (c->ws_len[id] < bytes)
+            return fail(LCS_EINVAL, "workspace plan holds " + std::to_string(c->ws_len[id]) +
+                                        " bytes for buffer " + std::to_string((int)id) + ", " +
+                                        std::to_string(bytes) + " requested");
+        *out = reinterpret_cast<T *>(c->ws + c->ws_off[id]);
+        return LCS_OK;
+    }
     if (c->cap[id] < bytes) {
         if (c->buf[id]) {
             HIP_TRY(hipDeviceSynchronize());  // the old buffer may still be in use
@@ -264,6 +279,149 @@ lcs_status check_options_for(const lcs_options *o, const lcs_matrix *A) {
 
 lcs_status check_ptr(const void *p, const char *what) {
     if (!p) return fail(LCS_EINVAL, std::string(what) + " is NULL");
+    return LCS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// caller-owned workspace: the layout of one call
+// ---------------------------------------------------------------------------
+// What a call may request from the workspace.  Each class requests the
+// buffers listed in plan_sizes at most at their largest size (K = N).
+enum What { kWhatPiece = 0, kWhatSpmv32, kWhatDomain, kWhatGather, kWhatSolve, kWhatBatch };
+constexpr size_t kWsAlign = 256;
+constexpr int kBoutChunk = 1024;   // batched results read back this many at a time
+
+size_t align_up(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+// the state and the reduction partials at the head of a workspace
+size_t ws_head_bytes() {
+    return align_up(sizeof(Scalars)) + align_up(sizeof(double) * kSlotElems * kPtSlots);
+}
+
+// slots of the restricted ELL matrix: the stencil's entries per row, or
+// the widest ELL copy of general sparse input
+int gather_width(const lcs_matrix *A) {
+    switch (A->kind) {
+    case LCS_STENCIL5_2D: return 5;
+    case LCS_STENCIL7_3D: return 7;
+    case LCS_CSR: return kCsrMaxRow;
+    default: return 9;
+    }
+}
+
+// Bytes of every buffer a call of class `what` on A with options o (NULL:
+// the defaults) may request, at its largest; 0 for the buffers it never
+// requests.  G: systems of a batched call.
+void plan_sizes(const lcs_matrix *A, const lcs_options *o, int what, int64_t G,
+                size_t len[B_NUM]) {
+    for (int i = 0; i < B_NUM; ++i) len[i] = 0;
+    lcs_options def;
+    if (!o) {
+        lcs_default_options(&def);
+        o = &def;
+    }
+    const size_t n = (size_t)A->nx * A->ny * A->nz;
+    const size_t d = sizeof(double), f = sizeof(float), i4 = sizeof(int32_t);
+    const bool csr = A->kind == LCS_CSR;
+    const bool mixed = o->precision == LCS_PREC_MIXED;
+    if (csr) {   // the checked ELL copy of width <= 16 and its diagonal
+        len[B_AFLAGS] = 2 * i4;
+        len[B_ACOL] = (size_t)kCsrMaxRow * n * i4;
+        len[B_AVAL] = (size_t)(kCsrMaxRow + 1) * n * d;
+        len[B_ACLR] = n;
+    }
+    const bool want32 = what == kWhatSpmv32 || (what == kWhatSolve && mixed);
+    if (want32 && (csr || !A->coef32))
+        len[B_COEF32] = (csr ? (size_t)(kCsrMaxRow + 1) : (size_t)n_arrays(A->kind)) * n * f;
+    const size_t W = (size_t)gather_width(A);
+    const size_t blockoff = 2 * (size_t)kMaxGrid * i4;
+    if (what == kWhatDomain || what == kWhatSolve) {
+        len[B_SCORE] = n * d;
+        len[B_STAMP] = (size_t)tiling_for((int64_t)n).npad;
+        len[B_INV] = n * i4;
+        len[B_BLOCKOFF] = blockoff;
+    }
+    if (what == kWhatGather || what == kWhatSolve) {
+        len[B_INV] = n * i4;
+        len[B_COL] = W * n * i4;
+        len[B_VAL] = W * n * d;
+        len[B_DG] = n * d;
+        len[B_CLR] = n;
+        len[B_RHSL] = n * d;
+        len[B_ROWLEN] = n * i4;
+        len[B_BLOCKOFF] = blockoff;
+    }
+    if (what == kWhatSolve) {
+        len[B_IDX] = n * i4;
+        len[B_DL] = n * d;
+        if (uses_gmres(A)) {
+            const size_t m = (size_t)std::max(1, std::min(o->restart > 0 ? o->restart : 40, kMaxRestart));
+            len[B_GMV] = (m + 1) * n * d;
+            len[B_GMW0] = len[B_GMW1] = n * d;
+            len[B_GMP0] = (size_t)kGmPartVals * kGmGrid * d;
+            len[B_GMPN] = (size_t)kGmGrid * d;
+            len[B_GMS] = sizeof(GmState);
+        } else if (!mixed) {
+            for (BufId b : {B_R, B_Z, B_P0, B_P1, B_Q, B_W0, B_W1, B_S0, B_S1}) len[b] = n * d;
+        } else {
+            len[B_VAL32] = W * n * f;
+            len[B_DG32] = n * f;
+            len[B_RES] = n * d;
+            for (BufId b : {B_R32, B_D32, B_RI32, B_Z32, B_P32A, B_P32B, B_Q32, B_W32A, B_W32B,
+                            B_S32A, B_S32B})
+                len[b] = n * f;
+        }
+    }
+    if (what == kWhatBatch) {
+        const size_t g = (size_t)std::max<int64_t>(G, 1);
+        len[B_BWS] = 4 * n * g * d;
+        len[B_BSTAMP] = n * g;
+        len[B_BIDX] = n * g * i4;
+        len[B_BOUT] = g * sizeof(BatchOut);
+        if (A->kind == LCS_STENCIL9N_2D)
+            len[B_BGMV] = (size_t)(std::max(1, std::min(o->restart, kMaxRestart)) + 1) * n * g * d;
+    }
+}
+
+// Offsets of the planned buffers after the head: the ELL copy of general
+// sparse input first (its place depends on N alone, so a copy kept for
+// csr_reuse stays where it is), then the others in BufId order.  Returns
+// the total bytes.
+size_t plan_offsets(const size_t len[B_NUM], size_t off[B_NUM]) {
+    size_t at = ws_head_bytes();
+    const BufId first[] = {B_AFLAGS, B_ACOL, B_AVAL, B_ACLR};
+    for (BufId b : first) {
+        off[b] = at;
+        at += align_up(len[b]);
+    }
+    for (int i = 0; i < B_NUM; ++i) {
+        if (i == B_AFLAGS || i == B_ACOL || i == B_AVAL || i == B_ACLR) continue;
+        off[i] = at;
+        at += align_up(len[i]);
+    }
+    return at;
+}
+
+size_t plan_total(const lcs_matrix *A, const lcs_options *o, int what, int64_t G) {
+    size_t len[B_NUM], off[B_NUM];
+    plan_sizes(A, o, what, G, len);
+    return plan_offsets(len, off);
+}
+
+// At the start of a call on a context with a caller-owned workspace: lay out
+// the buffers this call may use, or fail with LCS_EINVAL before any work if
+// the workspace is too small.  A call on another matrix may overwrite a kept
+// ELL copy, so only general sparse input keeps it.
+lcs_status plan_call(lcs_ctx *c, const lcs_matrix *A, const lcs_options *o, int what,
+                     int64_t G = 0) {
+    if (!c->ws) return LCS_OK;
+    plan_sizes(A, o, what, G, c->ws_len);
+    const size_t total = plan_offsets(c->ws_len, c->ws_off);
+    if (A->kind != LCS_CSR) c->ell.valid = false;
+    if (total > c->ws_bytes)
+        return fail(LCS_EINVAL, "workspace of " + std::to_string(c->ws_bytes) +
+                                    " bytes is smaller than the " + std::to_string(total) +
+                                    " bytes this call needs (lcs_workspace_bytes)");
     return LCS_OK;
 }
 
@@ -411,7 +569,8 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
 
 // General sparse input: check the structure (one synchronisation, before
 // any kernel reads through the column indices), then copy A into
-// column-major ELL of width 8 or 16 in the context.  Stencil kinds: nothing.
+// column-major ELL of width 5, 7, 9 or 16 in the context.  Stencil kinds:
+// nothing.
 lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
     if (A->kind != LCS_CSR) return LCS_OK;
     const int64_t n = A->nx;
@@ -897,11 +1056,6 @@ lcs_status run_gmres_t(lcs_ctx *c, const Op &A, const double *rhs, double *x, bo
     LCS_TRY(get_buf(c, B_GMP0, (size_t)kGmPartVals * kGmGrid, &ph0));
     LCS_TRY(get_buf(c, B_GMPN, (size_t)kGmGrid, &pn));
     LCS_TRY(get_buf(c, B_GMS, 1, &st));
-    if (!c->hgm && hipHostMalloc(&c->hgm, sizeof(GmState), hipHostMallocDefault) != hipSuccess) {
-        c->hgm = nullptr;
-        (void)hipGetLastError();
-        return fail(LCS_ENOMEM, "pinned GMRES state");
-    }
     const int g = band_grid(n, kGmGrid);
     const int check = o->check_every > 0 ? o->check_every : 8;
     if (x_zero) {
@@ -1242,6 +1396,7 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
         return fail(LCS_EINVAL, "batched solves take the Jacobi preconditioner or none");
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
     if (n > kMaxBatchN) return fail(LCS_EINVAL, "batched solves take at most 2^24 cells per system");
+    LCS_TRY(plan_call(c, A, o, kWhatBatch, G));
     hipStream_t s = (hipStream_t)stream;
     BatchArgs a{};
     a.coef_stride = (int64_t)n_arrays(A->kind) * n;
@@ -1269,19 +1424,6 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
     LCS_TRY(get_buf(c, B_BSTAMP, (size_t)n * G, &stamp));
     LCS_TRY(get_buf(c, B_BIDX, (size_t)n * G, &idx));
     LCS_TRY(get_buf(c, B_BOUT, (size_t)G, &dout));
-    if (c->hbout_cap < G) {
-        if (c->hbout) {
-            HIP_TRY(hipDeviceSynchronize());
-            HIP_TRY(hipHostFree(c->hbout));
-        }
-        c->hbout = nullptr;
-        c->hbout_cap = 0;
-        if (hipHostMalloc(&c->hbout, sizeof(BatchOut) * (size_t)G, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(LCS_ENOMEM, "pinned batch results");
-        }
-        c->hbout_cap = G;
-    }
     switch (A->kind) {
     case LCS_STENCIL5_2D:
         LCS_TRY(launch_batch(c, sop5<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));
@@ -1296,11 +1438,17 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
         LCS_TRY(launch_batch(c, sop7<double>(A, A->coef), o->precond, a, G, b, x, ws, stamp, idx, dout, s));
         break;
     }
-    HIP_TRY(hipMemcpyAsync(c->hbout, dout, sizeof(BatchOut) * (size_t)G, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
     int first_bad = -1;
+    int first_status = kStOk;
     for (int32_t g = 0; g < G; ++g) {
-        const BatchOut &r = c->hbout[g];
+        const int slot_g = g % kBoutChunk;
+        if (slot_g == 0) {   // the next chunk of results
+            const int m = std::min<int32_t>(kBoutChunk, G - g);
+            HIP_TRY(hipMemcpyAsync(c->hbout, dout + g, sizeof(BatchOut) * (size_t)m,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        const BatchOut &r = c->hbout[slot_g];
         if (st) {
             init_stats(&st[g]);
             st[g].K = r.K;
@@ -1312,16 +1460,60 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
             if (local) st[g].relres_after_local = r.relres_after_local;
             st[g].relres_final = r.relres_final;
         }
-        if (r.status != kStOk && first_bad < 0) first_bad = g;
+        if (r.status != kStOk && first_bad < 0) {
+            first_bad = g;
+            first_status = r.status;
+        }
     }
     if (first_bad >= 0) {
-        const lcs_status e = status_of(c->hbout[first_bad].status);
+        const lcs_status e = status_of(first_status);
         return fail(e, "system " + std::to_string(first_bad) + " of the batch: " + g_err);
     }
     return LCS_OK;
 }
 
+// Context creation: device state and partials from ws (caller-owned, at
+// least ws_head_bytes()) or from hipMalloc (ws == NULL); pinned host copies
+// and events in both cases.
+lcs_status create_ctx(lcs_ctx **out, void *ws, size_t ws_bytes) {
+    if (!out) return fail(LCS_EINVAL, "ctx is NULL");
+    *out = nullptr;
+    lcs_ctx *c = new lcs_ctx();
+    auto cleanup = [&](lcs_status st) {
+        lcs_destroy(c);
+        return st;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return cleanup(fail(LCS_EHIP, "no HIP device"));
+    if (ws) {
+        c->ws = static_cast<char *>(ws);
+        c->ws_bytes = ws_bytes;
+        c->dsc = reinterpret_cast<Scalars *>(c->ws);
+        c->partials = reinterpret_cast<double *>(c->ws + align_up(sizeof(Scalars)));
+    } else {
+        if (hipMalloc(&c->dsc, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_ENOMEM, "state"));
+        if (hipMalloc(&c->partials, sizeof(double) * kSlotElems * kPtSlots) != hipSuccess)
+            return cleanup(fail(LCS_ENOMEM, "partials"));
+    }
+    if (hipMemset(c->dsc, 0, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_EHIP, "memset"));
+    if (hipHostMalloc(&c->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "pinned state"));
+    if (hipHostMalloc(&c->hdone, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "pinned flags"));
+    if (hipHostMalloc(&c->hgm, sizeof(GmState), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "pinned GMRES state"));
+    if (hipHostMalloc(&c->hbout, sizeof(BatchOut) * kBoutChunk, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "pinned batch results"));
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(LCS_EHIP, "event"));
+    for (auto &e : c->chk)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(LCS_EHIP, "event"));
+    if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LCS_EHIP, "sync"));
+    *out = c;
+    return LCS_OK;
+}
 }  // namespace
+
 
 extern "C" {
 
@@ -1341,31 +1533,37 @@ void lcs_default_options(lcs_options *o) {
 
 const char *lcs_last_error(void) { return g_err.c_str(); }
 
-lcs_status lcs_create(lcs_ctx **out) {
+lcs_status lcs_create(lcs_ctx **out) { return create_ctx(out, nullptr, 0); }
+
+lcs_status lcs_create_with_workspace(lcs_ctx **out, void *workspace, size_t bytes) {
     if (!out) return fail(LCS_EINVAL, "ctx is NULL");
     *out = nullptr;
-    lcs_ctx *c = new lcs_ctx();
-    auto cleanup = [&](lcs_status st) {
-        lcs_destroy(c);
-        return st;
-    };
-    if (hipGetDevice(&c->device) != hipSuccess) return cleanup(fail(LCS_EHIP, "no HIP device"));
-    if (hipMalloc(&c->dsc, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_ENOMEM, "state"));
-    if (hipMemset(c->dsc, 0, sizeof(Scalars)) != hipSuccess) return cleanup(fail(LCS_EHIP, "memset"));
-    if (hipMalloc(&c->partials, sizeof(double) * kSlotElems * kPtSlots) != hipSuccess)
-        return cleanup(fail(LCS_ENOMEM, "partials"));
-    if (hipHostMalloc(&c->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
-        return cleanup(fail(LCS_ENOMEM, "pinned state"));
-    if (hipHostMalloc(&c->hdone, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
-        return cleanup(fail(LCS_ENOMEM, "pinned flags"));
-    for (auto &e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(LCS_EHIP, "event"));
-    for (auto &e : c->chk)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-            return cleanup(fail(LCS_EHIP, "event"));
-    if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LCS_EHIP, "sync"));
-    *out = c;
-    return LCS_OK;
+    if (!workspace) return fail(LCS_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % kWsAlign != 0)
+        return fail(LCS_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < ws_head_bytes())
+        return fail(LCS_EINVAL, "workspace smaller than its fixed head of " +
+                                    std::to_string(ws_head_bytes()) + " bytes");
+    return create_ctx(out, workspace, bytes);
+}
+
+size_t lcs_workspace_bytes(const lcs_matrix *A, const lcs_options *o) {
+    if (check_matrix(A) != LCS_OK) return 0;
+    if (o && check_options_for(o, A) != LCS_OK) return 0;
+    size_t m = 0;
+    for (int what : {kWhatPiece, kWhatSpmv32, kWhatDomain, kWhatGather, kWhatSolve})
+        m = std::max(m, plan_total(A, o, what, 0));
+    return m;
+}
+
+size_t lcs_workspace_bytes_batched(const lcs_matrix *A, int32_t G, const lcs_options *o) {
+    if (check_matrix(A) != LCS_OK) return 0;
+    if (o && check_options_for(o, A) != LCS_OK) return 0;
+    if (G < 1 || G > kMaxBatch) {
+        fail(LCS_EINVAL, "batch size G must be 1..65535");
+        return 0;
+    }
+    return plan_total(A, o, kWhatBatch, G);
 }
 
 void lcs_destroy(lcs_ctx *c) {
@@ -1373,8 +1571,10 @@ void lcs_destroy(lcs_ctx *c) {
     (void)hipDeviceSynchronize();
     for (int i = 0; i < B_NUM; ++i)
         if (c->buf[i]) (void)hipFree(c->buf[i]);
-    if (c->dsc) (void)hipFree(c->dsc);
-    if (c->partials) (void)hipFree(c->partials);
+    if (!c->ws) {
+        if (c->dsc) (void)hipFree(c->dsc);
+        if (c->partials) (void)hipFree(c->partials);
+    }
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hdone) (void)hipHostFree(c->hdone);
     if (c->hbout) (void)hipHostFree(c->hbout);
@@ -1391,6 +1591,7 @@ lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const 
                         double *r, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(plan_call(c, A, nullptr, kWhatPiece));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
@@ -1408,6 +1609,7 @@ lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const 
 lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double *g, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(plan_call(c, A, nullptr, kWhatPiece));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(g, "g"));
@@ -1426,6 +1628,7 @@ lcs_status lcs_spmv(lcs_ctx *c, const lcs_matrix *A, const void *x, void *y, int
                     int32_t reps, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(plan_call(c, A, nullptr, precision == LCS_PREC_MIXED ? kWhatSpmv32 : kWhatPiece));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(x, "x"));
     LCS_TRY(check_ptr(y, "y"));
@@ -1468,6 +1671,7 @@ lcs_status lcs_build_local_domain(lcs_ctx *c, const lcs_matrix *A, const double 
                                   int64_t *K, lcs_stats *st, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(plan_call(c, A, nullptr, kWhatDomain));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x0, "x0"));
@@ -1498,6 +1702,7 @@ lcs_status lcs_gather_restricted(lcs_ctx *c, const lcs_matrix *A, const int32_t 
                                  void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(plan_call(c, A, nullptr, kWhatGather));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     const int64_t n = (int64_t)A->nx * A->ny * A->nz;
     if (K < 0 || K > n) return fail(LCS_EINVAL, "K out of range");
@@ -1544,6 +1749,7 @@ lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, doubl
                          int32_t n_sweeps, void *stream) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
+    LCS_TRY(plan_call(c, A, nullptr, kWhatPiece));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
@@ -1568,6 +1774,7 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
     LCS_TRY(check_options_for(o, A));
+    LCS_TRY(plan_call(c, A, o, kWhatSolve));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
@@ -1604,6 +1811,7 @@ lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, dou
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
     LCS_TRY(check_options_for(o, A));
+    LCS_TRY(plan_call(c, A, o, kWhatSolve));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));
@@ -1649,6 +1857,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     LCS_TRY(check_matrix(A));
     LCS_TRY(check_options_for(o, A));
+    LCS_TRY(plan_call(c, A, o, kWhatSolve));
     LCS_TRY(prepare_matrix(c, A, (hipStream_t)stream));
     LCS_TRY(check_ptr(b, "b"));
     LCS_TRY(check_ptr(x, "x"));

@@ -36,7 +36,8 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_gather_restricted", "lcs_gs_sweeps", "lcs_cast_coef", "lcs_assemble_logk",
             "lcs_grad_logk", "lcs_set_kernel_timing", "lcs_get_kernel_timing",
             "lcs_set_tiling", "lcs_assemble_heat", "lcs_norm2_diff",
-            "lcs_solve_global_batched", "lcs_solve_local_then_global_batched"]
+            "lcs_solve_global_batched", "lcs_solve_local_then_global_batched",
+            "lcs_workspace_bytes", "lcs_workspace_bytes_batched", "lcs_create_with_workspace"]
 TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE = range(5)
 
 
@@ -103,6 +104,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lcs_set_tiling": (I32, [P, I32, I32]),
         "lcs_assemble_heat": (I32, [P, I32, I32, D, D, D, D, P, P, P, P, P]),
         "lcs_norm2_diff": (I32, [P, P, P, I64, ctypes.POINTER(D), P]),
+        "lcs_workspace_bytes": (ctypes.c_size_t, [PM, PO]),
+        "lcs_workspace_bytes_batched": (ctypes.c_size_t, [PM, I32, PO]),
+        "lcs_create_with_workspace": (I32, [ctypes.POINTER(P), P, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -259,11 +263,24 @@ class Stats:
 
 
 class Context:
-    """Owns a device workspace (lcs_create / lcs_destroy)."""
+    """A solver context (lcs_create / lcs_destroy).  Without `workspace` it
+    owns grow-only device buffers.  With `workspace`, a caller-owned device
+    tensor (for example torch.empty(workspace_bytes(A, opts), dtype=torch.uint8,
+    device=...)), every device buffer of every call comes from that tensor
+    (lcs_create_with_workspace) and no call allocates device memory; the
+    context keeps a reference to the tensor until it is closed."""
 
-    def __init__(self):
+    def __init__(self, workspace: Optional[torch.Tensor] = None):
         self._h = ctypes.c_void_p()
-        _check(lib().lcs_create(ctypes.byref(self._h)))
+        self._ws = None
+        if workspace is None:
+            _check(lib().lcs_create(ctypes.byref(self._h)))
+        else:
+            if not workspace.is_contiguous():
+                raise ValueError("workspace must be contiguous")
+            nbytes = workspace.numel() * workspace.element_size()
+            _check(lib().lcs_create_with_workspace(ctypes.byref(self._h), _ptr(workspace), nbytes))
+            self._ws = workspace
 
     @property
     def handle(self):
@@ -273,6 +290,7 @@ class Context:
         if self._h:
             lib().lcs_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._ws = None
 
     def __del__(self):
         try:
@@ -293,6 +311,26 @@ def default_context() -> Context:
 
 def _ctx(ctx):
     return (ctx or default_context()).handle
+
+
+def workspace_bytes(A, opts: Options = None) -> int:
+    """Bytes of a caller-owned workspace serving every single-system call on
+    A with opts (lcs_workspace_bytes; host arithmetic only)."""
+    o = opts.c() if opts is not None else None
+    nb = lib().lcs_workspace_bytes(ctypes.byref(A.c()), ctypes.byref(o) if o is not None else None)
+    if nb == 0:
+        raise LcsError(EINVAL, lib().lcs_last_error().decode())
+    return int(nb)
+
+
+def workspace_bytes_batched(A, G: int, opts: Options = None) -> int:
+    """lcs_workspace_bytes_batched: the same for batched calls on G systems."""
+    o = opts.c() if opts is not None else None
+    nb = lib().lcs_workspace_bytes_batched(ctypes.byref(A.c()), int(G),
+                                           ctypes.byref(o) if o is not None else None)
+    if nb == 0:
+        raise LcsError(EINVAL, lib().lcs_last_error().decode())
+    return int(nb)
 
 
 # ---------------------------------------------------------------------------
