@@ -207,6 +207,24 @@ lcs_status lcs_build_local_domain(lcs_ctx *ctx, const lcs_matrix *A, const doubl
                                   double theta, int32_t e_max, int32_t *idx, uint8_t *mask,
                                   int64_t *K, lcs_stats *st, void *stream);
 
+/* lcs_build_local_domain for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context, and no allocation of any kind.  Its device state
+ * and buffers live in one file-scope device array of 28 MiB that each GPU
+ * holds from the library's load until the process ends; the call looks up
+ * its address on the current device the first time.  Same arguments,
+ * results (idx, *K, mask, stats) and errors as lcs_build_local_domain, bit
+ * for bit, for the stencil kinds and N <= 2^21 cells (LCS_EINVAL for CSR
+ * input or a larger N, before any work).  Every buffer is fully written
+ * before it is read, so nothing needs clearing between calls.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller.
+ * Synchronises the stream. */
+lcs_status lcs_build_local_domain_static(const lcs_matrix *A, const double *b, const double *x0,
+                                         int32_t mode, int32_t thresh_kind, double theta,
+                                         int32_t e_max, int32_t *idx, uint8_t *mask, int64_t *K,
+                                         lcs_stats *st, void *stream);
+
 /* Steps 3-7 of Algorithm 1 for a given Omega = idx[0..K) (device, ascending,
  * distinct): solve B d = r^(0)_Omega from d = 0 (the correction form of
  * eq. loc-equ), x <- x + d on Omega (eq. sol-assemble), then n_smooth

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1514,6 +1515,42 @@ lcs_status create_ctx(lcs_ctx **out, void *ws, size_t ws_bytes) {
 }
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// local domain without allocation: the scratch array
+// ---------------------------------------------------------------------------
+// Device state, partials and the domain's buffers (scores, stamps, inv,
+// block counts) of lcs_build_local_domain_static, for grids of at most
+// kStaticMaxN cells.  Each GPU the library runs on holds its own copy until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host it only names the symbol): static_scratch() looks up its device
+// address once per device and every use goes through that address.
+constexpr int64_t kStaticMaxN = int64_t(1) << 21;
+constexpr size_t kStaticScratchBytes = size_t(28) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up on
+// the first call on each device, with that device current).
+lcs_status static_scratch(void **out, int *device) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LCS_EINVAL, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LCS_EHIP, "hipGetSymbolAddress gave no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    *device = dev;
+    return LCS_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -2051,6 +2088,55 @@ lcs_status lcs_grad_logk(lcs_ctx *c, int32_t kind, int32_t nx, int32_t ny, int32
                            x, lam, grad);
     LAUNCH_CHECK();
     return LCS_OK;
+}
+
+lcs_status lcs_build_local_domain_static(const lcs_matrix *A, const double *b, const double *x0,
+                                         int32_t mode, int32_t thresh_kind, double theta,
+                                         int32_t e_max, int32_t *idx, uint8_t *mask, int64_t *K,
+                                         lcs_stats *st, void *stream) {
+    LCS_TRY(check_matrix(A));
+    if (A->kind == LCS_CSR)
+        return fail(LCS_EINVAL, "the allocation-free local domain takes the stencil kinds");
+    const int64_t n = (int64_t)A->nx * A->ny * A->nz;
+    if (n > kStaticMaxN)
+        return fail(LCS_EINVAL, "the allocation-free local domain takes at most 2^21 cells, got " +
+                                    std::to_string(n));
+    LCS_TRY(check_ptr(b, "b"));
+    LCS_TRY(check_ptr(x0, "x0"));
+    LCS_TRY(check_ptr(idx, "idx"));
+    LCS_TRY(check_ptr(K, "K"));
+    LCS_TRY(check_mode(mode, thresh_kind, theta, e_max));
+    void *p = nullptr;
+    int dev = 0;
+    LCS_TRY(static_scratch(&p, &dev));
+    // a context on the stack whose state, partials and buffers lie in the
+    // scratch array; scalars come back into pageable host memory
+    lcs_ctx t;
+    t.device = dev;
+    t.ws = static_cast<char *>(p);
+    t.ws_bytes = kStaticScratchBytes;
+    t.dsc = reinterpret_cast<Scalars *>(t.ws);
+    t.partials = reinterpret_cast<double *>(t.ws + align_up(sizeof(Scalars)));
+    Scalars host_state;
+    t.hsc = &host_state;
+    LCS_TRY(plan_call(&t, A, nullptr, kWhatDomain));
+    hipStream_t s = (hipStream_t)stream;
+    return with_ops(&t, A, nullptr, vec_ok({b, x0}), [&](auto sop, auto op, auto, auto) -> lcs_status {
+        LCS_TRY(build_domain(&t, sop, op, b, x0, mode, thresh_kind, theta, e_max, -1.0, idx, K, s));
+        if (mask) {
+            uint8_t *stamp;
+            LCS_TRY(get_buf(&t, B_STAMP, tiling_for(sop.n).npad, &stamp));
+            HIP_TRY(hipMemcpyAsync(mask, stamp, (size_t)sop.n, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        if (st) {
+            init_stats(st);
+            st->K = *K;
+            st->e_rounds = host_state.ms.grown;
+            st->tau = host_state.ms.tau;
+        }
+        return LCS_OK;
+    });
 }
 
 }  // extern "C"

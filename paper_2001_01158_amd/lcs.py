@@ -37,7 +37,8 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_grad_logk", "lcs_set_kernel_timing", "lcs_get_kernel_timing",
             "lcs_set_tiling", "lcs_assemble_heat", "lcs_norm2_diff",
             "lcs_solve_global_batched", "lcs_solve_local_then_global_batched",
-            "lcs_workspace_bytes", "lcs_workspace_bytes_batched", "lcs_create_with_workspace"]
+            "lcs_workspace_bytes", "lcs_workspace_bytes_batched", "lcs_create_with_workspace",
+            "lcs_build_local_domain_static"]
 TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE = range(5)
 
 
@@ -107,6 +108,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lcs_workspace_bytes": (ctypes.c_size_t, [PM, PO]),
         "lcs_workspace_bytes_batched": (ctypes.c_size_t, [PM, I32, PO]),
         "lcs_create_with_workspace": (I32, [ctypes.POINTER(P), P, ctypes.c_size_t]),
+        "lcs_build_local_domain_static": (I32, [PM, P, P, I32, I32, D, I32, P, P,
+                                                ctypes.POINTER(I64), PS, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -360,6 +363,29 @@ def build_local_domain(A: Matrix, b: torch.Tensor, x0: torch.Tensor, mode: str =
                                         float(theta), int(e_max), _ptr(idx), _ptr(mask),
                                         ctypes.byref(K), ctypes.byref(st), _stream()))
     return idx[:K.value], mask, Stats.of(st)
+
+
+STATIC_MAX_N = 1 << 21   # cells of lcs_build_local_domain_static
+
+
+def build_local_domain_static(A: Matrix, b: torch.Tensor, x0: torch.Tensor, idx: torch.Tensor,
+                              mode: str = "residual", thresh: str = "relmax", theta: float = 1e-3,
+                              e_max: int = 1, mask: Optional[torch.Tensor] = None):
+    """lcs_build_local_domain_static: Algorithm 2 / 3 with no context and no
+    allocation; the caller passes idx (int32, capacity N) and optionally mask
+    (uint8, N).  Returns (K, Stats)."""
+    K = ctypes.c_int64(0)
+    st = _Stats()
+    if idx.dtype != torch.int32 or idx.numel() < A.n:
+        raise ValueError("idx must be int32 with capacity N")
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != A.n):
+        raise ValueError("mask must be uint8 of length N")
+    _check(lib().lcs_build_local_domain_static(ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+                                               _vec(x0, A.n, name="x0"), _MODES[mode],
+                                               _THRESH[thresh], float(theta), int(e_max),
+                                               _ptr(idx), _ptr(mask), ctypes.byref(K),
+                                               ctypes.byref(st), _stream()))
+    return K.value, Stats.of(st)
 
 
 def solve_local(A: Matrix, b: torch.Tensor, x: torch.Tensor, idx: torch.Tensor,
