@@ -118,7 +118,11 @@ typedef struct lcs_matrix {
                                  on this context that checked and copied them;
                                  the context then reuses its ELL copy (pointers,
                                  N, nnz and n_colours must match, else the call
-                                 checks and copies as with 0)                    */
+                                 checks and copies as with 0).  The library cannot
+                                 see values edited in place, nor a new matrix of
+                                 the same shape placed at the freed addresses of
+                                 the old one (as a caching allocator may do): set
+                                 1 only for arrays known to be unchanged        */
     int32_t csr_nonsym;       /* 1: A is not symmetric; every solve (global,
                                  local, global finish) uses GMRES(m) in FP64
                                  with Jacobi or no preconditioner, as for
@@ -281,7 +285,11 @@ enum {
                                      RB-SGS                                     */
     LCS_TIME_LOCAL_UPDATE = 2,    /* x, r, z update kernel of the local RB-SGS PCG */
     LCS_TIME_GLOBAL_AP = 3,       /* the same two classes for the global PCG    */
-    LCS_TIME_GLOBAL_UPDATE = 4
+    LCS_TIME_GLOBAL_UPDATE = 4,
+    LCS_TIME_SMOOTH = 5,          /* the Gauss-Seidel sweep kernels of Algorithm 1
+                                     step 7 (and lcs_gs_sweeps)                 */
+    LCS_TIME_SCORE = 6            /* the score kernel of the domain construction:
+                                     r^(0) and its norms, or g (Algorithms 2, 3) */
 };
 lcs_status lcs_set_kernel_timing(lcs_ctx *ctx, int32_t what);
 /* total milliseconds and number of timed launches since the last set */

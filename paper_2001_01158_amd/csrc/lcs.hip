@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lcs.h"
@@ -137,7 +138,7 @@ enum BufId {
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
     B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_W0, B_W1, B_S0, B_S1, B_W32A, B_W32B,
     B_S32A, B_S32B, B_BWS, B_BSTAMP, B_BIDX, B_BOUT, B_GMV, B_GMW0, B_GMW1, B_GMP0,
-    B_GMPN, B_GMS, B_BGMV, B_ACOL, B_AVAL, B_ACLR, B_AFLAGS, B_NUM
+    B_GMPN, B_GMS, B_BGMV, B_ACOL, B_AVAL, B_ACLR, B_AFLAGS, B_GSX, B_NUM
 };
 
 }  // namespace
@@ -146,7 +147,8 @@ struct lcs_ctx {
     int device = 0;
     Scalars *dsc = nullptr;    // device state
     Scalars *hsc = nullptr;    // pinned host copy
-    int32_t *hdone = nullptr;  // pinned: two slots for asynchronous convergence checks
+    int32_t *hdone = nullptr;  // pinned: the GMRES done flag
+    PcgState *hpcg = nullptr;  // pinned: two slots of the PCG state for asynchronous checks
     double *partials = nullptr;
     void *buf[B_NUM] = {};
     size_t cap[B_NUM] = {};
@@ -159,7 +161,10 @@ struct lcs_ctx {
     size_t ws_len[B_NUM] = {};
     hipEvent_t ev[5] = {};
     hipEvent_t chk[2] = {};
-    int last_its[2] = {0, 0};       // iterations of the previous global / local PCG
+    // iterations of the previous global (0) / local (1) PCG, by refinement
+    // step (mixed precision) or restart (FP64), for sizing the first chunk
+    int last_its[2][4] = {};
+    int cur_outer = 0;              // refinement step of the PCG being run
     // optional kernel timing (HIP events around one kernel class)
     int prof_what = 0;              // LCS_TIME_* or 0
     std::vector<hipEvent_t> prof_ev;
@@ -336,6 +341,9 @@ void plan_sizes(const lcs_matrix *A, const lcs_options *o, int what, int64_t G,
         len[B_COEF32] = (csr ? (size_t)(kCsrMaxRow + 1) : (size_t)n_arrays(A->kind)) * n * f;
     const size_t W = (size_t)gather_width(A);
     const size_t blockoff = 2 * (size_t)kMaxGrid * i4;
+    // the second buffer of the paired-colour sweeps of the nine-point stencil
+    if (A->kind == LCS_STENCIL9_2D && (what == kWhatPiece || what == kWhatSolve))
+        len[B_GSX] = n * d;
     if (what == kWhatDomain || what == kWhatSolve) {
         len[B_SCORE] = n * d;
         len[B_STAMP] = (size_t)tiling_for((int64_t)n).npad;
@@ -584,7 +592,8 @@ lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
     LCS_TRY(get_buf(c, B_AFLAGS, 2, &flags));
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, s, flags, 0, (int64_t)2);
     hipLaunchKernelGGL(k_csr_check, dim3(std::min(flat_grid(n), kMaxGrid)), dim3(kBlock), 0, s,
-                       A->row_ptr, A->col, n, A->nnz, A->colour, A->n_colours, flags);
+                       A->row_ptr, A->col, A->val, n, A->nnz, A->colour, A->n_colours,
+                       A->csr_nonsym ? 1 : 0, flags);
     LAUNCH_CHECK();
     int32_t h[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -599,7 +608,11 @@ lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
         if (h[0] & kCsrOrder) m += " columns not strictly ascending;";
         if (h[0] & kCsrNoDiag) m += " diagonal entry missing;";
         if (h[0] & kCsrColour) m += " colouring invalid (colour >= n_colours or two coupled rows share one);";
-        return fail(LCS_EINVAL, m);
+        if (h[0] & kCsrBadDiag)
+            m += A->csr_nonsym ? " zero diagonal entry;" : " diagonal entry <= 0 (not SPD);";
+        if (h[0] & kCsrNonFinite) m += " NaN or infinite value;";
+        // a well-formed matrix whose only fault is a non-finite value
+        return fail(h[0] == kCsrNonFinite ? LCS_ENONFINITE : LCS_EINVAL, m);
     }
     // the widths of the stencil kinds, whose ELL operators the local
     // systems already use, then 16
@@ -757,6 +770,72 @@ lcs_status flush_prof(lcs_ctx *c) {
     return LCS_OK;
 }
 
+// Enqueue PCG iterations in chunks between host checks, with up to two
+// chunks in flight: the host waits for the older chunk while the newer one
+// runs, so the GPU does not wait for the host.  launch(j) enqueues iteration
+// j; launch(max_iter) is the final stopping test.  After each chunk the PCG
+// state (stop flag, recursive residual, tolerance) is copied to pinned host
+// memory.  The first chunk is sized from the previous solve of the same
+// kind and step; later chunks from the residual's decay so far, so that few
+// launches run (and exit at once) after convergence.
+template <class F>
+lcs_status run_chunks(lcs_ctx *c, hipStream_t s, int max_iter, int check_every, int prev_its,
+                      F &&launch) {
+    int next_j = 0, nin = 0;
+    int inflight[2] = {0, 1}, launched_at[2] = {0, 0};
+    bool known = false;
+    int known_it = 0;
+    double rho = 0.0, rho0 = 0.0, tol = 0.0;
+    // launches the solve is expected to need in total (two over the estimate:
+    // a launch that exits at once costs less than a host round trip)
+    auto estimate = [&]() -> int {
+        if (!known) return prev_its > 0 ? prev_its + 2 : next_j + check_every;
+        const double q = std::pow(rho / rho0, 1.0 / std::max(known_it, 1));
+        if (!(q > 0.0) || !(q < 1.0) || !(tol > 0.0) || !(rho > tol))
+            return known_it + 1 + check_every;
+        const double rest = std::ceil(std::log(tol / rho) / std::log(q));
+        return known_it + 2 + (int)std::min(rest, 4.0 * check_every);
+    };
+    auto enqueue = [&](int len) -> lcs_status {
+        const int sl = nin == 0 ? 0 : inflight[0] ^ 1;
+        for (int k = 0; k < len && next_j < max_iter; ++k) LCS_TRY(launch(next_j++));
+        if (next_j >= max_iter) LCS_TRY(launch(next_j));   // final stopping test
+        launched_at[sl] = next_j;
+        HIP_TRY(hipMemcpyAsync(&c->hpcg[sl], &c->dsc->pcg, sizeof(PcgState),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(c->chk[sl], s));
+        inflight[nin++] = sl;
+        return LCS_OK;
+    };
+    LCS_TRY(enqueue(std::max(check_every, prev_its - check_every / 2)));
+    for (;;) {
+        if (nin < 2 && next_j < max_iter) {
+            const int len = std::min(check_every, estimate() - next_j);
+            if (len > 0) LCS_TRY(enqueue(len));
+        }
+        const int sl = inflight[0];
+        HIP_TRY(hipEventSynchronize(c->chk[sl]));
+        inflight[0] = inflight[1];
+        --nin;
+        const PcgState &h = c->hpcg[sl];
+        if (h.done) break;
+        // the last launch of the chunk tested the residual of iterate
+        // launched_at - 1
+        known = true;
+        known_it = launched_at[sl] - 1;
+        rho = std::sqrt(h.rr);
+        rho0 = std::sqrt(h.rr0);
+        tol = h.tol;
+        if (nin == 0) {
+            if (next_j >= max_iter) break;   // not reached: the final test sets the flag
+            LCS_TRY(enqueue(std::max(1, std::min(check_every, estimate() - next_j))));
+        }
+    }
+    return LCS_OK;
+}
+
+int &last_its_of(lcs_ctx *c, int scope) { return c->last_its[scope][std::min(c->cur_outer, 3)]; }
+
 // Single-synchronisation PCG (Jacobi / none): k_cg_init1, k_cg_init2, then
 // one k_cg_iter per iteration; the stopping test of x_j runs at the start of
 // iteration j.  Buffers: r, w, s double-buffered by iteration parity.
@@ -782,7 +861,6 @@ lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typena
     LAUNCH_CHECK();
     if (check_every < 1) check_every = 1;
     const bool timed = c->prof_what == (scope == 1 ? LCS_TIME_LOCAL_AP : LCS_TIME_GLOBAL_AP);
-    int next_j = 0;
     auto launch_iter = [&](int j) -> lcs_status {
         const int a = j & 1, b = a ^ 1;
         return launch_maybe_timed(c, timed, k_cg_iter<Op, kPc>, grid, s, A, x, B.p0,
@@ -790,25 +868,7 @@ lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typena
                                   (const real *)w[a], w[b], j, max_iter, tol_base, tol_factor,
                                   c->dsc, (const real *)part[a], part[b]);
     };
-    int first_chunk = std::max(check_every, c->last_its[scope] - check_every / 2);
-    auto enqueue_chunk = [&](int slot_id) -> lcs_status {
-        const int len = next_j == 0 ? first_chunk : check_every;
-        for (int k = 0; k < len && next_j < max_iter; ++k) LCS_TRY(launch_iter(next_j++));
-        if (next_j >= max_iter) LCS_TRY(launch_iter(next_j));  // final stopping test
-        HIP_TRY(hipMemcpyAsync(&c->hdone[slot_id], &c->dsc->pcg.done, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(c->chk[slot_id], s));
-        return LCS_OK;
-    };
-    LCS_TRY(enqueue_chunk(0));
-    int sl = 0;
-    for (;;) {
-        const bool more = next_j < max_iter;
-        if (more) LCS_TRY(enqueue_chunk(sl ^ 1));
-        HIP_TRY(hipEventSynchronize(c->chk[sl]));
-        if (c->hdone[sl] || !more) break;
-        sl ^= 1;
-    }
+    LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter));
     hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
     LAUNCH_CHECK();
     if (!sync_end) {
@@ -819,7 +879,7 @@ lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typena
     LCS_TRY(read_scalars(c, s));
     res->its = c->hsc->saved_it[scope];
     res->status = c->hsc->saved_status[scope];
-    c->last_its[scope] = res->its;
+    last_its_of(c, scope) = res->its;
     return LCS_OK;
 }
 
@@ -843,7 +903,7 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
     LAUNCH_CHECK();
     LCS_TRY((launch_precond<Op, kPc>(c, A, B, grid, ncol, s)));
     if (check_every < 1) check_every = 1;
-    int flip = 0, next_j = 0;
+    int flip = 0;
     const bool time_ap = c->prof_what == (scope == 1 ? LCS_TIME_LOCAL_AP : LCS_TIME_GLOBAL_AP);
     const bool time_up = c->prof_what == (scope == 1 ? LCS_TIME_LOCAL_UPDATE : LCS_TIME_GLOBAL_UPDATE);
     auto launch_ap = [&](int j) -> lcs_status {
@@ -853,36 +913,20 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
                                   (const real *)pold, pnew, B.q, j, max_iter, tol_base, tol_factor,
                                   c->dsc, (const real *)pupd, (const real *)psgs, pap);
     };
-    // the first chunk is sized from the previous solve of this kind (a
-    // sequence of systems converges in similar iteration counts)
-    int first_chunk = std::max(check_every, c->last_its[scope] - check_every / 2);
-    auto enqueue_chunk = [&](int slot_id) -> lcs_status {
-        const int len = next_j == 0 ? first_chunk : check_every;
-        for (int k = 0; k < len && next_j < max_iter; ++k) {
-            const int j = next_j++;
-            LCS_TRY(launch_ap(j));
-            real *pnew = flip ? B.p0 : B.p1;
-            LCS_TRY(launch_maybe_timed(c, time_up, k_pcg_update<Op, kPc>, grid, s, A, x,
-                                       (const real *)pnew, (const real *)B.q, B.r, B.z, j, c->dsc,
-                                       (const real *)pap, pupd));
-            LCS_TRY((launch_precond<Op, kPc>(c, A, B, grid, ncol, s)));
-            flip ^= 1;
-        }
-        if (next_j >= max_iter) LCS_TRY(launch_ap(next_j));  // final stopping test
-        HIP_TRY(hipMemcpyAsync(&c->hdone[slot_id], &c->dsc->pcg.done, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(c->chk[slot_id], s));
+    // iteration j: q = A p (with the stopping test), the update, the
+    // preconditioner; j == max_iter: the final stopping test alone
+    auto launch_iter = [&](int j) -> lcs_status {
+        LCS_TRY(launch_ap(j));
+        if (j >= max_iter) return LCS_OK;
+        real *pnew = flip ? B.p0 : B.p1;
+        LCS_TRY(launch_maybe_timed(c, time_up, k_pcg_update<Op, kPc>, grid, s, A, x,
+                                   (const real *)pnew, (const real *)B.q, B.r, B.z, j, c->dsc,
+                                   (const real *)pap, pupd));
+        LCS_TRY((launch_precond<Op, kPc>(c, A, B, grid, ncol, s)));
+        flip ^= 1;
         return LCS_OK;
     };
-    LCS_TRY(enqueue_chunk(0));
-    int sl = 0;
-    for (;;) {
-        const bool more = next_j < max_iter;
-        if (more) LCS_TRY(enqueue_chunk(sl ^ 1));
-        HIP_TRY(hipEventSynchronize(c->chk[sl]));
-        if (c->hdone[sl] || !more) break;
-        sl ^= 1;
-    }
+    LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter));
     hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
     LAUNCH_CHECK();
     if (!sync_end) {   // the caller reads saved_it / saved_status later
@@ -893,7 +937,7 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
     LCS_TRY(read_scalars(c, s));
     res->its = c->hsc->saved_it[scope];
     res->status = c->hsc->saved_status[scope];
-    c->last_its[scope] = res->its;
+    last_its_of(c, scope) = res->its;
     return LCS_OK;
 }
 
@@ -971,6 +1015,7 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
         LCS_TRY(get_buf(c, B_S1, n, &B.s1));
         if (scope == 1) {
             PcgResult pr;
+            c->cur_outer = 0;
             LCS_TRY(run_pcg(c, A, ncol, o->precond, rhs, x, x_zero, tol_base, tol_factor,
                             o->max_iter, check, B, s, &pr, scope, false));
             out->its = -1;
@@ -979,6 +1024,7 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
         bool zero = x_zero;
         for (int attempt = 0;; ++attempt) {
             PcgResult pr;
+            c->cur_outer = attempt;
             LCS_TRY(run_pcg(c, A, ncol, o->precond, rhs, x, zero, tol_base, tol_factor,
                             o->max_iter - out->its, check, B, s, &pr, scope, true));
             zero = false;
@@ -1025,6 +1071,7 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
                            (const double *)r64, r32, n, c->dsc);
         LAUNCH_CHECK();
         PcgResult pr;
+        c->cur_outer = outer;
         LCS_TRY(run_pcg(c, A32, ncol, o->precond, (const float *)r32, d32, true,
                         (const double *)nullptr, inner, o->max_iter - out->its, check, B, s, &pr,
                         scope, true));
@@ -1170,12 +1217,13 @@ lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *
     LCS_TRY(get_buf(c, B_STAMP, T.npad, &stamp));
     LCS_TRY(get_buf(c, B_INV, n, &inv));
     LCS_TRY(get_buf(c, B_BLOCKOFF, 2 * kMaxGrid, &blockoff));
+    const bool timed = c->prof_what == LCS_TIME_SCORE;
     if (mode == LCS_MODE_RESIDUAL)
-        hipLaunchKernelGGL((k_score<UOp, 0>), dim3(gs), dim3(kBlock), 0, s, Au, b, x0, score,
-                           slot(c, kPtScore));
+        LCS_TRY(launch_maybe_timed(c, timed, k_score<UOp, 0>, gs, s, Au, b, x0, score,
+                                   slot(c, kPtScore)));
     else
-        hipLaunchKernelGGL((k_score<UOp, 1>), dim3(gs), dim3(kBlock), 0, s, Au, b, x0, score,
-                           slot(c, kPtScore));
+        LCS_TRY(launch_maybe_timed(c, timed, k_score<UOp, 1>, gs, s, Au, b, x0, score,
+                                   slot(c, kPtScore)));
     const int gmark = std::min(flat_grid(T.npad), 512);
     hipLaunchKernelGGL(k_mark, dim3(gmark), dim3(kBlock), 0, s, (const double *)score, stamp, n,
                        T.npad, thresh, theta, eps0, (const double *)slot(c, kPtScore), gs, c->dsc);
@@ -1253,6 +1301,45 @@ struct Timers {
     }
 };
 
+template <class T>
+struct is_pair9 : std::false_type {};
+template <int W>
+struct is_pair9<U9<double, 2, W>> : std::true_type {};
+
+// n_sweeps colour-ordered Gauss-Seidel sweeps on A x = b (Algorithm 1 step
+// 7): one kernel per colour, or, for the nine-point stencil in strips of two
+// cells, one kernel per pair of colours (k_gs_pair9: rows of one parity)
+// through a second buffer.
+template <class UOp>
+lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, int ncol,
+                         int n_sweeps, hipStream_t s) {
+    const bool timed = c->prof_what == LCS_TIME_SMOOTH;
+    if constexpr (is_pair9<UOp>::value) {
+        if (ncol == 4) {
+            double *tmp;
+            LCS_TRY(get_buf(c, B_GSX, (size_t)Au.n, &tmp));
+            const int64_t strips = ((int64_t)Au.nx / 2 + kPairStep - 1) / kPairStep;
+            const int mh = (int)std::max<int64_t>(2, std::min<int64_t>(32, strips * Au.ny / 4096));
+            const int64_t tiles = strips * ((Au.ny + mh - 1) / mh);
+            int grid = (int)std::min<int64_t>(kStreamGrid, (tiles + kWaves - 1) / kWaves);
+            grid = std::max(kXcds, (grid + kXcds - 1) / kXcds * kXcds);
+            for (int sw = 0; sw < n_sweeps; ++sw) {
+                LCS_TRY(launch_maybe_timed(c, timed, k_gs_pair9<UOp>, grid, s, Au, b,
+                                           (const double *)x, tmp, 0, mh));
+                LCS_TRY(launch_maybe_timed(c, timed, k_gs_pair9<UOp>, grid, s, Au, b,
+                                           (const double *)tmp, x, 1, mh));
+            }
+            return LCS_OK;
+        }
+    }
+    const int grid = grid_for(Au, kStreamGrid);
+    for (int sw = 0; sw < n_sweeps; ++sw)
+        for (int col = 0; col < ncol; ++col)
+            LCS_TRY(launch_maybe_timed(c, timed, k_gs_half<UOp, false>, grid, s, Au, b, x, col,
+                                       (const Scalars *)nullptr, (double *)nullptr));
+    return LCS_OK;
+}
+
 // x <- x + d on Omega after solving B d = r^(0)_Omega, then smoothing.
 // r0: r^(0) over the whole grid when the caller already has it, else null.
 template <int W, class SOp, class UOp>
@@ -1287,14 +1374,7 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         LAUNCH_CHECK();
     }
     LCS_TRY(tm.mark(2));
-    if (o->n_smooth > 0) {
-        const int grid = grid_for(Au, kStreamGrid);
-        for (int sw = 0; sw < o->n_smooth; ++sw)
-            for (int col = 0; col < ncol; ++col)
-                hipLaunchKernelGGL((k_gs_half<UOp, false>), dim3(grid), dim3(kBlock), 0, s, Au, b, x,
-                                   col, (const Scalars *)nullptr, (double *)nullptr);
-        LAUNCH_CHECK();
-    }
+    if (o->n_smooth > 0) LCS_TRY(launch_sweeps(c, Au, b, x, ncol, o->n_smooth, s));
     LCS_TRY(tm.mark(3));
     return LCS_OK;
 }
@@ -1317,7 +1397,7 @@ lcs_status set_inv(lcs_ctx *c, const int32_t *idx, int64_t K, int64_t n, int32_t
 lcs_status finish_local(lcs_ctx *c, lcs_stats *st) {
     if (st->its_local >= 0) return LCS_OK;
     st->its_local = c->hsc->saved_it[1];
-    c->last_its[1] = st->its_local;
+    c->last_its[1][0] = st->its_local;
     const int ls = c->hsc->saved_status[1];
     if (ls == kStBreakdown || ls == kStNonFinite) return status_of(ls);
     return LCS_OK;
@@ -1500,6 +1580,8 @@ lcs_status create_ctx(lcs_ctx **out, void *ws, size_t ws_bytes) {
         return cleanup(fail(LCS_ENOMEM, "pinned state"));
     if (hipHostMalloc(&c->hdone, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(LCS_ENOMEM, "pinned flags"));
+    if (hipHostMalloc(&c->hpcg, 2 * sizeof(PcgState), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(LCS_ENOMEM, "pinned PCG state"));
     if (hipHostMalloc(&c->hgm, sizeof(GmState), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(LCS_ENOMEM, "pinned GMRES state"));
     if (hipHostMalloc(&c->hbout, sizeof(BatchOut) * kBoutChunk, hipHostMallocDefault) != hipSuccess)
@@ -1614,6 +1696,7 @@ void lcs_destroy(lcs_ctx *c) {
     }
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hdone) (void)hipHostFree(c->hdone);
+    if (c->hpcg) (void)hipHostFree(c->hpcg);
     if (c->hbout) (void)hipHostFree(c->hbout);
     if (c->hgm) (void)hipHostFree(c->hgm);
     for (auto &e : c->ev)
@@ -1795,13 +1878,9 @@ lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, doubl
     const int ncol = colours_of(A);
     if (ncol == 0) return fail(LCS_EINVAL, "Gauss-Seidel sweeps on a CSR matrix need its colouring");
     return with_ops(c, A, nullptr, vec_ok({b, x}), [&](auto, auto op, auto, auto) -> lcs_status {
-        const int grid = grid_for(op, kStreamGrid);
-        for (int sw = 0; sw < n_sweeps; ++sw)
-            for (int col = 0; col < ncol; ++col)
-                hipLaunchKernelGGL((k_gs_half<decltype(op), false>), dim3(grid), dim3(kBlock), 0, s,
-                                   op, b, x, col, (const Scalars *)nullptr, (double *)nullptr);
-        LAUNCH_CHECK();
+        LCS_TRY(launch_sweeps(c, op, b, x, ncol, n_sweeps, s));
         HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(flush_prof(c));
         return LCS_OK;
     });
 }
@@ -1982,7 +2061,7 @@ lcs_status lcs_solve_local_then_global_batched(lcs_ctx *c, const lcs_matrix *A, 
 
 lcs_status lcs_set_kernel_timing(lcs_ctx *c, int32_t what) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
-    if (what < LCS_TIME_NONE || what > LCS_TIME_GLOBAL_UPDATE) return fail(LCS_EINVAL, "timing class");
+    if (what < LCS_TIME_NONE || what > LCS_TIME_SCORE) return fail(LCS_EINVAL, "timing class");
     c->prof_what = what;
     c->prof_used = 0;
     c->prof_ms = 0.0;

@@ -23,17 +23,22 @@ enum : int32_t {
     kCsrNoDiag = 16,    // a row without its diagonal entry
     kCsrColour = 32,    // a colour >= n_colours, or one colour on both ends of an entry
     kCsrEnds = 64,      // row_ptr[0] != 0 or row_ptr[N] != nnz
-    kCsrEmpty = 128     // a row without entries
+    kCsrEmpty = 128,    // a row without entries
+    kCsrNonFinite = 256,  // a NaN or infinite value
+    kCsrBadDiag = 512     // a diagonal <= 0 (symmetric: not SPD) or == 0 (non-symmetric)
 };
 
-// Structure check and longest row.  flags[0] |= error bits, flags[1] =
-// max(flags[1], longest row); both start at zero.  Reads of col and clr
-// stay inside the ranges the row pointers claim only after those pointers
-// passed their own check.
+// Structure and value check and longest row.  flags[0] |= error bits,
+// flags[1] = max(flags[1], longest row); both start at zero.  Reads of col,
+// val and clr stay inside the ranges the row pointers claim only after those
+// pointers passed their own check.  Every value must be finite, and the
+// diagonal positive (symmetric input, which PCG needs SPD) or nonzero
+// (non-symmetric input, for the Jacobi scaling).
 __global__ __launch_bounds__(kBlock) void k_csr_check(const int32_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ col, int64_t n,
+                                                      const int32_t *__restrict__ col,
+                                                      const double *__restrict__ val, int64_t n,
                                                       int64_t nnz, const uint8_t *__restrict__ clr,
-                                                      int ncol, int32_t *flags) {
+                                                      int ncol, int nonsym, int32_t *flags) {
     int32_t err = 0, longest = 0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
@@ -56,14 +61,21 @@ __global__ __launch_bounds__(kBlock) void k_csr_check(const int32_t *__restrict_
         int64_t prev = -1;
         for (int64_t k = a; k < b; ++k) {
             const int64_t c = col[k];
+            const double v = val[k];
+            const bool finite = fabs(v) <= 1.7976931348623157e308;
+            if (!finite) err |= kCsrNonFinite;
             if (c < 0 || c >= n) {
                 err |= kCsrCol;
                 continue;
             }
             if (c <= prev) err |= kCsrOrder;
             prev = c;
-            if (c == i) diag = true;
-            else if (clr && (int)clr[c] == ci) err |= kCsrColour;
+            if (c == i) {
+                diag = true;
+                if (finite && (nonsym ? v == 0.0 : v <= 0.0)) err |= kCsrBadDiag;
+            } else if (clr && (int)clr[c] == ci) {
+                err |= kCsrColour;
+            }
         }
         if (!diag) err |= kCsrNoDiag;
     }

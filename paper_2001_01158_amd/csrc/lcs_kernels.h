@@ -203,16 +203,21 @@ __global__ __launch_bounds__(kBlock) void k_expand(Op A, const double *__restric
     double v[1] = {0.0};
     for (int64_t j = c.begin + threadIdx.x; j < c.end; j += kBlock) {
         if (stamp[j] != 0) continue;
+        // first the neighbours' stamps alone (the coefficient loads of this
+        // visit are dead and dropped), so that rows away from Omega read no
+        // coefficients
         bool nb = false;
+        A.for_each(j, [&](int64_t l, double) {
+            const int sl = stamp[l];
+            if (l != j && sl != 0 && sl <= m) nb = true;
+        });
+        if (!nb) continue;
         double acc = fabs(r[j]);
         A.for_each(j, [&](int64_t l, double a) {
             const int sl = stamp[l];
-            if (l != j && sl != 0 && sl <= m) {
-                nb = true;
-                acc += fabs(a * x[l]);
-            }
+            if (l != j && sl != 0 && sl <= m) acc += fabs(a * x[l]);
         });
-        if (nb && acc > tau) {
+        if (acc > tau) {
             stamp[j] = (uint8_t)(m + 1);
             v[0] += 1.0;
         }
@@ -743,6 +748,99 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const typename Op::rea
         if (any) A.put(U, z, zo);
     }
     if (kRz) write_partials<real, 1>(v, Ops<0u>(), part_sgs);
+}
+
+// Two colours of the four-colour Gauss-Seidel sweep of the nine-point
+// stencil (colour (x mod 2) + 2 (y mod 2)) in one pass.  The rows of parity p
+// hold colours 2p (x even) and 2p+1 (x odd), and nothing else: rows of one
+// parity never couple to each other, colour 2p reads only the other parity's
+// rows and colour 2p+1 of its own row, and colour 2p+1 reads the new colour
+// 2p of its own row (x - 1, x + 1) and the other parity's rows.  So the
+// sweep over colours 0, 1, 2, 3 is the pass p = 0 then the pass p = 1, with
+// per-cell results identical to four one-colour kernels: the same FMA chain
+// in ascending slot order over the same old and new values.
+//
+// The pass reads x from `in` and writes every row to `out`: rows of parity
+// p with their new values, the other rows copied.  Reading one buffer and
+// writing another keeps the old values of a row that a neighbouring wave
+// may be updating.  A wave owns 63 strips of V = 2 cells of a row (lanes
+// 0..62) and walks up mh rows; lane 63 holds the next strip's first unit,
+// whose new colour-2p value its left neighbour needs, and stores nothing.
+// Per own row a lane loads its row's five coefficient arrays, the three
+// south arrays of the row below, and the rows y and y+1 of x (row y-1 is
+// carried); every array element is read about once per pass.
+constexpr int kPairStep = kWave - 1;
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_gs_pair9(Op A, const double *__restrict__ b,
+                                                     const double *__restrict__ in,
+                                                     double *__restrict__ out, int parity, int mh) {
+    static_assert(Op::V == 2 && Op::NB == 9, "nine-point strips of two cells");
+    constexpr int V = 2;
+    using Unit = typename Op::Unit;
+    const int lane = threadIdx.x % kWave;
+    const int nx = A.nx, ny = A.ny;
+    const int64_t upr = nx / V;
+    const int64_t strips = (upr + kPairStep - 1) / kPairStep;
+    const int64_t tiles = strips * (int64_t)((ny + mh - 1) / mh);
+    for (int64_t t = (int64_t)logical_block() * kWaves + threadIdx.x / kWave; t < tiles;
+         t += (int64_t)gridDim.x * kWaves) {
+        const int64_t strip = t % strips, seg = t / strips;
+        const int64_t xr = strip * kPairStep + lane;
+        const bool active = xr < upr;
+        const bool owner = active && lane < kPairStep;
+        const int xu = (int)(active ? xr : upr - 1);   // lanes past the row end load a valid strip
+        const int x0 = xu * V;
+        const int y0 = (int)seg * mh, y1 = min(ny, y0 + mh);
+        double xs[V + 2], xc[V + 2], xn[V + 2];
+        int y = y0;
+        bool carried = false;
+        if ((y0 & 1) != parity) {   // a leading row of the other parity: copied
+            const int64_t i = (int64_t)y0 * nx + x0;
+            row_load<double, V>(in, i, i, x0, nx, true, true, xs);
+            if (owner) vst<double, V>(out + i, {xs[1], xs[2]});
+            carried = true;
+            ++y;
+        }
+        for (; y < y1; y += 2) {
+            const int64_t i0 = (int64_t)y * nx + x0;
+            if (!carried) row_load<double, V>(in, i0 - nx, i0, x0, nx, y > 0, true, xs);
+            row_load<double, V>(in, i0, i0, x0, nx, true, true, xc);
+            row_load<double, V>(in, i0 + nx, i0, x0, nx, y + 1 < ny, true, xn);
+            if (owner && y + 1 < y1) vst<double, V>(out + i0 + nx, {xn[1], xn[2]});
+            Unit U;
+            A.geom_walk(U, (int64_t)y * upr + xu, xu, y);
+            typename Op::South S;
+            A.south_init(S, U);
+            A.load_row(U, S);
+            double bb[V];
+            vld<double, V>(b + i0, bb);
+            double nv[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                double z[9];
+                z[0] = xs[k]; z[1] = xs[k + 1]; z[2] = xs[k + 2];
+                z[3] = xc[k]; z[4] = xc[k + 1]; z[5] = xc[k + 2];
+                z[6] = xn[k]; z[7] = xn[k + 1]; z[8] = xn[k + 2];
+                if (k == 1) {
+                    z[3] = nv[0];                           // colour 2p at x0, new
+                    z[5] = __shfl_down(nv[0], 1, kWave);    // colour 2p at x0 + 2, new
+                }
+                double acc = bb[k], d = 1.0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    if (!A.valid(U, q, k)) continue;
+                    if (q == Op::kC) d = U.a[q][k];
+                    else acc = fma(-U.a[q][k], z[q], acc);
+                }
+                nv[k] = acc / d;
+            }
+            if (owner) vst<double, V>(out + i0, nv);
+#pragma unroll
+            for (int k = 0; k < V + 2; ++k) xs[k] = xn[k];
+            carried = true;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -39,7 +39,8 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_solve_global_batched", "lcs_solve_local_then_global_batched",
             "lcs_workspace_bytes", "lcs_workspace_bytes_batched", "lcs_create_with_workspace",
             "lcs_build_local_domain_static"]
-TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE = range(5)
+(TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE, TIME_SMOOTH,
+ TIME_SCORE) = range(7)
 
 
 class LcsError(RuntimeError):
@@ -193,10 +194,17 @@ class CsrMatrix:
     val: torch.Tensor                      # float64 [nnz], device
     colour: Optional[torch.Tensor] = None  # uint8 [N], device
     n_colours: int = 0
-    reuse: bool = False   # arrays unchanged since the context last copied them
+    reuse: bool = False   # the arrays stay unchanged between calls: the context may
+                          # keep its checked copy (sent only while the tensors' data
+                          # pointers and versions are those of this context's last call)
     nonsym: bool = False  # not symmetric: solves use GMRES(m)
     kind = CSR
     max_row = 16
+    _seen: dict = dataclasses.field(default_factory=dict, repr=False, compare=False)
+
+    def _signature(self):
+        ts = [self.row_ptr, self.col, self.val] + ([self.colour] if self.colour is not None else [])
+        return tuple((t.data_ptr(), t._version) for t in ts)
 
     @property
     def n(self) -> int:
@@ -206,7 +214,10 @@ class CsrMatrix:
     def device(self) -> torch.device:
         return self.val.device
 
-    def c(self) -> _Matrix:
+    def c(self, ctx_key=None) -> _Matrix:
+        """The C description.  ctx_key: the context the call goes to; csr_reuse
+        is set only if reuse is on and no array was replaced or modified in
+        place (torch's version counter) since this context's previous call."""
         if self.row_ptr.dtype != torch.int32 or self.col.dtype != torch.int32:
             raise ValueError("row_ptr and col must be int32")
         if self.val.dtype != torch.float64 or self.val.numel() != self.col.numel():
@@ -221,7 +232,11 @@ class CsrMatrix:
         m.row_ptr, m.col, m.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
         m.nnz = self.col.numel()
         m.colour, m.n_colours = _ptr(self.colour), int(self.n_colours)
-        m.csr_reuse = 1 if self.reuse else 0
+        sig = self._signature()
+        keep = self.reuse and ctx_key is not None and self._seen.get(ctx_key) == sig
+        if ctx_key is not None:
+            self._seen[ctx_key] = sig
+        m.csr_reuse = 1 if keep else 0
         m.csr_nonsym = 1 if self.nonsym else 0
         return m
 
@@ -316,6 +331,14 @@ def _ctx(ctx):
     return (ctx or default_context()).handle
 
 
+def _mat(A, ctx):
+    """A's C description for a call on ctx (general sparse input tracks, per
+    context, whether its arrays changed since the previous call)."""
+    if isinstance(A, CsrMatrix):
+        return A.c(_ctx(ctx).value)
+    return A.c()
+
+
 def workspace_bytes(A, opts: Options = None) -> int:
     """Bytes of a caller-owned workspace serving every single-system call on
     A with opts (lcs_workspace_bytes; host arithmetic only)."""
@@ -345,7 +368,7 @@ def solve_global(A: Matrix, b: torch.Tensor, x: torch.Tensor, opts: Options = No
     opts = opts or Options()
     st = _Stats()
     o = opts.c()
-    _check(lib().lcs_solve_global(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+    _check(lib().lcs_solve_global(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(b, A.n, name="b"),
                                   _vec(x, A.n, name="x"), ctypes.byref(o), ctypes.byref(st), _stream()))
     return Stats.of(st)
 
@@ -358,7 +381,7 @@ def build_local_domain(A: Matrix, b: torch.Tensor, x0: torch.Tensor, mode: str =
     mask = torch.empty(A.n, dtype=torch.uint8, device=b.device) if want_mask else None
     K = ctypes.c_int64(0)
     st = _Stats()
-    _check(lib().lcs_build_local_domain(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+    _check(lib().lcs_build_local_domain(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(b, A.n, name="b"),
                                         _vec(x0, A.n, name="x0"), _MODES[mode], _THRESH[thresh],
                                         float(theta), int(e_max), _ptr(idx), _ptr(mask),
                                         ctypes.byref(K), ctypes.byref(st), _stream()))
@@ -397,7 +420,7 @@ def solve_local(A: Matrix, b: torch.Tensor, x: torch.Tensor, idx: torch.Tensor,
     idx = idx.contiguous()
     st = _Stats()
     o = opts.c()
-    _check(lib().lcs_solve_local(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+    _check(lib().lcs_solve_local(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(b, A.n, name="b"),
                                  _vec(x, A.n, name="x"), _ptr(idx) if idx.numel() else None,
                                  idx.numel(), ctypes.byref(o), ctypes.byref(st), _stream()))
     return Stats.of(st)
@@ -410,7 +433,7 @@ def solve_local_then_global(A: Matrix, b: torch.Tensor, x: torch.Tensor, mode: s
     opts = opts or Options()
     st = _Stats()
     o = opts.c()
-    _check(lib().lcs_solve_local_then_global(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+    _check(lib().lcs_solve_local_then_global(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(b, A.n, name="b"),
                                              _vec(x, A.n, name="x"), _MODES[mode], _THRESH[thresh],
                                              float(theta), int(e_max), ctypes.byref(o),
                                              ctypes.byref(st), _stream()))
@@ -456,7 +479,7 @@ def solve_global_batched(A: BatchMatrix, b: torch.Tensor, x: torch.Tensor, opts:
     G = A.G
     arr = (_Stats * G)()
     o = opts.c()
-    _check(lib().lcs_solve_global_batched(_ctx(ctx), ctypes.byref(A.c()), G,
+    _check(lib().lcs_solve_global_batched(_ctx(ctx), ctypes.byref(_mat(A, ctx)), G,
                                           _vec(b, G * A.n, name="b"), _vec(x, G * A.n, name="x"),
                                           ctypes.byref(o), arr, _stream()))
     return _batch_stats(arr, G)
@@ -472,7 +495,7 @@ def solve_local_then_global_batched(A: BatchMatrix, b: torch.Tensor, x: torch.Te
     G = A.G
     arr = (_Stats * G)()
     o = opts.c()
-    _check(lib().lcs_solve_local_then_global_batched(_ctx(ctx), ctypes.byref(A.c()), G,
+    _check(lib().lcs_solve_local_then_global_batched(_ctx(ctx), ctypes.byref(_mat(A, ctx)), G,
                                                      _vec(b, G * A.n, name="b"),
                                                      _vec(x, G * A.n, name="x"), _MODES[mode],
                                                      _THRESH[thresh], float(theta), int(e_max),
@@ -485,14 +508,14 @@ def solve_local_then_global_batched(A: BatchMatrix, b: torch.Tensor, x: torch.Te
 # ---------------------------------------------------------------------------
 def residual(A: Matrix, b: torch.Tensor, x: torch.Tensor, ctx: Context = None) -> torch.Tensor:
     r = torch.empty_like(b)
-    _check(lib().lcs_residual(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+    _check(lib().lcs_residual(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(b, A.n, name="b"),
                               _vec(x, A.n, name="x"), _ptr(r), _stream()))
     return r
 
 
 def gradient(A: Matrix, x: torch.Tensor, ctx: Context = None) -> torch.Tensor:
     g = torch.empty_like(x)
-    _check(lib().lcs_gradient(_ctx(ctx), ctypes.byref(A.c()), _vec(x, A.n, name="x"), _ptr(g),
+    _check(lib().lcs_gradient(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(x, A.n, name="x"), _ptr(g),
                               _stream()))
     return g
 
@@ -500,7 +523,7 @@ def gradient(A: Matrix, x: torch.Tensor, ctx: Context = None) -> torch.Tensor:
 def spmv(A: Matrix, x: torch.Tensor, y: torch.Tensor, reps: int = 1, ctx: Context = None):
     prec = PREC_FP64 if x.dtype == torch.float64 else PREC_MIXED
     dt = torch.float64 if prec == PREC_FP64 else torch.float32
-    _check(lib().lcs_spmv(_ctx(ctx), ctypes.byref(A.c()), _vec(x, A.n, dt, "x"), _vec(y, A.n, dt, "y"),
+    _check(lib().lcs_spmv(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(x, A.n, dt, "x"), _vec(y, A.n, dt, "y"),
                           prec, int(reps), _stream()))
     return y
 
@@ -513,21 +536,21 @@ def gather_restricted(A: Matrix, idx: torch.Tensor, ctx: Context = None):
     col = torch.empty(max(A.max_row * K, 1), dtype=torch.int32, device=dev)
     val = torch.empty(max(A.max_row * K, 1), dtype=torch.float64, device=dev)
     nnz = ctypes.c_int64(0)
-    _check(lib().lcs_gather_restricted(_ctx(ctx), ctypes.byref(A.c()),
+    _check(lib().lcs_gather_restricted(_ctx(ctx), ctypes.byref(_mat(A, ctx)),
                                        _ptr(idx.contiguous()) if K else None, K, _ptr(rp), _ptr(col),
                                        _ptr(val), ctypes.byref(nnz), _stream()))
     return rp, col[:nnz.value], val[:nnz.value]
 
 
 def gs_sweeps(A: Matrix, b: torch.Tensor, x: torch.Tensor, n_sweeps: int = 1, ctx: Context = None):
-    _check(lib().lcs_gs_sweeps(_ctx(ctx), ctypes.byref(A.c()), _vec(b, A.n, name="b"),
+    _check(lib().lcs_gs_sweeps(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _vec(b, A.n, name="b"),
                                _vec(x, A.n, name="x"), int(n_sweeps), _stream()))
     return x
 
 
 def cast_coef(A: Matrix, ctx: Context = None) -> torch.Tensor:
     c32 = torch.empty(A.coef.shape, dtype=torch.float32, device=A.coef.device)
-    _check(lib().lcs_cast_coef(_ctx(ctx), ctypes.byref(A.c()), _ptr(c32), _stream()))
+    _check(lib().lcs_cast_coef(_ctx(ctx), ctypes.byref(_mat(A, ctx)), _ptr(c32), _stream()))
     return c32
 
 

@@ -284,6 +284,14 @@ def _bad(kind):
         colour[col[rp[2]]] = colour[2] if col[rp[2]] != 2 else colour[col[rp[2] + 1]]
     elif kind == "colour_range":
         colour[0] = nc
+    elif kind == "nan_value":
+        val[rp[3] + 1] = np.nan
+    elif kind == "inf_value":
+        val[rp[7]] = -np.inf
+    elif kind == "zero_diag":
+        val[rp[4] + int(np.nonzero(col[rp[4]:rp[5]] == 4)[0][0])] = 0.0
+    elif kind == "neg_diag":
+        val[rp[6] + int(np.nonzero(col[rp[6]:rp[7]] == 6)[0][0])] = -2.0
     elif kind == "long_row":
         m = 20
         a = np.eye(m) * 30.0
@@ -296,8 +304,12 @@ def _bad(kind):
 
 
 @pytest.mark.parametrize("kind", ["unsorted", "no_diag", "col_range", "ends", "ptr_order",
-                                  "empty_row", "colour_clash", "colour_range", "long_row"])
+                                  "empty_row", "colour_clash", "colour_range", "long_row",
+                                  "nan_value", "inf_value", "zero_diag", "neg_diag"])
 def test_csr_malformed_structure_rejected(kind, ctx):
+    """Malformed structures and values are refused by the check before any
+    work: LCS_EINVAL, or LCS_ENONFINITE for a NaN / infinite value; x is
+    unchanged."""
     A = _bad(kind)
     say("csr malformed", kind)
     b = dev(np.ones(A.n))
@@ -306,9 +318,28 @@ def test_csr_malformed_structure_rejected(kind, ctx):
     with pytest.raises(lcs.LcsError) as e:
         lcs.solve_local_then_global(A, b, x, "residual", "relmax", 1e-3, 1, lcs.Options(eps=1e-10),
                                     ctx=ctx)
-    assert e.value.status == lcs.EINVAL
+    want = lcs.ENONFINITE if kind in ("nan_value", "inf_value") else lcs.EINVAL
+    assert e.value.status == want
     assert "CSR matrix" in str(e.value)
     assert np.array_equal(host(x), x0)
+
+
+def test_csr_zero_diagonal_of_nonsymmetric_input_rejected(ctx):
+    """Non-symmetric input accepts a negative diagonal but not a zero one
+    (the Jacobi scaling divides by it)."""
+    Ah, _ = irregular(9, 7, 5)
+    val = Ah.val.copy()
+    k4 = Ah.rp[4] + int(np.nonzero(Ah.col[Ah.rp[4]:Ah.rp[5]] == 4)[0][0])
+    for v, ok in ((0.0, False), (-50.0, True)):
+        val[k4] = v
+        A = lcs.CsrMatrix(dev(Ah.rp, torch.int32), dev(Ah.col, torch.int32), dev(val), nonsym=True)
+        y = dev(np.zeros(A.n))
+        if ok:
+            lcs.spmv(A, dev(np.ones(A.n)), y, ctx=ctx)
+        else:
+            with pytest.raises(lcs.LcsError) as e:
+                lcs.spmv(A, dev(np.ones(A.n)), y, ctx=ctx)
+            assert e.value.status == lcs.EINVAL and "zero diagonal" in str(e.value)
 
 
 def test_csr_option_errors_and_context_reuse(ctx):
@@ -390,6 +421,25 @@ def test_csr_streaming_operator_large(ctx):
                                      lcs.Options(eps=1e-10), ctx=ctx)
     assert st.K == d.K
     assert np.linalg.norm(oracle.residual(Ah, b, host(x))) <= 1.0001e-10 * np.linalg.norm(b)
+    # the FP32 instantiation of the streaming operator (mixed precision) and
+    # the colour-ordered SGS preconditioner on it: the domain equals the
+    # oracle's, the criterion holds as the oracle recomputes it, and the
+    # results agree with the FP64 Jacobi solve to within the criterion's reach
+    x64 = host(x)
+    nb = np.linalg.norm(b)
+    for precond in ("jacobi", "rbsgs"):
+        x = dev(x0)
+        st = lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-3, 1,
+                                         lcs.Options(eps=1e-10, precision="mixed", precond=precond),
+                                         ctx=ctx)
+        xg = host(x)
+        rel = np.linalg.norm(oracle.residual(Ah, b, xg)) / nb
+        dif = np.linalg.norm(xg - x64) / np.linalg.norm(x64)
+        say(f"  mixed {precond}: K={st.K} its={st.its_local}+{st.its_global} relres={rel:.1e} "
+            f"vs fp64 {dif:.1e}")
+        assert st.K == d.K
+        assert rel <= 1.0001e-10
+        assert dif <= 1e-9
 
 
 # ---- non-symmetric CSR input: GMRES(m) ----

@@ -115,6 +115,37 @@ def test_gs_sweeps_bitexact(name, ctx):
     assert np.array_equal(host(x), oracle.gs_sweeps(Ah, b, x0, 2))
 
 
+@pytest.mark.parametrize("dims", [(1008, 2001), (264, 67), (128, 64), (132, 5), (4, 9), (8, 1),
+                                  (256, 2)])
+def test_nine_point_paired_sweeps_bitexact(dims, ctx):
+    """The nine-point sweep on strips of two cells runs colours (0, 1) and
+    (2, 3) as two row-parity passes, each wave owning 63 strips plus one halo
+    strip: grids of several strips per row, an odd number of rows per tile
+    (1008 x 2001), a single strip, a single row and two rows give the
+    oracle's colour-ordered sweeps bit for bit, also with a nonzero
+    background, and inside Algorithm 1."""
+    nx, ny = dims
+    coef = W.assemble_9pt(nx, ny, 0.25, 100.0, 30.0)
+    Ah = oracle.csr_from_stencil(W.KIND_9PT, nx, ny, 1, coef)
+    rng = np.random.default_rng(nx + ny)
+    b = rng.random(nx * ny)
+    x0 = rng.random(nx * ny) - 0.5
+    A = lcs.matrix_from_numpy(W.KIND_9PT, nx, ny, 1, coef, DEV)
+    say("paired sweeps", dims)
+    for sweeps in (1, 2):
+        x = dev(x0)
+        lcs.gs_sweeps(A, dev(b), x, sweeps, ctx=ctx)
+        assert np.array_equal(host(x), oracle.gs_sweeps(Ah, b, x0, sweeps)), sweeps
+    if nx * ny >= 64:
+        # steps 3-7 of Algorithm 1: two local PCG iterations, then the sweep
+        d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-2, oracle.TH_RELMAX, 1)
+        x = dev(x0)
+        lcs.solve_local(A, dev(b), x, torch.as_tensor(d.idx).to(DEV),
+                        lcs.Options(eps=1e-10, max_iter=2, check_every=1), ctx=ctx)
+        xo, _ = oracle.solve_local(Ah, b, x0, d.idx, oracle.Options(eps=1e-10, max_iter=2))
+        assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv_fp64(name, ctx):
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
