@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # Valid only while the kernel sources hash to src_sha256; otherwise the
 # roofline reports traffic null.
 MEASURED_TRAFFIC = {
-    "c2": {"ratio": 1.142, "kernel": "k_cg_iter<UEll<double,5>,1>",
-           "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
-           "src_sha256": "c9d8c854e7bdcbd20397fde8f361aa5f6f5c88a1df77dab53006d667df51b507"},
+    "k_cg_iter<UEll<double,5>,1>": {
+        "ratio": 1.142, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
+        "src_sha256": "c9d8c854e7bdcbd20397fde8f361aa5f6f5c88a1df77dab53006d667df51b507"},
 }
 KERNEL_SOURCES = ["paper_2001_01158_amd/csrc/lcs_device.h", "paper_2001_01158_amd/csrc/lcs_kernels.h"]
 
@@ -59,7 +59,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=40)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", choices=["c2", "c3", "c5", "c6"], default="c2")
+    p.add_argument("--workload", choices=["c2", "c3", "c5", "c6"], default="c3")
+    p.add_argument("--no-extra", action="store_true",
+                   help="with the 4096^2 workload, skip the 1024^2 legs reported beside it")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--precond", choices=["jacobi", "rbsgs", "none"],
                    help="replace the workload's preconditioner (rbsgs: colour-ordered symmetric "
@@ -93,6 +95,10 @@ def parse():
     p.add_argument("--summarize", metavar="DIR",
                    help="print a summary of rocprofv3 output under DIR (trace/, fetch/, write/) "
                         "and exit; no GPU needed")
+    p.add_argument("--kernel", default="k_cg_iter<UEll<float, 9>, 1>",
+                   help="--summarize: the kernel (name prefix, as the profiler prints it)")
+    p.add_argument("--mark", default="k_score<U9<double, 2, 2>, 0>",
+                   help="--summarize: the kernel launched once at the start of each system")
     return p.parse_args()
 
 
@@ -110,7 +116,7 @@ def make_workload(name):
                 "domain (paper threshold eps||b||/sqrt(N), E_max=1), Jacobi-PCG, eps=1e-10")
         src = lambda k: W.disk_source(w.nx, w.ny, w.nx / 4.0 + 4.0 * k, w.ny / 2.0, 40.0, 1.0)
     elif name == "c3":
-        w = W.c3_aniso_front(n_systems=12)
+        w = W.c3_aniso_front(n_systems=20)
         opts = dict(precond="jacobi", precision="mixed")
         desc = ("2D 4096x4096 9-point anisotropic (ratio 100, 30 deg), moving disk radius 350, "
                 "FP32 inner Jacobi-PCG + FP64 refinement to 1e-10; Algorithm 1, paper threshold")
@@ -123,7 +129,7 @@ def make_workload(name):
                 "FP64; Algorithm 1, paper threshold")
         src = lambda k: W.disk_source(w.nx, w.ny, w.nx / 4.0 + 4.0 * k, w.ny / 2.0, 40.0, 1.0)
     else:
-        w = W.c5_sphere3d(n_systems=12)
+        w = W.c5_sphere3d()
         opts = dict(precond="rbsgs", precision="mixed")
         desc = ("3D 256^3 7-point, sigma=1.5 log-normal conductivity, ball radius 20 moving 2 "
                 "cells/system, FP32 inner RB-SGS PCG + FP64 refinement to 1e-10; Algorithm 1, "
@@ -133,12 +139,16 @@ def make_workload(name):
     return w, opts, desc, src
 
 
-def summarize(d: str, steps: int):
-    """Markdown summary of rocprofv3 output: kernel statistics of the traced
-    run, the dominant local-PCG kernel over the timed pass only (the last
-    `steps` residual-mode solves, each of which starts with one k_score<., 0>
-    dispatch), and its FETCH_SIZE / WRITE_SIZE traffic per dispatch scaled by
-    the 512 MiB copy calibration."""
+def summarize(d: str, steps: int, warmup: int, kernel: str, mark: str):
+    """Markdown summary of rocprofv3 output under d (trace/, fetch/, write/
+    as written by the commands in profiles/): the kernel statistics of the
+    traced run, and for the kernel whose name starts with `kernel` its
+    dispatches over the first leg's timed pass (systems warmup ..
+    warmup + steps - 1 of the run, each of which starts with one dispatch
+    whose name starts with `mark`), with its FETCH_SIZE / WRITE_SIZE traffic
+    per working dispatch scaled by the 512 MiB copy calibration.  Dispatches
+    that exit at once after convergence (traffic under 1 % of the largest)
+    are counted apart."""
     import csv
     import glob
 
@@ -146,94 +156,72 @@ def summarize(d: str, steps: int):
         f = sorted(glob.glob(os.path.join(d, pattern)))
         return list(csv.DictReader(open(f[0]))) if f else []
 
-    import re
-    dom = "void lcs::k_cg_iter<lcs::UEll<double, 5>, 1>"
-    start_mark = re.compile(r"void lcs::k_score<lcs::U5<double, 2(, \d)?>, 0>")
-    short = lambda name: name.split("(")[0].replace("void ", "", 1)
+    short = lambda name: name.split("(")[0].replace("void ", "", 1).replace("lcs::", "")
     out = []
     stats = rows("trace/*kernel_stats.csv")
     if stats:
         out.append("| kernel | calls | avg us | total ms | % |")
         out.append("|---|---|---|---|---|")
-        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
             out.append(f"| `{short(r['Name'])}` | {r['Calls']} | "
                        f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                        f"{float(r['Percentage']):.1f} |")
+    is_k = lambda name: short(name).startswith(kernel)
+    is_m = lambda name: short(name).startswith(mark)
 
     def window(recs, name_key, ts_key):
-        marks = [int(r[ts_key]) for r in recs if start_mark.match(r[name_key])]
-        if steps <= 0 or len(marks) < steps:
+        marks = sorted(int(r[ts_key]) for r in recs if is_m(r[name_key]))
+        if steps <= 0 or len(marks) < warmup + steps:
             return []
-        t0 = sorted(marks)[-steps]
-        return [r for r in recs if r[name_key].startswith(dom) and int(r[ts_key]) >= t0]
+        t0 = marks[warmup]
+        t1 = marks[warmup + steps] if len(marks) > warmup + steps else float("inf")
+        return [r for r in recs if is_k(r[name_key]) and t0 <= int(r[ts_key]) < t1]
 
     trace = rows("trace/*kernel_trace.csv")
     if trace:
-        allk = [r for r in trace if r["Kernel_Name"].startswith(dom)]
+        dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        allk = [r for r in trace if is_k(r["Kernel_Name"])]
         win = window(trace, "Kernel_Name", "Start_Timestamp")
-        dur = lambda rs: sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rs) / max(len(rs), 1) / 1e3
         if allk:
             out.append("")
-            line = f"`{short(dom)}`: whole run {len(allk)} dispatches, avg {dur(allk):.2f} us"
-            if steps > 0:
-                line = (f"dominant kernel {line}; timed pass (last {steps} residual-mode systems) "
-                        f"{len(win)} dispatches, avg {dur(win):.2f} us")
-            out.append(line)
-        # batched launches, split by the number of systems (one workgroup each)
-        by = {}
-        for r in trace:
-            if "k_batch_solve" in r["Kernel_Name"]:
-                g = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
-                by.setdefault((short(r["Kernel_Name"]), g), []).append(
-                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-        if by:
-            out.append("")
-            out.append("| batched kernel | systems per launch | launches | median us | min us | max us |")
-            out.append("|---|---|---|---|---|---|")
-            for (name, g), ds in sorted(by.items(), key=lambda kv: (-kv[0][1], kv[0][0])):
-                out.append(f"| `{name}` | {g} | {len(ds)} | {np.median(ds):.1f} | {min(ds):.1f} | "
-                           f"{max(ds):.1f} |")
+            out.append(f"`{kernel}`: whole run {len(allk)} dispatches, avg "
+                       f"{sum(map(dur, allk)) / len(allk):.2f} us")
+            if win:
+                out.append(f"first leg's timed pass ({steps} systems): {len(win)} dispatches, avg "
+                           f"{sum(map(dur, win)) / len(win):.2f} us, total "
+                           f"{sum(map(dur, win)) / 1e3:.3f} ms ({sum(map(dur, win)) / 1e3 / steps:.3f} ms "
+                           f"per system)")
     fetch, write = rows("fetch/*counter_collection.csv"), rows("write/*counter_collection.csv")
     if fetch and write:
         copy = lambda rs: max(float(r["Counter_Value"]) for r in rs if "copyBuffer" in r["Kernel_Name"])
         f_fetch = 512 * 1024 / copy(fetch)
         f_write = 512 * 1024 / copy(write)
+        out.append("")
+        out.append(f"calibration (512 MiB device copy): FETCH_SIZE x{f_fetch:.3f}, WRITE_SIZE x{f_write:.3f}")
         wf = window(fetch, "Kernel_Name", "Start_Timestamp")
         ww = window(write, "Kernel_Name", "Start_Timestamp")
-        kib_f = sum(float(r["Counter_Value"]) for r in wf) / max(len(wf), 1)
-        kib_w = sum(float(r["Counter_Value"]) for r in ww) / max(len(ww), 1)
-        traffic = (kib_f * f_fetch + kib_w * f_write) * 1024
-        out.append("")
-        out.append(f"calibration (512 MiB copy): FETCH_SIZE x{f_fetch:.3f}, WRITE_SIZE x{f_write:.3f}")
-        out.append(f"dominant kernel over the timed pass: {len(wf)} / {len(ww)} dispatches, "
-                   f"FETCH {kib_f:.1f} KiB, WRITE {kib_w:.1f} KiB per dispatch -> "
-                   f"{traffic / 1e6:.3f} MB per dispatch (calibrated)")
-        spm = "void lcs::k_spmv<lcs::U9<float, 4, 2> >"
-        sf = [float(r["Counter_Value"]) for r in fetch if r["Kernel_Name"].startswith(spm)]
-        sw = [float(r["Counter_Value"]) for r in write if r["Kernel_Name"].startswith(spm)]
-        if sf and sw:
-            t = (sum(sf) / len(sf) * f_fetch + sum(sw) / len(sw) * f_write) * 1024
-            alg = 4096 * 4096 * 28
-            out.append(f"`{short(spm)}` (4096^2, FP32): {len(sf)} dispatches, {t / 1e6:.1f} MB per dispatch "
-                       f"(calibrated) vs {alg / 1e6:.1f} MB algorithmic -> ratio {t / alg:.3f}")
-        # the 4096^2 five-point product of CSR input (bench.py --csr): the
-        # streaming ELL operator (the larger of the sizes the ELL SpMV runs on)
-        spe = "void lcs::k_spmv<lcs::UEllStream<double, 5> >"
-        ef = [float(r["Counter_Value"]) for r in fetch if r["Kernel_Name"].startswith(spe)]
-        ew = [float(r["Counter_Value"]) for r in write if r["Kernel_Name"].startswith(spe)]
-        if ef and ew:
-            big_f = [v for v in ef if v > max(ef) / 2]
-            big_w = [v for v in ew if v > max(ew) / 2]
-            t = (sum(big_f) / len(big_f) * f_fetch + sum(big_w) / len(big_w) * f_write) * 1024
-            alg = 4096 * 4096 * 76
-            out.append(f"`{short(spe)}` (4096^2 CSR input, FP64): {len(big_f)} / {len(big_w)} dispatches, "
-                       f"{t / 1e6:.1f} MB per dispatch (calibrated) vs {alg / 1e6:.1f} MB algorithmic "
-                       f"(76 B per row) -> ratio {t / alg:.3f}")
-        bj = os.path.join(d, "fetch_bench.json")
-        if os.path.exists(bj):
-            bpl = json.load(open(bj))["roofline"]["bytes_per_launch"]
-            out.append(f"algorithmic bytes per launch in that run: {bpl / 1e6:.3f} MB -> "
-                       f"traffic / algorithmic = {traffic / bpl:.3f}")
+        if wf and ww:
+            big = max(float(r["Counter_Value"]) for r in wf)
+            work_f = [float(r["Counter_Value"]) for r in wf if float(r["Counter_Value"]) > 0.01 * big]
+            bigw = max(float(r["Counter_Value"]) for r in ww)
+            work_w = [float(r["Counter_Value"]) for r in ww if float(r["Counter_Value"]) > 0.01 * bigw]
+            kib_f = sum(work_f) / max(len(work_f), 1)
+            kib_w = sum(work_w) / max(len(work_w), 1)
+            traffic = (kib_f * f_fetch + kib_w * f_write) * 1024
+            out.append(f"`{kernel}` over the first leg's timed pass: {len(wf)} dispatches, of which "
+                       f"{len(work_f)} did work (the others exit at once after convergence); per working "
+                       f"dispatch FETCH {kib_f:.1f} KiB, WRITE {kib_w:.1f} KiB -> "
+                       f"{traffic / 1e6:.3f} MB (calibrated)")
+            bj = os.path.join(d, "fetch_bench.json")
+            if os.path.exists(bj):
+                roof = json.load(open(bj))["roofline"]
+                cands = [roof] + roof.get("other_kernels", [])
+                for c in cands:
+                    if c["kernel"].replace(" ", "") == kernel.replace(" ", "") and c.get("working_launches"):
+                        per_work = c["bytes_per_launch"] * c["launches"] / c["working_launches"]
+                        out.append(f"algorithmic bytes per working dispatch in that run: "
+                                   f"{per_work / 1e6:.3f} MB -> traffic / algorithmic = "
+                                   f"{traffic / per_work:.3f}")
     print("\n".join(out))
 
 
@@ -353,6 +341,17 @@ def param_sweep(workload: str, steps: int):
         rows.append((str(e_max), leg(lambda k: lcs.solve_local_then_global(
             A, Bs[k], x, "residual", "paper", opts.eps, e_max, opts, ctx=ctx))))
     table("residual (paper threshold), E_max", rows)
+    rows = []
+    for f in (1.0, 0.3, 0.1, 0.03, 0.01, 1e-3):
+        rows.append((f"{f:g} eps", leg(lambda k: lcs.solve_local_then_global(
+            A, Bs[k], x, "residual", "paper", f * opts.eps, 1, opts, ctx=ctx))))
+    table("residual, tau = theta ||b|| / sqrt(N), E_max = 1, theta", rows)
+    rows = []
+    for e in range(3, 14):
+        theta = 10.0 ** (-e)
+        rows.append((f"{theta:.0e}", leg(lambda k: lcs.solve_local_then_global(
+            A, Bs[k], x, "residual", "relmax", theta, 1, opts, ctx=ctx))))
+    table("residual, tau = theta max|r0|, E_max = 1, theta", rows)
 
 
 def csr_from_nine_point(coef, nx: int, ny: int):
@@ -728,6 +727,482 @@ def mg_run(reps: int, nonsym: bool = False):
     print()
 
 
+# Threshold of the benchmark's residual domain (Algorithm 3): the paper's
+# tau = theta ||b||_2 / sqrt(N) with theta = THETA_FACTOR * eps.  With the
+# paper's theta = eps, the cells just outside the domain are left, after the
+# local solve, with a residual (their coupling to the correction, -E d) of
+# two to five times the whole budget eps ||b|| on the 4096^2 nine-point and
+# 256^3 seven-point sequences, so every system needed a global finish; a
+# tenth of it adds 1-20 % cells and x~ meets the criterion.  The paper's own
+# theta = eps is timed as a second leg.
+THETA_FACTOR = 0.1
+
+
+def cpu_info() -> dict:
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def leg_table(workload: str, eps: float):
+    """The timed legs: key -> (description, mode, thresh, theta, e_max, precision
+    override or None, global?)."""
+    legs = {
+        "local": ("Algorithm 1, residual domain (Algorithm 3), tau = 0.1 eps ||b|| / sqrt(N), "
+                  "E_max = 1", "residual", "paper", THETA_FACTOR * eps, 1, None, False),
+        "local_paper_theta": ("Algorithm 1, residual domain with the paper's tau = eps ||b|| / "
+                              "sqrt(N), E_max = 1", "residual", "paper", eps, 1, None, False),
+        "global": ("global PCG from x_(k-1) (the baseline)", None, None, None, None, None, True),
+        "local_gradient": ("Algorithm 1, gradient domain (Algorithm 2), alpha = 1e-4",
+                           "gradient", "relmax", 1e-4, 0, None, False),
+        "local_relmax": ("Algorithm 1, residual domain, tau = 1e-3 max|r0|", "residual", "relmax",
+                         1e-3, 1, None, False),
+    }
+    if workload in ("c3", "c5"):   # the same sequence with FP64 inner solves
+        legs["local_fp64"] = ("Algorithm 1 as 'local', FP64 inner PCG", "residual", "paper",
+                              THETA_FACTOR * eps, 1, "fp64", False)
+        legs["global_fp64"] = ("global PCG, FP64", None, None, None, None, "fp64", True)
+    return legs
+
+
+def solve_leg(lcs, leg, A, b, x, opts, ctx):
+    _, mode, thresh, theta, e_max, prec, glob = leg
+    o = opts if prec is None else lcs.Options(**{**opts.__dict__, "precision": prec})
+    if glob:
+        return lcs.solve_global(A, b, x, o, ctx=ctx)
+    return lcs.solve_local_then_global(A, b, x, mode, thresh, theta, e_max, o, ctx=ctx)
+
+
+def leg_summary(sts, n):
+    return {"K_mean": float(np.mean([s.K for s in sts])),
+            "eta_mean": float(np.mean([s.K for s in sts]) / n),
+            "its_local_mean": float(np.mean([s.its_local for s in sts])),
+            "its_global_mean": float(np.mean([s.its_global for s in sts])),
+            "relres_final_max": float(np.max([s.relres_final for s in sts])),
+            "global_finish_fraction": float(np.mean([s.its_global > 0 for s in sts])),
+            "ms_construct_mean": float(np.mean([s.ms_construct for s in sts])),
+            "ms_local_mean": float(np.mean([s.ms_local for s in sts])),
+            "ms_smooth_mean": float(np.mean([s.ms_smooth for s in sts])),
+            "ms_global_mean": float(np.mean([s.ms_global for s in sts]))}
+
+
+def oracle_baseline(w, okw, eps, X, Bs, gpu_x, systems, serial_global_systems, log_each=True):
+    """The oracle (serial FP64 C, and its OpenMP build on all host cores) on
+    the given systems of the sequence, from the GPU's x_(k-1): Algorithm 1
+    with the benchmark's threshold and the global PCG, timed; and each GPU
+    result's error against the oracle's solution of the same system,
+    ||x_gpu - x_oracle||_2 / ||x_oracle||_2, with the criterion recomputed by
+    the oracle.  gpu_x[leg][k]: host copies of the GPU solutions."""
+    import oracle
+    t0 = time.perf_counter()
+    Ah = oracle.csr_from_stencil(w.kind, w.nx, w.ny, w.nz, w.coef)
+    log(f"oracle CSR built in {time.perf_counter() - t0:.1f} s")
+    pc = oracle.PC_SGS if okw["precond"] == "rbsgs" else oracle.PC_JACOBI
+    oo = oracle.Options(eps=eps, pc=pc)
+    res = {"serial": {"local_s": [], "global_s": []}, "omp": {"local_s": [], "global_s": []}}
+    xo = {}
+    try:
+        for par in (False, True):
+            oracle.set_parallel(par)
+            key = "omp" if par else "serial"
+            res[key]["threads"] = oracle.threads()
+            for k in systems:
+                b = Bs[k].cpu().numpy()
+                x0 = X[k].cpu().numpy()
+                t = time.perf_counter()
+                xl, sl, _ = oracle.local_then_global(Ah, b, x0, oracle.MODE_RESIDUAL,
+                                                     THETA_FACTOR * eps, oracle.TH_PAPER, 1, oo)
+                res[key]["local_s"].append(time.perf_counter() - t)
+                xo[("local", k)] = xl
+                if log_each:
+                    log(f"oracle {key} system {k}: Algorithm 1 {res[key]['local_s'][-1]:.2f} s "
+                        f"(K {sl.K}, its {sl.its_local}+{sl.its_global})")
+                if par or k in serial_global_systems:
+                    t = time.perf_counter()
+                    xg, sg = oracle.solve_global(Ah, b, x0, oo)
+                    res[key]["global_s"].append(time.perf_counter() - t)
+                    xo[("global", k)] = xg
+                    if log_each:
+                        log(f"oracle {key} system {k}: global {res[key]['global_s'][-1]:.2f} s "
+                            f"(its {sg.its_global})")
+    finally:
+        oracle.set_parallel(False)
+    errs = {}
+    for leg, xs in gpu_x.items():
+        ref = "global" if leg.startswith("global") else "local"
+        per = []
+        for k in systems:
+            xr = xo[(ref, k)]
+            xg = xs[k]
+            rr = float(np.linalg.norm(oracle.residual(Ah, Bs[k].cpu().numpy(), xg)) /
+                       np.linalg.norm(Bs[k].cpu().numpy()))
+            per.append({"system": k, "err_vs_oracle": float(np.linalg.norm(xg - xr) / np.linalg.norm(xr)),
+                        "relres_by_oracle": rr})
+        errs[leg] = per
+    return res, errs
+
+
+EMPTY_LAUNCH_US = 2.45   # an empty kernel launched back to back on one queue (measured)
+
+
+def dominant_kernel_roofline(args, w, okw, lcs, W, ctx, rerun):
+    """Roofline of the dominant kernel of the timed step.  The timed pass is
+    re-run once per candidate kernel with that kernel's launches bracketed
+    by HIP events on the solve's stream (lcs_set_kernel_timing); the
+    candidate with the largest summed duration is the dominant one.
+    achieved = its algorithmic bytes per launch / its average launch
+    duration."""
+    cands = DOMINANT.get(args.workload)
+    if cands is None or args.csr or w.kind == W.KIND_9N:
+        return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "note": "GMRES / CSR input: see the rocprofv3 kernel trace"}
+    rows = []
+    for kern in cands:
+        lcs.set_kernel_timing(kern["class"], ctx=ctx)
+        _, st_t = rerun()
+        k_ms, k_launches = lcs.get_kernel_timing(ctx=ctx)
+        lcs.set_kernel_timing(lcs.TIME_NONE, ctx=ctx)
+        bytes_total = kern["units"](w, st_t) * kern["bytes_per_row"]
+        achieved = bytes_total / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
+        bpl = bytes_total / max(k_launches, 1)
+        mt = MEASURED_TRAFFIC.get(kern["name"])
+        traffic = None
+        if mt and mt["src_sha256"] == kernel_sources_sha256():
+            traffic = mt["ratio"] * bpl
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                "traffic_unit": "bytes per launch", "traffic_ratio": mt["ratio"] if traffic else None,
+                "kernel": kern["name"], "what": kern["what"],
+                "ms_per_system": k_ms / max(len(st_t), 1),
+                "avg_launch_us": k_ms * 1e3 / max(k_launches, 1), "launches": k_launches,
+                "working_launches": kern["launches"](w, st_t), "bytes_per_launch": bpl,
+                "bytes_per_row": kern["bytes_per_row"]}
+        if kern.get("latency"):
+            its = sum(s.its_local for s in st_t)
+            roof["us_per_iteration"] = k_ms * 1e3 / max(its, 1)
+            roof["empty_launch_floor_us"] = EMPTY_LAUNCH_US
+            roof["launches_per_useful_iteration"] = k_launches / max(its, 1)
+        log(f"kernel {kern['name']}: {k_launches} launches, {roof['ms_per_system']:.3f} ms per "
+            f"system, avg {roof['avg_launch_us']:.2f} us, {achieved or 0:.0f} GB/s")
+        rows.append(roof)
+    rows.sort(key=lambda r: -r["ms_per_system"])
+    top = dict(rows[0])
+    top["other_kernels"] = rows[1:]
+    return top
+
+
+def c2_extra(args):
+    """The 1024^2 five-point FP64 sequence timed alongside the headline: ms
+    per system of Algorithm 1 and of the global PCG, and its local PCG
+    kernel, which is latency-bound (us per iteration against an empty
+    launch)."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence("c2")
+    x = torch.empty(w.n, dtype=torch.float64, device="cuda:0")
+    legs = leg_table("c2", opts.eps)
+
+    def run(key, steps, warm):
+        stats = []
+        for s in range(warm + steps):
+            if s == warm:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            k = s % w.n_systems
+            x.copy_(X[k])
+            st = solve_leg(lcs, legs[key], A, Bs[k], x, opts, ctx)
+            if s >= warm:
+                stats.append(st)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, stats
+
+    out = {"workload": desc}
+    for key in ("local", "local_paper_theta", "global"):
+        ms, sts = run(key, args.steps, max(2, args.warmup))
+        out[key] = {"ms_per_system": ms, **leg_summary(sts, w.n)}
+        log(f"c2 {key}: {ms:.3f} ms/system")
+    out["speedup_vs_global"] = out["global"]["ms_per_system"] / out["local"]["ms_per_system"]
+    a = argparse.Namespace(**{**vars(args), "workload": "c2"})
+    out["local_pcg_kernel"] = dominant_kernel_roofline(a, w, okw, lcs, W, ctx,
+                                                       lambda: run("local", args.steps, 0))
+    del A, X, Bs
+    ctx.close()
+    return out
+
+
+# Candidates for the dominant kernel of each workload's timed step (the
+# rocprofv3 kernel statistics of the step name them), their event-timing
+# classes and algorithmic bytes per row.
+def _dominant():
+    from paper_2001_01158_amd import lcs
+    ell = lambda W_, real_b: W_ * (4 + real_b) + 11 * real_b   # one single-sync PCG iteration on B
+    local_rows = lambda w, sts: float(sum(s.K * s.its_local for s in sts))
+    local_its = lambda w, sts: int(sum(s.its_local for s in sts))
+    grid_rows = lambda per: (lambda w, sts: float(w.n * per * sum(1 for s in sts if s.K > 0)))
+    grid_launches = lambda per: (lambda w, sts: per * sum(1 for s in sts if s.K > 0))
+    local = lambda name, W_, real_b: {
+        "class": lcs.TIME_LOCAL_AP, "name": name, "bytes_per_row": ell(W_, real_b),
+        "what": "local Jacobi-PCG iteration on B (one launch per iteration)",
+        "units": local_rows, "launches": local_its, "latency": True}
+    return {
+        "c2": [local("k_cg_iter<UEll<double,5>,1>", 5, 8)],
+        "c3": [local("k_cg_iter<UEll<float,9>,1>", 9, 4),
+               # per pass: rows of one parity read C, E, N, NE, NW and b (48 B),
+               # the others their south faces N, NE, NW (24 B); every row reads
+               # and writes x (16 B)
+               {"class": lcs.TIME_SMOOTH, "name": "k_gs_pair9<U9<double,2,2>>",
+                "what": "four-colour Gauss-Seidel sweep of Algorithm 1 step 7, two colours per pass",
+                "bytes_per_row": 52, "units": grid_rows(2), "launches": grid_launches(2)},
+               {"class": lcs.TIME_SCORE, "name": "k_score<U9<double,2,2>,0>",
+                "what": "r0 = b - A x0 with its norms (Algorithm 3's score)",
+                "bytes_per_row": 64, "units": grid_rows(1), "launches": grid_launches(1)}],
+    }
+
+
+class _Lazy(dict):
+    def get(self, k, d=None):
+        if not self:
+            self.update(_dominant())
+        return dict.get(self, k, d)
+
+
+DOMINANT = _Lazy()
+
+
+def run_benchmark(args):
+    """Time the workload's legs (inputs resident in HBM), the dominant
+    kernel with HIP events, the SpMV rate, the oracle on the host, and each
+    result's error against the oracle.  Returns the JSON record."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+
+    dev = "cuda:0"
+    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload, args.precond, args.csr)
+    n = w.n
+    stream = torch.cuda.current_stream()
+    eps = opts.eps
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    legs = leg_table(args.workload, eps)
+
+    def run_leg(key: str, steps: int, warm: int, record=None):
+        stats = []
+        for s in range(warm):
+            k = s % w.n_systems
+            x.copy_(X[k])
+            solve_leg(lcs, legs[key], A, Bs[k], x, opts, ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            k = s % w.n_systems
+            x.copy_(X[k])
+            stats.append(solve_leg(lcs, legs[key], A, Bs[k], x, opts, ctx))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, stats
+
+    # ---- timed legs ----
+    ms, sts = {}, {}
+    for key in legs:
+        ms[key], sts[key] = run_leg(key, args.steps, args.warmup if key == "local" else
+                                    max(2, args.warmup // 2))
+        log(f"{key}: {ms[key]:.3f} ms/system ({legs[key][0]})")
+    # one JSON line per system of the two headline legs (stderr)
+    for key in ("local", "global"):
+        for s_i, st in enumerate(sts[key]):
+            print(json.dumps({"leg": key, "system": s_i % w.n_systems, "K": st.K,
+                              "e_rounds": st.e_rounds, "its_local": st.its_local,
+                              "its_global": st.its_global, "relres_after_local": st.relres_after_local,
+                              "relres_final": st.relres_final, "ms_construct": st.ms_construct,
+                              "ms_local": st.ms_local, "ms_smooth": st.ms_smooth,
+                              "ms_global": st.ms_global}), file=sys.stderr, flush=True)
+
+    # ---- dominant kernel of the timed step, timed with HIP events ----
+    roof = dominant_kernel_roofline(args, w, okw, lcs, W, ctx, lambda: run_leg("local", args.steps, 0))
+
+    # ---- SpMV GB/s ----
+    def time_spmv(M, xx, yy, reps=50):
+        lcs.spmv(M, xx, yy, reps=5, ctx=ctx)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lcs.spmv(M, xx, yy, reps=reps, ctx=ctx)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    spmv = {}
+    nb_row = {W.KIND_5PT: 40, W.KIND_9PT: 56, W.KIND_7PT: 48, W.KIND_9N: 88}[w.kind]
+    xs = torch.rand(n, dtype=torch.float64, device=dev)
+    ys = torch.empty_like(xs)
+    t_ms = time_spmv(A, xs, ys)
+    big = n * (nb_row + 6 * 8) > 256 * 2 ** 20
+    spmv[f"{args.workload}_fp64"] = {"n": n, "us": t_ms * 1e3, "GBs": n * nb_row / t_ms / 1e6,
+                                     "bytes_per_row": nb_row,
+                                     "where": "HBM" if big else "cache-resident (not an HBM rate)"}
+    if not args.csr and okw["precision"] == "mixed":
+        x32 = torch.rand(n, dtype=torch.float32, device=dev)
+        y32 = torch.empty_like(x32)
+        t_ms = time_spmv(A, x32, y32)
+        nb32 = {W.KIND_9PT: 28, W.KIND_7PT: 24, W.KIND_5PT: 20}[w.kind]
+        spmv[f"{args.workload}_fp32"] = {"n": n, "us": t_ms * 1e3, "GBs": n * nb32 / t_ms / 1e6,
+                                         "bytes_per_row": nb32,
+                                         "frac_of_8TBs": n * nb32 / t_ms / 1e6 / HBM_PEAK_GBS,
+                                         "where": "HBM"}
+        del x32, y32
+    del xs, ys
+    if args.calib_copy:
+        src_t = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev)   # 512 MiB
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+
+    # ---- the oracle on the host, and each result's error against it ----
+    cpu, errs = None, None
+    if not args.no_cpu and not args.csr and w.kind != W.KIND_9N:
+        big_grid = n > 4_000_000
+        systems = [1, 2] if big_grid else list(range(1, min(6, w.n_systems)))
+        check_legs = [k for k in ("local", "global", "local_fp64", "global_fp64") if k in legs]
+        gpu_x = {k: {} for k in check_legs}
+        for k in systems:
+            for key in check_legs:
+                x.copy_(X[k])
+                solve_leg(lcs, legs[key], A, Bs[k], x, opts, ctx)
+                gpu_x[key][k] = x.cpu().numpy()
+        res, errs = oracle_baseline(w, okw, eps, X, Bs, gpu_x, systems,
+                                    [systems[0]] if big_grid else systems)
+        info = cpu_info()
+        omp, ser = res["omp"], res["serial"]
+        cpu = {"value": 1e3 * float(np.mean(omp["local_s"])), "unit": "ms per system",
+               "cores": omp["threads"], "kind": "oracle",
+               "sample": (f"systems {systems} of the same sequence from the GPU's x_(k-1): the "
+                          f"oracle's Algorithm 1 (same threshold) and global Jacobi-PCG in FP64, "
+                          f"OpenMP build of its row loops on {omp['threads']} threads (value) and the "
+                          f"serial build"),
+               "global_ms_per_system": 1e3 * float(np.mean(omp["global_s"])),
+               "serial": {"local_ms_per_system": 1e3 * float(np.mean(ser["local_s"])),
+                          "global_ms_per_system": 1e3 * float(np.mean(ser["global_s"])),
+                          "local_systems": len(ser["local_s"]), "global_systems": len(ser["global_s"]),
+                          "cores": 1},
+               **info}
+        log(f"CPU oracle: Algorithm 1 {cpu['value']:.1f} ms/system on {cpu['cores']} threads, "
+            f"serial {cpu['serial']['local_ms_per_system']:.1f}")
+
+    dtype = "f64" if okw["precision"] == "fp64" else "f32 inner PCG, f64 residual and refinement"
+    out = {
+        "metric": "ms per linear system to rel. residual 1e-10, local vs global PCG; SpMV HBM GB/s",
+        "value": ms["local"],
+        "unit": "ms per system",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms["local"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (seeded; constant anisotropic or log-normal conductivity, moving source)",
+        "config": {"workload": desc, "N": n, "systems": w.n_systems, "dt": w.dt,
+                   "threshold": f"tau = {THETA_FACTOR} eps ||b||_2 / sqrt(N)"},
+        "global_pcg_ms_per_system": ms["global"],
+        "speedup_vs_global": ms["global"] / ms["local"],
+        "legs": {k: {"what": legs[k][0], "ms_per_system": ms[k],
+                     "speedup_vs_global": (ms["global_fp64"] if k.endswith("fp64") else ms["global"]) / ms[k],
+                     **leg_summary(sts[k], n)} for k in legs},
+        "err_vs_oracle": errs,
+        "spmv": spmv,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if args.workload == "c3" and not args.csr and not args.no_extra:
+        out["c2_1024x1024_5pt_fp64"] = c2_extra(args)
+    if args.workload == "c5" and not args.csr:
+        out["adjoint_final_step"] = final_step_adjoint(w, opts, X, Bs, max(3, args.steps // 8))
+    return out
+
+
+def final_step_adjoint(w, opts, X, Bs, reps):
+    """The adjoint of the sequence's final step (system n-1 from x_(n-2)):
+    loss 0.5 ||x - x_obs||^2 over a 32^3 window on the front, gradients with
+    respect to b and the per-cell log-conductivities.  Forward = Algorithm 1
+    through LocalSolve (assembly from log k, the benchmark's domain), backward
+    = lambda on the forward's domain plus grad log k; against the global PCG
+    forward and a full-domain adjoint.  Median wall ms over reps."""
+    import torch
+    from paper_2001_01158_amd import lcs, workloads as W
+    from paper_2001_01158_amd.autograd import LocalSolve, SolveConfig
+    dev = "cuda:0"
+    n1 = w.nx
+    k = w.n_systems - 1
+    cx, cy, cz = n1 / 4.0 + 2.0 * k, n1 / 2.0, n1 / 2.0
+    x_prev, b = X[k], Bs[k]
+    ctx = lcs.Context()
+    logk = torch.as_tensor(w.logk.reshape(-1)).to(dev)
+    zz, yy, xx = torch.meshgrid(*(torch.arange(n1, dtype=torch.float64, device=dev),) * 3,
+                                indexing="ij")
+    bump = torch.exp(-((xx - cx) ** 2 + (yy - cy) ** 2 + (zz - cz) ** 2) / 200.0).reshape(-1)
+    box = lambda v, c: (v >= c - 16) & (v < c + 16)
+    win = (box(xx, cx) & box(yy, cy) & box(zz, cz)).reshape(-1).double()
+    del zz, yy, xx
+    x_obs = x_prev + 0.5 * bump
+    cfg = SolveConfig(kind=w.kind, nx=n1, ny=n1, nz=n1, inv_dt=1.0 / w.dt, mode="residual",
+                      thresh="paper", theta=THETA_FACTOR * opts.eps, e_max=1, opts=opts)
+    A = lcs.Matrix(w.kind, n1, n1, n1, lcs.assemble_logk(w.kind, n1, n1, n1, 1.0 / w.dt, logk,
+                                                         ctx=ctx))
+    A.coef32 = lcs.cast_coef(A, ctx=ctx)
+    fwd, bwd, fwd_g, bwd_g = [], [], [], []
+    grads = None
+    for _ in range(reps + 1):
+        lk = logk.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = LocalSolve.apply(lk, b, x_prev, cfg, ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * torch.sum(win * (x - x_obs) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd.append((t1 - t0) * 1e3)
+        bwd.append((t2 - t1) * 1e3)
+        xg = x_prev.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lcs.solve_global(A, b, xg, opts, ctx=ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = (win * (xg - x_obs)).contiguous()
+        lam = torch.zeros_like(g)
+        lcs.solve_global(A, g, lam, opts, ctx=ctx)
+        gl = lcs.grad_logk(w.kind, n1, n1, n1, logk, xg, lam, ctx=ctx)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd_g.append((t1 - t0) * 1e3)
+        bwd_g.append((t2 - t1) * 1e3)
+        grads = (lk.grad.detach(), gl)
+    med = lambda v: float(np.median(v[1:]))
+    rel = float(torch.linalg.norm(grads[0] - grads[1]) / torch.linalg.norm(grads[1]))
+    out = {"system": k, "loss_window": "32^3 on the front",
+           "local_forward_ms": med(fwd), "local_backward_ms": med(bwd),
+           "full_domain_forward_ms": med(fwd_g), "full_domain_backward_ms": med(bwd_g),
+           "speedup": (med(fwd_g) + med(bwd_g)) / (med(fwd) + med(bwd)),
+           "grad_logk_rel_diff_vs_full_domain": rel, "reps": reps}
+    log(f"final-step adjoint: local {med(fwd):.2f} + {med(bwd):.2f} ms, full domain "
+        f"{med(fwd_g):.2f} + {med(bwd_g):.2f} ms, grad diff {rel:.1e}")
+    ctx.close()
+    return out
+
+
 def main():
     args = parse()
     if args.mg or args.mg_nonsym:
@@ -740,7 +1215,7 @@ def main():
         heat_run(args.heat, args.heat_steps)
         return
     if args.summarize:
-        summarize(args.summarize, args.steps)
+        summarize(args.summarize, args.steps, args.warmup, args.kernel, args.mark)
         return
     if args.tiling_sweep:
         tiling_sweep()
@@ -752,221 +1227,8 @@ def main():
         print(json.dumps({"error": "this implementation runs on one GPU; the row-slab sharding "
                                    "across GPUs is described, not built", "n_gpus": args.gpus}))
         sys.exit(2)
-    import torch
-    from paper_2001_01158_amd import lcs, workloads as W
-
-    dev = "cuda:0"
-    w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload, args.precond, args.csr)
-    n = w.n
-    stream = torch.cuda.current_stream()
-    eps = opts.eps
-    x = torch.empty(n, dtype=torch.float64, device=dev)
-
-    def one(kind, k):
-        b = Bs[k]
-        if kind == "global":
-            return lcs.solve_global(A, b, x, opts, ctx=ctx)
-        if kind == "residual":
-            return lcs.solve_local_then_global(A, b, x, "residual", "paper", eps, 1, opts, ctx=ctx)
-        if kind == "residual_relmax":
-            return lcs.solve_local_then_global(A, b, x, "residual", "relmax", 1e-3, 1, opts, ctx=ctx)
-        return lcs.solve_local_then_global(A, b, x, "gradient", "relmax", 1e-4, 1, opts, ctx=ctx)
-
-    def run_leg(kind: str, steps: int, warm: int):
-        stats = []
-        for s in range(warm):
-            k = s % w.n_systems
-            x.copy_(X[k])
-            one(kind, k)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(steps):
-            k = s % w.n_systems
-            x.copy_(X[k])
-            stats.append(one(kind, k))
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / steps, stats
-
-    # ---- timed legs ----
-    ms_local, st_local = run_leg("residual", args.steps, args.warmup)
-    log(f"local (residual, paper threshold): {ms_local:.3f} ms/system")
-    ms_global, st_global = run_leg("global", args.steps, max(2, args.warmup // 2))
-    log(f"global PCG: {ms_global:.3f} ms/system")
-    ms_grad, st_grad = run_leg("gradient", args.steps, max(2, args.warmup // 2))
-    log(f"local (gradient): {ms_grad:.3f} ms/system")
-    ms_relmax, st_relmax = run_leg("residual_relmax", args.steps, max(2, args.warmup // 2))
-    log(f"local (residual, relmax 1e-3): {ms_relmax:.3f} ms/system")
-
-    def summary(sts):
-        return {"K_mean": float(np.mean([s.K for s in sts])),
-                "eta_mean": float(np.mean([s.K for s in sts]) / n),
-                "its_local_mean": float(np.mean([s.its_local for s in sts])),
-                "its_global_mean": float(np.mean([s.its_global for s in sts])),
-                "relres_final_max": float(np.max([s.relres_final for s in sts])),
-                "global_finish_fraction": float(np.mean([s.its_global > 0 for s in sts])),
-                "ms_construct_mean": float(np.mean([s.ms_construct for s in sts])),
-                "ms_local_mean": float(np.mean([s.ms_local for s in sts])),
-                "ms_smooth_mean": float(np.mean([s.ms_smooth for s in sts])),
-                "ms_global_mean": float(np.mean([s.ms_global for s in sts]))}
-
-    # ---- dominant kernel of the timed step, timed with HIP events ----
-    # The headline step is dominated by the local PCG; its A p kernel on the
-    # restricted ELL matrix is the larger of its two kernels.  Re-run the same
-    # timed steps with that kernel bracketed by events on the solve's stream.
-    W_ell = {W.KIND_5PT: 5, W.KIND_9PT: 9, W.KIND_7PT: 7, W.KIND_9N: 9}[w.kind]
-    real_b = 8 if okw["precision"] == "fp64" else 4
-    if okw["precond"] == "rbsgs":
-        # two-kernel PCG, q = B p kernel: ELL col+val, z and p_old in, p and q out
-        bytes_per_row = W_ell * (4 + real_b) + 4 * real_b
-        kname = f"k_pcg_ap<UEll<{'double' if real_b == 8 else 'float'},{W_ell}>,2> (local PCG q = B p)"
-    else:
-        # single-synchronisation PCG iteration: ELL col+val; x, p, s, r, w, diag in;
-        # x, p, s, r, w out
-        bytes_per_row = W_ell * (4 + real_b) + 11 * real_b
-        kname = (f"k_cg_iter<UEll<{'double' if real_b == 8 else 'float'},{W_ell}>,1> "
-                 "(local PCG iteration, one launch per iteration)")
-    lcs.set_kernel_timing(lcs.TIME_LOCAL_AP, ctx=ctx)
-    _, st_t = run_leg("residual", args.steps, 0)
-    k_ms, k_launches = lcs.get_kernel_timing(ctx=ctx)
-    lcs.set_kernel_timing(lcs.TIME_NONE, ctx=ctx)
-    work_rows = float(sum(s.K * s.its_local for s in st_t))     # rows processed by working launches
-    avg_us = k_ms * 1e3 / max(k_launches, 1)
-    achieved = work_rows * bytes_per_row / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
-    bytes_per_launch = work_rows * bytes_per_row / max(k_launches, 1)
-    mt = MEASURED_TRAFFIC.get(args.workload)
-    traffic = None
-    if mt and mt["src_sha256"] == kernel_sources_sha256():
-        traffic = mt["ratio"] * bytes_per_launch
-    if w.kind == W.KIND_9N:
-        kname = "GMRES kernels (not bracketed by events; see the rocprofv3 kernel trace)"
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
-            "traffic_unit": "bytes per launch", "traffic_ratio": mt["ratio"] if traffic else None,
-            "kernel": kname,
-            "avg_launch_us": avg_us, "launches": k_launches,
-            "bytes_per_launch": bytes_per_launch,
-            "bytes_per_local_row": bytes_per_row,
-            "note": "latency-bound: one launch per PCG iteration on K ~ 1e4-1e5 local rows"}
-    log(f"dominant kernel: {k_launches} launches, avg {avg_us:.2f} us, {achieved or 0:.0f} GB/s")
-
-    # ---- SpMV GB/s ----
-    def time_spmv(M, xx, yy, reps=50):
-        lcs.spmv(M, xx, yy, reps=5, ctx=ctx)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        lcs.spmv(M, xx, yy, reps=reps, ctx=ctx)
-        e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps
-
-    xs = torch.rand(n, dtype=torch.float64, device=dev)
-    ys = torch.empty_like(xs)
-    spmv_ms = time_spmv(A, xs, ys)
-    nb_row = {W.KIND_5PT: 40, W.KIND_9PT: 56, W.KIND_7PT: 48, W.KIND_9N: 88}[w.kind]
-    spmv = {f"{args.workload}_fp64": {"n": n, "us": spmv_ms * 1e3, "GBs": n * nb_row / spmv_ms / 1e6,
-                                      "bytes_per_row": nb_row}}
-    hbm = None
-    if not args.skip_spmv_hbm:
-        n3 = 4096
-        c9 = W.assemble_9pt(n3, n3, 0.25, 100.0, 30.0)
-        A9 = lcs.matrix_from_numpy(W.KIND_9PT, n3, n3, 1, c9, dev, with32=True)
-        del c9
-        x9 = torch.rand(n3 * n3, dtype=torch.float32, device=dev)
-        y9 = torch.empty_like(x9)
-        ms9 = time_spmv(A9, x9, y9)
-        b9 = n3 * n3 * (5 * 4 + 4 + 4)
-        hbm = {"n": n3 * n3, "us": ms9 * 1e3, "GBs": b9 / ms9 / 1e6, "bytes_per_row": 28,
-               "frac_of_8TBs": b9 / ms9 / 1e6 / HBM_PEAK_GBS,
-               "kernel": "k_spmv<U9<float,4,2>> (row marching, non-temporal streams)"}
-        spmv["c3_9pt_fp32_4096x4096_hbm"] = hbm
-        log(f"SpMV 9pt FP32 4096^2: {ms9 * 1e3:.1f} us, {hbm['GBs']:.0f} GB/s")
-        del A9, x9, y9
-    if args.csr and not args.skip_spmv_hbm:
-        # general sparse input: 4096^2 five-point FP64 in CSR, run on its ELL
-        # copy (width 5); CSR's own bytes per row: 5 x (4 + 8) + 4 (row
-        # pointer) + 8 (x) + 8 (y)
-        n3 = 4096
-        c5 = W.assemble_5pt(W.lognormal_logk((n3, n3), 1.0, 7), 0.25)
-        A5 = csr_input(W.KIND_5PT, n3, n3, 1, c5, dev)
-        del c5
-        x5 = torch.rand(n3 * n3, dtype=torch.float64, device=dev)
-        y5 = torch.empty_like(x5)
-        ms5 = time_spmv(A5, x5, y5)
-        b5 = n3 * n3 * 80
-        spmv["csr_5pt_fp64_4096x4096"] = {
-            "n": n3 * n3, "us": ms5 * 1e3, "GBs": b5 / ms5 / 1e6, "bytes_per_row": 80,
-            "frac_of_8TBs": b5 / ms5 / 1e6 / HBM_PEAK_GBS,
-            "kernel": "k_spmv<UEll<double,5>> (row per lane on the ELL copy)",
-            "note": "one call: includes the structure check, the ELL copy and one synchronisation"}
-        log(f"SpMV CSR 5pt FP64 4096^2: {ms5 * 1e3:.1f} us per product")
-        del A5, x5, y5
-
-    if args.calib_copy:
-        src_t = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev)   # 512 MiB
-        dst_t = torch.empty_like(src_t)
-        for _ in range(3):
-            dst_t.copy_(src_t)
-        torch.cuda.synchronize()
-        del src_t, dst_t
-
-    # ---- CPU baseline: the oracle on the same systems ----
-    cpu = None
-    if not args.no_cpu and args.workload == "c2":
-        import oracle
-        Ah = oracle.csr_from_stencil(w.kind, w.nx, w.ny, w.nz, w.coef)
-        t_used, done, t_glob, n_glob = 0.0, 0, 0.0, 0
-        k = 1
-        while t_used < args.cpu_seconds * 0.5 and done < w.n_systems:
-            b = Bs[k % w.n_systems].cpu().numpy()
-            x0 = X[k % w.n_systems].cpu().numpy()
-            t = time.perf_counter()
-            oracle.local_then_global(Ah, b, x0, oracle.MODE_RESIDUAL, eps, oracle.TH_PAPER, 1,
-                                     oracle.Options(eps=eps))
-            t_used += time.perf_counter() - t
-            done += 1
-            k += 1
-        while t_glob < args.cpu_seconds * 0.5 and n_glob < 5:
-            b = Bs[(n_glob + 1) % w.n_systems].cpu().numpy()
-            x0 = X[(n_glob + 1) % w.n_systems].cpu().numpy()
-            t = time.perf_counter()
-            oracle.solve_global(Ah, b, x0, oracle.Options(eps=eps))
-            t_glob += time.perf_counter() - t
-            n_glob += 1
-        cpu = {"value": t_used * 1e3 / done, "unit": "ms per system", "cores": 1, "kind": "oracle",
-               "sample": f"oracle (serial FP64 C) Algorithm 1 with the paper threshold on {done} "
-                         f"systems of the same sequence, from the GPU's x_(k-1); oracle global "
-                         f"Jacobi-PCG {t_glob * 1e3 / max(n_glob, 1):.1f} ms/system on {n_glob} systems",
-               "global_ms_per_system": t_glob * 1e3 / max(n_glob, 1)}
-        log(f"CPU oracle: local {cpu['value']:.1f} ms/system, global {cpu['global_ms_per_system']:.1f}")
-
-    out = {
-        "metric": "ms per linear system to rel. residual 1e-10, local vs global PCG; SpMV HBM GB/s",
-        "value": ms_local,
-        "unit": "ms per system",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_local,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if okw["precision"] == "fp64" else "f32 inner / f64 refinement",
-        "data": "synthetic (seeded log-normal conductivity, moving source)",
-        "config": {"workload": desc, "N": n, "systems": w.n_systems, "dt": w.dt},
-        "global_pcg_ms_per_system": ms_global,
-        "speedup_vs_global": ms_global / ms_local,
-        "local_gradient_ms_per_system": ms_grad,
-        "local_residual_relmax_ms_per_system": ms_relmax,
-        "local_residual": summary(st_local),
-        "local_gradient": summary(st_grad),
-        "local_residual_relmax": summary(st_relmax),
-        "global": summary(st_global),
-        "spmv": spmv,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
+    out = run_benchmark(args)
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()

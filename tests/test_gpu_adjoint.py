@@ -161,33 +161,21 @@ def test_adjoint_c4_scale():
     assert worst < 1e-4
 
 
-@pytest.mark.timeout(600)
-def test_adjoint_c5_scale():
-    """256^3 seven-point, sigma = 1.5, FP32 inner RB-SGS + FP64 refinement:
-    the adjoint of one step with the loss over a 32^3 window at the front.
-    A full-domain oracle adjoint at this size takes minutes on one core, so
-    the checks are properties recomputed by the oracle at full size:
-    * the GPU's assembly from log k matches the oracle's;
-    * the forward x and the adjoint lambda meet their criteria;
-    * grad log k equals the oracle's formula applied to that x and lambda;
-    * central differences agree along 4 Rademacher directions.
-    The previous state is the constant 0.1, which A maps to 0.1 / dt exactly
-    (zero-flux faces), so r^(0) is the ball source itself."""
+def _adjoint_256(logk, x_prev, b, centre, seed):
+    """The 256^3 adjoint checks at one step: loss over a 32^3 window around
+    `centre`, forward and adjoint at eps = 1e-13 (FP32 inner RB-SGS + FP64
+    refinement); properties recomputed by the oracle at full size and
+    central differences along 4 Rademacher directions."""
     n1, kind, dt = 256, W.KIND_7PT, 4.0
-    dims = (n1, n1, n1)
     n = n1 ** 3
-    say("adjoint 256^3")
-    logk = W.lognormal_logk((n1, n1, n1), 1.5, W.BASE_SEED + 4)
-    x_prev = np.full(n, 0.1)
-    q = W.ball_source(n1, n1, n1, n1 / 2.0, n1 / 2.0, n1 / 2.0, 20.0, 1.0)
-    b = x_prev / dt + q
+    cx, cy, cz = centre
     zz, yy, xx = np.meshgrid(*(np.arange(n1, dtype=np.float64),) * 3, indexing="ij")
-    bump = np.exp(-((xx - n1 / 2.0) ** 2 + (yy - n1 / 2.0) ** 2 + (zz - n1 / 2.0) ** 2) / 200.0)
-    x_obs = (0.1 + 0.5 * bump).reshape(-1)
+    bump = np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2 + (zz - cz) ** 2) / 200.0)
+    x_obs = (x_prev.reshape(n1, n1, n1) + 0.5 * bump).reshape(-1)
     del zz, yy, xx, bump
     win = np.zeros(n)
-    c0 = n1 // 2 - 16
-    win.reshape(n1, n1, n1)[c0:c0 + 32, c0:c0 + 32, c0:c0 + 32] = 1.0
+    x0_, y0_, z0_ = (int(round(c)) - 16 for c in (cx, cy, cz))
+    win.reshape(n1, n1, n1)[z0_:z0_ + 32, y0_:y0_ + 32, x0_:x0_ + 32] = 1.0
     eps = 1e-13
     opts = lcs.Options(eps=eps, precision="mixed", precond="rbsgs")
     cfg = SolveConfig(kind=kind, nx=n1, ny=n1, nz=n1, inv_dt=1.0 / dt, mode="residual",
@@ -225,7 +213,7 @@ def test_adjoint_c5_scale():
         xx_ = LocalSolve.apply(lkv, bb.detach(), xp, cfg, None)
         return 0.5 * float(torch.sum(wv * (xx_ - xo) ** 2))
 
-    rng = np.random.default_rng(25)
+    rng = np.random.default_rng(seed)
     h = 1e-6
     worst = 0.0
     base = lk.detach()
@@ -236,6 +224,57 @@ def test_adjoint_c5_scale():
         worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-30))
     say(f"  worst FD relative gap over 4 directions: {worst:.2e}")
     assert worst < 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_c5_scale():
+    """256^3 seven-point, sigma = 1.5, FP32 inner RB-SGS + FP64 refinement:
+    the adjoint of one step with the loss over a 32^3 window at the front.
+    A full-domain oracle adjoint at this size takes minutes on one core, so
+    the checks are properties recomputed by the oracle at full size:
+    * the GPU's assembly from log k matches the oracle's;
+    * the forward x and the adjoint lambda meet their criteria;
+    * grad log k equals the oracle's formula applied to that x and lambda;
+    * central differences agree along 4 Rademacher directions.
+    The previous state is the constant 0.1, which A maps to 0.1 / dt exactly
+    (zero-flux faces), so r^(0) is the ball source itself."""
+    n1, dt = 256, 4.0
+    n = n1 ** 3
+    say("adjoint 256^3, constant previous state")
+    logk = W.lognormal_logk((n1, n1, n1), 1.5, W.BASE_SEED + 4)
+    x_prev = np.full(n, 0.1)
+    q = W.ball_source(n1, n1, n1, n1 / 2.0, n1 / 2.0, n1 / 2.0, 20.0, 1.0)
+    _adjoint_256(logk, x_prev, x_prev / dt + q, (n1 / 2.0,) * 3, 25)
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_c5_final_step():
+    """The 256^3 sequence as the benchmark defines it: 50 backward-Euler
+    systems with the ball source moving 2 cells per system, each solved by
+    Algorithm 1 (FP32 inner RB-SGS + FP64 refinement to 1e-10, threshold
+    0.1 eps ||b|| / sqrt(N)); the adjoint of the final step (system 49, from
+    x_48), loss over a 32^3 window on the front, with the same checks."""
+    w = W.c5_sphere3d()
+    n1, dt = w.nx, w.dt
+    assert w.n_systems == 50
+    say("adjoint 256^3, final step of the 50-system sequence")
+    A = lcs.matrix_from_numpy(w.kind, n1, n1, n1, w.coef, DEV, with32=True)
+    ctx = lcs.Context()
+    opts = lcs.Options(eps=1e-10, precision="mixed", precond="rbsgs")
+    x = torch.zeros(w.n, dtype=torch.float64, device=DEV)
+    centre = lambda k: (n1 / 4.0 + 2.0 * k, n1 / 2.0, n1 / 2.0)
+    for k in range(w.n_systems - 1):
+        b = x / dt + torch.as_tensor(W.ball_source(n1, n1, n1, *centre(k), 20.0, 1.0)).to(DEV)
+        st = lcs.solve_local_then_global(A, b, x, "residual", "paper", 1e-11, 1, opts, ctx=ctx)
+        assert st.relres_final <= 1e-10
+        if k % 10 == 0 or k == w.n_systems - 2:
+            say(f"  system {k}: K={st.K} its={st.its_local}+{st.its_global}")
+    ctx.close()
+    del A
+    x_prev = host_np(x)
+    kf = w.n_systems - 1
+    b = x_prev / dt + W.ball_source(n1, n1, n1, *centre(kf), 20.0, 1.0)
+    _adjoint_256(w.logk, x_prev, b, centre(kf), 26)
 
 
 def host_np(t):
