@@ -36,11 +36,11 @@
  *     grid is assumed, Section 2.1) in CSR, symmetric unless csr_nonsym is
  *     set (then solved by GMRES(m) as LCS_STENCIL9N_2D is): nx = N, ny = nz = 1,
  *     row_ptr int32[N+1], col int32[nnz] strictly ascending within each row
- *     with the diagonal stored, val double[nnz]; every row holds 1..16
+ *     with the diagonal stored, val double[nnz]; every row holds 1..64
  *     entries.  Each call checks this structure before any kernel reads
  *     through col (LCS_EINVAL naming what failed; symmetry is the caller's
  *     to ensure, as for the stencils) and copies A into column-major ELL
- *     of width 5, 7, 9 or 16 in the context's workspace, on which the whole path
+ *     of width 5, 7, 9, 16 or 64 in the context's workspace, on which the whole path
  *     runs.  Scores, thresholds, expansion, compaction and the gather of B
  *     follow the stencil kinds' definitions over the stored entries.  The
  *     Gauss-Seidel sweeps and the RB-SGS preconditioner need a colouring:
@@ -177,7 +177,7 @@ void lcs_destroy(lcs_ctx *ctx);
  * lcs_default_options): a fixed head (device state, reduction partials) plus
  * every buffer the path may use at its largest.  The local domain is counted
  * at K = N, because Algorithms 2 and 3 may mark the whole grid, and general
- * sparse input counts its ELL copy at width 16.  About 240 B per row for the
+ * sparse input counts its ELL copy and B at width 64.  About 240 B per row for the
  * nine-point stencil in mixed precision.  Host arithmetic only, no device
  * call.  Returns 0 if A or o is invalid (lcs_last_error() says why). */
 size_t lcs_workspace_bytes(const lcs_matrix *A, const lcs_options *o);

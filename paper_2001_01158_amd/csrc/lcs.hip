@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -73,6 +74,19 @@ struct Launch {
 
 // Chunked grid: at most kMaxGrid blocks (a multiple of 8 once large enough,
 // for the XCD remap), each owning `chunk` consecutive rows.
+// Chunked grid of up to `cap` blocks (<= kSlotElems for kernels that write
+// one partial per block), for per-row kernels whose rows are latency-bound
+// chains of dependent loads: more blocks, fewer rows per thread.
+Launch dims_wide(int64_t n, int cap) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    if (g >= 64) g = (g + kXcds - 1) / kXcds * kXcds;
+    int64_t chunk = (n + g - 1) / g;
+    if (chunk < 1) chunk = 1;
+    return {(int)g, chunk};
+}
+
 Launch dims_for(int64_t n) {
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
@@ -104,7 +118,10 @@ constexpr int kRedGrid = 512;     // reducing band kernels
 constexpr int kStreamGrid = 4096; // non-reducing band kernels
 
 // Grid of a unit-operator kernel: one wave per row-marching tile for the 2-D
-// stencils (waves loop over tiles beyond the cap), else the band grid.
+// stencils (waves loop over tiles beyond the cap), else the band grid.  The
+// reducing kernels on ELL rows (restricted systems, general sparse input)
+// take up to kMaxGrid blocks: their rows are gathers whose latency more
+// waves hide, and the fold of 1024 partials costs one round of loads.
 template <class Op>
 int grid_for(const Op &A, int cap) {
     if constexpr (Op::kMarch) {
@@ -113,7 +130,7 @@ int grid_for(const Op &A, int cap) {
         g = std::max<int64_t>(kXcds, std::min<int64_t>(g, cap));
         return (int)g;
     } else {
-        return band_grid(A.units(), cap);
+        return band_grid(A.units(), cap == kRedGrid ? kMaxGrid : cap);
     }
 }
 
@@ -161,6 +178,7 @@ struct lcs_ctx {
     size_t ws_len[B_NUM] = {};
     hipEvent_t ev[5] = {};
     hipEvent_t chk[2] = {};
+    hipEvent_t done_ev = nullptr;   // recorded by wait_for (null: block instead)
     // iterations of the previous global (0) / local (1) PCG, by refinement
     // step (mixed precision) or restart (FP64), for sizing the first chunk
     int last_its[2][4] = {};
@@ -181,7 +199,7 @@ struct lcs_ctx {
     GmState *hgm = nullptr;
     // ELL copy of the general sparse matrix of the current call
     struct {
-        int width = 0;         // 5, 7, 9 or 16
+        int width = 0;         // 5, 7, 9, 16 or 64
         int64_t n = 0;
         int32_t *col = nullptr;
         double *val = nullptr;   // width x n values, then the diagonal
@@ -208,13 +226,17 @@ lcs_status get_buf(lcs_ctx *c, BufId id, size_t count, T **out) {
         return LCS_OK;
     }
     if (c->cap[id] < bytes) {
+        // Slack for sequences whose K grows: an eighth on the first
+        // allocation, half once a buffer has had to grow (each regrowth
+        // synchronises the device and costs about a millisecond).
+        const bool regrow = c->buf[id] != nullptr;
         if (c->buf[id]) {
             HIP_TRY(hipDeviceSynchronize());  // the old buffer may still be in use
             HIP_TRY(hipFree(c->buf[id]));
         }
         c->buf[id] = nullptr;
         c->cap[id] = 0;
-        const size_t want = bytes + bytes / 8;  // slack for sequences of growing K
+        const size_t want = bytes + (regrow ? bytes / 2 : bytes / 8);
         if (hipMalloc(&c->buf[id], want) != hipSuccess) {
             (void)hipGetLastError();
             return fail(LCS_ENOMEM, "device workspace allocation of " + std::to_string(want) +
@@ -230,10 +252,47 @@ double *slot(lcs_ctx *c, int k) { return c->partials + (size_t)k * kSlotElems; }
 template <typename real>
 real *slot_as(lcs_ctx *c, int k) { return reinterpret_cast<real *>(slot(c, k)); }
 
+// Wait for an event by polling it.  A blocking wait sleeps until an
+// interrupt and resumes tens of microseconds after the GPU gets there; a
+// solve waits on the host several times (each chunk check, each refinement
+// step), so the poll, which resumes within a few microseconds, saves a
+// visible share of a millisecond-scale solve.  After kSpinUs of polling the
+// wait blocks.  Polling leaves hipErrorNotReady as the thread's last error,
+// which is cleared so that later launch checks (ours or the caller's) do
+// not see it.
+constexpr double kSpinUs = 2000.0;
+
+lcs_status spin_event(hipEvent_t e) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipError_t q = hipErrorNotReady;
+    for (int k = 0; q == hipErrorNotReady; ++k) {
+        q = hipEventQuery(e);
+        if (q == hipErrorNotReady && (k & 63) == 63 &&
+            std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() >
+                kSpinUs)
+            break;
+    }
+    if (hipPeekAtLastError() == hipErrorNotReady) (void)hipGetLastError();
+    if (q == hipSuccess) return LCS_OK;
+    if (q != hipErrorNotReady)
+        return fail(LCS_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    HIP_TRY(hipEventSynchronize(e));
+    return LCS_OK;
+}
+
+// Wait until stream s has executed everything enqueued so far.
+lcs_status wait_for(lcs_ctx *c, hipStream_t s) {
+    if (!c->done_ev) {   // a context without events (the allocation-free path)
+        HIP_TRY(hipStreamSynchronize(s));
+        return LCS_OK;
+    }
+    HIP_TRY(hipEventRecord(c->done_ev, s));
+    return spin_event(c->done_ev);
+}
+
 lcs_status read_scalars(lcs_ctx *c, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(c->hsc, c->dsc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return LCS_OK;
+    return wait_for(c, s);
 }
 
 lcs_status check_matrix(const lcs_matrix *A) {
@@ -245,7 +304,7 @@ lcs_status check_matrix(const lcs_matrix *A) {
         if (A->nx >= (1 << 27)) return fail(LCS_EINVAL, "N must be < 2^27");
         if (!A->row_ptr || !A->col || !A->val) return fail(LCS_EINVAL, "row_ptr, col or val is NULL");
         if (A->nnz < 1 || A->nnz > (int64_t)kCsrMaxRow * A->nx)
-            return fail(LCS_EINVAL, "nnz must be in 1 .. 16 N");
+            return fail(LCS_EINVAL, "nnz must be in 1 .. 64 N");
         if (A->colour && (A->n_colours < 1 || A->n_colours > 255))
             return fail(LCS_EINVAL, "n_colours must be 1..255 with a colouring");
         return LCS_OK;
@@ -538,7 +597,8 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
         case 5: return go(Width<5>());
         case 7: return go(Width<7>());
         case 9: return go(Width<9>());
-        default: return go(Width<16>());
+        case 16: return go(Width<16>());
+        default: return go(Width<64>());
         }
     }
     switch (A->kind) {
@@ -578,7 +638,7 @@ lcs_status with_ops(const lcs_ctx *c, const lcs_matrix *A, const float *coef32, 
 
 // General sparse input: check the structure (one synchronisation, before
 // any kernel reads through the column indices), then copy A into
-// column-major ELL of width 5, 7, 9 or 16 in the context.  Stencil kinds:
+// column-major ELL of width 5, 7, 9, 16 or 64 in the context.  Stencil kinds:
 // nothing.
 lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
     if (A->kind != LCS_CSR) return LCS_OK;
@@ -597,13 +657,13 @@ lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
     LAUNCH_CHECK();
     int32_t h[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    LCS_TRY(wait_for(c, s));
     if (h[0]) {
         std::string m = "CSR matrix:";
         if (h[0] & kCsrBadPtr) m += " row_ptr not non-decreasing in [0, nnz];";
         if (h[0] & kCsrEnds) m += " row_ptr[0] != 0 or row_ptr[N] != nnz;";
         if (h[0] & kCsrEmpty) m += " empty row;";
-        if (h[0] & kCsrLong) m += " row longer than 16 entries;";
+        if (h[0] & kCsrLong) m += " row longer than 64 entries;";
         if (h[0] & kCsrCol) m += " column out of range;";
         if (h[0] & kCsrOrder) m += " columns not strictly ascending;";
         if (h[0] & kCsrNoDiag) m += " diagonal entry missing;";
@@ -615,8 +675,10 @@ lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
         return fail(h[0] == kCsrNonFinite ? LCS_ENONFINITE : LCS_EINVAL, m);
     }
     // the widths of the stencil kinds, whose ELL operators the local
-    // systems already use, then 16
-    const int W = h[1] <= 5 ? 5 : h[1] <= 7 ? 7 : h[1] <= 9 ? 9 : 16;
+    // systems already use, then 16, then 64 for rows of up to 64 entries
+    // (a row's entries stay in registers: at 64 the kernels spill, a
+    // fallback for rare long rows rather than a tuned path)
+    const int W = h[1] <= 5 ? 5 : h[1] <= 7 ? 7 : h[1] <= 9 ? 9 : h[1] <= 16 ? 16 : 64;
     LCS_TRY(get_buf(c, B_ACOL, (size_t)W * n, &c->ell.col));
     LCS_TRY(get_buf(c, B_AVAL, (size_t)(W + 1) * n, &c->ell.val));
     LCS_TRY(get_buf(c, B_ACLR, (size_t)n, &c->ell.clr));
@@ -628,7 +690,8 @@ lcs_status prepare_matrix(lcs_ctx *c, const lcs_matrix *A, hipStream_t s) {
     case 5: conv(k_csr_to_ell<5>); break;
     case 7: conv(k_csr_to_ell<7>); break;
     case 9: conv(k_csr_to_ell<9>); break;
-    default: conv(k_csr_to_ell<16>); break;
+    case 16: conv(k_csr_to_ell<16>); break;
+    default: conv(k_csr_to_ell<64>); break;
     }
     LAUNCH_CHECK();
     E.width = W;
@@ -671,7 +734,7 @@ lcs_status ensure_coef32(lcs_ctx *c, const lcs_matrix *A, bool need, const float
 }
 
 lcs_status launch_norm(lcs_ctx *c, const double *v, int64_t n, double *out, hipStream_t s) {
-    const Launch L = dims_for(n);
+    const Launch L = dims_wide(n, 4096);   // one partial per block
     hipLaunchKernelGGL(k_norm2, dim3(L.grid), dim3(kBlock), 0, s, v, n, L.chunk, slot(c, kPtNorm));
     hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(kBlock), 0, s, (const double *)slot(c, kPtNorm),
                        L.grid, out);
@@ -814,7 +877,7 @@ lcs_status run_chunks(lcs_ctx *c, hipStream_t s, int max_iter, int check_every, 
             if (len > 0) LCS_TRY(enqueue(len));
         }
         const int sl = inflight[0];
-        HIP_TRY(hipEventSynchronize(c->chk[sl]));
+        LCS_TRY(spin_event(c->chk[sl]));
         inflight[0] = inflight[1];
         --nin;
         const PcgState &h = c->hpcg[sl];
@@ -1060,9 +1123,24 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
         hipLaunchKernelGGL(k_fill<double>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, 0.0, n);
         LAUNCH_CHECK();
     }
+    // The outcome of each inner PCG (iterations, status) stays on the device
+    // until the host reads the next FP64 residual: one host round trip per
+    // refinement step.
+    int pending = -1;   // refinement step whose inner outcome is not yet read
+    auto settle = [&]() -> lcs_status {
+        if (pending < 0) return LCS_OK;
+        const int it = c->hsc->saved_it[scope];
+        out->its += it;
+        c->last_its[scope][std::min(pending, 3)] = it;
+        pending = -1;
+        const int ps = c->hsc->saved_status[scope];
+        if (ps == kStBreakdown || ps == kStNonFinite) return status_of(ps);
+        return LCS_OK;
+    };
     for (int outer = 0;; ++outer) {
         LCS_TRY(launch_resnorm(c, A, rhs, x, r64, tol_base, tol_factor, s));
         LCS_TRY(read_scalars(c, s));
+        LCS_TRY(settle());
         out->rr = c->hsc->res.rr;
         if (c->hsc->res.status != kStOk) return status_of(c->hsc->res.status);
         if (c->hsc->res.done) return LCS_OK;
@@ -1074,12 +1152,11 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
         c->cur_outer = outer;
         LCS_TRY(run_pcg(c, A32, ncol, o->precond, (const float *)r32, d32, true,
                         (const double *)nullptr, inner, o->max_iter - out->its, check, B, s, &pr,
-                        scope, true));
-        out->its += pr.its;
-        if (pr.status == kStBreakdown || pr.status == kStNonFinite) return status_of(pr.status);
+                        scope, false));
         hipLaunchKernelGGL(k_axpy_scaled, dim3(flat_grid(n)), dim3(kBlock), 0, s, x,
-                           (const float *)d32, n, (const Scalars *)c->dsc);
+                           (const float *)d32, n, (const Scalars *)c->dsc, scope);
         LAUNCH_CHECK();
+        pending = outer;
         out->n_outer += 1;
     }
 }
@@ -1139,7 +1216,7 @@ lcs_status run_gmres_t(lcs_ctx *c, const Op &A, const double *rhs, double *x, bo
             ++j;
             if (j % check == 0 && j < steps) {
                 HIP_TRY(hipMemcpyAsync(c->hdone, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
+                LCS_TRY(wait_for(c, s));
                 if (c->hdone[0]) break;
             }
         }
@@ -1148,7 +1225,7 @@ lcs_status run_gmres_t(lcs_ctx *c, const Op &A, const double *rhs, double *x, bo
                            n, x, (const GmState *)st);
         LAUNCH_CHECK();
         HIP_TRY(hipMemcpyAsync(c->hgm, st, sizeof(GmState), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(wait_for(c, s));
         const GmState &h = *c->hgm;
         out->its += h.k;
         if (h.status != kStOk) return status_of(h.status);
@@ -1199,15 +1276,14 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
 // Algorithm 2 / Algorithm 3: scores, threshold, expansion, compaction
 // ---------------------------------------------------------------------------
 // Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
-// ascending domain in idx; returns K (host).  eps0 >= 0: an x0 with
-// ||b - A x0|| <= eps0 ||b|| (||b|| already in dsc->bnorm) gives the empty
-// domain and hsc->ms.conv0 = 1.
+// ascending domain in idx; returns K (host).  eps0 >= 0: ||b|| (from the
+// score pass) goes to dsc->bnorm, and an x0 with ||b - A x0|| <= eps0 ||b||
+// gives the empty domain and hsc->ms.conv0 = 1.
 template <class SOp, class UOp>
 lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *b,
                         const double *x0, int mode, int thresh, double theta, int e_max,
                         double eps0, int32_t *idx, int64_t *K, hipStream_t s) {
     const int64_t n = As.n;
-    const Launch L = dims_for(n);
     const Tiling T = tiling_for(n);
     const int gs = grid_for(Au, kRedGrid);
     double *score;
@@ -1224,20 +1300,21 @@ lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *
     else
         LCS_TRY(launch_maybe_timed(c, timed, k_score<UOp, 1>, gs, s, Au, b, x0, score,
                                    slot(c, kPtScore)));
-    const int gmark = std::min(flat_grid(T.npad), 512);
+    const int gmark = std::min(flat_grid(T.npad / 8), 2048);
     hipLaunchKernelGGL(k_mark, dim3(gmark), dim3(kBlock), 0, s, (const double *)score, stamp, n,
                        T.npad, thresh, theta, eps0, (const double *)slot(c, kPtScore), gs, c->dsc);
     LAUNCH_CHECK();
     const int ex = mode == LCS_MODE_RESIDUAL ? e_max : 0;
+    const Launch Le = dims_wide(n, 4096);   // one partial per block
     for (int m = 1; m <= ex; ++m)
-        hipLaunchKernelGGL((k_expand<SOp>), dim3(L.grid), dim3(kBlock), 0, s, As,
-                           (const double *)score, x0, stamp, m, L.chunk,
+        hipLaunchKernelGGL((k_expand<SOp>), dim3(Le.grid), dim3(kBlock), 0, s, As,
+                           (const double *)score, x0, stamp, m, Le.chunk,
                            (const double *)slot(c, kPtExp0 + ((m - 1) & 1)),
                            slot(c, kPtExp0 + (m & 1)), c->dsc);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_count, dim3(T.grid), dim3(kBlock), 0, s, (const uint8_t *)stamp, T.ntiles,
                        T.tiles_per_block, blockoff, ex, (const double *)slot(c, kPtExp0 + (ex & 1)),
-                       L.grid, c->dsc);
+                       Le.grid, c->dsc);
     hipLaunchKernelGGL(k_scatter, dim3(T.grid), dim3(kBlock), 0, s, (const uint8_t *)stamp, n,
                        T.ntiles, T.tiles_per_block, (const int32_t *)blockoff, idx, inv, c->dsc);
     LAUNCH_CHECK();
@@ -1527,7 +1604,7 @@ lcs_status solve_batched(lcs_ctx *c, const lcs_matrix *A, int32_t G, const doubl
             const int m = std::min<int32_t>(kBoutChunk, G - g);
             HIP_TRY(hipMemcpyAsync(c->hbout, dout + g, sizeof(BatchOut) * (size_t)m,
                                    hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            LCS_TRY(wait_for(c, s));
         }
         const BatchOut &r = c->hbout[slot_g];
         if (st) {
@@ -1591,6 +1668,8 @@ lcs_status create_ctx(lcs_ctx **out, void *ws, size_t ws_bytes) {
     for (auto &e : c->chk)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return cleanup(fail(LCS_EHIP, "event"));
+    if (hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(LCS_EHIP, "event"));
     if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LCS_EHIP, "sync"));
     *out = c;
     return LCS_OK;
@@ -1703,6 +1782,7 @@ void lcs_destroy(lcs_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chk)
         if (e) (void)hipEventDestroy(e);
+    if (c->done_ev) (void)hipEventDestroy(c->done_ev);
     for (auto &e : c->prof_ev) (void)hipEventDestroy(e);
     delete c;
 }
@@ -1721,7 +1801,7 @@ lcs_status lcs_residual(lcs_ctx *c, const lcs_matrix *A, const double *b, const 
         const int64_t n = op.units() * decltype(op)::V;
         LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         LCS_TRY(launch_resnorm(c, op, b, x, r, &c->dsc->bnorm, 1.0, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(wait_for(c, s));
         return LCS_OK;
     });
 }
@@ -1739,7 +1819,7 @@ lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double
         hipLaunchKernelGGL((k_score<decltype(op), 1>), dim3(grid), dim3(kBlock), 0, s, op, x, x, g,
                            slot(c, kPtScore));
         LAUNCH_CHECK();
-        HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(wait_for(c, s));
         return LCS_OK;
     });
 }
@@ -1805,7 +1885,7 @@ lcs_status lcs_build_local_domain(lcs_ctx *c, const lcs_matrix *A, const double 
             uint8_t *stamp;
             LCS_TRY(get_buf(c, B_STAMP, tiling_for(sop.n).npad, &stamp));
             HIP_TRY(hipMemcpyAsync(mask, stamp, (size_t)sop.n, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            LCS_TRY(wait_for(c, s));
         }
         if (st) {
             init_stats(st);
@@ -1842,7 +1922,7 @@ lcs_status lcs_gather_restricted(lcs_ctx *c, const lcs_matrix *A, const int32_t 
         if (K == 0) {
             *nnz = 0;
             HIP_TRY(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s));
-            HIP_TRY(hipStreamSynchronize(s));
+            LCS_TRY(wait_for(c, s));
             return LCS_OK;
         }
         Restricted<W> R;
@@ -1879,7 +1959,7 @@ lcs_status lcs_gs_sweeps(lcs_ctx *c, const lcs_matrix *A, const double *b, doubl
     if (ncol == 0) return fail(LCS_EINVAL, "Gauss-Seidel sweeps on a CSR matrix need its colouring");
     return with_ops(c, A, nullptr, vec_ok({b, x}), [&](auto, auto op, auto, auto) -> lcs_status {
         LCS_TRY(launch_sweeps(c, op, b, x, ncol, n_sweeps, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(wait_for(c, s));
         LCS_TRY(flush_prof(c));
         return LCS_OK;
     });
@@ -1910,7 +1990,7 @@ lcs_status lcs_solve_global(lcs_ctx *c, const lcs_matrix *A, const double *b, do
         const lcs_status rs = solve_system(c, op, op32, colours_of(A), b, x, false,
                                            &c->dsc->bnorm, o->eps, o, s, &so, 0, uses_gmres(A));
         LCS_TRY(tm.mark(4));
-        HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(wait_for(c, s));
         LCS_TRY(flush_prof(c));
         const double bn = c->hsc->bnorm;
         st->its_global = so.its;
@@ -1989,7 +2069,6 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
     LCS_TRY(ensure_coef32(c, A, o->precision == LCS_PREC_MIXED, &c32, s));
     return with_ops(c, A, c32, vec_ok({b, x}), [&](auto sop, auto op, auto op32, auto wtag) -> lcs_status {
         constexpr int W = decltype(wtag)::value;
-        LCS_TRY(launch_norm(c, b, n, &c->dsc->bnorm, s));
         int32_t *idx;
         LCS_TRY(get_buf(c, B_IDX, n, &idx));
         int64_t K = 0;
@@ -2006,7 +2085,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
             const double rr0 = std::sqrt(c->hsc->ms.rr0);
             st->relres_after_local = st->relres_final = bn > 0 ? rr0 / bn : rr0;
             LCS_TRY(tm.mark(1));
-            HIP_TRY(hipStreamSynchronize(s));
+            LCS_TRY(wait_for(c, s));
             LCS_TRY(flush_prof(c));
             st->ms_construct = tm.ms(0, 1);
             return LCS_OK;
@@ -2037,7 +2116,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
             st->relres_final = bn > 0 ? std::sqrt(so.rr) / bn : std::sqrt(so.rr);
             LCS_TRY(tm.mark(4));
         }
-        HIP_TRY(hipStreamSynchronize(s));
+        LCS_TRY(wait_for(c, s));
         LCS_TRY(flush_prof(c));
         st->ms_construct = tm.ms(0, 1);
         st->ms_local = tm.ms(1, 2);

@@ -12,7 +12,7 @@
 
 namespace lcs {
 
-constexpr int kCsrMaxRow = 16;
+constexpr int kCsrMaxRow = 64;
 
 // error bits of the structure check
 enum : int32_t {

@@ -1220,20 +1220,38 @@ __device__ __forceinline__ void write_partials(T (&v)[NV], O ops, T *part) {
 
 // Consumer side: fold the g partials of the producing kernel in a fixed order
 // (strided per thread, then the block tree).  Every block that calls this
-// gets bit-identical totals, valid in all of its threads.
+// gets bit-identical totals, valid in all of its threads.  A thread issues
+// the loads of kFoldLoads strided partials of every value before it combines
+// any of them, so a fold over g <= kFoldLoads x kBlock partials waits for one
+// round of cache latency rather than g / kBlock rounds in sequence (this fold
+// opens every launch of the iterative kernels).
+constexpr int kFoldLoads = 4;
 template <typename T, int NV, class O>
 __device__ __forceinline__ void read_partials(const T *part, int g, O ops, T (&tot)[NV]) {
     __shared__ T lds[kWaves][NV];
     T a[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        a[k] = T(0);
-        for (int b = threadIdx.x; b < g; b += kBlock) {
-            const T p = part[(size_t)k * g + b];
-            a[k] = (b == (int)threadIdx.x) ? p : ops.template apply<T>(k, a[k], p);
-        }
-        a[k] = ops.template reduce_wave<T>(k, a[k]);   // xor butterfly: the same in every lane
+    for (int k = 0; k < NV; ++k) a[k] = T(0);
+    for (int b0 = threadIdx.x; b0 < g; b0 += kFoldLoads * kBlock) {
+        T p[NV][kFoldLoads];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int m = 0; m < kFoldLoads; ++m) {
+                const int b = b0 + m * kBlock;
+                p[k][m] = b < g ? part[(size_t)k * g + b] : T(0);
+            }
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int m = 0; m < kFoldLoads; ++m) {
+                const int b = b0 + m * kBlock;
+                if (b < g) a[k] = (b == (int)threadIdx.x) ? p[k][m] : ops.template apply<T>(k, a[k], p[k][m]);
+            }
     }
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        a[k] = ops.template reduce_wave<T>(k, a[k]);   // xor butterfly: the same in every lane
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
@@ -1257,10 +1275,15 @@ __device__ __forceinline__ void block_prefix_of_counts(const int32_t *cnt, int g
                                                        int &before, int &total) {
     __shared__ int red[2][kWaves];
     int a = 0, t = 0;
-    for (int b = threadIdx.x; b < g; b += kBlock) {
-        const int c = cnt[b];
-        t += c;
-        if (b < upto) a += c;
+    for (int b0 = threadIdx.x; b0 < g; b0 += kFoldLoads * kBlock) {
+        int c[kFoldLoads];   // loads in flight together, as in read_partials
+#pragma unroll
+        for (int m = 0; m < kFoldLoads; ++m) c[m] = b0 + m * kBlock < g ? cnt[b0 + m * kBlock] : 0;
+#pragma unroll
+        for (int m = 0; m < kFoldLoads; ++m) {
+            t += c[m];
+            if (b0 + m * kBlock < upto) a += c[m];
+        }
     }
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {

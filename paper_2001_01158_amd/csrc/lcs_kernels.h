@@ -87,7 +87,8 @@ __device__ __forceinline__ void diag_of(const Op &A, const typename Op::Unit &U,
     }
 }
 
-// partial-sum slots (each kMaxGrid x 4 doubles)
+// partial-sum slots (each kMaxGrid x 4 doubles: up to four values for each of
+// up to 1024 blocks, or one value for each of up to 4096)
 enum PartSlot { kPtScore = 0, kPtExp0, kPtExp1, kPtNorm, kPtRes, kPtAp, kPtUpd, kPtSgs, kPtSlots };
 constexpr size_t kSlotElems = (size_t)kMaxGrid * 4;
 
@@ -147,9 +148,9 @@ __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict
 
 // tau from the score partials: REL_MAX theta*max|s|, ABS theta,
 // PAPER theta*||b||_2/sqrt(N); then stamp_i = (|s_i| > tau) (strict), zero on
-// the padding [n, npad).  With eps0 >= 0, an x0 that already meets the
-// criterion ||r^(0)|| <= eps0 ||b|| (||b|| from sc->bnorm) marks nothing and
-// sets conv0.
+// the padding [n, npad).  With eps0 >= 0, ||b|| from the score partials goes
+// to sc->bnorm, and an x0 that already meets the criterion
+// ||r^(0)|| <= eps0 ||b|| marks nothing and sets conv0.
 __global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
                                                  uint8_t *__restrict__ stamp, int64_t n,
                                                  int64_t npad, int thresh, double theta,
@@ -161,8 +162,10 @@ __global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
     if (thresh == 0) tau = theta * tot[0];
     else if (thresh == 1) tau = theta;
     else tau = theta * sqrt(tot[1]) / sqrt((double)n);
-    const bool conv0 = eps0 >= 0.0 && sqrt(tot[2]) <= eps0 * sc->bnorm;
+    const double bn = sqrt(tot[1]);
+    const bool conv0 = eps0 >= 0.0 && sqrt(tot[2]) <= eps0 * bn;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (eps0 >= 0.0) sc->bnorm = bn;
         sc->ms.tau = tau;
         sc->ms.smax = tot[0];
         sc->ms.bb = tot[1];
@@ -171,9 +174,21 @@ __global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
         sc->ms.stop = 0;
         sc->ms.grown = 0;
     }
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < npad;
-         i += (int64_t)gridDim.x * kBlock)
-        stamp[i] = (!conv0 && i < n && fabs(s[i]) > tau) ? 1 : 0;
+    // eight stamps per thread and step, written as one 64-bit word (npad is a
+    // multiple of the 2048-stamp tile)
+    uint64_t *w = reinterpret_cast<uint64_t *>(stamp);
+    for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < npad / 8;
+         q += (int64_t)gridDim.x * kBlock) {
+        const int64_t i0 = q * 8;
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = i0 + k < n ? s[i0 + k] : 0.0;
+        uint64_t word = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (!conv0 && i0 + k < n && fabs(v[k]) > tau) word |= (uint64_t)1 << (8 * k);
+        w[q] = word;
+    }
 }
 
 // One synchronous expansion round m (Algorithm 3, eq. extend-local-condition):
@@ -1174,9 +1189,14 @@ __global__ __launch_bounds__(kBlock) void k_cast_scale(const double *__restrict_
 }
 
 // x += s * d32 in FP64 with the scale of the current refinement step
+// x += scale * d32: the FP64 update of one refinement step; skipped when the
+// inner solve of that step (saved_status[scope]) broke down or went
+// non-finite, so x keeps the last good iterate.
 __global__ __launch_bounds__(kBlock) void k_axpy_scaled(double *__restrict__ x,
                                                         const float *__restrict__ d32,
-                                                        int64_t n, const Scalars *sc) {
+                                                        int64_t n, const Scalars *sc, int scope) {
+    const int st = sc->saved_status[scope];
+    if (st == kStBreakdown || st == kStNonFinite) return;
     const double s = sc->scale;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)

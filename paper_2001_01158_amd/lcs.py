@@ -187,7 +187,7 @@ class Matrix:
 @dataclasses.dataclass
 class CsrMatrix:
     """General symmetric sparse matrix in CSR (columns strictly ascending in
-    each row, diagonal stored, 1..16 entries per row), optionally with a
+    each row, diagonal stored, 1..64 entries per row), optionally with a
     colouring for the Gauss-Seidel sweeps; see include/lcs.h."""
     row_ptr: torch.Tensor                  # int32 [N + 1], device
     col: torch.Tensor                      # int32 [nnz], device
@@ -199,7 +199,7 @@ class CsrMatrix:
                           # pointers and versions are those of this context's last call)
     nonsym: bool = False  # not symmetric: solves use GMRES(m)
     kind = CSR
-    max_row = 16
+    max_row = 64
     _seen: dict = dataclasses.field(default_factory=dict, repr=False, compare=False)
 
     def _signature(self):

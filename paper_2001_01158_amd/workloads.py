@@ -549,14 +549,18 @@ def mg_batch_nonsym(nx: int = 88, ny: int = 80, G: int = 64, dt: float = 1.0, si
 # General sparse input: an irregular graph over the cells of an nx x ny grid
 # ---------------------------------------------------------------------------
 def irregular_spd(nx: int, ny: int, seed: int, p_diag: float = 0.5, p_long: float = 0.1,
-                  sigma: float = 1.0, mass: float = 0.25):
+                  sigma: float = 1.0, mass: float = 0.25, hub_every: int = 0,
+                  hub_len: tuple = (17, 64)):
     """Symmetric, strictly diagonally dominant M-matrix on an irregular graph
     (a stand-in for an unstructured mesh): every cell couples to its four
     grid neighbours, to each diagonal neighbour with probability p_diag and
     to the cell two steps east or north with probability p_long, with
     log-normal weights; the diagonal is the sum of the weights plus mass.
-    At most 11 entries per row.  Returns CSR (rp int64, col int32 ascending,
-    val float64)."""
+    At most 11 entries per row.  With hub_every > 0, every hub_every-th cell
+    is a hub linked to random distant cells until its row holds a length
+    drawn from hub_len (rows of 17 to 64 entries, as around a vertex of high
+    degree), and no other row grows past 16 entries.  Returns CSR (rp int64,
+    col int32 ascending, val float64)."""
     rng = np.random.default_rng(seed)
     n = nx * ny
     rows = [dict() for _ in range(n)]
@@ -581,6 +585,17 @@ def irregular_spd(nx: int, ny: int, seed: int, p_diag: float = 0.5, p_long: floa
                 link(i, i + 2)
             if y + 2 < ny and rng.random() < p_long:
                 link(i, i + 2 * nx)
+    if hub_every > 0:
+        hubs = set(range(hub_every // 2, n, hub_every))
+        for h in sorted(hubs):
+            want = int(rng.integers(hub_len[0], hub_len[1] + 1)) - 1   # entries besides the diagonal
+            tries = 0
+            while len(rows[h]) < want and tries < 50 * want:
+                tries += 1
+                j = int(rng.integers(0, n))
+                if j == h or j in rows[h] or j in hubs or len(rows[j]) >= 15:
+                    continue
+                link(h, j)
     rp = np.zeros(n + 1, np.int64)
     cols, vals = [], []
     for i in range(n):

@@ -118,9 +118,10 @@ def test_workspace_bytes_without_gpu():
     # without a caller FP32 copy the library casts the five arrays itself
     b9c = nbytes(_fake_matrix(lcs, lcs.STENCIL9_2D, 1024, 1024, 1), om)
     assert abs((b9c - b9m) - 5 * 4 * n) < 4096
-    # general sparse input adds its ELL copy at width 16 (indices, values, diagonal, colour)
+    # general sparse input counts B and its own ELL copy at the largest width,
+    # 64 (indices, values, diagonal, colour)
     bc = nbytes(_fake_matrix(lcs, lcs.CSR, n, 1, 1), o)
-    per_row = 8 + 1 + 4 + 4 + 16 * 12 + 8 + 1 + 8 + 4 + 8 + 72 + 16 * 4 + 17 * 8 + 1
+    per_row = 8 + 1 + 4 + 4 + 64 * 12 + 8 + 1 + 8 + 4 + 8 + 72 + 64 * 4 + 65 * 8 + 1
     assert abs((bc - head) - per_row * n) < 64 * 1024, (bc - head) / n
     assert nbytes(_fake_matrix(lcs, lcs.STENCIL5_2D, 1024, 1024, 1), None) == b5
     # batched: four FP64 vectors, stamps and indices per cell and system, plus results

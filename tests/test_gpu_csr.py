@@ -1,6 +1,7 @@
 """GPU parity on general sparse input (LCS_CSR): irregular graphs with rows
-of up to 11 entries (ELL width 16) and of 5 entries (width 5), a nine-point
-stencil given as CSR, and degenerate sizes.  Per-row kernels, local domains
+of up to 11 entries (ELL width 16), of 5 entries (width 5) and with hub rows
+of 18 to 64 entries (width 64), a nine-point stencil given as CSR, and
+degenerate sizes.  Per-row kernels, local domains
 and the restricted system bit for bit against the oracle; global PCG and
 Algorithm 1 converged and at equal iteration counts; malformed structures
 rejected before any kernel reads through them."""
@@ -50,6 +51,8 @@ def make_case(name):
     """Oracle CSR, GPU CSR, b, x0: x_true smooth, x0 off it on a disk."""
     if name == "irr16":
         Ah, (nx, ny) = irregular(61, 47, 11)
+    elif name == "hub64":   # hub rows of 18..64 entries among rows of at most 16
+        Ah, (nx, ny) = irregular(61, 47, 14, hub_every=29)
     elif name == "irr8":
         Ah, (nx, ny) = irregular(53, 41, 12, p_diag=0.0, p_long=0.0)
     elif name == "grid7":   # 3-D seven-point stencil (red-black), planes stacked in y
@@ -70,7 +73,7 @@ def make_case(name):
     return Ah, gpu_matrix(Ah), b, x0
 
 
-CASES = ["irr16", "irr8", "grid9", "grid7"]   # ELL widths 16, 5, 9, 7
+CASES = ["irr16", "irr8", "grid9", "grid7", "hub64"]   # ELL widths 16, 5, 9, 7, 64
 
 
 @pytest.fixture(scope="module")
@@ -293,9 +296,9 @@ def _bad(kind):
     elif kind == "neg_diag":
         val[rp[6] + int(np.nonzero(col[rp[6]:rp[7]] == 6)[0][0])] = -2.0
     elif kind == "long_row":
-        m = 20
-        a = np.eye(m) * 30.0
-        a[0, 1:18] = a[1:18, 0] = -1.0     # row 0: 18 entries
+        m = 80
+        a = np.eye(m) * 100.0
+        a[0, 1:70] = a[1:70, 0] = -1.0     # row 0: 70 entries
         B = oracle.csr_from_dense(a)
         rp, col, val = B.rp, B.col, B.val
         colour, nc = W.greedy_colouring(rp, col)
