@@ -1125,28 +1125,43 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
     }
     // The outcome of each inner PCG (iterations, status) stays on the device
     // until the host reads the next FP64 residual: one host round trip per
-    // refinement step.
+    // refinement step.  The first step is enqueued before its residual is
+    // read: k_cast_scale turns it into a no-op (zero right-hand side, the
+    // inner solve stops at its first test, x unchanged) when that residual
+    // already meets the criterion or is non-finite, and the next read then
+    // ends the solve exactly as a read before the step would have.
     int pending = -1;   // refinement step whose inner outcome is not yet read
     auto settle = [&]() -> lcs_status {
         if (pending < 0) return LCS_OK;
         const int it = c->hsc->saved_it[scope];
-        out->its += it;
-        c->last_its[scope][std::min(pending, 3)] = it;
-        pending = -1;
         const int ps = c->hsc->saved_status[scope];
-        if (ps == kStBreakdown || ps == kStNonFinite) return status_of(ps);
+        const int step = pending;
+        pending = -1;
+        if (ps == kStBreakdown || ps == kStNonFinite) {
+            out->its += it;
+            return status_of(ps);
+        }
+        if (it == 0) {   // the no-op first step (a non-zero residual takes >= 1 iteration)
+            out->n_outer -= 1;
+            return LCS_OK;
+        }
+        out->its += it;
+        c->last_its[scope][std::min(step, 3)] = it;
         return LCS_OK;
     };
     for (int outer = 0;; ++outer) {
         LCS_TRY(launch_resnorm(c, A, rhs, x, r64, tol_base, tol_factor, s));
-        LCS_TRY(read_scalars(c, s));
-        LCS_TRY(settle());
-        out->rr = c->hsc->res.rr;
-        if (c->hsc->res.status != kStOk) return status_of(c->hsc->res.status);
-        if (c->hsc->res.done) return LCS_OK;
-        if (outer >= outer_cap || out->its >= o->max_iter) return status_of(kStNoConv);
+        const bool early = outer == 0 && o->max_iter > 0;
+        if (!early) {
+            LCS_TRY(read_scalars(c, s));
+            LCS_TRY(settle());
+            out->rr = c->hsc->res.rr;
+            if (c->hsc->res.status != kStOk) return status_of(c->hsc->res.status);
+            if (c->hsc->res.done) return LCS_OK;
+            if (outer >= outer_cap || out->its >= o->max_iter) return status_of(kStNoConv);
+        }
         hipLaunchKernelGGL(k_cast_scale, dim3(flat_grid(n)), dim3(kBlock), 0, s,
-                           (const double *)r64, r32, n, c->dsc);
+                           (const double *)r64, r32, n, c->dsc, early ? 1 : 0);
         LAUNCH_CHECK();
         PcgResult pr;
         c->cur_outer = outer;
@@ -1386,10 +1401,14 @@ struct is_pair9<U9<double, 2, W>> : std::true_type {};
 // n_sweeps colour-ordered Gauss-Seidel sweeps on A x = b (Algorithm 1 step
 // 7): one kernel per colour, or, for the nine-point stencil in strips of two
 // cells, one kernel per pair of colours (k_gs_pair9: rows of one parity)
-// through a second buffer.
+// through a second buffer.  With crit_eps >= 0 the nine-point path also
+// forms the criterion of step 8 (||b - A x|| <= crit_eps ||b||, into
+// dsc->res) in its last pass and sets *crit_done; other paths leave it to
+// the caller.
 template <class UOp>
 lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, int ncol,
-                         int n_sweeps, hipStream_t s) {
+                         int n_sweeps, hipStream_t s, double crit_eps = -1.0,
+                         bool *crit_done = nullptr) {
     const bool timed = c->prof_what == LCS_TIME_SMOOTH;
     if constexpr (is_pair9<UOp>::value) {
         if (ncol == 4) {
@@ -1400,11 +1419,32 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
             const int64_t tiles = strips * ((Au.ny + mh - 1) / mh);
             int grid = (int)std::min<int64_t>(kStreamGrid, (tiles + kWaves - 1) / kWaves);
             grid = std::max(kXcds, (grid + kXcds - 1) / kXcds * kXcds);
+            // the fused last pass: 62 owned strips per wave, and at most
+            // kMaxGrid blocks (its partials); tiles grow until every wave
+            // has at most one
+            const bool fuse = crit_eps >= 0.0 && n_sweeps > 0;
+            const int64_t strips_r = ((int64_t)Au.nx / 2 + kPairOwn - 1) / kPairOwn;
+            int mh_r = mh;
+            while (mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > (int64_t)kMaxGrid * kWaves)
+                ++mh_r;
+            const int64_t tiles_r = strips_r * ((Au.ny + mh_r - 1) / mh_r);
+            int grid_r = (int)std::min<int64_t>(kMaxGrid, (tiles_r + kWaves - 1) / kWaves);
+            grid_r = std::min(kMaxGrid, std::max(kXcds, (grid_r + kXcds - 1) / kXcds * kXcds));
             for (int sw = 0; sw < n_sweeps; ++sw) {
                 LCS_TRY(launch_maybe_timed(c, timed, k_gs_pair9<UOp>, grid, s, Au, b,
                                            (const double *)x, tmp, 0, mh));
-                LCS_TRY(launch_maybe_timed(c, timed, k_gs_pair9<UOp>, grid, s, Au, b,
-                                           (const double *)tmp, x, 1, mh));
+                if (fuse && sw == n_sweeps - 1) {
+                    LCS_TRY(launch_maybe_timed(c, timed, k_gs_pair9_res<UOp>, grid_r, s, Au, b,
+                                               (const double *)tmp, x, 1, mh_r, slot(c, kPtRes)));
+                    hipLaunchKernelGGL(k_fin_res, dim3(1), dim3(kBlock), 0, s,
+                                       (const double *)slot(c, kPtRes), grid_r,
+                                       (const double *)&c->dsc->bnorm, crit_eps, c->dsc);
+                    LAUNCH_CHECK();
+                    *crit_done = true;
+                } else {
+                    LCS_TRY(launch_maybe_timed(c, timed, k_gs_pair9<UOp>, grid, s, Au, b,
+                                               (const double *)tmp, x, 1, mh));
+                }
             }
             return LCS_OK;
         }
@@ -1423,7 +1463,7 @@ template <int W, class SOp, class UOp>
 lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp &Au,
                        const double *b, double *x, const int32_t *idx, int64_t K,
                        const int32_t *inv, const double *r0, const lcs_options *o,
-                       lcs_stats *st, Timers &tm, hipStream_t s) {
+                       lcs_stats *st, Timers &tm, hipStream_t s, bool *crit_done) {
     const int ncol = colours_of(M);
     if (K > 0) {
         if (!r0) {
@@ -1451,7 +1491,8 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         LAUNCH_CHECK();
     }
     LCS_TRY(tm.mark(2));
-    if (o->n_smooth > 0) LCS_TRY(launch_sweeps(c, Au, b, x, ncol, o->n_smooth, s));
+    *crit_done = false;
+    if (o->n_smooth > 0) LCS_TRY(launch_sweeps(c, Au, b, x, ncol, o->n_smooth, s, o->eps, crit_done));
     LCS_TRY(tm.mark(3));
     return LCS_OK;
 }
@@ -2030,9 +2071,11 @@ lcs_status lcs_solve_local(lcs_ctx *c, const lcs_matrix *A, const double *b, dou
         LCS_TRY(get_buf(c, B_INV, n, &inv));
         LCS_TRY(set_inv(c, idx, K, n, inv, s));
         LCS_TRY(tm.mark(1));
-        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, nullptr, o, st, tm, s));
-        LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
-                               o->eps, s));
+        bool crit = false;
+        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, nullptr, o, st, tm, s, &crit));
+        if (!crit)
+            LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr,
+                                   &c->dsc->bnorm, o->eps, s));
         LCS_TRY(read_scalars(c, s));
         LCS_TRY(flush_prof(c));
         LCS_TRY(finish_local(c, st));
@@ -2096,10 +2139,13 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         LCS_TRY(get_buf(c, B_SCORE, n, &score));
         LCS_TRY(get_buf(c, B_INV, n, &inv));
         if (mode == LCS_MODE_RESIDUAL) r0 = score;
-        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, r0, o, st, tm, s));
-        // criterion after the local solve and smoothing (Algorithm 1 step 8)
-        LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr, &c->dsc->bnorm,
-                               o->eps, s));
+        // criterion after the local solve and smoothing (Algorithm 1 step
+        // 8), formed in the last sweep pass where the sweep allows it
+        bool crit = false;
+        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, r0, o, st, tm, s, &crit));
+        if (!crit)
+            LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr,
+                                   &c->dsc->bnorm, o->eps, s));
         LCS_TRY(read_scalars(c, s));
         LCS_TRY(finish_local(c, st));
         st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->res.rr) / bn : std::sqrt(c->hsc->res.rr);

@@ -858,6 +858,146 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9(Op A, const double *__restr
     }
 }
 
+// The pass p of k_gs_pair9 fused with the criterion after it (Algorithm 1
+// step 8): besides the pass's output it forms r = b - A x over the whole grid
+// from the values the pass leaves, per cell with k_resnorm's FMA chain, and
+// writes k_resnorm's partials (||r||^2, max|r|) for k_fin_res.  Rows are
+// visited one at a time, up from y0 - 1 to y1: the tile's rows of parity p
+// are updated and stored, the others copied, and the residual of row y - 1
+// is formed once rows y - 2 .. y hold their final values.  The rows y0 - 1
+// and y1 belong to the neighbouring tiles; when they have parity p the tile
+// updates them too, without storing, so that its residuals read final
+// values only.  In a row, lanes 1..62 own strips; lanes 0 and 63 update the
+// strips on either side (the new value at x0 - 1 of lane 1 and at x0 + 2 of
+// lane 62) and store nothing.  Each row reads x, the five coefficient arrays
+// and b once (the south faces are carried), and writes x once.
+constexpr int kPairOwn = kWave - 2;
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__restrict__ b,
+                                                         const double *__restrict__ in,
+                                                         double *__restrict__ out, int parity,
+                                                         int mh, double *part) {
+    static_assert(Op::V == 2 && Op::NB == 9, "nine-point strips of two cells");
+    constexpr int V = 2;
+    using Unit = typename Op::Unit;
+    const int lane = threadIdx.x % kWave;
+    const int nx = A.nx, ny = A.ny;
+    const int64_t upr = nx / V;
+    const int64_t strips = (upr + kPairOwn - 1) / kPairOwn;
+    const int64_t tiles = strips * (int64_t)((ny + mh - 1) / mh);
+    double v[2] = {0.0, 0.0};
+    for (int64_t t = (int64_t)logical_block() * kWaves + threadIdx.x / kWave; t < tiles;
+         t += (int64_t)gridDim.x * kWaves) {
+        const int64_t strip = t % strips, seg = t / strips;
+        const int64_t xr = strip * kPairOwn + lane - 1;
+        const bool active = xr >= 0 && xr < upr;
+        const bool owner = active && lane >= 1 && lane <= kPairOwn;
+        // lanes outside the row load a valid strip; what they compute is
+        // read only for neighbours outside the grid, whose slots are invalid
+        const int xu = (int)(xr < 0 ? 0 : (xr >= upr ? upr - 1 : xr));
+        const int x0 = xu * V;
+        const int y0 = (int)seg * mh, y1 = min(ny, y0 + mh);
+        // carried: old rows y-1 and y of `in`; final rows y-2 and y-1; the
+        // coefficients and b of row y-1; the south faces of row y
+        double om[V + 2], oc[V + 2], fm2[V + 2], fm1[V + 2];
+        {
+            const int ya = y0 - 2, yb = y0 - 1;
+            const int64_t sa = (int64_t)max(ya, 0) * nx + x0, sb = (int64_t)max(yb, 0) * nx + x0;
+            row_load<double, V>(in, sa, sa, x0, nx, ya >= 0, true, om);
+            row_load<double, V>(in, sb, sb, x0, nx, yb >= 0, true, oc);
+        }
+#pragma unroll
+        for (int k = 0; k < V + 2; ++k) fm2[k] = fm1[k] = 0.0;
+        Unit Up;
+        double bp[V] = {0.0, 0.0};
+        typename Op::South S;
+        for (int y = y0 - 1; y <= y1; ++y) {
+            const bool real = y >= 0 && y < ny;
+            const int yn = y + 1;
+            const int64_t sn = (int64_t)min(max(yn, 0), ny - 1) * nx + x0;
+            double on[V + 2];
+            row_load<double, V>(in, sn, sn, x0, nx, yn >= 0 && yn < ny, true, on);
+            Unit U;
+            double bb[V] = {0.0, 0.0};
+            if (real) {
+                A.geom_walk(U, (int64_t)y * upr + xu, xu, y);
+                if (y == max(y0 - 1, 0)) A.south_init(S, U);
+                A.load_row(U, S);
+                vld<double, V>(b + U.i0, bb);
+            } else {
+                U.i0 = 0;
+                U.x0 = x0;
+                U.y = y;
+#pragma unroll
+                for (int q = 0; q < 9; ++q)
+#pragma unroll
+                    for (int k = 0; k < V; ++k) U.a[q][k] = 0.0;
+            }
+            double f0[V + 2];
+            if (real && (y & 1) == parity) {
+                // colour 2p, then 2p+1 with the new 2p values of its row
+                double nv[V];
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    double z[9];
+                    z[0] = om[k]; z[1] = om[k + 1]; z[2] = om[k + 2];
+                    z[3] = oc[k]; z[4] = oc[k + 1]; z[5] = oc[k + 2];
+                    z[6] = on[k]; z[7] = on[k + 1]; z[8] = on[k + 2];
+                    if (k == 1) {
+                        z[3] = nv[0];
+                        z[5] = __shfl_down(nv[0], 1, kWave);
+                    }
+                    double acc = bb[k], d = 1.0;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        if (!A.valid(U, q, k)) continue;
+                        if (q == Op::kC) d = U.a[q][k];
+                        else acc = fma(-U.a[q][k], z[q], acc);
+                    }
+                    nv[k] = acc / d;
+                }
+                f0[0] = __shfl_up(nv[1], 1, kWave);
+                f0[1] = nv[0];
+                f0[2] = nv[1];
+                f0[3] = __shfl_down(nv[0], 1, kWave);
+            } else {
+#pragma unroll
+                for (int k = 0; k < V + 2; ++k) f0[k] = oc[k];
+            }
+            if (owner && y >= y0 && y < y1) vst<double, V>(out + U.i0, {f0[1], f0[2]});
+            if (owner && y - 1 >= y0 && y - 1 < y1) {
+                // residual of row y-1 from the final rows y-2, y-1, y
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    double z[9];
+                    z[0] = fm2[k]; z[1] = fm2[k + 1]; z[2] = fm2[k + 2];
+                    z[3] = fm1[k]; z[4] = fm1[k + 1]; z[5] = fm1[k + 2];
+                    z[6] = f0[k];  z[7] = f0[k + 1];  z[8] = f0[k + 2];
+                    double acc = bp[k];
+#pragma unroll
+                    for (int q = 0; q < 9; ++q)
+                        if (A.valid(Up, q, k)) acc = fma(-Up.a[q][k], z[q], acc);
+                    v[0] += acc * acc;
+                    const double m = fabs(acc);
+                    v[1] = m > v[1] ? m : v[1];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < V + 2; ++k) {
+                fm2[k] = fm1[k];
+                fm1[k] = f0[k];
+                om[k] = oc[k];
+                oc[k] = on[k];
+            }
+            Up = U;
+#pragma unroll
+            for (int k = 0; k < V; ++k) bp[k] = bb[k];
+        }
+    }
+    write_partials<double, 2>(v, Ops<2u>(), part);
+}
+
 // ---------------------------------------------------------------------------
 // single-synchronisation PCG (Jacobi or none): one kernel per iteration
 // ---------------------------------------------------------------------------
@@ -1178,14 +1318,19 @@ __global__ __launch_bounds__(kBlock) void k_fin_norm(const double *part, int gpr
 // ---------------------------------------------------------------------------
 // r32 = (float)(r / s) with s = max|r| (keeps the FP32 residual near 1 and
 // clear of denormals); block 0 records s for the update.
+// With guard set, a residual that already met the criterion or went
+// non-finite (res.done) gives r32 = 0 and scale 0 instead: the inner solve
+// then stops at its first test and the update leaves x as it is, so the host
+// can enqueue a refinement step before it has read the residual.
 __global__ __launch_bounds__(kBlock) void k_cast_scale(const double *__restrict__ r,
                                                        float *__restrict__ r32, int64_t n,
-                                                       Scalars *sc) {
+                                                       Scalars *sc, int guard) {
+    const bool skip = guard && sc->res.done;
     const double s = sc->res.rmax > 0.0 ? sc->res.rmax : 1.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->scale = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->scale = skip ? 0.0 : s;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)
-        r32[i] = (float)(r[i] / s);
+        r32[i] = skip ? 0.0f : (float)(r[i] / s);
 }
 
 // x += s * d32 in FP64 with the scale of the current refinement step

@@ -146,6 +146,33 @@ def test_nine_point_paired_sweeps_bitexact(dims, ctx):
         assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("dims", [(1008, 2001), (264, 67), (252, 37), (128, 64), (132, 5), (4, 9),
+                                  (8, 1), (256, 2)])
+def test_nine_point_sweep_forms_the_criterion(dims, ctx):
+    """The last pass of Algorithm 1's nine-point sweep also forms the
+    criterion of step 8 (each wave owning 62 strips, with the rows next to
+    its tile updated again where they have the pass's parity): on an empty
+    domain, solve_local returns the oracle's colour-ordered sweeps bit for
+    bit, and the relative residual it reports is the oracle's residual of
+    that x up to the summation order."""
+    nx, ny = dims
+    coef = W.assemble_9pt(nx, ny, 0.25, 100.0, 30.0)
+    Ah = oracle.csr_from_stencil(W.KIND_9PT, nx, ny, 1, coef)
+    rng = np.random.default_rng(3 * nx + ny)
+    b = rng.random(nx * ny)
+    x0 = rng.random(nx * ny) - 0.5
+    A = lcs.matrix_from_numpy(W.KIND_9PT, nx, ny, 1, coef, DEV)
+    empty = torch.empty(0, dtype=torch.int32, device=DEV)
+    for sweeps in (1, 2):
+        say("sweep + criterion", dims, sweeps)
+        x = dev(x0)
+        st = lcs.solve_local(A, dev(b), x, empty, lcs.Options(eps=1e-10, n_smooth=sweeps), ctx=ctx)
+        xs = oracle.gs_sweeps(Ah, b, x0, sweeps)
+        assert np.array_equal(host(x), xs), sweeps
+        rel = np.linalg.norm(oracle.residual(Ah, b, xs)) / np.linalg.norm(b)
+        assert abs(st.relres_final - rel) <= 1e-13 * rel, (st.relres_final, rel)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv_fp64(name, ctx):
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
