@@ -155,7 +155,7 @@ enum BufId {
     B_ROWLEN, B_RP, B_COL, B_VAL, B_VAL32, B_DG, B_DG32, B_CLR, B_R32, B_D32, B_RI32, B_Z32,
     B_P32A, B_P32B, B_Q32, B_COEF32, B_CSRCOL, B_CSRVAL, B_W0, B_W1, B_S0, B_S1, B_W32A, B_W32B,
     B_S32A, B_S32B, B_BWS, B_BSTAMP, B_BIDX, B_BOUT, B_GMV, B_GMW0, B_GMW1, B_GMP0,
-    B_GMPN, B_GMS, B_BGMV, B_ACOL, B_AVAL, B_ACLR, B_AFLAGS, B_GSX, B_NUM
+    B_GMPN, B_GMS, B_BGMV, B_ACOL, B_AVAL, B_ACLR, B_AFLAGS, B_GSX, B_IDXB, B_CBLK, B_NUM
 };
 
 }  // namespace
@@ -179,6 +179,12 @@ struct lcs_ctx {
     hipEvent_t ev[5] = {};
     hipEvent_t chk[2] = {};
     hipEvent_t done_ev = nullptr;   // recorded by wait_for (null: block instead)
+    // rows of the restricted system blocked by colour during a local solve:
+    // colour q in [start[q], start[q + 1]); n = 0 when not blocked
+    struct {
+        int n = 0;
+        int64_t start[kMaxBlkColours + 1] = {};
+    } cblk;
     // iterations of the previous global (0) / local (1) PCG, by refinement
     // step (mixed precision) or restart (FP64), for sizing the first chunk
     int last_its[2][4] = {};
@@ -422,6 +428,10 @@ void plan_sizes(const lcs_matrix *A, const lcs_options *o, int what, int64_t G,
     if (what == kWhatSolve) {
         len[B_IDX] = n * i4;
         len[B_DL] = n * d;
+        if (o->precond == LCS_PC_RBSGS) {   // the colour-blocked domain
+            len[B_IDXB] = n * i4;
+            len[B_CBLK] = (size_t)kMaxBlkColours * kMaxGrid * i4;
+        }
         if (uses_gmres(A)) {
             const size_t m = (size_t)std::max(1, std::min(o->restart > 0 ? o->restart : 40, kMaxRestart));
             len[B_GMV] = (m + 1) * n * d;
@@ -766,6 +776,28 @@ lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<typename Op::re
     if (kPc != LCS_PC_RBSGS) return LCS_OK;
     real *part = slot_as<real>(c, kPtSgs);
     const Scalars *sc = c->dsc;
+    if constexpr (is_ell<Op>) {
+        // a restricted system with its rows blocked by colour: each half
+        // sweep reads its colour's rows only
+        const auto &cb = c->cblk;
+        if (cb.n == ncol && ncol >= 2 && cb.start[ncol] == A.n) {
+            for (int col = 1; col < ncol; ++col)
+                hipLaunchKernelGGL((k_gs_half_blk<Op, false>), dim3(grid), dim3(kBlock), 0, s, A,
+                                   (const real *)B.r, B.z, cb.start[col], cb.start[col + 1], sc, part);
+            for (int col = ncol - 2; col >= 0; --col) {
+                if (col == 0)
+                    hipLaunchKernelGGL((k_gs_half_blk<Op, true>), dim3(grid), dim3(kBlock), 0, s, A,
+                                       (const real *)B.r, B.z, cb.start[col], cb.start[col + 1], sc,
+                                       part);
+                else
+                    hipLaunchKernelGGL((k_gs_half_blk<Op, false>), dim3(grid), dim3(kBlock), 0, s,
+                                       A, (const real *)B.r, B.z, cb.start[col], cb.start[col + 1],
+                                       sc, part);
+            }
+            LAUNCH_CHECK();
+            return LCS_OK;
+        }
+    }
     // colour 0 of the forward sweep is done by the kernel that formed r.
     // One colour (a diagonal matrix with a one-class colouring): the backward
     // pass is colour 0 again, which reproduces z bit for bit and writes the
@@ -1315,7 +1347,7 @@ lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *
     else
         LCS_TRY(launch_maybe_timed(c, timed, k_score<UOp, 1>, gs, s, Au, b, x0, score,
                                    slot(c, kPtScore)));
-    const int gmark = std::min(flat_grid(T.npad / 8), 2048);
+    const int gmark = (int)std::min<int64_t>(T.npad / kTile, 2048);   // 2048 stamps per block step
     hipLaunchKernelGGL(k_mark, dim3(gmark), dim3(kBlock), 0, s, (const double *)score, stamp, n,
                        T.npad, thresh, theta, eps0, (const double *)slot(c, kPtScore), gs, c->dsc);
     LAUNCH_CHECK();
@@ -1472,8 +1504,34 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
             LCS_TRY(launch_resnorm(c, Au, b, (const double *)x, r, &c->dsc->bnorm, o->eps, s));
             r0 = r;
         }
+        // With the Gauss-Seidel preconditioner the rows of B go colour by
+        // colour (ascending inside each colour, slots still in ascending
+        // grid order): every row's arithmetic is unchanged, and a half sweep
+        // reads its own colour's rows only.
+        const int32_t *dom = idx;
+        struct ClearBlocks {
+            lcs_ctx *c;
+            ~ClearBlocks() { c->cblk.n = 0; }
+        } clear_blocks{c};
+        if (o->precond == LCS_PC_RBSGS && ncol >= 2 && ncol <= kMaxBlkColours && !uses_gmres(M)) {
+            int32_t *idxb, *cnt;
+            LCS_TRY(get_buf(c, B_IDXB, K, &idxb));
+            LCS_TRY(get_buf(c, B_CBLK, (size_t)kMaxBlkColours * kMaxGrid, &cnt));
+            const int g = (int)std::min<int64_t>(kMaxGrid, std::max<int64_t>(1, (K + 2047) / 2048));
+            const int64_t chunk = (K + g - 1) / g;
+            hipLaunchKernelGGL((k_cblk_count<SOp>), dim3(g), dim3(kBlock), 0, s, As, idx, K, chunk,
+                               ncol, cnt);
+            hipLaunchKernelGGL((k_cblk_place<SOp>), dim3(g), dim3(kBlock), 0, s, As, idx, K, chunk,
+                               ncol, (const int32_t *)cnt, idxb, const_cast<int32_t *>(inv), c->dsc);
+            LAUNCH_CHECK();
+            LCS_TRY(read_scalars(c, s));
+            if (c->hsc->cstart[ncol] != K) return fail(LCS_EHIP, "colour blocks do not cover the domain");
+            c->cblk.n = ncol;
+            for (int q = 0; q <= ncol; ++q) c->cblk.start[q] = c->hsc->cstart[q];
+            dom = idxb;
+        }
         Restricted<W> R;
-        LCS_TRY(gather<W>(c, As, idx, K, inv, r0, o->precision == LCS_PREC_MIXED, &R, s));
+        LCS_TRY(gather<W>(c, As, dom, K, inv, r0, o->precision == LCS_PREC_MIXED, &R, s));
         double *d;
         LCS_TRY(get_buf(c, B_DL, K, &d));
         const double tl = o->tol_local > 0 ? o->tol_local : o->eps;
@@ -1486,7 +1544,7 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         if (ls != LCS_OK && ls != LCS_ENOCONV) return ls;
         st->its_local = so.its;   // -1: read from the device state after the next sync
         st->n_outer += so.n_outer;
-        hipLaunchKernelGGL(k_scatter_add, dim3(flat_grid(K)), dim3(kBlock), 0, s, idx,
+        hipLaunchKernelGGL(k_scatter_add, dim3(flat_grid(K)), dim3(kBlock), 0, s, dom,
                            (const double *)d, K, x);
         LAUNCH_CHECK();
     }

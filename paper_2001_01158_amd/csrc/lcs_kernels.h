@@ -60,6 +60,7 @@ struct Scalars {
     double cg_gamma[2];       // single-synchronisation PCG: r_j.z_j by iteration parity
     double cg_alpha[2];       //                             alpha_j by iteration parity
     double scratch_norm;      // result of lcs_norm2_diff
+    int64_t cstart[9];        // colour-blocked domain: first position of each colour, then K
 };
 
 // Own value of a gathered vector and the diagonal: for the stencils the
@@ -174,20 +175,29 @@ __global__ __launch_bounds__(kBlock) void k_mark(const double *__restrict__ s,
         sc->ms.stop = 0;
         sc->ms.grown = 0;
     }
-    // eight stamps per thread and step, written as one 64-bit word (npad is a
-    // multiple of the 2048-stamp tile)
+    // A block handles 2048 stamps per step (npad is a multiple of that
+    // tile): the scores are read coalesced, eight per thread 256 apart, the
+    // stamp bytes go through LDS, and each thread writes eight consecutive
+    // stamps as one 64-bit word.
+    __shared__ uint64_t tw[kBlock];
+    uint8_t *tile = reinterpret_cast<uint8_t *>(tw);
     uint64_t *w = reinterpret_cast<uint64_t *>(stamp);
-    for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < npad / 8;
-         q += (int64_t)gridDim.x * kBlock) {
-        const int64_t i0 = q * 8;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock * 8; base < npad;
+         base += (int64_t)gridDim.x * kBlock * 8) {
         double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = i0 + k < n ? s[i0 + k] : 0.0;
-        uint64_t word = 0;
+        for (int m = 0; m < 8; ++m) {
+            const int64_t i = base + m * kBlock + threadIdx.x;
+            v[m] = i < n ? s[i] : 0.0;
+        }
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (!conv0 && i0 + k < n && fabs(v[k]) > tau) word |= (uint64_t)1 << (8 * k);
-        w[q] = word;
+        for (int m = 0; m < 8; ++m) {
+            const int64_t i = base + m * kBlock + threadIdx.x;
+            tile[m * kBlock + threadIdx.x] = (!conv0 && i < n && fabs(v[m]) > tau) ? 1 : 0;
+        }
+        __syncthreads();
+        w[base / 8 + threadIdx.x] = tw[threadIdx.x];
+        __syncthreads();
     }
 }
 
@@ -397,6 +407,92 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict
             p += loc[k];
         }
         off += tt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// colour-blocked order of a domain (for the Gauss-Seidel preconditioner)
+// ---------------------------------------------------------------------------
+// The rows of the restricted system can be put colour by colour, ascending
+// inside each colour, so that a colour's half sweep streams only its own
+// rows.  Block b takes a contiguous chunk of the ascending domain idx:
+// k_cblk_count stores how many of its cells have each colour, and
+// k_cblk_place puts cell idx[k] at (cells of lower colours) + (cells of its
+// colour in lower blocks) + (its rank among them in its block), writes the
+// blocked domain and inv, and the first position of each colour (then K) to
+// sc->cstart.
+constexpr int kMaxBlkColours = 8;
+
+template <class SOp>
+__global__ __launch_bounds__(kBlock) void k_cblk_count(SOp A, const int32_t *__restrict__ idx,
+                                                       int64_t K, int64_t chunk, int ncol,
+                                                       int32_t *__restrict__ cnt) {
+    __shared__ int red[kMaxBlkColours][kWaves];
+    const int64_t k0 = (int64_t)blockIdx.x * chunk;
+    const int64_t k1 = k0 + chunk < K ? k0 + chunk : K;
+    int c[kMaxBlkColours];
+#pragma unroll
+    for (int q = 0; q < kMaxBlkColours; ++q) c[q] = 0;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlock) {
+        const int col = A.colour(idx[k]);
+#pragma unroll
+        for (int q = 0; q < kMaxBlkColours; ++q) c[q] += col == q ? 1 : 0;
+    }
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < kMaxBlkColours; ++q) {
+        const int t = wave_reduce(c[q], OpSum());
+        if ((threadIdx.x & (kWave - 1)) == 0) red[q][w] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < ncol) {
+        int t = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) t += red[threadIdx.x][q];
+        cnt[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+template <class SOp>
+__global__ __launch_bounds__(kBlock) void k_cblk_place(SOp A, const int32_t *__restrict__ idx,
+                                                       int64_t K, int64_t chunk, int ncol,
+                                                       const int32_t *__restrict__ cnt,
+                                                       int32_t *__restrict__ idxb,
+                                                       int32_t *__restrict__ inv, Scalars *sc) {
+    int64_t base[kMaxBlkColours];
+    int64_t lower = 0;   // cells of the colours below q
+#pragma unroll
+    for (int q = 0; q < kMaxBlkColours; ++q) {
+        base[q] = 0;
+        if (q < ncol) {
+            int before = 0, total = 0;
+            block_prefix_of_counts(cnt + (int64_t)q * gridDim.x, gridDim.x, blockIdx.x, before,
+                                   total);
+            base[q] = lower + before;
+            if (blockIdx.x == 0 && threadIdx.x == 0) sc->cstart[q] = lower;
+            lower += total;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->cstart[ncol] = lower;
+    const int64_t k0 = (int64_t)blockIdx.x * chunk;
+    const int64_t k1 = k0 + chunk < K ? k0 + chunk : K;
+    for (int64_t t0 = k0; t0 < k1; t0 += kBlock) {
+        const int64_t k = t0 + threadIdx.x;
+        const int32_t i = k < k1 ? idx[k] : 0;
+        const int col = k < k1 ? A.colour(i) : -1;
+#pragma unroll
+        for (int q = 0; q < kMaxBlkColours; ++q) {
+            if (q < ncol) {
+                int tot = 0;
+                const int pre = block_exclusive_scan(col == q ? 1 : 0, tot);
+                if (col == q) {
+                    const int64_t pos = base[q] + pre;
+                    idxb[pos] = i;
+                    inv[i] = (int32_t)pos;
+                }
+                base[q] += tot;
+            }
+        }
     }
 }
 
@@ -761,6 +857,47 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const typename Op::rea
             if (kRz) v[0] += ro[k] * zo[k];
         }
         if (any) A.put(U, z, zo);
+    }
+    if (kRz) write_partials<real, 1>(v, Ops<0u>(), part_sgs);
+}
+
+// The half sweep of colour c on a restricted system whose rows are blocked
+// by colour (rows [a, b) have colour c): only those rows are read and
+// updated, each with k_gs_half's arithmetic, so the z it leaves is the same
+// bit for bit.  With kRz the kernel visits every row for the r.z partials
+// (the other rows read r and z only).
+template <class Op, bool kRz>
+__global__ __launch_bounds__(kBlock) void k_gs_half_blk(Op A, const typename Op::real *__restrict__ r,
+                                                        typename Op::real *z, int64_t a, int64_t b,
+                                                        const Scalars *sc, typename Op::real *part_sgs) {
+    using real = typename Op::real;
+    constexpr int NB = Op::NB;
+    static_assert(Op::V == 1, "rows of the restricted system");
+    if (sc->pcg.done) return;
+    real v[1] = {real(0)};
+    const int64_t off = kRz ? 0 : a;
+    const Band B = my_band(kRz ? A.n : b - a);
+    for (int64_t u = B.u; u < B.end; u += B.step) {
+        const int64_t i = u + off;
+        if (!kRz || (i >= a && i < b)) {
+            typename Op::Unit U;
+            A.load(U, i);
+            real zv[NB][1], ro[1], zo[1];
+            A.gather(U, (const real *)z, zv);
+            A.own(U, r, ro);
+            real acc = ro[0], d = real(1);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (!A.valid(U, q, 0)) continue;
+                if (A.is_diag(U, q, 0)) d = U.a[q][0];
+                else acc = fma(-U.a[q][0], zv[q][0], acc);
+            }
+            zo[0] = acc / d;
+            A.put(U, z, zo);
+            if (kRz) v[0] += ro[0] * zo[0];
+        } else {
+            v[0] += r[i] * z[i];
+        }
     }
     if (kRz) write_partials<real, 1>(v, Ops<0u>(), part_sgs);
 }
