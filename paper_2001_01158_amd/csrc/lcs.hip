@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -934,23 +935,29 @@ int &last_its_of(lcs_ctx *c, int scope) { return c->last_its[scope][std::min(c->
 // Single-synchronisation PCG (Jacobi / none): k_cg_init1, k_cg_init2, then
 // one k_cg_iter per iteration; the stopping test of x_j runs at the start of
 // iteration j.  Buffers: r, w, s double-buffered by iteration parity.
+// prepared: the caller already zeroed x, put rhs into B.r and reset the PCG
+// state (k_refine_start), so the solve starts at k_cg_init2.  save: keep
+// the outcome in saved_it / saved_status[scope] here (else the caller's
+// next kernel does, as k_axpy_scaled does).
 template <class Op, int kPc>
 lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typename Op::real *x,
                    bool x_zero, const double *tol_base, double tol_factor, int max_iter,
                    int check_every, const PcgBufs<typename Op::real> &B, hipStream_t s,
-                   PcgResult *res, int scope, bool sync_end) {
+                   PcgResult *res, int scope, bool sync_end, bool save, bool prepared) {
     using real = typename Op::real;
     const int64_t n = A.units() * Op::V;
     const int grid = grid_for(A, kRedGrid);
     real *part[2] = {slot_as<real>(c, kPtAp), slot_as<real>(c, kPtUpd)};
     real *r[2] = {B.r, B.z}, *w[2] = {B.w0, B.w1}, *sv[2] = {B.s0, B.s1};
     if (max_iter < 0) max_iter = 0;
-    if (x_zero) {
-        hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, real(0), n);
-        LAUNCH_CHECK();
+    if (!prepared) {
+        if (x_zero) {
+            hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, real(0), n);
+            LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL((k_cg_init1<Op>), dim3(grid), dim3(kBlock), 0, s, A, rhs,
+                           (const real *)x, r[0], x_zero ? 1 : 0, c->dsc);
     }
-    hipLaunchKernelGGL((k_cg_init1<Op>), dim3(grid), dim3(kBlock), 0, s, A, rhs, (const real *)x,
-                       r[0], x_zero ? 1 : 0, c->dsc);
     hipLaunchKernelGGL((k_cg_init2<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A,
                        (const real *)r[0], w[0], part[0]);
     LAUNCH_CHECK();
@@ -964,8 +971,10 @@ lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typena
                                   c->dsc, (const real *)part[a], part[b]);
     };
     LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter));
-    hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
-    LAUNCH_CHECK();
+    if (save) {
+        hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
+        LAUNCH_CHECK();
+    }
     if (!sync_end) {
         res->its = -1;
         res->status = kStOk;
@@ -982,7 +991,7 @@ template <class Op, int kPc>
 lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real *rhs,
                      typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
                      int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
-                     hipStream_t s, PcgResult *res, int scope, bool sync_end) {
+                     hipStream_t s, PcgResult *res, int scope, bool sync_end, bool save) {
     using real = typename Op::real;
     const int64_t n = A.units() * Op::V;
     const int grid = grid_for(A, kRedGrid);
@@ -1022,8 +1031,10 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
         return LCS_OK;
     };
     LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter));
-    hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
-    LAUNCH_CHECK();
+    if (save) {
+        hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
+        LAUNCH_CHECK();
+    }
     if (!sync_end) {   // the caller reads saved_it / saved_status later
         res->its = -1;
         res->status = kStOk;
@@ -1040,17 +1051,18 @@ template <class Op>
 lcs_status run_pcg(lcs_ctx *c, const Op &A, int ncol, int pc, const typename Op::real *rhs,
                    typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
                    int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
-                   hipStream_t s, PcgResult *res, int scope, bool sync_end) {
+                   hipStream_t s, PcgResult *res, int scope, bool sync_end, bool save = true,
+                   bool prepared = false) {
     switch (pc) {
     case LCS_PC_NONE:
         return run_cg1<Op, 0>(c, A, rhs, x, x_zero, tol_base, tol_factor, max_iter, check_every, B,
-                              s, res, scope, sync_end);
+                              s, res, scope, sync_end, save, prepared);
     case LCS_PC_JACOBI:
         return run_cg1<Op, 1>(c, A, rhs, x, x_zero, tol_base, tol_factor, max_iter, check_every, B,
-                              s, res, scope, sync_end);
-    default:
+                              s, res, scope, sync_end, save, prepared);
+    default:   // the caller never prepares this one (k_pcg_init also starts z)
         return run_pcg_t<Op, 2>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                check_every, B, s, res, scope, sync_end);
+                                check_every, B, s, res, scope, sync_end, save);
     }
 }
 
@@ -1158,10 +1170,11 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
     // The outcome of each inner PCG (iterations, status) stays on the device
     // until the host reads the next FP64 residual: one host round trip per
     // refinement step.  The first step is enqueued before its residual is
-    // read: k_cast_scale turns it into a no-op (zero right-hand side, the
-    // inner solve stops at its first test, x unchanged) when that residual
-    // already meets the criterion or is non-finite, and the next read then
-    // ends the solve exactly as a read before the step would have.
+    // read: k_refine_start (or k_cast_scale) turns it into a no-op (zero
+    // right-hand side, the inner solve stops at its first test, x unchanged)
+    // when that residual already meets the criterion or is non-finite, and
+    // the next read then ends the solve exactly as a read before the step
+    // would have.
     int pending = -1;   // refinement step whose inner outcome is not yet read
     auto settle = [&]() -> lcs_status {
         if (pending < 0) return LCS_OK;
@@ -1192,16 +1205,23 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
             if (c->hsc->res.done) return LCS_OK;
             if (outer >= outer_cap || out->its >= o->max_iter) return status_of(kStNoConv);
         }
-        hipLaunchKernelGGL(k_cast_scale, dim3(flat_grid(n)), dim3(kBlock), 0, s,
-                           (const double *)r64, r32, n, c->dsc, early ? 1 : 0);
+        // the single-sync PCG starts from k_refine_start's r_0; the
+        // Gauss-Seidel-preconditioned one from the scaled right-hand side
+        const bool prep = o->precond != LCS_PC_RBSGS;
+        if (prep)
+            hipLaunchKernelGGL(k_refine_start, dim3(flat_grid(n)), dim3(kBlock), 0, s,
+                               (const double *)r64, B.r, d32, n, c->dsc, early ? 1 : 0);
+        else
+            hipLaunchKernelGGL(k_cast_scale, dim3(flat_grid(n)), dim3(kBlock), 0, s,
+                               (const double *)r64, r32, n, c->dsc, early ? 1 : 0);
         LAUNCH_CHECK();
         PcgResult pr;
         c->cur_outer = outer;
         LCS_TRY(run_pcg(c, A32, ncol, o->precond, (const float *)r32, d32, true,
                         (const double *)nullptr, inner, o->max_iter - out->its, check, B, s, &pr,
-                        scope, false));
+                        scope, false, false, prep));
         hipLaunchKernelGGL(k_axpy_scaled, dim3(flat_grid(n)), dim3(kBlock), 0, s, x,
-                           (const float *)d32, n, (const Scalars *)c->dsc, scope);
+                           (const float *)d32, n, c->dsc, scope);
         LAUNCH_CHECK();
         pending = outer;
         out->n_outer += 1;
@@ -1452,13 +1472,25 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
             int grid = (int)std::min<int64_t>(kStreamGrid, (tiles + kWaves - 1) / kWaves);
             grid = std::max(kXcds, (grid + kXcds - 1) / kXcds * kXcds);
             // the fused last pass: 62 owned strips per wave, and at most
-            // kMaxGrid blocks (its partials); tiles grow until every wave
-            // has at most one
+            // kMaxGrid blocks (its partials); tiles grow until there is at
+            // most one per wave that the GPU holds at once (its occupancy,
+            // asked of the runtime once), so that no wave waits for a
+            // second round
             const bool fuse = crit_eps >= 0.0 && n_sweeps > 0;
+            static std::atomic<int64_t> resident{0};
+            if (fuse && resident.load() == 0) {
+                int nb = 0, cus = 0, dev = 0;
+                HIP_TRY(hipGetDevice(&dev));
+                HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gs_pair9_res<UOp>,
+                                                                     kBlock, 0));
+                resident.store(std::max<int64_t>(1, (int64_t)nb * cus) * kWaves);
+            }
+            const int64_t waves_r = std::min<int64_t>((int64_t)kMaxGrid * kWaves,
+                                                      std::max<int64_t>(kWaves, resident.load()));
             const int64_t strips_r = ((int64_t)Au.nx / 2 + kPairOwn - 1) / kPairOwn;
             int mh_r = mh;
-            while (mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > (int64_t)kMaxGrid * kWaves)
-                ++mh_r;
+            while (mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > waves_r) ++mh_r;
             const int64_t tiles_r = strips_r * ((Au.ny + mh_r - 1) / mh_r);
             int grid_r = (int)std::min<int64_t>(kMaxGrid, (tiles_r + kWaves - 1) / kWaves);
             grid_r = std::min(kMaxGrid, std::max(kXcds, (grid_r + kXcds - 1) / kXcds * kXcds));

@@ -1000,8 +1000,10 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9(Op A, const double *__restr
 // from the values the pass leaves, per cell with k_resnorm's FMA chain, and
 // writes k_resnorm's partials (||r||^2, max|r|) for k_fin_res.  Rows are
 // visited one at a time, up from y0 - 1 to y1: the tile's rows of parity p
-// are updated and stored, the others copied, and the residual of row y - 1
-// is formed once rows y - 2 .. y hold their final values.  The rows y0 - 1
+// are updated and stored, the others copied; a row's residual takes its
+// slots 0..5 once the row itself is final and slots 6..8 one step later,
+// which keeps k_resnorm's order and carries two values instead of the
+// row's coefficients.  The rows y0 - 1
 // and y1 belong to the neighbouring tiles; when they have parity p the tile
 // updates them too, without storing, so that its residuals read final
 // values only.  In a row, lanes 1..62 own strips; lanes 0 and 63 update the
@@ -1035,9 +1037,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__r
         const int xu = (int)(xr < 0 ? 0 : (xr >= upr ? upr - 1 : xr));
         const int x0 = xu * V;
         const int y0 = (int)seg * mh, y1 = min(ny, y0 + mh);
-        // carried: old rows y-1 and y of `in`; final rows y-2 and y-1; the
-        // coefficients and b of row y-1; the south faces of row y
-        double om[V + 2], oc[V + 2], fm2[V + 2], fm1[V + 2];
+        // carried: old rows y-1 and y of `in`; the final row y-1; the
+        // south faces of row y (the N, NE, NW arrays of row y-1); and row
+        // y-1's residual over its slots 0..5, finished with slots 6..8 once
+        // row y holds its final values
+        double om[V + 2], oc[V + 2], fm1[V + 2], accp[V];
         {
             const int ya = y0 - 2, yb = y0 - 1;
             const int64_t sa = (int64_t)max(ya, 0) * nx + x0, sb = (int64_t)max(yb, 0) * nx + x0;
@@ -1045,31 +1049,38 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__r
             row_load<double, V>(in, sb, sb, x0, nx, yb >= 0, true, oc);
         }
 #pragma unroll
-        for (int k = 0; k < V + 2; ++k) fm2[k] = fm1[k] = 0.0;
-        Unit Up;
-        double bp[V] = {0.0, 0.0};
+        for (int k = 0; k < V + 2; ++k) fm1[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) accp[k] = 0.0;
         typename Op::South S;
+#pragma unroll
+        for (int k = 0; k < V; ++k) S.n[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k <= V; ++k) S.ne[k] = S.nw[k] = 0.0;
         for (int y = y0 - 1; y <= y1; ++y) {
             const bool real = y >= 0 && y < ny;
             const int yn = y + 1;
             const int64_t sn = (int64_t)min(max(yn, 0), ny - 1) * nx + x0;
             double on[V + 2];
             row_load<double, V>(in, sn, sn, x0, nx, yn >= 0 && yn < ny, true, on);
+            // slots 6..8 (NW, N, NE) of row y-1, before row y's load moves
+            // the south faces on
+            double a6[V], a7[V], a8[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                a6[k] = S.nw[k];
+                a7[k] = S.n[k];
+                a8[k] = S.ne[k + 1];
+            }
             Unit U;
+            U.x0 = x0;
+            U.y = y;
             double bb[V] = {0.0, 0.0};
             if (real) {
                 A.geom_walk(U, (int64_t)y * upr + xu, xu, y);
                 if (y == max(y0 - 1, 0)) A.south_init(S, U);
                 A.load_row(U, S);
                 vld<double, V>(b + U.i0, bb);
-            } else {
-                U.i0 = 0;
-                U.x0 = x0;
-                U.y = y;
-#pragma unroll
-                for (int q = 0; q < 9; ++q)
-#pragma unroll
-                    for (int k = 0; k < V; ++k) U.a[q][k] = 0.0;
             }
             double f0[V + 2];
             if (real && (y & 1) == parity) {
@@ -1104,32 +1115,40 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__r
             }
             if (owner && y >= y0 && y < y1) vst<double, V>(out + U.i0, {f0[1], f0[2]});
             if (owner && y - 1 >= y0 && y - 1 < y1) {
-                // residual of row y-1 from the final rows y-2, y-1, y
+                // row y-1's residual: its slots 6..8 over the final row y
+                Unit Ug;
+                Ug.x0 = x0;
+                Ug.y = y - 1;
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
-                    double z[9];
-                    z[0] = fm2[k]; z[1] = fm2[k + 1]; z[2] = fm2[k + 2];
-                    z[3] = fm1[k]; z[4] = fm1[k + 1]; z[5] = fm1[k + 2];
-                    z[6] = f0[k];  z[7] = f0[k + 1];  z[8] = f0[k + 2];
-                    double acc = bp[k];
-#pragma unroll
-                    for (int q = 0; q < 9; ++q)
-                        if (A.valid(Up, q, k)) acc = fma(-Up.a[q][k], z[q], acc);
+                    double acc = accp[k];
+                    if (A.valid(Ug, 6, k)) acc = fma(-a6[k], f0[k], acc);
+                    if (A.valid(Ug, 7, k)) acc = fma(-a7[k], f0[k + 1], acc);
+                    if (A.valid(Ug, 8, k)) acc = fma(-a8[k], f0[k + 2], acc);
                     v[0] += acc * acc;
                     const double m = fabs(acc);
                     v[1] = m > v[1] ? m : v[1];
                 }
             }
+            // row y's residual over its slots 0..5 (the final rows y-1, y),
+            // in k_resnorm's order
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                double z[6];
+                z[0] = fm1[k]; z[1] = fm1[k + 1]; z[2] = fm1[k + 2];
+                z[3] = f0[k];  z[4] = f0[k + 1];  z[5] = f0[k + 2];
+                double acc = bb[k];
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+                    if (real && A.valid(U, q, k)) acc = fma(-U.a[q][k], z[q], acc);
+                accp[k] = acc;
+            }
 #pragma unroll
             for (int k = 0; k < V + 2; ++k) {
-                fm2[k] = fm1[k];
                 fm1[k] = f0[k];
                 om[k] = oc[k];
                 oc[k] = on[k];
             }
-            Up = U;
-#pragma unroll
-            for (int k = 0; k < V; ++k) bp[k] = bb[k];
         }
     }
     write_partials<double, 2>(v, Ops<2u>(), part);
@@ -1470,14 +1489,41 @@ __global__ __launch_bounds__(kBlock) void k_cast_scale(const double *__restrict_
         r32[i] = skip ? 0.0f : (float)(r[i] / s);
 }
 
-// x += s * d32 in FP64 with the scale of the current refinement step
+// The start of one refinement step's inner solve with the single-sync PCG,
+// in one pass: k_cast_scale's scaled right-hand side (same guard) written
+// straight into r_0 (the inner solve starts from x = 0, so r_0 = rhs), the
+// inner x zeroed, and the PCG state reset as k_cg_init1 resets it.
+__global__ __launch_bounds__(kBlock) void k_refine_start(const double *__restrict__ r,
+                                                         float *__restrict__ r0,
+                                                         float *__restrict__ x32, int64_t n,
+                                                         Scalars *sc, int guard) {
+    const bool skip = guard && sc->res.done;
+    const double s = sc->res.rmax > 0.0 ? sc->res.rmax : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->scale = skip ? 0.0 : s;
+        sc->pcg.done = 0;
+        sc->pcg.status = kStOk;
+        sc->pcg.it = 0;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        r0[i] = skip ? 0.0f : (float)(r[i] / s);
+        x32[i] = 0.0f;
+    }
+}
+
 // x += scale * d32: the FP64 update of one refinement step; skipped when the
-// inner solve of that step (saved_status[scope]) broke down or went
-// non-finite, so x keeps the last good iterate.
+// inner solve of that step broke down or went non-finite, so x keeps the
+// last good iterate.  Also keeps the inner solve's outcome in
+// saved_it / saved_status[scope] (k_save_pcg's work).
 __global__ __launch_bounds__(kBlock) void k_axpy_scaled(double *__restrict__ x,
                                                         const float *__restrict__ d32,
-                                                        int64_t n, const Scalars *sc, int scope) {
-    const int st = sc->saved_status[scope];
+                                                        int64_t n, Scalars *sc, int scope) {
+    const int st = sc->pcg.done ? sc->pcg.status : kStNoConv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->saved_it[scope] = sc->pcg.it;
+        sc->saved_status[scope] = st;
+    }
     if (st == kStBreakdown || st == kStNonFinite) return;
     const double s = sc->scale;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
