@@ -41,6 +41,9 @@ MEASURED_TRAFFIC = {
     "k_cg_iter<UEll<double,5>,1>": {
         "ratio": 1.142, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
         "src_sha256": "c9d8c854e7bdcbd20397fde8f361aa5f6f5c88a1df77dab53006d667df51b507"},
+    "k_cg_iter<UEll<float,9>,1>": {
+        "ratio": 1.000, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "9ff9b4f8e87ea80dc67bf7bf30c9e41ac4091cb5fd31818b1c428e3bcbf570b3"},
 }
 KERNEL_SOURCES = ["paper_2001_01158_amd/csrc/lcs_device.h", "paper_2001_01158_amd/csrc/lcs_kernels.h"]
 
@@ -69,6 +72,12 @@ def parse():
     p.add_argument("--inner-tol", type=float,
                    help="relative tolerance of the FP32 inner PCG of each refinement step "
                         "(default 1e-5)")
+    p.add_argument("--no-colour-blocks", action="store_true",
+                   help="under RB-SGS keep the restricted systems' rows in the domain's ascending "
+                        "order instead of colour by colour (lcs_set_colour_blocking)")
+    p.add_argument("--headline-legs", action="store_true",
+                   help="time only the headline leg (Algorithm 1) and the global PCG (no other "
+                        "legs, no 1024^2 extra, no adjoint)")
     p.add_argument("--csr", nargs="?", const="copy", choices=["copy", "reuse"],
                    help="hand the workload's matrix to the library in CSR (general sparse "
                         "input) instead of as a stencil (c6: non-symmetric, GMRES).  copy: every "
@@ -101,6 +110,9 @@ def parse():
                    help="--summarize: the kernel (name prefix, as the profiler prints it)")
     p.add_argument("--mark", default="k_score<U9<double, 2, 2>, 0>",
                    help="--summarize: the kernel launched once at the start of each system")
+    p.add_argument("--end-mark",
+                   help="--summarize: a kernel of the next leg (ends the window when the run has "
+                        "no system after it)")
     return p.parse_args()
 
 
@@ -141,7 +153,7 @@ def make_workload(name):
     return w, opts, desc, src
 
 
-def summarize(d: str, steps: int, warmup: int, kernel: str, mark: str):
+def summarize(d: str, steps: int, warmup: int, kernel: str, mark: str, end_mark: str | None = None):
     """Markdown summary of rocprofv3 output under d (trace/, fetch/, write/
     as written by the commands in profiles/): the kernel statistics of the
     traced run, and for the kernel whose name starts with `kernel` its
@@ -150,7 +162,10 @@ def summarize(d: str, steps: int, warmup: int, kernel: str, mark: str):
     whose name starts with `mark`), with its FETCH_SIZE / WRITE_SIZE traffic
     per working dispatch scaled by the 512 MiB copy calibration.  Dispatches
     that exit at once after convergence (traffic under 1 % of the largest)
-    are counted apart."""
+    are counted apart.  end_mark: when the run has no system after the
+    window (only warmup + steps marks), the window ends at the first
+    dispatch whose name starts with end_mark after the last mark.  With
+    FETCH_SIZE alone (no write/ run) the fetch per dispatch is reported."""
     import csv
     import glob
 
@@ -177,6 +192,10 @@ def summarize(d: str, steps: int, warmup: int, kernel: str, mark: str):
             return []
         t0 = marks[warmup]
         t1 = marks[warmup + steps] if len(marks) > warmup + steps else float("inf")
+        if t1 == float("inf") and end_mark:
+            later = [int(r[ts_key]) for r in recs if short(r[name_key]).startswith(end_mark)
+                     and int(r[ts_key]) > marks[warmup + steps - 1]]
+            t1 = min(later) if later else t1
         return [r for r in recs if is_k(r[name_key]) and t0 <= int(r[ts_key]) < t1]
 
     trace = rows("trace/*kernel_trace.csv")
@@ -194,6 +213,16 @@ def summarize(d: str, steps: int, warmup: int, kernel: str, mark: str):
                            f"{sum(map(dur, win)) / 1e3:.3f} ms ({sum(map(dur, win)) / 1e3 / steps:.3f} ms "
                            f"per system)")
     fetch, write = rows("fetch/*counter_collection.csv"), rows("write/*counter_collection.csv")
+    if fetch and not write:
+        copy = max(float(r["Counter_Value"]) for r in fetch if "copyBuffer" in r["Kernel_Name"])
+        f_fetch = 512 * 1024 / copy
+        wf = window(fetch, "Kernel_Name", "Start_Timestamp")
+        if wf:
+            kib = sum(float(r["Counter_Value"]) for r in wf) / len(wf)
+            out.append("")
+            out.append(f"calibration (512 MiB device copy): FETCH_SIZE x{f_fetch:.3f}")
+            out.append(f"`{kernel}` over the first leg's timed pass: {len(wf)} dispatches, FETCH "
+                       f"{kib:.1f} KiB -> {kib * f_fetch * 1024 / 1e6:.3f} MB per dispatch (calibrated)")
     if fetch and write:
         copy = lambda rs: max(float(r["Counter_Value"]) for r in rs if "copyBuffer" in r["Kernel_Name"])
         f_fetch = 512 * 1024 / copy(fetch)
@@ -262,7 +291,7 @@ def csr_input(kind: int, nx: int, ny: int, nz: int, coef, dev):
 
 
 def setup_sequence(workload: str, precond: str | None = None, csr: str | None = None,
-                   inner_tol: float | None = None):
+                   inner_tol: float | None = None, colour_blocks: bool = True):
     """Operator, context, options and the evolved sequence (untimed): X[k] is
     x_(k-1) and Bs[k] is b_k of system k, resident on the GPU.  precond
     replaces the workload's preconditioner; csr hands the matrix over in CSR."""
@@ -284,6 +313,10 @@ def setup_sequence(workload: str, precond: str | None = None, csr: str | None = 
         A = lcs.matrix_from_numpy(w.kind, w.nx, w.ny, w.nz, w.coef, dev,
                                   with32=okw["precision"] == "mixed")
     ctx = lcs.Context()
+    if not colour_blocks:
+        lcs.set_colour_blocking(False, ctx=ctx)
+        if okw["precond"] == "rbsgs":
+            desc = f"{desc}; restricted systems in the domain's ascending order"
     opts = lcs.Options(eps=1e-10, n_smooth=1, check_every=8, **okw)
     if inner_tol:
         opts.inner_tol = inner_tol
@@ -878,8 +911,11 @@ def dominant_kernel_roofline(args, w, okw, lcs, W, ctx, rerun):
     duration."""
     cands = DOMINANT.get(args.workload)
     if cands is None or args.csr or w.kind == W.KIND_9N:
+        note = ("GMRES / CSR input: see the rocprofv3 kernel trace" if args.csr or w.kind == W.KIND_9N
+                else "no event-timed kernel class for this workload: see its rocprofv3 kernel trace "
+                     "under profiles/")
         return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                "traffic": None, "note": "GMRES / CSR input: see the rocprofv3 kernel trace"}
+                "traffic": None, "note": note}
     rows = []
     for kern in cands:
         lcs.set_kernel_timing(kern["class"], ctx=ctx)
@@ -1008,12 +1044,14 @@ def run_benchmark(args):
 
     dev = "cuda:0"
     w, okw, desc, A, ctx, opts, X, Bs = setup_sequence(args.workload, args.precond, args.csr,
-                                                        args.inner_tol)
+                                                        args.inner_tol, not args.no_colour_blocks)
     n = w.n
     stream = torch.cuda.current_stream()
     eps = opts.eps
     x = torch.empty(n, dtype=torch.float64, device=dev)
     legs = leg_table(args.workload, eps)
+    if args.headline_legs:
+        legs = {k: v for k, v in legs.items() if k in ("local", "global")}
 
     def run_leg(key: str, steps: int, warm: int, record=None):
         stats = []
@@ -1152,9 +1190,9 @@ def run_benchmark(args):
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    if args.workload == "c3" and not args.csr and not args.no_extra:
+    if args.workload == "c3" and not args.csr and not args.no_extra and not args.headline_legs:
         out["c2_1024x1024_5pt_fp64"] = c2_extra(args)
-    if args.workload == "c5" and not args.csr:
+    if args.workload == "c5" and not args.csr and not args.headline_legs:
         out["adjoint_final_step"] = final_step_adjoint(w, opts, X, Bs, max(3, args.steps // 8))
     return out
 
@@ -1243,7 +1281,7 @@ def main():
         heat_run(args.heat, args.heat_steps)
         return
     if args.summarize:
-        summarize(args.summarize, args.steps, args.warmup, args.kernel, args.mark)
+        summarize(args.summarize, args.steps, args.warmup, args.kernel, args.mark, args.end_mark)
         return
     if args.tiling_sweep:
         tiling_sweep()

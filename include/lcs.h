@@ -311,6 +311,19 @@ lcs_status lcs_get_kernel_timing(lcs_ctx *ctx, double *ms_total, int64_t *launch
  * settings; reductions may round differently. */
 lcs_status lcs_set_tiling(lcs_ctx *ctx, int32_t march_rows, int32_t nontemporal);
 
+/* Row order of the restricted system B under the red-black (multi-colour)
+ * symmetric Gauss-Seidel preconditioner (precond = LCS_PC_RBSGS, 2..4
+ * colours, symmetric operator).  on != 0 (the default): the local domain is
+ * reordered colour by colour, ascending inside each colour, before B is
+ * gathered, so that each half sweep of the preconditioner reads only the
+ * rows of its own colour; on = 0: B keeps the ascending order of the domain
+ * (Algorithm 1 step 3) and every half sweep walks all of B.  Each row keeps
+ * its entries in ascending grid order, so every per-row result (z of each
+ * half sweep, q = B p) is the same bit for bit either way; the reductions
+ * (r.z, p.q) add the same terms in another order.  Returns LCS_EINVAL for a
+ * NULL context. */
+lcs_status lcs_set_colour_blocking(lcs_ctx *ctx, int32_t on);
+
 /* ---- batched solves: the G decoupled group systems of a source iteration ---- */
 /* In each source iteration of the multi-group radiation diffusion equations
  * (Section 3.3, Algorithm 7) the G group equations are decoupled: G systems

@@ -196,6 +196,8 @@ struct lcs_ctx {
     size_t prof_used = 0;
     double prof_ms = 0.0;
     int64_t prof_launches = 0;
+    // restricted systems reordered by colour under RB-SGS (lcs_set_colour_blocking)
+    int colour_blocks = 1;
     // row-marching tiling of the 2-D stencil kernels (0 / -1: automatic)
     int march_rows = 0;
     int nontemporal = -1;
@@ -770,6 +772,17 @@ struct PcgResult {
 // z = M^-1 r for the symmetric red-black (or four-colour) Gauss-Seidel
 // preconditioner from z = 0: colours 0..nc-1, then nc-2..0 (the backward
 // pass's first colour would repeat the forward pass's last one exactly).
+// Whether op is the restricted system of the current local solve with its
+// rows blocked by colour (see local_phase).
+template <class Op>
+bool colour_blocked(const lcs_ctx *c, const Op &A, int ncol) {
+    if constexpr (is_ell<Op>) {
+        return c->cblk.n == ncol && ncol >= 2 && c->cblk.start[ncol] == A.n;
+    } else {
+        return false;
+    }
+}
+
 template <class Op, int kPc>
 lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<typename Op::real> &B, int grid,
                           int ncol, hipStream_t s) {
@@ -778,23 +791,24 @@ lcs_status launch_precond(lcs_ctx *c, const Op &A, const PcgBufs<typename Op::re
     real *part = slot_as<real>(c, kPtSgs);
     const Scalars *sc = c->dsc;
     if constexpr (is_ell<Op>) {
-        // a restricted system with its rows blocked by colour: each half
-        // sweep reads its colour's rows only
-        const auto &cb = c->cblk;
-        if (cb.n == ncol && ncol >= 2 && cb.start[ncol] == A.n) {
-            for (int col = 1; col < ncol; ++col)
-                hipLaunchKernelGGL((k_gs_half_blk<Op, false>), dim3(grid), dim3(kBlock), 0, s, A,
-                                   (const real *)B.r, B.z, cb.start[col], cb.start[col + 1], sc, part);
-            for (int col = ncol - 2; col >= 0; --col) {
-                if (col == 0)
+        if (colour_blocked(c, A, ncol)) {
+            // a restricted system with its rows blocked by colour: each half
+            // sweep reads its colour's rows only, and each colour's last update
+            // (colour ncol-1 forward, the others backward) writes the r.z
+            // partials of its rows into a set of its own
+            const auto &cb = c->cblk;
+            auto half = [&](int col, int set) {
+                if (set >= 0)
                     hipLaunchKernelGGL((k_gs_half_blk<Op, true>), dim3(grid), dim3(kBlock), 0, s, A,
                                        (const real *)B.r, B.z, cb.start[col], cb.start[col + 1], sc,
-                                       part);
+                                       part + (size_t)set * grid);
                 else
-                    hipLaunchKernelGGL((k_gs_half_blk<Op, false>), dim3(grid), dim3(kBlock), 0, s,
-                                       A, (const real *)B.r, B.z, cb.start[col], cb.start[col + 1],
-                                       sc, part);
-            }
+                    hipLaunchKernelGGL((k_gs_half_blk<Op, false>), dim3(grid), dim3(kBlock), 0, s, A,
+                                       (const real *)B.r, B.z, cb.start[col], cb.start[col + 1], sc,
+                                       part);
+            };
+            for (int col = 1; col < ncol; ++col) half(col, col == ncol - 1 ? 0 : -1);
+            for (int col = ncol - 2; col >= 0; --col) half(col, ncol - 1 - col);
             LAUNCH_CHECK();
             return LCS_OK;
         }
@@ -997,6 +1011,9 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
     const int grid = grid_for(A, kRedGrid);
     real *pupd = slot_as<real>(c, kPtUpd), *pap = slot_as<real>(c, kPtAp);
     real *psgs = slot_as<real>(c, kPtSgs);
+    // the r.z partials of the preconditioner: one set per colour when the
+    // rows are blocked by colour, else one
+    const int gsgs = colour_blocked(c, A, ncol) ? ncol * grid : grid;
     if (max_iter < 0) max_iter = 0;
     if (x_zero) {
         hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, real(0), n);
@@ -1015,7 +1032,7 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
         real *pnew = flip ? B.p0 : B.p1;
         return launch_maybe_timed(c, time_ap, k_pcg_ap<Op, kPc>, grid, s, A, (const real *)B.z,
                                   (const real *)pold, pnew, B.q, j, max_iter, tol_base, tol_factor,
-                                  c->dsc, (const real *)pupd, (const real *)psgs, pap);
+                                  c->dsc, (const real *)pupd, (const real *)psgs, gsgs, pap);
     };
     // iteration j: q = A p (with the stopping test), the update, the
     // preconditioner; j == max_iter: the final stopping test alone
@@ -1490,7 +1507,7 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
                                                       std::max<int64_t>(kWaves, resident.load()));
             const int64_t strips_r = ((int64_t)Au.nx / 2 + kPairOwn - 1) / kPairOwn;
             int mh_r = mh;
-            while (mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > waves_r) ++mh_r;
+            while (fuse && mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > waves_r) ++mh_r;
             const int64_t tiles_r = strips_r * ((Au.ny + mh_r - 1) / mh_r);
             int grid_r = (int)std::min<int64_t>(kMaxGrid, (tiles_r + kWaves - 1) / kWaves);
             grid_r = std::min(kMaxGrid, std::max(kXcds, (grid_r + kXcds - 1) / kXcds * kXcds));
@@ -1545,7 +1562,8 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
             lcs_ctx *c;
             ~ClearBlocks() { c->cblk.n = 0; }
         } clear_blocks{c};
-        if (o->precond == LCS_PC_RBSGS && ncol >= 2 && ncol <= kMaxBlkColours && !uses_gmres(M)) {
+        if (c->colour_blocks && o->precond == LCS_PC_RBSGS && ncol >= 2 && ncol <= kMaxBlkColours &&
+            !uses_gmres(M)) {
             int32_t *idxb, *cnt;
             LCS_TRY(get_buf(c, B_IDXB, K, &idxb));
             LCS_TRY(get_buf(c, B_CBLK, (size_t)kMaxBlkColours * kMaxGrid, &cnt));
@@ -2281,6 +2299,12 @@ lcs_status lcs_set_kernel_timing(lcs_ctx *c, int32_t what) {
     c->prof_used = 0;
     c->prof_ms = 0.0;
     c->prof_launches = 0;
+    return LCS_OK;
+}
+
+lcs_status lcs_set_colour_blocking(lcs_ctx *c, int32_t on) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    c->colour_blocks = on != 0;
     return LCS_OK;
 }
 

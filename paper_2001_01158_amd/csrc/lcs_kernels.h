@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict
 // colour in lower blocks) + (its rank among them in its block), writes the
 // blocked domain and inv, and the first position of each colour (then K) to
 // sc->cstart.
-constexpr int kMaxBlkColours = 8;
+constexpr int kMaxBlkColours = 4;
 
 template <class SOp>
 __global__ __launch_bounds__(kBlock) void k_cblk_count(SOp A, const int32_t *__restrict__ idx,
@@ -672,7 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
                                                    int max_iter, const double *tol_base,
                                                    double tol_factor, Scalars *sc,
                                                    const typename Op::real *part_upd,
-                                                   const typename Op::real *part_sgs,
+                                                   const typename Op::real *part_sgs, int gsgs,
                                                    typename Op::real *part_ap) {
     using real = typename Op::real;
     constexpr int V = Op::V, NB = Op::NB;
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_ap(Op A, const typename Op::real
     real rz = t[1];
     if (kPc == 2) {
         real u[1];
-        read_partials<real, 1>(part_sgs, gridDim.x, Ops<0u>(), u);
+        read_partials<real, 1>(part_sgs, gsgs, Ops<0u>(), u);
         rz = u[0];
     }
     if (done) return;
@@ -864,8 +864,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_half(Op A, const typename Op::rea
 // The half sweep of colour c on a restricted system whose rows are blocked
 // by colour (rows [a, b) have colour c): only those rows are read and
 // updated, each with k_gs_half's arithmetic, so the z it leaves is the same
-// bit for bit.  With kRz the kernel visits every row for the r.z partials
-// (the other rows read r and z only).
+// bit for bit.  With kRz this is the colour's last update of the sweep
+// pair, and the kernel writes the partials of r.z over its rows (one
+// partial set per colour; the consumer folds all of them).
 template <class Op, bool kRz>
 __global__ __launch_bounds__(kBlock) void k_gs_half_blk(Op A, const typename Op::real *__restrict__ r,
                                                         typename Op::real *z, int64_t a, int64_t b,
@@ -875,29 +876,24 @@ __global__ __launch_bounds__(kBlock) void k_gs_half_blk(Op A, const typename Op:
     static_assert(Op::V == 1, "rows of the restricted system");
     if (sc->pcg.done) return;
     real v[1] = {real(0)};
-    const int64_t off = kRz ? 0 : a;
-    const Band B = my_band(kRz ? A.n : b - a);
+    const Band B = my_band(b - a);
     for (int64_t u = B.u; u < B.end; u += B.step) {
-        const int64_t i = u + off;
-        if (!kRz || (i >= a && i < b)) {
-            typename Op::Unit U;
-            A.load(U, i);
-            real zv[NB][1], ro[1], zo[1];
-            A.gather(U, (const real *)z, zv);
-            A.own(U, r, ro);
-            real acc = ro[0], d = real(1);
+        const int64_t i = u + a;
+        typename Op::Unit U;
+        A.load(U, i);
+        real zv[NB][1], ro[1], zo[1];
+        A.gather(U, (const real *)z, zv);
+        A.own(U, r, ro);
+        real acc = ro[0], d = real(1);
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (!A.valid(U, q, 0)) continue;
-                if (A.is_diag(U, q, 0)) d = U.a[q][0];
-                else acc = fma(-U.a[q][0], zv[q][0], acc);
-            }
-            zo[0] = acc / d;
-            A.put(U, z, zo);
-            if (kRz) v[0] += ro[0] * zo[0];
-        } else {
-            v[0] += r[i] * z[i];
+        for (int q = 0; q < NB; ++q) {
+            if (!A.valid(U, q, 0)) continue;
+            if (A.is_diag(U, q, 0)) d = U.a[q][0];
+            else acc = fma(-U.a[q][0], zv[q][0], acc);
         }
+        zo[0] = acc / d;
+        A.put(U, z, zo);
+        if (kRz) v[0] += ro[0] * zo[0];
     }
     if (kRz) write_partials<real, 1>(v, Ops<0u>(), part_sgs);
 }

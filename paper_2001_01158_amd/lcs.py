@@ -38,7 +38,7 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_set_tiling", "lcs_assemble_heat", "lcs_norm2_diff",
             "lcs_solve_global_batched", "lcs_solve_local_then_global_batched",
             "lcs_workspace_bytes", "lcs_workspace_bytes_batched", "lcs_create_with_workspace",
-            "lcs_build_local_domain_static"]
+            "lcs_build_local_domain_static", "lcs_set_colour_blocking"]
 (TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE, TIME_SMOOTH,
  TIME_SCORE) = range(7)
 
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lcs_set_kernel_timing": (I32, [P, I32]),
         "lcs_get_kernel_timing": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "lcs_set_tiling": (I32, [P, I32, I32]),
+        "lcs_set_colour_blocking": (I32, [P, I32]),
         "lcs_assemble_heat": (I32, [P, I32, I32, D, D, D, D, P, P, P, P, P]),
         "lcs_norm2_diff": (I32, [P, P, P, I64, ctypes.POINTER(D), P]),
         "lcs_workspace_bytes": (ctypes.c_size_t, [PM, PO]),
@@ -615,6 +616,13 @@ def set_tiling(march_rows: int = 0, nontemporal: int = -1, ctx: Context = None):
     row-marching tiles of that many rows; nontemporal 0 turns the marching
     kernels' non-temporal hints off."""
     _check(lib().lcs_set_tiling(_ctx(ctx), int(march_rows), int(nontemporal)))
+
+
+def set_colour_blocking(on: bool = True, ctx: Context = None):
+    """Order of the restricted system's rows under RB-SGS: colour by colour
+    (True, the default) or the domain's ascending order (False); per-row
+    results are the same either way (lcs_set_colour_blocking)."""
+    _check(lib().lcs_set_colour_blocking(_ctx(ctx), 1 if on else 0))
 
 
 def matrix_from_numpy(kind: int, nx: int, ny: int, nz: int, coef, device="cuda",

@@ -398,6 +398,32 @@ def test_local_then_global_nine_point_sgs(name, mode, theta, ctx):
     assert err_g <= max(10 * err_o, 1e-10)
 
 
+@pytest.mark.parametrize("name", ["7pt", "7pt_v", "9pt_v", "5pt"])
+def test_colour_blocked_restricted_system(name):
+    """Under RB-SGS the local domain is reordered colour by colour before
+    the gather (each half sweep reads its own colour's rows); with the
+    reordering switched off B keeps the domain's ascending order.  Every
+    per-row result is the same, so equal iteration counts give solutions
+    that differ only by the reductions' summation order, and both follow
+    the oracle's trajectory."""
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1)
+    assert d.K > 100
+    oo = oracle.Options(eps=1e-10, max_iter=6, pc=oracle.PC_SGS)
+    xo, _ = oracle.solve_local(Ah, b, x0, d.idx, oo)
+    xs = []
+    for on in (True, False):
+        say("colour blocks", name, dims, on)
+        c = lcs.Context()
+        lcs.set_colour_blocking(on, ctx=c)
+        x = dev(x0)
+        lcs.solve_local(A, dev(b), x, dev(d.idx, torch.int32),
+                        lcs.Options(eps=1e-10, max_iter=6, check_every=1, precond="rbsgs"), ctx=c)
+        xs.append(host(x))
+        assert np.linalg.norm(xs[-1] - xo) <= 1e-12 * np.linalg.norm(xo), on
+    assert np.linalg.norm(xs[0] - xs[1]) <= 1e-13 * np.linalg.norm(xs[1])
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("pc", ["jacobi", "rbsgs"])
 def test_solve_local_trajectory_parity(name, pc, ctx):
