@@ -1467,6 +1467,27 @@ struct is_pair9 : std::false_type {};
 template <int W>
 struct is_pair9<U9<double, 2, W>> : std::true_type {};
 
+// Waves of k_gs_pair9 (kFused: k_gs_pair9_res) that the GPU holds at once:
+// blocks per compute unit at the kernel's occupancy x compute units x 4.
+template <class UOp, bool kFused>
+lcs_status pair_resident_waves(int64_t *out) {
+    static std::atomic<int64_t> cached{0};
+    int64_t v = cached.load();
+    if (v == 0) {
+        int nb = 0, cus = 0, dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        if constexpr (kFused)
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gs_pair9_res<UOp>, kBlock, 0));
+        else
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gs_pair9<UOp>, kBlock, 0));
+        v = std::max<int64_t>(1, (int64_t)nb * cus) * kWaves;
+        cached.store(v);
+    }
+    *out = v;
+    return LCS_OK;
+}
+
 // n_sweeps colour-ordered Gauss-Seidel sweeps on A x = b (Algorithm 1 step
 // 7): one kernel per colour, or, for the nine-point stencil in strips of two
 // cells, one kernel per pair of colours (k_gs_pair9: rows of one parity)
@@ -1483,31 +1504,27 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
         if (ncol == 4) {
             double *tmp;
             LCS_TRY(get_buf(c, B_GSX, (size_t)Au.n, &tmp));
+            // Tiles of up to 32 rows, about 4096 of them on large grids.  The
+            // fused pass owns 62 strips per wave and keeps at most kMaxGrid
+            // blocks (its partials); its tiles grow until there is at most
+            // one per wave that the GPU holds at once (its occupancy, asked
+            // of the runtime once), so that no wave waits for a second round.
+            // (Shorter tiles that fill every resident wave of the plain pass
+            // were measured 1 % slower.)
+            const bool fuse = crit_eps >= 0.0 && n_sweeps > 0;
             const int64_t strips = ((int64_t)Au.nx / 2 + kPairStep - 1) / kPairStep;
+            const int64_t strips_r = ((int64_t)Au.nx / 2 + kPairOwn - 1) / kPairOwn;
             const int mh = (int)std::max<int64_t>(2, std::min<int64_t>(32, strips * Au.ny / 4096));
             const int64_t tiles = strips * ((Au.ny + mh - 1) / mh);
             int grid = (int)std::min<int64_t>(kStreamGrid, (tiles + kWaves - 1) / kWaves);
             grid = std::max(kXcds, (grid + kXcds - 1) / kXcds * kXcds);
-            // the fused last pass: 62 owned strips per wave, and at most
-            // kMaxGrid blocks (its partials); tiles grow until there is at
-            // most one per wave that the GPU holds at once (its occupancy,
-            // asked of the runtime once), so that no wave waits for a
-            // second round
-            const bool fuse = crit_eps >= 0.0 && n_sweeps > 0;
-            static std::atomic<int64_t> resident{0};
-            if (fuse && resident.load() == 0) {
-                int nb = 0, cus = 0, dev = 0;
-                HIP_TRY(hipGetDevice(&dev));
-                HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-                HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gs_pair9_res<UOp>,
-                                                                     kBlock, 0));
-                resident.store(std::max<int64_t>(1, (int64_t)nb * cus) * kWaves);
-            }
-            const int64_t waves_r = std::min<int64_t>((int64_t)kMaxGrid * kWaves,
-                                                      std::max<int64_t>(kWaves, resident.load()));
-            const int64_t strips_r = ((int64_t)Au.nx / 2 + kPairOwn - 1) / kPairOwn;
             int mh_r = mh;
-            while (fuse && mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > waves_r) ++mh_r;
+            if (fuse) {
+                int64_t waves_r = 0;
+                LCS_TRY((pair_resident_waves<UOp, true>(&waves_r)));
+                waves_r = std::min<int64_t>(waves_r, (int64_t)kMaxGrid * kWaves);
+                while (mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > waves_r) ++mh_r;
+            }
             const int64_t tiles_r = strips_r * ((Au.ny + mh_r - 1) / mh_r);
             int grid_r = (int)std::min<int64_t>(kMaxGrid, (tiles_r + kWaves - 1) / kWaves);
             grid_r = std::min(kMaxGrid, std::max(kXcds, (grid_r + kXcds - 1) / kXcds * kXcds));
