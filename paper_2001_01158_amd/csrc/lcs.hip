@@ -969,7 +969,7 @@ lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typena
             hipLaunchKernelGGL(k_fill<real>, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, real(0), n);
             LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL((k_cg_init1<Op>), dim3(grid), dim3(kBlock), 0, s, A, rhs,
+        hipLaunchKernelGGL((k_cg_init1<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A, rhs,
                            (const real *)x, r[0], x_zero ? 1 : 0, c->dsc);
     }
     hipLaunchKernelGGL((k_cg_init2<Op, kPc>), dim3(grid), dim3(kBlock), 0, s, A,
@@ -1227,7 +1227,9 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
         const bool prep = o->precond != LCS_PC_RBSGS;
         if (prep)
             hipLaunchKernelGGL(k_refine_start, dim3(flat_grid(n)), dim3(kBlock), 0, s,
-                               (const double *)r64, B.r, d32, n, c->dsc, early ? 1 : 0);
+                               (const double *)r64,
+                               o->precond == LCS_PC_JACOBI ? A32.diag_ptr() : (const float *)nullptr,
+                               B.r, d32, n, c->dsc, early ? 1 : 0);
         else
             hipLaunchKernelGGL(k_cast_scale, dim3(flat_grid(n)), dim3(kBlock), 0, s,
                                (const double *)r64, r32, n, c->dsc, early ? 1 : 0);

@@ -434,7 +434,7 @@ struct U5 {
     }
     __device__ __forceinline__ int colour(const Unit &U, int k) const { return (U.x0 + k + U.y) & 1; }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
-    __device__ __forceinline__ const real *diag_ptr() const { return C; }
+    __host__ __device__ __forceinline__ const real *diag_ptr() const { return C; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
         vld<T, V>(p + U.i0, o);
@@ -661,7 +661,7 @@ struct U9 {
         return ((U.x0 + k) & 1) + 2 * (U.y & 1);
     }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
-    __device__ __forceinline__ const real *diag_ptr() const { return C; }
+    __host__ __device__ __forceinline__ const real *diag_ptr() const { return C; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
         vld<T, V>(p + U.i0, o);
@@ -770,7 +770,7 @@ struct U9N {
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const {
         vld<real, V>(a + 4 * n + U.i0, d);
     }
-    __device__ __forceinline__ const real *diag_ptr() const { return a + 4 * n; }
+    __host__ __device__ __forceinline__ const real *diag_ptr() const { return a + 4 * n; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
         vld<T, V>(p + U.i0, o);
@@ -992,7 +992,7 @@ struct U7 {
     }
     __device__ __forceinline__ int colour(const Unit &U, int k) const { return (U.x0 + k + U.y + U.z) & 1; }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[V]) const { vld<real, V>(C + U.i0, d); }
-    __device__ __forceinline__ const real *diag_ptr() const { return C; }
+    __host__ __device__ __forceinline__ const real *diag_ptr() const { return C; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[V]) const {
         vld<T, V>(p + U.i0, o);
@@ -1040,7 +1040,7 @@ struct UEll {
     }
     __device__ __forceinline__ int colour(const Unit &U, int) const { return clr[U.i0]; }
     __device__ __forceinline__ void diag(const Unit &U, real (&d)[1]) const { d[0] = dg[U.i0]; }
-    __device__ __forceinline__ const real *diag_ptr() const { return dg; }
+    __host__ __device__ __forceinline__ const real *diag_ptr() const { return dg; }
     template <typename T>
     __device__ __forceinline__ void own(const Unit &U, const T *__restrict__ p, T (&o)[1]) const {
         o[0] = p[U.i0];

@@ -1160,13 +1160,19 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__r
 // p_j = z_j + beta_j p_{j-1}, s_j = w_j + beta_j s_{j-1} (= A p_j),
 // x += alpha_j p_j, r_{j+1} = r_j - alpha_j s_j.  In exact arithmetic these
 // are the iterates of the standard PCG.  With a pointwise preconditioner the
-// next z is known at every neighbour from the stored r_j, w_j, s_{j-1} and
-// the diagonal, so w_{j+1} = A z_{j+1} is formed in the same pass: one launch
-// and one reduction per iteration.  r, w and s are double-buffered by
-// iteration parity (neighbours read the old values); p and x are own-only.
+// next z is known at every neighbour, so w_{j+1} = A z_{j+1} is formed in
+// the same pass: one launch and one reduction per iteration.  With Jacobi
+// (M = diag) the stored vectors are scaled by M^-1: z_j = M^-1 r_j,
+// M^-1 w_j and M^-1 s_j, so that z_{j+1} = z_j - alpha_j M^-1 s_j at a
+// neighbour needs three gathered values and no division, and the own row
+// forms r_{j+1} = diag z_{j+1} for the partials.  The buffers are
+// double-buffered by iteration parity (neighbours read the old values); p
+// and x are own-only.
 
-// r_0 = rhs - A x (or rhs when x = 0)
-template <class Op>
+// r_0 = rhs - A x (or rhs when x = 0); with the Jacobi preconditioner the
+// kernel stores z_0 = r_0 / diag instead (the iteration keeps z, A z / diag
+// and A p / diag in place of r, w and s)
+template <class Op, int kPc>
 __global__ __launch_bounds__(kBlock) void k_cg_init1(Op A, const typename Op::real *__restrict__ rhs,
                                                      const typename Op::real *__restrict__ x,
                                                      typename Op::real *__restrict__ r, int x_zero,
@@ -1182,7 +1188,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init1(Op A, const typename Op::re
         typename Op::Unit U;
         real rr[V];
         if (x_zero) {
-            W.geom(A, U);
+            if (kPc == 1) W.load(A, U);   // the diagonal
+            else W.geom(A, U);
             A.own(U, rhs, rr);
         } else {
             W.load(A, U);
@@ -1198,12 +1205,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_init1(Op A, const typename Op::re
                 rr[k] = acc;
             }
         }
+        if (kPc == 1) {
+            real dd[V];
+            diag_of(A, U, dd);
+#pragma unroll
+            for (int k = 0; k < V; ++k) rr[k] = rr[k] / dd[k];
+        }
         A.put(U, r, rr);
     }
 }
 
-// w_0 = A z_0 with z_0 = M^-1 r_0 (formed at each neighbour); partials
-// gamma_0, delta_0, rho_0
+// w_0 = A z_0; partials gamma_0 = r_0.z_0, delta_0 = w_0.z_0, rho_0 = r_0.r_0.
+// Jacobi: the input holds z_0 and the kernel stores w_0 / diag, with
+// r_0 = diag z_0 for the partials; none: z_0 = r_0.
 template <class Op, int kPc>
 __global__ __launch_bounds__(kBlock) void k_cg_init2(Op A, const typename Op::real *__restrict__ r,
                                                      typename Op::real *__restrict__ w,
@@ -1211,33 +1225,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_init2(Op A, const typename Op::re
     using real = typename Op::real;
     constexpr int V = Op::V, NB = Op::NB;
     real v[3] = {real(0), real(0), real(0)};
-    for (auto W = walk<2>(A); W.valid(); W.advance()) {
+    for (auto W = walk<1>(A); W.valid(); W.advance()) {
         typename Op::Unit U;
         W.load(A, U);
-        real rv[NB][V], ro[V], zo[V], wo[V];
-        W.template gather<0>(A, U, r, rv);
-        own_of(A, U, rv, r, ro);
+        real zv[NB][V], ro[V], zo[V], wo[V], dd[V];
+        W.template gather<0>(A, U, r, zv);
+        own_of(A, U, zv, r, zo);
         if (kPc == 1) {
-            real dv[NB][V], dd[V];
-            W.template gather<1>(A, U, A.diag_ptr(), dv);
             diag_of(A, U, dd);
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
-#pragma unroll
-                for (int k = 0; k < V; ++k) rv[q][k] = A.valid(U, q, k) ? rv[q][k] / dv[q][k] : real(0);
-#pragma unroll
-            for (int k = 0; k < V; ++k) zo[k] = ro[k] / dd[k];
+            for (int k = 0; k < V; ++k) ro[k] = dd[k] * zo[k];
         } else {
 #pragma unroll
-            for (int k = 0; k < V; ++k) zo[k] = ro[k];
+            for (int k = 0; k < V; ++k) ro[k] = zo[k];
         }
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             real acc = real(0);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
-                if (A.valid(U, q, k)) acc = fma(U.a[q][k], rv[q][k], acc);
-            wo[k] = acc;
+                if (A.valid(U, q, k)) acc = fma(U.a[q][k], zv[q][k], acc);
+            wo[k] = kPc == 1 ? acc / dd[k] : acc;
             v[0] += ro[k] * zo[k];
             v[1] += acc * zo[k];
             v[2] += ro[k] * ro[k];
@@ -1271,7 +1279,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
     const double tol_prev = sc->pcg.tol;
     const double gamma_prev = sc->cg_gamma[(j - 1) & 1], alpha_prev = sc->cg_alpha[(j - 1) & 1];
     const double tol_in = (j == 0 && tol_base) ? *tol_base : 0.0;
-    auto W = walk<4>(A);
+    auto W = walk<3>(A);
     typename Op::Unit U;
     if (W.valid()) W.load(A, U);
     real t[3];
@@ -1340,41 +1348,33 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(
 #pragma unroll
                 for (int k = 0; k < V; ++k) wv[q][k] = fma(beta, sv[q][k], wv[q][k]);
         }
-        // neighbours: s = w + beta s_old (in wv), r' = r - alpha s, z' = M^-1 r'
-        if (kPc == 1) {
-            real dv[NB][V];
-            W.template gather<3>(A, U, A.diag_ptr(), dv);
+        // neighbours: s = w + beta s_old (in wv), then the next z: with
+        // Jacobi z - alpha s in the scaled vectors, else r' = r - alpha s
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
+        for (int q = 0; q < NB; ++q)
 #pragma unroll
-                for (int k = 0; k < V; ++k)
-                    rv[q][k] = A.valid(U, q, k) ? fma(-alpha, wv[q][k], rv[q][k]) / dv[q][k] : real(0);
-        } else {
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-#pragma unroll
-                for (int k = 0; k < V; ++k)
-                    rv[q][k] = A.valid(U, q, k) ? fma(-alpha, wv[q][k], rv[q][k]) : real(0);
-        }
+            for (int k = 0; k < V; ++k)
+                rv[q][k] = A.valid(U, q, k) ? fma(-alpha, wv[q][k], rv[q][k]) : real(0);
         real sn[V], rn[V], wn[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            const real zk = kPc == 1 ? ro[k] / dd[k] : ro[k];
+            const real zk = ro[k];   // z_j (Jacobi: the stored z; none: r_j)
             const real pk = j > 0 ? fma(beta, po[k], zk) : zk;
             const real sk = j > 0 ? fma(beta, so[k], wo[k]) : wo[k];
             po[k] = pk;
             sn[k] = sk;
             xo[k] = fma(alpha, pk, xo[k]);
-            rn[k] = fma(-alpha, sk, ro[k]);
-            const real zn = kPc == 1 ? rn[k] / dd[k] : rn[k];
+            const real zn = fma(-alpha, sk, ro[k]);
             real acc = real(0);
 #pragma unroll
             for (int q = 0; q < NB; ++q)
                 if (A.valid(U, q, k)) acc = fma(U.a[q][k], rv[q][k], acc);
-            wn[k] = acc;
-            v[0] += rn[k] * zn;
+            const real rk = kPc == 1 ? dd[k] * zn : zn;   // r_{j+1}
+            rn[k] = zn;
+            wn[k] = kPc == 1 ? acc / dd[k] : acc;
+            v[0] += rk * zn;
             v[1] += acc * zn;
-            v[2] += rn[k] * rn[k];
+            v[2] += rk * rk;
         }
         A.put(U, x, xo);
         A.put(U, p, po);
@@ -1487,9 +1487,11 @@ __global__ __launch_bounds__(kBlock) void k_cast_scale(const double *__restrict_
 
 // The start of one refinement step's inner solve with the single-sync PCG,
 // in one pass: k_cast_scale's scaled right-hand side (same guard) written
-// straight into r_0 (the inner solve starts from x = 0, so r_0 = rhs), the
+// straight into r_0 (the inner solve starts from x = 0, so r_0 = rhs; with
+// the Jacobi diagonal dg, z_0 = r_0 / dg as k_cg_init1 stores it), the
 // inner x zeroed, and the PCG state reset as k_cg_init1 resets it.
 __global__ __launch_bounds__(kBlock) void k_refine_start(const double *__restrict__ r,
+                                                         const float *__restrict__ dg,
                                                          float *__restrict__ r0,
                                                          float *__restrict__ x32, int64_t n,
                                                          Scalars *sc, int guard) {
@@ -1503,7 +1505,8 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(const double *__restric
     }
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
-        r0[i] = skip ? 0.0f : (float)(r[i] / s);
+        const float v = skip ? 0.0f : (float)(r[i] / s);
+        r0[i] = dg ? v / dg[i] : v;
         x32[i] = 0.0f;
     }
 }
