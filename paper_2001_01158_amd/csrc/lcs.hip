@@ -1361,6 +1361,19 @@ lcs_status solve_system(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol, co
 // ---------------------------------------------------------------------------
 // Algorithm 2 / Algorithm 3: scores, threshold, expansion, compaction
 // ---------------------------------------------------------------------------
+// Neighbourhood of a structured stencil for k_expand_w: 5 (2-D cross),
+// 9 (2-D 3 x 3), 7 (3-D cross); 0: general sparse rows (k_expand).
+template <class SOp>
+struct expand_shape : std::integral_constant<int, 0> {};
+template <>
+struct expand_shape<Stencil5<double>> : std::integral_constant<int, 5> {};
+template <>
+struct expand_shape<Stencil9<double>> : std::integral_constant<int, 9> {};
+template <>
+struct expand_shape<Stencil9N<double>> : std::integral_constant<int, 9> {};
+template <>
+struct expand_shape<Stencil7<double>> : std::integral_constant<int, 7> {};
+
 // Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
 // ascending domain in idx; returns K (host).  eps0 >= 0: ||b|| (from the
 // score pass) goes to dsc->bnorm, and an x0 with ||b - A x0|| <= eps0 ||b||
@@ -1392,11 +1405,22 @@ lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *
     LAUNCH_CHECK();
     const int ex = mode == LCS_MODE_RESIDUAL ? e_max : 0;
     const Launch Le = dims_wide(n, 4096);   // one partial per block
-    for (int m = 1; m <= ex; ++m)
+    constexpr int shape = expand_shape<SOp>::value;
+    for (int m = 1; m <= ex; ++m) {
+        const double *prev = slot(c, kPtExp0 + ((m - 1) & 1));
+        double *cur = slot(c, kPtExp0 + (m & 1));
+        if constexpr (shape != 0) {
+            if (As.nx % 8 == 0) {   // eight cells per thread, rows of whole words
+                const int64_t plane = shape == 7 ? (int64_t)As.nx * As.ny : 0;
+                hipLaunchKernelGGL((k_expand_w<SOp, shape>), dim3(Le.grid), dim3(kBlock), 0, s, As,
+                                   (const double *)score, x0, stamp, m, As.nx, plane, prev, cur,
+                                   c->dsc);
+                continue;
+            }
+        }
         hipLaunchKernelGGL((k_expand<SOp>), dim3(Le.grid), dim3(kBlock), 0, s, As,
-                           (const double *)score, x0, stamp, m, Le.chunk,
-                           (const double *)slot(c, kPtExp0 + ((m - 1) & 1)),
-                           slot(c, kPtExp0 + (m & 1)), c->dsc);
+                           (const double *)score, x0, stamp, m, Le.chunk, prev, cur, c->dsc);
+    }
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_count, dim3(T.grid), dim3(kBlock), 0, s, (const uint8_t *)stamp, T.ntiles,
                        T.tiles_per_block, blockoff, ex, (const double *)slot(c, kPtExp0 + (ex & 1)),

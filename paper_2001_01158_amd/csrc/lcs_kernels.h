@@ -250,6 +250,94 @@ __global__ __launch_bounds__(kBlock) void k_expand(Op A, const double *__restric
     write_partials<double, 1>(v, Ops<0u>(), part);
 }
 
+// The same round on a structured grid whose rows are a multiple of 8 cells:
+// a thread takes eight cells at a time as one 64-bit word of stamps and
+// reads the neighbouring rows' words (and the bytes just left and right of
+// each), so that a cell with no neighbour in Omega costs a few byte tests
+// and no scattered load.  Cells that do touch Omega take k_expand's test
+// (same sum, same order), so the stamps are the same bit for bit.  kShape:
+// 5 (2-D cross), 9 (2-D 3 x 3) or 7 (3-D cross, plane = nx * ny).
+template <class Op, int kShape>
+__global__ __launch_bounds__(kBlock) void k_expand_w(Op A, const double *__restrict__ r,
+                                                     const double *__restrict__ x,
+                                                     uint8_t *stamp, int m, int nx, int64_t plane,
+                                                     const double *part_prev, double *part,
+                                                     Scalars *sc) {
+    if (sc->ms.stop) return;
+    if (m >= 2) {
+        double added[1];
+        read_partials<double, 1>(part_prev, gridDim.x, Ops<0u>(), added);
+        if (added[0] == 0.0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) sc->ms.stop = 1;
+            return;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->ms.grown = m - 1;
+    }
+    const int64_t n = A.n, nw = n / 8, rw = nx / 8;
+    const Chunk c = my_chunk(nw, (nw + gridDim.x - 1) / gridDim.x);
+    const double tau = sc->ms.tau;
+    const uint64_t *w = reinterpret_cast<const uint64_t *>(stamp);
+    auto in = [&](int b) { return b != 0 && b <= m; };
+    // a row's eight stamps with the bytes at x0 - 1 and x0 + 8 (0 outside)
+    auto row = [&](int64_t q, int64_t i0, int x0, int (&t)[10]) {
+        const uint64_t v = w[q];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k + 1] = (int)((v >> (8 * k)) & 0xff);
+        t[0] = x0 > 0 ? stamp[i0 - 1] : 0;
+        t[9] = x0 + 8 < nx ? stamp[i0 + 8] : 0;
+    };
+    double v[1] = {0.0};
+    for (int64_t q = c.begin + threadIdx.x; q < c.end; q += kBlock) {
+        const uint64_t own = w[q];
+        // any cell outside Omega (a zero byte)?
+        const uint64_t t = own | (own >> 4);
+        const uint64_t t2 = t | (t >> 2);
+        if ((((t2 | (t2 >> 1)) & 0x0101010101010101ull)) == 0x0101010101010101ull) continue;
+        const int64_t i0 = q * 8;
+        const int64_t rowi = i0 / nx;
+        const int x0 = (int)(i0 - rowi * nx);
+        int cc[10], sn[10], nn[10], dn[10], up[10];
+        row(q, i0, x0, cc);
+        bool has_s, has_n, has_d = false, has_u = false;
+        if (kShape == 7) {
+            const int64_t z = i0 / plane;
+            const int y = (int)((i0 - z * plane) / nx);
+            has_s = y > 0;
+            has_n = (int64_t)(y + 1) * nx < plane;
+            has_d = z > 0;
+            has_u = (z + 1) * plane < n;
+        } else {
+            has_s = rowi > 0;
+            has_n = i0 + nx < n;
+        }
+        if (has_s) row(q - rw, i0 - nx, x0, sn);
+        if (has_n) row(q + rw, i0 + nx, x0, nn);
+        if (has_d) row(q - plane / 8, i0 - plane, x0, dn);
+        if (has_u) row(q + plane / 8, i0 + plane, x0, up);
+#pragma unroll
+        for (int k = 1; k <= 8; ++k) {
+            if (cc[k] != 0) continue;
+            bool nb = in(cc[k - 1]) || in(cc[k + 1]);
+            if (has_s) nb = nb || in(sn[k]) || (kShape == 9 && (in(sn[k - 1]) || in(sn[k + 1])));
+            if (has_n) nb = nb || in(nn[k]) || (kShape == 9 && (in(nn[k - 1]) || in(nn[k + 1])));
+            if (has_d) nb = nb || in(dn[k]);
+            if (has_u) nb = nb || in(up[k]);
+            if (!nb) continue;
+            const int64_t j = i0 + k - 1;
+            double acc = fabs(r[j]);
+            A.for_each(j, [&](int64_t l, double a) {
+                const int sl = stamp[l];
+                if (l != j && sl != 0 && sl <= m) acc += fabs(a * x[l]);
+            });
+            if (acc > tau) {
+                stamp[j] = (uint8_t)(m + 1);
+                v[0] += 1.0;
+            }
+        }
+    }
+    write_partials<double, 1>(v, Ops<0u>(), part);
+}
+
 // ---------------------------------------------------------------------------
 // stream compaction: stamps -> idx (ascending), inv, K
 // ---------------------------------------------------------------------------
@@ -1059,15 +1147,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__r
             const int64_t sn = (int64_t)min(max(yn, 0), ny - 1) * nx + x0;
             double on[V + 2];
             row_load<double, V>(in, sn, sn, x0, nx, yn >= 0 && yn < ny, true, on);
-            // slots 6..8 (NW, N, NE) of row y-1, before row y's load moves
-            // the south faces on
-            double a6[V], a7[V], a8[V];
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                a6[k] = S.nw[k];
-                a7[k] = S.n[k];
-                a8[k] = S.ne[k + 1];
-            }
+            // slots 6..8 (NW, N, NE) of row y-1 are the south faces of row
+            // y, which row y's load puts into its slots 0..2; the two that
+            // fall outside those (NW at x0, NE at x0 + 2) are kept first
+            static_assert(V == 2, "the face bookkeeping below is for strips of two");
+            const double nw_x0 = S.nw[0], ne_x2 = S.ne[2];
             Unit U;
             U.x0 = x0;
             U.y = y;
@@ -1115,6 +1199,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__r
                 Unit Ug;
                 Ug.x0 = x0;
                 Ug.y = y - 1;
+                // row y-1's NW, N, NE at x0 + k: k = 0: (nw_x0, a[1][0],
+                // a[0][1]); k = 1: (a[2][0], a[1][1], ne_x2)
+                const double a6[V] = {nw_x0, U.a[2][0]};
+                const double a7[V] = {U.a[1][0], U.a[1][1]};
+                const double a8[V] = {U.a[0][1], ne_x2};
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
                     double acc = accp[k];

@@ -48,6 +48,8 @@ CASES = {
     "5pt_v": (W.KIND_5PT, (96, 71, 1)),
     "9pt_v": (W.KIND_9PT, (84, 67, 1)),
     "7pt_v": (W.KIND_7PT, (24, 19, 17)),
+    # rows of whole 8-cell words: the word-wise expansion round
+    "9pt_w": (W.KIND_9PT, (88, 61, 1)),
 }
 
 
