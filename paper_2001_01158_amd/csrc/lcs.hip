@@ -1493,22 +1493,19 @@ struct is_pair9 : std::false_type {};
 template <int W>
 struct is_pair9<U9<double, 2, W>> : std::true_type {};
 
-// Waves of k_gs_pair9 (kFused: k_gs_pair9_res) that the GPU holds at once:
-// blocks per compute unit at the kernel's occupancy x compute units x 4.
-template <class UOp, bool kFused>
-lcs_status pair_resident_waves(int64_t *out) {
-    static std::atomic<int64_t> cached{0};
-    int64_t v = cached.load();
+// Waves of `kernel` that the GPU holds at once: blocks per compute unit at
+// its occupancy x compute units x 4; asked of the runtime once and kept in
+// `cache`.
+template <class K>
+lcs_status resident_waves(K kernel, std::atomic<int64_t> &cache, int64_t *out) {
+    int64_t v = cache.load();
     if (v == 0) {
         int nb = 0, cus = 0, dev = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        if constexpr (kFused)
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gs_pair9_res<UOp>, kBlock, 0));
-        else
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_gs_pair9<UOp>, kBlock, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0));
         v = std::max<int64_t>(1, (int64_t)nb * cus) * kWaves;
-        cached.store(v);
+        cache.store(v);
     }
     *out = v;
     return LCS_OK;
@@ -1530,30 +1527,73 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
         if (ncol == 4) {
             double *tmp;
             LCS_TRY(get_buf(c, B_GSX, (size_t)Au.n, &tmp));
-            // Tiles of up to 32 rows, about 4096 of them on large grids.  The
-            // fused pass owns 62 strips per wave and keeps at most kMaxGrid
-            // blocks (its partials); its tiles grow until there is at most
-            // one per wave that the GPU holds at once (its occupancy, asked
-            // of the runtime once), so that no wave waits for a second round.
-            // (Shorter tiles that fill every resident wave of the plain pass
-            // were measured 1 % slower.)
             const bool fuse = crit_eps >= 0.0 && n_sweeps > 0;
+            const int64_t strips1 = ((int64_t)Au.nx / 2 + kSweepOwn - 1) / kSweepOwn;
+            if (fuse && strips1 * ((Au.ny + 15) / 16) >= kMaxGrid) {
+                // Whole sweeps in one pass each (k_gs_sweep9), the last one
+                // forming the criterion; they alternate between x and the
+                // second buffer, and a copy brings an odd count's result back
+                // to x.  Tiles of an even number of rows, at least 16 (a tile
+                // updates two or three rows outside it again), grown until
+                // there is at most one per wave that the GPU holds at once
+                // (the kernel's occupancy, asked of the runtime once), so
+                // that no wave waits for a second round; at most kMaxGrid
+                // blocks (the partials).  Used once the grid has at least
+                // kMaxGrid such tiles.
+                static std::atomic<int64_t> held{0};
+                int64_t waves = 0;
+                LCS_TRY(resident_waves(k_gs_sweep9<UOp, true>, held, &waves));
+                waves = std::min<int64_t>(waves, (int64_t)kMaxGrid * kWaves);
+                int mh = 16;
+                while (mh < Au.ny && strips1 * ((Au.ny + mh - 1) / mh) > waves) mh += 2;
+                const int64_t tiles = strips1 * ((Au.ny + mh - 1) / mh);
+                int grid = (int)std::min<int64_t>(kMaxGrid, (tiles + kWaves - 1) / kWaves);
+                grid = std::min(kMaxGrid, std::max(kXcds, (grid + kXcds - 1) / kXcds * kXcds));
+                const double *src = x;
+                double *dst = tmp;
+                for (int sw = 0; sw < n_sweeps; ++sw) {
+                    if (sw == n_sweeps - 1) {
+                        LCS_TRY(launch_maybe_timed(c, timed, k_gs_sweep9<UOp, true>, grid, s, Au, b,
+                                                   src, dst, mh, slot(c, kPtRes)));
+                        hipLaunchKernelGGL(k_fin_res, dim3(1), dim3(kBlock), 0, s,
+                                           (const double *)slot(c, kPtRes), grid,
+                                           (const double *)&c->dsc->bnorm, crit_eps, c->dsc);
+                        LAUNCH_CHECK();
+                    } else {
+                        LCS_TRY(launch_maybe_timed(c, timed, k_gs_sweep9<UOp, false>, grid, s, Au,
+                                                   b, src, dst, mh, slot(c, kPtRes)));
+                    }
+                    src = dst;
+                    dst = dst == tmp ? x : tmp;
+                }
+                if (src != x)
+                    HIP_TRY(hipMemcpyAsync(x, src, sizeof(double) * (size_t)Au.n,
+                                           hipMemcpyDeviceToDevice, s));
+                *crit_done = true;
+                return LCS_OK;
+            }
+            // two passes per sweep (k_gs_pair9), each over the rows of one
+            // parity, in tiles of up to 32 rows, about 4096 of them on large
+            // grids; with the criterion, the last pass forms it
+            // (k_gs_pair9_res: 62 owned strips per wave, at most kMaxGrid
+            // blocks, tiles grown to at most one per resident wave)
             const int64_t strips = ((int64_t)Au.nx / 2 + kPairStep - 1) / kPairStep;
-            const int64_t strips_r = ((int64_t)Au.nx / 2 + kPairOwn - 1) / kPairOwn;
             const int mh = (int)std::max<int64_t>(2, std::min<int64_t>(32, strips * Au.ny / 4096));
             const int64_t tiles = strips * ((Au.ny + mh - 1) / mh);
             int grid = (int)std::min<int64_t>(kStreamGrid, (tiles + kWaves - 1) / kWaves);
             grid = std::max(kXcds, (grid + kXcds - 1) / kXcds * kXcds);
-            int mh_r = mh;
+            int mh_r = mh, grid_r = kXcds;
             if (fuse) {
+                static std::atomic<int64_t> held_r{0};
                 int64_t waves_r = 0;
-                LCS_TRY((pair_resident_waves<UOp, true>(&waves_r)));
+                LCS_TRY(resident_waves(k_gs_pair9_res<UOp>, held_r, &waves_r));
                 waves_r = std::min<int64_t>(waves_r, (int64_t)kMaxGrid * kWaves);
+                const int64_t strips_r = ((int64_t)Au.nx / 2 + kPairOwn - 1) / kPairOwn;
                 while (mh_r < Au.ny && strips_r * ((Au.ny + mh_r - 1) / mh_r) > waves_r) ++mh_r;
+                const int64_t tiles_r = strips_r * ((Au.ny + mh_r - 1) / mh_r);
+                grid_r = (int)std::min<int64_t>(kMaxGrid, (tiles_r + kWaves - 1) / kWaves);
+                grid_r = std::min(kMaxGrid, std::max(kXcds, (grid_r + kXcds - 1) / kXcds * kXcds));
             }
-            const int64_t tiles_r = strips_r * ((Au.ny + mh_r - 1) / mh_r);
-            int grid_r = (int)std::min<int64_t>(kMaxGrid, (tiles_r + kWaves - 1) / kWaves);
-            grid_r = std::min(kMaxGrid, std::max(kXcds, (grid_r + kXcds - 1) / kXcds * kXcds));
             for (int sw = 0; sw < n_sweeps; ++sw) {
                 LCS_TRY(launch_maybe_timed(c, timed, k_gs_pair9<UOp>, grid, s, Au, b,
                                            (const double *)x, tmp, 0, mh));

@@ -1239,6 +1239,195 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair9_res(Op A, const double *__r
     write_partials<double, 2>(v, Ops<2u>(), part);
 }
 
+// A whole four-colour sweep of the nine-point stencil in one pass, with the
+// criterion's residual after it when kRes (Algorithm 1 steps 7 and 8).  A
+// tile visits its even rows going up; at even row y it updates row y
+// (colours 0 and 1, from the old odd rows y - 1 and y + 1) and then the odd
+// row y - 1 (colours 2 and 3, from the new even rows y - 2 and y), so each
+// cell's update reads exactly the values of the colour-ordered sweep, with
+// k_gs_pair9's FMA chains.  The residual of odd row y - 1 is formed at the
+// same step; that of even row y takes its slots 0..5 there and slots 6..8
+// at the next step (k_resnorm's order).  The pass reads `in` and writes
+// every row to `out`.  A wave owns 60 strips (lanes 2..61) and updates the
+// two strips on either side too, storing nothing: the odd rows read the new
+// even rows one cell beyond the owned range, and a halo strip's value there
+// is right only when its own outer neighbour strip was updated as well.  A
+// tile owns rows [y0, y1) with y0 even and updates again, without storing,
+// the even rows y0 - 2 and y1 (and the odd row y0 - 1) that its own rows and
+// residuals read.
+constexpr int kSweepOwn = kWave - 4;
+
+template <class Op, bool kRes>
+__global__ __launch_bounds__(kBlock) void k_gs_sweep9(Op A, const double *__restrict__ b,
+                                                      const double *__restrict__ in,
+                                                      double *__restrict__ out, int mh,
+                                                      double *part) {
+    static_assert(Op::V == 2 && Op::NB == 9, "nine-point strips of two cells");
+    constexpr int V = 2;
+    using Unit = typename Op::Unit;
+    const int lane = threadIdx.x % kWave;
+    const int nx = A.nx, ny = A.ny;
+    const int64_t upr = nx / V;
+    const int64_t strips = (upr + kSweepOwn - 1) / kSweepOwn;
+    const int64_t tiles = strips * (int64_t)((ny + mh - 1) / mh);
+    double v[2] = {0.0, 0.0};
+    for (int64_t t = (int64_t)logical_block() * kWaves + threadIdx.x / kWave; t < tiles;
+         t += (int64_t)gridDim.x * kWaves) {
+        const int64_t strip = t % strips, seg = t / strips;
+        const int64_t xr = strip * kSweepOwn + lane - 2;
+        const bool active = xr >= 0 && xr < upr;
+        const bool owner = active && lane >= 2 && lane < 2 + kSweepOwn;
+        const int xu = (int)(xr < 0 ? 0 : (xr >= upr ? upr - 1 : xr));
+        const int x0 = xu * V;
+        const int y0 = (int)seg * mh, y1 = min(ny, y0 + mh);
+        const int ylast = (y1 + 1) & ~1;   // the first even row at or above y1
+        auto old_row = [&](int y, double (&o)[V + 2]) {
+            const int64_t sr = (int64_t)min(max(y, 0), ny - 1) * nx + x0;
+            row_load<double, V>(in, sr, sr, x0, nx, y >= 0 && y < ny, true, o);
+        };
+        // one row's update: colour c0 = 2 (y mod 2) from old values, then
+        // c0 + 1 with the new c0 values of its row; z rows s (y - 1), c (y,
+        // old), n (y + 1) as the colour-ordered sweep sees them
+        auto update = [&](const Unit &U, const double (&bb)[V], const double (&zs)[V + 2],
+                          const double (&zc)[V + 2], const double (&zn)[V + 2],
+                          double (&f)[V + 2]) {
+            double nv[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                double z[9];
+                z[0] = zs[k]; z[1] = zs[k + 1]; z[2] = zs[k + 2];
+                z[3] = zc[k]; z[4] = zc[k + 1]; z[5] = zc[k + 2];
+                z[6] = zn[k]; z[7] = zn[k + 1]; z[8] = zn[k + 2];
+                if (k == 1) {
+                    z[3] = nv[0];
+                    z[5] = __shfl_down(nv[0], 1, kWave);
+                }
+                double acc = bb[k], d = 1.0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    if (!A.valid(U, q, k)) continue;
+                    if (q == Op::kC) d = U.a[q][k];
+                    else acc = fma(-U.a[q][k], z[q], acc);
+                }
+                nv[k] = acc / d;
+            }
+            f[0] = __shfl_up(nv[1], 1, kWave);
+            f[1] = nv[0];
+            f[2] = nv[1];
+            f[3] = __shfl_down(nv[0], 1, kWave);
+        };
+        double om1[V + 2], n2[V + 2], accp[V] = {0.0, 0.0};
+        old_row(y0 - 3, om1);
+#pragma unroll
+        for (int k = 0; k < V + 2; ++k) n2[k] = 0.0;
+        for (int y = y0 - 2; y <= ylast; y += 2) {
+            const bool real_e = y >= 0 && y < ny, real_o = y - 1 >= 0 && y - 1 < ny;
+            double o0[V + 2], op1[V + 2];
+            old_row(y, o0);
+            old_row(y + 1, op1);
+            // even row y
+            Unit Ue;
+            Ue.x0 = x0;
+            Ue.y = y;
+            double be[V] = {0.0, 0.0}, f0[V + 2];
+            if (real_e) {
+                typename Op::South S;
+                A.geom_walk(Ue, (int64_t)y * upr + xu, xu, y);
+                A.south_init(S, Ue);
+                A.load_row(Ue, S);
+                vld<double, V>(b + Ue.i0, be);
+                update(Ue, be, om1, o0, op1, f0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < V + 2; ++k) f0[k] = 0.0;
+            }
+            if (owner && real_e && y >= y0 && y < y1) vst<double, V>(out + Ue.i0, {f0[1], f0[2]});
+            if (y > y0 - 2) {
+                // odd row y-1
+                Unit Uo;
+                Uo.x0 = x0;
+                Uo.y = y - 1;
+                double bo[V] = {0.0, 0.0}, f1[V + 2];
+                double nw_x0 = 0.0, ne_x2 = 0.0;   // row y-2's NW at x0, NE at x0 + 2
+                if (real_o) {
+                    typename Op::South S;
+                    A.geom_walk(Uo, (int64_t)(y - 1) * upr + xu, xu, y - 1);
+                    A.south_init(S, Uo);
+                    nw_x0 = S.nw[0];
+                    ne_x2 = S.ne[2];
+                    A.load_row(Uo, S);
+                    vld<double, V>(b + Uo.i0, bo);
+                    update(Uo, bo, n2, om1, f0, f1);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < V + 2; ++k) f1[k] = 0.0;
+                }
+                if (owner && real_o && y - 1 >= y0 && y - 1 < y1)
+                    vst<double, V>(out + Uo.i0, {f1[1], f1[2]});
+                if (kRes && owner) {
+                    // even row y-2: slots 6..8 (its NW, N, NE: the south
+                    // faces of row y-1) over the new row y-1
+                    if (y - 2 >= y0 && y - 2 < y1) {
+                        Unit Ug;
+                        Ug.x0 = x0;
+                        Ug.y = y - 2;
+                        const double a6[V] = {nw_x0, Uo.a[2][0]};
+                        const double a7[V] = {Uo.a[1][0], Uo.a[1][1]};
+                        const double a8[V] = {Uo.a[0][1], ne_x2};
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            double acc = accp[k];
+                            if (real_o && A.valid(Ug, 6, k)) acc = fma(-a6[k], f1[k], acc);
+                            if (real_o && A.valid(Ug, 7, k)) acc = fma(-a7[k], f1[k + 1], acc);
+                            if (real_o && A.valid(Ug, 8, k)) acc = fma(-a8[k], f1[k + 2], acc);
+                            v[0] += acc * acc;
+                            const double m = fabs(acc);
+                            v[1] = m > v[1] ? m : v[1];
+                        }
+                    }
+                    // odd row y-1, whole
+                    if (real_o && y - 1 >= y0 && y - 1 < y1) {
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            double z[9];
+                            z[0] = n2[k]; z[1] = n2[k + 1]; z[2] = n2[k + 2];
+                            z[3] = f1[k]; z[4] = f1[k + 1]; z[5] = f1[k + 2];
+                            z[6] = f0[k]; z[7] = f0[k + 1]; z[8] = f0[k + 2];
+                            double acc = bo[k];
+#pragma unroll
+                            for (int q = 0; q < 9; ++q)
+                                if (A.valid(Uo, q, k)) acc = fma(-Uo.a[q][k], z[q], acc);
+                            v[0] += acc * acc;
+                            const double m = fabs(acc);
+                            v[1] = m > v[1] ? m : v[1];
+                        }
+                    }
+                    // even row y: slots 0..5 over the new rows y-1 and y
+                    if (real_e) {
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            double z[6];
+                            z[0] = f1[k]; z[1] = f1[k + 1]; z[2] = f1[k + 2];
+                            z[3] = f0[k]; z[4] = f0[k + 1]; z[5] = f0[k + 2];
+                            double acc = be[k];
+#pragma unroll
+                            for (int q = 0; q < 6; ++q)
+                                if (A.valid(Ue, q, k)) acc = fma(-Ue.a[q][k], z[q], acc);
+                            accp[k] = acc;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < V + 2; ++k) {
+                om1[k] = op1[k];
+                n2[k] = f0[k];
+            }
+        }
+    }
+    if (kRes) write_partials<double, 2>(v, Ops<2u>(), part);
+}
+
 // ---------------------------------------------------------------------------
 // single-synchronisation PCG (Jacobi or none): one kernel per iteration
 // ---------------------------------------------------------------------------
