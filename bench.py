@@ -1009,16 +1009,13 @@ def _dominant():
     return {
         "c2": [local("k_cg_iter<UEll<double,5>,1>", 5, 8)],
         "c3": [local("k_cg_iter<UEll<float,9>,1>", 9, 4),
-               # first pass: rows of one parity read C, E, N, NE, NW and b
-               # (48 B), the others their south faces N, NE, NW (24 B), every
-               # row reads and writes x (16 B): 52 B per row; second pass,
-               # which also forms step 8's residual: every row reads the five
-               # arrays, b and x and writes x, 64 B per row; 58 B per row and
-               # launch on average
-               {"class": lcs.TIME_SMOOTH, "name": "k_gs_pair9 + k_gs_pair9_res<U9<double,2,2>>",
-                "what": "four-colour Gauss-Seidel sweep of Algorithm 1 step 7, two colours per "
-                        "pass, the second pass also forming the residual of step 8",
-                "bytes_per_row": 58, "units": grid_rows(2), "launches": grid_launches(2)},
+               # one pass per sweep: every row reads the five coefficient
+               # arrays, b and x and writes x (64 B per row); the residual of
+               # step 8 is formed in the same pass
+               {"class": lcs.TIME_SMOOTH, "name": "k_gs_sweep9<U9<double,2,2>,true>",
+                "what": "four-colour Gauss-Seidel sweep of Algorithm 1 step 7 in one pass, "
+                        "forming the residual of step 8",
+                "bytes_per_row": 64, "units": grid_rows(1), "launches": grid_launches(1)},
                {"class": lcs.TIME_SCORE, "name": "k_score<U9<double,2,2>,0>",
                 "what": "r0 = b - A x0 with its norms (Algorithm 3's score)",
                 "bytes_per_row": 64, "units": grid_rows(1), "launches": grid_launches(1)}],
