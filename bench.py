@@ -106,7 +106,7 @@ def parse():
     p.add_argument("--summarize", metavar="DIR",
                    help="print a summary of rocprofv3 output under DIR (trace/, fetch/, write/) "
                         "and exit; no GPU needed")
-    p.add_argument("--kernel", default="k_cg_iter<UEll<float, 9>, 1>",
+    p.add_argument("--kernel", default="k_cg_iter<UEllShort<float, 9>, 1>",
                    help="--summarize: the kernel (name prefix, as the profiler prints it)")
     p.add_argument("--mark", default="k_score<U9<double, 2, 2>, 0>",
                    help="--summarize: the kernel launched once at the start of each system")
@@ -997,7 +997,10 @@ def c2_extra(args):
 # classes and algorithmic bytes per row.
 def _dominant():
     from paper_2001_01158_amd import lcs
-    ell = lambda W_, real_b: W_ * (4 + real_b) + 11 * real_b   # one single-sync PCG iteration on B
+    # one single-sync PCG iteration on B: W slots of index (2 B in the
+    # short form of the 2-D stencils' domains) and value, and 11 vector
+    # accesses
+    ell = lambda W_, real_b, idx_b=2: W_ * (idx_b + real_b) + 11 * real_b
     local_rows = lambda w, sts: float(sum(s.K * s.its_local for s in sts))
     local_its = lambda w, sts: int(sum(s.its_local for s in sts))
     grid_rows = lambda per: (lambda w, sts: float(w.n * per * sum(1 for s in sts if s.K > 0)))
@@ -1007,8 +1010,8 @@ def _dominant():
         "what": "local Jacobi-PCG iteration on B (one launch per iteration)",
         "units": local_rows, "launches": local_its, "latency": True}
     return {
-        "c2": [local("k_cg_iter<UEll<double,5>,1>", 5, 8)],
-        "c3": [local("k_cg_iter<UEll<float,9>,1>", 9, 4),
+        "c2": [local("k_cg_iter<UEllShort<double,5>,1>", 5, 8)],
+        "c3": [local("k_cg_iter<UEllShort<float,9>,1>", 9, 4),
                # one pass per sweep: every row reads the five coefficient
                # arrays, b and x and writes x (64 B per row); the residual of
                # step 8 is formed in the same pass

@@ -324,6 +324,17 @@ lcs_status lcs_set_tiling(lcs_ctx *ctx, int32_t march_rows, int32_t nontemporal)
  * NULL context. */
 lcs_status lcs_set_colour_blocking(lcs_ctx *ctx, int32_t on);
 
+/* Index form of the restricted system B (Algorithm 1 step 4) built by the
+ * local solves.  on != 0 (the default): where B's rows keep the domain's
+ * ascending grid order and every stencil neighbour lies within 32767 rows
+ * of its row (nx <= 32766 for the 2-D stencils, nx * ny <= 32767 for the
+ * seven-point one; never for LCS_CSR), each column index is stored as a
+ * 16-bit offset from its row, which halves the index bytes every product
+ * with B reads; otherwise, and with on = 0, as a 32-bit index.  B's members,
+ * their order and every result are the same bit for bit either way.
+ * Returns LCS_EINVAL for a NULL context. */
+lcs_status lcs_set_short_columns(lcs_ctx *ctx, int32_t on);
+
 /* ---- batched solves: the G decoupled group systems of a source iteration ---- */
 /* In each source iteration of the multi-group radiation diffusion equations
  * (Section 3.3, Algorithm 7) the G group equations are decoupled: G systems

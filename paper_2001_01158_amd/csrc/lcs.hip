@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -66,6 +67,19 @@ bool uses_gmres(const lcs_matrix *A) {
 // without a colouring (no sweeps)
 int colours_of(const lcs_matrix *A) {
     return A->kind == LCS_CSR ? (A->colour ? A->n_colours : 0) : n_colours(A->kind);
+}
+
+// Largest |j - i| between a grid row i and a stencil neighbour j (the
+// index distance, in grid order, that a member of a restricted row can lie
+// from the row); unbounded for general sparse input.
+int64_t stencil_reach(const lcs_matrix *A) {
+    switch (A->kind) {
+    case LCS_STENCIL5_2D: return A->nx;
+    case LCS_STENCIL9_2D:
+    case LCS_STENCIL9N_2D: return (int64_t)A->nx + 1;
+    case LCS_STENCIL7_3D: return (int64_t)A->nx * A->ny;
+    default: return std::numeric_limits<int64_t>::max();
+    }
 }
 
 struct Launch {
@@ -198,6 +212,9 @@ struct lcs_ctx {
     int64_t prof_launches = 0;
     // restricted systems reordered by colour under RB-SGS (lcs_set_colour_blocking)
     int colour_blocks = 1;
+    // 16-bit column offsets in restricted systems where they fit
+    // (lcs_set_short_columns)
+    int short_cols = 1;
     // row-marching tiling of the 2-D stencil kernels (0 / -1: automatic)
     int march_rows = 0;
     int nontemporal = -1;
@@ -1374,6 +1391,15 @@ struct expand_shape<Stencil9N<double>> : std::integral_constant<int, 9> {};
 template <>
 struct expand_shape<Stencil7<double>> : std::integral_constant<int, 7> {};
 
+// Scalar operators whose restricted systems may take the short column form
+// (UEllShort): the symmetric 2-D stencils.
+template <class SOp>
+struct short_cols_ok : std::false_type {};
+template <>
+struct short_cols_ok<Stencil5<double>> : std::true_type {};
+template <>
+struct short_cols_ok<Stencil9<double>> : std::true_type {};
+
 // Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
 // ascending domain in idx; returns K (host).  eps0 >= 0: ||b|| (from the
 // score pass) goes to dsc->bnorm, and an x0 with ||b - A x0|| <= eps0 ||b||
@@ -1441,12 +1467,17 @@ struct Restricted {
     UEll<double, W> B64;
     UEll<float, W> B32;
     double *rhs;
+    const int16_t *dcol;   // the short form's column offsets (B64/B32.col unset), or null
+    UEllShort<double, W> short64() const { return {B64, dcol}; }
+    UEllShort<float, W> short32() const { return {B32, dcol}; }
 };
 
 // B = A[idx, idx] in ELL (one pass, no scan); rhs = r[idx] when r is given.
+// short_cols: the indices as 16-bit offsets from the row, in the same
+// buffer (the caller checks that every offset fits).
 template <int W, class SOp>
 lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const int32_t *inv,
-                  const double *r, bool with32, Restricted<W> *R, hipStream_t s) {
+                  const double *r, bool with32, bool short_cols, Restricted<W> *R, hipStream_t s) {
     int32_t *col;
     double *val, *dg, *rhs;
     float *val32 = nullptr, *dg32 = nullptr;
@@ -1460,11 +1491,15 @@ lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const
         LCS_TRY(get_buf(c, B_VAL32, (size_t)K * W, &val32));
         LCS_TRY(get_buf(c, B_DG32, K, &dg32));
     }
+    int16_t *dcol = short_cols ? reinterpret_cast<int16_t *>(col) : nullptr;
     hipLaunchKernelGGL((k_gather_ell<SOp>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K, inv,
-                       W, col, val, val32, dg, dg32, clr, r, r ? rhs : nullptr);
+                       W, short_cols ? nullptr : col, dcol, val, val32, dg, dg32, clr, r,
+                       r ? rhs : nullptr);
     LAUNCH_CHECK();
+    if (short_cols) col = nullptr;
     R->B64 = {col, val, dg, clr, K};
     R->B32 = {col, val32, dg32, clr, K};
+    R->dcol = dcol;
     R->rhs = rhs;
     return LCS_OK;
 }
@@ -1663,15 +1698,30 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
             for (int q = 0; q <= ncol; ++q) c->cblk.start[q] = c->hsc->cstart[q];
             dom = idxb;
         }
+        // a domain in grid order keeps every column within the stencil's
+        // reach of its row (the short form is built for the symmetric 2-D
+        // stencils)
+        const bool short_cols = short_cols_ok<SOp>::value && c->short_cols && dom == idx &&
+                                stencil_reach(M) <= kMaxCol16;
         Restricted<W> R;
-        LCS_TRY(gather<W>(c, As, dom, K, inv, r0, o->precision == LCS_PREC_MIXED, &R, s));
+        LCS_TRY(gather<W>(c, As, dom, K, inv, r0, o->precision == LCS_PREC_MIXED, short_cols, &R,
+                          s));
         double *d;
         LCS_TRY(get_buf(c, B_DL, K, &d));
         const double tl = o->tol_local > 0 ? o->tol_local : o->eps;
         SolveOut so;
-        const lcs_status ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
-                                           &c->dsc->bnorm, tl, o, s, &so, 1,
-                                           uses_gmres(M));
+        lcs_status ls;
+        if constexpr (short_cols_ok<SOp>::value) {
+            if (short_cols)
+                ls = solve_system(c, R.short64(), R.short32(), ncol, (const double *)R.rhs, d,
+                                  true, &c->dsc->bnorm, tl, o, s, &so, 1, uses_gmres(M));
+            else
+                ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
+                                  &c->dsc->bnorm, tl, o, s, &so, 1, uses_gmres(M));
+        } else {
+            ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
+                              &c->dsc->bnorm, tl, o, s, &so, 1, uses_gmres(M));
+        }
         // a local solve that stops at its iteration cap still improves x;
         // the global finish takes over from there
         if (ls != LCS_OK && ls != LCS_ENOCONV) return ls;
@@ -2158,7 +2208,7 @@ lcs_status lcs_gather_restricted(lcs_ctx *c, const lcs_matrix *A, const int32_t 
             return LCS_OK;
         }
         Restricted<W> R;
-        LCS_TRY(gather<W>(c, sop, idx, K, inv, nullptr, false, &R, s));
+        LCS_TRY(gather<W>(c, sop, idx, K, inv, nullptr, false, false, &R, s));
         // ELL -> CSR: row lengths, exclusive scan, fill
         LCS_TRY(get_buf(c, B_ROWLEN, K, &len));
         LCS_TRY(get_buf(c, B_BLOCKOFF, 2 * kMaxGrid, &blocksum));
@@ -2388,6 +2438,12 @@ lcs_status lcs_set_kernel_timing(lcs_ctx *c, int32_t what) {
 lcs_status lcs_set_colour_blocking(lcs_ctx *c, int32_t on) {
     if (!c) return fail(LCS_EINVAL, "ctx is NULL");
     c->colour_blocks = on != 0;
+    return LCS_OK;
+}
+
+lcs_status lcs_set_short_columns(lcs_ctx *c, int32_t on) {
+    if (!c) return fail(LCS_EINVAL, "ctx is NULL");
+    c->short_cols = on != 0;
     return LCS_OK;
 }
 

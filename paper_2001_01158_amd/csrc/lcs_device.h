@@ -1051,6 +1051,31 @@ struct UEll {
     }
 };
 
+// B with its column indices in the short form: the offset col - k of each
+// member in 16 bits (kNoCol16 for padding), for domains in grid order whose
+// rows reach at most kMaxCol16 rows away.  Half the index bytes of UEll,
+// the same members, order and arithmetic.
+constexpr int kNoCol16 = -32768;
+constexpr int64_t kMaxCol16 = 32767;
+
+template <typename real_, int NB_>
+struct UEllShort : UEll<real_, NB_> {
+    using Base = UEll<real_, NB_>;
+    using Unit = typename Base::Unit;
+    const int16_t *dcol;
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        U.i0 = u;
+#pragma unroll
+        for (int s = 0; s < NB_; ++s) {
+            const int d = dcol[s * this->n + u];
+            U.c[s] = d == kNoCol16 ? -1 : (int32_t)u + d;
+            U.a[s][0] = this->val[s * this->n + u];
+        }
+    }
+};
+template <typename real, int NB>
+constexpr bool is_ell<UEllShort<real, NB>> = true;
+
 
 // ---------------------------------------------------------------------------
 // walks: the order in which a grid-sized kernel visits its units

@@ -589,14 +589,16 @@ __global__ __launch_bounds__(kBlock) void k_cblk_place(SOp A, const int32_t *__r
 // ---------------------------------------------------------------------------
 // Row k of B (global row idx[k]) in column-major ELL of width W: members in
 // ascending column order (columns renumbered through inv, which keeps the
-// order), then col = -1.  Also the diagonal, the colour of the row and
-// rhs_B = r^(0)_Omega (right-hand side of the correction form of eq. loc-equ).
+// order), then col = -1; with dcol, the column offsets from k in its place
+// (the caller guarantees they fit in 16 bits).  Also the diagonal, the
+// colour of the row and rhs_B = r^(0)_Omega (right-hand side of the
+// correction form of eq. loc-equ).
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_gather_ell(
     Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv, int W,
-    int32_t *__restrict__ col, double *__restrict__ val, float *__restrict__ val32,
-    double *__restrict__ dg, float *__restrict__ dg32, uint8_t *__restrict__ clr,
-    const double *__restrict__ r, double *__restrict__ rhs) {
+    int32_t *__restrict__ col, int16_t *__restrict__ dcol, double *__restrict__ val,
+    float *__restrict__ val32, double *__restrict__ dg, float *__restrict__ dg32,
+    uint8_t *__restrict__ clr, const double *__restrict__ r, double *__restrict__ rhs) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
          k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = idx[k];
@@ -604,14 +606,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_ell(
         A.for_each(i, [&](int64_t j, double a) {
             const int32_t cj = inv[j];
             if (cj >= 0) {
-                col[t * K + k] = cj;
+                if (dcol) dcol[t * K + k] = (int16_t)(cj - k);
+                else col[t * K + k] = cj;
                 val[t * K + k] = a;
                 if (val32) val32[t * K + k] = (float)a;
                 ++t;
             }
         });
         for (; t < W; ++t) {
-            col[t * K + k] = -1;
+            if (dcol) dcol[t * K + k] = (int16_t)kNoCol16;
+            else col[t * K + k] = -1;
             val[t * K + k] = 0.0;
             if (val32) val32[t * K + k] = 0.0f;
         }

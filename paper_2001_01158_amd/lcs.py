@@ -38,7 +38,8 @@ EXPORTED = ["lcs_default_options", "lcs_create", "lcs_destroy", "lcs_last_error"
             "lcs_set_tiling", "lcs_assemble_heat", "lcs_norm2_diff",
             "lcs_solve_global_batched", "lcs_solve_local_then_global_batched",
             "lcs_workspace_bytes", "lcs_workspace_bytes_batched", "lcs_create_with_workspace",
-            "lcs_build_local_domain_static", "lcs_set_colour_blocking"]
+            "lcs_build_local_domain_static", "lcs_set_colour_blocking",
+            "lcs_set_short_columns"]
 (TIME_NONE, TIME_LOCAL_AP, TIME_LOCAL_UPDATE, TIME_GLOBAL_AP, TIME_GLOBAL_UPDATE, TIME_SMOOTH,
  TIME_SCORE) = range(7)
 
@@ -105,6 +106,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lcs_get_kernel_timing": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "lcs_set_tiling": (I32, [P, I32, I32]),
         "lcs_set_colour_blocking": (I32, [P, I32]),
+        "lcs_set_short_columns": (I32, [P, I32]),
         "lcs_assemble_heat": (I32, [P, I32, I32, D, D, D, D, P, P, P, P, P]),
         "lcs_norm2_diff": (I32, [P, P, P, I64, ctypes.POINTER(D), P]),
         "lcs_workspace_bytes": (ctypes.c_size_t, [PM, PO]),
@@ -623,6 +625,13 @@ def set_colour_blocking(on: bool = True, ctx: Context = None):
     (True, the default) or the domain's ascending order (False); per-row
     results are the same either way (lcs_set_colour_blocking)."""
     _check(lib().lcs_set_colour_blocking(_ctx(ctx), 1 if on else 0))
+
+
+def set_short_columns(on: bool = True, ctx: Context = None):
+    """Index form of the restricted system: 16-bit offsets from the row
+    where they fit (True, the default) or 32-bit indices (False); results
+    are the same either way (lcs_set_short_columns)."""
+    _check(lib().lcs_set_short_columns(_ctx(ctx), 1 if on else 0))
 
 
 def matrix_from_numpy(kind: int, nx: int, ny: int, nz: int, coef, device="cuda",

@@ -426,6 +426,70 @@ def test_colour_blocked_restricted_system(name):
     assert np.linalg.norm(xs[0] - xs[1]) <= 1e-13 * np.linalg.norm(xs[1])
 
 
+@pytest.mark.parametrize("name", ["5pt", "5pt_v", "9pt", "9pt_v", "9pt_w"])
+@pytest.mark.parametrize("prec,pc", [("mixed", "jacobi"), ("fp64", "jacobi"), ("mixed", "rbsgs")])
+def test_short_column_form(name, prec, pc):
+    """The restricted system's column indices as 16-bit offsets from the row
+    (the default on the 2-D stencils) or as 32-bit indices: the same members
+    in the same order, so the local solve returns the same x and iteration
+    count bit for bit.  Under RB-SGS with colour blocking off, so that the
+    domain keeps its grid order."""
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1)
+    assert d.K > 100
+    xs, its = [], []
+    for on in (True, False):
+        say("short columns", name, dims, prec, pc, on)
+        c = lcs.Context()
+        lcs.set_short_columns(on, ctx=c)
+        lcs.set_colour_blocking(False, ctx=c)
+        x = dev(x0)
+        st = lcs.solve_local(A, dev(b), x, dev(d.idx, torch.int32),
+                             lcs.Options(eps=1e-10, precision=prec, precond=pc), ctx=c)
+        xs.append(host(x))
+        its.append(st.its_local)
+    assert its[0] == its[1] > 0
+    assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("kind,nx", [(W.KIND_5PT, 32767), (W.KIND_9PT, 32766),
+                                     (W.KIND_9PT, 32767)])
+def test_short_columns_at_the_offset_limit(kind, nx):
+    """Whole-grid domains on grids as wide as the 16-bit offsets allow (a
+    member 32767 rows from its row: the five-point stencil's north neighbour
+    at nx = 32767, the nine-point's north-east one at nx = 32766) and one
+    wider (nx = 32767 on the nine-point stencil: 32-bit indices).  Short and
+    long forms agree bit for bit, and both follow the oracle's trajectory."""
+    ny, dt = 5, 4.0
+    if kind == W.KIND_5PT:
+        coef = W.assemble_5pt(W.lognormal_logk((ny, nx), 1.0, 7), 1.0 / dt)
+    else:
+        coef = W.assemble_9pt(nx, ny, 1.0 / dt, 100.0, 30.0)
+    n = nx * ny
+    rng = np.random.default_rng(3)
+    Ah = oracle.csr_from_stencil(kind, nx, ny, 1, coef)
+    b = oracle.spmv(Ah, rng.random(n))
+    x0 = np.zeros(n)
+    idx = np.arange(n, dtype=np.int32)
+    oo = oracle.Options(eps=1e-10, max_iter=6, n_smooth=1, pc=oracle.PC_JACOBI)
+    xo, so = oracle.solve_local(Ah, b, x0, idx, oo)
+    A = lcs.matrix_from_numpy(kind, nx, ny, 1, coef, DEV)
+    xs = []
+    for on in (True, False):
+        say("short columns at the limit", kind, nx, ny, on)
+        c = lcs.Context()
+        lcs.set_short_columns(on, ctx=c)
+        x = dev(x0)
+        st = lcs.solve_local(A, dev(b), x, dev(idx, torch.int32),
+                             lcs.Options(eps=1e-10, max_iter=6, n_smooth=1, check_every=1),
+                             ctx=c)
+        assert st.its_local == so.its_local == 6
+        xs.append(host(x))
+        rel = np.linalg.norm(xs[-1] - xo) / np.linalg.norm(xo)
+        assert rel <= 1e-12, (on, rel)
+    assert np.array_equal(xs[0], xs[1])
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("pc", ["jacobi", "rbsgs"])
 def test_solve_local_trajectory_parity(name, pc, ctx):
