@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <mutex>
 #include <string>
@@ -313,6 +314,20 @@ lcs_status wait_for(lcs_ctx *c, hipStream_t s) {
         return LCS_OK;
     }
     HIP_TRY(hipEventRecord(c->done_ev, s));
+    return spin_event(c->done_ev);
+}
+
+// Record done_ev on s, for a later wait_recorded (work enqueued before a
+// wait, such as a refinement step's tail).
+lcs_status record_done(lcs_ctx *c, hipStream_t s) {
+    if (c->done_ev) HIP_TRY(hipEventRecord(c->done_ev, s));
+    return LCS_OK;
+}
+lcs_status wait_recorded(lcs_ctx *c, hipStream_t s) {
+    if (!c->done_ev) {
+        HIP_TRY(hipStreamSynchronize(s));
+        return LCS_OK;
+    }
     return spin_event(c->done_ev);
 }
 
@@ -897,6 +912,10 @@ lcs_status flush_prof(lcs_ctx *c) {
     return LCS_OK;
 }
 
+// A caller's work that follows a PCG solve on the stream and ends with a
+// copy of the scalars to hsc and a record_done (see run_chunks).
+using Tail = std::function<lcs_status()>;
+
 // Enqueue PCG iterations in chunks between host checks, with up to two
 // chunks in flight: the host waits for the older chunk while the newer one
 // runs, so the GPU does not wait for the host.  launch(j) enqueues iteration
@@ -905,11 +924,19 @@ lcs_status flush_prof(lcs_ctx *c) {
 // memory.  The first chunk is sized from the previous solve of the same
 // kind and step; later chunks from the residual's decay so far, so that few
 // launches run (and exit at once) after convergence.
+// tail (optional): enqueued right behind the chunk after which the solve is
+// expected to have stopped; its kernels must do nothing while the stop flag
+// is unset.  No chunk is enqueued behind it: the host waits for the tail,
+// and if the solve had not stopped, enqueues more chunks and the tail again.
+// *tailed: the solve ended with a tail that ran after the stop (hsc holds
+// its copy); otherwise the caller does that work itself.
 template <class F>
 lcs_status run_chunks(lcs_ctx *c, hipStream_t s, int max_iter, int check_every, int prev_its,
-                      F &&launch) {
+                      F &&launch, const Tail *tail = nullptr, bool *tailed = nullptr) {
     int next_j = 0, nin = 0;
     int inflight[2] = {0, 1}, launched_at[2] = {0, 0};
+    bool tail_in = false;
+    if (tailed) *tailed = false;
     bool known = false;
     int known_it = 0;
     double rho = 0.0, rho0 = 0.0, tol = 0.0;
@@ -934,18 +961,46 @@ lcs_status run_chunks(lcs_ctx *c, hipStream_t s, int max_iter, int check_every, 
         inflight[nin++] = sl;
         return LCS_OK;
     };
+    // the tail, once the chunks enqueued so far are expected to end the
+    // solve (always after the final stopping test)
+    auto maybe_tail = [&]() -> lcs_status {
+        if (!tail || tail_in || (next_j < max_iter && next_j < estimate())) return LCS_OK;
+        LCS_TRY((*tail)());
+        tail_in = true;
+        return LCS_OK;
+    };
     LCS_TRY(enqueue(std::max(check_every, prev_its - check_every / 2)));
+    LCS_TRY(maybe_tail());
     for (;;) {
-        if (nin < 2 && next_j < max_iter) {
+        if (!tail_in && nin < 2 && next_j < max_iter) {
             const int len = std::min(check_every, estimate() - next_j);
-            if (len > 0) LCS_TRY(enqueue(len));
+            if (len > 0) {
+                LCS_TRY(enqueue(len));
+                LCS_TRY(maybe_tail());
+            }
+        }
+        if (nin == 0) {
+            // only the tail is in flight, behind a chunk that ended unstopped
+            // (the tail left everything as it was): go on after it
+            if (!tail_in) return fail(LCS_EHIP, "PCG driver: nothing in flight");
+            LCS_TRY(wait_recorded(c, s));
+            tail_in = false;
+            LCS_TRY(enqueue(std::max(1, std::min(check_every, estimate() - next_j))));
+            LCS_TRY(maybe_tail());
+            continue;
         }
         const int sl = inflight[0];
         LCS_TRY(spin_event(c->chk[sl]));
         inflight[0] = inflight[1];
         --nin;
         const PcgState &h = c->hpcg[sl];
-        if (h.done) break;
+        if (h.done) {
+            if (tail_in) {   // the tail runs after the stop
+                LCS_TRY(wait_recorded(c, s));
+                *tailed = true;
+            }
+            break;
+        }
         // the last launch of the chunk tested the residual of iterate
         // launched_at - 1
         known = true;
@@ -953,9 +1008,10 @@ lcs_status run_chunks(lcs_ctx *c, hipStream_t s, int max_iter, int check_every, 
         rho = std::sqrt(h.rr);
         rho0 = std::sqrt(h.rr0);
         tol = h.tol;
-        if (nin == 0) {
+        if (nin == 0 && !tail_in) {
             if (next_j >= max_iter) break;   // not reached: the final test sets the flag
             LCS_TRY(enqueue(std::max(1, std::min(check_every, estimate() - next_j))));
+            LCS_TRY(maybe_tail());
         }
     }
     return LCS_OK;
@@ -974,7 +1030,8 @@ template <class Op, int kPc>
 lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typename Op::real *x,
                    bool x_zero, const double *tol_base, double tol_factor, int max_iter,
                    int check_every, const PcgBufs<typename Op::real> &B, hipStream_t s,
-                   PcgResult *res, int scope, bool sync_end, bool save, bool prepared) {
+                   PcgResult *res, int scope, bool sync_end, bool save, bool prepared,
+                   const Tail *tail, bool *tailed) {
     using real = typename Op::real;
     const int64_t n = A.units() * Op::V;
     const int grid = grid_for(A, kRedGrid);
@@ -1001,7 +1058,8 @@ lcs_status run_cg1(lcs_ctx *c, const Op &A, const typename Op::real *rhs, typena
                                   (const real *)w[a], w[b], j, max_iter, tol_base, tol_factor,
                                   c->dsc, (const real *)part[a], part[b]);
     };
-    LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter));
+    LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter, tail,
+                       tailed));
     if (save) {
         hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
         LAUNCH_CHECK();
@@ -1022,7 +1080,8 @@ template <class Op, int kPc>
 lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real *rhs,
                      typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
                      int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
-                     hipStream_t s, PcgResult *res, int scope, bool sync_end, bool save) {
+                     hipStream_t s, PcgResult *res, int scope, bool sync_end, bool save,
+                     const Tail *tail, bool *tailed) {
     using real = typename Op::real;
     const int64_t n = A.units() * Op::V;
     const int grid = grid_for(A, kRedGrid);
@@ -1064,7 +1123,8 @@ lcs_status run_pcg_t(lcs_ctx *c, const Op &A, int ncol, const typename Op::real 
         flip ^= 1;
         return LCS_OK;
     };
-    LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter));
+    LCS_TRY(run_chunks(c, s, max_iter, check_every, last_its_of(c, scope), launch_iter, tail,
+                       tailed));
     if (save) {
         hipLaunchKernelGGL(k_save_pcg, dim3(1), dim3(1), 0, s, c->dsc, scope);
         LAUNCH_CHECK();
@@ -1086,17 +1146,17 @@ lcs_status run_pcg(lcs_ctx *c, const Op &A, int ncol, int pc, const typename Op:
                    typename Op::real *x, bool x_zero, const double *tol_base, double tol_factor,
                    int max_iter, int check_every, const PcgBufs<typename Op::real> &B,
                    hipStream_t s, PcgResult *res, int scope, bool sync_end, bool save = true,
-                   bool prepared = false) {
+                   bool prepared = false, const Tail *tail = nullptr, bool *tailed = nullptr) {
     switch (pc) {
     case LCS_PC_NONE:
         return run_cg1<Op, 0>(c, A, rhs, x, x_zero, tol_base, tol_factor, max_iter, check_every, B,
-                              s, res, scope, sync_end, save, prepared);
+                              s, res, scope, sync_end, save, prepared, tail, tailed);
     case LCS_PC_JACOBI:
         return run_cg1<Op, 1>(c, A, rhs, x, x_zero, tol_base, tol_factor, max_iter, check_every, B,
-                              s, res, scope, sync_end, save, prepared);
+                              s, res, scope, sync_end, save, prepared, tail, tailed);
     default:   // the caller never prepares this one (k_pcg_init also starts z)
         return run_pcg_t<Op, 2>(c, A, ncol, rhs, x, x_zero, tol_base, tol_factor, max_iter,
-                                check_every, B, s, res, scope, sync_end, save);
+                                check_every, B, s, res, scope, sync_end, save, tail, tailed);
     }
 }
 
@@ -1228,11 +1288,25 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
         c->last_its[scope][std::min(step, 3)] = it;
         return LCS_OK;
     };
-    for (int outer = 0;; ++outer) {
+    // A step's update, the next step's FP64 residual and the read of both
+    // form the step's tail: the PCG driver enqueues it behind the iterations
+    // it expects the inner solve to need (the update waits on the inner
+    // solve's stop flag), so one host round trip serves the end of the inner
+    // solve and the criterion.
+    bool have_res = false;   // the previous step's tail formed and read this step's residual
+    const Tail tail = [&]() -> lcs_status {
+        hipLaunchKernelGGL(k_axpy_scaled, dim3(flat_grid(n)), dim3(kBlock), 0, s, x,
+                           (const float *)d32, n, c->dsc, scope);
+        LAUNCH_CHECK();
         LCS_TRY(launch_resnorm(c, A, rhs, x, r64, tol_base, tol_factor, s));
+        HIP_TRY(hipMemcpyAsync(c->hsc, c->dsc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        return record_done(c, s);
+    };
+    for (int outer = 0;; ++outer) {
+        if (!have_res) LCS_TRY(launch_resnorm(c, A, rhs, x, r64, tol_base, tol_factor, s));
         const bool early = outer == 0 && o->max_iter > 0;
         if (!early) {
-            LCS_TRY(read_scalars(c, s));
+            if (!have_res) LCS_TRY(read_scalars(c, s));
             LCS_TRY(settle());
             out->rr = c->hsc->res.rr;
             if (c->hsc->res.status != kStOk) return status_of(c->hsc->res.status);
@@ -1253,12 +1327,16 @@ lcs_status solve_system_sym(lcs_ctx *c, const Op64 &A, const Op32 &A32, int ncol
         LAUNCH_CHECK();
         PcgResult pr;
         c->cur_outer = outer;
+        bool tailed = false;
         LCS_TRY(run_pcg(c, A32, ncol, o->precond, (const float *)r32, d32, true,
                         (const double *)nullptr, inner, o->max_iter - out->its, check, B, s, &pr,
-                        scope, false, false, prep));
-        hipLaunchKernelGGL(k_axpy_scaled, dim3(flat_grid(n)), dim3(kBlock), 0, s, x,
-                           (const float *)d32, n, c->dsc, scope);
-        LAUNCH_CHECK();
+                        scope, false, false, prep, &tail, &tailed));
+        if (!tailed) {
+            hipLaunchKernelGGL(k_axpy_scaled, dim3(flat_grid(n)), dim3(kBlock), 0, s, x,
+                               (const float *)d32, n, c->dsc, scope);
+            LAUNCH_CHECK();
+        }
+        have_res = tailed;
         pending = outer;
         out->n_outer += 1;
     }
@@ -2387,13 +2465,15 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         if (!crit)
             LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr,
                                    &c->dsc->bnorm, o->eps, s));
+        // the end of the solve when the criterion holds (a global finish
+        // records it again); the read's wait then covers every timer event
+        LCS_TRY(tm.mark(4));
         LCS_TRY(read_scalars(c, s));
         LCS_TRY(finish_local(c, st));
         st->relres_after_local = bn > 0 ? std::sqrt(c->hsc->res.rr) / bn : std::sqrt(c->hsc->res.rr);
         lcs_status rs = LCS_OK;
         if (c->hsc->res.done) {
             st->relres_final = st->relres_after_local;
-            LCS_TRY(tm.mark(4));
         } else {
             SolveOut so;
             rs = solve_system(c, op, op32, colours_of(A), b, x, false, &c->dsc->bnorm, o->eps,
@@ -2402,8 +2482,8 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
             st->n_outer += so.n_outer;
             st->relres_final = bn > 0 ? std::sqrt(so.rr) / bn : std::sqrt(so.rr);
             LCS_TRY(tm.mark(4));
+            LCS_TRY(wait_for(c, s));
         }
-        LCS_TRY(wait_for(c, s));
         LCS_TRY(flush_prof(c));
         st->ms_construct = tm.ms(0, 1);
         st->ms_local = tm.ms(1, 2);

@@ -1796,11 +1796,15 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(const double *__restric
 // x += scale * d32: the FP64 update of one refinement step; skipped when the
 // inner solve of that step broke down or went non-finite, so x keeps the
 // last good iterate.  Also keeps the inner solve's outcome in
-// saved_it / saved_status[scope] (k_save_pcg's work).
+// saved_it / saved_status[scope] (k_save_pcg's work).  Nothing happens
+// while the inner solve has not stopped (its stop flag unset): the host may
+// enqueue the update behind the iterations it expects the solve to need,
+// and enqueues more iterations and the update again if they were too few.
 __global__ __launch_bounds__(kBlock) void k_axpy_scaled(double *__restrict__ x,
                                                         const float *__restrict__ d32,
                                                         int64_t n, Scalars *sc, int scope) {
-    const int st = sc->pcg.done ? sc->pcg.status : kStNoConv;
+    if (!sc->pcg.done) return;
+    const int st = sc->pcg.status;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->saved_it[scope] = sc->pcg.it;
         sc->saved_status[scope] = st;
