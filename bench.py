@@ -1019,9 +1019,12 @@ def _dominant():
                 "what": "four-colour Gauss-Seidel sweep of Algorithm 1 step 7 in one pass, "
                         "forming the residual of step 8",
                 "bytes_per_row": 64, "units": grid_rows(1), "launches": grid_launches(1)},
+               # reads the five coefficient arrays, b and x0 and writes r0,
+               # plus the copy of x0 that the one-pass sweep starts from
                {"class": lcs.TIME_SCORE, "name": "k_score<U9<double,2,2>,0>",
-                "what": "r0 = b - A x0 with its norms (Algorithm 3's score)",
-                "bytes_per_row": 64, "units": grid_rows(1), "launches": grid_launches(1)}],
+                "what": "r0 = b - A x0 with its norms (Algorithm 3's score), and the copy of "
+                        "x0 the sweep starts from",
+                "bytes_per_row": 72, "units": grid_rows(1), "launches": grid_launches(1)}],
     }
 
 

@@ -1481,11 +1481,13 @@ struct short_cols_ok<Stencil9<double>> : std::true_type {};
 // Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
 // ascending domain in idx; returns K (host).  eps0 >= 0: ||b|| (from the
 // score pass) goes to dsc->bnorm, and an x0 with ||b - A x0|| <= eps0 ||b||
-// gives the empty domain and hsc->ms.conv0 = 1.
+// gives the empty domain and hsc->ms.conv0 = 1.  xcopy (optional): the score
+// pass also copies x0 there.
 template <class SOp, class UOp>
 lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *b,
                         const double *x0, int mode, int thresh, double theta, int e_max,
-                        double eps0, int32_t *idx, int64_t *K, hipStream_t s) {
+                        double eps0, int32_t *idx, int64_t *K, hipStream_t s,
+                        double *xcopy = nullptr) {
     const int64_t n = As.n;
     const Tiling T = tiling_for(n);
     const int gs = grid_for(Au, kRedGrid);
@@ -1499,10 +1501,10 @@ lcs_status build_domain(lcs_ctx *c, const SOp &As, const UOp &Au, const double *
     const bool timed = c->prof_what == LCS_TIME_SCORE;
     if (mode == LCS_MODE_RESIDUAL)
         LCS_TRY(launch_maybe_timed(c, timed, k_score<UOp, 0>, gs, s, Au, b, x0, score,
-                                   slot(c, kPtScore)));
+                                   slot(c, kPtScore), xcopy));
     else
         LCS_TRY(launch_maybe_timed(c, timed, k_score<UOp, 1>, gs, s, Au, b, x0, score,
-                                   slot(c, kPtScore)));
+                                   slot(c, kPtScore), xcopy));
     const int gmark = (int)std::min<int64_t>(T.npad / kTile, 2048);   // 2048 stamps per block step
     hipLaunchKernelGGL(k_mark, dim3(gmark), dim3(kBlock), 0, s, (const double *)score, stamp, n,
                        T.npad, thresh, theta, eps0, (const double *)slot(c, kPtScore), gs, c->dsc);
@@ -1631,10 +1633,24 @@ lcs_status resident_waves(K kernel, std::atomic<int64_t> &cache, int64_t *out) {
 // forms the criterion of step 8 (||b - A x|| <= crit_eps ||b||, into
 // dsc->res) in its last pass and sets *crit_done; other paths leave it to
 // the caller.
+// Whether launch_sweeps takes the one-pass path (k_gs_sweep9): the
+// nine-point stencil in strips of two cells, four colours, with the
+// criterion, on grids of at least kMaxGrid tiles of 16 rows.
+template <class UOp>
+bool one_pass_sweeps(const UOp &Au, int ncol, int n_sweeps, double crit_eps) {
+    if constexpr (is_pair9<UOp>::value) {
+        const int64_t strips1 = ((int64_t)Au.nx / 2 + kSweepOwn - 1) / kSweepOwn;
+        return ncol == 4 && crit_eps >= 0.0 && n_sweeps > 0 &&
+               strips1 * ((Au.ny + 15) / 16) >= kMaxGrid;
+    } else {
+        return false;
+    }
+}
+
 template <class UOp>
 lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, int ncol,
                          int n_sweeps, hipStream_t s, double crit_eps = -1.0,
-                         bool *crit_done = nullptr) {
+                         bool *crit_done = nullptr, bool tmp_holds_x = false) {
     const bool timed = c->prof_what == LCS_TIME_SMOOTH;
     if constexpr (is_pair9<UOp>::value) {
         if (ncol == 4) {
@@ -1642,13 +1658,15 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
             LCS_TRY(get_buf(c, B_GSX, (size_t)Au.n, &tmp));
             const bool fuse = crit_eps >= 0.0 && n_sweeps > 0;
             const int64_t strips1 = ((int64_t)Au.nx / 2 + kSweepOwn - 1) / kSweepOwn;
-            if (fuse && strips1 * ((Au.ny + 15) / 16) >= kMaxGrid) {
+            if (one_pass_sweeps(Au, ncol, n_sweeps, crit_eps)) {
                 // Whole sweeps in one pass each (k_gs_sweep9), the last one
                 // forming the criterion; they alternate between x and the
-                // second buffer, and a copy brings an odd count's result back
-                // to x.  Tiles of an even number of rows, at least 16 (a tile
-                // updates two or three rows outside it again), grown until
-                // there is at most one per wave that the GPU holds at once
+                // second buffer and end in x: an odd count starts from the
+                // second buffer when it holds x already (tmp_holds_x), else
+                // a copy brings the result back.  Tiles of an even number of
+                // rows, at least 16 (a tile updates two or three rows
+                // outside it again), grown until there is at most one per
+                // wave that the GPU holds at once
                 // (the kernel's occupancy, asked of the runtime once), so
                 // that no wave waits for a second round; at most kMaxGrid
                 // blocks (the partials).  Used once the grid has at least
@@ -1662,8 +1680,9 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
                 const int64_t tiles = strips1 * ((Au.ny + mh - 1) / mh);
                 int grid = (int)std::min<int64_t>(kMaxGrid, (tiles + kWaves - 1) / kWaves);
                 grid = std::min(kMaxGrid, std::max(kXcds, (grid + kXcds - 1) / kXcds * kXcds));
-                const double *src = x;
-                double *dst = tmp;
+                const bool from_tmp = tmp_holds_x && (n_sweeps & 1);
+                const double *src = from_tmp ? tmp : x;
+                double *dst = from_tmp ? x : tmp;
                 for (int sw = 0; sw < n_sweeps; ++sw) {
                     if (sw == n_sweeps - 1) {
                         LCS_TRY(launch_maybe_timed(c, timed, k_gs_sweep9<UOp, true>, grid, s, Au, b,
@@ -1736,11 +1755,14 @@ lcs_status launch_sweeps(lcs_ctx *c, const UOp &Au, const double *b, double *x, 
 
 // x <- x + d on Omega after solving B d = r^(0)_Omega, then smoothing.
 // r0: r^(0) over the whole grid when the caller already has it, else null.
+// xcopy: the sweeps' second buffer when it holds a copy of x (kept equal to
+// x through the update), else null.
 template <int W, class SOp, class UOp>
 lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp &Au,
                        const double *b, double *x, const int32_t *idx, int64_t K,
                        const int32_t *inv, const double *r0, const lcs_options *o,
-                       lcs_stats *st, Timers &tm, hipStream_t s, bool *crit_done) {
+                       lcs_stats *st, Timers &tm, hipStream_t s, bool *crit_done,
+                       double *xcopy = nullptr) {
     const int ncol = colours_of(M);
     if (K > 0) {
         if (!r0) {
@@ -1806,12 +1828,14 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         st->its_local = so.its;   // -1: read from the device state after the next sync
         st->n_outer += so.n_outer;
         hipLaunchKernelGGL(k_scatter_add, dim3(flat_grid(K)), dim3(kBlock), 0, s, dom,
-                           (const double *)d, K, x);
+                           (const double *)d, K, x, xcopy);
         LAUNCH_CHECK();
     }
     LCS_TRY(tm.mark(2));
     *crit_done = false;
-    if (o->n_smooth > 0) LCS_TRY(launch_sweeps(c, Au, b, x, ncol, o->n_smooth, s, o->eps, crit_done));
+    if (o->n_smooth > 0)
+        LCS_TRY(launch_sweeps(c, Au, b, x, ncol, o->n_smooth, s, o->eps, crit_done,
+                              xcopy != nullptr));
     LCS_TRY(tm.mark(3));
     return LCS_OK;
 }
@@ -2177,7 +2201,7 @@ lcs_status lcs_gradient(lcs_ctx *c, const lcs_matrix *A, const double *x, double
     return with_ops(c, A, nullptr, vec_ok({x, g}), [&](auto, auto op, auto, auto) -> lcs_status {
         const int grid = grid_for(op, kRedGrid);
         hipLaunchKernelGGL((k_score<decltype(op), 1>), dim3(grid), dim3(kBlock), 0, s, op, x, x, g,
-                           slot(c, kPtScore));
+                           slot(c, kPtScore), (double *)nullptr);
         LAUNCH_CHECK();
         LCS_TRY(wait_for(c, s));
         return LCS_OK;
@@ -2434,8 +2458,13 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         int32_t *idx;
         LCS_TRY(get_buf(c, B_IDX, n, &idx));
         int64_t K = 0;
+        // an odd number of one-pass sweeps starts from a copy of x that the
+        // score pass writes (so that the last one writes x itself)
+        double *xcopy = nullptr;
+        if (one_pass_sweeps(op, colours_of(A), o->n_smooth, o->eps) && (o->n_smooth & 1))
+            LCS_TRY(get_buf(c, B_GSX, (size_t)n, &xcopy));
         LCS_TRY(build_domain(c, sop, op, b, (const double *)x, mode, thresh_kind, theta, e_max,
-                             o->eps, idx, &K, s));
+                             o->eps, idx, &K, s, xcopy));
         st->K = K;
         st->e_rounds = c->hsc->ms.grown;
         st->tau = c->hsc->ms.tau;
@@ -2461,7 +2490,7 @@ lcs_status lcs_solve_local_then_global(lcs_ctx *c, const lcs_matrix *A, const do
         // criterion after the local solve and smoothing (Algorithm 1 step
         // 8), formed in the last sweep pass where the sweep allows it
         bool crit = false;
-        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, r0, o, st, tm, s, &crit));
+        LCS_TRY(local_phase<W>(c, A, sop, op, b, x, idx, K, inv, r0, o, st, tm, s, &crit, xcopy));
         if (!crit)
             LCS_TRY(launch_resnorm(c, op, b, (const double *)x, (double *)nullptr,
                                    &c->dsc->bnorm, o->eps, s));

@@ -99,11 +99,13 @@ constexpr size_t kSlotElems = (size_t)kMaxGrid * 4;
 // Residual mode: s = r^(0) = b - A x0 (FMA chain, ascending columns).
 // Gradient mode: s = g, g_i = sum_{j != i} |x_i - x_j| (eq. grad).
 // Partials: max |s_i|, ||b||^2 and ||r^(0)||^2 (the gradient mode forms r^(0)
-// in registers for the last one).
+// in registers for the last one).  xc (optional): a copy of x0, written from
+// the values the pass has loaded anyway.
 template <class Op, int kMode>
 __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict__ b,
                                                   const double *__restrict__ x,
-                                                  double *__restrict__ s, double *part) {
+                                                  double *__restrict__ s, double *part,
+                                                  double *__restrict__ xc) {
     constexpr int V = Op::V, NB = Op::NB;
     double v[3] = {0.0, 0.0, 0.0};
     for (auto W = walk<1>(A); W.valid(); W.advance()) {
@@ -138,6 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_score(Op A, const double *__restrict
             }
         }
         A.put(U, s, out);
+        if (xc) {
+            double xo[V];
+            own_of(A, U, xv, x, xo);
+            A.put(U, xc, xo);
+        }
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             const double m = fabs(out[k]);
@@ -425,16 +432,34 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint8_t *__restrict__ 
         int tt;
         int pos = off + block_exclusive_scan(c, tt);
         const int64_t row0 = t * kTile + (int64_t)threadIdx.x * 8;
+        if (row0 + 8 <= n) {
+            // the thread's 8 rows of inv as two 16-byte stores (row0 is a
+            // multiple of 8), so that a wave writes whole lines
+            int v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t i = row0 + k;
-            if (i >= n) break;
-            if ((word >> (8 * k)) & 0xffull) {
-                idx[pos] = (int32_t)i;
-                inv[i] = pos;
-                ++pos;
-            } else {
-                inv[i] = -1;
+            for (int k = 0; k < 8; ++k) {
+                if ((word >> (8 * k)) & 0xffull) {
+                    idx[pos] = (int32_t)(row0 + k);
+                    v[k] = pos++;
+                } else {
+                    v[k] = -1;
+                }
+            }
+            int4 *o = reinterpret_cast<int4 *>(inv + row0);
+            o[0] = make_int4(v[0], v[1], v[2], v[3]);
+            o[1] = make_int4(v[4], v[5], v[6], v[7]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t i = row0 + k;
+                if (i >= n) break;
+                if ((word >> (8 * k)) & 0xffull) {
+                    idx[pos] = (int32_t)i;
+                    inv[i] = pos;
+                    ++pos;
+                } else {
+                    inv[i] = -1;
+                }
             }
         }
         off += tt;
@@ -671,13 +696,19 @@ __global__ __launch_bounds__(kBlock) void k_set_inv(const int32_t *__restrict__ 
     }
 }
 
-// x[idx[k]] += d[k]  (eq. sol-assemble in correction form)
+// x[idx[k]] += d[k]  (eq. sol-assemble in correction form); x2 (optional,
+// a copy of x) gets the same new values.
 __global__ __launch_bounds__(kBlock) void k_scatter_add(const int32_t *__restrict__ idx,
                                                         const double *__restrict__ d, int64_t K,
-                                                        double *__restrict__ x) {
+                                                        double *__restrict__ x,
+                                                        double *__restrict__ x2) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
-         k += (int64_t)gridDim.x * kBlock)
-        x[idx[k]] += d[k];
+         k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = idx[k];
+        const double v = x[i] + d[k];
+        x[i] = v;
+        if (x2) x2[i] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------

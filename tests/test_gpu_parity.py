@@ -175,6 +175,44 @@ def test_nine_point_sweep_forms_the_criterion(dims, ctx):
         assert abs(st.relres_final - rel) <= 1e-13 * rel, (st.relres_final, rel)
 
 
+@pytest.mark.parametrize("dims", [(1008, 2001), (2048, 1030)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_one_pass_sweep_from_the_score_copy(dims, prec):
+    """Algorithm 1 on grids where the nine-point sweep runs in one pass: the
+    score pass copies x^(0) into the sweep's second buffer, step 6 keeps the
+    copy equal to x, and the single sweep reads it and writes x (no copy
+    back).  x^(0) differs from the solution on a box, which the domain
+    covers, so the local solve and the sweep meet the criterion.  The result
+    equals solve_local's on the same domain (the sweep from x with a copy
+    back) bit for bit, and the oracle's within the criterion."""
+    nx, ny = dims
+    coef = W.assemble_9pt(nx, ny, 0.25, 100.0, 30.0)
+    Ah = oracle.csr_from_stencil(W.KIND_9PT, nx, ny, 1, coef)
+    rng = np.random.default_rng(nx + 7 * ny)
+    x_true = 0.1 + 0.01 * rng.random(nx * ny)
+    b = oracle.spmv(Ah, x_true)
+    x0 = x_true.copy()
+    g = x0.reshape(ny, nx)
+    g[ny // 3: ny // 3 + 40, nx // 2: nx // 2 + 50] *= 1.0 + 0.3 * rng.random((40, 50))
+    A = lcs.matrix_from_numpy(W.KIND_9PT, nx, ny, 1, coef, DEV)
+    opts = lcs.Options(eps=1e-10, precision=prec)
+    say("one-pass sweep from the score copy", dims, prec)
+    x = dev(x0)
+    st = lcs.solve_local_then_global(A, dev(b), x, "residual", "relmax", 1e-12, 1, opts,
+                                     ctx=lcs.Context())
+    assert st.its_global == 0 and st.relres_final <= 1e-10, (st.its_global, st.relres_final)
+    c2 = lcs.Context()
+    idx, _, _ = lcs.build_local_domain(A, dev(b), dev(x0), "residual", "relmax", 1e-12, 1, ctx=c2)
+    assert idx.numel() == st.K > 2000
+    x2 = dev(x0)
+    st2 = lcs.solve_local(A, dev(b), x2, idx, opts, ctx=c2)
+    assert np.array_equal(host(x), host(x2))
+    assert abs(st.relres_final - st2.relres_final) <= 1e-13 * st2.relres_final
+    xo, so = oracle.solve_local(Ah, b, x0, host(idx), oracle.Options(eps=1e-10))
+    rel = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    assert rel <= 1e-9, rel
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv_fp64(name, ctx):
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
