@@ -997,10 +997,9 @@ def c2_extra(args):
 # classes and algorithmic bytes per row.
 def _dominant():
     from paper_2001_01158_amd import lcs
-    # one single-sync PCG iteration on B: W slots of index (2 B in the
-    # short form of the 2-D stencils' domains) and value, and 11 vector
-    # accesses
-    ell = lambda W_, real_b, idx_b=2: W_ * (idx_b + real_b) + 11 * real_b
+    # one single-sync PCG iteration on B: W value slots, the row's column
+    # code (5 B on the 2-D stencils' domains) and 11 vector accesses
+    ell = lambda W_, real_b: W_ * real_b + 5 + 11 * real_b
     local_rows = lambda w, sts: float(sum(s.K * s.its_local for s in sts))
     local_its = lambda w, sts: int(sum(s.its_local for s in sts))
     grid_rows = lambda per: (lambda w, sts: float(w.n * per * sum(1 for s in sts if s.K > 0)))

@@ -1547,14 +1547,18 @@ struct Restricted {
     UEll<double, W> B64;
     UEll<float, W> B32;
     double *rhs;
-    const int16_t *dcol;   // the short form's column offsets (B64/B32.col unset), or null
-    UEllShort<double, W> short64() const { return {B64, dcol}; }
-    UEllShort<float, W> short32() const { return {B32, dcol}; }
+    bool row_coded;   // B64 / B32 in UEllShort's form (code), their col unset
+    RowCode code;
 };
+template <int W>
+UEllShort<double, W> short64(const Restricted<W> &R) { return {R.B64, R.code}; }
+template <int W>
+UEllShort<float, W> short32(const Restricted<W> &R) { return {R.B32, R.code}; }
 
 // B = A[idx, idx] in ELL (one pass, no scan); rhs = r[idx] when r is given.
-// short_cols: the indices as 16-bit offsets from the row, in the same
-// buffer (the caller checks that every offset fits).
+// short_cols: in UEllShort's form (the caller checks that the domain is in
+// grid order on a five- or nine-point stencil whose reach fits), its row
+// codes in the column buffer.
 template <int W, class SOp>
 lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const int32_t *inv,
                   const double *r, bool with32, bool short_cols, Restricted<W> *R, hipStream_t s) {
@@ -1571,15 +1575,32 @@ lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const
         LCS_TRY(get_buf(c, B_VAL32, (size_t)K * W, &val32));
         LCS_TRY(get_buf(c, B_DG32, K, &dg32));
     }
-    int16_t *dcol = short_cols ? reinterpret_cast<int16_t *>(col) : nullptr;
+    R->row_coded = false;
+    R->code = RowCode{nullptr, nullptr, nullptr};
+    if constexpr (short_cols_ok<SOp>::value) {
+        if (short_cols) {
+            static_assert(SOp::kSlots == W, "row codes take the stencil's slots");
+            // 5 bytes per row of the column buffer's 4 W
+            int16_t *so = reinterpret_cast<int16_t *>(col), *no = so + K;
+            uint8_t *mk = reinterpret_cast<uint8_t *>(no + K);
+            hipLaunchKernelGGL((k_gather_rowcode<SOp>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A,
+                               idx, K, inv, so, no, mk, val, val32, dg, dg32, clr, r,
+                               r ? rhs : nullptr);
+            LAUNCH_CHECK();
+            R->B64 = {nullptr, val, dg, clr, K};
+            R->B32 = {nullptr, val32, dg32, clr, K};
+            R->rhs = rhs;
+            R->row_coded = true;
+            R->code = RowCode{so, no, mk};
+            return LCS_OK;
+        }
+    }
+    if (short_cols) return fail(LCS_EINVAL, "short column form on this operator");
     hipLaunchKernelGGL((k_gather_ell<SOp>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A, idx, K, inv,
-                       W, short_cols ? nullptr : col, dcol, val, val32, dg, dg32, clr, r,
-                       r ? rhs : nullptr);
+                       W, col, val, val32, dg, dg32, clr, r, r ? rhs : nullptr);
     LAUNCH_CHECK();
-    if (short_cols) col = nullptr;
     R->B64 = {col, val, dg, clr, K};
     R->B32 = {col, val32, dg32, clr, K};
-    R->dcol = dcol;
     R->rhs = rhs;
     return LCS_OK;
 }
@@ -1812,8 +1833,8 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         SolveOut so;
         lcs_status ls;
         if constexpr (short_cols_ok<SOp>::value) {
-            if (short_cols)
-                ls = solve_system(c, R.short64(), R.short32(), ncol, (const double *)R.rhs, d,
+            if (R.row_coded)
+                ls = solve_system(c, short64(R), short32(R), ncol, (const double *)R.rhs, d,
                                   true, &c->dsc->bnorm, tl, o, s, &so, 1, uses_gmres(M));
             else
                 ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,

@@ -61,6 +61,18 @@ struct Stencil5 {
         if (x < nx - 1) f(i + 1, E[i]);
         if (y < ny - 1) f(i + nx, N[i]);
     }
+    // the same members with their stencil slots: S, W, C, E, N (ascending)
+    static constexpr int kSlots = 5;
+    template <class F>
+    __device__ __forceinline__ void for_each_slot(int64_t i, F &&f) const {
+        const int y = (int)((uint32_t)i / (uint32_t)nx);
+        const int x = (int)i - y * nx;
+        if (y > 0) f(0, i - nx, N[i - nx]);
+        if (x > 0) f(1, i - 1, E[i - 1]);
+        f(2, i, C[i]);
+        if (x < nx - 1) f(3, i + 1, E[i]);
+        if (y < ny - 1) f(4, i + nx, N[i]);
+    }
     __device__ __forceinline__ real diag(int64_t i) const { return C[i]; }
     __device__ __forceinline__ int colour(int64_t i) const {
         const int y = (int)((uint32_t)i / (uint32_t)nx);
@@ -88,6 +100,24 @@ struct Stencil9 {
         if (nn && w) f(i + nx - 1, NW[i]);
         if (nn) f(i + nx, N[i]);
         if (nn && e) f(i + nx + 1, NE[i]);
+    }
+    // the same members with their stencil slots: SW, S, SE, W, C, E, NW, N,
+    // NE (ascending)
+    static constexpr int kSlots = 9;
+    template <class F>
+    __device__ __forceinline__ void for_each_slot(int64_t i, F &&f) const {
+        const int y = (int)((uint32_t)i / (uint32_t)nx);
+        const int x = (int)i - y * nx;
+        const bool w = x > 0, e = x < nx - 1, s = y > 0, nn = y < ny - 1;
+        if (s && w) f(0, i - nx - 1, NE[i - nx - 1]);
+        if (s) f(1, i - nx, N[i - nx]);
+        if (s && e) f(2, i - nx + 1, NW[i - nx + 1]);
+        if (w) f(3, i - 1, E[i - 1]);
+        f(4, i, C[i]);
+        if (e) f(5, i + 1, E[i]);
+        if (nn && w) f(6, i + nx - 1, NW[i]);
+        if (nn) f(7, i + nx, N[i]);
+        if (nn && e) f(8, i + nx + 1, NE[i]);
     }
     __device__ __forceinline__ real diag(int64_t i) const { return C[i]; }
     // four colours: no two cells of one colour share a nine-point stencil
@@ -1051,26 +1081,56 @@ struct UEll {
     }
 };
 
-// B with its column indices in the short form: the offset col - k of each
-// member in 16 bits (kNoCol16 for padding), for domains in grid order whose
-// rows reach at most kMaxCol16 rows away.  Half the index bytes of UEll,
-// the same members, order and arithmetic.
-constexpr int kNoCol16 = -32768;
+// B of a domain in grid order on the five- or nine-point stencil, with its
+// columns coded per row instead of per member: the values sit in the
+// stencil's fixed slots (S, W, C, E, N or SW, S, SE, W, C, E, NW, N, NE:
+// ascending column order, zero where the neighbour is outside the grid or
+// the domain), and a member's column follows from the row's position k, a
+// presence bit and, for the rows below and above, soff / noff = p - k, p the
+// number of domain cells before the cell straight below (above) in grid
+// order: W = k - 1, E = k + 1, S = p, SW = p - 1, SE = p + [S present], and
+// the same above.  5 bytes per row instead of 4 per member, for domains
+// whose rows reach at most kMaxCol16 rows away; the same members, order and
+// arithmetic as UEll.
 constexpr int64_t kMaxCol16 = 32767;
+
+struct RowCode {
+    const int16_t *soff, *noff;
+    const uint8_t *mask;   // bit b: slot b (b < centre) or b + 1 present
+};
 
 template <typename real_, int NB_>
 struct UEllShort : UEll<real_, NB_> {
+    static_assert(NB_ == 5 || NB_ == 9, "row codes of the 2-D stencils");
     using Base = UEll<real_, NB_>;
     using Unit = typename Base::Unit;
-    const int16_t *dcol;
+    static constexpr int kMid = NB_ / 2;
+    RowCode code;
     __device__ __forceinline__ void load(Unit &U, int64_t u) const {
         U.i0 = u;
-#pragma unroll
-        for (int s = 0; s < NB_; ++s) {
-            const int d = dcol[s * this->n + u];
-            U.c[s] = d == kNoCol16 ? -1 : (int32_t)u + d;
-            U.a[s][0] = this->val[s * this->n + u];
+        const int k = (int)u;
+        const int so = k + code.soff[u], no = k + code.noff[u];
+        const unsigned m = code.mask[u];
+        auto has = [&](int sl) -> int { return (int)((m >> (sl < kMid ? sl : sl - 1)) & 1u); };
+        if constexpr (NB_ == 9) {
+            U.c[0] = has(0) ? so - 1 : -1;
+            U.c[1] = has(1) ? so : -1;
+            U.c[2] = has(2) ? so + has(1) : -1;
+            U.c[3] = has(3) ? k - 1 : -1;
+            U.c[4] = k;
+            U.c[5] = has(5) ? k + 1 : -1;
+            U.c[6] = has(6) ? no - 1 : -1;
+            U.c[7] = has(7) ? no : -1;
+            U.c[8] = has(8) ? no + has(7) : -1;
+        } else {
+            U.c[0] = has(0) ? so : -1;
+            U.c[1] = has(1) ? k - 1 : -1;
+            U.c[2] = k;
+            U.c[3] = has(3) ? k + 1 : -1;
+            U.c[4] = has(4) ? no : -1;
         }
+#pragma unroll
+        for (int sl = 0; sl < NB_; ++sl) U.a[sl][0] = this->val[sl * this->n + u];
     }
 };
 template <typename real, int NB>

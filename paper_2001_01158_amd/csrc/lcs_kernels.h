@@ -614,16 +614,14 @@ __global__ __launch_bounds__(kBlock) void k_cblk_place(SOp A, const int32_t *__r
 // ---------------------------------------------------------------------------
 // Row k of B (global row idx[k]) in column-major ELL of width W: members in
 // ascending column order (columns renumbered through inv, which keeps the
-// order), then col = -1; with dcol, the column offsets from k in its place
-// (the caller guarantees they fit in 16 bits).  Also the diagonal, the
-// colour of the row and rhs_B = r^(0)_Omega (right-hand side of the
-// correction form of eq. loc-equ).
+// order), then col = -1.  Also the diagonal, the colour of the row and
+// rhs_B = r^(0)_Omega (right-hand side of the correction form of eq. loc-equ).
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_gather_ell(
     Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv, int W,
-    int32_t *__restrict__ col, int16_t *__restrict__ dcol, double *__restrict__ val,
-    float *__restrict__ val32, double *__restrict__ dg, float *__restrict__ dg32,
-    uint8_t *__restrict__ clr, const double *__restrict__ r, double *__restrict__ rhs) {
+    int32_t *__restrict__ col, double *__restrict__ val, float *__restrict__ val32,
+    double *__restrict__ dg, float *__restrict__ dg32, uint8_t *__restrict__ clr,
+    const double *__restrict__ r, double *__restrict__ rhs) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
          k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = idx[k];
@@ -631,19 +629,74 @@ __global__ __launch_bounds__(kBlock) void k_gather_ell(
         A.for_each(i, [&](int64_t j, double a) {
             const int32_t cj = inv[j];
             if (cj >= 0) {
-                if (dcol) dcol[t * K + k] = (int16_t)(cj - k);
-                else col[t * K + k] = cj;
+                col[t * K + k] = cj;
                 val[t * K + k] = a;
                 if (val32) val32[t * K + k] = (float)a;
                 ++t;
             }
         });
         for (; t < W; ++t) {
-            if (dcol) dcol[t * K + k] = (int16_t)kNoCol16;
-            else col[t * K + k] = -1;
+            col[t * K + k] = -1;
             val[t * K + k] = 0.0;
             if (val32) val32[t * K + k] = 0.0f;
         }
+        const double d = A.diag(i);
+        dg[k] = d;
+        if (dg32) dg32[k] = (float)d;
+        clr[k] = (uint8_t)A.colour(i);
+        if (rhs) rhs[k] = r[i];
+    }
+}
+
+// The same B in UEllShort's form (a domain in grid order on the five- or
+// nine-point stencil): the values in the stencil's fixed slots (zero where
+// the neighbour is not a member), each row's presence bits and the offsets
+// soff / noff of the number of members before the cell straight below /
+// above (found from whichever of the cells below / above are members; zero
+// when none is).
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_gather_rowcode(
+    Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv,
+    int16_t *__restrict__ soff, int16_t *__restrict__ noff, uint8_t *__restrict__ mask,
+    double *__restrict__ val, float *__restrict__ val32, double *__restrict__ dg,
+    float *__restrict__ dg32, uint8_t *__restrict__ clr, const double *__restrict__ r,
+    double *__restrict__ rhs) {
+    constexpr int NB = Op::kSlots, kMid = NB / 2;
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = idx[k];
+        int32_t cs[NB];
+        double a[NB];
+#pragma unroll
+        for (int sl = 0; sl < NB; ++sl) {
+            cs[sl] = -1;
+            a[sl] = 0.0;
+        }
+        A.for_each_slot(i, [&](int sl, int64_t j, double v) {
+            const int32_t cj = inv[j];
+            if (cj >= 0) {
+                cs[sl] = cj;
+                a[sl] = v;
+            }
+        });
+        unsigned m = 0;
+#pragma unroll
+        for (int sl = 0; sl < NB; ++sl) {
+            if (sl != kMid && cs[sl] >= 0) m |= 1u << (sl < kMid ? sl : sl - 1);
+            val[sl * K + k] = a[sl];
+            if (val32) val32[sl * K + k] = (float)a[sl];
+        }
+        int64_t ps = k, pn = k;
+        if constexpr (NB == 9) {
+            ps = cs[0] >= 0 ? cs[0] + 1 : cs[1] >= 0 ? cs[1] : cs[2] >= 0 ? cs[2] : k;
+            pn = cs[6] >= 0 ? cs[6] + 1 : cs[7] >= 0 ? cs[7] : cs[8] >= 0 ? cs[8] : k;
+        } else {
+            ps = cs[0] >= 0 ? cs[0] : k;
+            pn = cs[4] >= 0 ? cs[4] : k;
+        }
+        soff[k] = (int16_t)(ps - k);
+        noff[k] = (int16_t)(pn - k);
+        mask[k] = (uint8_t)m;
         const double d = A.diag(i);
         dg[k] = d;
         if (dg32) dg32[k] = (float)d;
