@@ -467,11 +467,12 @@ def test_colour_blocked_restricted_system(name):
 @pytest.mark.parametrize("name", ["5pt", "5pt_v", "9pt", "9pt_v", "9pt_w"])
 @pytest.mark.parametrize("prec,pc", [("mixed", "jacobi"), ("fp64", "jacobi"), ("mixed", "rbsgs")])
 def test_short_column_form(name, prec, pc):
-    """The restricted system's column indices as 16-bit offsets from the row
-    (the default on the 2-D stencils) or as 32-bit indices: the same members
-    in the same order, so the local solve returns the same x and iteration
-    count bit for bit.  Under RB-SGS with colour blocking off, so that the
-    domain keeps its grid order."""
+    """The restricted system's columns coded per row (fixed stencil slots,
+    offsets to the rows below and above and presence bits: the default on
+    the 2-D stencils) or as 32-bit indices: the same members in the same
+    order, so the local solve returns the same x and iteration count bit for
+    bit.  Under RB-SGS with colour blocking off, so that the domain keeps its
+    grid order."""
     kind, dims, coef, Ah, A, b, x0 = make_case(name)
     d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1)
     assert d.K > 100
@@ -493,11 +494,12 @@ def test_short_column_form(name, prec, pc):
 @pytest.mark.parametrize("kind,nx", [(W.KIND_5PT, 32767), (W.KIND_9PT, 32766),
                                      (W.KIND_9PT, 32767)])
 def test_short_columns_at_the_offset_limit(kind, nx):
-    """Whole-grid domains on grids as wide as the 16-bit offsets allow (a
-    member 32767 rows from its row: the five-point stencil's north neighbour
-    at nx = 32767, the nine-point's north-east one at nx = 32766) and one
-    wider (nx = 32767 on the nine-point stencil: 32-bit indices).  Short and
-    long forms agree bit for bit, and both follow the oracle's trajectory."""
+    """Whole-grid domains on grids as wide as the row codes' 16-bit offsets
+    allow (the five-point stencil's rows below and above 32767 rows away at
+    nx = 32767; the nine-point stencil's reach nx + 1 = 32767 at nx = 32766)
+    and one wider (nx = 32767 on the nine-point stencil: 32-bit indices).
+    The two forms agree bit for bit, and both follow the oracle's
+    trajectory."""
     ny, dt = 5, 4.0
     if kind == W.KIND_5PT:
         coef = W.assemble_5pt(W.lognormal_logk((ny, nx), 1.0, 7), 1.0 / dt)
