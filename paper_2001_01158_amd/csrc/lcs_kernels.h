@@ -1408,6 +1408,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_sweep9(Op A, const double *__rest
         old_row(y0 - 3, om1);
 #pragma unroll
         for (int k = 0; k < V + 2; ++k) n2[k] = 0.0;
+        // the faces (N, NE, NW) of the even row of the previous step: the
+        // south faces of this step's odd row, kept in registers (a step
+        // later they are no longer in the cache); the even row's own south
+        // faces are the odd row's arrays of the same step
+        typename Op::South Sp{};
         for (int y = y0 - 2; y <= ylast; y += 2) {
             const bool real_e = y >= 0 && y < ny, real_o = y - 1 >= 0 && y - 1 < ny;
             double o0[V + 2], op1[V + 2];
@@ -1418,11 +1423,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_sweep9(Op A, const double *__rest
             Ue.x0 = x0;
             Ue.y = y;
             double be[V] = {0.0, 0.0}, f0[V + 2];
+            typename Op::South Se{};
             if (real_e) {
-                typename Op::South S;
                 A.geom_walk(Ue, (int64_t)y * upr + xu, xu, y);
-                A.south_init(S, Ue);
-                A.load_row(Ue, S);
+                A.south_init(Se, Ue);
+                A.load_row(Ue, Se);
                 vld<double, V>(b + Ue.i0, be);
                 update(Ue, be, om1, o0, op1, f0);
             } else {
@@ -1438,9 +1443,10 @@ __global__ __launch_bounds__(kBlock) void k_gs_sweep9(Op A, const double *__rest
                 double bo[V] = {0.0, 0.0}, f1[V + 2];
                 double nw_x0 = 0.0, ne_x2 = 0.0;   // row y-2's NW at x0, NE at x0 + 2
                 if (real_o) {
-                    typename Op::South S;
+                    // row y-2 (even, >= 0 as y-1 is an odd row) was the
+                    // previous step's even row
+                    typename Op::South S = Sp;
                     A.geom_walk(Uo, (int64_t)(y - 1) * upr + xu, xu, y - 1);
-                    A.south_init(S, Uo);
                     nw_x0 = S.nw[0];
                     ne_x2 = S.ne[2];
                     A.load_row(Uo, S);
@@ -1511,6 +1517,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_sweep9(Op A, const double *__rest
                 om1[k] = op1[k];
                 n2[k] = f0[k];
             }
+            Sp = Se;
         }
     }
     if (kRes) write_partials<double, 2>(v, Ops<2u>(), part);
