@@ -38,12 +38,18 @@ HBM_PEAK_GBS = 8000.0
 # Valid only while the kernel sources hash to src_sha256; otherwise the
 # roofline reports traffic null.
 MEASURED_TRAFFIC = {
-    "k_cg_iter<UEll<double,5>,1>": {
-        "ratio": 1.142, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
-        "src_sha256": "c9d8c854e7bdcbd20397fde8f361aa5f6f5c88a1df77dab53006d667df51b507"},
-    "k_cg_iter<UEll<float,9>,1>": {
-        "ratio": 1.000, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "9ff9b4f8e87ea80dc67bf7bf30c9e41ac4091cb5fd31818b1c428e3bcbf570b3"},
+    "k_cg_iter<UEllShort<double,5>,1>": {
+        "ratio": 1.066, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
+        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
+    "k_cg_iter<UEllShort<float,9>,1>": {
+        "ratio": 0.981, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
+    "k_gs_sweep9<U9<double,2,2>,true>": {
+        "ratio": 1.081, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
+    "k_score<U9<double,2,2>,0>": {
+        "ratio": 1.025, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
 }
 KERNEL_SOURCES = ["paper_2001_01158_amd/csrc/lcs_device.h", "paper_2001_01158_amd/csrc/lcs_kernels.h"]
 
