@@ -1,18 +1,20 @@
 """Benchmark: ms per linear system to relative residual 1e-10, local vs global PCG,
 plus SpMV HBM GB/s, on one MI355X.
 
-Default workload (c2): the 2-D 1024x1024 five-point FP64 sequence of 20
-backward-Euler systems with log-normal conductivity (sigma = 1) and a
-radius-40 disk source moving 4 cells per system.  Setup (untimed) evolves the
-sequence on the GPU, so every system's x^(0) = x_{k-1} and b_k are resident
-in HBM before the timed region.  One step = one system solved by Algorithm 1
-(local domain by residual, Algorithm 3, paper threshold eps ||b|| / sqrt(N),
-E_max = 1), cycling through the systems.  The global Jacobi-PCG from the same
-x^(0) is timed the same way as the baseline, the gradient-based domain
-(Algorithm 2) and the max-norm-relative residual threshold as variants.
+Default workload (c3): the 2-D 4096x4096 nine-point anisotropic sequence of
+20 backward-Euler systems (ratio 100 rotated 30 degrees, a radius-350 disk
+source moving 8 cells per system), FP32 inner Jacobi-PCG with FP64
+refinement.  Setup (untimed) evolves the sequence on the GPU, so every
+system's x^(0) = x_{k-1} and b_k are resident in HBM before the timed
+region.  One step = one system solved by Algorithm 1 (local domain by
+residual, Algorithm 3, tau = 0.1 eps ||b|| / sqrt(N), E_max = 1), cycling
+through the systems.  The global Jacobi-PCG from the same x^(0) is timed the
+same way as the baseline; the paper's tau, the gradient-based domain
+(Algorithm 2), the max-norm-relative threshold and FP64 inner solves as
+variants.  The 1024^2 five-point FP64 sequence is timed beside it.
 
---workload c3 / c5 run the 4096^2 nine-point (FP32 inner + FP64 refinement)
-and 256^3 seven-point (mixed, red-black SGS) sequences the same way.
+--workload c2 / c5 run the 1024^2 five-point (FP64) and the 256^3
+seven-point (mixed, red-black SGS) sequences the same way.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
 """
