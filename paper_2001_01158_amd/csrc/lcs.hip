@@ -1477,6 +1477,14 @@ template <>
 struct short_cols_ok<Stencil5<double>> : std::true_type {};
 template <>
 struct short_cols_ok<Stencil9<double>> : std::true_type {};
+// ... and whose red-black colour-blocked restricted systems may take the
+// red-black row codes (UEllRB): the five- and seven-point stencils
+template <class SOp>
+struct rb_code_ok : std::false_type {};
+template <>
+struct rb_code_ok<Stencil5<double>> : std::true_type {};
+template <>
+struct rb_code_ok<Stencil7<double>> : std::true_type {};
 
 // Leaves s (r^(0) or g) in B_SCORE, stamps in B_STAMP, inv in B_INV and the
 // ascending domain in idx; returns K (host).  eps0 >= 0: ||b|| (from the
@@ -1549,19 +1557,37 @@ struct Restricted {
     double *rhs;
     bool row_coded;   // B64 / B32 in UEllShort's form (code), their col unset
     RowCode code;
+    bool rb_coded;    // B64 / B32 in UEllRB's form (rbcode), their col unset
+    RBCode rbcode;
 };
 template <int W>
 UEllShort<double, W> short64(const Restricted<W> &R) { return {R.B64, R.code}; }
 template <int W>
 UEllShort<float, W> short32(const Restricted<W> &R) { return {R.B32, R.code}; }
+template <int W>
+UEllRB<double, W> rb64(const Restricted<W> &R) { return {R.B64, R.rbcode}; }
+template <int W>
+UEllRB<float, W> rb32(const Restricted<W> &R) { return {R.B32, R.rbcode}; }
+
+// UEllRB's code arrays in the column buffer of a K-row system (13 K bytes
+// of its 4 W K): the distance words, then q, then the presence bits.
+RBCode rb_code_in(int32_t *col, int64_t K) {
+    uint64_t *d = reinterpret_cast<uint64_t *>(col);
+    int32_t *q = reinterpret_cast<int32_t *>(d + K);
+    return RBCode{d, q, reinterpret_cast<uint8_t *>(q + K)};
+}
 
 // B = A[idx, idx] in ELL (one pass, no scan); rhs = r[idx] when r is given.
 // short_cols: in UEllShort's form (the caller checks that the domain is in
 // grid order on a five- or nine-point stencil whose reach fits), its row
-// codes in the column buffer.
+// codes in the column buffer.  rb_code: in UEllRB's form (the caller checks
+// that idx is the red-black blocked order on a five- or seven-point stencil
+// whose reach fits, and k_cblk_place left each row's q at the start of the
+// column buffer).
 template <int W, class SOp>
 lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const int32_t *inv,
-                  const double *r, bool with32, bool short_cols, Restricted<W> *R, hipStream_t s) {
+                  const double *r, bool with32, bool short_cols, Restricted<W> *R, hipStream_t s,
+                  bool rb_code = false) {
     int32_t *col;
     double *val, *dg, *rhs;
     float *val32 = nullptr, *dg32 = nullptr;
@@ -1577,6 +1603,26 @@ lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const
     }
     R->row_coded = false;
     R->code = RowCode{nullptr, nullptr, nullptr};
+    R->rb_coded = false;
+    R->rbcode = RBCode{nullptr, nullptr, nullptr};
+    if constexpr (rb_code_ok<SOp>::value) {
+        if (rb_code) {
+            static_assert(SOp::kSlots == W, "row codes take the stencil's slots");
+            const RBCode rc = rb_code_in(col, K);
+            hipLaunchKernelGGL((k_gather_rbcode<SOp>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A,
+                               idx, K, inv, rc.q, const_cast<uint64_t *>(rc.d),
+                               const_cast<uint8_t *>(rc.mask), val, val32, dg, dg32, clr, r,
+                               r ? rhs : nullptr);
+            LAUNCH_CHECK();
+            R->B64 = {nullptr, val, dg, clr, K};
+            R->B32 = {nullptr, val32, dg32, clr, K};
+            R->rhs = rhs;
+            R->rb_coded = true;
+            R->rbcode = rc;
+            return LCS_OK;
+        }
+    }
+    if (rb_code) return fail(LCS_EINVAL, "red-black row codes on this operator");
     if constexpr (short_cols_ok<SOp>::value) {
         if (short_cols) {
             static_assert(SOp::kSlots == W, "row codes take the stencil's slots");
@@ -1797,6 +1843,7 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
         // grid order): every row's arithmetic is unchanged, and a half sweep
         // reads its own colour's rows only.
         const int32_t *dom = idx;
+        bool rb_code = false;
         struct ClearBlocks {
             lcs_ctx *c;
             ~ClearBlocks() { c->cblk.n = 0; }
@@ -1806,12 +1853,23 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
             int32_t *idxb, *cnt;
             LCS_TRY(get_buf(c, B_IDXB, K, &idxb));
             LCS_TRY(get_buf(c, B_CBLK, (size_t)kMaxBlkColours * kMaxGrid, &cnt));
+            // red-black rows coded per row: each row's q straight into the
+            // code's place in the column buffer
+            int32_t *qv = nullptr;
+            rb_code = rb_code_ok<SOp>::value && c->short_cols && ncol == 2 &&
+                      stencil_reach(M) <= kMaxRB16;
+            if (rb_code) {
+                int32_t *colbuf;
+                LCS_TRY(get_buf(c, B_COL, (size_t)K * W, &colbuf));
+                qv = const_cast<int32_t *>(rb_code_in(colbuf, K).q);
+            }
             const int g = (int)std::min<int64_t>(kMaxGrid, std::max<int64_t>(1, (K + 2047) / 2048));
             const int64_t chunk = (K + g - 1) / g;
             hipLaunchKernelGGL((k_cblk_count<SOp>), dim3(g), dim3(kBlock), 0, s, As, idx, K, chunk,
                                ncol, cnt);
             hipLaunchKernelGGL((k_cblk_place<SOp>), dim3(g), dim3(kBlock), 0, s, As, idx, K, chunk,
-                               ncol, (const int32_t *)cnt, idxb, const_cast<int32_t *>(inv), c->dsc);
+                               ncol, (const int32_t *)cnt, idxb, const_cast<int32_t *>(inv), c->dsc,
+                               qv);
             LAUNCH_CHECK();
             LCS_TRY(read_scalars(c, s));
             if (c->hsc->cstart[ncol] != K) return fail(LCS_EHIP, "colour blocks do not cover the domain");
@@ -1826,23 +1884,30 @@ lcs_status local_phase(lcs_ctx *c, const lcs_matrix *M, const SOp &As, const UOp
                                 stencil_reach(M) <= kMaxCol16;
         Restricted<W> R;
         LCS_TRY(gather<W>(c, As, dom, K, inv, r0, o->precision == LCS_PREC_MIXED, short_cols, &R,
-                          s));
+                          s, rb_code));
         double *d;
         LCS_TRY(get_buf(c, B_DL, K, &d));
         const double tl = o->tol_local > 0 ? o->tol_local : o->eps;
         SolveOut so;
-        lcs_status ls;
+        lcs_status ls = LCS_OK;
+        bool solved = false;
         if constexpr (short_cols_ok<SOp>::value) {
-            if (R.row_coded)
+            if (R.row_coded) {
                 ls = solve_system(c, short64(R), short32(R), ncol, (const double *)R.rhs, d,
                                   true, &c->dsc->bnorm, tl, o, s, &so, 1, uses_gmres(M));
-            else
-                ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
+                solved = true;
+            }
+        }
+        if constexpr (rb_code_ok<SOp>::value) {
+            if (!solved && R.rb_coded) {
+                ls = solve_system(c, rb64(R), rb32(R), ncol, (const double *)R.rhs, d, true,
                                   &c->dsc->bnorm, tl, o, s, &so, 1, uses_gmres(M));
-        } else {
+                solved = true;
+            }
+        }
+        if (!solved)
             ls = solve_system(c, R.B64, R.B32, ncol, (const double *)R.rhs, d, true,
                               &c->dsc->bnorm, tl, o, s, &so, 1, uses_gmres(M));
-        }
         // a local solve that stops at its iteration cap still improves x;
         // the global finish takes over from there
         if (ls != LCS_OK && ls != LCS_ENOCONV) return ls;

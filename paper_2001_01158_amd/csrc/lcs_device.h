@@ -148,6 +148,24 @@ struct Stencil7 {
         if (y < ny - 1) f(i + nx, N[i]);
         if (z < nz - 1) f(i + pl, U[i]);
     }
+    // the same members with their stencil slots: D, S, W, C, E, N, U
+    // (ascending)
+    static constexpr int kSlots = 7;
+    template <class F>
+    __device__ __forceinline__ void for_each_slot(int64_t i, F &&f) const {
+        const int64_t pl = (int64_t)nx * ny;
+        const int z = (int)((uint64_t)i / (uint64_t)pl);
+        const int r = (int)(i - (int64_t)z * pl);
+        const int y = (int)((uint32_t)r / (uint32_t)nx);
+        const int x = r - y * nx;
+        if (z > 0) f(0, i - pl, U[i - pl]);
+        if (y > 0) f(1, i - nx, N[i - nx]);
+        if (x > 0) f(2, i - 1, E[i - 1]);
+        f(3, i, C[i]);
+        if (x < nx - 1) f(4, i + 1, E[i]);
+        if (y < ny - 1) f(5, i + nx, N[i]);
+        if (z < nz - 1) f(6, i + pl, U[i]);
+    }
     __device__ __forceinline__ real diag(int64_t i) const { return C[i]; }
     __device__ __forceinline__ int colour(int64_t i) const {
         const int64_t pl = (int64_t)nx * ny;
@@ -1135,6 +1153,65 @@ struct UEllShort : UEll<real_, NB_> {
 };
 template <typename real, int NB>
 constexpr bool is_ell<UEllShort<real, NB>> = true;
+
+// B of a red-black colour-blocked domain (two colours, rows colour by
+// colour, each colour in grid order) on the five- or seven-point stencil,
+// coded per row: the values in the stencil's fixed slots (S, W, C, E, N or
+// D, S, W, C, E, N, U, ascending grid order as in the blocked UEll rows),
+// and, since every neighbour has the other colour, the row's q (the
+// position the other colour's block gives a cell at the row's own grid
+// index: the number of its members before it, plus the block's start) and
+// unsigned 16-bit distances (one 64-bit word) to the members straight below
+// and above:
+// W = q - 1, E = q, S = q - ds, N = q + dn, D = q - dd, U = q + du.  9 or 13
+// bytes per row instead of 4 per member; the same members, order and
+// arithmetic as UEll.  The distances count members of the other colour in
+// half a row or half a plane, at most 65535 while that reach is at most
+// kMaxRB16 cells.
+constexpr int64_t kMaxRB16 = 131068;
+
+struct RBCode {
+    const uint64_t *d;     // ds | dn << 16 | dd << 32 | du << 48 (dd, du: seven-point only)
+    const int32_t *q;
+    const uint8_t *mask;   // bit b: slot b (b < centre) or b + 1 present
+};
+
+template <typename real_, int NB_>
+struct UEllRB : UEll<real_, NB_> {
+    static_assert(NB_ == 5 || NB_ == 7, "red-black row codes of the five- and seven-point stencils");
+    using Base = UEll<real_, NB_>;
+    using Unit = typename Base::Unit;
+    static constexpr int kMid = NB_ / 2;
+    RBCode code;
+    __device__ __forceinline__ void load(Unit &U, int64_t u) const {
+        U.i0 = u;
+        const uint64_t w = code.d[u];
+        const int q = code.q[u];
+        const unsigned m = code.mask[u];
+        const int ds = (int)(w & 0xffffu), dn = (int)((w >> 16) & 0xffffu);
+        auto has = [&](int sl) -> bool { return (m >> (sl < kMid ? sl : sl - 1)) & 1u; };
+        if constexpr (NB_ == 7) {
+            const int dd = (int)((w >> 32) & 0xffffu), du = (int)(w >> 48);
+            U.c[0] = has(0) ? q - dd : -1;
+            U.c[1] = has(1) ? q - ds : -1;
+            U.c[2] = has(2) ? q - 1 : -1;
+            U.c[3] = (int)u;
+            U.c[4] = has(4) ? q : -1;
+            U.c[5] = has(5) ? q + dn : -1;
+            U.c[6] = has(6) ? q + du : -1;
+        } else {
+            U.c[0] = has(0) ? q - ds : -1;
+            U.c[1] = has(1) ? q - 1 : -1;
+            U.c[2] = (int)u;
+            U.c[3] = has(3) ? q : -1;
+            U.c[4] = has(4) ? q + dn : -1;
+        }
+#pragma unroll
+        for (int sl = 0; sl < NB_; ++sl) U.a[sl][0] = this->val[sl * this->n + u];
+    }
+};
+template <typename real, int NB>
+constexpr bool is_ell<UEllRB<real, NB>> = true;
 
 
 // ---------------------------------------------------------------------------

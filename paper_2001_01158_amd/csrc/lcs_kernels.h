@@ -566,12 +566,15 @@ __global__ __launch_bounds__(kBlock) void k_cblk_count(SOp A, const int32_t *__r
     }
 }
 
+// qv (optional, two colours): at each row's position, the position the
+// other colour's block gives a cell at the row's grid index (UEllRB's q).
 template <class SOp>
 __global__ __launch_bounds__(kBlock) void k_cblk_place(SOp A, const int32_t *__restrict__ idx,
                                                        int64_t K, int64_t chunk, int ncol,
                                                        const int32_t *__restrict__ cnt,
                                                        int32_t *__restrict__ idxb,
-                                                       int32_t *__restrict__ inv, Scalars *sc) {
+                                                       int32_t *__restrict__ inv, Scalars *sc,
+                                                       int32_t *__restrict__ qv) {
     int64_t base[kMaxBlkColours];
     int64_t lower = 0;   // cells of the colours below q
 #pragma unroll
@@ -593,6 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_cblk_place(SOp A, const int32_t *__r
         const int64_t k = t0 + threadIdx.x;
         const int32_t i = k < k1 ? idx[k] : 0;
         const int col = k < k1 ? A.colour(i) : -1;
+        int64_t own = 0, other = 0;
 #pragma unroll
         for (int q = 0; q < kMaxBlkColours; ++q) {
             if (q < ncol) {
@@ -602,10 +606,14 @@ __global__ __launch_bounds__(kBlock) void k_cblk_place(SOp A, const int32_t *__r
                     const int64_t pos = base[q] + pre;
                     idxb[pos] = i;
                     inv[i] = (int32_t)pos;
+                    own = pos;
+                } else {
+                    other = base[q] + pre;
                 }
                 base[q] += tot;
             }
         }
+        if (qv && col >= 0) qv[own] = (int32_t)other;
     }
 }
 
@@ -696,6 +704,63 @@ __global__ __launch_bounds__(kBlock) void k_gather_rowcode(
         }
         soff[k] = (int16_t)(ps - k);
         noff[k] = (int16_t)(pn - k);
+        mask[k] = (uint8_t)m;
+        const double d = A.diag(i);
+        dg[k] = d;
+        if (dg32) dg32[k] = (float)d;
+        clr[k] = (uint8_t)A.colour(i);
+        if (rhs) rhs[k] = r[i];
+    }
+}
+
+// The red-black colour-blocked B in UEllRB's form: rows in the blocked
+// order idx (k_cblk_place's, which left each row's q in code.q), values in
+// the stencil's fixed slots, presence bits and the distances from q to the
+// members below and above.
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_gather_rbcode(
+    Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv,
+    const int32_t *__restrict__ qv, uint64_t *__restrict__ dw, uint8_t *__restrict__ mask,
+    double *__restrict__ val, float *__restrict__ val32, double *__restrict__ dg,
+    float *__restrict__ dg32, uint8_t *__restrict__ clr, const double *__restrict__ r,
+    double *__restrict__ rhs) {
+    constexpr int NB = Op::kSlots, kMid = NB / 2;
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = idx[k];
+        const int64_t q = qv[k];
+        int32_t cs[NB];
+        double a[NB];
+#pragma unroll
+        for (int sl = 0; sl < NB; ++sl) {
+            cs[sl] = -1;
+            a[sl] = 0.0;
+        }
+        A.for_each_slot(i, [&](int sl, int64_t j, double v) {
+            const int32_t cj = inv[j];
+            if (cj >= 0) {
+                cs[sl] = cj;
+                a[sl] = v;
+            }
+        });
+        unsigned m = 0;
+#pragma unroll
+        for (int sl = 0; sl < NB; ++sl) {
+            if (sl != kMid && cs[sl] >= 0) m |= 1u << (sl < kMid ? sl : sl - 1);
+            val[sl * K + k] = a[sl];
+            if (val32) val32[sl * K + k] = (float)a[sl];
+        }
+        uint64_t ds = 0, dn = 0, dd = 0, du = 0;
+        if constexpr (NB == 7) {
+            dd = (uint64_t)(cs[0] >= 0 ? q - cs[0] : 0);
+            ds = (uint64_t)(cs[1] >= 0 ? q - cs[1] : 0);
+            dn = (uint64_t)(cs[5] >= 0 ? cs[5] - q : 0);
+            du = (uint64_t)(cs[6] >= 0 ? cs[6] - q : 0);
+        } else {
+            ds = (uint64_t)(cs[0] >= 0 ? q - cs[0] : 0);
+            dn = (uint64_t)(cs[4] >= 0 ? cs[4] - q : 0);
+        }
+        dw[k] = ds | dn << 16 | dd << 32 | du << 48;
         mask[k] = (uint8_t)m;
         const double d = A.diag(i);
         dg[k] = d;

@@ -491,6 +491,72 @@ def test_short_column_form(name, prec, pc):
     assert np.array_equal(xs[0], xs[1])
 
 
+@pytest.mark.parametrize("name", ["5pt", "5pt_v", "7pt", "7pt_v"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_red_black_row_codes(name, prec):
+    """RB-SGS with the restricted rows blocked by colour: on the five- and
+    seven-point stencils each row's columns are coded from its position in
+    the other colour's block (the default) or stored as 32-bit indices.  The
+    same members in the same order, so the local solve returns the same x
+    and iteration count bit for bit, and follows the oracle."""
+    kind, dims, coef, Ah, A, b, x0 = make_case(name)
+    d = oracle.build_local_domain(Ah, b, x0, oracle.MODE_RESIDUAL, 1e-3, oracle.TH_RELMAX, 1)
+    assert d.K > 100
+    xs, its = [], []
+    for on in (True, False):
+        say("red-black row codes", name, dims, prec, on)
+        c = lcs.Context()
+        lcs.set_short_columns(on, ctx=c)
+        x = dev(x0)
+        st = lcs.solve_local(A, dev(b), x, dev(d.idx, torch.int32),
+                             lcs.Options(eps=1e-10, precision=prec, precond="rbsgs"), ctx=c)
+        xs.append(host(x))
+        its.append(st.its_local)
+    assert its[0] == its[1] > 0
+    assert np.array_equal(xs[0], xs[1])
+    xo, _ = oracle.solve_local(Ah, b, x0, d.idx, oracle.Options(eps=1e-10, pc=oracle.PC_SGS))
+    rel = np.linalg.norm(xs[0] - xo) / np.linalg.norm(xo)
+    assert rel <= 1e-9, rel
+
+
+@pytest.mark.parametrize("kind,dims", [(W.KIND_5PT, (131068, 3, 1)), (W.KIND_7PT, (362, 362, 3)),
+                                       (W.KIND_7PT, (363, 362, 3))])
+def test_red_black_row_codes_at_the_limit(kind, dims):
+    """Whole-grid domains under RB-SGS on grids as wide as the red-black
+    codes' 16-bit distances allow (half a row of 131068 cells; half a plane
+    of 362 x 362) and one wider plane (363 x 362: 32-bit indices).  The two
+    forms agree bit for bit, and both follow the oracle's trajectory."""
+    nx, ny, nz = dims
+    dt = 4.0
+    if kind == W.KIND_5PT:
+        coef = W.assemble_5pt(W.lognormal_logk((ny, nx), 1.0, 11), 1.0 / dt)
+    else:
+        coef = W.assemble_7pt(W.lognormal_logk((nz, ny, nx), 1.0, 11), 1.0 / dt)
+    n = nx * ny * nz
+    rng = np.random.default_rng(13)
+    Ah = oracle.csr_from_stencil(kind, nx, ny, nz, coef)
+    b = oracle.spmv(Ah, rng.random(n))
+    x0 = np.zeros(n)
+    idx = np.arange(n, dtype=np.int32)
+    xo, so = oracle.solve_local(Ah, b, x0, idx,
+                                oracle.Options(eps=1e-10, max_iter=6, n_smooth=1, pc=oracle.PC_SGS))
+    A = lcs.matrix_from_numpy(kind, nx, ny, nz, coef, DEV)
+    xs = []
+    for on in (True, False):
+        say("red-black row codes at the limit", kind, dims, on)
+        c = lcs.Context()
+        lcs.set_short_columns(on, ctx=c)
+        x = dev(x0)
+        st = lcs.solve_local(A, dev(b), x, dev(idx, torch.int32),
+                             lcs.Options(eps=1e-10, max_iter=6, n_smooth=1, check_every=1,
+                                         precond="rbsgs"), ctx=c)
+        assert st.its_local == so.its_local == 6
+        xs.append(host(x))
+        rel = np.linalg.norm(xs[-1] - xo) / np.linalg.norm(xo)
+        assert rel <= 1e-12, (on, rel)
+    assert np.array_equal(xs[0], xs[1])
+
+
 @pytest.mark.parametrize("kind,nx", [(W.KIND_5PT, 32767), (W.KIND_9PT, 32766),
                                      (W.KIND_9PT, 32767)])
 def test_short_columns_at_the_offset_limit(kind, nx):
