@@ -1602,7 +1602,7 @@ lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const
         LCS_TRY(get_buf(c, B_DG32, K, &dg32));
     }
     R->row_coded = false;
-    R->code = RowCode{nullptr, nullptr, nullptr};
+    R->code = RowCode{nullptr, nullptr};
     R->rb_coded = false;
     R->rbcode = RBCode{nullptr, nullptr, nullptr};
     if constexpr (rb_code_ok<SOp>::value) {
@@ -1627,17 +1627,17 @@ lcs_status gather(lcs_ctx *c, const SOp &A, const int32_t *idx, int64_t K, const
         if (short_cols) {
             static_assert(SOp::kSlots == W, "row codes take the stencil's slots");
             // 5 bytes per row of the column buffer's 4 W
-            int16_t *so = reinterpret_cast<int16_t *>(col), *no = so + K;
-            uint8_t *mk = reinterpret_cast<uint8_t *>(no + K);
+            uint32_t *of = reinterpret_cast<uint32_t *>(col);
+            uint8_t *mk = reinterpret_cast<uint8_t *>(of + K);
             hipLaunchKernelGGL((k_gather_rowcode<SOp>), dim3(flat_grid(K)), dim3(kBlock), 0, s, A,
-                               idx, K, inv, so, no, mk, val, val32, dg, dg32, clr, r,
+                               idx, K, inv, of, mk, val, val32, dg, dg32, clr, r,
                                r ? rhs : nullptr);
             LAUNCH_CHECK();
             R->B64 = {nullptr, val, dg, clr, K};
             R->B32 = {nullptr, val32, dg32, clr, K};
             R->rhs = rhs;
             R->row_coded = true;
-            R->code = RowCode{so, no, mk};
+            R->code = RowCode{of, mk};
             return LCS_OK;
         }
     }

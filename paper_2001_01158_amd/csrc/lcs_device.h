@@ -1104,16 +1104,16 @@ struct UEll {
 // stencil's fixed slots (S, W, C, E, N or SW, S, SE, W, C, E, NW, N, NE:
 // ascending column order, zero where the neighbour is outside the grid or
 // the domain), and a member's column follows from the row's position k, a
-// presence bit and, for the rows below and above, soff / noff = p - k, p the
-// number of domain cells before the cell straight below (above) in grid
-// order: W = k - 1, E = k + 1, S = p, SW = p - 1, SE = p + [S present], and
+// presence bit and, for the rows below and above, soff / noff = p - k (two
+// 16-bit halves of one word), p the number of domain cells before the cell
+// straight below (above) in grid order: W = k - 1, E = k + 1, S = p, SW = p - 1, SE = p + [S present], and
 // the same above.  5 bytes per row instead of 4 per member, for domains
 // whose rows reach at most kMaxCol16 rows away; the same members, order and
 // arithmetic as UEll.
 constexpr int64_t kMaxCol16 = 32767;
 
 struct RowCode {
-    const int16_t *soff, *noff;
+    const uint32_t *off;   // (uint16) soff | (uint16) noff << 16
     const uint8_t *mask;   // bit b: slot b (b < centre) or b + 1 present
 };
 
@@ -1127,7 +1127,8 @@ struct UEllShort : UEll<real_, NB_> {
     __device__ __forceinline__ void load(Unit &U, int64_t u) const {
         U.i0 = u;
         const int k = (int)u;
-        const int so = k + code.soff[u], no = k + code.noff[u];
+        const uint32_t w = code.off[u];
+        const int so = k + (int)(int16_t)(w & 0xffffu), no = k + (int)(int16_t)(w >> 16);
         const unsigned m = code.mask[u];
         auto has = [&](int sl) -> int { return (int)((m >> (sl < kMid ? sl : sl - 1)) & 1u); };
         if constexpr (NB_ == 9) {

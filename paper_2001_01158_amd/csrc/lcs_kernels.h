@@ -665,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_ell(
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_gather_rowcode(
     Op A, const int32_t *__restrict__ idx, int64_t K, const int32_t *__restrict__ inv,
-    int16_t *__restrict__ soff, int16_t *__restrict__ noff, uint8_t *__restrict__ mask,
+    uint32_t *__restrict__ off, uint8_t *__restrict__ mask,
     double *__restrict__ val, float *__restrict__ val32, double *__restrict__ dg,
     float *__restrict__ dg32, uint8_t *__restrict__ clr, const double *__restrict__ r,
     double *__restrict__ rhs) {
@@ -702,8 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_rowcode(
             ps = cs[0] >= 0 ? cs[0] : k;
             pn = cs[4] >= 0 ? cs[4] : k;
         }
-        soff[k] = (int16_t)(ps - k);
-        noff[k] = (int16_t)(pn - k);
+        off[k] = (uint32_t)(uint16_t)(int16_t)(ps - k) | (uint32_t)(uint16_t)(int16_t)(pn - k) << 16;
         mask[k] = (uint8_t)m;
         const double d = A.diag(i);
         dg[k] = d;
