@@ -41,17 +41,17 @@ HBM_PEAK_GBS = 8000.0
 # roofline reports traffic null.
 MEASURED_TRAFFIC = {
     "k_cg_iter<UEllShort<double,5>,1>": {
-        "ratio": 1.066, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
-        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
+        "ratio": 1.065, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
+        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
     "k_cg_iter<UEllShort<float,9>,1>": {
-        "ratio": 0.981, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
+        "ratio": 0.980, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
     "k_gs_sweep9<U9<double,2,2>,true>": {
-        "ratio": 1.081, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
+        "ratio": 1.080, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
     "k_score<U9<double,2,2>,0>": {
-        "ratio": 1.025, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "944ee1d9e4a484dd49eb14fec0add9d8115750e104e47faa386cff6d292364f3"},
+        "ratio": 1.024, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
 }
 KERNEL_SOURCES = ["paper_2001_01158_amd/csrc/lcs_device.h", "paper_2001_01158_amd/csrc/lcs_kernels.h"]
 
