@@ -262,8 +262,9 @@ def summarize(d: str, steps: int, warmup: int, kernel: str, mark: str, end_mark:
             if os.path.exists(bj):
                 roof = json.load(open(bj))["roofline"]
                 cands = [roof] + roof.get("other_kernels", [])
-                for c in cands:
-                    if c["kernel"].replace(" ", "") == kernel.replace(" ", "") and c.get("working_launches"):
+                for c in cands:   # a workload without event-timed candidates has only a note
+                    if (c.get("kernel", "").replace(" ", "") == kernel.replace(" ", "")
+                            and c.get("working_launches")):
                         per_work = c["bytes_per_launch"] * c["launches"] / c["working_launches"]
                         out.append(f"algorithmic bytes per working dispatch in that run: "
                                    f"{per_work / 1e6:.3f} MB -> traffic / algorithmic = "
