@@ -325,16 +325,21 @@ lcs_status lcs_set_tiling(lcs_ctx *ctx, int32_t march_rows, int32_t nontemporal)
 lcs_status lcs_set_colour_blocking(lcs_ctx *ctx, int32_t on);
 
 /* Index form of the restricted system B (Algorithm 1 step 4) built by the
- * local solves.  on != 0 (the default): on the five- and nine-point stencils
- * (LCS_STENCIL5_2D, LCS_STENCIL9_2D) with nx <= 32766, where B's rows keep
- * the domain's ascending grid order (always, except under RB-SGS with
- * colour blocking), B's values sit in the stencil's fixed slots and its
- * columns are coded per row (5 bytes: two 16-bit offsets to the rows below
- * and above and the slots' presence bits) instead of a 32-bit index per
- * member, so that every product with B reads fewer bytes; otherwise, and
- * with on = 0, as 32-bit indices.  B's members, their order and every
- * result are the same bit for bit either way.  Returns LCS_EINVAL for a
- * NULL context. */
+ * local solves.  on != 0 (the default): B's values sit in the stencil's
+ * fixed slots and its columns are coded per row instead of a 32-bit index
+ * per member, so that every product with B reads fewer bytes:
+ *   - on the five- and nine-point stencils (LCS_STENCIL5_2D,
+ *     LCS_STENCIL9_2D) with nx <= 32766, where B's rows keep the domain's
+ *     ascending grid order: two 16-bit offsets to the rows below and above
+ *     and the slots' presence bits (5 bytes);
+ *   - under RB-SGS with the rows blocked by colour (lcs_set_colour_blocking)
+ *     on the five- and seven-point stencils (LCS_STENCIL7_3D), while half a
+ *     row (2-D) or half a plane (3-D) holds at most 65535 cells: the row's
+ *     position in the other colour's block, 16-bit distances to the members
+ *     below and above, and the presence bits (9 or 13 bytes).
+ * Otherwise, and with on = 0, as 32-bit indices.  B's members, their order
+ * and every result are the same bit for bit either way.  Returns LCS_EINVAL
+ * for a NULL context. */
 lcs_status lcs_set_short_columns(lcs_ctx *ctx, int32_t on);
 
 /* ---- batched solves: the G decoupled group systems of a source iteration ---- */

@@ -628,9 +628,10 @@ def set_colour_blocking(on: bool = True, ctx: Context = None):
 
 
 def set_short_columns(on: bool = True, ctx: Context = None):
-    """Index form of the restricted system: columns coded per row on the
-    five- and nine-point stencils where they fit (True, the default) or
-    32-bit indices (False); results are the same either way
+    """Index form of the restricted system: columns coded per row where
+    they fit (True, the default: the five- and nine-point stencils in grid
+    order, and the red-black colour-blocked five- and seven-point rows under
+    RB-SGS) or 32-bit indices (False); results are the same either way
     (lcs_set_short_columns)."""
     _check(lib().lcs_set_short_columns(_ctx(ctx), 1 if on else 0))
 
