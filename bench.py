@@ -42,16 +42,16 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "k_cg_iter<UEllShort<double,5>,1>": {
         "ratio": 1.065, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
-        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
+        "src_sha256": "96be5074a0897772803804c2bd6c825ddf7fca4fa4a8acecd9c508681846bb52"},
     "k_cg_iter<UEllShort<float,9>,1>": {
         "ratio": 0.980, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
+        "src_sha256": "96be5074a0897772803804c2bd6c825ddf7fca4fa4a8acecd9c508681846bb52"},
     "k_gs_sweep9<U9<double,2,2>,true>": {
         "ratio": 1.080, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
+        "src_sha256": "96be5074a0897772803804c2bd6c825ddf7fca4fa4a8acecd9c508681846bb52"},
     "k_score<U9<double,2,2>,0>": {
         "ratio": 1.024, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "5b673ffe1810842da8179642a06f17fe276d1fc867a411dbae28bdc4ed863f2a"},
+        "src_sha256": "96be5074a0897772803804c2bd6c825ddf7fca4fa4a8acecd9c508681846bb52"},
 }
 KERNEL_SOURCES = ["paper_2001_01158_amd/csrc/lcs_device.h", "paper_2001_01158_amd/csrc/lcs_kernels.h"]
 

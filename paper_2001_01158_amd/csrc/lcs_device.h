@@ -1100,16 +1100,16 @@ struct UEll {
 };
 
 // B of a domain in grid order on the five- or nine-point stencil, with its
-// columns coded per row instead of per member: the values sit in the
+// columns coded per row instead of per member.  The values sit in the
 // stencil's fixed slots (S, W, C, E, N or SW, S, SE, W, C, E, NW, N, NE:
 // ascending column order, zero where the neighbour is outside the grid or
-// the domain), and a member's column follows from the row's position k, a
+// the domain).  A member's column follows from the row's position k, a
 // presence bit and, for the rows below and above, soff / noff = p - k (two
-// 16-bit halves of one word), p the number of domain cells before the cell
-// straight below (above) in grid order: W = k - 1, E = k + 1, S = p, SW = p - 1, SE = p + [S present], and
-// the same above.  5 bytes per row instead of 4 per member, for domains
-// whose rows reach at most kMaxCol16 rows away; the same members, order and
-// arithmetic as UEll.
+// 16-bit halves of one word), p being the number of domain cells before the
+// cell straight below (above) in grid order: W = k - 1, E = k + 1, S = p,
+// SW = p - 1, SE = p + [S present], and the same above.  5 bytes per row
+// instead of 4 per member, for domains whose rows reach at most kMaxCol16
+// rows away; the same members, order and arithmetic as UEll.
 constexpr int64_t kMaxCol16 = 32767;
 
 struct RowCode {
@@ -1157,17 +1157,16 @@ constexpr bool is_ell<UEllShort<real, NB>> = true;
 
 // B of a red-black colour-blocked domain (two colours, rows colour by
 // colour, each colour in grid order) on the five- or seven-point stencil,
-// coded per row: the values in the stencil's fixed slots (S, W, C, E, N or
-// D, S, W, C, E, N, U, ascending grid order as in the blocked UEll rows),
-// and, since every neighbour has the other colour, the row's q (the
-// position the other colour's block gives a cell at the row's own grid
-// index: the number of its members before it, plus the block's start) and
-// unsigned 16-bit distances (one 64-bit word) to the members straight below
-// and above:
+// coded per row.  The values sit in the stencil's fixed slots (S, W, C, E, N
+// or D, S, W, C, E, N, U: grid order, as in the blocked UEll rows).  Every
+// neighbour has the other colour, so a row keeps q, the position the other
+// colour's block gives a cell at the row's own grid index (the number of
+// its members before it, plus the block's start), and unsigned 16-bit
+// distances (one 64-bit word) to the members straight below and above:
 // W = q - 1, E = q, S = q - ds, N = q + dn, D = q - dd, U = q + du.  9 or 13
 // bytes per row instead of 4 per member; the same members, order and
-// arithmetic as UEll.  The distances count members of the other colour in
-// half a row or half a plane, at most 65535 while that reach is at most
+// arithmetic as UEll.  A distance counts members of the other colour in
+// half a row or half a plane: at most 65535 while that reach is at most
 // kMaxRB16 cells.
 constexpr int64_t kMaxRB16 = 131068;
 
