@@ -1110,6 +1110,13 @@ struct UEll {
 // SW = p - 1, SE = p + [S present], and the same above.  5 bytes per row
 // instead of 4 per member, for domains whose rows reach at most kMaxCol16
 // rows away; the same members, order and arithmetic as UEll.
+//
+// Only the upper half of the slots is stored (C, E, N or C, E, NW, N, NE:
+// slot s at val[(s - centre) * K + k]).  The stencils are stored as half
+// stencils, so B is symmetric to the bit, and the coupling with a member j
+// below or to the left is j's own entry in the mirrored slot (NB - 1 - s).
+// Each row still loads NB values, but the lower ones come from rows that
+// neighbouring lanes and waves load too.
 constexpr int64_t kMaxCol16 = 32767;
 
 struct RowCode {
@@ -1149,7 +1156,16 @@ struct UEllShort : UEll<real_, NB_> {
             U.c[4] = has(4) ? no : -1;
         }
 #pragma unroll
-        for (int sl = 0; sl < NB_; ++sl) U.a[sl][0] = this->val[sl * this->n + u];
+        for (int sl = kMid; sl < NB_; ++sl) U.a[sl][0] = this->val[(sl - kMid) * this->n + u];
+        // the lower slots from the members' mirrored entries; an absent
+        // member (c = -1) reads the last entry of the slot before, in bounds,
+        // and is masked
+#pragma unroll
+        for (int sl = 0; sl < kMid; ++sl) {
+            const int j = U.c[sl];
+            const real_ t = this->val[(NB_ - 1 - sl - kMid) * this->n + j];
+            U.a[sl][0] = j >= 0 ? t : real_(0);
+        }
     }
 };
 template <typename real, int NB>

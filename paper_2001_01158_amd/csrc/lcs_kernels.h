@@ -657,8 +657,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_ell(
 }
 
 // The same B in UEllShort's form (a domain in grid order on the five- or
-// nine-point stencil): the values in the stencil's fixed slots (zero where
-// the neighbour is not a member), each row's presence bits and the offsets
+// nine-point stencil): the values of the upper slots (C and above, zero
+// where the neighbour is not a member), each row's presence bits and the offsets
 // soff / noff of the number of members before the cell straight below /
 // above (found from whichever of the cells below / above are members; zero
 // when none is).
@@ -691,8 +691,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_rowcode(
 #pragma unroll
         for (int sl = 0; sl < NB; ++sl) {
             if (sl != kMid && cs[sl] >= 0) m |= 1u << (sl < kMid ? sl : sl - 1);
-            val[sl * K + k] = a[sl];
-            if (val32) val32[sl * K + k] = (float)a[sl];
+            if (sl >= kMid) {
+                val[(sl - kMid) * K + k] = a[sl];
+                if (val32) val32[(sl - kMid) * K + k] = (float)a[sl];
+            }
         }
         int64_t ps = k, pn = k;
         if constexpr (NB == 9) {
