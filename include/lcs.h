@@ -331,7 +331,9 @@ lcs_status lcs_set_colour_blocking(lcs_ctx *ctx, int32_t on);
  *   - on the five- and nine-point stencils (LCS_STENCIL5_2D,
  *     LCS_STENCIL9_2D) with nx <= 32766, where B's rows keep the domain's
  *     ascending grid order: two 16-bit offsets to the rows below and above
- *     and the slots' presence bits (5 bytes);
+ *     and the slots' presence bits (5 bytes), with only the upper slots'
+ *     values stored (the lower couplings are read from the neighbours'
+ *     mirrored slots, B being symmetric);
  *   - under RB-SGS with the rows blocked by colour (lcs_set_colour_blocking)
  *     on the five- and seven-point stencils (LCS_STENCIL7_3D), while half a
  *     row (2-D) or half a plane (3-D) holds at most 65535 cells: the row's
