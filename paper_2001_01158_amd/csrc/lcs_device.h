@@ -201,6 +201,23 @@ struct Stencil9N {
         if (nn) f(i + nx, a[7 * n + i]);
         if (nn && e) f(i + nx + 1, a[8 * n + i]);
     }
+    // the same members with their slots: SW, S, SE, W, C, E, NW, N, NE
+    static constexpr int kSlots = 9;
+    template <class F>
+    __device__ __forceinline__ void for_each_slot(int64_t i, F &&f) const {
+        const int y = (int)((uint32_t)i / (uint32_t)nx);
+        const int x = (int)i - y * nx;
+        const bool w = x > 0, e = x < nx - 1, s = y > 0, nn = y < ny - 1;
+        if (s && w) f(0, i - nx - 1, a[i]);
+        if (s) f(1, i - nx, a[n + i]);
+        if (s && e) f(2, i - nx + 1, a[2 * n + i]);
+        if (w) f(3, i - 1, a[3 * n + i]);
+        f(4, i, a[4 * n + i]);
+        if (e) f(5, i + 1, a[5 * n + i]);
+        if (nn && w) f(6, i + nx - 1, a[6 * n + i]);
+        if (nn) f(7, i + nx, a[7 * n + i]);
+        if (nn && e) f(8, i + nx + 1, a[8 * n + i]);
+    }
     __device__ __forceinline__ real diag(int64_t i) const { return a[4 * n + i]; }
     __device__ __forceinline__ int colour(int64_t i) const {
         const int y = (int)((uint32_t)i / (uint32_t)nx);

@@ -259,11 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_expand(Op A, const double *__restric
 
 // The same round on a structured grid whose rows are a multiple of 8 cells:
 // a thread takes eight cells at a time as one 64-bit word of stamps and
-// reads the neighbouring rows' words (and the bytes just left and right of
-// each), so that a cell with no neighbour in Omega costs a few byte tests
-// and no scattered load.  Cells that do touch Omega take k_expand's test
-// (same sum, same order), so the stamps are the same bit for bit.  kShape:
-// 5 (2-D cross), 9 (2-D 3 x 3) or 7 (3-D cross, plane = nx * ny).
+// reads the neighbouring rows' words, the bytes just left and right of its
+// own, and on nine points the corners beside the rows below and above.  A
+// word none of whose neighbours is stamped leaves at once; a cell with no
+// neighbour in Omega costs a few byte tests and no scattered load.  Cells
+// that do touch Omega take k_expand's test (same sum, same order), so the
+// stamps are the same bit for bit.  kShape: 5 (2-D cross), 9 (2-D 3 x 3)
+// or 7 (3-D cross, plane = nx * ny).
 template <class Op, int kShape>
 __global__ __launch_bounds__(kBlock) void k_expand_w(Op A, const double *__restrict__ r,
                                                      const double *__restrict__ x,
@@ -285,13 +287,18 @@ __global__ __launch_bounds__(kBlock) void k_expand_w(Op A, const double *__restr
     const double tau = sc->ms.tau;
     const uint64_t *w = reinterpret_cast<const uint64_t *>(stamp);
     auto in = [&](int b) { return b != 0 && b <= m; };
-    // a row's eight stamps with the bytes at x0 - 1 and x0 + 8 (0 outside)
-    auto row = [&](int64_t q, int64_t i0, int x0, int (&t)[10]) {
-        const uint64_t v = w[q];
+    // grid positions by 32-bit division while the grid has < 2^32 cells
+    const bool small = n <= (int64_t)0xffffffffu;
+    auto div = [&](int64_t a, int64_t d) -> int64_t {
+        return small ? (int64_t)((uint32_t)a / (uint32_t)d) : a / d;
+    };
+    // a row's eight stamps from its word, with the bytes e0 (x0 - 1) and e1
+    // (x0 + 8) beside them
+    auto unpack = [&](uint64_t v, int e0, int e1, int (&t)[10]) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) t[k + 1] = (int)((v >> (8 * k)) & 0xff);
-        t[0] = x0 > 0 ? stamp[i0 - 1] : 0;
-        t[9] = x0 + 8 < nx ? stamp[i0 + 8] : 0;
+        t[0] = e0;
+        t[9] = e1;
     };
     double v[1] = {0.0};
     for (int64_t q = c.begin + threadIdx.x; q < c.end; q += kBlock) {
@@ -301,14 +308,12 @@ __global__ __launch_bounds__(kBlock) void k_expand_w(Op A, const double *__restr
         const uint64_t t2 = t | (t >> 2);
         if ((((t2 | (t2 >> 1)) & 0x0101010101010101ull)) == 0x0101010101010101ull) continue;
         const int64_t i0 = q * 8;
-        const int64_t rowi = i0 / nx;
+        const int64_t rowi = div(i0, nx);
         const int x0 = (int)(i0 - rowi * nx);
-        int cc[10], sn[10], nn[10], dn[10], up[10];
-        row(q, i0, x0, cc);
         bool has_s, has_n, has_d = false, has_u = false;
         if (kShape == 7) {
-            const int64_t z = i0 / plane;
-            const int y = (int)((i0 - z * plane) / nx);
+            const int64_t z = div(i0, plane);
+            const int y = (int)div(i0 - z * plane, nx);
             has_s = y > 0;
             has_n = (int64_t)(y + 1) * nx < plane;
             has_d = z > 0;
@@ -317,10 +322,63 @@ __global__ __launch_bounds__(kBlock) void k_expand_w(Op A, const double *__restr
             has_s = rowi > 0;
             has_n = i0 + nx < n;
         }
-        if (has_s) row(q - rw, i0 - nx, x0, sn);
-        if (has_n) row(q + rw, i0 + nx, x0, nn);
-        if (has_d) row(q - plane / 8, i0 - plane, x0, dn);
-        if (has_u) row(q + plane / 8, i0 + plane, x0, up);
+        const bool left = x0 > 0, right = x0 + 8 < nx;
+        const uint64_t ws = has_s ? w[q - rw] : 0, wn = has_n ? w[q + rw] : 0;
+        const uint64_t wd = has_d ? w[q - plane / 8] : 0, wu = has_u ? w[q + plane / 8] : 0;
+        const int e0 = left ? stamp[i0 - 1] : 0, e1 = right ? stamp[i0 + 8] : 0;
+        // the corners beside the rows below and above (nine points only)
+        int s0 = 0, s1 = 0, n0 = 0, n1 = 0;
+        if (kShape == 9) {
+            s0 = has_s && left ? stamp[i0 - nx - 1] : 0;
+            s1 = has_s && right ? stamp[i0 - nx + 8] : 0;
+            n0 = has_n && left ? stamp[i0 + nx - 1] : 0;
+            n1 = has_n && right ? stamp[i0 + nx + 8] : 0;
+        }
+        // no stamped cell among the neighbours: nothing can join
+        if ((own | ws | wn | wd | wu) == 0 && (e0 | e1 | s0 | s1 | n0 | n1) == 0) continue;
+        int cc[10], sn[10], nn[10], dn[10], up[10];
+        unpack(own, e0, e1, cc);
+        unpack(ws, s0, s1, sn);
+        unpack(wn, n0, n1, nn);
+        unpack(wd, 0, 0, dn);
+        unpack(wu, 0, 0, up);
+        // the neighbours' stamps come from these registers, not from memory:
+        // during the round a stamp only changes from 0 to m + 1, and both
+        // read as outside
+        auto nstamp = [&](int sl, int k) -> int {
+            if (kShape == 9) {
+                switch (sl) {
+                case 0: return sn[k - 1];
+                case 1: return sn[k];
+                case 2: return sn[k + 1];
+                case 3: return cc[k - 1];
+                case 5: return cc[k + 1];
+                case 6: return nn[k - 1];
+                case 7: return nn[k];
+                case 8: return nn[k + 1];
+                default: return 0;
+                }
+            } else if (kShape == 5) {
+                switch (sl) {
+                case 0: return sn[k];
+                case 1: return cc[k - 1];
+                case 3: return cc[k + 1];
+                case 4: return nn[k];
+                default: return 0;
+                }
+            } else {
+                switch (sl) {
+                case 0: return dn[k];
+                case 1: return sn[k];
+                case 2: return cc[k - 1];
+                case 4: return cc[k + 1];
+                case 5: return nn[k];
+                case 6: return up[k];
+                default: return 0;
+                }
+            }
+        };
+        uint64_t joined = 0;
 #pragma unroll
         for (int k = 1; k <= 8; ++k) {
             if (cc[k] != 0) continue;
@@ -332,15 +390,18 @@ __global__ __launch_bounds__(kBlock) void k_expand_w(Op A, const double *__restr
             if (!nb) continue;
             const int64_t j = i0 + k - 1;
             double acc = fabs(r[j]);
-            A.for_each(j, [&](int64_t l, double a) {
-                const int sl = stamp[l];
-                if (l != j && sl != 0 && sl <= m) acc += fabs(a * x[l]);
+            // the members in ascending order, the centre excluded (its
+            // register stamp reads 0)
+            A.for_each_slot(j, [&](int sl, int64_t l, double a) {
+                if (in(nstamp(sl, k))) acc += fabs(a * x[l]);
             });
             if (acc > tau) {
-                stamp[j] = (uint8_t)(m + 1);
+                joined |= (uint64_t)(m + 1) << (8 * (k - 1));
                 v[0] += 1.0;
             }
         }
+        // the word's new members in one store (the word is this thread's)
+        if (joined) reinterpret_cast<uint64_t *>(stamp)[q] = own | joined;
     }
     write_partials<double, 1>(v, Ops<0u>(), part);
 }
