@@ -41,17 +41,17 @@ HBM_PEAK_GBS = 8000.0
 # roofline reports traffic null.
 MEASURED_TRAFFIC = {
     "k_cg_iter<UEllShort<double,5>,1>": {
-        "ratio": 1.085, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
-        "src_sha256": "5df264f54dcf78bf3ace058a315abe48f5f428f97c356078392450fd435c56e1"},
+        "ratio": 1.087, "profile": "profiles/k_cg_iter_ell5_c2_1024x1024_fp64.md",
+        "src_sha256": "10bf99c31718ca809310a0d70f7eed26d18d09c2221c70ff5299ba9b072b3e76"},
     "k_cg_iter<UEllShort<float,9>,1>": {
-        "ratio": 0.986, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "5df264f54dcf78bf3ace058a315abe48f5f428f97c356078392450fd435c56e1"},
+        "ratio": 0.987, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "10bf99c31718ca809310a0d70f7eed26d18d09c2221c70ff5299ba9b072b3e76"},
     "k_gs_sweep9<U9<double,2,2>,true>": {
         "ratio": 1.080, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "5df264f54dcf78bf3ace058a315abe48f5f428f97c356078392450fd435c56e1"},
+        "src_sha256": "10bf99c31718ca809310a0d70f7eed26d18d09c2221c70ff5299ba9b072b3e76"},
     "k_score<U9<double,2,2>,0>": {
-        "ratio": 1.024, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
-        "src_sha256": "5df264f54dcf78bf3ace058a315abe48f5f428f97c356078392450fd435c56e1"},
+        "ratio": 1.025, "profile": "profiles/k_cg_iter_ellf9_c3_4096x4096_mixed.md",
+        "src_sha256": "10bf99c31718ca809310a0d70f7eed26d18d09c2221c70ff5299ba9b072b3e76"},
 }
 KERNEL_SOURCES = ["paper_2001_01158_amd/csrc/lcs_device.h", "paper_2001_01158_amd/csrc/lcs_kernels.h"]
 
